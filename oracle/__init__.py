@@ -1,0 +1,38 @@
+"""CPU oracle for the hole k.p eigenproblem -- TEST INFRASTRUCTURE ONLY.
+
+This package is a plain, slow, obviously-correct reference for what the GPU
+library computes: the lowest eigenpairs of the finite-difference 6x6
+Luttinger-Kohn Hamiltonian with Bir-Pikus strain, Zeeman and Peierls terms and
+an electrostatic potential (paper Sec. II.B, Eqs. HNI and LK).  It assembles H
+with scipy.sparse from the textbook definitions and diagonalises it with
+library routines (dense LAPACK for small grids, ARPACK for large ones).
+
+Only the test-suite, the smoke check and the CPU-baseline leg of the benchmark
+may import it.  It shares no code with the GPU path, and the GPU path never
+imports it.
+
+Pinning status (see tests/test_oracle_pins.py):
+  * kinetic operator          -- pinned (closed-form bulk dispersion along
+                                 [001] and [111], hard-wall chain, separable limit)
+  * |J m_j> vs |L S> forms     -- pinned (two independent assemblies agree via U)
+  * spin-orbit + Zeeman onsite -- pinned (closed-form m_j sectors, Wigner-Eckart)
+  * strain                     -- pinned (uniaxial / [111]-shear closed forms,
+                                 both assemblies agree)
+  * Peierls phases             -- pinned (gauge invariance, time reversal,
+                                 Kramers degeneracy at B=0)
+  * harmonic confinement       -- pinned (Richardson-extrapolated oscillator levels)
+  * Hellmann-Feynman gradient  -- pinned (central finite differences)
+  * Zeeman sign convention and absolute g-factors -- parity unpinned against the
+    paper (the paper prints no Zeeman term); only the invariants above hold.
+"""
+
+from .constants import E0, MU_B, E_OVER_HBAR, SI_MATERIAL  # noqa: F401
+from .grid import Grid  # noqa: F401
+from .hamiltonian import (  # noqa: F401
+    hamiltonian_ls, hamiltonian_j, onsite_so_zeeman_ls, strain_orbital_ls,
+    U_J_FROM_LS, to_j_basis,
+)
+from .solve import (  # noqa: F401
+    lowest_dense, lowest_arpack, residuals, hf_gradient, gate_potential,
+    solve_lowest,
+)
