@@ -1,0 +1,210 @@
+/*
+ * hkp.h -- C ABI of an MI355X (gfx950) solver for the lowest hole eigenpairs
+ * of the finite-difference 6x6 Luttinger-Kohn k.p Hamiltonian
+ *
+ *     H_NI = H_LK + H_PB + V_DQD            (paper, Sec. II.C, Eq. HNI)
+ *
+ * with Bir-Pikus strain, Zeeman and Peierls-phase magnetic terms and an
+ * electrostatic potential, discretised on a homogeneous grid with Dirichlet
+ * walls (Sec. II.B).  The eigenpairs are found by Chebyshev-filtered subspace
+ * iteration with Rayleigh-Ritz (the Rayleigh-Chebyshev method named in
+ * Sec. II.B).  This is the Schroedinger half of the paper's self-consistent
+ * Schroedinger-Poisson loop (Fig. 2a).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  Units: energy eV, length nm, magnetic field T, gate voltage V.
+ *  Hole picture: H = -H_valence, so bound hole states are the LOWEST
+ *  eigenvalues.
+ *  Grid: interior points r = ((i+1)h, (j+1)h, (k+1)h), 0 <= i < nx, ...;
+ *  psi = 0 one spacing outside the grid (hard wall).
+ *  Scalar fields (V, lever arms): double [nx][ny][nz], C order (z fastest).
+ *  Strain: double [nx][ny][nz][6], symmetric tensor components in the order
+ *  xx, yy, zz, yz, xz, xy (tensor, not engineering, shear).
+ *  Spinor blocks (X0, psi, apply operands): complex double (re, im pairs)
+ *  [nvec][nx][ny][nz][6]; the six components are |J, m_j> in the order
+ *  |3/2,+3/2>, |3/2,+1/2>, |3/2,-1/2>, |3/2,-3/2>, |1/2,+1/2>, |1/2,-1/2>
+ *  (the order listed in Sec. II.C).  Vector potential in the symmetric gauge
+ *  A = B x (r - r0) / 2 about the box centre r0 = ((n+1)h/2, ...).
+ *  Wavefunctions are normalised to sum over grid and components of |psi|^2 = 1.
+ *
+ *  Pointers documented "device" must be device (HBM) memory of the current
+ *  HIP device; "host" pointers are read before the call returns.  The caller
+ *  owns every buffer.  No entry point allocates device memory: scratch comes
+ *  from the caller's workspace.  Work is enqueued on `hip_stream` (a
+ *  hipStream_t, NULL = default stream); entry points that return results in
+ *  host structs synchronise that stream before returning.
+ *
+ *  Return codes: 0 success, > 0 warning (results written), < 0 error (nothing
+ *  valid written).  Inputs are validated before any GPU work is enqueued.
+ *  hkp_last_error() returns a thread-local description of the last failure.
+ */
+#ifndef HKP_H
+#define HKP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define HKP_OK 0
+#define HKP_W_NOT_CONVERGED 1   /* best Ritz pairs and their residuals written */
+#define HKP_E_ARG (-1)          /* invalid argument (sizes, NULL, NaN/Inf input) */
+#define HKP_E_WORKSPACE (-2)    /* workspace smaller than hkp_*_workspace_bytes */
+#define HKP_E_NUMERICAL (-3)    /* breakdown of the orthonormalisation */
+#define HKP_E_HIP (-4)          /* a HIP runtime call failed */
+#define HKP_E_UNSUPPORTED (-5)  /* no GPU of the supported architecture */
+
+#define HKP_NB_MAX 64           /* largest block size */
+
+#define HKP_PREC_FP64 0         /* every step in double precision */
+#define HKP_PREC_MIXED 1        /* FP32 filter; FP64 orthonormalisation, RR, residual */
+
+#define HKP_FLAG_X0 1           /* use the caller's initial block X0 */
+#define HKP_FLAG_GRAPH 2        /* record outer iterations once in a hipGraph and replay */
+#define HKP_FLAG_NO_FP64_POLISH 4 /* mixed: never switch the filter to FP64 */
+
+/* Grid: nx, ny, nz >= 1 points, spacing h (nm) > 0. */
+typedef struct {
+  int32_t nx, ny, nz;
+  double h_nm;
+} hkp_grid;
+
+/* Material: Luttinger parameters, split-off energy Delta_0 (eV), isotropic
+ * magnetic parameter kappa, deformation potentials a_v, b, d (eV)
+ * (paper, Appendix A, Table I).  q (the cubic Zeeman term) is zero. */
+typedef struct {
+  double gamma1, gamma2, gamma3;
+  double delta_so_eV;
+  double kappa;
+  double a_v_eV, b_eV, d_eV;
+} hkp_material;
+
+/* Solver options.  nb = 0 or degree = 0 selects the autotuned value. */
+typedef struct {
+  int32_t nev;        /* eigenpairs wanted, 1 <= nev < nb */
+  int32_t nb;         /* subspace block size, nev < nb <= HKP_NB_MAX, nb <= 6 N */
+  int32_t degree;     /* Chebyshev polynomial degree per outer iteration (2..200) */
+  int32_t max_iter;   /* outer iterations before HKP_W_NOT_CONVERGED */
+  double tol_eV;      /* convergence: ||H psi_n - E_n psi_n||_2 <= tol for n < nev */
+  int32_t precision;  /* HKP_PREC_FP64 or HKP_PREC_MIXED */
+  int32_t flags;      /* HKP_FLAG_* */
+  uint64_t seed;      /* seed of the random initial block */
+} hkp_opts;
+
+typedef struct {
+  int32_t iters;            /* outer iterations performed (max over a batch) */
+  int32_t n_converged;      /* wanted states meeting tol (min over a batch) */
+  int64_t n_hx_fp64;        /* column applications of H in FP64 (sum over a batch) */
+  int64_t n_hx_fp32;        /* column applications of H in FP32 */
+  int32_t fp64_switch_iter; /* mixed: first outer iteration filtered in FP64, -1 none */
+  int32_t nb, degree;       /* values used (after autotuning) */
+  double seconds;           /* wall time of the call */
+  double t_setup, t_filter, t_orth, t_rr, t_resid; /* event-timed phases (eager mode) */
+  double lambda_max_bound;  /* upper spectral bound used by the filter (eV) */
+} hkp_stats;
+
+/* Autotuner result for the stencil (filter step) kernel on one shape. */
+typedef struct {
+  int32_t tile_y;      /* rows of the x-y tile (the tile is 64 x tile_y) */
+  int32_t zchunk;      /* planes marched per workgroup */
+  double us_per_step;  /* measured time of one filter step over the block */
+  double gbps;         /* algorithmic bytes / time */
+} hkp_tune;
+
+/* Silicon parameters of Table I with gamma3 = 1.446. */
+void hkp_default_material(hkp_material* m);
+/* nev 8, nb 0, degree 0, max_iter 200, tol 1e-8 eV, FP64, flags 0, seed 1. */
+void hkp_default_opts(hkp_opts* o);
+
+/* Bytes of device workspace hkp_solve / hkp_solve_batch need for `batch`
+ * Hamiltonians on `grid` with `opts` (nb = 0 sizes for the largest autotuned
+ * block).  Returns 0 on invalid arguments. */
+size_t hkp_workspace_bytes(const hkp_grid* grid, const hkp_opts* opts, int32_t batch);
+
+/* Lowest opts->nev eigenpairs of H for one potential (paper Sec. II.B).
+ *   V_eV      device double [nx][ny][nz]
+ *   strain    device double [nx][ny][nz][6] or NULL (no strain)
+ *   B_T       host double[3], magnetic field (T)
+ *   X0        device complex double [nb][nx][ny][nz][6] used when
+ *             opts->flags & HKP_FLAG_X0, else ignored (may be NULL)
+ *   eig_eV    device double [nev], ascending
+ *   psi       device complex double [nev][nx][ny][nz][6] (may be NULL)
+ *   resid_eV  device double [nev], ||H psi_n - E_n psi_n||_2 (may be NULL)
+ *   workspace device, ws_bytes >= hkp_workspace_bytes(grid, opts, 1)
+ *   stats     host, may be NULL
+ * Returns HKP_OK, HKP_W_NOT_CONVERGED or an error. */
+int hkp_solve(const hkp_grid* grid, const hkp_material* mat, const hkp_opts* opts,
+              const double* V_eV, const double* strain, const double B_T[3],
+              const void* X0, double* eig_eV, void* psi, double* resid_eV,
+              void* workspace, size_t ws_bytes, void* hip_stream, hkp_stats* stats);
+
+/* The same for `batch` Hamiltonians that differ only in the potential (a
+ * gate-voltage sweep, Fig. 2f): V_eV is [batch][nx][ny][nz]; eig_eV
+ * [batch][nev], psi [batch][nev][nx][ny][nz][6], resid_eV [batch][nev].
+ * Every kernel of an outer iteration covers the whole batch in one launch;
+ * with HKP_FLAG_GRAPH the iterations are recorded once as a hipGraph and
+ * replayed, converged members turning into no-ops on the device. */
+int hkp_solve_batch(const hkp_grid* grid, const hkp_material* mat, const hkp_opts* opts,
+                    int32_t batch, const double* V_eV, const double* strain,
+                    const double B_T[3], double* eig_eV, void* psi, double* resid_eV,
+                    void* workspace, size_t ws_bytes, void* hip_stream, hkp_stats* stats);
+
+/* Workspace of hkp_apply / hkp_filter_step for nvec vectors. */
+size_t hkp_apply_workspace_bytes(const hkp_grid* grid, int32_t nvec);
+
+/* Y = alpha (H - shift) X + beta Y_old  on nvec spinors (one Chebyshev
+ * recurrence step; alpha = 1, shift = beta = 0 gives Y = H X).
+ *   X, Y      device complex double [nvec][nx][ny][nz][6]
+ *   Y_old     device, same layout, or NULL when beta == 0; may alias Y
+ *   precision HKP_PREC_FP64 or HKP_PREC_MIXED (operands rounded to FP32 and
+ *             the stencil evaluated in FP32; result returned in FP64) */
+int hkp_filter_step(const hkp_grid* grid, const hkp_material* mat, const double* V_eV,
+                    const double* strain, const double B_T[3], int32_t nvec,
+                    const void* X, const void* Y_old, void* Y, double alpha, double shift,
+                    double beta, int32_t precision, void* workspace, size_t ws_bytes,
+                    void* hip_stream);
+
+/* Y = H X (hkp_filter_step with alpha 1, shift 0, beta 0). */
+int hkp_apply(const hkp_grid* grid, const hkp_material* mat, const double* V_eV,
+              const double* strain, const double B_T[3], int32_t nvec, const void* X,
+              void* Y, int32_t precision, void* workspace, size_t ws_bytes,
+              void* hip_stream);
+
+/* V_out = V_bg + sum_g Vg[g] L[g]  (the linear gate -> potential map).
+ *   V_bg, V_out device double [N]; L device double [G][N]; Vg device double [G]. */
+int hkp_gate_potential(int64_t N, int32_t G, const double* V_bg, const double* L,
+                       const double* Vg, double* V_out, void* hip_stream);
+
+/* Hellmann-Feynman gradient: grad[g] = sum_n w[n] sum_r sum_c |psi_{n,c}(r)|^2 L[g](r),
+ * the derivative of sum_n w_n E_n with respect to the gate voltages, since
+ * dH/dV_g = L_g(r) times the identity on the spinor components.
+ *   psi  device complex double [nev][N][6]; w device double [nev];
+ *   L    device double [G][N] (1 <= G <= 16); grad device double [G];
+ *   workspace device, ws_bytes >= hkp_hf_grad_workspace_bytes(G) (block
+ *   partial sums, reduced in a fixed order: the result is deterministic).
+ * Exact for a degenerate pair only if both members carry equal weight. */
+size_t hkp_hf_grad_workspace_bytes(int32_t G);
+int hkp_hf_grad(int64_t N, int32_t nev, const void* psi, const double* w, int32_t G,
+                const double* L, double* grad, void* workspace, size_t ws_bytes,
+                void* hip_stream);
+
+/* Time the filter-step kernel variants for this shape and block size, cache
+ * the fastest (per process, keyed by shape, nb and precision) and report it.
+ * Needs workspace >= hkp_workspace_bytes(grid, opts{nb}, 1). */
+int hkp_autotune(const hkp_grid* grid, int32_t nb, int32_t precision, int32_t with_strain,
+                 int32_t with_field, void* workspace, size_t ws_bytes, void* hip_stream,
+                 hkp_tune* out);
+
+/* Thread-local message of the last error (never NULL). */
+const char* hkp_last_error(void);
+
+/* ABI version (major * 100 + minor). */
+int hkp_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* HKP_H */

@@ -1,0 +1,17 @@
+"""MI355X-native solver for the lowest hole eigenpairs of the finite-difference
+6x6 Luttinger-Kohn k.p Hamiltonian (Bir-Pikus strain, Zeeman and Peierls
+terms, gate potential), the Schroedinger step of the self-consistent
+Schroedinger-Poisson loop of arXiv 2607.08447.
+
+The computation runs in hand-written HIP kernels for gfx950 behind the C ABI in
+include/hkp.h; this package is its Python binding.  Importing it loads the
+in-tree libhkp.so and fails if it is missing.
+"""
+
+from ._lib import HkpError, lib  # noqa: F401
+from .api import (  # noqa: F401
+    SI, EigvalsFromPotential, SolveResult, apply, autotune, filter_step, gate_potential,
+    hf_grad, solve, solve_batch, workspace_bytes,
+)
+
+__version__ = "1.0.0"

@@ -1,0 +1,116 @@
+"""ctypes declarations of the C ABI in include/hkp.h (argument marshalling only).
+
+The shared library is built in-tree by paper_2607_08447_amd/build.py.  There is
+no fallback: if libhkp.so is missing or fails to load, importing this module
+raises.
+"""
+
+import ctypes as C
+import os
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libhkp.so")
+
+HKP_OK = 0
+HKP_W_NOT_CONVERGED = 1
+HKP_E_ARG = -1
+HKP_E_WORKSPACE = -2
+HKP_E_NUMERICAL = -3
+HKP_E_HIP = -4
+HKP_E_UNSUPPORTED = -5
+HKP_NB_MAX = 64
+HKP_PREC_FP64 = 0
+HKP_PREC_MIXED = 1
+HKP_FLAG_X0 = 1
+HKP_FLAG_GRAPH = 2
+HKP_FLAG_NO_FP64_POLISH = 4
+
+
+class hkp_grid(C.Structure):
+    _fields_ = [("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32), ("h_nm", C.c_double)]
+
+
+class hkp_material(C.Structure):
+    _fields_ = [("gamma1", C.c_double), ("gamma2", C.c_double), ("gamma3", C.c_double),
+                ("delta_so_eV", C.c_double), ("kappa", C.c_double), ("a_v_eV", C.c_double),
+                ("b_eV", C.c_double), ("d_eV", C.c_double)]
+
+
+class hkp_opts(C.Structure):
+    _fields_ = [("nev", C.c_int32), ("nb", C.c_int32), ("degree", C.c_int32),
+                ("max_iter", C.c_int32), ("tol_eV", C.c_double), ("precision", C.c_int32),
+                ("flags", C.c_int32), ("seed", C.c_uint64)]
+
+
+class hkp_stats(C.Structure):
+    _fields_ = [("iters", C.c_int32), ("n_converged", C.c_int32), ("n_hx_fp64", C.c_int64),
+                ("n_hx_fp32", C.c_int64), ("fp64_switch_iter", C.c_int32), ("nb", C.c_int32),
+                ("degree", C.c_int32), ("seconds", C.c_double), ("t_setup", C.c_double),
+                ("t_filter", C.c_double), ("t_orth", C.c_double), ("t_rr", C.c_double),
+                ("t_resid", C.c_double), ("lambda_max_bound", C.c_double)]
+
+    def as_dict(self):
+        return {name: getattr(self, name) for name, _ in self._fields_}
+
+
+class hkp_tune(C.Structure):
+    _fields_ = [("tile_y", C.c_int32), ("zchunk", C.c_int32), ("us_per_step", C.c_double),
+                ("gbps", C.c_double)]
+
+
+_P = C.c_void_p
+_D = C.POINTER(C.c_double)
+
+SIGNATURES = {
+    "hkp_default_material": (None, [C.POINTER(hkp_material)]),
+    "hkp_default_opts": (None, [C.POINTER(hkp_opts)]),
+    "hkp_workspace_bytes": (C.c_size_t, [C.POINTER(hkp_grid), C.POINTER(hkp_opts), C.c_int32]),
+    "hkp_solve": (C.c_int, [C.POINTER(hkp_grid), C.POINTER(hkp_material), C.POINTER(hkp_opts),
+                            _P, _P, _D, _P, _P, _P, _P, _P, C.c_size_t, _P,
+                            C.POINTER(hkp_stats)]),
+    "hkp_solve_batch": (C.c_int, [C.POINTER(hkp_grid), C.POINTER(hkp_material),
+                                  C.POINTER(hkp_opts), C.c_int32, _P, _P, _D, _P, _P, _P, _P,
+                                  C.c_size_t, _P, C.POINTER(hkp_stats)]),
+    "hkp_apply_workspace_bytes": (C.c_size_t, [C.POINTER(hkp_grid), C.c_int32]),
+    "hkp_filter_step": (C.c_int, [C.POINTER(hkp_grid), C.POINTER(hkp_material), _P, _P, _D,
+                                  C.c_int32, _P, _P, _P, C.c_double, C.c_double, C.c_double,
+                                  C.c_int32, _P, C.c_size_t, _P]),
+    "hkp_apply": (C.c_int, [C.POINTER(hkp_grid), C.POINTER(hkp_material), _P, _P, _D, C.c_int32,
+                            _P, _P, C.c_int32, _P, C.c_size_t, _P]),
+    "hkp_gate_potential": (C.c_int, [C.c_int64, C.c_int32, _P, _P, _P, _P, _P]),
+    "hkp_hf_grad_workspace_bytes": (C.c_size_t, [C.c_int32]),
+    "hkp_hf_grad": (C.c_int, [C.c_int64, C.c_int32, _P, _P, C.c_int32, _P, _P, _P, C.c_size_t,
+                              _P]),
+    "hkp_autotune": (C.c_int, [C.POINTER(hkp_grid), C.c_int32, C.c_int32, C.c_int32, C.c_int32,
+                               _P, C.c_size_t, _P, C.POINTER(hkp_tune)]),
+    "hkp_last_error": (C.c_char_p, []),
+    "hkp_version": (C.c_int, []),
+}
+
+
+def load(path=LIB_PATH):
+    if not os.path.exists(path):
+        raise ImportError(
+            f"{path} is missing: build it with `python -m paper_2607_08447_amd.build` "
+            "(there is no CPU fallback)")
+    lib = C.CDLL(path)
+    for name, (res, args) in SIGNATURES.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    return lib
+
+
+lib = load()
+
+
+class HkpError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"hkp error {code}: {msg}")
+        self.code = code
+
+
+def check(code):
+    if code < 0:
+        raise HkpError(code, lib.hkp_last_error().decode())
+    return code

@@ -1,0 +1,281 @@
+"""Python binding of the hole k.p eigensolver (PyTorch supplies device memory
+and streams; every step of the computation runs in the HIP library).
+
+Layouts follow include/hkp.h: fields are float64 [nx, ny, nz] (strain with a
+trailing Voigt axis of 6), spinor blocks complex128 [nvec, nx, ny, nz, 6] in
+the |J m_j> basis and the symmetric gauge.
+"""
+
+import ctypes as C
+from dataclasses import dataclass
+
+import torch
+
+from . import _lib as L
+
+SI = dict(gamma1=4.285, gamma2=0.339, gamma3=1.446, delta_so_eV=0.044, kappa=-0.42,
+          a_v_eV=2.46, b_eV=-2.35, d_eV=-5.32)
+
+
+def _material(m=None):
+    mat = L.hkp_material()
+    L.lib.hkp_default_material(C.byref(mat))
+    if m:
+        for k, v in m.items():
+            k2 = {"delta_so": "delta_so_eV", "a_v": "a_v_eV", "b": "b_eV", "d": "d_eV"}.get(k, k)
+            setattr(mat, k2, float(v))
+    return mat
+
+
+def _grid(shape, h):
+    nx, ny, nz = (int(s) for s in shape)
+    return L.hkp_grid(nx, ny, nz, float(h))
+
+
+def _dev(x, dtype):
+    """Device tensor (contiguous) of the given dtype; numpy arrays are copied over."""
+    if x is None:
+        return None
+    if not torch.is_tensor(x):
+        x = torch.as_tensor(x)
+    if not x.is_cuda:
+        x = x.to("cuda")
+    return x.to(dtype).contiguous()
+
+
+def _ptr(t):
+    return C.c_void_p(t.data_ptr()) if t is not None else C.c_void_p(0)
+
+
+def _stream(stream=None):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return C.c_void_p(s.cuda_stream)
+
+
+def _B(B):
+    return (C.c_double * 3)(*[float(b) for b in B])
+
+
+@dataclass
+class SolveResult:
+    E: torch.Tensor          # [nev] or [batch, nev], eV
+    psi: torch.Tensor        # [nev, nx, ny, nz, 6] complex128 (or batched), or None
+    resid: torch.Tensor      # same leading shape as E, eV
+    stats: dict
+    status: int
+
+
+def _opts(nev, nb, degree, max_iter, tol, precision, flags, seed):
+    o = L.hkp_opts()
+    L.lib.hkp_default_opts(C.byref(o))
+    o.nev = int(nev)
+    o.nb = int(nb)
+    o.degree = int(degree)
+    o.max_iter = int(max_iter)
+    o.tol_eV = float(tol)
+    o.precision = L.HKP_PREC_MIXED if precision in ("mixed", 1) else L.HKP_PREC_FP64
+    o.flags = int(flags)
+    o.seed = int(seed)
+    return o
+
+
+def workspace_bytes(shape, h, nev, nb=0, degree=0, precision="fp64", batch=1):
+    g = _grid(shape, h)
+    o = _opts(nev, nb, degree, 10, 1e-8, precision, 0, 1)
+    n = L.lib.hkp_workspace_bytes(C.byref(g), C.byref(o), int(batch))
+    if n == 0:
+        raise L.HkpError(L.HKP_E_ARG, L.lib.hkp_last_error().decode())
+    return int(n)
+
+
+def solve(V, h, nev, strain=None, B=(0.0, 0.0, 0.0), nb=0, degree=0, tol=1e-8,
+          precision="fp64", max_iter=200, seed=1, X0=None, graph=False, material=None,
+          return_psi=True, workspace=None, polish=True):
+    """Lowest `nev` eigenpairs of H for the potential V (float64 [nx, ny, nz], eV)."""
+    V = _dev(V, torch.float64)
+    shape = tuple(V.shape)
+    if len(shape) != 3:
+        raise ValueError("V must be [nx, ny, nz]")
+    strain = _dev(strain, torch.float64)
+    g = _grid(shape, h)
+    flags = (L.HKP_FLAG_GRAPH if graph else 0) | (L.HKP_FLAG_X0 if X0 is not None else 0)
+    if not polish:
+        flags |= L.HKP_FLAG_NO_FP64_POLISH
+    o = _opts(nev, nb, degree, max_iter, tol, precision, flags, seed)
+    need = L.lib.hkp_workspace_bytes(C.byref(g), C.byref(o), 1)
+    if need == 0:
+        raise L.HkpError(L.HKP_E_ARG, L.lib.hkp_last_error().decode())
+    ws = workspace
+    if ws is None or ws.numel() < need:
+        ws = torch.empty(need, dtype=torch.uint8, device="cuda")
+    E = torch.empty(nev, dtype=torch.float64, device="cuda")
+    R = torch.empty(nev, dtype=torch.float64, device="cuda")
+    psi = torch.empty((nev,) + shape + (6,), dtype=torch.complex128, device="cuda") \
+        if return_psi else None
+    X0d = _dev(X0, torch.complex128)
+    st = L.hkp_stats()
+    stream_ctx = torch.cuda.Stream() if graph else None
+    mat = _material(material)
+    if stream_ctx is not None:
+        stream_ctx.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(stream_ctx):
+            code = L.lib.hkp_solve(C.byref(g), C.byref(mat), C.byref(o), _ptr(V), _ptr(strain),
+                                   _B(B), _ptr(X0d), _ptr(E), _ptr(psi), _ptr(R), _ptr(ws),
+                                   C.c_size_t(ws.numel()), _stream(stream_ctx), C.byref(st))
+        torch.cuda.current_stream().wait_stream(stream_ctx)
+    else:
+        code = L.lib.hkp_solve(C.byref(g), C.byref(mat), C.byref(o), _ptr(V), _ptr(strain),
+                               _B(B), _ptr(X0d), _ptr(E), _ptr(psi), _ptr(R), _ptr(ws),
+                               C.c_size_t(ws.numel()), _stream(), C.byref(st))
+    L.check(code)
+    return SolveResult(E, psi, R, st.as_dict(), code)
+
+
+def solve_batch(V, h, nev, strain=None, B=(0.0, 0.0, 0.0), nb=0, degree=0, tol=1e-8,
+                precision="fp64", max_iter=200, seed=1, graph=True, material=None,
+                return_psi=False, workspace=None, polish=True):
+    """Lowest eigenpairs of `batch` Hamiltonians differing in V ([batch, nx, ny, nz])."""
+    V = _dev(V, torch.float64)
+    if V.dim() != 4:
+        raise ValueError("V must be [batch, nx, ny, nz]")
+    batch = V.shape[0]
+    shape = tuple(V.shape[1:])
+    strain = _dev(strain, torch.float64)
+    g = _grid(shape, h)
+    flags = L.HKP_FLAG_GRAPH if graph else 0
+    if not polish:
+        flags |= L.HKP_FLAG_NO_FP64_POLISH
+    o = _opts(nev, nb, degree, max_iter, tol, precision, flags, seed)
+    need = L.lib.hkp_workspace_bytes(C.byref(g), C.byref(o), batch)
+    if need == 0:
+        raise L.HkpError(L.HKP_E_ARG, L.lib.hkp_last_error().decode())
+    ws = workspace
+    if ws is None or ws.numel() < need:
+        ws = torch.empty(need, dtype=torch.uint8, device="cuda")
+    E = torch.empty((batch, nev), dtype=torch.float64, device="cuda")
+    R = torch.empty((batch, nev), dtype=torch.float64, device="cuda")
+    psi = torch.empty((batch, nev) + shape + (6,), dtype=torch.complex128, device="cuda") \
+        if return_psi else None
+    st = L.hkp_stats()
+    mat = _material(material)
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        code = L.lib.hkp_solve_batch(C.byref(g), C.byref(mat), C.byref(o), batch, _ptr(V),
+                                     _ptr(strain), _B(B), _ptr(E), _ptr(psi), _ptr(R), _ptr(ws),
+                                     C.c_size_t(ws.numel()), _stream(s), C.byref(st))
+    torch.cuda.current_stream().wait_stream(s)
+    L.check(code)
+    return SolveResult(E, psi, R, st.as_dict(), code)
+
+
+def filter_step(V, h, X, Y_old=None, alpha=1.0, shift=0.0, beta=0.0, strain=None,
+                B=(0.0, 0.0, 0.0), precision="fp64", material=None):
+    """Y = alpha (H - shift) X + beta Y_old on a complex128 block [nvec, nx, ny, nz, 6]."""
+    V = _dev(V, torch.float64)
+    shape = tuple(V.shape)
+    X = _dev(X, torch.complex128)
+    nvec = X.shape[0]
+    if tuple(X.shape[1:]) != shape + (6,):
+        raise ValueError("X must be [nvec, nx, ny, nz, 6]")
+    Y_old = _dev(Y_old, torch.complex128)
+    strain = _dev(strain, torch.float64)
+    g = _grid(shape, h)
+    need = L.lib.hkp_apply_workspace_bytes(C.byref(g), nvec)
+    ws = torch.empty(need, dtype=torch.uint8, device="cuda")
+    Y = torch.empty_like(X)
+    prec = L.HKP_PREC_MIXED if precision in ("mixed", 1) else L.HKP_PREC_FP64
+    L.check(L.lib.hkp_filter_step(C.byref(g), C.byref(_material(material)), _ptr(V), _ptr(strain),
+                                  _B(B), nvec, _ptr(X), _ptr(Y_old), _ptr(Y), float(alpha),
+                                  float(shift), float(beta), prec, _ptr(ws),
+                                  C.c_size_t(need), _stream()))
+    return Y
+
+
+def apply(V, h, X, strain=None, B=(0.0, 0.0, 0.0), precision="fp64", material=None):
+    """Y = H X."""
+    return filter_step(V, h, X, None, 1.0, 0.0, 0.0, strain, B, precision, material)
+
+
+def gate_potential(V_bg, Lg, Vg):
+    """V = V_bg + sum_g Vg[g] L[g] on the device."""
+    V_bg = _dev(V_bg, torch.float64)
+    Lg = _dev(Lg, torch.float64)
+    Vg = _dev(Vg, torch.float64)
+    out = torch.empty_like(V_bg)
+    L.check(L.lib.hkp_gate_potential(V_bg.numel(), Lg.shape[0], _ptr(V_bg), _ptr(Lg), _ptr(Vg),
+                                      _ptr(out), _stream()))
+    return out
+
+
+def hf_grad(psi, w, Lg):
+    """grad[g] = sum_n w_n <psi_n| L_g |psi_n> (Hellmann-Feynman)."""
+    psi = _dev(psi, torch.complex128)
+    w = _dev(w, torch.float64)
+    Lg = _dev(Lg, torch.float64)
+    nev = psi.shape[0]
+    N = Lg[0].numel()
+    G = Lg.shape[0]
+    need = L.lib.hkp_hf_grad_workspace_bytes(G)
+    if need == 0:
+        raise L.HkpError(L.HKP_E_ARG, L.lib.hkp_last_error().decode())
+    ws = torch.empty(need, dtype=torch.uint8, device="cuda")
+    grad = torch.empty(G, dtype=torch.float64, device="cuda")
+    L.check(L.lib.hkp_hf_grad(N, nev, _ptr(psi), _ptr(w), G, _ptr(Lg), _ptr(grad), _ptr(ws),
+                              C.c_size_t(need), _stream()))
+    return grad
+
+
+def autotune(shape, h, nb, precision="fp64", with_strain=True, with_field=True):
+    g = _grid(shape, h)
+    prec = L.HKP_PREC_MIXED if precision in ("mixed", 1) else L.HKP_PREC_FP64
+    need = workspace_bytes(shape, h, max(1, nb - 1), nb=nb, precision=precision)
+    ws = torch.empty(need, dtype=torch.uint8, device="cuda")
+    t = L.hkp_tune()
+    L.check(L.lib.hkp_autotune(C.byref(g), nb, prec, int(with_strain), int(with_field), _ptr(ws),
+                               C.c_size_t(need), _stream(), C.byref(t)))
+    return dict(tile_y=t.tile_y, zchunk=t.zchunk, us_per_step=t.us_per_step, gbps=t.gbps)
+
+
+class EigvalsFromPotential(torch.autograd.Function):
+    """Gate voltages -> lowest eigenvalues, with a Hellmann-Feynman backward.
+
+    forward(Vg [G], L [G, nx, ny, nz], V_bg [nx, ny, nz], cfg) -> E [nev]
+    cfg: dict(h, nev, strain, B, tol, ...) passed to solve().
+    Backward: dLoss/dVg = hf_grad(psi, dLoss/dE, L).  Degenerate eigenvalues
+    (Kramers pairs at B = 0) must carry equal upstream weights, else the
+    gradient of the individual levels is not defined and this raises.
+    """
+
+    @staticmethod
+    def forward(ctx, Vg, Lg, V_bg, cfg):
+        V = gate_potential(V_bg, Lg, Vg)
+        kw = dict(cfg)
+        h = kw.pop("h")
+        nev = kw.pop("nev")
+        res = solve(V, h, nev, **kw)
+        if res.status != L.HKP_OK:
+            raise L.HkpError(res.status, "eigensolver did not converge")
+        ctx.save_for_backward(res.psi, Lg, res.E)
+        ctx.degenerate_tol = cfg.get("degenerate_tol", 1e-9)
+        return res.E.clone()
+
+    @staticmethod
+    def backward(ctx, gE):
+        psi, Lg, E = ctx.saved_tensors
+        w = gE.detach().to(torch.float64).contiguous()
+        # members of a degenerate group must carry equal weights
+        e = E.detach().cpu()
+        wc = w.cpu()
+        i = 0
+        n = e.numel()
+        while i < n:
+            j = i + 1
+            while j < n and abs(float(e[j] - e[i])) <= ctx.degenerate_tol:
+                j += 1
+            if j - i > 1 and float((wc[i:j] - wc[i]).abs().max()) > 1e-12 * max(1.0, float(wc[i:j].abs().max())):
+                raise ValueError("unequal weights within a degenerate eigenvalue group: "
+                                 "the gradient of an individual degenerate level is undefined")
+            i = j
+        g = hf_grad(psi, w, Lg.reshape(Lg.shape[0], -1))
+        return g, None, None, None

@@ -1,0 +1,375 @@
+// C ABI entry points (include/hkp.h): argument validation, workspace checks
+// and translation of failures into return codes.  No exception crosses the
+// ABI; nothing is enqueued on the GPU before the arguments have been checked.
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "hkp_internal.h"
+#include "solver.h"
+
+namespace hkp {
+
+namespace {
+thread_local std::string g_err = "no error";
+
+bool finite_pos(double x) { return std::isfinite(x) && x > 0.0; }
+
+int check_grid(const hkp_grid* g) {
+  if (!g) {
+    set_error("grid is NULL");
+    return HKP_E_ARG;
+  }
+  if (g->nx < 1 || g->ny < 1 || g->nz < 1 || !finite_pos(g->h_nm)) {
+    set_error("grid needs nx, ny, nz >= 1 and h > 0");
+    return HKP_E_ARG;
+  }
+  const long long N = (long long)g->nx * g->ny * g->nz;
+  if (N > (1LL << 31) / 6) {
+    set_error("grid too large");
+    return HKP_E_ARG;
+  }
+  return HKP_OK;
+}
+
+int check_material(const hkp_material* m) {
+  if (!m) {
+    set_error("material is NULL");
+    return HKP_E_ARG;
+  }
+  const double v[] = {m->gamma1, m->gamma2, m->gamma3, m->delta_so_eV,
+                      m->kappa,  m->a_v_eV, m->b_eV,   m->d_eV};
+  for (double x : v)
+    if (!std::isfinite(x)) {
+      set_error("material parameter is not finite");
+      return HKP_E_ARG;
+    }
+  return HKP_OK;
+}
+
+int check_field(const double* B) {
+  if (!B) {
+    set_error("B_T is NULL");
+    return HKP_E_ARG;
+  }
+  for (int i = 0; i < 3; ++i)
+    if (!std::isfinite(B[i])) {
+      set_error("B is not finite");
+      return HKP_E_ARG;
+    }
+  return HKP_OK;
+}
+
+int check_opts(const hkp_grid* g, const hkp_opts* o) {
+  if (!o) {
+    set_error("opts is NULL");
+    return HKP_E_ARG;
+  }
+  const long long n6 = 6LL * g->nx * g->ny * g->nz;
+  if (o->nev < 1 || o->nev > n6) {
+    set_error("nev must satisfy 1 <= nev <= 6 N");
+    return HKP_E_ARG;
+  }
+  const int nb = o->nb > 0 ? o->nb : default_nb(o->nev, n6);
+  if (o->nb < 0 || nb > HKP_NB_MAX || nb > n6 || nb <= o->nev) {
+    set_error("block size must satisfy nev < nb <= min(64, 6 N)");
+    return HKP_E_ARG;
+  }
+  if (o->degree < 0 || o->degree > 200) {
+    set_error("degree must be 0 (auto) or 2..200");
+    return HKP_E_ARG;
+  }
+  if (o->max_iter < 1) {
+    set_error("max_iter must be >= 1");
+    return HKP_E_ARG;
+  }
+  if (!(o->tol_eV > 0.0) || !std::isfinite(o->tol_eV)) {
+    set_error("tol must be > 0");
+    return HKP_E_ARG;
+  }
+  if (o->precision != HKP_PREC_FP64 && o->precision != HKP_PREC_MIXED) {
+    set_error("precision must be HKP_PREC_FP64 or HKP_PREC_MIXED");
+    return HKP_E_ARG;
+  }
+  return HKP_OK;
+}
+
+int check_device() {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) {
+    set_error(std::string("no HIP device: ") + hipGetErrorString(e));
+    return HKP_E_UNSUPPORTED;
+  }
+  hipDeviceProp_t prop;
+  e = hipGetDeviceProperties(&prop, dev);
+  if (e != hipSuccess) {
+    set_error(std::string("hipGetDeviceProperties: ") + hipGetErrorString(e));
+    return HKP_E_HIP;
+  }
+  if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0) {
+    set_error(std::string("unsupported GPU architecture ") + prop.gcnArchName +
+              " (built for gfx950)");
+    return HKP_E_UNSUPPORTED;
+  }
+  return HKP_OK;
+}
+
+#define HKP_TRY(x)            \
+  do {                        \
+    int r_ = (x);             \
+    if (r_ != HKP_OK) return r_; \
+  } while (0)
+
+int solve_common(const hkp_grid* grid, const hkp_material* mat, const hkp_opts* opts,
+                 int32_t batch, const double* V, const double* strain, const double B[3],
+                 const void* X0, double* eig, void* psi, double* resid, void* ws,
+                 size_t ws_bytes, void* stream, hkp_stats* stats) {
+  HKP_TRY(check_grid(grid));
+  HKP_TRY(check_material(mat));
+  HKP_TRY(check_field(B));
+  HKP_TRY(check_opts(grid, opts));
+  if (batch < 1) {
+    set_error("batch must be >= 1");
+    return HKP_E_ARG;
+  }
+  if (!V || !eig || !ws) {
+    set_error("V, eig_eV and workspace must not be NULL");
+    return HKP_E_ARG;
+  }
+  if ((opts->flags & HKP_FLAG_X0) && (!X0 || batch != 1)) {
+    set_error("HKP_FLAG_X0 needs X0 and batch == 1");
+    return HKP_E_ARG;
+  }
+  if ((opts->flags & HKP_FLAG_GRAPH) && stream == nullptr) {
+    set_error("HKP_FLAG_GRAPH needs a non-default stream (the legacy stream cannot be captured)");
+    return HKP_E_ARG;
+  }
+  Plan p = make_plan(*grid, *opts, batch);
+  const size_t need = plan_bytes(p);
+  if (ws_bytes < need) {
+    set_error("workspace too small: need " + std::to_string(need) + " bytes");
+    return HKP_E_WORKSPACE;
+  }
+  HKP_TRY(check_device());
+  SolveArgs a{};
+  a.plan = p;
+  a.mat = *mat;
+  a.V = V;
+  a.strain = strain;
+  for (int i = 0; i < 3; ++i) a.B[i] = B[i];
+  a.X0 = (opts->flags & HKP_FLAG_X0) ? X0 : nullptr;
+  a.eig = eig;
+  a.psi = psi;
+  a.resid = resid;
+  a.workspace = ws;
+  a.stream = stream;
+  a.tol = opts->tol_eV;
+  a.max_iter = opts->max_iter;
+  a.flags = opts->flags;
+  a.seed = opts->seed;
+  a.tile_y = autotuned_tile(*grid, p.nb, p.mixed);
+  a.graph_chunk = 4;
+  return guarded([&]() { return run_solve(a, stats); });
+}
+
+}  // namespace
+
+void set_error(const std::string& msg) { g_err = msg; }
+
+}  // namespace hkp
+
+using namespace hkp;
+
+extern "C" {
+
+void hkp_default_material(hkp_material* m) {
+  if (!m) return;
+  m->gamma1 = 4.285;
+  m->gamma2 = 0.339;
+  m->gamma3 = 1.446;
+  m->delta_so_eV = 0.044;
+  m->kappa = -0.42;
+  m->a_v_eV = 2.46;
+  m->b_eV = -2.35;
+  m->d_eV = -5.32;
+}
+
+void hkp_default_opts(hkp_opts* o) {
+  if (!o) return;
+  o->nev = 8;
+  o->nb = 0;
+  o->degree = 0;
+  o->max_iter = 200;
+  o->tol_eV = 1e-8;
+  o->precision = HKP_PREC_FP64;
+  o->flags = 0;
+  o->seed = 1;
+}
+
+size_t hkp_workspace_bytes(const hkp_grid* grid, const hkp_opts* opts, int32_t batch) {
+  if (check_grid(grid) != HKP_OK || check_opts(grid, opts) != HKP_OK) return 0;
+  if (batch < 1) {
+    set_error("batch must be >= 1");
+    return 0;
+  }
+  return plan_bytes(make_plan(*grid, *opts, batch));
+}
+
+int hkp_solve(const hkp_grid* grid, const hkp_material* mat, const hkp_opts* opts,
+              const double* V_eV, const double* strain, const double B_T[3], const void* X0,
+              double* eig_eV, void* psi, double* resid_eV, void* workspace, size_t ws_bytes,
+              void* hip_stream, hkp_stats* stats) {
+  return solve_common(grid, mat, opts, 1, V_eV, strain, B_T, X0, eig_eV, psi, resid_eV,
+                      workspace, ws_bytes, hip_stream, stats);
+}
+
+int hkp_solve_batch(const hkp_grid* grid, const hkp_material* mat, const hkp_opts* opts,
+                    int32_t batch, const double* V_eV, const double* strain, const double B_T[3],
+                    double* eig_eV, void* psi, double* resid_eV, void* workspace,
+                    size_t ws_bytes, void* hip_stream, hkp_stats* stats) {
+  if (opts && (opts->flags & HKP_FLAG_X0)) {
+    set_error("hkp_solve_batch takes no initial block");
+    return HKP_E_ARG;
+  }
+  return solve_common(grid, mat, opts, batch, V_eV, strain, B_T, nullptr, eig_eV, psi, resid_eV,
+                      workspace, ws_bytes, hip_stream, stats);
+}
+
+size_t hkp_apply_workspace_bytes(const hkp_grid* grid, int32_t nvec) {
+  if (check_grid(grid) != HKP_OK) return 0;
+  if (nvec < 1) {
+    set_error("nvec must be >= 1");
+    return 0;
+  }
+  return apply_bytes(*grid, nvec);
+}
+
+int hkp_filter_step(const hkp_grid* grid, const hkp_material* mat, const double* V_eV,
+                    const double* strain, const double B_T[3], int32_t nvec, const void* X,
+                    const void* Y_old, void* Y, double alpha, double shift, double beta,
+                    int32_t precision, void* workspace, size_t ws_bytes, void* hip_stream) {
+  HKP_TRY(check_grid(grid));
+  HKP_TRY(check_material(mat));
+  HKP_TRY(check_field(B_T));
+  if (nvec < 1 || !V_eV || !X || !Y || !workspace) {
+    set_error("nvec >= 1 and non-NULL V, X, Y, workspace required");
+    return HKP_E_ARG;
+  }
+  if (!std::isfinite(alpha) || !std::isfinite(shift) || !std::isfinite(beta)) {
+    set_error("alpha, shift, beta must be finite");
+    return HKP_E_ARG;
+  }
+  if (beta != 0.0 && !Y_old) {
+    set_error("beta != 0 needs Y_old");
+    return HKP_E_ARG;
+  }
+  if (precision != HKP_PREC_FP64 && precision != HKP_PREC_MIXED) {
+    set_error("precision must be HKP_PREC_FP64 or HKP_PREC_MIXED");
+    return HKP_E_ARG;
+  }
+  if (ws_bytes < apply_bytes(*grid, nvec)) {
+    set_error("workspace too small: need " + std::to_string(apply_bytes(*grid, nvec)) + " bytes");
+    return HKP_E_WORKSPACE;
+  }
+  HKP_TRY(check_device());
+  FilterArgs a{};
+  a.grid = *grid;
+  a.mat = *mat;
+  a.V = V_eV;
+  a.strain = strain;
+  for (int i = 0; i < 3; ++i) a.B[i] = B_T[i];
+  a.nvec = nvec;
+  a.X = X;
+  a.Y_old = Y_old;
+  a.Y = Y;
+  a.alpha = alpha;
+  a.shift = shift;
+  a.beta = beta;
+  a.precision = precision;
+  a.workspace = workspace;
+  a.stream = hip_stream;
+  a.tile_y = autotuned_tile(*grid, nvec, precision == HKP_PREC_MIXED);
+  return guarded([&]() { return run_filter_step(a); });
+}
+
+int hkp_apply(const hkp_grid* grid, const hkp_material* mat, const double* V_eV,
+              const double* strain, const double B_T[3], int32_t nvec, const void* X, void* Y,
+              int32_t precision, void* workspace, size_t ws_bytes, void* hip_stream) {
+  return hkp_filter_step(grid, mat, V_eV, strain, B_T, nvec, X, nullptr, Y, 1.0, 0.0, 0.0,
+                         precision, workspace, ws_bytes, hip_stream);
+}
+
+int hkp_gate_potential(int64_t N, int32_t G, const double* V_bg, const double* L,
+                       const double* Vg, double* V_out, void* hip_stream) {
+  if (N < 1 || G < 0 || !V_bg || !V_out || (G > 0 && (!L || !Vg))) {
+    set_error("hkp_gate_potential: invalid arguments");
+    return HKP_E_ARG;
+  }
+  HKP_TRY(check_device());
+  return guarded([&]() {
+    hipError_t e = launch_gate_potential(N, G, V_bg, L, Vg, V_out, (hipStream_t)hip_stream);
+    if (e != hipSuccess) {
+      set_error(hipGetErrorString(e));
+      return HKP_E_HIP;
+    }
+    return HKP_OK;
+  });
+}
+
+size_t hkp_hf_grad_workspace_bytes(int32_t G) {
+  if (G < 1 || G > 16) {
+    set_error("hkp_hf_grad: 1 <= G <= 16");
+    return 0;
+  }
+  return hf_partial_bytes(G);
+}
+
+int hkp_hf_grad(int64_t N, int32_t nev, const void* psi, const double* w, int32_t G,
+                const double* L, double* grad, void* workspace, size_t ws_bytes,
+                void* hip_stream) {
+  if (N < 1 || nev < 1 || G < 1 || G > 16 || !psi || !w || !L || !grad || !workspace) {
+    set_error("hkp_hf_grad: invalid arguments (1 <= G <= 16)");
+    return HKP_E_ARG;
+  }
+  if (ws_bytes < hf_partial_bytes(G)) {
+    set_error("workspace too small: need " + std::to_string(hf_partial_bytes(G)) + " bytes");
+    return HKP_E_WORKSPACE;
+  }
+  HKP_TRY(check_device());
+  return guarded([&]() {
+    hipError_t e = launch_hf_grad(N, nev, psi, w, G, L, (double*)workspace, grad,
+                                  (hipStream_t)hip_stream);
+    if (e != hipSuccess) {
+      set_error(hipGetErrorString(e));
+      return HKP_E_HIP;
+    }
+    return HKP_OK;
+  });
+}
+
+int hkp_autotune(const hkp_grid* grid, int32_t nb, int32_t precision, int32_t with_strain,
+                 int32_t with_field, void* workspace, size_t ws_bytes, void* hip_stream,
+                 hkp_tune* out) {
+  HKP_TRY(check_grid(grid));
+  if (nb < 1 || nb > HKP_NB_MAX || !workspace || !out ||
+      (precision != HKP_PREC_FP64 && precision != HKP_PREC_MIXED)) {
+    set_error("hkp_autotune: invalid arguments");
+    return HKP_E_ARG;
+  }
+  HKP_TRY(check_device());
+  return guarded([&]() {
+    return run_autotune(*grid, nb, precision == HKP_PREC_MIXED, with_strain != 0,
+                        with_field != 0, workspace, ws_bytes, hip_stream, out);
+  });
+}
+
+const char* hkp_last_error(void) { return g_err.c_str(); }
+
+int hkp_version(void) { return 100; }
+
+}  // extern "C"

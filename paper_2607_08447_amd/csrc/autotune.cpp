@@ -1,0 +1,117 @@
+// Autotuner for the stencil (Chebyshev step) kernel: times the tile shapes on
+// the caller's grid and block size with HIP events and caches the fastest per
+// (shape, nb, precision, strain, field) for the life of the process.
+#include <map>
+#include <mutex>
+#include <tuple>
+
+#include "hkp_internal.h"
+#include "solver.h"
+
+namespace hkp {
+
+namespace {
+
+using Key = std::tuple<int, int, int, int, int>;   // nx, ny, nz, nb, mixed
+std::mutex g_mu;
+std::map<Key, int> g_cache;
+
+size_t al(size_t x) { return (x + 255) & ~(size_t)255; }
+
+}  // namespace
+
+int autotuned_tile(const hkp_grid& g, int nb, bool mixed) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  auto it = g_cache.find(Key{g.nx, g.ny, g.nz, nb, mixed ? 1 : 0});
+  if (it != g_cache.end()) return it->second;
+  // untuned default: tall tiles on wide planes, thin tiles on narrow ones
+  return g.ny >= 32 ? 4 : (g.ny >= 8 ? 2 : 1);
+}
+
+int run_autotune(const hkp_grid& g, int nb, bool mixed, bool strain, bool field, void* ws,
+                 size_t ws_bytes, void* stream, hkp_tune* out) {
+  const long long N = (long long)g.nx * g.ny * g.nz, n6 = 6 * N;
+  const size_t esz = mixed ? 8 : 16;
+  size_t need = al(6 * N * 8) + al((size_t)g.nz * 16) + al((size_t)g.nz * g.nx * 16) +
+                3 * al((size_t)nb * n6 * esz);
+  if (ws_bytes < need) {
+    set_error("autotune workspace too small: need " + std::to_string(need) + " bytes");
+    return HKP_E_WORKSPACE;
+  }
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  char* p = reinterpret_cast<char*>(ws);
+  size_t off = 0;
+  auto take = [&](size_t b) {
+    char* q = p + off;
+    off += al(b);
+    return q;
+  };
+  void* D = take(6 * N * 8);
+  void* wt = take((size_t)g.nz * 16);
+  void* vt = take((size_t)g.nz * g.nx * 16);
+  void* X = take((size_t)nb * n6 * esz);
+  void* O = take((size_t)nb * n6 * esz);
+  void* Y = take((size_t)nb * n6 * esz);
+  // contents do not affect the timing; give them finite values
+  if (hipMemsetAsync(p, 0, off, s) != hipSuccess) return HKP_E_HIP;
+  hkp_material m;
+  hkp_default_material(&m);
+  const double B[3] = {field ? 0.5 : 0.0, 0.0, 0.0};
+  const StencilConsts<double> c = make_consts(m, g.h_nm, B);
+  hipEvent_t e0, e1;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return HKP_E_HIP;
+  const int cand[] = {1, 2, 4, 8};
+  int best = 4;
+  double best_us = 1e300;
+  for (int ty : cand) {
+    if (ty > 1 && ty > 2 * g.ny) continue;
+    StencilLaunch a{};
+    a.nx = g.nx;
+    a.ny = g.ny;
+    a.nz = g.nz;
+    a.nvec = nb;
+    a.batch = 1;
+    a.in = X;
+    a.old = O;
+    a.old_fp64 = !mixed;
+    a.out = Y;
+    a.out_fp64 = !mixed;
+    a.D = D;
+    a.strain = strain;
+    a.wtab = field ? wt : nullptr;
+    a.vtab = field ? vt : nullptr;
+    a.coef.alpha = 1.0;
+    a.coef.shift = 0.5;
+    a.coef.beta = -1.0;
+    a.tile_y = ty;
+    a.fp64 = !mixed;
+    if (launch_stencil(a, c, s) != hipSuccess) continue;   // warm-up
+    const int reps = 5;
+    (void)hipEventRecord(e0, s);
+    for (int r = 0; r < reps; ++r) (void)launch_stencil(a, c, s);
+    (void)hipEventRecord(e1, s);
+    (void)hipEventSynchronize(e1);
+    float ms = 0;
+    (void)hipEventElapsedTime(&ms, e0, e1);
+    const double us = 1e3 * ms / reps;
+    if (us < best_us) {
+      best_us = us;
+      best = ty;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  {
+    std::lock_guard<std::mutex> lk(g_mu);
+    g_cache[Key{g.nx, g.ny, g.nz, nb, mixed ? 1 : 0}] = best;
+  }
+  out->tile_y = best;
+  out->zchunk = g.nz;
+  out->us_per_step = best_us;
+  // algorithmic bytes of one filter step: read X and Y_old, write Y, plus fields
+  const double bytes = 3.0 * nb * n6 * esz + (double)N * (mixed ? 28 : 56);
+  out->gbps = bytes / (best_us * 1e-6) / 1e9;
+  return HKP_OK;
+}
+
+}  // namespace hkp

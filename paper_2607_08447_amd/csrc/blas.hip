@@ -1,0 +1,538 @@
+// Block operations of the subspace iteration on tall-skinny complex blocks
+// X (n x nb, vector-major: each vector contiguous, complex interleaved):
+//
+//   Gram     C = A^H B (nb x nb)          FP64 MFMA (v_mfma_f64_16x16x4f64),
+//                                         split over K, fixed-order reduction
+//   rotate   X <- X Q                     FP64 MFMA, in place
+//   resid    r_j^2 = || W_j - theta_j X_j ||^2
+//   cheb     Y1 = alpha (W - shift X)     first filter step from W = H X
+//   Lanczos  dots, three-term update, normalisation (spectral bound)
+//
+// The complex products are evaluated as real products of the (re, im)
+// columns: Re(A^H B) = Ar'Br + Ai'Bi, Im(A^H B) = Ar'Bi - Ai'Br, so the
+// MFMA work equals the complex flop count (8 n nb^2 real flops per product).
+#include "hkp_internal.h"
+
+namespace hkp {
+
+namespace {
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ d4 mfma(double a, double b, d4 c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+constexpr int kGramChunkMin = 1024;   // complex elements per split-K chunk, minimum
+
+// ---------------------------------------------------------------------------
+// Gram: one wave per 16-vector row tile of A; it walks every 16-vector column
+// tile of B (only j >= i for a Hermitian product).  MFMA operand layout for
+// 16x16x4 f64: lane l supplies A[l % 16][l / 16] and B[l / 16][l % 16]; the
+// result D[i][j] sits in lane j + 16 (i % 4), register i / 4 (checked on gfx950).
+// ---------------------------------------------------------------------------
+template <int NT>
+__global__ void __launch_bounds__(64 * 4)
+gram_partial_kernel(const double* A, long long a_bstride, int nba, const double* B,
+                    long long b_bstride, int nbb, long long n, long long chunk, int hermitian,
+                    const int* active, double* partial) {
+  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int ti = blockIdx.y * 4 + wv;   // row tile handled by this wave
+  const int b = blockIdx.z;
+  const int nchunks = gridDim.x;
+  if (active && !active[b]) return;
+  const int ntb = (nbb + 15) / 16;
+  if (ti * 16 >= nba) return;
+  const long long e0 = (long long)blockIdx.x * chunk;
+  long long e1 = e0 + chunk;
+  if (e1 > n) e1 = n;
+  const int r = lane & 15, q = lane >> 4;
+  const int va = ti * 16 + r;
+  const bool vaok = va < nba;
+  const double* pa = A + 2 * ((long long)b * a_bstride + (long long)(vaok ? va : 0) * n);
+  const double* pb[NT];
+  bool vbok[NT];
+#pragma unroll
+  for (int t = 0; t < NT; ++t) {
+    const int vb = t * 16 + r;
+    vbok[t] = t < ntb && vb < nbb;
+    pb[t] = B + 2 * ((long long)b * b_bstride + (long long)(vbok[t] ? vb : 0) * n);
+  }
+  d4 rr[NT], ii[NT], ri[NT], ir[NT];
+#pragma unroll
+  for (int t = 0; t < NT; ++t) {
+    rr[t] = d4{0, 0, 0, 0};
+    ii[t] = rr[t];
+    ri[t] = rr[t];
+    ir[t] = rr[t];
+  }
+  const int t0 = hermitian ? ti : 0;
+  const long long nks = (e1 - e0 + 3) / 4;   // k-steps (uniform across the wave)
+  for (long long st = 0; st < nks; ++st) {
+    const long long e = e0 + 4 * st + q;
+    const bool eok = e < e1;
+    double2 av = (vaok && eok) ? *reinterpret_cast<const double2*>(pa + 2 * e) : make_double2(0, 0);
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+      if (t < t0 || t >= ntb) continue;
+      double2 bv = (vbok[t] && eok) ? *reinterpret_cast<const double2*>(pb[t] + 2 * e)
+                                   : make_double2(0, 0);
+      rr[t] = mfma(av.x, bv.x, rr[t]);
+      ii[t] = mfma(av.y, bv.y, ii[t]);
+      ri[t] = mfma(av.x, bv.y, ri[t]);
+      ir[t] = mfma(av.y, bv.x, ir[t]);
+    }
+  }
+  // partial[b][chunk][i][j] complex
+  double* out = partial + 2 * (((long long)b * nchunks + blockIdx.x) * nba * nbb);
+#pragma unroll
+  for (int t = 0; t < NT; ++t) {
+    if (t < t0 || t >= ntb) continue;
+    const int j = t * 16 + (lane & 15);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const int i = ti * 16 + 4 * k + (lane >> 4);
+      if (i < nba && j < nbb) {
+        out[2 * ((long long)i * nbb + j)] = rr[t][k] + ii[t][k];
+        out[2 * ((long long)i * nbb + j) + 1] = ri[t][k] - ir[t][k];
+      }
+    }
+  }
+}
+
+__global__ void gram_reduce_kernel(int nchunks, int nba, int nbb, int hermitian,
+                                   const int* active, const double* partial, double* out) {
+  const int b = blockIdx.y;
+  if (active && !active[b]) return;
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= nba * nbb) return;
+  const int i = idx / nbb, j = idx % nbb;
+  double* o = out + 2 * ((long long)b * nba * nbb);
+  if (hermitian && j < i) return;  // filled from the upper triangle
+  double re = 0.0, im = 0.0;
+  // the wave of row tile i/16 wrote tiles with column tile >= row tile
+  int si = i, sj = j;
+  const double* p = partial + 2 * ((long long)b * nchunks * nba * nbb);
+  if (hermitian && (sj / 16) < (si / 16)) {
+    // not computed directly (lower tile): use conj of the transposed entry
+    int tmp = si;
+    si = sj;
+    sj = tmp;
+  }
+  for (int c = 0; c < nchunks; ++c) {
+    const double* q = p + 2 * ((long long)c * nba * nbb + (long long)si * nbb + sj);
+    re += q[0];
+    im += q[1];
+  }
+  if (si != i) im = -im;
+  if (hermitian) {
+    if (i == j) im = 0.0;
+    o[2 * ((long long)i * nbb + j)] = re;
+    o[2 * ((long long)i * nbb + j) + 1] = im;
+    o[2 * ((long long)j * nbb + i)] = re;
+    o[2 * ((long long)j * nbb + i) + 1] = -im;
+  } else {
+    o[2 * ((long long)i * nbb + j)] = re;
+    o[2 * ((long long)i * nbb + j) + 1] = im;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// rotate: Y[:, w] = sum_v X[:, v] Q[v][w].  Computed as D^T = Q^T X^T with
+// MFMA: M = 16 real output columns (8 output vectors: (w, re), (w, im), ...),
+// N = 16 elements, K = 4 real input columns (2 input vectors x (re, im)).
+// Each wave owns 16 consecutive elements; it loads all its X values before
+// storing, so Y may alias X.  Q lives in LDS.
+// ---------------------------------------------------------------------------
+constexpr int kRotWaves = 4;
+
+template <int NBIN_MAX>
+__global__ void __launch_bounds__(64 * kRotWaves)
+rotate_kernel(const double* X, long long x_bstride, double* Y, long long y_bstride, long long n,
+              int nin, int nout, const double* Q, const int* active) {
+  extern __shared__ double qs[];   // [nin][nout] complex
+  const int b = blockIdx.y;
+  if (active && !active[b]) return;
+  const double* Qb = Q + 2 * ((long long)b * nin * nout);
+  for (int t = threadIdx.x; t < 2 * nin * nout; t += blockDim.x) qs[t] = Qb[t];
+  __syncthreads();
+  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int r = lane & 15, q = lane >> 4;
+  constexpr int KS = NBIN_MAX / 2;       // k-steps of 2 input vectors
+  const int ks = (nin + 1) / 2;
+  const int mt = (nout + 7) / 8;          // M tiles of 8 output vectors
+  const double* xb = X + 2 * ((long long)b * x_bstride);
+  double* yb = Y + 2 * ((long long)b * y_bstride);
+  const long long ntile = (n + 15) / 16;
+  for (long long tile = (long long)blockIdx.x * kRotWaves + wv; tile < ntile;
+       tile += (long long)gridDim.x * kRotWaves) {
+    const long long e = tile * 16 + r;
+    const bool eok = e < n;
+    // B operand: X^T[k][e], k = 2 v + part
+    double xv[KS];
+#pragma unroll
+    for (int s = 0; s < KS; ++s) {
+      if (s < ks) {
+        const int v = 2 * s + (q >> 1);
+        xv[s] = (eok && v < nin) ? xb[2 * ((long long)v * n + e) + (q & 1)] : 0.0;
+      } else {
+        xv[s] = 0.0;
+      }
+    }
+    for (int m = 0; m < mt; ++m) {
+      d4 acc = d4{0, 0, 0, 0};
+      // A operand: Qhat^T[mrow][k]; row mrow of the result lands in lane
+      // group mrow % 4, register mrow / 4, so order the rows as
+      // mrow -> (w = 8m + 2 (mrow % 4) + (mrow / 8), part = (mrow / 4) % 2)
+      // and every lane ends up holding (w, re), (w, im), (w+1, re), (w+1, im)
+      const int w = m * 8 + 2 * (r & 3) + (r >> 3);
+      const int op = (r >> 2) & 1;
+#pragma unroll
+      for (int s = 0; s < KS; ++s) {
+        if (s < ks) {
+          const int v = 2 * s + (q >> 1);
+          const int ip = q & 1;
+          double a = 0.0;
+          if (v < nin && w < nout) {
+            const double qr = qs[2 * (v * nout + w)], qi = qs[2 * (v * nout + w) + 1];
+            // Yr += Xr Qr - Xi Qi ; Yi += Xr Qi + Xi Qr
+            a = op == 0 ? (ip == 0 ? qr : -qi) : (ip == 0 ? qi : qr);
+          }
+          acc = mfma(a, xv[s], acc);
+        }
+      }
+      // D[mrow][e]: lane holds rows 4 k + l/16 -> (w0, re), (w0, im), (w0+1, re), (w0+1, im)
+      const int w0 = m * 8 + 2 * q;
+      if (eok) {
+        if (w0 < nout)
+          *reinterpret_cast<double2*>(yb + 2 * ((long long)w0 * n + e)) = make_double2(acc[0], acc[1]);
+        if (w0 + 1 < nout)
+          *reinterpret_cast<double2*>(yb + 2 * ((long long)(w0 + 1) * n + e)) = make_double2(acc[2], acc[3]);
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// residual partial sums: r2[b][j] = sum_e |W_j(e) - theta_j X_j(e)|^2
+// ---------------------------------------------------------------------------
+constexpr int kResThreads = 256;
+
+__global__ void __launch_bounds__(kResThreads)
+resid_partial_kernel(const double* X, const double* W, long long bstride, long long n, int nb,
+                     const double* theta, const int* active, double* partial) {
+  const int j = blockIdx.y, b = blockIdx.z;
+  if (active && !active[b]) return;
+  const double th = theta[(long long)b * nb + j];
+  const double2* x = reinterpret_cast<const double2*>(X) + (long long)b * bstride + (long long)j * n;
+  const double2* w = reinterpret_cast<const double2*>(W) + (long long)b * bstride + (long long)j * n;
+  double s = 0.0;
+  for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < n;
+       e += (long long)gridDim.x * blockDim.x) {
+    const double2 xv = x[e], wv = w[e];
+    const double dr = wv.x - th * xv.x, di = wv.y - th * xv.y;
+    s = fma(dr, dr, fma(di, di, s));
+  }
+  __shared__ double red[kResThreads / 64];
+  for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = 0.0;
+    for (int k = 0; k < kResThreads / 64; ++k) t += red[k];
+    partial[((long long)b * nb + j) * gridDim.x + blockIdx.x] = t;
+  }
+}
+
+__global__ void sum_partials_kernel(int nparts, int count, const double* partial, double* out,
+                                    const int* active, int per_batch) {
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= count) return;
+  if (active && !active[idx / per_batch]) return;
+  double s = 0.0;
+  for (int k = 0; k < nparts; ++k) s += partial[(long long)idx * nparts + k];
+  out[idx] = s;
+}
+
+// complex dots conj(a_b) . b_b for one vector per batch member: out[b] = (re, im)
+__global__ void __launch_bounds__(kResThreads)
+dot_partial_kernel(const double* A, const double* B, long long bstride, long long n,
+                   double* partial) {
+  const int b = blockIdx.y;
+  const double2* a = reinterpret_cast<const double2*>(A) + (long long)b * bstride;
+  const double2* c = reinterpret_cast<const double2*>(B) + (long long)b * bstride;
+  double sr = 0.0, si = 0.0;
+  for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < n;
+       e += (long long)gridDim.x * blockDim.x) {
+    const double2 x = a[e], y = c[e];
+    sr = fma(x.x, y.x, fma(x.y, y.y, sr));
+    si = fma(x.x, y.y, fma(-x.y, y.x, si));
+  }
+  __shared__ double red[2][kResThreads / 64];
+  for (int off = 32; off > 0; off >>= 1) {
+    sr += __shfl_down(sr, off, 64);
+    si += __shfl_down(si, off, 64);
+  }
+  if ((threadIdx.x & 63) == 0) {
+    red[0][threadIdx.x >> 6] = sr;
+    red[1][threadIdx.x >> 6] = si;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double tr = 0.0, ti = 0.0;
+    for (int k = 0; k < kResThreads / 64; ++k) {
+      tr += red[0][k];
+      ti += red[1][k];
+    }
+    partial[2 * ((long long)b * gridDim.x + blockIdx.x)] = tr;
+    partial[2 * ((long long)b * gridDim.x + blockIdx.x) + 1] = ti;
+  }
+}
+
+__global__ void dot_reduce_kernel(int nparts, const double* partial, double* out) {
+  const int b = blockIdx.x;
+  if (threadIdx.x != 0) return;
+  double sr = 0.0, si = 0.0;
+  for (int k = 0; k < nparts; ++k) {
+    sr += partial[2 * ((long long)b * nparts + k)];
+    si += partial[2 * ((long long)b * nparts + k) + 1];
+  }
+  out[2 * b] = sr;
+  out[2 * b + 1] = si;
+}
+
+// w <- w - alpha v - beta vprev, alpha = Re(dot) and beta = sqrt(norm2prev) read
+// from device arrays of (re, im) pairs per batch member
+__global__ void lanczos_update_kernel(double* w, const double* v, const double* vprev,
+                                      long long n, long long bstride, const double* alpha,
+                                      const double* norm2prev) {
+  const int b = blockIdx.y;
+  const double al = alpha[2 * b], be = norm2prev ? sqrt(norm2prev[2 * b]) : 0.0;
+  double2* wb = reinterpret_cast<double2*>(w) + (long long)b * bstride;
+  const double2* vb = reinterpret_cast<const double2*>(v) + (long long)b * bstride;
+  const double2* pb = vprev ? reinterpret_cast<const double2*>(vprev) + (long long)b * bstride
+                            : nullptr;
+  for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < n;
+       e += (long long)gridDim.x * blockDim.x) {
+    double2 x = wb[e];
+    const double2 y = vb[e];
+    x.x -= al * y.x;
+    x.y -= al * y.y;
+    if (pb) {
+      const double2 z = pb[e];
+      x.x -= be * z.x;
+      x.y -= be * z.y;
+    }
+    wb[e] = x;
+  }
+}
+
+// v <- v / sqrt(norm2[2b])
+__global__ void scale_kernel(double* v, long long n, long long bstride, const double* norm2) {
+  const int b = blockIdx.y;
+  const double nn = norm2[2 * b];
+  const double s = nn > 1e-300 ? 1.0 / sqrt(nn) : 0.0;   // breakdown: vector becomes zero
+  double2* vb = reinterpret_cast<double2*>(v) + (long long)b * bstride;
+  for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < n;
+       e += (long long)gridDim.x * blockDim.x) {
+    double2 x = vb[e];
+    x.x *= s;
+    x.y *= s;
+    vb[e] = x;
+  }
+}
+
+template <typename TO>
+__global__ void cheb_first_kernel(const double* X, const double* W, long long bstride,
+                                  long long count, TO* out, long long out_bstride,
+                                  const double* coef, int coef_stride, const int* active) {
+  const int b = blockIdx.y;
+  if (active && !active[b]) return;
+  const double al = coef[(long long)b * coef_stride], sh = coef[(long long)b * coef_stride + 1];
+  const double2* x = reinterpret_cast<const double2*>(X) + (long long)b * bstride;
+  const double2* w = reinterpret_cast<const double2*>(W) + (long long)b * bstride;
+  TO* o = out + 2 * (long long)b * out_bstride;
+  for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < count;
+       e += (long long)gridDim.x * blockDim.x) {
+    const double2 xv = x[e], wv = w[e];
+    o[2 * e] = (TO)(al * (wv.x - sh * xv.x));
+    o[2 * e + 1] = (TO)(al * (wv.y - sh * xv.y));
+  }
+}
+
+template <typename TI, typename TO>
+__global__ void cast_kernel(const TI* in, TO* out, long long count) {
+  for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < count;
+       e += (long long)gridDim.x * blockDim.x)
+    out[e] = (TO)in[e];
+}
+
+// counter-based generator: splitmix64 of (seed, batch, vector, element)
+__device__ __forceinline__ unsigned long long splitmix64(unsigned long long z) {
+  z += 0x9E3779B97F4A7C15ULL;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
+  return z ^ (z >> 31);
+}
+
+__global__ void random_kernel(double* X, long long n, int nvec, long long bstride,
+                              unsigned long long seed) {
+  const int b = blockIdx.z, v = blockIdx.y;
+  double* xb = X + 2 * ((long long)b * bstride + (long long)v * n);
+  const unsigned long long base =
+      splitmix64(seed ^ splitmix64(((unsigned long long)b << 32) | (unsigned)v));
+  for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < n;
+       e += (long long)gridDim.x * blockDim.x) {
+    const unsigned long long r = splitmix64(base + (unsigned long long)e);
+    const double re = ((double)(r >> 11) * 0x1.0p-53) * 2.0 - 1.0;
+    const unsigned long long r2 = splitmix64(r);
+    const double im = ((double)(r2 >> 11) * 0x1.0p-53) * 2.0 - 1.0;
+    xb[2 * e] = re;
+    xb[2 * e + 1] = im;
+  }
+}
+
+unsigned grid_for(long long count, int threads, unsigned cap = 4096) {
+  long long g = (count + threads - 1) / threads;
+  if (g < 1) g = 1;
+  if (g > cap) g = cap;
+  return (unsigned)g;
+}
+
+}  // namespace
+
+int gram_chunks(long long n, int batch) {
+  // aim for about 2048 workgroups (x row-tile blocks) over the batch
+  long long per = 2048 / (batch > 0 ? batch : 1);
+  if (per < 8) per = 8;
+  long long maxc = (n + kGramChunkMin - 1) / kGramChunkMin;
+  if (per > maxc) per = maxc;
+  if (per < 1) per = 1;
+  return (int)per;
+}
+
+size_t gram_partial_bytes(int nb, long long n, int batch) {
+  return (size_t)gram_chunks(n, batch) * batch * nb * nb * 16;
+}
+
+hipError_t launch_gram(const BlockDesc& A, const BlockDesc& B, int hermitian, int batch,
+                       double* partial, double* out, const int* active, hipStream_t s) {
+  const long long n = A.n;
+  const int nchunks = gram_chunks(n, batch);
+  long long chunk = (n + nchunks - 1) / nchunks;
+  chunk = (chunk + 3) & ~3LL;
+  const int nta = (A.nvec + 15) / 16, ntb = (B.nvec + 15) / 16;
+  dim3 grid((unsigned)nchunks, (unsigned)((nta + 3) / 4), (unsigned)batch);
+  switch (ntb) {
+    case 1: gram_partial_kernel<1><<<grid, 256, 0, s>>>(A.ptr, A.bstride, A.nvec, B.ptr, B.bstride, B.nvec, n, chunk, hermitian, active, partial); break;
+    case 2: gram_partial_kernel<2><<<grid, 256, 0, s>>>(A.ptr, A.bstride, A.nvec, B.ptr, B.bstride, B.nvec, n, chunk, hermitian, active, partial); break;
+    case 3: gram_partial_kernel<3><<<grid, 256, 0, s>>>(A.ptr, A.bstride, A.nvec, B.ptr, B.bstride, B.nvec, n, chunk, hermitian, active, partial); break;
+    case 4: gram_partial_kernel<4><<<grid, 256, 0, s>>>(A.ptr, A.bstride, A.nvec, B.ptr, B.bstride, B.nvec, n, chunk, hermitian, active, partial); break;
+    default: return hipErrorInvalidValue;
+  }
+  const int cnt = A.nvec * B.nvec;
+  dim3 g2((unsigned)((cnt + 255) / 256), (unsigned)batch);
+  gram_reduce_kernel<<<g2, 256, 0, s>>>(nchunks, A.nvec, B.nvec, hermitian, active, partial, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_rotate(const BlockDesc& X, const BlockDesc& Y, int nin, int nout,
+                         const double* Q, int batch, const int* active, hipStream_t s) {
+  if (nin > HKP_NB_MAX || nout > nin) return hipErrorInvalidValue;
+  const long long ntile = (X.n + 15) / 16;
+  long long g = (ntile + kRotWaves - 1) / kRotWaves;
+  const long long cap = 4096 / (batch > 0 ? batch : 1) + 1;
+  if (g > cap) g = cap;
+  dim3 grid((unsigned)g, (unsigned)batch);
+  const size_t lds = (size_t)nin * nout * 16;
+  if (nin <= 16)
+    rotate_kernel<16><<<grid, 64 * kRotWaves, lds, s>>>(X.ptr, X.bstride, Y.ptr, Y.bstride, X.n, nin, nout, Q, active);
+  else if (nin <= 32)
+    rotate_kernel<32><<<grid, 64 * kRotWaves, lds, s>>>(X.ptr, X.bstride, Y.ptr, Y.bstride, X.n, nin, nout, Q, active);
+  else if (nin <= 48)
+    rotate_kernel<48><<<grid, 64 * kRotWaves, lds, s>>>(X.ptr, X.bstride, Y.ptr, Y.bstride, X.n, nin, nout, Q, active);
+  else
+    rotate_kernel<64><<<grid, 64 * kRotWaves, lds, s>>>(X.ptr, X.bstride, Y.ptr, Y.bstride, X.n, nin, nout, Q, active);
+  return hipGetLastError();
+}
+
+int resid_parts(long long n) {
+  long long p = (n + 4095) / 4096;
+  if (p > 64) p = 64;
+  if (p < 1) p = 1;
+  return (int)p;
+}
+
+hipError_t launch_resid(const BlockDesc& X, const BlockDesc& W, const double* theta, int batch,
+                        double* partial, double* r, const int* active, hipStream_t s) {
+  const int parts = resid_parts(X.n);
+  dim3 grid((unsigned)parts, (unsigned)X.nvec, (unsigned)batch);
+  resid_partial_kernel<<<grid, kResThreads, 0, s>>>(X.ptr, W.ptr, X.bstride, X.n, X.nvec, theta,
+                                                     active, partial);
+  const int cnt = batch * X.nvec;
+  sum_partials_kernel<<<(cnt + 255) / 256, 256, 0, s>>>(parts, cnt, partial, r, active, X.nvec);
+  return hipGetLastError();
+}
+
+hipError_t launch_cheb_first(const BlockDesc& X, const BlockDesc& W, void* out, int out_fp64,
+                             long long out_bstride, int batch, const double* coef,
+                             int coef_stride, const int* active, hipStream_t s) {
+  const long long count = X.n * X.nvec;
+  dim3 grid(grid_for(count, 256, 8192 / (batch > 0 ? batch : 1) + 1), (unsigned)batch);
+  if (out_fp64)
+    cheb_first_kernel<double><<<grid, 256, 0, s>>>(X.ptr, W.ptr, X.bstride, count, (double*)out,
+                                                   out_bstride, coef, coef_stride, active);
+  else
+    cheb_first_kernel<float><<<grid, 256, 0, s>>>(X.ptr, W.ptr, X.bstride, count, (float*)out,
+                                                  out_bstride, coef, coef_stride, active);
+  return hipGetLastError();
+}
+
+hipError_t launch_cast(const void* in, int in_fp64, void* out, int out_fp64, long long count,
+                       hipStream_t s) {
+  const unsigned g = grid_for(count, 256, 16384);
+  if (in_fp64 && !out_fp64)
+    cast_kernel<double, float><<<g, 256, 0, s>>>((const double*)in, (float*)out, count);
+  else if (!in_fp64 && out_fp64)
+    cast_kernel<float, double><<<g, 256, 0, s>>>((const float*)in, (double*)out, count);
+  else if (in_fp64)
+    cast_kernel<double, double><<<g, 256, 0, s>>>((const double*)in, (double*)out, count);
+  else
+    cast_kernel<float, float><<<g, 256, 0, s>>>((const float*)in, (float*)out, count);
+  return hipGetLastError();
+}
+
+hipError_t launch_random_block(double* X, long long n, int nvec, int batch, long long bstride,
+                               unsigned long long seed, hipStream_t s) {
+  dim3 grid(grid_for(n, 256, 1024), (unsigned)nvec, (unsigned)batch);
+  random_kernel<<<grid, 256, 0, s>>>(X, n, nvec, bstride, seed);
+  return hipGetLastError();
+}
+
+int dot_parts() { return 256; }
+
+hipError_t launch_dots(const double* a, const double* b, long long n, int batch,
+                       long long bstride, double* partial, double* out, hipStream_t s) {
+  const int parts = dot_parts();
+  dim3 grid((unsigned)parts, (unsigned)batch);
+  dot_partial_kernel<<<grid, kResThreads, 0, s>>>(a, b, bstride, n, partial);
+  dot_reduce_kernel<<<batch, 64, 0, s>>>(parts, partial, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_lanczos_update(double* w, const double* v, const double* vprev, long long n,
+                                 int batch, long long bstride, const double* alpha,
+                                 const double* beta, hipStream_t s) {
+  dim3 grid(grid_for(n, 256, 2048), (unsigned)batch);
+  lanczos_update_kernel<<<grid, 256, 0, s>>>(w, v, vprev, n, bstride, alpha, beta);
+  return hipGetLastError();
+}
+
+hipError_t launch_scale(double* v, long long n, int batch, long long bstride,
+                        const double* norm2, hipStream_t s) {
+  dim3 grid(grid_for(n, 256, 2048), (unsigned)batch);
+  scale_kernel<<<grid, 256, 0, s>>>(v, n, bstride, norm2);
+  return hipGetLastError();
+}
+
+}  // namespace hkp

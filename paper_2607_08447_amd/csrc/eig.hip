@@ -1,0 +1,379 @@
+// Small dense Hermitian eigenproblems of the subspace iteration, one
+// workgroup per matrix (nb <= 64), entirely on the device so that an outer
+// iteration needs no host round trip and can be recorded in a hipGraph.
+//
+// Method: cyclic two-sided Jacobi with the round-robin (tournament) ordering,
+// nb/2 disjoint rotations per round applied in parallel; complex rotations
+// J = diag(1, e^{-i phi}) R(theta) reduce each 2x2 Hermitian block to a real
+// symmetric one.  Converges quadratically to full FP64 accuracy.
+//
+// Modes
+//   RR   (Rayleigh-Ritz):  A -> eigenvalues ascending + eigenvectors Q[v][w]
+//   SVQB (orthonormaliser): S (Gram) -> T = D U diag(lambda)^-1/2 with
+//         D = diag(S)^-1/2 and D S D = U diag(lambda) U^H; X T is orthonormal.
+//
+// Also: the control kernel that turns Ritz values and residuals into the
+// convergence flags and the next Chebyshev filter coefficients.
+#include "hkp_internal.h"
+
+namespace hkp {
+
+namespace {
+
+constexpr int kJacThreads = 256;
+constexpr int kNBP = HKP_NB_MAX;   // padded size (even)
+
+struct Rot {
+  double c, s, er, ei;   // cos, sin, e^{i phi}
+  int p, q;
+};
+
+// pair k of `round` for n players (n even): returns (p, q) with p < q
+__device__ __forceinline__ void pair_of(int k, int round, int n, int* p, int* q) {
+  const int m = n - 1;
+  int a, b;
+  if (k == 0) {
+    a = m;
+    b = round % m;
+  } else {
+    a = (round + k) % m;
+    b = (round - k + m) % m;
+  }
+  *p = a < b ? a : b;
+  *q = a < b ? b : a;
+}
+
+__global__ void __launch_bounds__(kJacThreads)
+heev_kernel(double* A, int nb, long long mat_stride, double* evals, double* out, int mode,
+            int* status, const int* active) {
+  __shared__ double2 a[kNBP][kNBP + 1];
+  __shared__ double2 v[kNBP][kNBP + 1];
+  __shared__ Rot rot[kNBP / 2];
+  __shared__ double dscale[kNBP];
+  __shared__ double lam[kNBP];
+  __shared__ int rank[kNBP];
+  __shared__ double red[kJacThreads / 64];
+  __shared__ int any_rot;
+
+  const int b = blockIdx.x;
+  if (active && !active[b]) return;
+  const int tid = threadIdx.x;
+  const int n = nb + (nb & 1);      // even number of players; the pad is decoupled
+  const double2* Ab = reinterpret_cast<const double2*>(A + 2 * (long long)b * mat_stride);
+
+  for (int t = tid; t < n * n; t += kJacThreads) {
+    const int i = t / n, j = t % n;
+    double2 x = make_double2(0, 0);
+    if (i < nb && j < nb) x = Ab[(long long)i * nb + j];
+    a[i][j] = x;
+    v[i][j] = make_double2(i == j ? 1.0 : 0.0, 0.0);
+  }
+  __syncthreads();
+  if (mode == 1) {
+    // D = diag(S)^-1/2, A <- D S D
+    for (int i = tid; i < n; i += kJacThreads) {
+      const double d = i < nb ? a[i][i].x : 1.0;
+      dscale[i] = d > 0.0 ? 1.0 / sqrt(d) : 0.0;
+    }
+    __syncthreads();
+    for (int t = tid; t < n * n; t += kJacThreads) {
+      const int i = t / n, j = t % n;
+      const double s = dscale[i] * dscale[j];
+      a[i][j].x *= s;
+      a[i][j].y *= s;
+    }
+    __syncthreads();
+  }
+  for (int t = tid; t < n; t += kJacThreads) a[t][t].y = 0.0;
+  // Frobenius norm: absolute threshold of the Rayleigh-Ritz mode (its
+  // diagonal may be ~0 or negative); SVQB uses the relative test alone
+  {
+    double f = 0.0;
+    for (int t = tid; t < n * n; t += kJacThreads) {
+      const double2 x = a[t / n][t % n];
+      f += x.x * x.x + x.y * x.y;
+    }
+    for (int off = 32; off > 0; off >>= 1) f += __shfl_down(f, off, 64);
+    if ((tid & 63) == 0) red[tid >> 6] = f;
+  }
+  __syncthreads();
+  double frob = 0.0;
+  for (int k = 0; k < kJacThreads / 64; ++k) frob += red[k];
+  frob = sqrt(frob);
+  const double abs_thr = mode == 0 ? 1e-3 * 2.220446049250313e-16 * frob : 1e-300;
+  __syncthreads();
+
+  const double eps = 2.220446049250313e-16;
+  for (int sweep = 0; sweep < 40; ++sweep) {
+    if (tid == 0) any_rot = 0;
+    __syncthreads();
+    for (int round = 0; round < n - 1; ++round) {
+      // rotation parameters, one thread per pair
+      if (tid < n / 2) {
+        int p, q;
+        pair_of(tid, round, n, &p, &q);
+        const double app = a[p][p].x, aqq = a[q][q].x;
+        const double2 apq = a[p][q];
+        const double mag = sqrt(apq.x * apq.x + apq.y * apq.y);
+        Rot r;
+        r.p = p;
+        r.q = q;
+        if (mag > eps * 0.5 * sqrt(fabs(app * aqq)) && mag > abs_thr) {
+          const double zeta = (aqq - app) / (2.0 * mag);
+          const double t = (zeta >= 0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+          r.c = 1.0 / sqrt(1.0 + t * t);
+          r.s = t * r.c;
+          r.er = apq.x / mag;
+          r.ei = apq.y / mag;
+          any_rot = 1;
+        } else {
+          r.c = 1.0;
+          r.s = 0.0;
+          r.er = 1.0;
+          r.ei = 0.0;
+        }
+        rot[tid] = r;
+      }
+      __syncthreads();
+      // rows: row p <- c A[p,:] - s e^{i phi} A[q,:],  row q <- s A[p,:] + c e^{i phi} A[q,:]
+      for (int t = tid; t < (n / 2) * n; t += kJacThreads) {
+        const Rot r = rot[t / n];
+        if (r.s == 0.0) continue;
+        const int j = t % n;
+        const double2 xp = a[r.p][j], xq = a[r.q][j];
+        const double2 eq = make_double2(r.er * xq.x - r.ei * xq.y, r.er * xq.y + r.ei * xq.x);
+        a[r.p][j] = make_double2(r.c * xp.x - r.s * eq.x, r.c * xp.y - r.s * eq.y);
+        a[r.q][j] = make_double2(r.s * xp.x + r.c * eq.x, r.s * xp.y + r.c * eq.y);
+      }
+      __syncthreads();
+      // columns (A and V): col p <- c A[:,p] - s e^{-i phi} A[:,q], col q <- s A[:,p] + c e^{-i phi} A[:,q]
+      for (int t = tid; t < (n / 2) * n; t += kJacThreads) {
+        const Rot r = rot[t / n];
+        if (r.s == 0.0) continue;
+        const int i = t % n;
+        {
+          const double2 xp = a[i][r.p], xq = a[i][r.q];
+          const double2 eq = make_double2(r.er * xq.x + r.ei * xq.y, r.er * xq.y - r.ei * xq.x);
+          a[i][r.p] = make_double2(r.c * xp.x - r.s * eq.x, r.c * xp.y - r.s * eq.y);
+          a[i][r.q] = make_double2(r.s * xp.x + r.c * eq.x, r.s * xp.y + r.c * eq.y);
+        }
+        {
+          const double2 xp = v[i][r.p], xq = v[i][r.q];
+          const double2 eq = make_double2(r.er * xq.x + r.ei * xq.y, r.er * xq.y - r.ei * xq.x);
+          v[i][r.p] = make_double2(r.c * xp.x - r.s * eq.x, r.c * xp.y - r.s * eq.y);
+          v[i][r.q] = make_double2(r.s * xp.x + r.c * eq.x, r.s * xp.y + r.c * eq.y);
+        }
+      }
+      __syncthreads();
+      // exact zero of the annihilated entries and real diagonal
+      if (tid < n / 2) {
+        const Rot r = rot[tid];
+        if (r.s != 0.0) {
+          a[r.p][r.q] = make_double2(0, 0);
+          a[r.q][r.p] = make_double2(0, 0);
+          a[r.p][r.p].y = 0.0;
+          a[r.q][r.q].y = 0.0;
+        }
+      }
+      __syncthreads();
+    }
+    const int go = any_rot;
+    __syncthreads();
+    if (!go) break;
+  }
+
+  // eigenvalues (real diagonal) and ascending order (stable in index)
+  for (int i = tid; i < n; i += kJacThreads) lam[i] = a[i][i].x;
+  __syncthreads();
+  for (int i = tid; i < nb; i += kJacThreads) {
+    int rk = 0;
+    const double li = lam[i];
+    for (int j = 0; j < nb; ++j) {
+      const double lj = lam[j];
+      rk += (lj < li) || (lj == li && j < i);
+    }
+    rank[i] = rk;
+  }
+  __syncthreads();
+  double* ev = evals + (long long)b * nb;
+  double2* Ob = reinterpret_cast<double2*>(out + 2 * (long long)b * mat_stride);
+  if (mode == 0) {
+    for (int i = tid; i < nb; i += kJacThreads) ev[rank[i]] = lam[i];
+    for (int t = tid; t < nb * nb; t += kJacThreads) {
+      const int r = t / nb, c = t % nb;   // component r of eigenvector c
+      Ob[(long long)r * nb + rank[c]] = v[r][c];
+    }
+  } else {
+    // T[:, k] = D U[:, k] / sqrt(lambda_k) with a floor on tiny lambda
+    double lmax = 0.0;
+    for (int i = 0; i < nb; ++i) lmax = fmax(lmax, lam[i]);
+    const double floor_ = lmax * 1e-15;
+    int bad = 0;
+    for (int i = tid; i < nb; i += kJacThreads) {
+      ev[rank[i]] = lam[i];
+      if (!(lam[i] > floor_)) bad = 1;
+    }
+    if (bad && status) atomicOr(status + b, 1);
+    for (int t = tid; t < nb * nb; t += kJacThreads) {
+      const int r = t / nb, c = t % nb;
+      const double l = lam[c] > floor_ ? lam[c] : floor_;
+      const double s = dscale[r] / sqrt(l);
+      Ob[(long long)r * nb + rank[c]] = make_double2(v[r][c].x * s, v[r][c].y * s);
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// control: residual norms -> convergence; Ritz values -> next filter interval
+// ---------------------------------------------------------------------------
+__global__ void control_kernel(Control c, int nb, int nev, int degree, int kmax, double tol,
+                               int mixed, int allow_switch, int iter) {
+  const int b = blockIdx.x;
+  if (threadIdx.x != 0) return;
+  int* fl = c.flags + 8 * b;
+  if (fl[0]) {   // done before this iteration: keep its results
+    c.active[b] = 0;
+    c.act32[b] = 0;
+    c.act64[b] = 0;
+    return;
+  }
+  const double* th = c.theta + (long long)b * nb;
+  const double* r2 = c.r2 + (long long)b * nb;
+  double* bd = c.bounds + 4 * b;
+  int nconv = 0;
+  double rmax = 0.0;
+  for (int j = 0; j < nev; ++j) {
+    const double r = sqrt(r2[j]);
+    if (r <= tol) ++nconv;
+    rmax = fmax(rmax, r);
+  }
+  const int it = fl[3] + 1;   // outer iterations so far (counted on the device)
+  fl[3] = it;
+  fl[4] = nconv;
+  if (nconv == nev) fl[0] = 1;
+  // mixed precision: leave the FP32 filter when it can no longer reduce the
+  // residual (stagnation over two iterations), or once residuals sit within
+  // ~30 FP32 ulps of the spectral radius while the target lies below that
+  if (mixed && allow_switch && !fl[1] && !fl[0]) {
+    const double prev = bd[3];
+    const double floor32 = 30.0 * 5.96e-8 * bd[0];
+    if (rmax > 0.5 * prev && prev > 0.0) fl[2] += 1; else fl[2] = 0;
+    if (fl[2] >= 2 || (rmax < floor32 && tol < floor32)) {
+      fl[1] = 1;
+      fl[5] = it + 1;
+    }
+  }
+  bd[3] = rmax;
+  c.active[b] = fl[0] ? 0 : 1;
+  c.act32[b] = (!fl[0] && mixed && !fl[1]) ? 1 : 0;
+  c.act64[b] = (!fl[0] && !(mixed && !fl[1])) ? 1 : 0;
+  // next filter: damp [a_cut, b_up], scaled to 1 at a0 = lowest Ritz value
+  const double bup = bd[0];
+  double acut = th[nb - 1];
+  const double a0 = th[0];
+  if (acut - a0 < 1e-9 * (bup - a0)) acut = a0 + 1e-9 * (bup - a0);
+  bd[1] = acut;
+  bd[2] = a0;
+  const double e = 0.5 * (bup - acut), cc = 0.5 * (bup + acut);
+  const double sigma1 = e / (a0 - cc);
+  double* co = c.coef + (long long)b * kmax * 4;
+  double sig = sigma1;
+  co[0] = sigma1 / e;
+  co[1] = cc;
+  co[2] = 0.0;
+  for (int k = 1; k < degree && k < kmax; ++k) {
+    const double sn = 1.0 / (2.0 / sigma1 - sig);
+    co[4 * k] = 2.0 * sn / e;
+    co[4 * k + 1] = cc;
+    co[4 * k + 2] = -sig * sn;
+    sig = sn;
+  }
+}
+
+// first filter coefficients from the bounds alone (before any Rayleigh-Ritz)
+__global__ void init_coef_kernel(Control c, int degree, int kmax) {
+  const int b = blockIdx.x;
+  if (threadIdx.x != 0) return;
+  double* bd = c.bounds + 4 * b;
+  const double bup = bd[0], acut = bd[1], a0 = bd[2];
+  const double e = 0.5 * (bup - acut), cc = 0.5 * (bup + acut);
+  const double sigma1 = e / (a0 - cc);
+  double* co = c.coef + (long long)b * kmax * 4;
+  double sig = sigma1;
+  co[0] = sigma1 / e;
+  co[1] = cc;
+  co[2] = 0.0;
+  for (int k = 1; k < degree && k < kmax; ++k) {
+    const double sn = 1.0 / (2.0 / sigma1 - sig);
+    co[4 * k] = 2.0 * sn / e;
+    co[4 * k + 1] = cc;
+    co[4 * k + 2] = -sig * sn;
+    sig = sn;
+  }
+}
+
+// eig[b][j] = theta[b][j], resid[b][j] = sqrt(r2[b][j]) for j < nev
+__global__ void finish_kernel(const double* theta, const double* r2, int nb, int nev, int batch,
+                              double* eig, double* resid) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= batch * nev) return;
+  const int b = t / nev, j = t % nev;
+  if (eig) eig[t] = theta[(long long)b * nb + j];
+  if (resid) resid[t] = sqrt(r2[(long long)b * nb + j]);
+}
+
+__global__ void finite_kernel(const double* x, long long count, int* flag) {
+  int bad = 0;
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < count;
+       i += (long long)gridDim.x * blockDim.x)
+    bad |= !isfinite(x[i]);
+  if (bad) atomicOr(flag, 1);
+}
+
+__global__ void fill_int_kernel(int* p, int count, int value) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < count) p[t] = value;
+}
+
+}  // namespace
+
+hipError_t launch_finish(const double* theta, const double* r2, int nb, int nev, int batch,
+                         double* eig, double* resid, hipStream_t s) {
+  const int cnt = batch * nev;
+  finish_kernel<<<(cnt + 255) / 256, 256, 0, s>>>(theta, r2, nb, nev, batch, eig, resid);
+  return hipGetLastError();
+}
+
+hipError_t launch_check_finite(const double* x, long long count, int* flag, hipStream_t s) {
+  long long g = (count + 255) / 256;
+  if (g > 2048) g = 2048;
+  if (g < 1) g = 1;
+  finite_kernel<<<(unsigned)g, 256, 0, s>>>(x, count, flag);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill_int(int* p, int count, int value, hipStream_t s) {
+  if (count <= 0) return hipSuccess;
+  fill_int_kernel<<<(count + 255) / 256, 256, 0, s>>>(p, count, value);
+  return hipGetLastError();
+}
+
+hipError_t launch_heev(double* A, int nb, int batch, long long mat_stride, double* evals,
+                       double* out, int mode, int* status, const int* active, hipStream_t s) {
+  if (nb > HKP_NB_MAX || nb < 1) return hipErrorInvalidValue;
+  heev_kernel<<<batch, kJacThreads, 0, s>>>(A, nb, mat_stride, evals, out, mode, status, active);
+  return hipGetLastError();
+}
+
+hipError_t launch_control(const Control& c, int batch, int nb, int nev, int degree, int kmax,
+                          double tol, int mixed, int allow_switch, int iter, hipStream_t s) {
+  control_kernel<<<batch, 64, 0, s>>>(c, nb, nev, degree, kmax, tol, mixed, allow_switch, iter);
+  return hipGetLastError();
+}
+
+hipError_t launch_init_coef(const Control& c, int batch, int degree, int kmax, hipStream_t s) {
+  init_coef_kernel<<<batch, 64, 0, s>>>(c, degree, kmax);
+  return hipGetLastError();
+}
+
+}  // namespace hkp

@@ -1,0 +1,299 @@
+// Field setup, boundary transforms, the gate -> potential map and the
+// Hellmann-Feynman gradient.
+#include "hkp_internal.h"
+
+namespace hkp {
+
+namespace {
+
+constexpr double kS3 = 1.7320508075688772935;
+constexpr double kS2 = 1.4142135623730950488;
+constexpr double kInvS6 = 0.40824829046386301637;
+
+// psi_J = U psi_LS at every grid point.  Rows: |J m_j> (|3/2,+3/2>, |3/2,+1/2>,
+// |3/2,-1/2>, |3/2,-3/2>, |1/2,+1/2>, |1/2,-1/2>), columns: |X up>, |Y up>,
+// |Z up>, |X dn>, |Y dn>, |Z dn>; every entry times 1/sqrt(6).  These are the
+// standard p-orbital expansions of the |J m_j> states, e.g.
+// |3/2,+3/2> = -(i/sqrt2) (X + iY) up, in the phase convention in which the
+// |J m_j> Hamiltonian takes the Luttinger-Kohn layout of Eq. LK.
+__constant__ double kUre[6][6] = {
+    {0, kS3, 0, 0, 0, 0},
+    {0, 0, 0, 0, 1, 0},
+    {0, 1, 0, 0, 0, 0},
+    {0, 0, 0, 0, kS3, 0},
+    {0, 0, 0, 0, -kS2, 0},
+    {0, kS2, 0, 0, 0, 0}};
+__constant__ double kUim[6][6] = {
+    {kS3, 0, 0, 0, 0, 0},
+    {0, 0, -2, 1, 0, 0},
+    {-1, 0, 0, 0, 0, -2},
+    {0, 0, 0, -kS3, 0, 0},
+    {0, 0, -kS2, -kS2, 0, 0},
+    {-kS2, 0, 0, 0, 0, kS2}};
+
+__device__ __forceinline__ double2 cmul(double2 a, double2 b) {
+  return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+
+// gauge function chi (coordinates about the box centre)
+__device__ __forceinline__ double chi_at(int i, int j, int k, int nx, int ny, int nz, double h,
+                                         double Bx, double By, double Bz) {
+  const double X = (i - 0.5 * (nx - 1)) * h, Y = (j - 0.5 * (ny - 1)) * h,
+               Z = (k - 0.5 * (nz - 1)) * h;
+  return -0.5 * Bz * X * Y - 0.5 * By * X * Z + 0.5 * Bx * Y * Z;
+}
+
+__global__ void onsite_kernel(int nx, int ny, int nz, const double* V, long long V_bstride,
+                              const double* strain, double l_, double m_, double n_,
+                              double* D64, float* D32, long long D_bstride, int with_strain) {
+  const long long N = (long long)nx * ny * nz;
+  const long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const int b = blockIdx.y;
+  if (p >= N) return;
+  // internal index p = (z ny + y) nx + x
+  const int x = (int)(p % nx);
+  const int y = (int)((p / nx) % ny);
+  const int z = (int)(p / ((long long)nx * ny));
+  const long long a = ((long long)x * ny + y) * nz + z;  // ABI index
+  const double v = V[(long long)b * V_bstride + a];
+  double d[6];
+  if (with_strain) {
+    const double* e = strain + 6 * a;
+    const double tr = e[0] + e[1] + e[2];
+    d[0] = v + l_ * e[0] + m_ * (tr - e[0]);
+    d[1] = v + l_ * e[1] + m_ * (tr - e[1]);
+    d[2] = v + l_ * e[2] + m_ * (tr - e[2]);
+    d[3] = n_ * e[3];  // yz
+    d[4] = n_ * e[4];  // xz
+    d[5] = n_ * e[5];  // xy
+  } else {
+    d[0] = v;
+  }
+  const int nd = with_strain ? 6 : 1;
+  double* o64 = D64 + (long long)b * D_bstride;
+  for (int c = 0; c < nd; ++c) o64[c * N + p] = d[c];
+  if (D32) {
+    float* o32 = D32 + (long long)b * D_bstride;
+    for (int c = 0; c < nd; ++c) o32[c * N + p] = (float)d[c];
+  }
+}
+
+__global__ void phase_kernel(int nx, int nz, double h, double Bx, double By, double Bz,
+                             double* w64, double* v64, float* w32, float* v32) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  const double kh = kEoverHbar * h;
+  if (t < nz) {
+    const double Z = (t - 0.5 * (nz - 1)) * h;
+    double s, c;
+    sincos(kh * By * Z, &s, &c);
+    w64[2 * t] = c;
+    w64[2 * t + 1] = s;
+    if (w32) {
+      w32[2 * t] = (float)c;
+      w32[2 * t + 1] = (float)s;
+    }
+  }
+  if (t < nx * nz) {
+    const int x = t % nx, z = t / nx;
+    const double X = (x - 0.5 * (nx - 1)) * h, Z = (z - 0.5 * (nz - 1)) * h;
+    double s, c;
+    sincos(kh * (Bz * X - Bx * Z), &s, &c);
+    v64[2 * t] = c;
+    v64[2 * t + 1] = s;
+    if (v32) {
+      v32[2 * t] = (float)c;
+      v32[2 * t + 1] = (float)s;
+    }
+  }
+}
+
+// ABI block [v][x][y][z][6] (J, symmetric gauge) -> internal [v][c][z][y][x] (LS, GPU gauge)
+template <typename TO>
+__global__ void abi_to_internal_kernel(int nx, int ny, int nz, double h, double Bx, double By,
+                                       double Bz, const double2* abi, TO* internal) {
+  const long long N = (long long)nx * ny * nz;
+  const long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const int v = blockIdx.y;
+  if (p >= N) return;
+  const int x = (int)(p % nx);
+  const int y = (int)((p / nx) % ny);
+  const int z = (int)(p / ((long long)nx * ny));
+  const long long a = ((long long)x * ny + y) * nz + z;
+  const double2* src = abi + ((long long)v * N + a) * 6;
+  double2 j[6];
+  for (int c = 0; c < 6; ++c) j[c] = src[c];
+  double s, co;
+  sincos(kEoverHbar * chi_at(x, y, z, nx, ny, nz, h, Bx, By, Bz), &s, &co);
+  const double2 g = make_double2(co, s);  // exp(+i k chi)
+  for (int c = 0; c < 6; ++c) {
+    // (U^H psi_J)_c = sum_j conj(U_jc) psi_J,j
+    double2 acc = make_double2(0, 0);
+    for (int r = 0; r < 6; ++r) {
+      const double2 u = make_double2(kUre[r][c] * kInvS6, -kUim[r][c] * kInvS6);
+      const double2 t = cmul(u, j[r]);
+      acc.x += t.x;
+      acc.y += t.y;
+    }
+    acc = cmul(g, acc);
+    TO* dst = internal + 2 * (((long long)v * 6 + c) * N + p);
+    dst[0] = (TO)acc.x;
+    dst[1] = (TO)acc.y;
+  }
+}
+
+__global__ void internal_to_abi_kernel(int nx, int ny, int nz, double h, double Bx, double By,
+                                       double Bz, const double2* internal, long long in_bstride,
+                                       double2* abi, long long abi_bstride, int nvec) {
+  const long long N = (long long)nx * ny * nz;
+  const long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const int v = blockIdx.y;
+  const int b = blockIdx.z;
+  if (p >= N) return;
+  const int x = (int)(p % nx);
+  const int y = (int)((p / nx) % ny);
+  const int z = (int)(p / ((long long)nx * ny));
+  const long long a = ((long long)x * ny + y) * nz + z;
+  double2 l[6];
+  const double2* src = internal + (long long)b * in_bstride + (long long)v * 6 * N;
+  double s, co;
+  sincos(kEoverHbar * chi_at(x, y, z, nx, ny, nz, h, Bx, By, Bz), &s, &co);
+  const double2 g = make_double2(co, -s);  // exp(-i k chi)
+  for (int c = 0; c < 6; ++c) l[c] = cmul(g, src[(long long)c * N + p]);
+  double2* dst = abi + (long long)b * abi_bstride + ((long long)v * N + a) * 6;
+  for (int r = 0; r < 6; ++r) {
+    double2 acc = make_double2(0, 0);
+    for (int c = 0; c < 6; ++c) {
+      const double2 u = make_double2(kUre[r][c] * kInvS6, kUim[r][c] * kInvS6);
+      const double2 t = cmul(u, l[c]);
+      acc.x += t.x;
+      acc.y += t.y;
+    }
+    dst[r] = acc;
+  }
+}
+
+__global__ void gate_kernel(long long N, int G, const double* Vbg, const double* L,
+                            const double* Vg, double* out) {
+  const long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= N) return;
+  double v = Vbg[p];
+  for (int g = 0; g < G; ++g) v = fma(Vg[g], L[(long long)g * N + p], v);
+  out[p] = v;
+}
+
+constexpr int kHfThreads = 256;
+constexpr int kHfMaxG = 16;
+
+// grad partials: one value per (block, g); the density is formed on the fly
+__global__ void __launch_bounds__(kHfThreads)
+hf_partial_kernel(long long N, int nev, const double2* psi, const double* w, int G,
+                  const double* L, double* partial) {
+  double acc[kHfMaxG];
+  for (int g = 0; g < kHfMaxG; ++g) acc[g] = 0.0;
+  for (long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x; p < N;
+       p += (long long)gridDim.x * blockDim.x) {
+    double dens = 0.0;
+    for (int n = 0; n < nev; ++n) {
+      const double2* q = psi + ((long long)n * N + p) * 6;
+      double s = 0.0;
+#pragma unroll
+      for (int c = 0; c < 6; ++c) {
+        const double2 v = q[c];
+        s = fma(v.x, v.x, fma(v.y, v.y, s));
+      }
+      dens = fma(w[n], s, dens);
+    }
+    for (int g = 0; g < G; ++g) acc[g] = fma(dens, L[(long long)g * N + p], acc[g]);
+  }
+  __shared__ double red[kHfThreads / 64][kHfMaxG];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  for (int g = 0; g < G; ++g) {
+    double v = acc[g];
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+    if (lane == 0) red[wv][g] = v;
+  }
+  __syncthreads();
+  if (threadIdx.x < G) {
+    double v = 0.0;
+    for (int k = 0; k < kHfThreads / 64; ++k) v += red[k][threadIdx.x];
+    partial[(long long)blockIdx.x * G + threadIdx.x] = v;
+  }
+}
+
+__global__ void hf_reduce_kernel(int nblk, int G, const double* partial, double* grad) {
+  const int g = threadIdx.x;
+  if (g >= G) return;
+  double v = 0.0;
+  for (int k = 0; k < nblk; ++k) v += partial[(long long)k * G + g];
+  grad[g] = v;
+}
+
+}  // namespace
+
+hipError_t launch_onsite(const hkp_material& m, int nx, int ny, int nz, int batch,
+                         const double* V, long long V_bstride, const double* strain,
+                         double* D64, float* D32, long long D_bstride, hipStream_t s) {
+  const long long N = (long long)nx * ny * nz;
+  // Bir-Pikus orbital coefficients in the hole picture
+  const double l_ = -(m.a_v_eV + 2.0 * m.b_eV);
+  const double m_ = -(m.a_v_eV - m.b_eV);
+  const double n_ = -kS3 * m.d_eV;
+  dim3 grid((unsigned)((N + 255) / 256), (unsigned)batch);
+  onsite_kernel<<<grid, 256, 0, s>>>(nx, ny, nz, V, V_bstride, strain, l_, m_, n_, D64, D32,
+                                     D_bstride, strain != nullptr);
+  return hipGetLastError();
+}
+
+hipError_t launch_phase_tables(int nx, int nz, double h, const double B[3], double* w64,
+                               double* v64, float* w32, float* v32, hipStream_t s) {
+  const int n = nx * nz > nz ? nx * nz : nz;
+  phase_kernel<<<(n + 255) / 256, 256, 0, s>>>(nx, nz, h, B[0], B[1], B[2], w64, v64, w32, v32);
+  return hipGetLastError();
+}
+
+hipError_t launch_abi_to_internal(int nx, int ny, int nz, double h, const double B[3],
+                                  int nvec, const void* abi, void* internal, int to_fp32,
+                                  hipStream_t s) {
+  const long long N = (long long)nx * ny * nz;
+  dim3 grid((unsigned)((N + 255) / 256), (unsigned)nvec);
+  if (to_fp32)
+    abi_to_internal_kernel<float><<<grid, 256, 0, s>>>(
+        nx, ny, nz, h, B[0], B[1], B[2], (const double2*)abi, (float*)internal);
+  else
+    abi_to_internal_kernel<double><<<grid, 256, 0, s>>>(
+        nx, ny, nz, h, B[0], B[1], B[2], (const double2*)abi, (double*)internal);
+  return hipGetLastError();
+}
+
+hipError_t launch_internal_to_abi(int nx, int ny, int nz, double h, const double B[3],
+                                  int nvec, int batch, const void* internal,
+                                  long long in_bstride, void* abi, long long abi_bstride,
+                                  hipStream_t s) {
+  const long long N = (long long)nx * ny * nz;
+  dim3 grid((unsigned)((N + 255) / 256), (unsigned)nvec, (unsigned)batch);
+  internal_to_abi_kernel<<<grid, 256, 0, s>>>(nx, ny, nz, h, B[0], B[1], B[2],
+                                              (const double2*)internal, in_bstride,
+                                              (double2*)abi, abi_bstride, nvec);
+  return hipGetLastError();
+}
+
+hipError_t launch_gate_potential(long long N, int G, const double* Vbg, const double* L,
+                                 const double* Vg, double* out, hipStream_t s) {
+  gate_kernel<<<(unsigned)((N + 255) / 256), 256, 0, s>>>(N, G, Vbg, L, Vg, out);
+  return hipGetLastError();
+}
+
+int hf_blocks() { return 1024; }
+
+size_t hf_partial_bytes(int G) { return (size_t)hf_blocks() * G * 8; }
+
+hipError_t launch_hf_grad(long long N, int nev, const void* psi, const double* w, int G,
+                          const double* L, double* partial, double* grad, hipStream_t s) {
+  if (G > kHfMaxG) return hipErrorInvalidValue;
+  const int nblk = hf_blocks();
+  hf_partial_kernel<<<nblk, kHfThreads, 0, s>>>(N, nev, (const double2*)psi, w, G, L, partial);
+  hf_reduce_kernel<<<1, 64, 0, s>>>(nblk, G, partial, grad);
+  return hipGetLastError();
+}
+
+}  // namespace hkp

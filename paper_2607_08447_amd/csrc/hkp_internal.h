@@ -1,0 +1,174 @@
+// Internal declarations shared by the host orchestration and the HIP kernels.
+//
+// Internal data layout (device, HBM):
+//   spinor block   complex [vec][c][z][y][x], c = 0..5 in the |L S> basis
+//                  |X up>,|Y up>,|Z up>,|X dn>,|Y dn>,|Z dn> (spin-major),
+//                  x fastest; one (vec, c) slice is a contiguous 3-D field.
+//   onsite fields  real [6][z][y][x]: d00 d11 d22 d12 d02 d01 of the orbital
+//                  3x3 block V + H_eps (strain present), or [z][y][x] = V.
+//   gauge          A' = (By (z-z0), Bz (x-x0) - Bx (z-z0), 0): links along z
+//                  carry no phase, x-links a phase per plane, y-links a phase
+//                  per (plane, column).  Related to the symmetric gauge of the
+//                  ABI by psi_sym = exp(-i (e/hbar) chi) psi' with
+//                  chi = -Bz XY/2 - By XZ/2 + Bx YZ/2 (coordinates about r0).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+
+#include "hkp.h"
+
+namespace hkp {
+
+void set_error(const std::string& msg);   // thread-local message for hkp_last_error
+
+constexpr double kE0 = 0.0380998212;          // hbar^2/(2 m0), eV nm^2
+constexpr double kMuB = 5.7883818060e-5;      // eV/T
+constexpr double kEoverHbar = 1.519267447e-3; // 1/(T nm^2)
+
+// ---------------------------------------------------------------------------
+// stencil constants (host-computed in double, converted to the kernel type)
+// ---------------------------------------------------------------------------
+template <typename T>
+struct StencilConsts {
+  T cLM, cM, czZ, cN8;   // face and edge coefficients
+  T dgU, dgD;            // spin-diagonal onsite constant (kinetic centre + SO/Zeeman)
+  T aUx, aUy, aUz;       // i (aU x v) term of the up block
+  T aDx, aDy, aDz;       // i (aD x v) term of the down block
+  T d3;                  // Delta/3 (spin-flip spin-orbit)
+  T bx, by;              // mu_B Bx, mu_B By (spin-flip Zeeman)
+};
+
+StencilConsts<double> make_consts(const hkp_material& m, double h, const double B[3]);
+template <typename T>
+StencilConsts<T> cast_consts(const StencilConsts<double>& c);
+
+// Chebyshev step coefficients, device array [batch][kmax][4] = alpha, shift, beta, pad
+struct StepCoef {
+  const double* coef;  // may be null: use the host values below
+  int stride;          // doubles between batch members
+  double alpha, shift, beta;
+};
+
+struct StencilLaunch {
+  int nx, ny, nz;
+  int nvec;              // vectors per Hamiltonian in this launch
+  int batch;             // Hamiltonians
+  const void* in;        // kernel-type complex block
+  long long in_bstride;  // complex elements between Hamiltonians
+  const void* old;       // may be null (beta = 0)
+  int old_fp64;          // element type of old
+  long long old_bstride;
+  void* out;
+  int out_fp64;
+  long long out_bstride;
+  const void* D;         // onsite fields (kernel type)
+  long long D_bstride;   // reals between Hamiltonians
+  int strain;            // D holds 6 arrays
+  const void* wtab;      // [nz] complex, kernel type, or null (B = 0)
+  const void* vtab;      // [nz][nx] complex
+  StepCoef coef;
+  const int* active;     // [batch] 0 = skip, or null
+  int tile_y;            // 1, 2, 4, 8
+  int fp64;              // kernel type
+};
+
+hipError_t launch_stencil(const StencilLaunch& a, const StencilConsts<double>& c,
+                          hipStream_t s);
+
+// ---------------------------------------------------------------------------
+// field setup and boundary transforms
+// ---------------------------------------------------------------------------
+hipError_t launch_onsite(const hkp_material& m, int nx, int ny, int nz, int batch,
+                         const double* V, long long V_bstride, const double* strain,
+                         double* D64, float* D32, long long D_bstride, hipStream_t s);
+hipError_t launch_phase_tables(int nx, int nz, double h, const double B[3], double* w64,
+                               double* v64, float* w32, float* v32, hipStream_t s);
+// ABI (J basis, symmetric gauge, [v][x][y][z][6]) <-> internal (LS, GPU gauge)
+hipError_t launch_abi_to_internal(int nx, int ny, int nz, double h, const double B[3],
+                                  int nvec, const void* abi, void* internal, int to_fp32,
+                                  hipStream_t s);
+hipError_t launch_internal_to_abi(int nx, int ny, int nz, double h, const double B[3],
+                                  int nvec, int batch, const void* internal,
+                                  long long in_bstride, void* abi, long long abi_bstride,
+                                  hipStream_t s);
+hipError_t launch_gate_potential(long long N, int G, const double* Vbg, const double* L,
+                                 const double* Vg, double* out, hipStream_t s);
+size_t hf_partial_bytes(int G);
+hipError_t launch_hf_grad(long long N, int nev, const void* psi, const double* w, int G,
+                          const double* L, double* partial, double* grad, hipStream_t s);
+
+// ---------------------------------------------------------------------------
+// block linear algebra
+// ---------------------------------------------------------------------------
+struct BlockDesc {   // complex double block set: [batch][nvec][n]
+  double* ptr;       // as doubles (re, im interleaved)
+  long long n;       // complex elements per vector
+  int nvec;
+  long long bstride; // complex elements between Hamiltonians
+};
+
+// partial Gram of A^H B over chunks (MFMA f64); out: [batch][nb_a][nb_b] complex
+int gram_chunks(long long n, int batch);
+size_t gram_partial_bytes(int nb, long long n, int batch);
+hipError_t launch_gram(const BlockDesc& A, const BlockDesc& B, int hermitian, int batch,
+                       double* partial, double* out, const int* active, hipStream_t s);
+// X[:, 0:nout] <- X[:, 0:nin] Q (Q complex [batch][nin][nout], column-major by
+// output), in place allowed
+hipError_t launch_rotate(const BlockDesc& X, const BlockDesc& Y, int nin, int nout,
+                         const double* Q, int batch, const int* active, hipStream_t s);
+// r[b][j] = || W_j - theta_j X_j ||^2 partial sums -> r
+hipError_t launch_resid(const BlockDesc& X, const BlockDesc& W, const double* theta,
+                        int batch, double* partial, double* r, const int* active,
+                        hipStream_t s);
+// Y1 = alpha (W - shift X) (first filter step from a known W = H X)
+hipError_t launch_cheb_first(const BlockDesc& X, const BlockDesc& W, void* out, int out_fp64,
+                             long long out_bstride, int batch, const double* coef,
+                             int coef_stride, const int* active, hipStream_t s);
+hipError_t launch_cast(const void* in, int in_fp64, void* out, int out_fp64, long long count,
+                       hipStream_t s);
+hipError_t launch_random_block(double* X, long long n, int nvec, int batch, long long bstride,
+                               unsigned long long seed, hipStream_t s);
+// per-vector complex dot products (conj(a) . b) and norms for Lanczos
+hipError_t launch_dots(const double* a, const double* b, long long n, int batch,
+                       long long bstride, double* partial, double* out, hipStream_t s);
+hipError_t launch_lanczos_update(double* w, const double* v, const double* vprev, long long n,
+                                 int batch, long long bstride, const double* alpha,
+                                 const double* beta, hipStream_t s);
+hipError_t launch_scale(double* v, long long n, int batch, long long bstride,
+                        const double* norm2, hipStream_t s);
+
+// ---------------------------------------------------------------------------
+// small dense eigenproblems (one workgroup per matrix)
+// ---------------------------------------------------------------------------
+// mode 0 (RR):   A Hermitian nb x nb -> eigenvalues theta (ascending) and
+//                eigenvectors Q (columns), written over A's buffer layout
+// mode 1 (SVQB): A = Gram S -> T = D U diag(lambda)^-1/2, D = diag(S)^-1/2
+hipError_t launch_heev(double* A, int nb, int batch, long long mat_stride, double* evals,
+                       double* out, int mode, int* status, const int* active, hipStream_t s);
+
+// control: convergence flags, next Chebyshev coefficients
+struct Control {
+  double* theta;     // [batch][nb]
+  double* r2;        // [batch][nb] squared residuals
+  double* coef;      // [batch][kmax*4]
+  double* bounds;    // [batch][4]: b_upper, a_cut, a0, last rmax
+  int* flags;        // [batch][8]: done, fp64, stagnation, iters, nconv, switch iter
+  int* active;       // [batch] not converged
+  int* act32;        // [batch] not converged, FP32 filter
+  int* act64;        // [batch] not converged, FP64 filter
+};
+hipError_t launch_control(const Control& c, int batch, int nb, int nev, int degree,
+                          int kmax, double tol, int mixed, int allow_switch, int iter,
+                          hipStream_t s);
+hipError_t launch_finish(const double* theta, const double* r2, int nb, int nev, int batch,
+                         double* eig, double* resid, hipStream_t s);
+hipError_t launch_check_finite(const double* x, long long count, int* flag, hipStream_t s);
+hipError_t launch_fill_int(int* p, int count, int value, hipStream_t s);
+hipError_t launch_init_coef(const Control& c, int batch, int degree, int kmax,
+                            hipStream_t s);
+
+}  // namespace hkp

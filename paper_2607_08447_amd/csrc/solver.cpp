@@ -1,0 +1,682 @@
+// Host orchestration of the Chebyshev-filtered subspace iteration (the
+// Rayleigh-Chebyshev method named in the paper, Sec. II.B):
+//
+//   bounds   k-step Lanczos -> upper spectral bound b
+//   init     random block, SVQB, Rayleigh-Ritz
+//   repeat   filter:  Y = p_m(H) X, scaled three-term Chebyshev recurrence on
+//                     [a_cut, b] (a_cut = largest Ritz value of the block,
+//                     normalised at the lowest Ritz value) -- m fused stencil
+//                     steps, FP64 or FP32 (mixed precision)
+//            orth:    SVQB twice (Gram, Jacobi eig, rotate), FP64
+//            RR:      W = H X (FP64), X^H W, Jacobi eig, X <- X Q, W <- W Q
+//            resid:   ||W_j - theta_j X_j||, convergence and next interval
+//   until    the nev lowest residuals are <= tol
+//
+// All per-iteration decisions (convergence, precision switch, filter
+// coefficients) are made on the device, so one outer iteration is a fixed
+// sequence of launches.  Eager mode reads the flags after every iteration;
+// graph mode records a batch of iterations once and replays it.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <functional>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "hkp_internal.h"
+#include "solver.h"
+
+namespace hkp {
+
+namespace {
+
+struct HipError : std::runtime_error {
+  using std::runtime_error::runtime_error;
+};
+
+#define HKP_CHECK(x)                                                                   \
+  do {                                                                                 \
+    hipError_t e_ = (x);                                                               \
+    if (e_ != hipSuccess)                                                              \
+      throw HipError(std::string(#x) + ": " + hipGetErrorString(e_));                  \
+  } while (0)
+
+size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
+
+constexpr int kLanczosSteps = 40;
+constexpr int kKmax = 200;       // largest Chebyshev degree
+constexpr int kDotParts = 256;
+constexpr int kResParts = 64;
+
+struct Layout {
+  size_t D64, D32, w64, v64, w32, v32, X, W, A32, B32, gram, mat1, mat2, theta, lam, r2, rpart,
+      coef, bounds, flags, active, act32, act64, status, lal, lnrm, lpart, total;
+};
+
+Layout make_layout(const Plan& p) {
+  Layout L{};
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    size_t o = off;
+    off += align_up(bytes);
+    return o;
+  };
+  const size_t B = p.batch;
+  const size_t N = p.N, n6 = p.n6;
+  L.D64 = take(B * 6 * N * 8);
+  L.D32 = p.mixed ? take(B * 6 * N * 4) : 0;
+  L.w64 = take((size_t)p.nz * 16);
+  L.v64 = take((size_t)p.nz * p.nx * 16);
+  L.w32 = take((size_t)p.nz * 8);
+  L.v32 = take((size_t)p.nz * p.nx * 8);
+  L.X = take(B * p.nb * n6 * 16);
+  L.W = take(B * p.nb * n6 * 16);
+  if (p.mixed) {
+    L.A32 = take(B * p.nb * n6 * 8);
+    L.B32 = take(B * p.nb * n6 * 8);
+  }
+  L.gram = take(gram_partial_bytes(p.nb, n6, p.batch));
+  L.mat1 = take(B * p.nb * p.nb * 16);
+  L.mat2 = take(B * p.nb * p.nb * 16);
+  L.theta = take(B * p.nb * 8);
+  L.lam = take(B * p.nb * 8);
+  L.r2 = take(B * p.nb * 8);
+  L.rpart = take(B * p.nb * kResParts * 8);
+  L.coef = take(B * kKmax * 4 * 8);
+  L.bounds = take(B * 4 * 8);
+  L.flags = take(B * 8 * 4);
+  L.active = take(B * 4);
+  L.act32 = take(B * 4);
+  L.act64 = take(B * 4);
+  L.status = take(B * 4 + 4);
+  L.lal = take((size_t)kLanczosSteps * B * 16);
+  L.lnrm = take((size_t)(kLanczosSteps + 1) * B * 16);
+  L.lpart = take(B * kDotParts * 16);
+  L.total = off;
+  return L;
+}
+
+// largest and smallest eigenvalue of a symmetric tridiagonal matrix (Sturm bisection)
+int sturm_count(const std::vector<double>& a, const std::vector<double>& b2, double x) {
+  // number of eigenvalues < x; b2[i] = beta_i^2 couples i-1 and i
+  int cnt = 0;
+  double d = a[0] - x;
+  if (d < 0) ++cnt;
+  for (size_t i = 1; i < a.size(); ++i) {
+    if (d == 0) d = 1e-300;
+    d = a[i] - x - b2[i] / d;
+    if (d < 0) ++cnt;
+  }
+  return cnt;
+}
+
+void tridiag_extremes(const std::vector<double>& a, const std::vector<double>& b2, double* lo,
+                      double* hi) {
+  const size_t k = a.size();
+  double gl = a[0], gh = a[0];
+  for (size_t i = 0; i < k; ++i) {
+    double r = 0;
+    if (i > 0) r += std::sqrt(b2[i]);
+    if (i + 1 < k) r += std::sqrt(b2[i + 1]);
+    gl = std::min(gl, a[i] - r);
+    gh = std::max(gh, a[i] + r);
+  }
+  const int kk = (int)k;
+  double l = gl, h = gh;
+  for (int it = 0; it < 200; ++it) {   // largest: count(x) < k
+    const double m = 0.5 * (l + h);
+    if (sturm_count(a, b2, m) < kk) l = m; else h = m;
+  }
+  *hi = h;
+  l = gl;
+  h = gh;
+  for (int it = 0; it < 200; ++it) {   // smallest: count(x) >= 1
+    const double m = 0.5 * (l + h);
+    if (sturm_count(a, b2, m) >= 1) h = m; else l = m;
+  }
+  *lo = l;
+}
+
+struct Ctx {
+  Plan p;
+  Layout L;
+  char* ws;
+  hipStream_t s;
+  StencilConsts<double> consts;
+  bool field;
+  bool strain;
+  template <typename T>
+  T* at(size_t off) const { return reinterpret_cast<T*>(ws + off); }
+  long long bstride() const { return (long long)p.nb * p.n6; }
+  BlockDesc blk(size_t off, int nvec) const {
+    return BlockDesc{at<double>(off), p.n6, nvec, bstride()};
+  }
+  Control control() const {
+    return Control{at<double>(L.theta), at<double>(L.r2),     at<double>(L.coef),
+                   at<double>(L.bounds), at<int>(L.flags),    at<int>(L.active),
+                   at<int>(L.act32),     at<int>(L.act64)};
+  }
+};
+
+StencilLaunch base_launch(const Ctx& c, bool fp64, int nvec) {
+  StencilLaunch a{};
+  a.nx = c.p.nx;
+  a.ny = c.p.ny;
+  a.nz = c.p.nz;
+  a.nvec = nvec;
+  a.batch = c.p.batch;
+  a.D = fp64 ? (const void*)c.at<double>(c.L.D64) : (const void*)c.at<float>(c.L.D32);
+  a.D_bstride = 6LL * c.p.N;
+  a.strain = c.strain;
+  if (c.field) {
+    a.wtab = fp64 ? (const void*)c.at<double>(c.L.w64) : (const void*)c.at<float>(c.L.w32);
+    a.vtab = fp64 ? (const void*)c.at<double>(c.L.v64) : (const void*)c.at<float>(c.L.v32);
+  }
+  a.tile_y = c.p.tile_y;
+  a.fp64 = fp64;
+  a.coef.coef = nullptr;
+  a.coef.alpha = 1.0;
+  a.coef.shift = 0.0;
+  a.coef.beta = 0.0;
+  return a;
+}
+
+// W = H X over the whole block (FP64)
+void apply_block(const Ctx& c, size_t x_off, size_t w_off, const int* active) {
+  StencilLaunch a = base_launch(c, true, c.p.nb);
+  a.in = c.at<double>(x_off);
+  a.in_bstride = c.bstride();
+  a.out = c.at<double>(w_off);
+  a.out_fp64 = 1;
+  a.out_bstride = c.bstride();
+  a.active = active;
+  HKP_CHECK(launch_stencil(a, c.consts, c.s));
+}
+
+// Chebyshev filter in FP64: the filtered block ends in X (degree even)
+void filter64(const Ctx& c, const int* active) {
+  const int m = c.p.degree;
+  const int kstride = kKmax * 4;
+  HKP_CHECK(launch_cheb_first(c.blk(c.L.X, c.p.nb), c.blk(c.L.W, c.p.nb), c.at<double>(c.L.W),
+                              1, c.bstride(), c.p.batch, c.at<double>(c.L.coef), kstride, active,
+                              c.s));
+  size_t cur = c.L.W, oth = c.L.X;
+  for (int k = 1; k < m; ++k) {
+    StencilLaunch a = base_launch(c, true, c.p.nb);
+    a.in = c.at<double>(cur);
+    a.in_bstride = c.bstride();
+    a.old = c.at<double>(oth);
+    a.old_fp64 = 1;
+    a.old_bstride = c.bstride();
+    a.out = c.at<double>(oth);
+    a.out_fp64 = 1;
+    a.out_bstride = c.bstride();
+    a.coef.coef = c.at<double>(c.L.coef) + 4 * k;
+    a.coef.stride = kstride;
+    a.active = active;
+    HKP_CHECK(launch_stencil(a, c.consts, c.s));
+    std::swap(cur, oth);
+  }
+}
+
+// Chebyshev filter in FP32 (mixed precision): X (FP64) and W = H X start it,
+// the last step writes FP64 into X
+void filter32(const Ctx& c, const int* active) {
+  const int m = c.p.degree;
+  const int kstride = kKmax * 4;
+  float* A = c.at<float>(c.L.A32);
+  float* Bf = c.at<float>(c.L.B32);
+  HKP_CHECK(launch_cheb_first(c.blk(c.L.X, c.p.nb), c.blk(c.L.W, c.p.nb), A, 0, c.bstride(),
+                              c.p.batch, c.at<double>(c.L.coef), kstride, active, c.s));
+  // step k: in = Y_k (FP32), old = Y_{k-1} (X in FP64 for k = 1), out = Y_{k+1}
+  const void* in = A;
+  const void* old = c.at<double>(c.L.X);
+  int old64 = 1;
+  float* free32 = Bf;
+  for (int k = 1; k < m; ++k) {
+    const bool last = k == m - 1;
+    StencilLaunch a = base_launch(c, false, c.p.nb);
+    a.in = in;
+    a.in_bstride = c.bstride();
+    a.old = old;
+    a.old_fp64 = old64;
+    a.old_bstride = c.bstride();
+    void* out = last ? (void*)c.at<double>(c.L.X) : (void*)(old64 ? free32 : (float*)old);
+    a.out = out;
+    a.out_fp64 = last ? 1 : 0;
+    a.out_bstride = c.bstride();
+    a.coef.coef = c.at<double>(c.L.coef) + 4 * k;
+    a.coef.stride = kstride;
+    a.active = active;
+    HKP_CHECK(launch_stencil(a, c.consts, c.s));
+    old = in;
+    old64 = 0;
+    in = out;
+  }
+}
+
+void svqb(const Ctx& c, const int* active) {
+  BlockDesc X = c.blk(c.L.X, c.p.nb);
+  HKP_CHECK(launch_gram(X, X, 1, c.p.batch, c.at<double>(c.L.gram), c.at<double>(c.L.mat1),
+                        active, c.s));
+  HKP_CHECK(launch_heev(c.at<double>(c.L.mat1), c.p.nb, c.p.batch, (long long)c.p.nb * c.p.nb,
+                        c.at<double>(c.L.lam), c.at<double>(c.L.mat2), 1, c.at<int>(c.L.status),
+                        active, c.s));
+  HKP_CHECK(launch_rotate(X, X, c.p.nb, c.p.nb, c.at<double>(c.L.mat2), c.p.batch, active, c.s));
+}
+
+void rayleigh_ritz(const Ctx& c, const int* active) {
+  BlockDesc X = c.blk(c.L.X, c.p.nb), W = c.blk(c.L.W, c.p.nb);
+  apply_block(c, c.L.X, c.L.W, active);
+  HKP_CHECK(launch_gram(X, W, 1, c.p.batch, c.at<double>(c.L.gram), c.at<double>(c.L.mat1),
+                        active, c.s));
+  HKP_CHECK(launch_heev(c.at<double>(c.L.mat1), c.p.nb, c.p.batch, (long long)c.p.nb * c.p.nb,
+                        c.at<double>(c.L.theta), c.at<double>(c.L.mat2), 0, nullptr, active,
+                        c.s));
+  HKP_CHECK(launch_rotate(X, X, c.p.nb, c.p.nb, c.at<double>(c.L.mat2), c.p.batch, active, c.s));
+  HKP_CHECK(launch_rotate(W, W, c.p.nb, c.p.nb, c.at<double>(c.L.mat2), c.p.batch, active, c.s));
+}
+
+void residuals(const Ctx& c, const int* active) {
+  HKP_CHECK(launch_resid(c.blk(c.L.X, c.p.nb), c.blk(c.L.W, c.p.nb), c.at<double>(c.L.theta),
+                         c.p.batch, c.at<double>(c.L.rpart), c.at<double>(c.L.r2), active, c.s));
+}
+
+// k-step Lanczos per Hamiltonian: upper spectral bound (theta_max + beta_k)
+void lanczos_bounds(const Ctx& c, std::vector<double>& bup) {
+  const int B = c.p.batch;
+  const long long n = c.p.n6, bs = c.bstride();
+  double* vp = c.at<double>(c.L.X);
+  double* v = c.at<double>(c.L.X) + 2 * n;
+  double* w = c.at<double>(c.L.W);
+  double* al = c.at<double>(c.L.lal);
+  double* nrm = c.at<double>(c.L.lnrm);
+  double* part = c.at<double>(c.L.lpart);
+  HKP_CHECK(launch_random_block(v, n, 1, B, bs, 0x5eedULL, c.s));
+  HKP_CHECK(launch_dots(v, v, n, B, bs, part, nrm, c.s));
+  HKP_CHECK(launch_scale(v, n, B, bs, nrm, c.s));
+  const int ksteps = (int)std::min<long long>(kLanczosSteps, std::max<long long>(2, n / 2));
+  for (int j = 0; j < ksteps; ++j) {
+    StencilLaunch a = base_launch(c, true, 1);
+    a.in = v;
+    a.in_bstride = bs;
+    a.out = w;
+    a.out_fp64 = 1;
+    a.out_bstride = bs;
+    HKP_CHECK(launch_stencil(a, c.consts, c.s));
+    double* alj = al + 2LL * j * B;
+    HKP_CHECK(launch_dots(v, w, n, B, bs, part, alj, c.s));
+    HKP_CHECK(launch_lanczos_update(w, v, j > 0 ? vp : nullptr, n, B, bs, alj,
+                                    j > 0 ? nrm + 2LL * j * B : nullptr, c.s));
+    double* nj = nrm + 2LL * (j + 1) * B;
+    HKP_CHECK(launch_dots(w, w, n, B, bs, part, nj, c.s));
+    HKP_CHECK(launch_scale(w, n, B, bs, nj, c.s));
+    double* t = vp;
+    vp = v;
+    v = w;
+    w = t;
+  }
+  std::vector<double> hal(2 * (size_t)kLanczosSteps * B), hn(2 * (size_t)(kLanczosSteps + 1) * B);
+  HKP_CHECK(hipMemcpyAsync(hal.data(), al, hal.size() * 8, hipMemcpyDeviceToHost, c.s));
+  HKP_CHECK(hipMemcpyAsync(hn.data(), nrm, hn.size() * 8, hipMemcpyDeviceToHost, c.s));
+  HKP_CHECK(hipStreamSynchronize(c.s));
+  bup.resize(B);
+  for (int b = 0; b < B; ++b) {
+    std::vector<double> a(ksteps), b2(ksteps + 1, 0.0);
+    for (int j = 0; j < ksteps; ++j) a[j] = hal[2 * ((size_t)j * B + b)];
+    for (int j = 1; j <= ksteps; ++j) b2[j] = hn[2 * ((size_t)j * B + b)];
+    double lo, hi;
+    tridiag_extremes(a, b2, &lo, &hi);
+    const double betak = std::sqrt(b2[ksteps]);
+    bup[b] = hi + betak;
+    if (!std::isfinite(bup[b])) throw std::runtime_error("Lanczos bound is not finite");
+  }
+}
+
+struct Timer {
+  hipEvent_t e0, e1;
+  bool on;
+  double acc = 0;
+  explicit Timer(bool enable) : on(enable) {
+    if (on) {
+      HKP_CHECK(hipEventCreate(&e0));
+      HKP_CHECK(hipEventCreate(&e1));
+    }
+  }
+  ~Timer() {
+    if (on) {
+      (void)hipEventDestroy(e0);
+      (void)hipEventDestroy(e1);
+    }
+  }
+  void start(hipStream_t s) {
+    if (on) HKP_CHECK(hipEventRecord(e0, s));
+  }
+  void stop(hipStream_t s) {
+    if (on) HKP_CHECK(hipEventRecord(e1, s));
+  }
+  void collect() {
+    if (!on) return;
+    float ms = 0;
+    HKP_CHECK(hipEventSynchronize(e1));
+    HKP_CHECK(hipEventElapsedTime(&ms, e0, e1));
+    acc += ms * 1e-3;
+  }
+};
+
+}  // namespace
+
+Plan make_plan(const hkp_grid& g, const hkp_opts& o, int batch) {
+  Plan p{};
+  p.nx = g.nx;
+  p.ny = g.ny;
+  p.nz = g.nz;
+  p.h = g.h_nm;
+  p.N = (long long)g.nx * g.ny * g.nz;
+  p.n6 = 6 * p.N;
+  p.batch = batch;
+  p.nev = o.nev;
+  p.nb = o.nb > 0 ? o.nb : default_nb(o.nev, p.n6);
+  int m = o.degree > 0 ? o.degree : 16;
+  if (m & 1) ++m;
+  if (m > kKmax) m = kKmax;
+  p.degree = m;
+  p.mixed = o.precision == HKP_PREC_MIXED;
+  p.tile_y = 4;
+  return p;
+}
+
+int default_nb(int nev, long long n6) {
+  int nb = nev + std::max(8, nev / 2);
+  nb = (nb + 7) / 8 * 8;
+  if (nb > HKP_NB_MAX) nb = HKP_NB_MAX;
+  if (nb > n6) nb = (int)n6;
+  return nb;
+}
+
+size_t plan_bytes(const Plan& p) { return make_layout(p).total; }
+
+int run_solve(const SolveArgs& A, hkp_stats* stats) {
+  const auto t_start = std::chrono::steady_clock::now();
+  Ctx c;
+  c.p = A.plan;
+  c.L = make_layout(c.p);
+  c.ws = reinterpret_cast<char*>(A.workspace);
+  c.s = reinterpret_cast<hipStream_t>(A.stream);
+  c.field = A.B[0] != 0.0 || A.B[1] != 0.0 || A.B[2] != 0.0;
+  c.strain = A.strain != nullptr;
+  c.consts = make_consts(A.mat, c.p.h, A.B);
+  if (A.tile_y > 0) c.p.tile_y = A.tile_y;
+  const Plan& p = c.p;
+  const bool eager = !(A.flags & HKP_FLAG_GRAPH);
+  const bool timed = eager && stats != nullptr;
+  Timer t_setup(timed), t_filter(timed), t_orth(timed), t_rr(timed), t_res(timed);
+
+  // ---- setup: on-site fields, phase tables, flags
+  t_setup.start(c.s);
+  HKP_CHECK(launch_fill_int(c.at<int>(c.L.status), p.batch + 1, 0, c.s));
+  HKP_CHECK(launch_check_finite(A.V, (long long)p.batch * p.N, c.at<int>(c.L.status) + p.batch,
+                                c.s));
+  if (A.strain)
+    HKP_CHECK(launch_check_finite(A.strain, 6LL * p.N, c.at<int>(c.L.status) + p.batch, c.s));
+  int bad = 0;
+  HKP_CHECK(hipMemcpyAsync(&bad, c.at<int>(c.L.status) + p.batch, 4, hipMemcpyDeviceToHost, c.s));
+  HKP_CHECK(hipStreamSynchronize(c.s));
+  if (bad) {
+    set_error("V or strain contains NaN or Inf");
+    return HKP_E_ARG;
+  }
+  HKP_CHECK(launch_onsite(A.mat, p.nx, p.ny, p.nz, p.batch, A.V, p.N, A.strain,
+                          c.at<double>(c.L.D64), p.mixed ? c.at<float>(c.L.D32) : nullptr,
+                          6LL * p.N, c.s));
+  if (c.field)
+    HKP_CHECK(launch_phase_tables(p.nx, p.nz, p.h, A.B, c.at<double>(c.L.w64),
+                                  c.at<double>(c.L.v64), c.at<float>(c.L.w32),
+                                  c.at<float>(c.L.v32), c.s));
+  HKP_CHECK(launch_fill_int(c.at<int>(c.L.flags), 8 * p.batch, 0, c.s));
+  HKP_CHECK(launch_fill_int(c.at<int>(c.L.active), p.batch, 1, c.s));
+  HKP_CHECK(launch_fill_int(c.at<int>(c.L.act32), p.batch, p.mixed ? 1 : 0, c.s));
+  HKP_CHECK(launch_fill_int(c.at<int>(c.L.act64), p.batch, p.mixed ? 0 : 1, c.s));
+
+  // ---- spectral bound
+  std::vector<double> bup;
+  lanczos_bounds(c, bup);
+  {
+    std::vector<double> hb(4 * (size_t)p.batch, 0.0);
+    for (int b = 0; b < p.batch; ++b) hb[4 * b] = bup[b];
+    HKP_CHECK(hipMemcpyAsync(c.at<double>(c.L.bounds), hb.data(), hb.size() * 8,
+                             hipMemcpyHostToDevice, c.s));
+    HKP_CHECK(hipStreamSynchronize(c.s));
+  }
+
+  // ---- initial block: caller's X0 or random; SVQB; Rayleigh-Ritz
+  if (A.X0) {
+    HKP_CHECK(launch_abi_to_internal(p.nx, p.ny, p.nz, p.h, A.B, p.nb, A.X0,
+                                     c.at<double>(c.L.X), 0, c.s));
+  } else {
+    HKP_CHECK(launch_random_block(c.at<double>(c.L.X), p.n6, p.nb, p.batch, c.bstride(),
+                                  A.seed, c.s));
+  }
+  const int* act = c.at<int>(c.L.active);
+  svqb(c, act);
+  svqb(c, act);
+  rayleigh_ritz(c, act);
+  residuals(c, act);
+  HKP_CHECK(launch_control(c.control(), p.batch, p.nb, p.nev, p.degree, kKmax, A.tol, p.mixed,
+                           !(A.flags & HKP_FLAG_NO_FP64_POLISH), 0, c.s));
+  t_setup.stop(c.s);
+  t_setup.collect();
+
+  long long n_hx64 = (long long)kLanczosSteps + p.nb, n_hx32 = 0;
+  int iters = 0;
+  std::vector<int> hflags(8 * (size_t)p.batch);
+  auto read_flags = [&]() {
+    HKP_CHECK(hipMemcpyAsync(hflags.data(), c.at<int>(c.L.flags), hflags.size() * 4,
+                             hipMemcpyDeviceToHost, c.s));
+    HKP_CHECK(hipStreamSynchronize(c.s));
+  };
+  read_flags();
+  auto all_done = [&]() {
+    for (int b = 0; b < p.batch; ++b)
+      if (!hflags[8 * b]) return false;
+    return true;
+  };
+  auto count_work = [&]() {
+    for (int b = 0; b < p.batch; ++b) {
+      if (hflags[8 * b]) continue;
+      const bool f32 = p.mixed && !hflags[8 * b + 1];
+      (f32 ? n_hx32 : n_hx64) += (long long)p.nb * p.degree;
+      n_hx64 += p.nb;
+    }
+  };
+
+  auto iteration = [&](int it, bool single_path_known, bool f32_only) {
+    t_filter.start(c.s);
+    if (!single_path_known) {
+      if (p.mixed) filter32(c, c.at<int>(c.L.act32));
+      filter64(c, c.at<int>(c.L.act64));
+    } else if (f32_only) {
+      filter32(c, act);
+    } else {
+      filter64(c, act);
+    }
+    t_filter.stop(c.s);
+    t_orth.start(c.s);
+    svqb(c, act);
+    svqb(c, act);
+    t_orth.stop(c.s);
+    t_rr.start(c.s);
+    rayleigh_ritz(c, act);
+    t_rr.stop(c.s);
+    t_res.start(c.s);
+    residuals(c, act);
+    HKP_CHECK(launch_control(c.control(), p.batch, p.nb, p.nev, p.degree, kKmax, A.tol,
+                             p.mixed, !(A.flags & HKP_FLAG_NO_FP64_POLISH), it, c.s));
+    t_res.stop(c.s);
+  };
+
+  if (eager) {
+    while (iters < A.max_iter && !all_done()) {
+      ++iters;
+      count_work();
+      if (p.batch == 1) {
+        const bool f32 = p.mixed && !hflags[1];
+        iteration(iters, true, f32);
+      } else {
+        iteration(iters, false, false);
+      }
+      read_flags();
+      t_filter.collect();
+      t_orth.collect();
+      t_rr.collect();
+      t_res.collect();
+    }
+  } else {
+    // record a chunk of iterations once, replay until converged
+    const int chunk = std::max(1, std::min(A.graph_chunk > 0 ? A.graph_chunk : 4, A.max_iter));
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    HKP_CHECK(hipStreamBeginCapture(c.s, hipStreamCaptureModeThreadLocal));
+    try {
+      for (int k = 0; k < chunk; ++k) iteration(-1, false, false);
+    } catch (...) {
+      hipGraph_t g2 = nullptr;
+      (void)hipStreamEndCapture(c.s, &g2);
+      if (g2) (void)hipGraphDestroy(g2);
+      throw;
+    }
+    HKP_CHECK(hipStreamEndCapture(c.s, &graph));
+    HKP_CHECK(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
+    while (iters < A.max_iter && !all_done()) {
+      for (int k = 0; k < chunk; ++k) count_work();   // upper estimate per replay
+      HKP_CHECK(hipGraphLaunch(exec, c.s));
+      iters += chunk;
+      read_flags();
+    }
+    (void)hipGraphExecDestroy(exec);
+    (void)hipGraphDestroy(graph);
+  }
+
+  // ---- outputs
+  HKP_CHECK(launch_finish(c.at<double>(c.L.theta), c.at<double>(c.L.r2), p.nb, p.nev, p.batch,
+                          A.eig, A.resid, c.s));
+  if (A.psi)
+    HKP_CHECK(launch_internal_to_abi(p.nx, p.ny, p.nz, p.h, A.B, p.nev, p.batch,
+                                     c.at<double>(c.L.X), c.bstride(), A.psi,
+                                     (long long)p.nev * p.n6, c.s));
+  HKP_CHECK(hipStreamSynchronize(c.s));
+  int all = 1, minconv = p.nev, maxit = 0, sw = -1;
+  for (int b = 0; b < p.batch; ++b) {
+    all &= hflags[8 * b] != 0;
+    minconv = std::min(minconv, hflags[8 * b + 4]);
+    maxit = std::max(maxit, hflags[8 * b + 3]);
+    if (hflags[8 * b + 1]) sw = sw < 0 ? hflags[8 * b + 5] : std::min(sw, hflags[8 * b + 5]);
+  }
+  if (stats) {
+    stats->iters = eager ? iters : maxit;
+    stats->n_converged = minconv;
+    stats->n_hx_fp64 = n_hx64;
+    stats->n_hx_fp32 = n_hx32;
+    stats->fp64_switch_iter = p.mixed ? sw : -1;
+    stats->nb = p.nb;
+    stats->degree = p.degree;
+    stats->t_setup = t_setup.acc;
+    stats->t_filter = t_filter.acc;
+    stats->t_orth = t_orth.acc;
+    stats->t_rr = t_rr.acc;
+    stats->t_resid = t_res.acc;
+    stats->lambda_max_bound = bup.empty() ? 0.0 : bup[0];
+    stats->seconds =
+        std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count();
+  }
+  return all ? HKP_OK : HKP_W_NOT_CONVERGED;
+}
+
+// ---------------------------------------------------------------------------
+// operator-level entry (tests): Y = alpha (H - shift) X + beta Y_old in the ABI layout
+// ---------------------------------------------------------------------------
+size_t apply_bytes(const hkp_grid& g, int nvec) {
+  const size_t N = (size_t)g.nx * g.ny * g.nz;
+  const size_t n6 = 6 * N;
+  size_t b = 0;
+  b += align_up(6 * N * 8) + align_up(6 * N * 4);                     // D64, D32
+  b += align_up((size_t)g.nz * 16) + align_up((size_t)g.nz * g.nx * 16);
+  b += align_up((size_t)g.nz * 8) + align_up((size_t)g.nz * g.nx * 8);
+  b += 3 * align_up((size_t)nvec * n6 * 16);                          // X, Old, Y (FP64)
+  b += align_up((size_t)nvec * n6 * 8);                               // X (FP32)
+  return b;
+}
+
+int run_filter_step(const FilterArgs& A) {
+  const hkp_grid& g = A.grid;
+  const size_t N = (size_t)g.nx * g.ny * g.nz, n6 = 6 * N;
+  char* ws = reinterpret_cast<char*>(A.workspace);
+  hipStream_t s = reinterpret_cast<hipStream_t>(A.stream);
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    char* p = ws + off;
+    off += align_up(bytes);
+    return p;
+  };
+  double* D64 = (double*)take(6 * N * 8);
+  float* D32 = (float*)take(6 * N * 4);
+  double* w64 = (double*)take((size_t)g.nz * 16);
+  double* v64 = (double*)take((size_t)g.nz * g.nx * 16);
+  float* w32 = (float*)take((size_t)g.nz * 8);
+  float* v32 = (float*)take((size_t)g.nz * g.nx * 8);
+  double* Xi = (double*)take((size_t)A.nvec * n6 * 16);
+  double* Oi = (double*)take((size_t)A.nvec * n6 * 16);
+  double* Yi = (double*)take((size_t)A.nvec * n6 * 16);
+  float* Xf = (float*)take((size_t)A.nvec * n6 * 8);
+  const bool fp64 = A.precision == HKP_PREC_FP64;
+  const bool field = A.B[0] != 0.0 || A.B[1] != 0.0 || A.B[2] != 0.0;
+  HKP_CHECK(launch_onsite(A.mat, g.nx, g.ny, g.nz, 1, A.V, 0, A.strain, D64, D32, 0, s));
+  if (field) HKP_CHECK(launch_phase_tables(g.nx, g.nz, g.h_nm, A.B, w64, v64, w32, v32, s));
+  HKP_CHECK(launch_abi_to_internal(g.nx, g.ny, g.nz, g.h_nm, A.B, A.nvec, A.X,
+                                   fp64 ? (void*)Xi : (void*)Xf, fp64 ? 0 : 1, s));
+  const bool has_old = A.Y_old != nullptr && A.beta != 0.0;
+  if (has_old)
+    HKP_CHECK(launch_abi_to_internal(g.nx, g.ny, g.nz, g.h_nm, A.B, A.nvec, A.Y_old, Oi, 0, s));
+  StencilLaunch a{};
+  a.nx = g.nx;
+  a.ny = g.ny;
+  a.nz = g.nz;
+  a.nvec = A.nvec;
+  a.batch = 1;
+  a.in = fp64 ? (const void*)Xi : (const void*)Xf;
+  a.old = has_old ? Oi : nullptr;
+  a.old_fp64 = 1;
+  a.out = Yi;
+  a.out_fp64 = 1;
+  a.D = fp64 ? (const void*)D64 : (const void*)D32;
+  a.strain = A.strain != nullptr;
+  if (field) {
+    a.wtab = fp64 ? (const void*)w64 : (const void*)w32;
+    a.vtab = fp64 ? (const void*)v64 : (const void*)v32;
+  }
+  a.coef.alpha = A.alpha;
+  a.coef.shift = A.shift;
+  a.coef.beta = has_old ? A.beta : 0.0;
+  a.tile_y = A.tile_y > 0 ? A.tile_y : 4;
+  a.fp64 = fp64;
+  HKP_CHECK(launch_stencil(a, make_consts(A.mat, g.h_nm, A.B), s));
+  HKP_CHECK(launch_internal_to_abi(g.nx, g.ny, g.nz, g.h_nm, A.B, A.nvec, 1, Yi, 0, A.Y, 0, s));
+  return HKP_OK;
+}
+
+// translate a HIP failure into the ABI error code
+int guarded(const std::function<int()>& f) {
+  try {
+    return f();
+  } catch (const HipError& e) {
+    set_error(e.what());
+    return HKP_E_HIP;
+  } catch (const std::exception& e) {
+    set_error(e.what());
+    return HKP_E_NUMERICAL;
+  }
+}
+
+}  // namespace hkp

@@ -1,0 +1,67 @@
+// Host-side solver interface used by the C ABI layer.
+#pragma once
+
+#include <functional>
+
+#include "hkp_internal.h"
+
+namespace hkp {
+
+struct Plan {
+  int nx, ny, nz;
+  double h;
+  long long N, n6;   // grid points, complex unknowns per vector
+  int batch, nev, nb, degree;
+  bool mixed;
+  int tile_y;
+};
+
+struct SolveArgs {
+  Plan plan;
+  hkp_material mat;
+  const double* V;
+  const double* strain;
+  double B[3];
+  const void* X0;
+  double* eig;
+  void* psi;
+  double* resid;
+  void* workspace;
+  void* stream;
+  double tol;
+  int max_iter;
+  int flags;
+  unsigned long long seed;
+  int tile_y;       // 0: plan default
+  int graph_chunk;  // iterations per recorded graph
+};
+
+struct FilterArgs {
+  hkp_grid grid;
+  hkp_material mat;
+  const double* V;
+  const double* strain;
+  double B[3];
+  int nvec;
+  const void* X;
+  const void* Y_old;
+  void* Y;
+  double alpha, shift, beta;
+  int precision;
+  void* workspace;
+  void* stream;
+  int tile_y;
+};
+
+int default_nb(int nev, long long n6);
+Plan make_plan(const hkp_grid& g, const hkp_opts& o, int batch);
+size_t plan_bytes(const Plan& p);
+int run_solve(const SolveArgs& a, hkp_stats* stats);
+size_t apply_bytes(const hkp_grid& g, int nvec);
+int run_filter_step(const FilterArgs& a);
+int guarded(const std::function<int()>& f);
+int autotuned_tile(const hkp_grid& g, int nb, bool mixed);
+int run_autotune(const hkp_grid& g, int nb, bool mixed, bool strain, bool field, void* ws,
+                 size_t ws_bytes, void* stream, hkp_tune* out);
+
+}  // namespace hkp

@@ -1,0 +1,120 @@
+"""Host-side checks of the C ABI (no GPU work): the library loads, exports
+every function declared in include/hkp.h, and rejects invalid arguments with
+the documented codes before touching the device."""
+
+import ctypes as C
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    txt = open(os.path.join(ROOT, "include", "hkp.h")).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    names = re.findall(r"\b(hkp_[a-z_0-9]+)\s*\(", txt)
+    return sorted(set(names))
+
+
+def test_header_declares_the_expected_calls():
+    names = _declared()
+    for n in ("hkp_solve", "hkp_solve_batch", "hkp_apply", "hkp_filter_step", "hkp_hf_grad",
+              "hkp_gate_potential", "hkp_workspace_bytes", "hkp_autotune", "hkp_last_error"):
+        assert n in names
+
+
+def test_library_exports_every_declared_symbol():
+    from paper_2607_08447_amd import _lib
+    raw = C.CDLL(_lib.LIB_PATH)
+    for n in _declared():
+        assert hasattr(raw, n), n
+    assert set(_declared()) == set(_lib.SIGNATURES)
+
+
+def _structs():
+    from paper_2607_08447_amd import _lib as L
+    g = L.hkp_grid(10, 8, 8, 0.5)
+    m = L.hkp_material()
+    L.lib.hkp_default_material(C.byref(m))
+    o = L.hkp_opts()
+    L.lib.hkp_default_opts(C.byref(o))
+    return L, g, m, o
+
+
+def test_defaults():
+    L, g, m, o = _structs()
+    assert m.gamma3 == 1.446 and m.delta_so_eV == 0.044 and m.kappa == -0.42
+    assert o.tol_eV == 1e-8 and o.nb == 0 and o.precision == 0
+    assert L.lib.hkp_version() >= 100
+
+
+def test_workspace_query_and_argument_errors():
+    L, g, m, o = _structs()
+    o.nev = 8
+    n = L.lib.hkp_workspace_bytes(C.byref(g), C.byref(o), 1)
+    assert n > 2 * 16 * 3840 * 16
+    assert L.lib.hkp_workspace_bytes(C.byref(g), C.byref(o), 4) > 3 * n
+    o.nev = 6 * 640 + 1
+    assert L.lib.hkp_workspace_bytes(C.byref(g), C.byref(o), 1) == 0
+    assert b"nev" in L.lib.hkp_last_error()
+    o.nev, o.nb = 8, 8
+    assert L.lib.hkp_workspace_bytes(C.byref(g), C.byref(o), 1) == 0
+    o.nb = 65
+    assert L.lib.hkp_workspace_bytes(C.byref(g), C.byref(o), 1) == 0
+    bad = L.hkp_grid(0, 8, 8, 0.5)
+    o.nb = 0
+    assert L.lib.hkp_workspace_bytes(C.byref(bad), C.byref(o), 1) == 0
+
+
+def test_solve_rejects_before_any_gpu_work():
+    L, g, m, o = _structs()
+    fake = C.c_void_p(0x1000)   # never dereferenced: validation fails first
+    B = (C.c_double * 3)(0.0, 0.0, 0.0)
+    st = L.hkp_stats()
+    # NULL grid
+    assert L.lib.hkp_solve(None, C.byref(m), C.byref(o), fake, None, B, None, fake, None, None,
+                           fake, 1 << 30, None, C.byref(st)) == L.HKP_E_ARG
+    # nb <= nev
+    o.nev, o.nb = 8, 8
+    assert L.lib.hkp_solve(C.byref(g), C.byref(m), C.byref(o), fake, None, B, None, fake, None,
+                           None, fake, 1 << 30, None, C.byref(st)) == L.HKP_E_ARG
+    # workspace too small
+    o.nb = 16
+    assert L.lib.hkp_solve(C.byref(g), C.byref(m), C.byref(o), fake, None, B, None, fake, None,
+                           None, fake, 16, None, C.byref(st)) == L.HKP_E_WORKSPACE
+    assert b"workspace too small" in L.lib.hkp_last_error()
+    # NaN field
+    Bn = (C.c_double * 3)(float("nan"), 0.0, 0.0)
+    assert L.lib.hkp_solve(C.byref(g), C.byref(m), C.byref(o), fake, None, Bn, None, fake, None,
+                           None, fake, 1 << 30, None, C.byref(st)) == L.HKP_E_ARG
+    # graph mode on the legacy default stream
+    o.flags = L.HKP_FLAG_GRAPH
+    assert L.lib.hkp_solve(C.byref(g), C.byref(m), C.byref(o), fake, None, B, None, fake, None,
+                           None, fake, 1 << 30, None, C.byref(st)) == L.HKP_E_ARG
+    # X0 flag without X0
+    o.flags = L.HKP_FLAG_X0
+    assert L.lib.hkp_solve(C.byref(g), C.byref(m), C.byref(o), fake, None, B, None, fake, None,
+                           None, fake, 1 << 30, None, C.byref(st)) == L.HKP_E_ARG
+    # bad precision / tol / degree
+    o.flags = 0
+    for field, val in (("precision", 7), ("tol_eV", -1.0), ("degree", 500), ("max_iter", 0)):
+        o2 = L.hkp_opts.from_buffer_copy(o)
+        setattr(o2, field, val)
+        assert L.lib.hkp_solve(C.byref(g), C.byref(m), C.byref(o2), fake, None, B, None, fake,
+                               None, None, fake, 1 << 30, None, C.byref(st)) == L.HKP_E_ARG
+
+
+def test_other_entry_points_validate():
+    L, g, m, o = _structs()
+    fake = C.c_void_p(0x1000)
+    B = (C.c_double * 3)(0.0, 0.0, 0.0)
+    assert L.lib.hkp_filter_step(C.byref(g), C.byref(m), fake, None, B, 1, fake, None, fake, 1.0,
+                                 0.0, 0.5, 0, fake, 1 << 30, None) == L.HKP_E_ARG   # beta w/o Y_old
+    assert L.lib.hkp_apply(C.byref(g), C.byref(m), fake, None, B, 2, fake, fake, 0, fake, 10,
+                           None) == L.HKP_E_WORKSPACE
+    assert L.lib.hkp_hf_grad(100, 2, fake, fake, 17, fake, fake, fake, 1 << 20, None) == L.HKP_E_ARG
+    assert L.lib.hkp_hf_grad_workspace_bytes(0) == 0
+    assert L.lib.hkp_hf_grad(100, 2, fake, fake, 3, fake, fake, fake, 8, None) == L.HKP_E_WORKSPACE
+    assert L.lib.hkp_gate_potential(0, 1, fake, fake, fake, fake, None) == L.HKP_E_ARG
