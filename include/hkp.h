@@ -104,6 +104,14 @@ typedef struct {
   double seconds;           /* wall time of the call */
   double t_setup, t_filter, t_orth, t_rr, t_resid; /* event-timed phases (eager mode) */
   double lambda_max_bound;  /* upper spectral bound used by the filter (eV) */
+  /* stencil launches (filter steps and H X): algorithmic bytes moved -- the
+   * spinor blocks read and written plus the on-site fields once per launch --
+   * and, in eager mode with stats requested, their event-timed durations on
+   * the solver's stream, split by arithmetic precision */
+  double hx_bytes;                       /* all stencil launches */
+  int64_t n_stencil32, n_stencil64;      /* timed launches */
+  double t_stencil32, t_stencil64;       /* summed durations (s) */
+  double bytes_stencil32, bytes_stencil64; /* algorithmic bytes of the timed launches */
 } hkp_stats;
 
 /* Autotuner result for the stencil (filter step) kernel on one shape. */

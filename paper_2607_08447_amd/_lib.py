@@ -47,7 +47,10 @@ class hkp_stats(C.Structure):
                 ("n_hx_fp32", C.c_int64), ("fp64_switch_iter", C.c_int32), ("nb", C.c_int32),
                 ("degree", C.c_int32), ("seconds", C.c_double), ("t_setup", C.c_double),
                 ("t_filter", C.c_double), ("t_orth", C.c_double), ("t_rr", C.c_double),
-                ("t_resid", C.c_double), ("lambda_max_bound", C.c_double)]
+                ("t_resid", C.c_double), ("lambda_max_bound", C.c_double),
+                ("hx_bytes", C.c_double), ("n_stencil32", C.c_int64), ("n_stencil64", C.c_int64),
+                ("t_stencil32", C.c_double), ("t_stencil64", C.c_double),
+                ("bytes_stencil32", C.c_double), ("bytes_stencil64", C.c_double)]
 
     def as_dict(self):
         return {name: getattr(self, name) for name, _ in self._fields_}

@@ -1,6 +1,8 @@
 // Autotuner for the stencil (Chebyshev step) kernel: times the tile shapes on
 // the caller's grid and block size with HIP events and caches the fastest per
 // (shape, nb, precision, strain, field) for the life of the process.
+#include <cstdio>
+#include <cstdlib>
 #include <map>
 #include <mutex>
 #include <tuple>
@@ -14,7 +16,7 @@ namespace {
 
 using Key = std::tuple<int, int, int, int, int>;   // nx, ny, nz, nb, mixed
 std::mutex g_mu;
-std::map<Key, int> g_cache;
+std::map<Key, std::pair<int, int>> g_cache;        // tile_y, order
 
 size_t al(size_t x) { return (x + 255) & ~(size_t)255; }
 
@@ -23,9 +25,16 @@ size_t al(size_t x) { return (x + 255) & ~(size_t)255; }
 int autotuned_tile(const hkp_grid& g, int nb, bool mixed) {
   std::lock_guard<std::mutex> lk(g_mu);
   auto it = g_cache.find(Key{g.nx, g.ny, g.nz, nb, mixed ? 1 : 0});
-  if (it != g_cache.end()) return it->second;
+  if (it != g_cache.end()) return it->second.first;
   // untuned default: tall tiles on wide planes, thin tiles on narrow ones
   return g.ny >= 32 ? 4 : (g.ny >= 8 ? 2 : 1);
+}
+
+int autotuned_order(const hkp_grid& g, int nb, bool mixed) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  auto it = g_cache.find(Key{g.nx, g.ny, g.nz, nb, mixed ? 1 : 0});
+  if (it != g_cache.end()) return it->second.second;
+  return 1;
 }
 
 int run_autotune(const hkp_grid& g, int nb, bool mixed, bool strain, bool field, void* ws,
@@ -33,7 +42,7 @@ int run_autotune(const hkp_grid& g, int nb, bool mixed, bool strain, bool field,
   const long long N = (long long)g.nx * g.ny * g.nz, n6 = 6 * N;
   const size_t esz = mixed ? 8 : 16;
   size_t need = al(6 * N * 8) + al((size_t)g.nz * 16) + al((size_t)g.nz * g.nx * 16) +
-                3 * al((size_t)nb * n6 * esz);
+                2 * al((size_t)nb * n6 * esz);
   if (ws_bytes < need) {
     set_error("autotune workspace too small: need " + std::to_string(need) + " bytes");
     return HKP_E_WORKSPACE;
@@ -51,7 +60,7 @@ int run_autotune(const hkp_grid& g, int nb, bool mixed, bool strain, bool field,
   void* vt = take((size_t)g.nz * g.nx * 16);
   void* X = take((size_t)nb * n6 * esz);
   void* O = take((size_t)nb * n6 * esz);
-  void* Y = take((size_t)nb * n6 * esz);
+  void* Y = O;   // the solver's filter writes over the block it reads as Y_old
   // contents do not affect the timing; give them finite values
   if (hipMemsetAsync(p, 0, off, s) != hipSuccess) return HKP_E_HIP;
   hkp_material m;
@@ -61,8 +70,10 @@ int run_autotune(const hkp_grid& g, int nb, bool mixed, bool strain, bool field,
   hipEvent_t e0, e1;
   if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return HKP_E_HIP;
   const int cand[] = {1, 2, 4, 8};
-  int best = 4;
+  int best = 4, best_order = 1;
   double best_us = 1e300;
+  const char* dbg = std::getenv("HKP_TUNE_TRACE");
+  for (int order = 0; order < 2; ++order)
   for (int ty : cand) {
     if (ty > 1 && ty > 2 * g.ny) continue;
     StencilLaunch a{};
@@ -84,6 +95,7 @@ int run_autotune(const hkp_grid& g, int nb, bool mixed, bool strain, bool field,
     a.coef.shift = 0.5;
     a.coef.beta = -1.0;
     a.tile_y = ty;
+    a.order = order;
     a.fp64 = !mixed;
     if (launch_stencil(a, c, s) != hipSuccess) continue;   // warm-up
     const int reps = 5;
@@ -94,16 +106,18 @@ int run_autotune(const hkp_grid& g, int nb, bool mixed, bool strain, bool field,
     float ms = 0;
     (void)hipEventElapsedTime(&ms, e0, e1);
     const double us = 1e3 * ms / reps;
+    if (dbg && dbg[0] == '1') std::fprintf(stderr, "[hkp tune] ty %d order %d: %.1f us\n", ty, order, us);
     if (us < best_us) {
       best_us = us;
       best = ty;
+      best_order = order;
     }
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   {
     std::lock_guard<std::mutex> lk(g_mu);
-    g_cache[Key{g.nx, g.ny, g.nz, nb, mixed ? 1 : 0}] = best;
+    g_cache[Key{g.nx, g.ny, g.nz, nb, mixed ? 1 : 0}] = {best, best_order};
   }
   out->tile_y = best;
   out->zchunk = g.nz;

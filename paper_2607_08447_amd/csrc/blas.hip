@@ -100,31 +100,31 @@ gram_partial_kernel(const double* A, long long a_bstride, int nba, const double*
   }
 }
 
-__global__ void gram_reduce_kernel(int nchunks, int nba, int nbb, int hermitian,
-                                   const int* active, const double* partial, double* out) {
+// fixed-order reduction of the chunk partials: one wave per output entry,
+// lane l sums chunks l, l+64, ..., then a shuffle tree (deterministic)
+__global__ void __launch_bounds__(256)
+gram_reduce_kernel(int nchunks, int nba, int nbb, int hermitian, const int* active,
+                   const double* partial, double* out) {
   const int b = blockIdx.y;
   if (active && !active[b]) return;
-  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  const int lane = threadIdx.x & 63;
+  const int idx = blockIdx.x * 4 + (threadIdx.x >> 6);
   if (idx >= nba * nbb) return;
   const int i = idx / nbb, j = idx % nbb;
-  double* o = out + 2 * ((long long)b * nba * nbb);
   if (hermitian && j < i) return;  // filled from the upper triangle
+  const double* p = partial + 2 * ((long long)b * nchunks * nba * nbb + (long long)i * nbb + j);
+  const long long cs = 2LL * nba * nbb;
   double re = 0.0, im = 0.0;
-  // the wave of row tile i/16 wrote tiles with column tile >= row tile
-  int si = i, sj = j;
-  const double* p = partial + 2 * ((long long)b * nchunks * nba * nbb);
-  if (hermitian && (sj / 16) < (si / 16)) {
-    // not computed directly (lower tile): use conj of the transposed entry
-    int tmp = si;
-    si = sj;
-    sj = tmp;
+  for (int c = lane; c < nchunks; c += 64) {
+    re += p[c * cs];
+    im += p[c * cs + 1];
   }
-  for (int c = 0; c < nchunks; ++c) {
-    const double* q = p + 2 * ((long long)c * nba * nbb + (long long)si * nbb + sj);
-    re += q[0];
-    im += q[1];
+  for (int off = 32; off > 0; off >>= 1) {
+    re += __shfl_down(re, off, 64);
+    im += __shfl_down(im, off, 64);
   }
-  if (si != i) im = -im;
+  if (lane != 0) return;
+  double* o = out + 2 * ((long long)b * nba * nbb);
   if (hermitian) {
     if (i == j) im = 0.0;
     o[2 * ((long long)i * nbb + j)] = re;
@@ -431,7 +431,7 @@ hipError_t launch_gram(const BlockDesc& A, const BlockDesc& B, int hermitian, in
     default: return hipErrorInvalidValue;
   }
   const int cnt = A.nvec * B.nvec;
-  dim3 g2((unsigned)((cnt + 255) / 256), (unsigned)batch);
+  dim3 g2((unsigned)((cnt + 3) / 4), (unsigned)batch);
   gram_reduce_kernel<<<g2, 256, 0, s>>>(nchunks, A.nvec, B.nvec, hermitian, active, partial, out);
   return hipGetLastError();
 }

@@ -45,7 +45,7 @@ __device__ __forceinline__ void pair_of(int k, int round, int n, int* p, int* q)
 
 __global__ void __launch_bounds__(kJacThreads)
 heev_kernel(double* A, int nb, long long mat_stride, double* evals, double* out, int mode,
-            int* status, const int* active) {
+            int* status, const int* active, int* again) {
   __shared__ double2 a[kNBP][kNBP + 1];
   __shared__ double2 v[kNBP][kNBP + 1];
   __shared__ Rot rot[kNBP / 2];
@@ -56,7 +56,10 @@ heev_kernel(double* A, int nb, long long mat_stride, double* evals, double* out,
   __shared__ int any_rot;
 
   const int b = blockIdx.x;
-  if (active && !active[b]) return;
+  if (active && !active[b]) {
+    if (again && threadIdx.x == 0) again[b] = 0;
+    return;
+  }
   const int tid = threadIdx.x;
   const int n = nb + (nb & 1);      // even number of players; the pad is decoupled
   const double2* Ab = reinterpret_cast<const double2*>(A + 2 * (long long)b * mat_stride);
@@ -214,6 +217,13 @@ heev_kernel(double* A, int nb, long long mat_stride, double* evals, double* out,
       if (!(lam[i] > floor_)) bad = 1;
     }
     if (bad && status) atomicOr(status + b, 1);
+    // a second orthonormalisation pass is needed only for an ill-conditioned
+    // Gram matrix (one SVQB pass leaves an orthogonality error ~ eps kappa(S))
+    if (again && tid == 0) {
+      double lmin = lmax;
+      for (int i = 0; i < nb; ++i) lmin = fmin(lmin, lam[i]);
+      again[b] = !(lmin > 1e-4 * lmax);
+    }
     for (int t = tid; t < nb * nb; t += kJacThreads) {
       const int r = t / nb, c = t % nb;
       const double l = lam[c] > floor_ ? lam[c] : floor_;
@@ -251,14 +261,16 @@ __global__ void control_kernel(Control c, int nb, int nev, int degree, int kmax,
   fl[3] = it;
   fl[4] = nconv;
   if (nconv == nev) fl[0] = 1;
-  // mixed precision: leave the FP32 filter when it can no longer reduce the
-  // residual (stagnation over two iterations), or once residuals sit within
-  // ~30 FP32 ulps of the spectral radius while the target lies below that
+  // mixed precision: leave the FP32 filter once it can no longer reduce the
+  // residual.  FP32 rounding of the filtered block leaves a residual floor of
+  // a few FP32 ulps of the spectral radius (measured: ~3 eps32 |H|); stagnation
+  // (less than a 30% decrease on two consecutive iterations) is only counted
+  // within 30 eps32 |H| of the floor
   if (mixed && allow_switch && !fl[1] && !fl[0]) {
     const double prev = bd[3];
-    const double floor32 = 30.0 * 5.96e-8 * bd[0];
-    if (rmax > 0.5 * prev && prev > 0.0) fl[2] += 1; else fl[2] = 0;
-    if (fl[2] >= 2 || (rmax < floor32 && tol < floor32)) {
+    const double near_floor = 30.0 * 5.96e-8 * bd[0];
+    if (prev > 0.0 && rmax > 0.7 * prev && rmax < near_floor) fl[2] += 1; else fl[2] = 0;
+    if (fl[2] >= 2) {
       fl[1] = 1;
       fl[5] = it + 1;
     }
@@ -359,9 +371,11 @@ hipError_t launch_fill_int(int* p, int count, int value, hipStream_t s) {
 }
 
 hipError_t launch_heev(double* A, int nb, int batch, long long mat_stride, double* evals,
-                       double* out, int mode, int* status, const int* active, hipStream_t s) {
+                       double* out, int mode, int* status, const int* active, hipStream_t s,
+                       int* again) {
   if (nb > HKP_NB_MAX || nb < 1) return hipErrorInvalidValue;
-  heev_kernel<<<batch, kJacThreads, 0, s>>>(A, nb, mat_stride, evals, out, mode, status, active);
+  heev_kernel<<<batch, kJacThreads, 0, s>>>(A, nb, mat_stride, evals, out, mode, status, active,
+                                            again);
   return hipGetLastError();
 }
 

@@ -70,9 +70,11 @@ struct StencilLaunch {
   int strain;            // D holds 6 arrays
   const void* wtab;      // [nz] complex, kernel type, or null (B = 0)
   const void* vtab;      // [nz][nx] complex
+  int phase_general;     // Bz != 0: y-link phases vary along x
   StepCoef coef;
   const int* active;     // [batch] 0 = skip, or null
   int tile_y;            // 1, 2, 4, 8
+  int order;             // workgroup order: 0 tile-major, 1 vector-major
   int fp64;              // kernel type
 };
 
@@ -147,8 +149,11 @@ hipError_t launch_scale(double* v, long long n, int batch, long long bstride,
 // mode 0 (RR):   A Hermitian nb x nb -> eigenvalues theta (ascending) and
 //                eigenvectors Q (columns), written over A's buffer layout
 // mode 1 (SVQB): A = Gram S -> T = D U diag(lambda)^-1/2, D = diag(S)^-1/2
+// SVQB mode: again[b] (if given) is set to 1 when the Gram matrix is so ill
+// conditioned that a second pass is needed (and the member is active)
 hipError_t launch_heev(double* A, int nb, int batch, long long mat_stride, double* evals,
-                       double* out, int mode, int* status, const int* active, hipStream_t s);
+                       double* out, int mode, int* status, const int* active, hipStream_t s,
+                       int* again = nullptr);
 
 // control: convergence flags, next Chebyshev coefficients
 struct Control {

@@ -19,6 +19,8 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <functional>
 #include <stdexcept>
@@ -52,7 +54,7 @@ constexpr int kResParts = 64;
 
 struct Layout {
   size_t D64, D32, w64, v64, w32, v32, X, W, A32, B32, gram, mat1, mat2, theta, lam, r2, rpart,
-      coef, bounds, flags, active, act32, act64, status, lal, lnrm, lpart, total;
+      coef, bounds, flags, active, act32, act64, again, status, lal, lnrm, lpart, total;
 };
 
 Layout make_layout(const Plan& p) {
@@ -90,6 +92,7 @@ Layout make_layout(const Plan& p) {
   L.active = take(B * 4);
   L.act32 = take(B * 4);
   L.act64 = take(B * 4);
+  L.again = take(B * 4);
   L.status = take(B * 4 + 4);
   L.lal = take((size_t)kLanczosSteps * B * 16);
   L.lnrm = take((size_t)(kLanczosSteps + 1) * B * 16);
@@ -139,13 +142,78 @@ void tridiag_extremes(const std::vector<double>& a, const std::vector<double>& b
   *lo = l;
 }
 
+// per-launch accounting of the stencil kernel: algorithmic bytes always,
+// event-timed durations when requested (eager mode)
+struct StencilStats {
+  bool timed = false;
+  std::vector<hipEvent_t> ev;   // start/stop pairs
+  std::vector<int> kind;        // 0: FP32 stencil, 1: FP64
+  std::vector<double> bytes;
+  size_t used = 0;
+  double hx_bytes = 0, t32 = 0, t64 = 0, b32 = 0, b64 = 0;
+  long long n32 = 0, n64 = 0;
+  ~StencilStats() {
+    for (auto e : ev) (void)hipEventDestroy(e);
+  }
+  void launch(const StencilLaunch& a, const StencilConsts<double>& c, hipStream_t s,
+              long long N, int active_members) {
+    const double sin = a.fp64 ? 16 : 8;
+    const double sold = a.old ? (a.old_fp64 ? 16 : 8) : 0;
+    const double sout = a.out_fp64 ? 16 : 8;
+    const double b = (double)active_members *
+                     ((double)N * 6 * a.nvec * (sin + sold + sout) +
+                      (double)N * (a.strain ? 6 : 1) * (a.fp64 ? 8 : 4));
+    hx_bytes += b;
+    if (!timed) {
+      HKP_CHECK(launch_stencil(a, c, s));
+      return;
+    }
+    if (2 * used + 2 > ev.size()) {
+      hipEvent_t e0, e1;
+      HKP_CHECK(hipEventCreate(&e0));
+      HKP_CHECK(hipEventCreate(&e1));
+      ev.push_back(e0);
+      ev.push_back(e1);
+      kind.push_back(0);
+      bytes.push_back(0);
+    }
+    HKP_CHECK(hipEventRecord(ev[2 * used], s));
+    HKP_CHECK(launch_stencil(a, c, s));
+    HKP_CHECK(hipEventRecord(ev[2 * used + 1], s));
+    kind[used] = a.fp64 ? 1 : 0;
+    bytes[used] = b;
+    ++used;
+  }
+  void collect() {
+    if (!timed || used == 0) return;
+    HKP_CHECK(hipEventSynchronize(ev[2 * used - 1]));
+    for (size_t i = 0; i < used; ++i) {
+      float ms = 0;
+      HKP_CHECK(hipEventElapsedTime(&ms, ev[2 * i], ev[2 * i + 1]));
+      if (kind[i]) {
+        t64 += ms * 1e-3;
+        b64 += bytes[i];
+        ++n64;
+      } else {
+        t32 += ms * 1e-3;
+        b32 += bytes[i];
+        ++n32;
+      }
+    }
+    used = 0;
+  }
+};
+
 struct Ctx {
+  StencilStats* ss = nullptr;
+  int active_members = 1;   // host view of unconverged Hamiltonians (byte accounting)
   Plan p;
   Layout L;
   char* ws;
   hipStream_t s;
   StencilConsts<double> consts;
   bool field;
+  bool field_z;   // Bz != 0: y-link phases vary along x
   bool strain;
   template <typename T>
   T* at(size_t off) const { return reinterpret_cast<T*>(ws + off); }
@@ -173,8 +241,10 @@ StencilLaunch base_launch(const Ctx& c, bool fp64, int nvec) {
   if (c.field) {
     a.wtab = fp64 ? (const void*)c.at<double>(c.L.w64) : (const void*)c.at<float>(c.L.w32);
     a.vtab = fp64 ? (const void*)c.at<double>(c.L.v64) : (const void*)c.at<float>(c.L.v32);
+    a.phase_general = c.field_z;
   }
   a.tile_y = c.p.tile_y;
+  a.order = c.p.order;
   a.fp64 = fp64;
   a.coef.coef = nullptr;
   a.coef.alpha = 1.0;
@@ -192,12 +262,11 @@ void apply_block(const Ctx& c, size_t x_off, size_t w_off, const int* active) {
   a.out_fp64 = 1;
   a.out_bstride = c.bstride();
   a.active = active;
-  HKP_CHECK(launch_stencil(a, c.consts, c.s));
+  c.ss->launch(a, c.consts, c.s, c.p.N, c.active_members);
 }
 
-// Chebyshev filter in FP64: the filtered block ends in X (degree even)
-void filter64(const Ctx& c, const int* active) {
-  const int m = c.p.degree;
+// Chebyshev filter of degree m (even) in FP64: the filtered block ends in X
+void filter64(const Ctx& c, const int* active, int m) {
   const int kstride = kKmax * 4;
   HKP_CHECK(launch_cheb_first(c.blk(c.L.X, c.p.nb), c.blk(c.L.W, c.p.nb), c.at<double>(c.L.W),
                               1, c.bstride(), c.p.batch, c.at<double>(c.L.coef), kstride, active,
@@ -216,15 +285,14 @@ void filter64(const Ctx& c, const int* active) {
     a.coef.coef = c.at<double>(c.L.coef) + 4 * k;
     a.coef.stride = kstride;
     a.active = active;
-    HKP_CHECK(launch_stencil(a, c.consts, c.s));
+    c.ss->launch(a, c.consts, c.s, c.p.N, c.active_members);
     std::swap(cur, oth);
   }
 }
 
 // Chebyshev filter in FP32 (mixed precision): X (FP64) and W = H X start it,
 // the last step writes FP64 into X
-void filter32(const Ctx& c, const int* active) {
-  const int m = c.p.degree;
+void filter32(const Ctx& c, const int* active, int m) {
   const int kstride = kKmax * 4;
   float* A = c.at<float>(c.L.A32);
   float* Bf = c.at<float>(c.L.B32);
@@ -250,21 +318,30 @@ void filter32(const Ctx& c, const int* active) {
     a.coef.coef = c.at<double>(c.L.coef) + 4 * k;
     a.coef.stride = kstride;
     a.active = active;
-    HKP_CHECK(launch_stencil(a, c.consts, c.s));
+    c.ss->launch(a, c.consts, c.s, c.p.N, c.active_members);
     old = in;
     old64 = 0;
     in = out;
   }
 }
 
-void svqb(const Ctx& c, const int* active) {
+// one SVQB pass on X; `again` (optional) receives the per-member need for a second pass
+void svqb(const Ctx& c, const int* active, int* again = nullptr) {
   BlockDesc X = c.blk(c.L.X, c.p.nb);
   HKP_CHECK(launch_gram(X, X, 1, c.p.batch, c.at<double>(c.L.gram), c.at<double>(c.L.mat1),
                         active, c.s));
   HKP_CHECK(launch_heev(c.at<double>(c.L.mat1), c.p.nb, c.p.batch, (long long)c.p.nb * c.p.nb,
                         c.at<double>(c.L.lam), c.at<double>(c.L.mat2), 1, c.at<int>(c.L.status),
-                        active, c.s));
+                        active, c.s, again));
   HKP_CHECK(launch_rotate(X, X, c.p.nb, c.p.nb, c.at<double>(c.L.mat2), c.p.batch, active, c.s));
+}
+
+// orthonormalise X: SVQB, repeated (only for the members that need it) when
+// the first Gram matrix was ill conditioned
+void orthonormalise(const Ctx& c, const int* active) {
+  int* again = c.at<int>(c.L.again);
+  svqb(c, active, again);
+  svqb(c, again);
 }
 
 void rayleigh_ritz(const Ctx& c, const int* active) {
@@ -305,7 +382,7 @@ void lanczos_bounds(const Ctx& c, std::vector<double>& bup) {
     a.out = w;
     a.out_fp64 = 1;
     a.out_bstride = bs;
-    HKP_CHECK(launch_stencil(a, c.consts, c.s));
+    c.ss->launch(a, c.consts, c.s, c.p.N, B);
     double* alj = al + 2LL * j * B;
     HKP_CHECK(launch_dots(v, w, n, B, bs, part, alj, c.s));
     HKP_CHECK(launch_lanczos_update(w, v, j > 0 ? vp : nullptr, n, B, bs, alj,
@@ -379,7 +456,11 @@ Plan make_plan(const hkp_grid& g, const hkp_opts& o, int batch) {
   p.batch = batch;
   p.nev = o.nev;
   p.nb = o.nb > 0 ? o.nb : default_nb(o.nev, p.n6);
-  int m = o.degree > 0 ? o.degree : 16;
+  // degree 0: ramp 16 -> 32 -> m_max over the first outer iterations, so that
+  // the amplification of the lowest components relative to the filter's cut
+  // stays within the arithmetic's dynamic range while the interval settles
+  p.degree_fixed = o.degree > 0;
+  int m = o.degree > 0 ? o.degree : (o.precision == HKP_PREC_MIXED ? 64 : 96);
   if (m & 1) ++m;
   if (m > kKmax) m = kKmax;
   p.degree = m;
@@ -401,18 +482,26 @@ size_t plan_bytes(const Plan& p) { return make_layout(p).total; }
 int run_solve(const SolveArgs& A, hkp_stats* stats) {
   const auto t_start = std::chrono::steady_clock::now();
   Ctx c;
+  StencilStats sst;
+  c.ss = &sst;
+  c.active_members = A.plan.batch;
   c.p = A.plan;
   c.L = make_layout(c.p);
   c.ws = reinterpret_cast<char*>(A.workspace);
   c.s = reinterpret_cast<hipStream_t>(A.stream);
   c.field = A.B[0] != 0.0 || A.B[1] != 0.0 || A.B[2] != 0.0;
+  c.field_z = A.B[2] != 0.0;
   c.strain = A.strain != nullptr;
   c.consts = make_consts(A.mat, c.p.h, A.B);
   if (A.tile_y > 0) c.p.tile_y = A.tile_y;
+  c.p.order = A.order;
   const Plan& p = c.p;
   const bool eager = !(A.flags & HKP_FLAG_GRAPH);
+  const char* tr = std::getenv("HKP_TRACE");
+  const bool trace = tr && tr[0] == '1';
   const bool timed = eager && stats != nullptr;
   Timer t_setup(timed), t_filter(timed), t_orth(timed), t_rr(timed), t_res(timed);
+  sst.timed = timed;
 
   // ---- setup: on-site fields, phase tables, flags
   t_setup.start(c.s);
@@ -460,11 +549,10 @@ int run_solve(const SolveArgs& A, hkp_stats* stats) {
                                   A.seed, c.s));
   }
   const int* act = c.at<int>(c.L.active);
-  svqb(c, act);
-  svqb(c, act);
+  orthonormalise(c, act);
   rayleigh_ritz(c, act);
   residuals(c, act);
-  HKP_CHECK(launch_control(c.control(), p.batch, p.nb, p.nev, p.degree, kKmax, A.tol, p.mixed,
+  HKP_CHECK(launch_control(c.control(), p.batch, p.nb, p.nev, kKmax, kKmax, A.tol, p.mixed,
                            !(A.flags & HKP_FLAG_NO_FP64_POLISH), 0, c.s));
   t_setup.stop(c.s);
   t_setup.collect();
@@ -483,11 +571,19 @@ int run_solve(const SolveArgs& A, hkp_stats* stats) {
       if (!hflags[8 * b]) return false;
     return true;
   };
+  auto degree_at = [&](int it) {   // it = 1, 2, ...
+    if (p.degree_fixed) return p.degree;
+    const int ramp = it == 1 ? 16 : (it == 2 ? 32 : p.degree);
+    return std::min(ramp, p.degree);
+  };
+  int m_cur = degree_at(1);
   auto count_work = [&]() {
+    c.active_members = 0;
+    for (int b = 0; b < p.batch; ++b) c.active_members += hflags[8 * b] ? 0 : 1;
     for (int b = 0; b < p.batch; ++b) {
       if (hflags[8 * b]) continue;
       const bool f32 = p.mixed && !hflags[8 * b + 1];
-      (f32 ? n_hx32 : n_hx64) += (long long)p.nb * p.degree;
+      (f32 ? n_hx32 : n_hx64) += (long long)p.nb * m_cur;
       n_hx64 += p.nb;
     }
   };
@@ -495,31 +591,33 @@ int run_solve(const SolveArgs& A, hkp_stats* stats) {
   auto iteration = [&](int it, bool single_path_known, bool f32_only) {
     t_filter.start(c.s);
     if (!single_path_known) {
-      if (p.mixed) filter32(c, c.at<int>(c.L.act32));
-      filter64(c, c.at<int>(c.L.act64));
+      if (p.mixed) filter32(c, c.at<int>(c.L.act32), m_cur);
+      filter64(c, c.at<int>(c.L.act64), m_cur);
     } else if (f32_only) {
-      filter32(c, act);
+      filter32(c, act, m_cur);
     } else {
-      filter64(c, act);
+      filter64(c, act, m_cur);
     }
     t_filter.stop(c.s);
     t_orth.start(c.s);
-    svqb(c, act);
-    svqb(c, act);
+    orthonormalise(c, act);
     t_orth.stop(c.s);
     t_rr.start(c.s);
     rayleigh_ritz(c, act);
     t_rr.stop(c.s);
     t_res.start(c.s);
     residuals(c, act);
-    HKP_CHECK(launch_control(c.control(), p.batch, p.nb, p.nev, p.degree, kKmax, A.tol,
+    HKP_CHECK(launch_control(c.control(), p.batch, p.nb, p.nev, kKmax, kKmax, A.tol,
                              p.mixed, !(A.flags & HKP_FLAG_NO_FP64_POLISH), it, c.s));
     t_res.stop(c.s);
   };
 
-  if (eager) {
-    while (iters < A.max_iter && !all_done()) {
+  // eager iterations: all of them, or in graph mode the ramp-up ones
+  const int eager_iters = eager ? A.max_iter : (p.degree_fixed ? 0 : 2);
+  {
+    while (iters < std::min(A.max_iter, eager_iters) && !all_done()) {
       ++iters;
+      m_cur = degree_at(iters);
       count_work();
       if (p.batch == 1) {
         const bool f32 = p.mixed && !hflags[1];
@@ -528,13 +626,22 @@ int run_solve(const SolveArgs& A, hkp_stats* stats) {
         iteration(iters, false, false);
       }
       read_flags();
+      if (trace) {
+        double bd[4];
+        HKP_CHECK(hipMemcpy(bd, c.at<double>(c.L.bounds), 32, hipMemcpyDeviceToHost));
+        std::fprintf(stderr, "[hkp] it %d nconv %d rmax %.3e a_cut %.6f a0 %.6f fp64 %d\n", iters,
+                     hflags[4], bd[3], bd[1], bd[2], hflags[1]);
+      }
       t_filter.collect();
       t_orth.collect();
       t_rr.collect();
       t_res.collect();
+      sst.collect();
     }
-  } else {
+  }
+  if (!eager && iters < A.max_iter && !all_done()) {
     // record a chunk of iterations once, replay until converged
+    m_cur = p.degree;
     const int chunk = std::max(1, std::min(A.graph_chunk > 0 ? A.graph_chunk : 4, A.max_iter));
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
@@ -575,7 +682,7 @@ int run_solve(const SolveArgs& A, hkp_stats* stats) {
     if (hflags[8 * b + 1]) sw = sw < 0 ? hflags[8 * b + 5] : std::min(sw, hflags[8 * b + 5]);
   }
   if (stats) {
-    stats->iters = eager ? iters : maxit;
+    stats->iters = std::max(0, maxit - 1);   // device count includes the initial Rayleigh-Ritz
     stats->n_converged = minconv;
     stats->n_hx_fp64 = n_hx64;
     stats->n_hx_fp32 = n_hx32;
@@ -588,6 +695,14 @@ int run_solve(const SolveArgs& A, hkp_stats* stats) {
     stats->t_rr = t_rr.acc;
     stats->t_resid = t_res.acc;
     stats->lambda_max_bound = bup.empty() ? 0.0 : bup[0];
+    sst.collect();
+    stats->hx_bytes = sst.hx_bytes;
+    stats->n_stencil32 = sst.n32;
+    stats->n_stencil64 = sst.n64;
+    stats->t_stencil32 = sst.t32;
+    stats->t_stencil64 = sst.t64;
+    stats->bytes_stencil32 = sst.b32;
+    stats->bytes_stencil64 = sst.b64;
     stats->seconds =
         std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count();
   }
@@ -655,11 +770,13 @@ int run_filter_step(const FilterArgs& A) {
   if (field) {
     a.wtab = fp64 ? (const void*)w64 : (const void*)w32;
     a.vtab = fp64 ? (const void*)v64 : (const void*)v32;
+    a.phase_general = A.B[2] != 0.0;
   }
   a.coef.alpha = A.alpha;
   a.coef.shift = A.shift;
   a.coef.beta = has_old ? A.beta : 0.0;
   a.tile_y = A.tile_y > 0 ? A.tile_y : 4;
+  a.order = A.order;
   a.fp64 = fp64;
   HKP_CHECK(launch_stencil(a, make_consts(A.mat, g.h_nm, A.B), s));
   HKP_CHECK(launch_internal_to_abi(g.nx, g.ny, g.nz, g.h_nm, A.B, A.nvec, 1, Yi, 0, A.Y, 0, s));

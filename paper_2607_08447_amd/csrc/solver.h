@@ -11,9 +11,11 @@ struct Plan {
   int nx, ny, nz;
   double h;
   long long N, n6;   // grid points, complex unknowns per vector
-  int batch, nev, nb, degree;
+  int batch, nev, nb, degree;   // degree: fixed value or the ramp's maximum
+  bool degree_fixed;
   bool mixed;
   int tile_y;
+  int order;
 };
 
 struct SolveArgs {
@@ -33,6 +35,7 @@ struct SolveArgs {
   int flags;
   unsigned long long seed;
   int tile_y;       // 0: plan default
+  int order;        // stencil workgroup order
   int graph_chunk;  // iterations per recorded graph
 };
 
@@ -51,6 +54,7 @@ struct FilterArgs {
   void* workspace;
   void* stream;
   int tile_y;
+  int order;
 };
 
 int default_nb(int nev, long long n6);
@@ -61,6 +65,7 @@ size_t apply_bytes(const hkp_grid& g, int nvec);
 int run_filter_step(const FilterArgs& a);
 int guarded(const std::function<int()>& f);
 int autotuned_tile(const hkp_grid& g, int nb, bool mixed);
+int autotuned_order(const hkp_grid& g, int nb, bool mixed);
 int run_autotune(const hkp_grid& g, int nb, bool mixed, bool strain, bool field, void* ws,
                  size_t ws_bytes, void* stream, hkp_tune* out);
 

@@ -19,8 +19,9 @@
 // LDS and "pushes" the plane's contributions into three register accumulators
 // for the output planes z-1, z and z+1.  The x-z and y-z edge couplings of a
 // plane therefore need only that plane's x/y neighbours, so one plane of LDS
-// per vector suffices.  The next plane is prefetched into registers while the
-// current one is computed, so HBM loads overlap arithmetic.  Output plane z-1
+// per vector suffices.  Planes are double-buffered in LDS: the next plane is
+// loaded into the other buffer while the current one is read (one barrier
+// per plane), so HBM loads of one wave overlap the arithmetic of the others.  Output plane z-1
 // is complete after plane z has been pushed and is written straight to HBM
 // (alpha, beta and the old block fused in).  Workgroups are mapped to XCDs in
 // contiguous runs so that the vectors of one tile share an L2.
@@ -119,35 +120,57 @@ struct KArgs {
   const int* active;
   int nx, ny, nz, nvec;
   int tiles_x, tiles_y;
+  int order;
   StencilConsts<T> k;
 };
 
-template <typename T, typename TO, typename TW, bool PH, bool STR, int TY>
-__global__ void __launch_bounds__(64 * TY)
+template <int V>
+struct IC {
+  static constexpr int value = V;
+};
+
+template <typename T, typename TO, typename TW, int PH, bool STR, int TY>
+__global__ void __launch_bounds__(128 * TY)
 stencil_kernel(KArgs<T> a) {
   constexpr int W = 66;               // 64 + halo
   constexpr int ROWS = TY + 2;
   constexpr int SLOTS = W * ROWS;
-  constexpr int NT = 64 * TY;
+  constexpr int PLANE = SLOTS;        // elements per (buffer, component) plane
+  constexpr int NT = 128 * TY;        // (x, y, spin) threads
   constexpr int NS = (SLOTS + NT - 1) / NT;
-  __shared__ cx<T> lds[6][ROWS][W];
+  __shared__ cx<T> ldsb[2 * 6 * PLANE];   // [buffer][component][row][col], double-buffered
 
   const int logical = xcd_remap(blockIdx.x, gridDim.x);
-  const int vec = logical % a.nvec;
-  int rest = logical / a.nvec;
-  const int tile = rest % (a.tiles_x * a.tiles_y);
-  const int b = rest / (a.tiles_x * a.tiles_y);
+  const int ntiles = a.tiles_x * a.tiles_y;
+  int vec, tile, b;
+  if (a.order == 0) {
+    // tile-major: the vectors of one tile run together (share on-site fields in L2)
+    vec = logical % a.nvec;
+    const int rest = logical / a.nvec;
+    tile = rest % ntiles;
+    b = rest / ntiles;
+  } else {
+    // vector-major: all tiles of one vector run together on one XCD and march z
+    // in step, so the halo rows a tile shares with its neighbours hit in L2
+    tile = logical % ntiles;
+    const int rest = logical / ntiles;
+    vec = rest % a.nvec;
+    b = rest / a.nvec;
+  }
   if (a.active && !a.active[b]) return;
   const int tx0 = (tile % a.tiles_x) * 64;
   const int ty0 = (tile / a.tiles_x) * TY;
 
   const int nx = a.nx, ny = a.ny, nz = a.nz;
-  const long long nxy = (long long)nx * ny;
-  const long long N = nxy * nz;
-  const int tid = threadIdx.x + 64 * threadIdx.y;
+  const unsigned nxy = (unsigned)nx * (unsigned)ny;
+  const unsigned N = nxy * (unsigned)nz;   // < 2^28 (checked on the host)
   const int lx = threadIdx.x, ly = threadIdx.y;
+  // the spin is uniform across a wave (64 consecutive threads share threadIdx.z)
+  const int sp = __builtin_amdgcn_readfirstlane(threadIdx.z);
+  const int tid = lx + 64 * (ly + TY * sp);
   const int gx = tx0 + lx, gy = ty0 + ly;
   const bool mine = gx < nx && gy < ny;
+  const int X = 3 * sp, F = 3 - X;      // own and flipped-spin component offsets
 
   T alpha, shift, beta;
   if (a.coef) {
@@ -162,176 +185,220 @@ stencil_kernel(KArgs<T> a) {
   }
   const bool has_old = a.old != nullptr && beta != (T)0;
 
-  const T* in = a.in + 2 * ((long long)b * a.in_bstride + (long long)vec * 6 * N);
-  const long long old_off = (long long)b * a.old_bstride + (long long)vec * 6 * N;
-  const long long out_off = (long long)b * a.out_bstride + (long long)vec * 6 * N;
-  const T* D = a.D + (long long)b * a.D_bstride;
+  // uniform (scalar) bases; lane offsets are 32-bit element indices
+  const T* __restrict__ in = a.in + 2 * ((long long)b * a.in_bstride + (long long)vec * 6 * N);
+  const TO* __restrict__ oldp = has_old
+      ? reinterpret_cast<const TO*>(a.old) +
+            2 * ((long long)b * a.old_bstride + (long long)vec * 6 * N + (long long)X * N)
+      : nullptr;
+  TW* __restrict__ outp = reinterpret_cast<TW*>(a.out) +
+                          2 * ((long long)b * a.out_bstride + (long long)vec * 6 * N +
+                               (long long)X * N);
+  const T* __restrict__ D = a.D + (long long)b * a.D_bstride;
   const StencilConsts<T> k = a.k;
+  // spin-dependent constants (sp is wave-uniform: scalar selects)
+  const T dgs = sp == 0 ? k.dgU : k.dgD;
+  const T ax = sp == 0 ? k.aUx : k.aDx, ay = sp == 0 ? k.aUy : k.aDy,
+          az = sp == 0 ? k.aUz : k.aDz;
+  const T sd3 = sp == 0 ? -k.d3 : k.d3;   // sign of the d3 f_Z and f_X spin-flip terms
+  const T sby = sp == 0 ? -k.by : k.by;   // (bx -+ i by)
 
-  // slot -> (row, col) of the halo tile owned by this thread for loads
-  int srow[NS], scol[NS];
-  bool sval[NS];
-  long long soff[NS];
+  // halo-tile slots this thread loads (clamped offset + mask; waves whose
+  // slots are all inside the grid skip the mask)
+  unsigned soff[NS];
+  int sidx[NS];
+  bool sval[NS], sin_[NS], wmask[NS];
 #pragma unroll
   for (int s = 0; s < NS; ++s) {
     const int slot = tid + s * NT;
-    srow[s] = slot / W;
-    scol[s] = slot % W;
-    const int x = tx0 + scol[s] - 1, y = ty0 + srow[s] - 1;
-    sval[s] = slot < SLOTS && x >= 0 && x < nx && y >= 0 && y < ny;
-    soff[s] = sval[s] ? (long long)y * nx + x : 0;
+    sin_[s] = slot < SLOTS;
+    const int row = slot / W, colx = slot % W;
+    const int x = tx0 + colx - 1, y = ty0 + row - 1;
+    sval[s] = sin_[s] && x >= 0 && x < nx && y >= 0 && y < ny;
+    soff[s] = sval[s] ? (unsigned)(y * nx + x) : 0u;
+    sidx[s] = sin_[s] ? slot : 0;
+    wmask[s] = !__all(sval[s] || !sin_[s]);
   }
 
-  cx<T> pf[NS][6];
-  auto prefetch = [&](int z) {
-#pragma unroll
-    for (int s = 0; s < NS; ++s)
-#pragma unroll
-      for (int c = 0; c < 6; ++c)
-        pf[s][c] = sval[s] ? ld(in + 2 * ((long long)c * N + (long long)z * nxy + soff[s]))
-                           : mk<T>(0, 0);
-  };
-
-  cx<T> acc0[6], acc1[6];
-#pragma unroll
-  for (int c = 0; c < 6; ++c) acc0[c] = acc1[c] = mk<T>(0, 0);
-
-  const long long col = mine ? (long long)gy * nx + gx : 0;
+  const unsigned col = mine ? (unsigned)(gy * nx + gx) : 0u;
   const int gxc = gx < nx ? gx : nx - 1;
+  const int lb = (ly + 1) * W + (lx + 1);   // this thread's centre in an LDS plane
 
-  auto finalize = [&](int z, cx<T>* acc) {
-    if (!mine) return;
-    const long long base = (long long)z * nxy + col;
+  cx<T> acc0[3], acc1[3], oldv[3];
 #pragma unroll
-    for (int c = 0; c < 6; ++c) {
-      cx<T> r = scl(alpha, acc[c]);
-      if (has_old) {
-        cx<TO> o = ldg<TO>(a.old, old_off + (long long)c * N + base);
-        r = fma_s(r, beta, mk<T>((T)o.r, (T)o.i));
+  for (int i = 0; i < 3; ++i) acc0[i] = acc1[i] = oldv[i] = mk<T>(0, 0);
+
+  // next plane: loads issued before the current plane is computed, written to
+  // the other LDS buffer after it (the wave's own arithmetic hides the latency)
+  auto fetch = [&](int z, cx<T> (&v)[NS][6]) {
+    const unsigned zo = (unsigned)z * nxy;
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+      if (NS * NT > SLOTS && !sin_[s]) continue;
+#pragma unroll
+      for (int c = 0; c < 6; ++c) v[s][c] = ld(in + 2 * (size_t)((unsigned)c * N + zo + soff[s]));
+    }
+  };
+  auto commit = [&](cx<T> (&v)[NS][6], auto BUF) {
+    constexpr int B0 = decltype(BUF)::value * 6 * PLANE;
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+      if (NS * NT > SLOTS && !sin_[s]) continue;
+#pragma unroll
+      for (int c = 0; c < 6; ++c) {
+        cx<T> x = v[s][c];
+        if (wmask[s] && !sval[s]) x = mk<T>(0, 0);
+        ldsb[B0 + c * PLANE + sidx[s]] = x;
       }
-      stg<TW>(a.out, out_off + (long long)c * N + base, r);
     }
   };
 
-  prefetch(0);
-  for (int z = 0; z < nz; ++z) {
-    __syncthreads();
+  auto load_old = [&](int z) {
+    if (!has_old || !mine) return;
+    const unsigned o = (unsigned)z * nxy + col;
 #pragma unroll
-    for (int s = 0; s < NS; ++s)
-      if (tid + s * NT < SLOTS)
-#pragma unroll
-        for (int c = 0; c < 6; ++c) lds[c][srow[s]][scol[s]] = pf[s][c];
-    __syncthreads();
-    if (z + 1 < nz) prefetch(z + 1);
-
-    // ---- neighbourhood of (gx, gy, z) from LDS
-    const int r0 = ly + 1, c0 = lx + 1;
-    cx<T> own[6], xp[6], xm[6], yp[6], ym[6];
-#pragma unroll
-    for (int c = 0; c < 6; ++c) {
-      own[c] = lds[c][r0][c0];
-      xp[c] = lds[c][r0][c0 + 1];
-      xm[c] = lds[c][r0][c0 - 1];
-      yp[c] = lds[c][r0 + 1][c0];
-      ym[c] = lds[c][r0 - 1][c0];
+    for (int i = 0; i < 3; ++i) {
+      cx<TO> q = ld(oldp + 2 * (size_t)((unsigned)i * N + o));
+      oldv[i] = mk<T>((T)q.r, (T)q.i);
     }
+  };
+  auto finalize = [&](int z) {
+    if (!mine) return;
+    const unsigned o = (unsigned)z * nxy + col;
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      cx<T> r = scl(alpha, acc0[i]);
+      if (has_old) r = fma_s(r, beta, oldv[i]);
+      stg<TW>(outp, (long long)((unsigned)i * N + o), r);
+    }
+  };
 
-    // ---- phases (GPU gauge): x-links per plane, y-links per (plane, column)
+  auto step = [&](int z, auto BUF) {
+    constexpr int cur = decltype(BUF)::value;
+    // the next plane goes to the other buffer while this one is read; the
+    // barrier at the end of the step publishes it and retires this buffer
+    // FP32: loads of the next plane issued before the arithmetic and written to
+    // LDS after it (latency hidden by this wave's own work); FP64 writes them
+    // at once (its register budget is already exhausted by the arithmetic)
+    constexpr bool late = sizeof(T) == 4;
+    cx<T> nxt[NS][6];
+    const bool more = z + 1 < nz;
+    if (more) {
+      fetch(z + 1, nxt);
+      if constexpr (!late) commit(nxt, IC<1 - cur>{});
+    }
+    if (z >= 1) load_old(z - 1);
+    const cx<T>* L = ldsb + cur * 6 * PLANE + lb;
+    auto at = [&](int c, int dy, int dx) { return L[c * PLANE + dy * W + dx]; };
+
+    // ---- phases (GPU gauge): x-links per plane, y-links per (plane, column);
+    // with Bz = 0 (PH == 1) every phase is uniform over the plane
     cx<T> w0, wm, wp, v0, vm, vp, vxp, vxm;
-    if constexpr (PH) {
+    if constexpr (PH != 0) {
       const int zm = z > 0 ? z - 1 : 0, zq = z + 1 < nz ? z + 1 : nz - 1;
       w0 = ld(a.wtab + 2 * z);
       wm = ld(a.wtab + 2 * zm);
       wp = ld(a.wtab + 2 * zq);
-      v0 = ld(a.vtab + 2 * ((long long)z * nx + gxc));
-      vm = ld(a.vtab + 2 * ((long long)zm * nx + gxc));
-      vp = ld(a.vtab + 2 * ((long long)zq * nx + gxc));
-      vxp = ld(a.vtab + 2 * ((long long)z * nx + (gxc + 1 < nx ? gxc + 1 : gxc)));
-      vxm = ld(a.vtab + 2 * ((long long)z * nx + (gxc > 0 ? gxc - 1 : 0)));
+      const int xc = PH == 1 ? 0 : gxc;
+      v0 = ld(a.vtab + 2 * (z * nx + xc));
+      vm = ld(a.vtab + 2 * (zm * nx + xc));
+      vp = ld(a.vtab + 2 * (zq * nx + xc));
+      if constexpr (PH == 2) {
+        vxp = ld(a.vtab + 2 * (z * nx + (gxc + 1 < nx ? gxc + 1 : gxc)));
+        vxm = ld(a.vtab + 2 * (z * nx + (gxc > 0 ? gxc - 1 : 0)));
+      }
     }
 
-    cx<T> acc2[6];
-#pragma unroll
-    for (int s = 0; s < 2; ++s) {
-      const int X = 3 * s, Y = 3 * s + 1, Z = 3 * s + 2;
-      // faces in the plane
+    cx<T> acc2[3];
+    {
+      // faces in the plane (this spin's three orbitals)
       cx<T> Sx[3], Sy[3];
 #pragma unroll
       for (int i = 0; i < 3; ++i) {
-        if constexpr (PH) {
-          Sx[i] = wsum(w0, xp[X + i], xm[X + i]);
-          Sy[i] = wsum(v0, yp[X + i], ym[X + i]);
+        const cx<T> xp = at(X + i, 0, 1), xm = at(X + i, 0, -1);
+        const cx<T> yp = at(X + i, 1, 0), ym = at(X + i, -1, 0);
+        if constexpr (PH != 0) {
+          Sx[i] = wsum(w0, xp, xm);
+          Sy[i] = wsum(v0, yp, ym);
         } else {
-          Sx[i] = add(xp[X + i], xm[X + i]);
-          Sy[i] = add(yp[X + i], ym[X + i]);
+          Sx[i] = add(xp, xm);
+          Sy[i] = add(yp, ym);
         }
       }
-      acc1[X] = fma_s(acc1[X], k.cLM, Sx[0]);
-      acc1[Y] = fma_s(acc1[Y], k.cLM, Sy[1]);
+      acc1[0] = fma_s(acc1[0], k.cLM, Sx[0]);
+      acc1[1] = fma_s(acc1[1], k.cLM, Sy[1]);
 #pragma unroll
-      for (int i = 0; i < 3; ++i) acc1[X + i] = fma_s(acc1[X + i], k.cM, add(Sx[i], Sy[i]));
-
+      for (int i = 0; i < 3; ++i) acc1[i] = fma_s(acc1[i], k.cM, add(Sx[i], Sy[i]));
+    }
+    {
       // x-y edges (in plane): couple X <-> Y
-      {
-        const cx<T> fY_pp = lds[Y][r0 + 1][c0 + 1], fY_pm = lds[Y][r0 - 1][c0 + 1];
-        const cx<T> fY_mp = lds[Y][r0 + 1][c0 - 1], fY_mm = lds[Y][r0 - 1][c0 - 1];
-        const cx<T> fX_pp = lds[X][r0 + 1][c0 + 1], fX_pm = lds[X][r0 - 1][c0 + 1];
-        const cx<T> fX_mp = lds[X][r0 + 1][c0 - 1], fX_mm = lds[X][r0 - 1][c0 - 1];
-        if constexpr (PH) {
-          // P(sx, sy) = w^sx [ v(x+sx)^sy + v(x)^sy ]
-          const cx<T> ppp = mul(w0, add(vxp, v0));
-          const cx<T> ppm = mul(w0, conj(add(vxp, v0)));
-          const cx<T> pmp = mul(conj(w0), add(vxm, v0));
-          const cx<T> pmm = mul(conj(w0), conj(add(vxm, v0)));
-          cx<T> eY = sub(add(mul(ppp, fY_pp), mul(pmm, fY_mm)), add(mul(ppm, fY_pm), mul(pmp, fY_mp)));
-          cx<T> eX = sub(add(mul(ppp, fX_pp), mul(pmm, fX_mm)), add(mul(ppm, fX_pm), mul(pmp, fX_mp)));
-          acc1[X] = fma_s(acc1[X], k.cN8, eY);
-          acc1[Y] = fma_s(acc1[Y], k.cN8, eX);
-        } else {
-          cx<T> eY = sub(add(fY_pp, fY_mm), add(fY_pm, fY_mp));
-          cx<T> eX = sub(add(fX_pp, fX_mm), add(fX_pm, fX_mp));
-          const T c2 = k.cN8 + k.cN8;
-          acc1[X] = fma_s(acc1[X], c2, eY);
-          acc1[Y] = fma_s(acc1[Y], c2, eX);
-        }
-      }
-
-      // z faces: pushed to z-1 and z+1
-      acc0[X] = fma_s(acc0[X], k.cM, own[X]);
-      acc0[Y] = fma_s(acc0[Y], k.cM, own[Y]);
-      acc0[Z] = fma_s(acc0[Z], k.czZ, own[Z]);
-      acc2[X] = scl(k.cM, own[X]);
-      acc2[Y] = scl(k.cM, own[Y]);
-      acc2[Z] = scl(k.czZ, own[Z]);
-
-      // x-z and y-z edges of this plane, pushed to z-1 (sz = +1) and z+1 (sz = -1)
-      if constexpr (PH) {
-        const cx<T> wu = add(wm, w0), wd = add(wp, w0);   // path averages (x2)
-        const cx<T> vu = add(vm, v0), vd = add(vp, v0);
-        acc0[X] = fma_s(acc0[X], k.cN8, wdiff(wu, xp[Z], xm[Z]));
-        acc0[Z] = fma_s(acc0[Z], k.cN8, wdiff(wu, xp[X], xm[X]));
-        acc0[Y] = fma_s(acc0[Y], k.cN8, wdiff(vu, yp[Z], ym[Z]));
-        acc0[Z] = fma_s(acc0[Z], k.cN8, wdiff(vu, yp[Y], ym[Y]));
-        acc2[X] = fma_s(acc2[X], -k.cN8, wdiff(wd, xp[Z], xm[Z]));
-        acc2[Z] = fma_s(acc2[Z], -k.cN8, wdiff(wd, xp[X], xm[X]));
-        acc2[Y] = fma_s(acc2[Y], -k.cN8, wdiff(vd, yp[Z], ym[Z]));
-        acc2[Z] = fma_s(acc2[Z], -k.cN8, wdiff(vd, yp[Y], ym[Y]));
-      } else {
+      const cx<T> fY_pp = at(X + 1, 1, 1), fY_pm = at(X + 1, -1, 1);
+      const cx<T> fY_mp = at(X + 1, 1, -1), fY_mm = at(X + 1, -1, -1);
+      const cx<T> fX_pp = at(X, 1, 1), fX_pm = at(X, -1, 1);
+      const cx<T> fX_mp = at(X, 1, -1), fX_mm = at(X, -1, -1);
+      if constexpr (PH == 2) {
+        // P(sx, sy) = w^sx [ v(x+sx)^sy + v(x)^sy ]
+        const cx<T> ppp = mul(w0, add(vxp, v0));
+        const cx<T> ppm = mul(w0, conj(add(vxp, v0)));
+        const cx<T> pmp = mul(conj(w0), add(vxm, v0));
+        const cx<T> pmm = mul(conj(w0), conj(add(vxm, v0)));
+        cx<T> eY = sub(add(mul(ppp, fY_pp), mul(pmm, fY_mm)), add(mul(ppm, fY_pm), mul(pmp, fY_mp)));
+        cx<T> eX = sub(add(mul(ppp, fX_pp), mul(pmm, fX_mm)), add(mul(ppm, fX_pm), mul(pmp, fX_mp)));
+        acc1[0] = fma_s(acc1[0], k.cN8, eY);
+        acc1[1] = fma_s(acc1[1], k.cN8, eX);
+      } else if constexpr (PH == 1) {
+        // uniform phases: P(sx, sy) = 2 w^sx v^sy, so the corner sum is
+        // 2 [w (v f++ - v* f+-) - w* (v f-+ - v* f--)]
         const T c2 = k.cN8 + k.cN8;
-        const cx<T> dxZ = sub(xp[Z], xm[Z]), dxX = sub(xp[X], xm[X]);
-        const cx<T> dyZ = sub(yp[Z], ym[Z]), dyY = sub(yp[Y], ym[Y]);
-        acc0[X] = fma_s(acc0[X], c2, dxZ);
-        acc0[Z] = fma_s(acc0[Z], c2, add(dxX, dyY));
-        acc0[Y] = fma_s(acc0[Y], c2, dyZ);
-        acc2[X] = fma_s(acc2[X], -c2, dxZ);
-        acc2[Z] = fma_s(acc2[Z], -c2, add(dxX, dyY));
-        acc2[Y] = fma_s(acc2[Y], -c2, dyZ);
+        const cx<T> eY = wdiff(w0, wdiff(v0, fY_pp, fY_pm), wdiff(v0, fY_mp, fY_mm));
+        const cx<T> eX = wdiff(w0, wdiff(v0, fX_pp, fX_pm), wdiff(v0, fX_mp, fX_mm));
+        acc1[0] = fma_s(acc1[0], c2, eY);
+        acc1[1] = fma_s(acc1[1], c2, eX);
+      } else {
+        cx<T> eY = sub(add(fY_pp, fY_mm), add(fY_pm, fY_mp));
+        cx<T> eX = sub(add(fX_pp, fX_mm), add(fX_pm, fX_mp));
+        const T c2 = k.cN8 + k.cN8;
+        acc1[0] = fma_s(acc1[0], c2, eY);
+        acc1[1] = fma_s(acc1[1], c2, eX);
       }
     }
-
-    // ---- on-site: orbital block (V + strain) on both spins, constants, SO/Zeeman
     {
-      const long long p = (long long)z * nxy + col;
+      const cx<T> oX = at(X, 0, 0), oY = at(X + 1, 0, 0), oZ = at(X + 2, 0, 0);
+      // z faces: pushed to z-1 and z+1
+      acc0[0] = fma_s(acc0[0], k.cM, oX);
+      acc0[1] = fma_s(acc0[1], k.cM, oY);
+      acc0[2] = fma_s(acc0[2], k.czZ, oZ);
+      acc2[0] = scl(k.cM, oX);
+      acc2[1] = scl(k.cM, oY);
+      acc2[2] = scl(k.czZ, oZ);
+      // x-z and y-z edges of this plane, pushed to z-1 (sz = +1) and z+1 (sz = -1)
+      const cx<T> xpZ = at(X + 2, 0, 1), xmZ = at(X + 2, 0, -1);
+      const cx<T> xpX = at(X, 0, 1), xmX = at(X, 0, -1);
+      const cx<T> ypZ = at(X + 2, 1, 0), ymZ = at(X + 2, -1, 0);
+      const cx<T> ypY = at(X + 1, 1, 0), ymY = at(X + 1, -1, 0);
+      if constexpr (PH != 0) {
+        const cx<T> wu = add(wm, w0), wd = add(wp, w0);   // path averages (x2)
+        const cx<T> vu = add(vm, v0), vd = add(vp, v0);
+        acc0[0] = fma_s(acc0[0], k.cN8, wdiff(wu, xpZ, xmZ));
+        acc0[2] = fma_s(acc0[2], k.cN8, add(wdiff(wu, xpX, xmX), wdiff(vu, ypY, ymY)));
+        acc0[1] = fma_s(acc0[1], k.cN8, wdiff(vu, ypZ, ymZ));
+        acc2[0] = fma_s(acc2[0], -k.cN8, wdiff(wd, xpZ, xmZ));
+        acc2[2] = fma_s(acc2[2], -k.cN8, add(wdiff(wd, xpX, xmX), wdiff(vd, ypY, ymY)));
+        acc2[1] = fma_s(acc2[1], -k.cN8, wdiff(vd, ypZ, ymZ));
+      } else {
+        const T c2 = k.cN8 + k.cN8;
+        const cx<T> dxZ = sub(xpZ, xmZ), dxX = sub(xpX, xmX);
+        const cx<T> dyZ = sub(ypZ, ymZ), dyY = sub(ypY, ymY);
+        acc0[0] = fma_s(acc0[0], c2, dxZ);
+        acc0[2] = fma_s(acc0[2], c2, add(dxX, dyY));
+        acc0[1] = fma_s(acc0[1], c2, dyZ);
+        acc2[0] = fma_s(acc2[0], -c2, dxZ);
+        acc2[2] = fma_s(acc2[2], -c2, add(dxX, dyY));
+        acc2[1] = fma_s(acc2[1], -c2, dyZ);
+      }
+
+      // ---- on-site: orbital block (V + strain), constants, SO/Zeeman
+      const unsigned p = (unsigned)z * nxy + col;
       T d00, d11, d22, d12 = 0, d02 = 0, d01 = 0;
       if constexpr (STR) {
         d00 = D[p];
@@ -343,69 +410,68 @@ stencil_kernel(KArgs<T> a) {
       } else {
         d00 = d11 = d22 = D[p];
       }
-#pragma unroll
-      for (int s = 0; s < 2; ++s) {
-        const int X = 3 * s;
-        const T dg = (s == 0 ? k.dgU : k.dgD) - shift;
-        const cx<T> u0 = own[X], u1 = own[X + 1], u2 = own[X + 2];
-        cx<T> r0v = scl(d00 + dg, u0), r1v = scl(d11 + dg, u1), r2v = scl(d22 + dg, u2);
-        if constexpr (STR) {
-          r0v = fma_s(fma_s(r0v, d01, u1), d02, u2);
-          r1v = fma_s(fma_s(r1v, d01, u0), d12, u2);
-          r2v = fma_s(fma_s(r2v, d02, u0), d12, u1);
-        }
-        // i (a x u)
-        const T ax = s == 0 ? k.aUx : k.aDx, ay = s == 0 ? k.aUy : k.aDy,
-                az = s == 0 ? k.aUz : k.aDz;
-        cx<T> c0v, c1v, c2v;
-        if constexpr (PH) {
-          c0v = sub(scl(ay, u2), scl(az, u1));
-          c1v = sub(scl(az, u0), scl(ax, u2));
-          c2v = sub(scl(ax, u1), scl(ay, u0));
-        } else {
-          c0v = scl(-az, u1);
-          c1v = scl(az, u0);
-          c2v = mk<T>(0, 0);
-        }
-        r0v = add(r0v, mul_i(c0v));
-        r1v = add(r1v, mul_i(c1v));
-        r2v = add(r2v, mul_i(c2v));
-        // spin flip: up <- -d3 (v_Z, -i v_Z, -v_X + i v_Y) + (bx - i by) v   (v = down)
-        //            dn <- -d3 (-v_Z, -i v_Z, v_X + i v_Y) + (bx + i by) v   (v = up)
-        const int F = 3 - X;
-        const cx<T> f0 = own[F], f1 = own[F + 1], f2 = own[F + 2];
-        if (s == 0) {
-          r0v = fma_s(r0v, -k.d3, f2);
-          r1v = fma_s(r1v, k.d3, mul_i(f2));
-          r2v = fma_s(r2v, -k.d3, sub(mul_i(f1), f0));
-        } else {
-          r0v = fma_s(r0v, k.d3, f2);
-          r1v = fma_s(r1v, k.d3, mul_i(f2));
-          r2v = fma_s(r2v, -k.d3, add(mul_i(f1), f0));
-        }
-        if constexpr (PH) {
-          const cx<T> bz = mk<T>(k.bx, s == 0 ? -k.by : k.by);
-          r0v = add(r0v, mul(bz, f0));
-          r1v = add(r1v, mul(bz, f1));
-          r2v = add(r2v, mul(bz, f2));
-        }
-        acc1[X] = add(acc1[X], r0v);
-        acc1[X + 1] = add(acc1[X + 1], r1v);
-        acc1[X + 2] = add(acc1[X + 2], r2v);
+      const T dg = dgs - shift;
+      cx<T> r0v = scl(d00 + dg, oX), r1v = scl(d11 + dg, oY), r2v = scl(d22 + dg, oZ);
+      if constexpr (STR) {
+        r0v = fma_s(fma_s(r0v, d01, oY), d02, oZ);
+        r1v = fma_s(fma_s(r1v, d01, oX), d12, oZ);
+        r2v = fma_s(fma_s(r2v, d02, oX), d12, oY);
       }
+      // i (a x u)
+      if constexpr (PH != 0) {
+        r0v = add(r0v, mul_i(sub(scl(ay, oZ), scl(az, oY))));
+        r1v = add(r1v, mul_i(sub(scl(az, oX), scl(ax, oZ))));
+        r2v = add(r2v, mul_i(sub(scl(ax, oY), scl(ay, oX))));
+      } else {
+        r0v = fma_s(r0v, -az, mul_i(oY));
+        r1v = fma_s(r1v, az, mul_i(oX));
+      }
+      // spin flip: up <- -d3 (v_Z, -i v_Z, -v_X + i v_Y) + (bx - i by) v   (v = down)
+      //            dn <- -d3 (-v_Z, -i v_Z, v_X + i v_Y) + (bx + i by) v   (v = up)
+      // i.e. r_X += s d3 v_Z, r_Y += d3 i v_Z, r_Z += -d3 i v_Y - s d3 v_X with
+      // s = -1 (up), +1 (down)
+      const cx<T> f0 = at(F, 0, 0), f1 = at(F + 1, 0, 0), f2 = at(F + 2, 0, 0);
+      r0v = fma_s(r0v, sd3, f2);
+      r1v = fma_s(r1v, k.d3, mul_i(f2));
+      r2v = fma_s(fma_s(r2v, -k.d3, mul_i(f1)), -sd3, f0);
+      if constexpr (PH != 0) {
+        const cx<T> bz = mk<T>(k.bx, sby);
+        r0v = add(r0v, mul(bz, f0));
+        r1v = add(r1v, mul(bz, f1));
+        r2v = add(r2v, mul(bz, f2));
+      }
+      acc1[0] = add(acc1[0], r0v);
+      acc1[1] = add(acc1[1], r1v);
+      acc1[2] = add(acc1[2], r2v);
     }
 
-    if (z >= 1) finalize(z - 1, acc0);
-#pragma unroll
-    for (int c = 0; c < 6; ++c) {
-      acc0[c] = acc1[c];
-      acc1[c] = acc2[c];
+    if (z >= 1) finalize(z - 1);
+    if constexpr (late) {
+      if (more) commit(nxt, IC<1 - cur>{});
     }
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      acc0[i] = acc1[i];
+      acc1[i] = acc2[i];
+    }
+    __syncthreads();
+  };
+
+  {
+    cx<T> first[NS][6];
+    fetch(0, first);
+    commit(first, IC<0>{});
   }
-  finalize(nz - 1, acc0);
+  __syncthreads();
+  for (int z = 0; z < nz; z += 2) {
+    step(z, IC<0>{});
+    if (z + 1 < nz) step(z + 1, IC<1>{});
+  }
+  load_old(nz - 1);
+  finalize(nz - 1);
 }
 
-template <typename T, typename TO, typename TW, bool PH, bool STR>
+template <typename T, typename TO, typename TW, int PH, bool STR>
 hipError_t launch_t(const StencilLaunch& L, const StencilConsts<double>& c, hipStream_t s) {
   KArgs<T> a;
   a.in = reinterpret_cast<const T*>(L.in);
@@ -428,6 +494,7 @@ hipError_t launch_t(const StencilLaunch& L, const StencilConsts<double>& c, hipS
   a.ny = L.ny;
   a.nz = L.nz;
   a.nvec = L.nvec;
+  a.order = L.order;
   a.k = cast_consts<T>(c);
   const int ty = L.tile_y;
   a.tiles_x = (L.nx + 63) / 64;
@@ -437,10 +504,10 @@ hipError_t launch_t(const StencilLaunch& L, const StencilConsts<double>& c, hipS
   if (nwg > 0x7fffffffLL) return hipErrorInvalidValue;
   dim3 grid((unsigned)nwg);
   switch (ty) {
-    case 1: stencil_kernel<T, TO, TW, PH, STR, 1><<<grid, dim3(64, 1), 0, s>>>(a); break;
-    case 2: stencil_kernel<T, TO, TW, PH, STR, 2><<<grid, dim3(64, 2), 0, s>>>(a); break;
-    case 4: stencil_kernel<T, TO, TW, PH, STR, 4><<<grid, dim3(64, 4), 0, s>>>(a); break;
-    case 8: stencil_kernel<T, TO, TW, PH, STR, 8><<<grid, dim3(64, 8), 0, s>>>(a); break;
+    case 1: stencil_kernel<T, TO, TW, PH, STR, 1><<<grid, dim3(64, 1, 2), 0, s>>>(a); break;
+    case 2: stencil_kernel<T, TO, TW, PH, STR, 2><<<grid, dim3(64, 2, 2), 0, s>>>(a); break;
+    case 4: stencil_kernel<T, TO, TW, PH, STR, 4><<<grid, dim3(64, 4, 2), 0, s>>>(a); break;
+    case 8: stencil_kernel<T, TO, TW, PH, STR, 8><<<grid, dim3(64, 8, 2), 0, s>>>(a); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -448,13 +515,13 @@ hipError_t launch_t(const StencilLaunch& L, const StencilConsts<double>& c, hipS
 
 template <typename T, typename TO, typename TW>
 hipError_t launch_ph(const StencilLaunch& L, const StencilConsts<double>& c, hipStream_t s) {
-  const bool ph = L.wtab != nullptr;
-  if (ph) {
-    return L.strain ? launch_t<T, TO, TW, true, true>(L, c, s)
-                    : launch_t<T, TO, TW, true, false>(L, c, s);
-  }
-  return L.strain ? launch_t<T, TO, TW, false, true>(L, c, s)
-                  : launch_t<T, TO, TW, false, false>(L, c, s);
+  // 0: no field; 1: Bz = 0 (all link phases uniform over a z-plane); 2: general
+  const int ph = L.wtab == nullptr ? 0 : (L.phase_general ? 2 : 1);
+  if (ph == 2)
+    return L.strain ? launch_t<T, TO, TW, 2, true>(L, c, s) : launch_t<T, TO, TW, 2, false>(L, c, s);
+  if (ph == 1)
+    return L.strain ? launch_t<T, TO, TW, 1, true>(L, c, s) : launch_t<T, TO, TW, 1, false>(L, c, s);
+  return L.strain ? launch_t<T, TO, TW, 0, true>(L, c, s) : launch_t<T, TO, TW, 0, false>(L, c, s);
 }
 
 }  // namespace
