@@ -65,6 +65,7 @@ extern "C" {
 #define HKP_FLAG_X0 1           /* use the caller's initial block X0 */
 #define HKP_FLAG_GRAPH 2        /* record outer iterations once in a hipGraph and replay */
 #define HKP_FLAG_NO_FP64_POLISH 4 /* mixed: never switch the filter to FP64 */
+#define HKP_FLAG_NO_LOCK 8      /* filter every vector of the block, converged or not */
 
 /* Grid: nx, ny, nz >= 1 points, spacing h (nm) > 0. */
 typedef struct {
@@ -117,7 +118,9 @@ typedef struct {
 /* Autotuner result for the stencil (filter step) kernel on one shape. */
 typedef struct {
   int32_t tile_y;      /* rows of the x-y tile (the tile is 64 x tile_y) */
-  int32_t zchunk;      /* planes marched per workgroup */
+  int32_t vgroup;      /* vectors of one tile run side by side (1: vector-major) */
+  int32_t dma;         /* 1: halo-tile rows copied global -> LDS directly */
+  int32_t reserved;
   double us_per_step;  /* measured time of one filter step over the block */
   double gbps;         /* algorithmic bytes / time */
 } hkp_tune;

@@ -24,6 +24,7 @@ HKP_PREC_MIXED = 1
 HKP_FLAG_X0 = 1
 HKP_FLAG_GRAPH = 2
 HKP_FLAG_NO_FP64_POLISH = 4
+HKP_FLAG_NO_LOCK = 8
 
 
 class hkp_grid(C.Structure):
@@ -57,8 +58,8 @@ class hkp_stats(C.Structure):
 
 
 class hkp_tune(C.Structure):
-    _fields_ = [("tile_y", C.c_int32), ("zchunk", C.c_int32), ("us_per_step", C.c_double),
-                ("gbps", C.c_double)]
+    _fields_ = [("tile_y", C.c_int32), ("vgroup", C.c_int32), ("dma", C.c_int32),
+                ("reserved", C.c_int32), ("us_per_step", C.c_double), ("gbps", C.c_double)]
 
 
 _P = C.c_void_p

@@ -90,8 +90,11 @@ def workspace_bytes(shape, h, nev, nb=0, degree=0, precision="fp64", batch=1):
 
 def solve(V, h, nev, strain=None, B=(0.0, 0.0, 0.0), nb=0, degree=0, tol=1e-8,
           precision="fp64", max_iter=200, seed=1, X0=None, graph=False, material=None,
-          return_psi=True, workspace=None, polish=True):
-    """Lowest `nev` eigenpairs of H for the potential V (float64 [nx, ny, nz], eV)."""
+          return_psi=True, workspace=None, polish=True, lock=True):
+    """Lowest `nev` eigenpairs of H for the potential V (float64 [nx, ny, nz], eV).
+
+    lock=False filters every vector of the block in every iteration (no soft
+    locking of converged Kramers pairs)."""
     V = _dev(V, torch.float64)
     shape = tuple(V.shape)
     if len(shape) != 3:
@@ -101,6 +104,8 @@ def solve(V, h, nev, strain=None, B=(0.0, 0.0, 0.0), nb=0, degree=0, tol=1e-8,
     flags = (L.HKP_FLAG_GRAPH if graph else 0) | (L.HKP_FLAG_X0 if X0 is not None else 0)
     if not polish:
         flags |= L.HKP_FLAG_NO_FP64_POLISH
+    if not lock:
+        flags |= L.HKP_FLAG_NO_LOCK
     o = _opts(nev, nb, degree, max_iter, tol, precision, flags, seed)
     need = L.lib.hkp_workspace_bytes(C.byref(g), C.byref(o), 1)
     if need == 0:
@@ -133,7 +138,7 @@ def solve(V, h, nev, strain=None, B=(0.0, 0.0, 0.0), nb=0, degree=0, tol=1e-8,
 
 def solve_batch(V, h, nev, strain=None, B=(0.0, 0.0, 0.0), nb=0, degree=0, tol=1e-8,
                 precision="fp64", max_iter=200, seed=1, graph=True, material=None,
-                return_psi=False, workspace=None, polish=True):
+                return_psi=False, workspace=None, polish=True, lock=True):
     """Lowest eigenpairs of `batch` Hamiltonians differing in V ([batch, nx, ny, nz])."""
     V = _dev(V, torch.float64)
     if V.dim() != 4:
@@ -145,6 +150,8 @@ def solve_batch(V, h, nev, strain=None, B=(0.0, 0.0, 0.0), nb=0, degree=0, tol=1
     flags = L.HKP_FLAG_GRAPH if graph else 0
     if not polish:
         flags |= L.HKP_FLAG_NO_FP64_POLISH
+    if not lock:
+        flags |= L.HKP_FLAG_NO_LOCK
     o = _opts(nev, nb, degree, max_iter, tol, precision, flags, seed)
     need = L.lib.hkp_workspace_bytes(C.byref(g), C.byref(o), batch)
     if need == 0:
@@ -234,7 +241,8 @@ def autotune(shape, h, nb, precision="fp64", with_strain=True, with_field=True):
     t = L.hkp_tune()
     L.check(L.lib.hkp_autotune(C.byref(g), nb, prec, int(with_strain), int(with_field), _ptr(ws),
                                C.c_size_t(need), _stream(), C.byref(t)))
-    return dict(tile_y=t.tile_y, zchunk=t.zchunk, us_per_step=t.us_per_step, gbps=t.gbps)
+    return dict(tile_y=t.tile_y, vgroup=t.vgroup, dma=t.dma, us_per_step=t.us_per_step,
+                gbps=t.gbps)
 
 
 class EigvalsFromPotential(torch.autograd.Function):

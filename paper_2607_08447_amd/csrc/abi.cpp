@@ -172,8 +172,7 @@ int solve_common(const hkp_grid* grid, const hkp_material* mat, const hkp_opts* 
   a.max_iter = opts->max_iter;
   a.flags = opts->flags;
   a.seed = opts->seed;
-  a.tile_y = autotuned_tile(*grid, p.nb, p.mixed);
-  a.order = autotuned_order(*grid, p.nb, p.mixed);
+  a.st = autotuned(*grid, p.nb, p.mixed);
   a.graph_chunk = 4;
   return guarded([&]() { return run_solve(a, stats); });
 }
@@ -294,8 +293,7 @@ int hkp_filter_step(const hkp_grid* grid, const hkp_material* mat, const double*
   a.precision = precision;
   a.workspace = workspace;
   a.stream = hip_stream;
-  a.tile_y = autotuned_tile(*grid, nvec, precision == HKP_PREC_MIXED);
-  a.order = autotuned_order(*grid, nvec, precision == HKP_PREC_MIXED);
+  a.st = autotuned(*grid, nvec, precision == HKP_PREC_MIXED);
   return guarded([&]() { return run_filter_step(a); });
 }
 

@@ -1,11 +1,13 @@
 // Autotuner for the stencil (Chebyshev step) kernel: times the tile shapes on
 // the caller's grid and block size with HIP events and caches the fastest per
 // (shape, nb, precision, strain, field) for the life of the process.
+#include <algorithm>
 #include <cstdio>
 #include <cstdlib>
 #include <map>
 #include <mutex>
 #include <tuple>
+#include <vector>
 
 #include "hkp_internal.h"
 #include "solver.h"
@@ -16,25 +18,33 @@ namespace {
 
 using Key = std::tuple<int, int, int, int, int>;   // nx, ny, nz, nb, mixed
 std::mutex g_mu;
-std::map<Key, std::pair<int, int>> g_cache;        // tile_y, order
+std::map<Key, StencilTune> g_cache;
 
 size_t al(size_t x) { return (x + 255) & ~(size_t)255; }
 
-}  // namespace
-
-int autotuned_tile(const hkp_grid& g, int nb, bool mixed) {
-  std::lock_guard<std::mutex> lk(g_mu);
-  auto it = g_cache.find(Key{g.nx, g.ny, g.nz, nb, mixed ? 1 : 0});
-  if (it != g_cache.end()) return it->second.first;
-  // untuned default: tall tiles on wide planes, thin tiles on narrow ones
-  return g.ny >= 32 ? 4 : (g.ny >= 8 ? 2 : 1);
+// HKP_STENCIL="tile_y,vgroup,dma" forces one launch shape (tests of a variant)
+bool forced(StencilTune* t) {
+  const char* e = std::getenv("HKP_STENCIL");
+  if (!e || !e[0]) return false;
+  StencilTune f;
+  if (std::sscanf(e, "%d,%d,%d", &f.tile_y, &f.vgroup, &f.dma) != 3) return false;
+  *t = f;
+  return true;
 }
 
-int autotuned_order(const hkp_grid& g, int nb, bool mixed) {
+}  // namespace
+
+StencilTune autotuned(const hkp_grid& g, int nb, bool mixed) {
+  StencilTune t;
+  if (forced(&t)) return t;
   std::lock_guard<std::mutex> lk(g_mu);
   auto it = g_cache.find(Key{g.nx, g.ny, g.nz, nb, mixed ? 1 : 0});
-  if (it != g_cache.end()) return it->second.second;
-  return 1;
+  if (it != g_cache.end()) return it->second;
+  // untuned default: tall tiles on wide planes, thin tiles on narrow ones;
+  // rows staged global -> LDS directly when tiles are full along x
+  t.tile_y = g.ny >= 32 ? 4 : (g.ny >= 8 ? 2 : 1);
+  t.dma = g.nx % 64 == 0 ? 1 : 0;
+  return t;
 }
 
 int run_autotune(const hkp_grid& g, int nb, bool mixed, bool strain, bool field, void* ws,
@@ -69,13 +79,17 @@ int run_autotune(const hkp_grid& g, int nb, bool mixed, bool strain, bool field,
   const StencilConsts<double> c = make_consts(m, g.h_nm, B);
   hipEvent_t e0, e1;
   if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return HKP_E_HIP;
-  const int cand[] = {1, 2, 4, 8};
-  int best = 4, best_order = 1;
+  StencilTune best;
   double best_us = 1e300;
   const char* dbg = std::getenv("HKP_TUNE_TRACE");
-  for (int order = 0; order < 2; ++order)
-  for (int ty : cand) {
+  std::vector<int> groups;   // 1 (vector-major), 2, 4, nb (tile-major)
+  for (int vg : {1, 2, 4, nb})
+    if (vg <= nb && std::find(groups.begin(), groups.end(), vg) == groups.end()) groups.push_back(vg);
+  for (int dma = 0; dma < 2; ++dma)
+  for (int vg : groups)
+  for (int ty : {1, 2, 4}) {
     if (ty > 1 && ty > 2 * g.ny) continue;
+    if (dma && g.nx % 64 != 0) continue;
     StencilLaunch a{};
     a.nx = g.nx;
     a.ny = g.ny;
@@ -95,7 +109,8 @@ int run_autotune(const hkp_grid& g, int nb, bool mixed, bool strain, bool field,
     a.coef.shift = 0.5;
     a.coef.beta = -1.0;
     a.tile_y = ty;
-    a.order = order;
+    a.vgroup = vg;
+    a.dma = dma;
     a.fp64 = !mixed;
     if (launch_stencil(a, c, s) != hipSuccess) continue;   // warm-up
     const int reps = 5;
@@ -106,21 +121,25 @@ int run_autotune(const hkp_grid& g, int nb, bool mixed, bool strain, bool field,
     float ms = 0;
     (void)hipEventElapsedTime(&ms, e0, e1);
     const double us = 1e3 * ms / reps;
-    if (dbg && dbg[0] == '1') std::fprintf(stderr, "[hkp tune] ty %d order %d: %.1f us\n", ty, order, us);
+    if (dbg && dbg[0] == '1')
+      std::fprintf(stderr, "[hkp tune] ty %d vgroup %d dma %d: %.1f us\n", ty, vg, dma, us);
     if (us < best_us) {
       best_us = us;
-      best = ty;
-      best_order = order;
+      best.tile_y = ty;
+      best.vgroup = vg;
+      best.dma = dma;
     }
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   {
     std::lock_guard<std::mutex> lk(g_mu);
-    g_cache[Key{g.nx, g.ny, g.nz, nb, mixed ? 1 : 0}] = {best, best_order};
+    g_cache[Key{g.nx, g.ny, g.nz, nb, mixed ? 1 : 0}] = best;
   }
-  out->tile_y = best;
-  out->zchunk = g.nz;
+  out->tile_y = best.tile_y;
+  out->vgroup = best.vgroup;
+  out->dma = best.dma;
+  out->reserved = 0;
   out->us_per_step = best_us;
   // algorithmic bytes of one filter step: read X and Y_old, write Y, plus fields
   const double bytes = 3.0 * nb * n6 * esz + (double)N * (mixed ? 28 : 56);

@@ -345,14 +345,16 @@ __global__ void scale_kernel(double* v, long long n, long long bstride, const do
 template <typename TO>
 __global__ void cheb_first_kernel(const double* X, const double* W, long long bstride,
                                   long long count, TO* out, long long out_bstride,
-                                  const double* coef, int coef_stride, const int* active) {
+                                  const double* coef, int coef_stride, const int* active,
+                                  const int* lock, long long n) {
   const int b = blockIdx.y;
   if (active && !active[b]) return;
   const double al = coef[(long long)b * coef_stride], sh = coef[(long long)b * coef_stride + 1];
   const double2* x = reinterpret_cast<const double2*>(X) + (long long)b * bstride;
   const double2* w = reinterpret_cast<const double2*>(W) + (long long)b * bstride;
   TO* o = out + 2 * (long long)b * out_bstride;
-  for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < count;
+  const long long e0 = lock ? (long long)lock[b] * n : 0;   // locked vectors are not filtered
+  for (long long e = e0 + (long long)blockIdx.x * blockDim.x + threadIdx.x; e < count;
        e += (long long)gridDim.x * blockDim.x) {
     const double2 xv = x[e], wv = w[e];
     o[2 * e] = (TO)(al * (wv.x - sh * xv.x));
@@ -476,15 +478,18 @@ hipError_t launch_resid(const BlockDesc& X, const BlockDesc& W, const double* th
 
 hipError_t launch_cheb_first(const BlockDesc& X, const BlockDesc& W, void* out, int out_fp64,
                              long long out_bstride, int batch, const double* coef,
-                             int coef_stride, const int* active, hipStream_t s) {
+                             int coef_stride, const int* active, const int* lock,
+                             hipStream_t s) {
   const long long count = X.n * X.nvec;
   dim3 grid(grid_for(count, 256, 8192 / (batch > 0 ? batch : 1) + 1), (unsigned)batch);
   if (out_fp64)
     cheb_first_kernel<double><<<grid, 256, 0, s>>>(X.ptr, W.ptr, X.bstride, count, (double*)out,
-                                                   out_bstride, coef, coef_stride, active);
+                                                   out_bstride, coef, coef_stride, active, lock,
+                                                   X.n);
   else
     cheb_first_kernel<float><<<grid, 256, 0, s>>>(X.ptr, W.ptr, X.bstride, count, (float*)out,
-                                                  out_bstride, coef, coef_stride, active);
+                                                  out_bstride, coef, coef_stride, active, lock,
+                                                  X.n);
   return hipGetLastError();
 }
 

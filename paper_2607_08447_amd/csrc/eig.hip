@@ -237,7 +237,7 @@ heev_kernel(double* A, int nb, long long mat_stride, double* evals, double* out,
 // control: residual norms -> convergence; Ritz values -> next filter interval
 // ---------------------------------------------------------------------------
 __global__ void control_kernel(Control c, int nb, int nev, int degree, int kmax, double tol,
-                               int mixed, int allow_switch, int iter) {
+                               int mixed, int allow_switch, int allow_lock, int iter) {
   const int b = blockIdx.x;
   if (threadIdx.x != 0) return;
   int* fl = c.flags + 8 * b;
@@ -245,6 +245,7 @@ __global__ void control_kernel(Control c, int nb, int nev, int degree, int kmax,
     c.active[b] = 0;
     c.act32[b] = 0;
     c.act64[b] = 0;
+    c.lock[b] = 0;
     return;
   }
   const double* th = c.theta + (long long)b * nb;
@@ -279,6 +280,13 @@ __global__ void control_kernel(Control c, int nb, int nev, int degree, int kmax,
   c.active[b] = fl[0] ? 0 : 1;
   c.act32[b] = (!fl[0] && mixed && !fl[1]) ? 1 : 0;
   c.act64[b] = (!fl[0] && !(mixed && !fl[1])) ? 1 : 0;
+  // soft locking: the leading run of converged states, whole Kramers pairs,
+  // is left out of the next filter (it stays in the block, so orthonormalisation
+  // and Rayleigh-Ritz still see it, and it is released if its residual grows)
+  int lead = 0;
+  while (allow_lock && lead < nev && sqrt(r2[lead]) <= tol) ++lead;
+  c.lock[b] = fl[0] ? 0 : (lead & ~1);
+  fl[6] = c.lock[b];
   // next filter: damp [a_cut, b_up], scaled to 1 at a0 = lowest Ritz value
   const double bup = bd[0];
   double acut = th[nb - 1];
@@ -300,6 +308,29 @@ __global__ void control_kernel(Control c, int nb, int nev, int degree, int kmax,
     co[4 * k + 2] = -sig * sn;
     sig = sn;
   }
+}
+
+// prefix sums of the vectors each member still has to process: the stencil
+// launches map their live workgroups onto these so that converged members and
+// locked vectors leave no XCD idle
+__global__ void worktable_kernel(Control c, int batch, int nb) {
+  if (blockIdx.x != 0 || threadIdx.x != 0) return;
+  int* t32 = c.work;
+  int* t64 = c.work + (batch + 1);
+  int* tall = c.work + 2 * (batch + 1);
+  int s32 = 0, s64 = 0, sall = 0;
+  for (int b = 0; b < batch; ++b) {
+    t32[b] = s32;
+    t64[b] = s64;
+    tall[b] = sall;
+    const int nf = nb - c.lock[b];
+    s32 += c.act32[b] ? nf : 0;
+    s64 += c.act64[b] ? nf : 0;
+    sall += c.active[b] ? nb : 0;
+  }
+  t32[batch] = s32;
+  t64[batch] = s64;
+  tall[batch] = sall;
 }
 
 // first filter coefficients from the bounds alone (before any Rayleigh-Ritz)
@@ -380,8 +411,16 @@ hipError_t launch_heev(double* A, int nb, int batch, long long mat_stride, doubl
 }
 
 hipError_t launch_control(const Control& c, int batch, int nb, int nev, int degree, int kmax,
-                          double tol, int mixed, int allow_switch, int iter, hipStream_t s) {
-  control_kernel<<<batch, 64, 0, s>>>(c, nb, nev, degree, kmax, tol, mixed, allow_switch, iter);
+                          double tol, int mixed, int allow_switch, int allow_lock, int iter,
+                          hipStream_t s) {
+  control_kernel<<<batch, 64, 0, s>>>(c, nb, nev, degree, kmax, tol, mixed, allow_switch,
+                                      allow_lock, iter);
+  worktable_kernel<<<1, 64, 0, s>>>(c, batch, nb);
+  return hipGetLastError();
+}
+
+hipError_t launch_worktable(const Control& c, int batch, int nb, hipStream_t s) {
+  worktable_kernel<<<1, 64, 0, s>>>(c, batch, nb);
   return hipGetLastError();
 }
 

@@ -73,8 +73,14 @@ struct StencilLaunch {
   int phase_general;     // Bz != 0: y-link phases vary along x
   StepCoef coef;
   const int* active;     // [batch] 0 = skip, or null
+  const int* lock;       // [batch] vectors below this index are skipped, or null
+  const int* work;       // [batch + 1] prefix sums of the vectors to process per member
+                         // (vector lock[b] + i of member b is virtual vector work[b] + i);
+                         // the grid covers nvec * batch vectors and only the first
+                         // work[batch] are live, spread evenly over the XCDs. Or null.
   int tile_y;            // 1, 2, 4, 8
-  int order;             // workgroup order: 0 tile-major, 1 vector-major
+  int vgroup;            // vectors of one tile side by side (1 vector-major, nvec tile-major)
+  int dma;               // 1: rows staged global -> LDS directly (needs nx % 64 == 0)
   int fp64;              // kernel type
 };
 
@@ -129,7 +135,8 @@ hipError_t launch_resid(const BlockDesc& X, const BlockDesc& W, const double* th
 // Y1 = alpha (W - shift X) (first filter step from a known W = H X)
 hipError_t launch_cheb_first(const BlockDesc& X, const BlockDesc& W, void* out, int out_fp64,
                              long long out_bstride, int batch, const double* coef,
-                             int coef_stride, const int* active, hipStream_t s);
+                             int coef_stride, const int* active, const int* lock,
+                             hipStream_t s);
 hipError_t launch_cast(const void* in, int in_fp64, void* out, int out_fp64, long long count,
                        hipStream_t s);
 hipError_t launch_random_block(double* X, long long n, int nvec, int batch, long long bstride,
@@ -161,14 +168,19 @@ struct Control {
   double* r2;        // [batch][nb] squared residuals
   double* coef;      // [batch][kmax*4]
   double* bounds;    // [batch][4]: b_upper, a_cut, a0, last rmax
-  int* flags;        // [batch][8]: done, fp64, stagnation, iters, nconv, switch iter
+  int* flags;        // [batch][8]: done, fp64, stagnation, iters, nconv, switch iter, lock
   int* active;       // [batch] not converged
   int* act32;        // [batch] not converged, FP32 filter
   int* act64;        // [batch] not converged, FP64 filter
+  int* lock;         // [batch] leading vectors left out of the filter (converged pairs)
+  int* work;         // [3][batch + 1] prefix sums of vectors to process per member:
+                     // FP32 filter, FP64 filter (both after the lock), whole block
 };
+// rebuild Control::work from the active masks and lock counts
+hipError_t launch_worktable(const Control& c, int batch, int nb, hipStream_t s);
 hipError_t launch_control(const Control& c, int batch, int nb, int nev, int degree,
-                          int kmax, double tol, int mixed, int allow_switch, int iter,
-                          hipStream_t s);
+                          int kmax, double tol, int mixed, int allow_switch, int allow_lock,
+                          int iter, hipStream_t s);
 hipError_t launch_finish(const double* theta, const double* r2, int nb, int nev, int batch,
                          double* eig, double* resid, hipStream_t s);
 hipError_t launch_check_finite(const double* x, long long count, int* flag, hipStream_t s);

@@ -54,7 +54,7 @@ constexpr int kResParts = 64;
 
 struct Layout {
   size_t D64, D32, w64, v64, w32, v32, X, W, A32, B32, gram, mat1, mat2, theta, lam, r2, rpart,
-      coef, bounds, flags, active, act32, act64, again, status, lal, lnrm, lpart, total;
+      coef, bounds, flags, active, act32, act64, lock, work, again, status, lal, lnrm, lpart, total;
 };
 
 Layout make_layout(const Plan& p) {
@@ -92,6 +92,8 @@ Layout make_layout(const Plan& p) {
   L.active = take(B * 4);
   L.act32 = take(B * 4);
   L.act64 = take(B * 4);
+  L.lock = take(B * 4);
+  L.work = take(3 * (B + 1) * 4);
   L.again = take(B * 4);
   L.status = take(B * 4 + 4);
   L.lal = take((size_t)kLanczosSteps * B * 16);
@@ -155,14 +157,16 @@ struct StencilStats {
   ~StencilStats() {
     for (auto e : ev) (void)hipEventDestroy(e);
   }
+  // nvec_done: vectors the launch processes summed over the active members
+  // (< 0: every vector of every active member)
   void launch(const StencilLaunch& a, const StencilConsts<double>& c, hipStream_t s,
-              long long N, int active_members) {
+              long long N, int active_members, double nvec_done = -1) {
     const double sin = a.fp64 ? 16 : 8;
     const double sold = a.old ? (a.old_fp64 ? 16 : 8) : 0;
     const double sout = a.out_fp64 ? 16 : 8;
-    const double b = (double)active_members *
-                     ((double)N * 6 * a.nvec * (sin + sold + sout) +
-                      (double)N * (a.strain ? 6 : 1) * (a.fp64 ? 8 : 4));
+    if (nvec_done < 0) nvec_done = (double)active_members * a.nvec;
+    const double b = (double)N * 6 * nvec_done * (sin + sold + sout) +
+                     (double)active_members * N * (a.strain ? 6 : 1) * (a.fp64 ? 8 : 4);
     hx_bytes += b;
     if (!timed) {
       HKP_CHECK(launch_stencil(a, c, s));
@@ -207,6 +211,7 @@ struct StencilStats {
 struct Ctx {
   StencilStats* ss = nullptr;
   int active_members = 1;   // host view of unconverged Hamiltonians (byte accounting)
+  double filtered_vectors = -1;   // host view of the vectors the filter processes (-1: all)
   Plan p;
   Layout L;
   char* ws;
@@ -221,10 +226,13 @@ struct Ctx {
   BlockDesc blk(size_t off, int nvec) const {
     return BlockDesc{at<double>(off), p.n6, nvec, bstride()};
   }
+  // work table of the FP32 filter (0), FP64 filter (1) or whole block (2)
+  const int* work(int k) const { return at<int>(L.work) + k * (p.batch + 1); }
   Control control() const {
     return Control{at<double>(L.theta), at<double>(L.r2),     at<double>(L.coef),
                    at<double>(L.bounds), at<int>(L.flags),    at<int>(L.active),
-                   at<int>(L.act32),     at<int>(L.act64)};
+                   at<int>(L.act32),     at<int>(L.act64),    at<int>(L.lock),
+                   at<int>(L.work)};
   }
 };
 
@@ -243,8 +251,9 @@ StencilLaunch base_launch(const Ctx& c, bool fp64, int nvec) {
     a.vtab = fp64 ? (const void*)c.at<double>(c.L.v64) : (const void*)c.at<float>(c.L.v32);
     a.phase_general = c.field_z;
   }
-  a.tile_y = c.p.tile_y;
-  a.order = c.p.order;
+  a.tile_y = c.p.st.tile_y;
+  a.vgroup = c.p.st.vgroup;
+  a.dma = c.p.st.dma;
   a.fp64 = fp64;
   a.coef.coef = nullptr;
   a.coef.alpha = 1.0;
@@ -262,6 +271,7 @@ void apply_block(const Ctx& c, size_t x_off, size_t w_off, const int* active) {
   a.out_fp64 = 1;
   a.out_bstride = c.bstride();
   a.active = active;
+  a.work = c.work(2);
   c.ss->launch(a, c.consts, c.s, c.p.N, c.active_members);
 }
 
@@ -270,7 +280,7 @@ void filter64(const Ctx& c, const int* active, int m) {
   const int kstride = kKmax * 4;
   HKP_CHECK(launch_cheb_first(c.blk(c.L.X, c.p.nb), c.blk(c.L.W, c.p.nb), c.at<double>(c.L.W),
                               1, c.bstride(), c.p.batch, c.at<double>(c.L.coef), kstride, active,
-                              c.s));
+                              c.at<int>(c.L.lock), c.s));
   size_t cur = c.L.W, oth = c.L.X;
   for (int k = 1; k < m; ++k) {
     StencilLaunch a = base_launch(c, true, c.p.nb);
@@ -285,7 +295,9 @@ void filter64(const Ctx& c, const int* active, int m) {
     a.coef.coef = c.at<double>(c.L.coef) + 4 * k;
     a.coef.stride = kstride;
     a.active = active;
-    c.ss->launch(a, c.consts, c.s, c.p.N, c.active_members);
+    a.lock = c.at<int>(c.L.lock);
+    a.work = c.work(1);
+    c.ss->launch(a, c.consts, c.s, c.p.N, c.active_members, c.filtered_vectors);
     std::swap(cur, oth);
   }
 }
@@ -297,7 +309,8 @@ void filter32(const Ctx& c, const int* active, int m) {
   float* A = c.at<float>(c.L.A32);
   float* Bf = c.at<float>(c.L.B32);
   HKP_CHECK(launch_cheb_first(c.blk(c.L.X, c.p.nb), c.blk(c.L.W, c.p.nb), A, 0, c.bstride(),
-                              c.p.batch, c.at<double>(c.L.coef), kstride, active, c.s));
+                              c.p.batch, c.at<double>(c.L.coef), kstride, active,
+                              c.at<int>(c.L.lock), c.s));
   // step k: in = Y_k (FP32), old = Y_{k-1} (X in FP64 for k = 1), out = Y_{k+1}
   const void* in = A;
   const void* old = c.at<double>(c.L.X);
@@ -318,7 +331,9 @@ void filter32(const Ctx& c, const int* active, int m) {
     a.coef.coef = c.at<double>(c.L.coef) + 4 * k;
     a.coef.stride = kstride;
     a.active = active;
-    c.ss->launch(a, c.consts, c.s, c.p.N, c.active_members);
+    a.lock = c.at<int>(c.L.lock);
+    a.work = c.work(0);
+    c.ss->launch(a, c.consts, c.s, c.p.N, c.active_members, c.filtered_vectors);
     old = in;
     old64 = 0;
     in = out;
@@ -465,7 +480,6 @@ Plan make_plan(const hkp_grid& g, const hkp_opts& o, int batch) {
   if (m > kKmax) m = kKmax;
   p.degree = m;
   p.mixed = o.precision == HKP_PREC_MIXED;
-  p.tile_y = 4;
   return p;
 }
 
@@ -493,8 +507,7 @@ int run_solve(const SolveArgs& A, hkp_stats* stats) {
   c.field_z = A.B[2] != 0.0;
   c.strain = A.strain != nullptr;
   c.consts = make_consts(A.mat, c.p.h, A.B);
-  if (A.tile_y > 0) c.p.tile_y = A.tile_y;
-  c.p.order = A.order;
+  c.p.st = A.st;
   const Plan& p = c.p;
   const bool eager = !(A.flags & HKP_FLAG_GRAPH);
   const char* tr = std::getenv("HKP_TRACE");
@@ -528,6 +541,8 @@ int run_solve(const SolveArgs& A, hkp_stats* stats) {
   HKP_CHECK(launch_fill_int(c.at<int>(c.L.active), p.batch, 1, c.s));
   HKP_CHECK(launch_fill_int(c.at<int>(c.L.act32), p.batch, p.mixed ? 1 : 0, c.s));
   HKP_CHECK(launch_fill_int(c.at<int>(c.L.act64), p.batch, p.mixed ? 0 : 1, c.s));
+  HKP_CHECK(launch_fill_int(c.at<int>(c.L.lock), p.batch, 0, c.s));
+  HKP_CHECK(launch_worktable(c.control(), p.batch, p.nb, c.s));
 
   // ---- spectral bound
   std::vector<double> bup;
@@ -553,7 +568,8 @@ int run_solve(const SolveArgs& A, hkp_stats* stats) {
   rayleigh_ritz(c, act);
   residuals(c, act);
   HKP_CHECK(launch_control(c.control(), p.batch, p.nb, p.nev, kKmax, kKmax, A.tol, p.mixed,
-                           !(A.flags & HKP_FLAG_NO_FP64_POLISH), 0, c.s));
+                           !(A.flags & HKP_FLAG_NO_FP64_POLISH), !(A.flags & HKP_FLAG_NO_LOCK), 0,
+                           c.s));
   t_setup.stop(c.s);
   t_setup.collect();
 
@@ -579,11 +595,14 @@ int run_solve(const SolveArgs& A, hkp_stats* stats) {
   int m_cur = degree_at(1);
   auto count_work = [&]() {
     c.active_members = 0;
-    for (int b = 0; b < p.batch; ++b) c.active_members += hflags[8 * b] ? 0 : 1;
+    c.filtered_vectors = 0;
     for (int b = 0; b < p.batch; ++b) {
       if (hflags[8 * b]) continue;
+      ++c.active_members;
+      const int nf = p.nb - hflags[8 * b + 6];   // locked vectors are not filtered
+      c.filtered_vectors += nf;
       const bool f32 = p.mixed && !hflags[8 * b + 1];
-      (f32 ? n_hx32 : n_hx64) += (long long)p.nb * m_cur;
+      (f32 ? n_hx32 : n_hx64) += (long long)nf * m_cur;
       n_hx64 += p.nb;
     }
   };
@@ -608,7 +627,8 @@ int run_solve(const SolveArgs& A, hkp_stats* stats) {
     t_res.start(c.s);
     residuals(c, act);
     HKP_CHECK(launch_control(c.control(), p.batch, p.nb, p.nev, kKmax, kKmax, A.tol,
-                             p.mixed, !(A.flags & HKP_FLAG_NO_FP64_POLISH), it, c.s));
+                             p.mixed, !(A.flags & HKP_FLAG_NO_FP64_POLISH),
+                             !(A.flags & HKP_FLAG_NO_LOCK), it, c.s));
     t_res.stop(c.s);
   };
 
@@ -645,6 +665,11 @@ int run_solve(const SolveArgs& A, hkp_stats* stats) {
     const int chunk = std::max(1, std::min(A.graph_chunk > 0 ? A.graph_chunk : 4, A.max_iter));
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
+    // byte accounting of a replay: the recorded chunk with every member active
+    // and no vector locked (an upper estimate; the kernels skip on the device)
+    const double bytes_before = sst.hx_bytes;
+    c.active_members = p.batch;
+    c.filtered_vectors = -1;
     HKP_CHECK(hipStreamBeginCapture(c.s, hipStreamCaptureModeThreadLocal));
     try {
       for (int k = 0; k < chunk; ++k) iteration(-1, false, false);
@@ -655,9 +680,12 @@ int run_solve(const SolveArgs& A, hkp_stats* stats) {
       throw;
     }
     HKP_CHECK(hipStreamEndCapture(c.s, &graph));
+    const double chunk_bytes = sst.hx_bytes - bytes_before;
+    sst.hx_bytes = bytes_before;
     HKP_CHECK(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
     while (iters < A.max_iter && !all_done()) {
       for (int k = 0; k < chunk; ++k) count_work();   // upper estimate per replay
+      sst.hx_bytes += chunk_bytes;
       HKP_CHECK(hipGraphLaunch(exec, c.s));
       iters += chunk;
       read_flags();
@@ -775,8 +803,9 @@ int run_filter_step(const FilterArgs& A) {
   a.coef.alpha = A.alpha;
   a.coef.shift = A.shift;
   a.coef.beta = has_old ? A.beta : 0.0;
-  a.tile_y = A.tile_y > 0 ? A.tile_y : 4;
-  a.order = A.order;
+  a.tile_y = A.st.tile_y;
+  a.vgroup = A.st.vgroup;
+  a.dma = A.st.dma;
   a.fp64 = fp64;
   HKP_CHECK(launch_stencil(a, make_consts(A.mat, g.h_nm, A.B), s));
   HKP_CHECK(launch_internal_to_abi(g.nx, g.ny, g.nz, g.h_nm, A.B, A.nvec, 1, Yi, 0, A.Y, 0, s));

@@ -7,6 +7,14 @@
 
 namespace hkp {
 
+// launch shape of the stencil kernel: rows per tile, vectors of one tile run
+// side by side (1: vector-major order), rows staged global -> LDS directly
+struct StencilTune {
+  int tile_y = 4;
+  int vgroup = 1;
+  int dma = 0;
+};
+
 struct Plan {
   int nx, ny, nz;
   double h;
@@ -14,8 +22,7 @@ struct Plan {
   int batch, nev, nb, degree;   // degree: fixed value or the ramp's maximum
   bool degree_fixed;
   bool mixed;
-  int tile_y;
-  int order;
+  StencilTune st;
 };
 
 struct SolveArgs {
@@ -34,8 +41,7 @@ struct SolveArgs {
   int max_iter;
   int flags;
   unsigned long long seed;
-  int tile_y;       // 0: plan default
-  int order;        // stencil workgroup order
+  StencilTune st;
   int graph_chunk;  // iterations per recorded graph
 };
 
@@ -53,8 +59,7 @@ struct FilterArgs {
   int precision;
   void* workspace;
   void* stream;
-  int tile_y;
-  int order;
+  StencilTune st;
 };
 
 int default_nb(int nev, long long n6);
@@ -64,8 +69,7 @@ int run_solve(const SolveArgs& a, hkp_stats* stats);
 size_t apply_bytes(const hkp_grid& g, int nvec);
 int run_filter_step(const FilterArgs& a);
 int guarded(const std::function<int()>& f);
-int autotuned_tile(const hkp_grid& g, int nb, bool mixed);
-int autotuned_order(const hkp_grid& g, int nb, bool mixed);
+StencilTune autotuned(const hkp_grid& g, int nb, bool mixed);
 int run_autotune(const hkp_grid& g, int nb, bool mixed, bool strain, bool field, void* ws,
                  size_t ws_bytes, void* stream, hkp_tune* out);
 

@@ -118,46 +118,87 @@ struct KArgs {
   int coef_stride;
   double alpha, shift, beta;
   const int* active;
+  const int* lock;
+  const int* work;
+  int batch;
   int nx, ny, nz, nvec;
   int tiles_x, tiles_y;
-  int order;
+  int vgroup;   // vectors of one tile run side by side (1: vector-major)
   StencilConsts<T> k;
 };
+
+// 16 bytes per lane, global -> LDS without registers: lane t's bytes land at
+// lds + 16 t (lds is wave-uniform).  The builtin exists only for the device
+// pass; the host pass sees an empty body so the kernel's host stub is emitted.
+__device__ __forceinline__ void dma16(const void* g, void* lds) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  __builtin_amdgcn_global_load_lds(g, (__attribute__((address_space(3))) void*)lds, 16, 0, 0);
+#endif
+}
 
 template <int V>
 struct IC {
   static constexpr int value = V;
 };
 
-template <typename T, typename TO, typename TW, int PH, bool STR, int TY>
+// DMA = true (tiles full along x): the 64 interior elements of every halo-tile
+// row go global -> LDS directly (global_load_lds, no registers), issued one
+// plane ahead and waited for at the end of the step; the two x-halo columns
+// use ordinary loads.
+template <typename T, typename TO, typename TW, int PH, bool STR, int TY, bool DMA>
 __global__ void __launch_bounds__(128 * TY)
 stencil_kernel(KArgs<T> a) {
-  constexpr int W = 66;               // 64 + halo
+  // LDS row: [pad] left halo, 64 interior, right halo [pad]; with FP32 DMA the
+  // interior starts on a 16-byte boundary (column 2 of a 68-wide row)
+  constexpr int C0 = (DMA && sizeof(T) == 4) ? 2 : 1;   // column of x = tx0
+  constexpr int W = (DMA && sizeof(T) == 4) ? 68 : 66;
   constexpr int ROWS = TY + 2;
   constexpr int SLOTS = W * ROWS;
   constexpr int PLANE = SLOTS;        // elements per (buffer, component) plane
   constexpr int NT = 128 * TY;        // (x, y, spin) threads
   constexpr int NS = (SLOTS + NT - 1) / NT;
-  __shared__ cx<T> ldsb[2 * 6 * PLANE];   // [buffer][component][row][col], double-buffered
+  // double-buffered plane: [component][row][col] each (two distinct arrays, so the
+  // compiler can tell the buffer being read from the one being filled)
+  __shared__ cx<T> lds0[6 * PLANE];
+  __shared__ cx<T> lds1[6 * PLANE];
+  auto bufp = [&](auto BUF) -> cx<T>* {
+    if constexpr (decltype(BUF)::value == 0) return lds0; else return lds1;
+  };
 
-  const int logical = xcd_remap(blockIdx.x, gridDim.x);
   const int ntiles = a.tiles_x * a.tiles_y;
-  int vec, tile, b;
-  if (a.order == 0) {
-    // tile-major: the vectors of one tile run together (share on-site fields in L2)
-    vec = logical % a.nvec;
-    const int rest = logical / a.nvec;
-    tile = rest % ntiles;
-    b = rest / ntiles;
+  // Workgroup order: groups of vgroup vectors; inside a group the vectors of
+  // one tile are adjacent (they share the tile's on-site fields in L2) and the
+  // tiles follow each other (neighbouring tiles march z side by side on one XCD,
+  // so the halo rows they share hit in L2).  vgroup = 1 is vector-major order,
+  // vgroup = nvec tile-major order.  With a work table the order runs over the
+  // live (virtual) vectors of all members and the rest of the grid exits.
+  int b, vec, tile;
+  if (a.work) {
+    const int nv = a.work[a.batch];
+    const int nlive = nv * ntiles;
+    if ((int)blockIdx.x >= nlive) return;
+    const int logical = xcd_remap(blockIdx.x, nlive);
+    const int g = logical / (a.vgroup * ntiles);
+    const int within = logical - g * a.vgroup * ntiles;
+    const int gsize = min(a.vgroup, nv - g * a.vgroup);
+    tile = within / gsize;
+    const int u = g * a.vgroup + (within - tile * gsize);
+    b = 0;
+    while (a.work[b + 1] <= u) ++b;
+    vec = (a.lock ? a.lock[b] : 0) + (u - a.work[b]);
   } else {
-    // vector-major: all tiles of one vector run together on one XCD and march z
-    // in step, so the halo rows a tile shares with its neighbours hit in L2
-    tile = logical % ntiles;
-    const int rest = logical / ntiles;
-    vec = rest % a.nvec;
-    b = rest / a.nvec;
+    const int logical = xcd_remap(blockIdx.x, gridDim.x);
+    const int per_b = ntiles * a.nvec;
+    b = logical / per_b;
+    const int r = logical - b * per_b;
+    const int g = r / (a.vgroup * ntiles);
+    const int within = r - g * a.vgroup * ntiles;
+    const int gsize = min(a.vgroup, a.nvec - g * a.vgroup);
+    tile = within / gsize;
+    vec = g * a.vgroup + (within - tile * gsize);
+    if (a.active && !a.active[b]) return;
+    if (a.lock && vec < a.lock[b]) return;   // converged vectors are not filtered
   }
-  if (a.active && !a.active[b]) return;
   const int tx0 = (tile % a.tiles_x) * 64;
   const int ty0 = (tile / a.tiles_x) * TY;
 
@@ -213,7 +254,7 @@ stencil_kernel(KArgs<T> a) {
     const int slot = tid + s * NT;
     sin_[s] = slot < SLOTS;
     const int row = slot / W, colx = slot % W;
-    const int x = tx0 + colx - 1, y = ty0 + row - 1;
+    const int x = tx0 + colx - C0, y = ty0 + row - 1;
     sval[s] = sin_[s] && x >= 0 && x < nx && y >= 0 && y < ny;
     soff[s] = sval[s] ? (unsigned)(y * nx + x) : 0u;
     sidx[s] = sin_[s] ? slot : 0;
@@ -222,7 +263,7 @@ stencil_kernel(KArgs<T> a) {
 
   const unsigned col = mine ? (unsigned)(gy * nx + gx) : 0u;
   const int gxc = gx < nx ? gx : nx - 1;
-  const int lb = (ly + 1) * W + (lx + 1);   // this thread's centre in an LDS plane
+  const int lb = (ly + 1) * W + (lx + C0);   // this thread's centre in an LDS plane
 
   cx<T> acc0[3], acc1[3], oldv[3];
 #pragma unroll
@@ -240,7 +281,7 @@ stencil_kernel(KArgs<T> a) {
     }
   };
   auto commit = [&](cx<T> (&v)[NS][6], auto BUF) {
-    constexpr int B0 = decltype(BUF)::value * 6 * PLANE;
+    cx<T>* dst = bufp(BUF);
 #pragma unroll
     for (int s = 0; s < NS; ++s) {
       if (NS * NT > SLOTS && !sin_[s]) continue;
@@ -248,9 +289,43 @@ stencil_kernel(KArgs<T> a) {
       for (int c = 0; c < 6; ++c) {
         cx<T> x = v[s][c];
         if (wmask[s] && !sval[s]) x = mk<T>(0, 0);
-        ldsb[B0 + c * PLANE + sidx[s]] = x;
+        dst[c * PLANE + sidx[s]] = x;
       }
     }
+  };
+
+  // ---- DMA staging: row loads spread over the workgroup's waves
+  constexpr int NW = 2 * TY;
+  const int wave = __builtin_amdgcn_readfirstlane(ly + TY * sp);
+  auto dma_plane = [&](int z, auto BUF) {
+    cx<T>* dst = bufp(BUF);
+    const unsigned zo = (unsigned)z * nxy;
+    for (int j = wave; j < 6 * ROWS; j += NW) {
+      const int c = j / ROWS, r = j % ROWS;
+      const int y = ty0 + r - 1;
+      if (y < 0 || y >= ny) continue;
+      const T* src = in + 2 * (size_t)((unsigned)c * N + zo + (unsigned)(y * nx + tx0)) +
+                     (sizeof(T) == 8 ? 2 : 4) * lx;
+      cx<T>* drow = dst + c * PLANE + r * W + C0;
+      if (sizeof(T) == 8 || lx < 32)
+        dma16(src, drow);
+    }
+  };
+  // x-halo columns: element e of 12 ROWS per plane (side, component, row)
+  const int he = tid;
+  const bool hown = he < 12 * ROWS;
+  const int hside = he & 1, hc = (he >> 1) % 6, hr = (he >> 1) / 6;
+  const int hx = hside ? tx0 + 64 : tx0 - 1, hy = ty0 + hr - 1;
+  const bool hval = hown && hx >= 0 && hx < nx && hy >= 0 && hy < ny;
+  const unsigned hoff = hval ? (unsigned)(hc * N + hy * nx + hx) : 0u;
+  const int hidx = hc * PLANE + hr * W + (hside ? C0 + 64 : C0 - 1);
+  auto halo_load = [&](int z) -> cx<T> {
+    cx<T> v = mk<T>(0, 0);
+    if (hval) v = ld(in + 2 * (size_t)(hoff + (unsigned)z * nxy));
+    return v;
+  };
+  auto halo_commit = [&](cx<T> v, auto BUF) {
+    if (hown) bufp(BUF)[hidx] = v;
   };
 
   auto load_old = [&](int z) {
@@ -281,14 +356,35 @@ stencil_kernel(KArgs<T> a) {
     // LDS after it (latency hidden by this wave's own work); FP64 writes them
     // at once (its register budget is already exhausted by the arithmetic)
     constexpr bool late = sizeof(T) == 4;
-    cx<T> nxt[NS][6];
+    cx<T> nxt[DMA ? 1 : NS][6];
+    cx<T> hv = mk<T>(0, 0);
     const bool more = z + 1 < nz;
-    if (more) {
-      fetch(z + 1, nxt);
-      if constexpr (!late) commit(nxt, IC<1 - cur>{});
+    if constexpr (!DMA) {
+      if (more) {
+        fetch(z + 1, nxt);
+        if constexpr (!late) commit(nxt, IC<1 - cur>{});
+      }
+    } else {
+      if (more) hv = halo_load(z + 1);
     }
     if (z >= 1) load_old(z - 1);
-    const cx<T>* L = ldsb + cur * 6 * PLANE + lb;
+    // on-site fields of this plane (loaded before the next plane's DMA is issued)
+    const unsigned p = (unsigned)z * nxy + col;
+    T d00, d11, d22, d12 = 0, d02 = 0, d01 = 0;
+    if constexpr (STR) {
+      d00 = D[p];
+      d11 = D[N + p];
+      d22 = D[2 * N + p];
+      d12 = D[3 * N + p];
+      d02 = D[4 * N + p];
+      d01 = D[5 * N + p];
+    } else {
+      d00 = d11 = d22 = D[p];
+    }
+    if constexpr (DMA) {
+      if (more) dma_plane(z + 1, IC<1 - cur>{});
+    }
+    const cx<T>* L = bufp(IC<cur>{}) + lb;
     auto at = [&](int c, int dy, int dx) { return L[c * PLANE + dy * W + dx]; };
 
     // ---- phases (GPU gauge): x-links per plane, y-links per (plane, column);
@@ -398,18 +494,6 @@ stencil_kernel(KArgs<T> a) {
       }
 
       // ---- on-site: orbital block (V + strain), constants, SO/Zeeman
-      const unsigned p = (unsigned)z * nxy + col;
-      T d00, d11, d22, d12 = 0, d02 = 0, d01 = 0;
-      if constexpr (STR) {
-        d00 = D[p];
-        d11 = D[N + p];
-        d22 = D[2 * N + p];
-        d12 = D[3 * N + p];
-        d02 = D[4 * N + p];
-        d01 = D[5 * N + p];
-      } else {
-        d00 = d11 = d22 = D[p];
-      }
       const T dg = dgs - shift;
       cx<T> r0v = scl(d00 + dg, oX), r1v = scl(d11 + dg, oY), r2v = scl(d22 + dg, oZ);
       if constexpr (STR) {
@@ -446,7 +530,9 @@ stencil_kernel(KArgs<T> a) {
     }
 
     if (z >= 1) finalize(z - 1);
-    if constexpr (late) {
+    if constexpr (DMA) {
+      if (more) halo_commit(hv, IC<1 - cur>{});
+    } else if constexpr (late) {
       if (more) commit(nxt, IC<1 - cur>{});
     }
 #pragma unroll
@@ -457,7 +543,16 @@ stencil_kernel(KArgs<T> a) {
     __syncthreads();
   };
 
-  {
+  if constexpr (DMA) {
+    // rows outside the grid are never loaded: zero both buffers once
+    for (int i = tid; i < 6 * PLANE; i += NT) {
+      lds0[i] = mk<T>(0, 0);
+      lds1[i] = mk<T>(0, 0);
+    }
+    __syncthreads();
+    halo_commit(halo_load(0), IC<0>{});
+    dma_plane(0, IC<0>{});
+  } else {
     cx<T> first[NS][6];
     fetch(0, first);
     commit(first, IC<0>{});
@@ -490,11 +585,14 @@ hipError_t launch_t(const StencilLaunch& L, const StencilConsts<double>& c, hipS
   a.shift = L.coef.shift;
   a.beta = L.coef.beta;
   a.active = L.active;
+  a.lock = L.lock;
+  a.work = L.work;
+  a.batch = L.batch;
   a.nx = L.nx;
   a.ny = L.ny;
   a.nz = L.nz;
   a.nvec = L.nvec;
-  a.order = L.order;
+  a.vgroup = L.vgroup < 1 ? 1 : (L.vgroup > L.nvec ? L.nvec : L.vgroup);
   a.k = cast_consts<T>(c);
   const int ty = L.tile_y;
   a.tiles_x = (L.nx + 63) / 64;
@@ -503,11 +601,20 @@ hipError_t launch_t(const StencilLaunch& L, const StencilConsts<double>& c, hipS
   if (nwg <= 0) return hipSuccess;
   if (nwg > 0x7fffffffLL) return hipErrorInvalidValue;
   dim3 grid((unsigned)nwg);
+  if (L.dma && L.nx % 64 == 0) {
+    switch (ty) {
+      case 1: stencil_kernel<T, TO, TW, PH, STR, 1, true><<<grid, dim3(64, 1, 2), 0, s>>>(a); break;
+      case 2: stencil_kernel<T, TO, TW, PH, STR, 2, true><<<grid, dim3(64, 2, 2), 0, s>>>(a); break;
+      case 4: stencil_kernel<T, TO, TW, PH, STR, 4, true><<<grid, dim3(64, 4, 2), 0, s>>>(a); break;
+      default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+  }
   switch (ty) {
-    case 1: stencil_kernel<T, TO, TW, PH, STR, 1><<<grid, dim3(64, 1, 2), 0, s>>>(a); break;
-    case 2: stencil_kernel<T, TO, TW, PH, STR, 2><<<grid, dim3(64, 2, 2), 0, s>>>(a); break;
-    case 4: stencil_kernel<T, TO, TW, PH, STR, 4><<<grid, dim3(64, 4, 2), 0, s>>>(a); break;
-    case 8: stencil_kernel<T, TO, TW, PH, STR, 8><<<grid, dim3(64, 8, 2), 0, s>>>(a); break;
+    case 1: stencil_kernel<T, TO, TW, PH, STR, 1, false><<<grid, dim3(64, 1, 2), 0, s>>>(a); break;
+    case 2: stencil_kernel<T, TO, TW, PH, STR, 2, false><<<grid, dim3(64, 2, 2), 0, s>>>(a); break;
+    case 4: stencil_kernel<T, TO, TW, PH, STR, 4, false><<<grid, dim3(64, 4, 2), 0, s>>>(a); break;
+    case 8: stencil_kernel<T, TO, TW, PH, STR, 8, false><<<grid, dim3(64, 8, 2), 0, s>>>(a); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();

@@ -80,3 +80,25 @@ def test_mixed_precision_within_1ueV():
     E = res.E.cpu().numpy()
     assert np.abs(E - E_ref).max() <= 1e-6
     assert res.stats["n_hx_fp32"] > 0
+
+
+@pytest.mark.parametrize("precision,tol,tol_E", [("fp64", 1e-9, 1e-8), ("mixed", 1e-6, 1e-6)])
+def test_soft_locking_same_result_less_filtering(precision, tol, tol_E):
+    """Leaving converged Kramers pairs out of the filter gives the oracle's
+    eigenpairs (to the same bar) with fewer filtered vector-steps."""
+    w = workload("dqd_small")
+    nev = 12
+    H = hamiltonian_ls(Grid(*w.shape, w.h), SI_MATERIAL, w.V, w.strain.reshape(-1, 6), w.B)
+    E_ref, _ = lowest_arpack(H, nev, tol=1e-13)
+    # a low fixed degree: many outer iterations, the lowest pairs converge first
+    on = _gpu_solve(w, nev=nev, nb=24, tol=tol, precision=precision, degree=10)
+    off = _gpu_solve(w, nev=nev, nb=24, tol=tol, precision=precision, degree=10, lock=False)
+    assert on.status == 0 and off.status == 0
+    for res in (on, off):
+        assert np.abs(res.E.cpu().numpy() - E_ref).max() <= tol_E
+    if precision == "fp64":
+        _check_pairs(w, on, E_ref, tol_E, tol)
+    work = [r.stats["n_hx_fp64"] + r.stats["n_hx_fp32"] for r in (on, off)]
+    print(f"filtered vector-steps with locking {work[0]}, without {work[1]}; "
+          f"iterations {on.stats['iters']} / {off.stats['iters']}", flush=True)
+    assert work[0] < work[1]
