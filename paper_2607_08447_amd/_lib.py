@@ -97,6 +97,9 @@ def load(path=LIB_PATH):
         raise ImportError(
             f"{path} is missing: build it with `python -m paper_2607_08447_amd.build` "
             "(there is no CPU fallback)")
+    # torch first: the library then binds to the HIP runtime torch has loaded
+    # (one HIP/HSA runtime per process; a second copy would see no device)
+    import torch  # noqa: F401
     lib = C.CDLL(path)
     for name, (res, args) in SIGNATURES.items():
         fn = getattr(lib, name)
