@@ -13,7 +13,16 @@ value  = algorithmic H.X bytes of all stencil launches in the timed solves /
 roofline = the FP32 filter-step stencil (the dominant kernel): its algorithmic
          bytes per launch over its event-timed average launch duration.
 
-Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu]
+Also reported (same JSON line): the device copy bandwidth; the 64-Hamiltonian
+barrier sweep (192 x 40 x 40 each) as seconds per Hamiltonian, batched mixed
+precision in one hipGraph vs a loop of FP64 solves; the Hellmann-Feynman
+backward of the 192 x 40 x 40 adjoint workload (time, error against central
+finite differences).
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-extra]
+       python bench.py --traffic-from FETCH_CSV WRITE_CSV   (writes the HBM traffic
+           summary of the FP32 stencil from two rocprofv3 --pmc runs of
+           `bench.py --copy-calibration --no-cpu --no-extra --steps 1 --warmup 0`)
 """
 
 import argparse
@@ -37,17 +46,157 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
+TRAFFIC_JSON = os.path.join(ROOT, "profiles", "stencil_fp32_dqd_256x48x48_traffic.json")
+STENCIL_SRC = os.path.join(ROOT, "paper_2607_08447_amd", "csrc", "stencil.hip")
+
+
+def _src_hash():
+    with open(STENCIL_SRC, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()
+
+
 def _traffic_for(kernel_src_hash):
     """HBM bytes per launch of the dominant kernel from the committed rocprofv3
     counter summary, if it was taken on the current kernel source."""
-    path = os.path.join(ROOT, "profiles", "stencil_fp32_dqd_256x48x48_traffic.json")
-    if not os.path.exists(path):
+    if not os.path.exists(TRAFFIC_JSON):
         return None
-    with open(path) as f:
+    with open(TRAFFIC_JSON) as f:
         d = json.load(f)
     if d.get("stencil_src_sha256") != kernel_src_hash:
         return None
     return d.get("hbm_bytes_per_launch")
+
+
+def traffic_from(fetch_csv, write_csv):
+    """HBM bytes per launch of the FP32 filter-step stencil from rocprofv3
+    FETCH_SIZE and WRITE_SIZE (KiB per dispatch) collection files.  Each
+    counter is scaled by what it reads for the 1 GiB device copy the profiled
+    run makes first (1 GiB read + 1 GiB written)."""
+    import csv
+
+    def per_kernel(path, counter):
+        copy, sten = [], []
+        with open(path) as f:
+            for r in csv.DictReader(f):
+                if r["Counter_Name"] != counter:
+                    continue
+                v = float(r["Counter_Value"]) * 1024.0
+                name = r["Kernel_Name"]
+                if "copyBuffer" in name and not copy:
+                    copy.append(v)
+                elif "stencil_kernel<float" in name:
+                    sten.append(v)
+        if not copy or not sten:
+            raise SystemExit(f"{path}: no copy calibration or no FP32 stencil dispatches")
+        return copy[0], sten
+
+    cf, sf = per_kernel(fetch_csv, "FETCH_SIZE")
+    cw, sw = per_kernel(write_csv, "WRITE_SIZE")
+    if len(sf) != len(sw):
+        raise SystemExit("FETCH and WRITE runs saw different dispatch counts")
+    gib = float(1 << 30)
+    kf, kw = gib / cf, gib / cw
+    per_launch = [kf * a + kw * b for a, b in zip(sf, sw)]
+    d = {
+        "kernel": "stencil_kernel<float, ...> (FP32 Chebyshev filter step), dqd_256x48x48, nb 48",
+        "stencil_src_sha256": _src_hash(),
+        "dispatches": len(per_launch),
+        "hbm_bytes_per_launch": sum(per_launch) / len(per_launch),
+        "fetch_bytes_per_launch": kf * sum(sf) / len(sf),
+        "write_bytes_per_launch": kw * sum(sw) / len(sw),
+        "copy_calibration": {"fetch_factor": kf, "write_factor": kw,
+                             "note": "1 GiB device copy: counter bytes x factor = true bytes"},
+        "made_by": ["rocprofv3 --pmc FETCH_SIZE -- python3 bench.py --copy-calibration --no-cpu "
+                    "--no-extra --steps 1 --warmup 0",
+                    "rocprofv3 --pmc WRITE_SIZE -- (same)",
+                    "python bench.py --traffic-from <fetch csv> <write csv>"],
+    }
+    with open(TRAFFIC_JSON, "w") as f:
+        json.dump(d, f, indent=1)
+    print(json.dumps(d, indent=1))
+
+
+def copy_bandwidth(torch, nbytes=2 << 30, reps=5):
+    """Device-to-device copy (read + write) rate of a 2 GiB buffer, GB/s."""
+    src = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    e1.record()
+    e1.synchronize()
+    dt = e0.elapsed_time(e1) * 1e-3 / reps
+    del src, dst
+    return 2.0 * nbytes / dt / 1e9
+
+
+def sweep_measure(torch, hkp, workload):
+    """Barrier sweep: 64 Hamiltonians batched (mixed, one hipGraph) vs a loop
+    of FP64 solves over 8 of them (evenly spaced), both to residual 1e-5 eV."""
+    w = workload("sweep64_dqd_192x40x40")
+    V = torch.from_numpy(w.V).cuda()
+    S = torch.from_numpy(w.strain).cuda()
+    hkp.autotune(w.shape, w.h, 24, "mixed")
+    hkp.autotune(w.shape, w.h, 24, "fp64")
+    kw = dict(strain=S, B=w.B, nb=24, tol=1e-5)
+    hkp.solve_batch(V[:2], w.h, w.nev, precision="mixed", graph=True, **kw)   # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    rb = hkp.solve_batch(V, w.h, w.nev, precision="mixed", graph=True, **kw)
+    torch.cuda.synchronize()
+    t_batch = time.perf_counter() - t0
+    idx = list(range(0, 64, 9))
+    t0 = time.perf_counter()
+    errs = []
+    for i in idx:
+        r = hkp.solve(V[i], w.h, w.nev, precision="fp64", return_psi=False, **kw)
+        errs.append(float((r.E - rb.E[i]).abs().max()))
+    torch.cuda.synchronize()
+    t_loop = (time.perf_counter() - t0) / len(idx)
+    return {"workload": "sweep64_dqd_192x40x40", "hamiltonians": 64, "nev": w.nev, "nb": 24,
+            "s_per_hamiltonian_batched_mixed_graph": round(t_batch / 64, 5),
+            "s_per_hamiltonian_looped_fp64": round(t_loop, 5),
+            "looped_sample": f"{len(idx)} of 64 (indices {idx[0]}..{idx[-1]} step 9)",
+            "speedup": round(t_loop / (t_batch / 64), 3),
+            "status_batched": rb.status,
+            "max_abs_dE_batched_vs_looped_eV": max(errs)}
+
+
+def adjoint_measure(torch, hkp, workload):
+    """Hellmann-Feynman backward of loss = sum of the lowest 8 eigenvalues in
+    the 5 gate voltages (192 x 40 x 40, B = 0): time of the backward and its
+    error against central finite differences (dV = 1e-4 V)."""
+    w = workload("adjoint_dqd_192x40x40")
+    Ld = torch.from_numpy(w.extra["L"]).cuda()
+    Vbg = torch.from_numpy(w.V).cuda()
+    S = torch.from_numpy(w.strain).cuda()
+    cfg = dict(h=w.h, nev=8, strain=S, B=w.B, nb=16, tol=1e-10)
+    Vg = torch.zeros(5, dtype=torch.float64, device="cuda", requires_grad=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    E = hkp.EigvalsFromPotential.apply(Vg, Ld, Vbg, cfg)
+    loss = E.sum()
+    torch.cuda.synchronize()
+    t_fwd = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    loss.backward()
+    torch.cuda.synchronize()
+    t_bwd = time.perf_counter() - t0
+    grad = Vg.grad.cpu().numpy()
+
+    def esum(vg):
+        V = Vbg + torch.tensordot(torch.as_tensor(vg, device="cuda"), Ld, dims=1)
+        return float(hkp.solve(V, w.h, 8, strain=S, B=w.B, nb=16, tol=1e-10,
+                               return_psi=False).E.sum())
+
+    d = 1e-4
+    fd = np.array([(esum(d * np.eye(5)[k]) - esum(-d * np.eye(5)[k])) / (2 * d)
+                   for k in range(5)])
+    return {"workload": "adjoint_dqd_192x40x40", "forward_s": round(t_fwd, 4),
+            "backward_s": round(t_bwd, 6),
+            "grad_rel_err_vs_fd": float(np.abs(grad - fd).max() / np.abs(fd).max())}
 
 
 def cpu_baseline(w, seconds=15.0):
@@ -87,12 +236,22 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also copy a 1 GiB buffer (reference for HBM byte counters)")
+    ap.add_argument("--no-extra", action="store_true",
+                    help="skip the sweep, adjoint and copy-bandwidth measurements")
+    ap.add_argument("--traffic-from", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"))
+    ap.add_argument("--stencil", metavar="TY,VGROUP,DMA",
+                    help="use this stencil launch shape instead of autotuning (profiled runs)")
     args = ap.parse_args()
+    if args.traffic_from:
+        traffic_from(*args.traffic_from)
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); this build has no "
               "multi-GPU path", file=sys.stderr)
         sys.exit(2)
 
+    if args.stencil:
+        os.environ["HKP_STENCIL"] = args.stencil
     import torch
     import paper_2607_08447_amd as hkp
     from synth import workload
@@ -110,9 +269,12 @@ def main():
     V = torch.from_numpy(w.V).cuda()
     S = torch.from_numpy(w.strain).cuda()
     log(f"workload {WORKLOAD} {w.shape} h={w.h} nev={nev} nb={nb}")
-    tune64 = hkp.autotune(w.shape, w.h, nb, "fp64")
-    tune32 = hkp.autotune(w.shape, w.h, nb, "mixed")
-    log(f"autotune fp64 {tune64} fp32 {tune32}")
+    if args.stencil:
+        tune64 = tune32 = {"forced": args.stencil}
+    else:
+        tune64 = hkp.autotune(w.shape, w.h, nb, "fp64")
+        tune32 = hkp.autotune(w.shape, w.h, nb, "mixed")
+    log(f"stencil launch shape: fp64 {tune64} fp32 {tune32}")
     ws = torch.empty(max(hkp.workspace_bytes(w.shape, w.h, nev, nb=nb, precision="mixed"),
                          hkp.workspace_bytes(w.shape, w.h, nev, nb=nb, precision="fp64")),
                      dtype=torch.uint8, device="cuda")
@@ -157,8 +319,17 @@ def main():
     bytes_per_launch = b32 / max(n32, 1)
     avg_launch = t32 / max(n32, 1)
     achieved = bytes_per_launch / avg_launch / 1e9
-    src = open(os.path.join(ROOT, "paper_2607_08447_amd", "csrc", "stencil.hip"), "rb").read()
-    traffic = _traffic_for(hashlib.sha256(src).hexdigest())
+    traffic = _traffic_for(_src_hash())
+    extra = {}
+    if not args.no_extra:
+        log("copy bandwidth ...")
+        extra["copy_gbps"] = round(copy_bandwidth(torch), 1)
+        log("sweep: 64 Hamiltonians batched vs looped ...")
+        extra["sweep"] = sweep_measure(torch, hkp, workload)
+        log(f"sweep {extra['sweep']}")
+        log("adjoint ...")
+        extra["adjoint"] = adjoint_measure(torch, hkp, workload)
+        log(f"adjoint {extra['adjoint']}")
 
     out = {
         "metric": METRIC,
@@ -193,10 +364,14 @@ def main():
             "algorithmic_bytes_per_launch": bytes_per_launch,
             "avg_launch_us": round(avg_launch * 1e6, 1),
             "launches": n32,
+            "frac_of_copy": (round(achieved / extra["copy_gbps"], 4)
+                             if "copy_gbps" in extra else None),
         },
+        "stencil_launch": {"fp32": tune32, "fp64": tune64},
         "fp64_stencil_gbps": round(r64.stats["bytes_stencil64"] /
                                    max(r64.stats["t_stencil64"], 1e-12) / 1e9, 1),
     }
+    out.update(extra)
     if not args.no_cpu:
         log("cpu baseline (oracle) ...")
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_seconds)

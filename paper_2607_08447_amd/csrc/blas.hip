@@ -100,6 +100,101 @@ gram_partial_kernel(const double* A, long long a_bstride, int nba, const double*
   }
 }
 
+// Hermitian Gram, balanced: the workgroup's four waves split the chunk's
+// elements into four contiguous runs and every wave computes all upper tile
+// pairs (ti <= tj) of its run, so all four SIMDs issue the same MFMA stream
+// and each element of A and B is loaded once per workgroup.  The real part
+// accumulates Ar'Br + Ai'Bi, the imaginary part Ar'Bi - Ai'Br, chained on two
+// accumulators per pair.  The four runs are summed in LDS in a fixed order.
+template <int NT>
+__global__ void __launch_bounds__(64 * 4)
+gram_herm_kernel(const double* A, long long a_bstride, int nba, const double* B,
+                 long long b_bstride, int nbb, long long n, long long chunk, const int* active,
+                 double* partial) {
+  constexpr int NP = NT * (NT + 1) / 2;
+  __shared__ double2 red[4][16][17];
+  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int b = blockIdx.y;
+  if (active && !active[b]) return;
+  const int nchunks = gridDim.x;
+  const long long c0 = (long long)blockIdx.x * chunk;
+  long long c1 = c0 + chunk;
+  if (c1 > n) c1 = n;
+  // this wave's run: a multiple of 4 elements
+  long long q4 = ((c1 - c0 + 15) / 16) * 4;
+  long long e0 = c0 + wv * q4;
+  long long e1 = e0 + q4;
+  if (e1 > c1) e1 = c1;
+  if (e0 > c1) e0 = c1;
+  const int r = lane & 15, q = lane >> 4;
+  const double* pa[NT];
+  const double* pb[NT];
+  bool aok[NT], bok[NT];
+#pragma unroll
+  for (int t = 0; t < NT; ++t) {
+    const int va = t * 16 + r, vb = t * 16 + r;
+    aok[t] = va < nba;
+    bok[t] = vb < nbb;
+    pa[t] = A + 2 * ((long long)b * a_bstride + (long long)(aok[t] ? va : 0) * n);
+    pb[t] = B + 2 * ((long long)b * b_bstride + (long long)(bok[t] ? vb : 0) * n);
+  }
+  d4 re[NP], im[NP];
+#pragma unroll
+  for (int k = 0; k < NP; ++k) {
+    re[k] = d4{0, 0, 0, 0};
+    im[k] = re[k];
+  }
+  const long long nks = (e1 - e0 + 3) / 4;
+  for (long long st = 0; st < nks; ++st) {
+    const long long e = e0 + 4 * st + q;
+    const bool eok = e < e1;
+    double2 av[NT], bv[NT];
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+      av[t] = (aok[t] && eok) ? *reinterpret_cast<const double2*>(pa[t] + 2 * e)
+                              : make_double2(0, 0);
+      bv[t] = (bok[t] && eok) ? *reinterpret_cast<const double2*>(pb[t] + 2 * e)
+                              : make_double2(0, 0);
+    }
+    int k = 0;
+#pragma unroll
+    for (int ti = 0; ti < NT; ++ti) {
+#pragma unroll
+      for (int tj = ti; tj < NT; ++tj, ++k) {
+        re[k] = mfma(av[ti].x, bv[tj].x, re[k]);
+        re[k] = mfma(av[ti].y, bv[tj].y, re[k]);
+        im[k] = mfma(av[ti].x, bv[tj].y, im[k]);
+        im[k] = mfma(-av[ti].y, bv[tj].x, im[k]);
+      }
+    }
+  }
+  // partial[b][chunk][i][j]: sum of the four runs, pair by pair
+  double* out = partial + 2 * (((long long)b * nchunks + blockIdx.x) * nba * nbb);
+  int k = 0;
+#pragma unroll
+  for (int ti = 0; ti < NT; ++ti) {
+#pragma unroll
+    for (int tj = ti; tj < NT; ++tj, ++k) {
+#pragma unroll
+      for (int g = 0; g < 4; ++g) red[wv][4 * g + q][r] = make_double2(re[k][g], im[k][g]);
+      __syncthreads();
+      {
+        const int i = threadIdx.x >> 4, j = threadIdx.x & 15;
+        double2 sum = red[0][i][j];
+#pragma unroll
+        for (int w = 1; w < 4; ++w) {
+          sum.x += red[w][i][j].x;
+          sum.y += red[w][i][j].y;
+        }
+        const int gi = ti * 16 + i, gj = tj * 16 + j;
+        if (gi < nba && gj < nbb)
+          *reinterpret_cast<double2*>(out + 2 * ((long long)gi * nbb + gj)) = sum;
+      }
+      __syncthreads();
+    }
+  }
+}
+
 // fixed-order reduction of the chunk partials: one wave per output entry,
 // lane l sums chunks l, l+64, ..., then a shuffle tree (deterministic)
 __global__ void __launch_bounds__(256)
@@ -422,15 +517,26 @@ hipError_t launch_gram(const BlockDesc& A, const BlockDesc& B, int hermitian, in
   const long long n = A.n;
   const int nchunks = gram_chunks(n, batch);
   long long chunk = (n + nchunks - 1) / nchunks;
-  chunk = (chunk + 3) & ~3LL;
+  chunk = (chunk + 15) & ~15LL;
   const int nta = (A.nvec + 15) / 16, ntb = (B.nvec + 15) / 16;
-  dim3 grid((unsigned)nchunks, (unsigned)((nta + 3) / 4), (unsigned)batch);
-  switch (ntb) {
-    case 1: gram_partial_kernel<1><<<grid, 256, 0, s>>>(A.ptr, A.bstride, A.nvec, B.ptr, B.bstride, B.nvec, n, chunk, hermitian, active, partial); break;
-    case 2: gram_partial_kernel<2><<<grid, 256, 0, s>>>(A.ptr, A.bstride, A.nvec, B.ptr, B.bstride, B.nvec, n, chunk, hermitian, active, partial); break;
-    case 3: gram_partial_kernel<3><<<grid, 256, 0, s>>>(A.ptr, A.bstride, A.nvec, B.ptr, B.bstride, B.nvec, n, chunk, hermitian, active, partial); break;
-    case 4: gram_partial_kernel<4><<<grid, 256, 0, s>>>(A.ptr, A.bstride, A.nvec, B.ptr, B.bstride, B.nvec, n, chunk, hermitian, active, partial); break;
-    default: return hipErrorInvalidValue;
+  if (hermitian && A.nvec == B.nvec) {
+    dim3 grid((unsigned)nchunks, (unsigned)batch);
+    switch (nta) {
+      case 1: gram_herm_kernel<1><<<grid, 256, 0, s>>>(A.ptr, A.bstride, A.nvec, B.ptr, B.bstride, B.nvec, n, chunk, active, partial); break;
+      case 2: gram_herm_kernel<2><<<grid, 256, 0, s>>>(A.ptr, A.bstride, A.nvec, B.ptr, B.bstride, B.nvec, n, chunk, active, partial); break;
+      case 3: gram_herm_kernel<3><<<grid, 256, 0, s>>>(A.ptr, A.bstride, A.nvec, B.ptr, B.bstride, B.nvec, n, chunk, active, partial); break;
+      case 4: gram_herm_kernel<4><<<grid, 256, 0, s>>>(A.ptr, A.bstride, A.nvec, B.ptr, B.bstride, B.nvec, n, chunk, active, partial); break;
+      default: return hipErrorInvalidValue;
+    }
+  } else {
+    dim3 grid((unsigned)nchunks, (unsigned)((nta + 3) / 4), (unsigned)batch);
+    switch (ntb) {
+      case 1: gram_partial_kernel<1><<<grid, 256, 0, s>>>(A.ptr, A.bstride, A.nvec, B.ptr, B.bstride, B.nvec, n, chunk, hermitian, active, partial); break;
+      case 2: gram_partial_kernel<2><<<grid, 256, 0, s>>>(A.ptr, A.bstride, A.nvec, B.ptr, B.bstride, B.nvec, n, chunk, hermitian, active, partial); break;
+      case 3: gram_partial_kernel<3><<<grid, 256, 0, s>>>(A.ptr, A.bstride, A.nvec, B.ptr, B.bstride, B.nvec, n, chunk, hermitian, active, partial); break;
+      case 4: gram_partial_kernel<4><<<grid, 256, 0, s>>>(A.ptr, A.bstride, A.nvec, B.ptr, B.bstride, B.nvec, n, chunk, hermitian, active, partial); break;
+      default: return hipErrorInvalidValue;
+    }
   }
   const int cnt = A.nvec * B.nvec;
   dim3 g2((unsigned)((cnt + 3) / 4), (unsigned)batch);

@@ -78,7 +78,7 @@ struct StencilLaunch {
                          // (vector lock[b] + i of member b is virtual vector work[b] + i);
                          // the grid covers nvec * batch vectors and only the first
                          // work[batch] are live, spread evenly over the XCDs. Or null.
-  int tile_y;            // 1, 2, 4, 8
+  int tile_y;            // 1, 2, 4
   int vgroup;            // vectors of one tile side by side (1 vector-major, nvec tile-major)
   int dma;               // 1: rows staged global -> LDS directly (needs nx % 64 == 0)
   int fp64;              // kernel type

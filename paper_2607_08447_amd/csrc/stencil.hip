@@ -75,6 +75,18 @@ __device__ __forceinline__ cx<T> wsum(cx<T> w, cx<T> a, cx<T> b) {
   cx<T> d = sub(a, b), s = add(a, b);
   return {fma(w.r, s.r, -w.i * d.i), fma(w.r, s.i, w.i * d.r)};
 }
+// acc + c a + conj(c) b  (c carries a real stencil coefficient times a link phase)
+template <typename T>
+__device__ __forceinline__ cx<T> wsum_acc(cx<T> acc, cx<T> c, cx<T> a, cx<T> b) {
+  cx<T> d = sub(a, b), s = add(a, b);
+  return {fma(-c.i, d.i, fma(c.r, s.r, acc.r)), fma(c.i, d.r, fma(c.r, s.i, acc.i))};
+}
+// acc + c a - conj(c) b
+template <typename T>
+__device__ __forceinline__ cx<T> wdiff_acc(cx<T> acc, cx<T> c, cx<T> a, cx<T> b) {
+  cx<T> d = sub(a, b), s = add(a, b);
+  return {fma(-c.i, s.i, fma(c.r, d.r, acc.r)), fma(c.i, s.r, fma(c.r, d.i, acc.i))};
+}
 
 template <typename T>
 __device__ __forceinline__ cx<T> ld(const T* p) {
@@ -348,14 +360,60 @@ stencil_kernel(KArgs<T> a) {
     }
   };
 
+  // link phases (GPU gauge) as a rolling window over planes z-1, z, z+1,
+  // loaded one plane ahead: x-links per plane (w), y-links per (plane, column)
+  // (v; with Bz = 0, PH == 1, uniform over the plane); PH == 2 also needs the
+  // y-links of the neighbouring columns in plane z (vx+, vx-)
+  const int xc = PH == 2 ? gxc : 0;
+  const int xcp = gxc + 1 < nx ? gxc + 1 : gxc, xcm = gxc > 0 ? gxc - 1 : 0;
+  cx<T> pw[3], pv[3], pvxp, pvxm;
+  if constexpr (PH != 0) {
+    const int z1 = nz > 1 ? 1 : 0;
+    pw[0] = pw[1] = ld(a.wtab);
+    pw[2] = ld(a.wtab + 2 * z1);
+    pv[0] = pv[1] = ld(a.vtab + 2 * xc);
+    pv[2] = ld(a.vtab + 2 * (z1 * nx + xc));
+    if constexpr (PH == 2) {
+      pvxp = ld(a.vtab + 2 * xcp);
+      pvxm = ld(a.vtab + 2 * xcm);
+    }
+  }
+
+  // on-site fields of this column, loaded one plane ahead (d00 d11 d22 d12 d02 d01;
+  // without strain only the first)
+  constexpr int ND = STR ? 6 : 1;
+  auto load_d = [&](int z, T (&d)[ND]) {
+    const unsigned pz = (unsigned)z * nxy + col;
+#pragma unroll
+    for (int i = 0; i < ND; ++i) d[i] = D[(unsigned)i * N + pz];
+  };
+  T cd[ND];
+  load_d(0, cd);
+
   auto step = [&](int z, auto BUF) {
     constexpr int cur = decltype(BUF)::value;
+    // loads in the order they are needed (the memory counter retires them in
+    // order): next plane's phases, this plane's on-site fields, the old block
+    // for the output plane, the next plane's halo, the next plane's rows
+    cx<T> nw, nv, nvxp, nvxm;
+    if constexpr (PH != 0) {
+      const int z2 = z + 2 < nz ? z + 2 : nz - 1, z1 = z + 1 < nz ? z + 1 : nz - 1;
+      nw = ld(a.wtab + 2 * z2);
+      nv = ld(a.vtab + 2 * (z2 * nx + xc));
+      if constexpr (PH == 2) {
+        nvxp = ld(a.vtab + 2 * (z1 * nx + xcp));
+        nvxm = ld(a.vtab + 2 * (z1 * nx + xcm));
+      }
+    }
     // the next plane goes to the other buffer while this one is read; the
     // barrier at the end of the step publishes it and retires this buffer
     // FP32: loads of the next plane issued before the arithmetic and written to
     // LDS after it (latency hidden by this wave's own work); FP64 writes them
     // at once (its register budget is already exhausted by the arithmetic)
     constexpr bool late = sizeof(T) == 4;
+    T nd[ND];
+    load_d(z + 1 < nz ? z + 1 : z, nd);
+    if (z >= 1) load_old(z - 1);
     cx<T> nxt[DMA ? 1 : NS][6];
     cx<T> hv = mk<T>(0, 0);
     const bool more = z + 1 < nz;
@@ -365,66 +423,47 @@ stencil_kernel(KArgs<T> a) {
         if constexpr (!late) commit(nxt, IC<1 - cur>{});
       }
     } else {
-      if (more) hv = halo_load(z + 1);
+      if (more) {
+        hv = halo_load(z + 1);
+        dma_plane(z + 1, IC<1 - cur>{});
+      }
     }
-    if (z >= 1) load_old(z - 1);
-    // on-site fields of this plane (loaded before the next plane's DMA is issued)
-    const unsigned p = (unsigned)z * nxy + col;
-    T d00, d11, d22, d12 = 0, d02 = 0, d01 = 0;
-    if constexpr (STR) {
-      d00 = D[p];
-      d11 = D[N + p];
-      d22 = D[2 * N + p];
-      d12 = D[3 * N + p];
-      d02 = D[4 * N + p];
-      d01 = D[5 * N + p];
-    } else {
-      d00 = d11 = d22 = D[p];
-    }
-    if constexpr (DMA) {
-      if (more) dma_plane(z + 1, IC<1 - cur>{});
-    }
+    // (indices stay inside cd for ND = 1; the strain terms are then zero)
+    const T d00 = cd[0], d11 = cd[STR ? 1 : 0], d22 = cd[STR ? 2 : 0];
+    const T d12 = STR ? cd[STR ? 3 : 0] : (T)0;
+    const T d02 = STR ? cd[STR ? 4 : 0] : (T)0;
+    const T d01 = STR ? cd[STR ? 5 : 0] : (T)0;
     const cx<T>* L = bufp(IC<cur>{}) + lb;
     auto at = [&](int c, int dy, int dx) { return L[c * PLANE + dy * W + dx]; };
 
     // ---- phases (GPU gauge): x-links per plane, y-links per (plane, column);
     // with Bz = 0 (PH == 1) every phase is uniform over the plane
-    cx<T> w0, wm, wp, v0, vm, vp, vxp, vxm;
-    if constexpr (PH != 0) {
-      const int zm = z > 0 ? z - 1 : 0, zq = z + 1 < nz ? z + 1 : nz - 1;
-      w0 = ld(a.wtab + 2 * z);
-      wm = ld(a.wtab + 2 * zm);
-      wp = ld(a.wtab + 2 * zq);
-      const int xc = PH == 1 ? 0 : gxc;
-      v0 = ld(a.vtab + 2 * (z * nx + xc));
-      vm = ld(a.vtab + 2 * (zm * nx + xc));
-      vp = ld(a.vtab + 2 * (zq * nx + xc));
-      if constexpr (PH == 2) {
-        vxp = ld(a.vtab + 2 * (z * nx + (gxc + 1 < nx ? gxc + 1 : gxc)));
-        vxm = ld(a.vtab + 2 * (z * nx + (gxc > 0 ? gxc - 1 : 0)));
-      }
-    }
+    const cx<T> wm = pw[0], w0 = pw[1], wp = pw[2], vm = pv[0], v0 = pv[1], vp = pv[2];
+    const cx<T> vxp = pvxp, vxm = pvxm;
 
     cx<T> acc2[3];
     {
-      // faces in the plane (this spin's three orbitals)
-      cx<T> Sx[3], Sy[3];
+      // faces in the plane (this spin's three orbitals); the coefficient of the
+      // x faces is (L-M) + M on |X> and M on |Y>, |Z> (y faces: on |Y> and the
+      // others), folded with the link phase into one complex constant per plane
+      const T cLMM = k.cLM + k.cM;
+      if constexpr (PH != 0) {
+        const cx<T> cx_o = scl(k.cM, w0), cx_a = scl(cLMM, w0);
+        const cx<T> cy_o = scl(k.cM, v0), cy_a = scl(cLMM, v0);
 #pragma unroll
-      for (int i = 0; i < 3; ++i) {
-        const cx<T> xp = at(X + i, 0, 1), xm = at(X + i, 0, -1);
-        const cx<T> yp = at(X + i, 1, 0), ym = at(X + i, -1, 0);
-        if constexpr (PH != 0) {
-          Sx[i] = wsum(w0, xp, xm);
-          Sy[i] = wsum(v0, yp, ym);
-        } else {
-          Sx[i] = add(xp, xm);
-          Sy[i] = add(yp, ym);
+        for (int i = 0; i < 3; ++i) {
+          acc1[i] = wsum_acc(acc1[i], i == 0 ? cx_a : cx_o, at(X + i, 0, 1), at(X + i, 0, -1));
+          acc1[i] = wsum_acc(acc1[i], i == 1 ? cy_a : cy_o, at(X + i, 1, 0), at(X + i, -1, 0));
+        }
+      } else {
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+          const cx<T> sx = add(at(X + i, 0, 1), at(X + i, 0, -1));
+          const cx<T> sy = add(at(X + i, 1, 0), at(X + i, -1, 0));
+          acc1[i] = fma_s(acc1[i], i == 0 ? cLMM : k.cM, sx);
+          acc1[i] = fma_s(acc1[i], i == 1 ? cLMM : k.cM, sy);
         }
       }
-      acc1[0] = fma_s(acc1[0], k.cLM, Sx[0]);
-      acc1[1] = fma_s(acc1[1], k.cLM, Sy[1]);
-#pragma unroll
-      for (int i = 0; i < 3; ++i) acc1[i] = fma_s(acc1[i], k.cM, add(Sx[i], Sy[i]));
     }
     {
       // x-y edges (in plane): couple X <-> Y
@@ -444,12 +483,12 @@ stencil_kernel(KArgs<T> a) {
         acc1[1] = fma_s(acc1[1], k.cN8, eX);
       } else if constexpr (PH == 1) {
         // uniform phases: P(sx, sy) = 2 w^sx v^sy, so the corner sum is
-        // 2 [w (v f++ - v* f+-) - w* (v f-+ - v* f--)]
+        // q f++ + conj(q) f-- - (p f+- + conj(p) f-+) with q = 2 cN8 w v and
+        // p = 2 cN8 w conj(v) (f indexed by the signs of dx, dy)
         const T c2 = k.cN8 + k.cN8;
-        const cx<T> eY = wdiff(w0, wdiff(v0, fY_pp, fY_pm), wdiff(v0, fY_mp, fY_mm));
-        const cx<T> eX = wdiff(w0, wdiff(v0, fX_pp, fX_pm), wdiff(v0, fX_mp, fX_mm));
-        acc1[0] = fma_s(acc1[0], c2, eY);
-        acc1[1] = fma_s(acc1[1], c2, eX);
+        const cx<T> q = scl(c2, mul(w0, v0)), mp = scl(-c2, mul(w0, conj(v0)));
+        acc1[0] = wsum_acc(wsum_acc(acc1[0], q, fY_pp, fY_mm), mp, fY_pm, fY_mp);
+        acc1[1] = wsum_acc(wsum_acc(acc1[1], q, fX_pp, fX_mm), mp, fX_pm, fX_mp);
       } else {
         cx<T> eY = sub(add(fY_pp, fY_mm), add(fY_pm, fY_mp));
         cx<T> eX = sub(add(fX_pp, fX_mm), add(fX_pm, fX_mp));
@@ -473,14 +512,15 @@ stencil_kernel(KArgs<T> a) {
       const cx<T> ypZ = at(X + 2, 1, 0), ymZ = at(X + 2, -1, 0);
       const cx<T> ypY = at(X + 1, 1, 0), ymY = at(X + 1, -1, 0);
       if constexpr (PH != 0) {
-        const cx<T> wu = add(wm, w0), wd = add(wp, w0);   // path averages (x2)
-        const cx<T> vu = add(vm, v0), vd = add(vp, v0);
-        acc0[0] = fma_s(acc0[0], k.cN8, wdiff(wu, xpZ, xmZ));
-        acc0[2] = fma_s(acc0[2], k.cN8, add(wdiff(wu, xpX, xmX), wdiff(vu, ypY, ymY)));
-        acc0[1] = fma_s(acc0[1], k.cN8, wdiff(vu, ypZ, ymZ));
-        acc2[0] = fma_s(acc2[0], -k.cN8, wdiff(wd, xpZ, xmZ));
-        acc2[2] = fma_s(acc2[2], -k.cN8, add(wdiff(wd, xpX, xmX), wdiff(vd, ypY, ymY)));
-        acc2[1] = fma_s(acc2[1], -k.cN8, wdiff(vd, ypZ, ymZ));
+        // path-averaged phases (x2) times +-cN8, one complex constant each
+        const cx<T> cu = scl(k.cN8, add(wm, w0)), cd = scl(-k.cN8, add(wp, w0));
+        const cx<T> du = scl(k.cN8, add(vm, v0)), dd = scl(-k.cN8, add(vp, v0));
+        acc0[0] = wdiff_acc(acc0[0], cu, xpZ, xmZ);
+        acc0[2] = wdiff_acc(wdiff_acc(acc0[2], cu, xpX, xmX), du, ypY, ymY);
+        acc0[1] = wdiff_acc(acc0[1], du, ypZ, ymZ);
+        acc2[0] = wdiff_acc(acc2[0], cd, xpZ, xmZ);
+        acc2[2] = wdiff_acc(wdiff_acc(acc2[2], cd, xpX, xmX), dd, ypY, ymY);
+        acc2[1] = wdiff_acc(acc2[1], dd, ypZ, ymZ);
       } else {
         const T c2 = k.cN8 + k.cN8;
         const cx<T> dxZ = sub(xpZ, xmZ), dxX = sub(xpX, xmX);
@@ -539,6 +579,20 @@ stencil_kernel(KArgs<T> a) {
     for (int i = 0; i < 3; ++i) {
       acc0[i] = acc1[i];
       acc1[i] = acc2[i];
+    }
+#pragma unroll
+    for (int i = 0; i < ND; ++i) cd[i] = nd[i];
+    if constexpr (PH != 0) {
+      pw[0] = pw[1];
+      pw[1] = pw[2];
+      pw[2] = nw;
+      pv[0] = pv[1];
+      pv[1] = pv[2];
+      pv[2] = nv;
+      if constexpr (PH == 2) {
+        pvxp = nvxp;
+        pvxm = nvxm;
+      }
     }
     __syncthreads();
   };
@@ -614,7 +668,6 @@ hipError_t launch_t(const StencilLaunch& L, const StencilConsts<double>& c, hipS
     case 1: stencil_kernel<T, TO, TW, PH, STR, 1, false><<<grid, dim3(64, 1, 2), 0, s>>>(a); break;
     case 2: stencil_kernel<T, TO, TW, PH, STR, 2, false><<<grid, dim3(64, 2, 2), 0, s>>>(a); break;
     case 4: stencil_kernel<T, TO, TW, PH, STR, 4, false><<<grid, dim3(64, 4, 2), 0, s>>>(a); break;
-    case 8: stencil_kernel<T, TO, TW, PH, STR, 8, false><<<grid, dim3(64, 8, 2), 0, s>>>(a); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();

@@ -99,8 +99,7 @@ def test_apply_full_size_sampled_rows():
     assert err < 1e-13
 
 
-VARIANTS = [(ty, vg, dma) for dma in (0, 1) for vg in (1, 2, 4) for ty in (1, 2, 4, 8)
-            if not (dma and ty == 8)]
+VARIANTS = [(ty, vg, dma) for dma in (0, 1) for vg in (1, 2, 4) for ty in (1, 2, 4)]
 VARIANT_SHAPES = [
     # x spans whole 64-wide tiles (the row-DMA variant applies); y ragged for every tile height
     ((128, 7, 5), 0.4, True, (0.5, 0.0, 0.0)),
