@@ -20,7 +20,7 @@ namespace hkp {
 
 namespace {
 
-constexpr int kJacThreads = 256;
+constexpr int kJacThreads = 1024;
 constexpr int kNBP = HKP_NB_MAX;   // padded size (even)
 
 struct Rot {
@@ -138,44 +138,60 @@ heev_kernel(double* A, int nb, long long mat_stride, double* evals, double* out,
         rot[tid] = r;
       }
       __syncthreads();
-      // rows: row p <- c A[p,:] - s e^{i phi} A[q,:],  row q <- s A[p,:] + c e^{i phi} A[q,:]
-      for (int t = tid; t < (n / 2) * n; t += kJacThreads) {
-        const Rot r = rot[t / n];
-        if (r.s == 0.0) continue;
-        const int j = t % n;
-        const double2 xp = a[r.p][j], xq = a[r.q][j];
-        const double2 eq = make_double2(r.er * xq.x - r.ei * xq.y, r.er * xq.y + r.ei * xq.x);
-        a[r.p][j] = make_double2(r.c * xp.x - r.s * eq.x, r.c * xp.y - r.s * eq.y);
-        a[r.q][j] = make_double2(r.s * xp.x + r.c * eq.x, r.s * xp.y + r.c * eq.y);
-      }
-      __syncthreads();
-      // columns (A and V): col p <- c A[:,p] - s e^{-i phi} A[:,q], col q <- s A[:,p] + c e^{-i phi} A[:,q]
-      for (int t = tid; t < (n / 2) * n; t += kJacThreads) {
-        const Rot r = rot[t / n];
-        if (r.s == 0.0) continue;
-        const int i = t % n;
-        {
-          const double2 xp = a[i][r.p], xq = a[i][r.q];
-          const double2 eq = make_double2(r.er * xq.x + r.ei * xq.y, r.er * xq.y - r.ei * xq.x);
-          a[i][r.p] = make_double2(r.c * xp.x - r.s * eq.x, r.c * xp.y - r.s * eq.y);
-          a[i][r.q] = make_double2(r.s * xp.x + r.c * eq.x, r.s * xp.y + r.c * eq.y);
-        }
-        {
-          const double2 xp = v[i][r.p], xq = v[i][r.q];
-          const double2 eq = make_double2(r.er * xq.x + r.ei * xq.y, r.er * xq.y - r.ei * xq.x);
-          v[i][r.p] = make_double2(r.c * xp.x - r.s * eq.x, r.c * xp.y - r.s * eq.y);
-          v[i][r.q] = make_double2(r.s * xp.x + r.c * eq.x, r.s * xp.y + r.c * eq.y);
-        }
-      }
-      __syncthreads();
-      // exact zero of the annihilated entries and real diagonal
-      if (tid < n / 2) {
-        const Rot r = rot[tid];
-        if (r.s != 0.0) {
-          a[r.p][r.q] = make_double2(0, 0);
-          a[r.q][r.p] = make_double2(0, 0);
-          a[r.p][r.p].y = 0.0;
-          a[r.q][r.q].y = 0.0;
+      // A <- N^H A N and V <- V N with N block diagonal over the pairs,
+      // N_k = [[c, s], [-s e^{-i phi}, c e^{-i phi}]] on (p_k, q_k): every 2x2
+      // block of A (pair P rows, pair Q columns) and every (row, pair) slice of
+      // V is owned by one thread, so one phase updates everything in place
+      {
+        const int h = n / 2;
+        const int nblk = h * h;
+        for (int t = tid; t < nblk + n * h; t += kJacThreads) {
+          if (t < nblk) {
+            const Rot rp = rot[t / h], rq = rot[t % h];
+            if (rp.s == 0.0 && rq.s == 0.0) continue;
+            double2 a00 = a[rp.p][rq.p], a01 = a[rp.p][rq.q];
+            double2 a10 = a[rp.q][rq.p], a11 = a[rp.q][rq.q];
+            if (rq.s != 0.0) {
+              // T = A_PQ N_Q: col p <- c col_p - s e^{-i phi} col_q, col q <- s col_p + c e^{-i phi} col_q
+              const double2 e01 = make_double2(rq.er * a01.x + rq.ei * a01.y, rq.er * a01.y - rq.ei * a01.x);
+              const double2 e11 = make_double2(rq.er * a11.x + rq.ei * a11.y, rq.er * a11.y - rq.ei * a11.x);
+              const double2 t00 = make_double2(rq.c * a00.x - rq.s * e01.x, rq.c * a00.y - rq.s * e01.y);
+              const double2 t01 = make_double2(rq.s * a00.x + rq.c * e01.x, rq.s * a00.y + rq.c * e01.y);
+              const double2 t10 = make_double2(rq.c * a10.x - rq.s * e11.x, rq.c * a10.y - rq.s * e11.y);
+              const double2 t11 = make_double2(rq.s * a10.x + rq.c * e11.x, rq.s * a10.y + rq.c * e11.y);
+              a00 = t00; a01 = t01; a10 = t10; a11 = t11;
+            }
+            if (rp.s != 0.0) {
+              // N_P^H T: row p <- c row_p - s e^{i phi} row_q, row q <- s row_p + c e^{i phi} row_q
+              const double2 e10 = make_double2(rp.er * a10.x - rp.ei * a10.y, rp.er * a10.y + rp.ei * a10.x);
+              const double2 e11 = make_double2(rp.er * a11.x - rp.ei * a11.y, rp.er * a11.y + rp.ei * a11.x);
+              const double2 u00 = make_double2(rp.c * a00.x - rp.s * e10.x, rp.c * a00.y - rp.s * e10.y);
+              const double2 u01 = make_double2(rp.c * a01.x - rp.s * e11.x, rp.c * a01.y - rp.s * e11.y);
+              const double2 u10 = make_double2(rp.s * a00.x + rp.c * e10.x, rp.s * a00.y + rp.c * e10.y);
+              const double2 u11 = make_double2(rp.s * a01.x + rp.c * e11.x, rp.s * a01.y + rp.c * e11.y);
+              a00 = u00; a01 = u01; a10 = u10; a11 = u11;
+            }
+            if (t / h == t % h) {
+              // the rotated pair itself: annihilated entry exactly zero, real diagonal
+              a01 = make_double2(0, 0);
+              a10 = make_double2(0, 0);
+              a00.y = 0.0;
+              a11.y = 0.0;
+            }
+            a[rp.p][rq.p] = a00;
+            a[rp.p][rq.q] = a01;
+            a[rp.q][rq.p] = a10;
+            a[rp.q][rq.q] = a11;
+          } else {
+            const int u = t - nblk;
+            const Rot rq = rot[u % h];
+            if (rq.s == 0.0) continue;
+            const int i = u / h;
+            const double2 xp = v[i][rq.p], xq = v[i][rq.q];
+            const double2 eq = make_double2(rq.er * xq.x + rq.ei * xq.y, rq.er * xq.y - rq.ei * xq.x);
+            v[i][rq.p] = make_double2(rq.c * xp.x - rq.s * eq.x, rq.c * xp.y - rq.s * eq.y);
+            v[i][rq.q] = make_double2(rq.s * xp.x + rq.c * eq.x, rq.s * xp.y + rq.c * eq.y);
+          }
         }
       }
       __syncthreads();
