@@ -55,19 +55,25 @@ def _src_hash():
         return hashlib.sha256(f.read()).hexdigest()
 
 
-def _traffic_for(kernel_src_hash):
+def _shape_key(tune):
+    return f"{tune['tile_y']},{tune['vgroup']},{tune['dma']}"
+
+
+def _traffic_for(kernel_src_hash, shape):
     """HBM bytes per launch of the dominant kernel from the committed rocprofv3
-    counter summary, if it was taken on the current kernel source."""
+    counter summary, if it was taken on the current kernel source with the
+    launch shape (tile height, vector group, row DMA) this run uses."""
     if not os.path.exists(TRAFFIC_JSON):
         return None
     with open(TRAFFIC_JSON) as f:
         d = json.load(f)
     if d.get("stencil_src_sha256") != kernel_src_hash:
         return None
-    return d.get("hbm_bytes_per_launch")
+    entry = d.get("by_launch", {}).get(shape)
+    return entry.get("hbm_bytes_per_launch") if entry else None
 
 
-def traffic_from(fetch_csv, write_csv):
+def traffic_from(fetch_csv, write_csv, shape):
     """HBM bytes per launch of the FP32 filter-step stencil from rocprofv3
     FETCH_SIZE and WRITE_SIZE (KiB per dispatch) collection files.  Each
     counter is scaled by what it reads for the 1 GiB device copy the profiled
@@ -97,19 +103,25 @@ def traffic_from(fetch_csv, write_csv):
     gib = float(1 << 30)
     kf, kw = gib / cf, gib / cw
     per_launch = [kf * a + kw * b for a, b in zip(sf, sw)]
-    d = {
-        "kernel": "stencil_kernel<float, ...> (FP32 Chebyshev filter step), dqd_256x48x48, nb 48",
-        "stencil_src_sha256": _src_hash(),
+    d = {}
+    if os.path.exists(TRAFFIC_JSON):
+        with open(TRAFFIC_JSON) as f:
+            d = json.load(f)
+    if d.get("stencil_src_sha256") != _src_hash():
+        d = {"by_launch": {}}   # counters of an older kernel source are dropped
+    d["kernel"] = "stencil_kernel<float, ...> (FP32 Chebyshev filter step), dqd_256x48x48, nb 48"
+    d["stencil_src_sha256"] = _src_hash()
+    d["by_launch"][shape] = {
         "dispatches": len(per_launch),
         "hbm_bytes_per_launch": sum(per_launch) / len(per_launch),
         "fetch_bytes_per_launch": kf * sum(sf) / len(sf),
         "write_bytes_per_launch": kw * sum(sw) / len(sw),
         "copy_calibration": {"fetch_factor": kf, "write_factor": kw,
                              "note": "1 GiB device copy: counter bytes x factor = true bytes"},
-        "made_by": ["rocprofv3 --pmc FETCH_SIZE -- python3 bench.py --copy-calibration --no-cpu "
-                    "--no-extra --steps 1 --warmup 0",
+        "made_by": [f"rocprofv3 --pmc FETCH_SIZE -- python3 bench.py --copy-calibration --no-cpu "
+                    f"--no-extra --steps 1 --warmup 0 --stencil {shape}",
                     "rocprofv3 --pmc WRITE_SIZE -- (same)",
-                    "python bench.py --traffic-from <fetch csv> <write csv>"],
+                    f"python bench.py --traffic-from <fetch csv> <write csv> --stencil {shape}"],
     }
     with open(TRAFFIC_JSON, "w") as f:
         json.dump(d, f, indent=1)
@@ -243,7 +255,9 @@ def main():
                     help="use this stencil launch shape instead of autotuning (profiled runs)")
     args = ap.parse_args()
     if args.traffic_from:
-        traffic_from(*args.traffic_from)
+        if not args.stencil:
+            raise SystemExit("--traffic-from needs --stencil TY,VGROUP,DMA (the profiled launch shape)")
+        traffic_from(*args.traffic_from, args.stencil)
         return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); this build has no "
@@ -270,7 +284,8 @@ def main():
     S = torch.from_numpy(w.strain).cuda()
     log(f"workload {WORKLOAD} {w.shape} h={w.h} nev={nev} nb={nb}")
     if args.stencil:
-        tune64 = tune32 = {"forced": args.stencil}
+        ty, vg, dma = (int(v) for v in args.stencil.split(","))
+        tune64 = tune32 = {"tile_y": ty, "vgroup": vg, "dma": dma, "forced": True}
     else:
         tune64 = hkp.autotune(w.shape, w.h, nb, "fp64")
         tune32 = hkp.autotune(w.shape, w.h, nb, "mixed")
@@ -319,7 +334,7 @@ def main():
     bytes_per_launch = b32 / max(n32, 1)
     avg_launch = t32 / max(n32, 1)
     achieved = bytes_per_launch / avg_launch / 1e9
-    traffic = _traffic_for(_src_hash())
+    traffic = _traffic_for(_src_hash(), _shape_key(tune32))
     extra = {}
     if not args.no_extra:
         log("copy bandwidth ...")
