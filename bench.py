@@ -55,14 +55,15 @@ def _src_hash():
         return hashlib.sha256(f.read()).hexdigest()
 
 
-def _shape_key(tune):
-    return f"{tune['tile_y']},{tune['vgroup']},{tune['dma']}"
+def _shape_key(tune, nb):
+    return f"{tune['tile_y']},{tune['vgroup']},{tune['dma']}/nb{nb}"
 
 
 def _traffic_for(kernel_src_hash, shape):
     """HBM bytes per launch of the dominant kernel from the committed rocprofv3
     counter summary, if it was taken on the current kernel source with the
-    launch shape (tile height, vector group, row DMA) this run uses."""
+    launch shape (tile height, vector group, row DMA) and block size this run
+    uses."""
     if not os.path.exists(TRAFFIC_JSON):
         return None
     with open(TRAFFIC_JSON) as f:
@@ -73,7 +74,7 @@ def _traffic_for(kernel_src_hash, shape):
     return entry.get("hbm_bytes_per_launch") if entry else None
 
 
-def traffic_from(fetch_csv, write_csv, shape):
+def traffic_from(fetch_csv, write_csv, stencil, nb):
     """HBM bytes per launch of the FP32 filter-step stencil from rocprofv3
     FETCH_SIZE and WRITE_SIZE (KiB per dispatch) collection files.  Each
     counter is scaled by what it reads for the 1 GiB device copy the profiled
@@ -109,9 +110,10 @@ def traffic_from(fetch_csv, write_csv, shape):
             d = json.load(f)
     if d.get("stencil_src_sha256") != _src_hash():
         d = {"by_launch": {}}   # counters of an older kernel source are dropped
-    d["kernel"] = "stencil_kernel<float, ...> (FP32 Chebyshev filter step), dqd_256x48x48, nb 48"
+    d["kernel"] = ("stencil_kernel<float, ...> (FP32 Chebyshev filter step), dqd_256x48x48; "
+                   "entries keyed by tile height, vector group, row DMA / block size")
     d["stencil_src_sha256"] = _src_hash()
-    d["by_launch"][shape] = {
+    d["by_launch"][f"{stencil}/nb{nb}"] = {
         "dispatches": len(per_launch),
         "hbm_bytes_per_launch": sum(per_launch) / len(per_launch),
         "fetch_bytes_per_launch": kf * sum(sf) / len(sf),
@@ -119,9 +121,10 @@ def traffic_from(fetch_csv, write_csv, shape):
         "copy_calibration": {"fetch_factor": kf, "write_factor": kw,
                              "note": "1 GiB device copy: counter bytes x factor = true bytes"},
         "made_by": [f"rocprofv3 --pmc FETCH_SIZE -- python3 bench.py --copy-calibration --no-cpu "
-                    f"--no-extra --steps 1 --warmup 0 --stencil {shape}",
+                    f"--no-extra --steps 1 --warmup 0 --stencil {stencil} --nb {nb}",
                     "rocprofv3 --pmc WRITE_SIZE -- (same)",
-                    f"python bench.py --traffic-from <fetch csv> <write csv> --stencil {shape}"],
+                    f"python bench.py --traffic-from <fetch csv> <write csv> --stencil {stencil} "
+                    f"--nb {nb}"],
     }
     with open(TRAFFIC_JSON, "w") as f:
         json.dump(d, f, indent=1)
@@ -146,13 +149,17 @@ def copy_bandwidth(torch, nbytes=2 << 30, reps=5):
 
 def sweep_measure(torch, hkp, workload):
     """Barrier sweep: 64 Hamiltonians batched (mixed, one hipGraph) vs a loop
-    of FP64 solves over 8 of them (evenly spaced), both to residual 1e-5 eV."""
+    of FP64 solves over 8 of them (evenly spaced), both to residual 1e-5 eV.
+    Block size and stencil launch shape are autotuned on the first member."""
     w = workload("sweep64_dqd_192x40x40")
     V = torch.from_numpy(w.V).cuda()
     S = torch.from_numpy(w.strain).cuda()
-    hkp.autotune(w.shape, w.h, 24, "mixed")
-    hkp.autotune(w.shape, w.h, 24, "fp64")
-    kw = dict(strain=S, B=w.B, nb=24, tol=1e-5)
+    blk = {}
+    for prec in ("mixed", "fp64"):
+        blk[prec] = hkp.autotune_block(V[0], w.h, w.nev, strain=S, B=w.B, candidates=[24, 32],
+                                       tol=1e-5, precision=prec)
+        hkp.autotune(w.shape, w.h, blk[prec]["nb"], prec)
+    kw = dict(strain=S, B=w.B, nb=0, tol=1e-5)
     hkp.solve_batch(V[:2], w.h, w.nev, precision="mixed", graph=True, **kw)   # warm-up
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -167,7 +174,9 @@ def sweep_measure(torch, hkp, workload):
         errs.append(float((r.E - rb.E[i]).abs().max()))
     torch.cuda.synchronize()
     t_loop = (time.perf_counter() - t0) / len(idx)
-    return {"workload": "sweep64_dqd_192x40x40", "hamiltonians": 64, "nev": w.nev, "nb": 24,
+    return {"workload": "sweep64_dqd_192x40x40", "hamiltonians": 64, "nev": w.nev,
+            "nb": {"mixed": blk["mixed"]["nb"], "fp64": blk["fp64"]["nb"]},
+            "nb_tuning_s": {p: blk[p]["seconds"] for p in blk},
             "s_per_hamiltonian_batched_mixed_graph": round(t_batch / 64, 5),
             "s_per_hamiltonian_looped_fp64": round(t_loop, 5),
             "looped_sample": f"{len(idx)} of 64 (indices {idx[0]}..{idx[-1]} step 9)",
@@ -253,11 +262,14 @@ def main():
     ap.add_argument("--traffic-from", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"))
     ap.add_argument("--stencil", metavar="TY,VGROUP,DMA",
                     help="use this stencil launch shape instead of autotuning (profiled runs)")
+    ap.add_argument("--nb", type=int, default=0,
+                    help="use this block size instead of autotuning it (profiled runs)")
     args = ap.parse_args()
     if args.traffic_from:
-        if not args.stencil:
-            raise SystemExit("--traffic-from needs --stencil TY,VGROUP,DMA (the profiled launch shape)")
-        traffic_from(*args.traffic_from, args.stencil)
+        if not args.stencil or not args.nb:
+            raise SystemExit("--traffic-from needs --stencil TY,VGROUP,DMA and --nb NB "
+                             "(the profiled launch shape and block size)")
+        traffic_from(*args.traffic_from, args.stencil, args.nb)
         return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); this build has no "
@@ -279,23 +291,33 @@ def main():
         del src_buf, dst_buf
 
     w = workload(WORKLOAD)
-    nev, nb, tol = 32, 48, 1e-5
+    nev, tol = 32, 1e-5
     V = torch.from_numpy(w.V).cuda()
     S = torch.from_numpy(w.strain).cuda()
-    log(f"workload {WORKLOAD} {w.shape} h={w.h} nev={nev} nb={nb}")
+    log(f"workload {WORKLOAD} {w.shape} h={w.h} nev={nev}")
+    # block size per precision: measured (one solve per candidate) unless forced
+    nbs, nb_tuning = {}, {}
+    for prec in ("mixed", "fp64"):
+        if args.nb:
+            nbs[prec] = args.nb
+        else:
+            t = hkp.autotune_block(V, w.h, nev, strain=S, B=w.B, candidates=[40, 48, 56],
+                                   tol=tol, precision=prec)
+            nbs[prec], nb_tuning[prec] = t["nb"], t["seconds"]
+    log(f"block size {nbs} {nb_tuning}")
     if args.stencil:
         ty, vg, dma = (int(v) for v in args.stencil.split(","))
         tune64 = tune32 = {"tile_y": ty, "vgroup": vg, "dma": dma, "forced": True}
     else:
-        tune64 = hkp.autotune(w.shape, w.h, nb, "fp64")
-        tune32 = hkp.autotune(w.shape, w.h, nb, "mixed")
+        tune64 = hkp.autotune(w.shape, w.h, nbs["fp64"], "fp64")
+        tune32 = hkp.autotune(w.shape, w.h, nbs["mixed"], "mixed")
     log(f"stencil launch shape: fp64 {tune64} fp32 {tune32}")
-    ws = torch.empty(max(hkp.workspace_bytes(w.shape, w.h, nev, nb=nb, precision="mixed"),
-                         hkp.workspace_bytes(w.shape, w.h, nev, nb=nb, precision="fp64")),
+    ws = torch.empty(max(hkp.workspace_bytes(w.shape, w.h, nev, nb=nbs["mixed"], precision="mixed"),
+                         hkp.workspace_bytes(w.shape, w.h, nev, nb=nbs["fp64"], precision="fp64")),
                      dtype=torch.uint8, device="cuda")
 
     def solve(prec, t):
-        return hkp.solve(V, w.h, nev, strain=S, B=w.B, nb=nb, tol=t, precision=prec,
+        return hkp.solve(V, w.h, nev, strain=S, B=w.B, nb=nbs[prec], tol=t, precision=prec,
                          workspace=ws, return_psi=False)
 
     t0 = time.perf_counter()
@@ -334,7 +356,7 @@ def main():
     bytes_per_launch = b32 / max(n32, 1)
     avg_launch = t32 / max(n32, 1)
     achieved = bytes_per_launch / avg_launch / 1e9
-    traffic = _traffic_for(_src_hash(), _shape_key(tune32))
+    traffic = _traffic_for(_src_hash(), _shape_key(tune32, nbs["mixed"]))
     extra = {}
     if not args.no_extra:
         log("copy bandwidth ...")
@@ -360,7 +382,9 @@ def main():
         "dtype": "c64 filter / c128 orth+RR+residual",
         "data": "synthetic (seeded DQD fin potential, strain, B field)",
         "config": {"workload": WORKLOAD, "grid": list(w.shape), "h_nm": w.h, "nev": nev,
-                   "nb": nb, "precision": "mixed", "stop": "per-state residual <= 1e-5 eV",
+                   "nb": nbs["mixed"], "nb_fp64": nbs["fp64"],
+                   "nb_tuning_s": nb_tuning or "forced",
+                   "precision": "mixed", "stop": "per-state residual <= 1e-5 eV",
                    "B_T": list(w.B), "strain": "ezz -0.3% + smooth perturbation"},
         "s_per_solve_mixed": round(t_steps / args.steps, 4),
         "s_per_solve_fp64": round(t_fp64, 4),

@@ -131,8 +131,9 @@ void hkp_default_material(hkp_material* m);
 void hkp_default_opts(hkp_opts* o);
 
 /* Bytes of device workspace hkp_solve / hkp_solve_batch need for `batch`
- * Hamiltonians on `grid` with `opts` (nb = 0 sizes for the largest autotuned
- * block).  Returns 0 on invalid arguments. */
+ * Hamiltonians on `grid` with `opts` (nb = 0: the block size from
+ * hkp_autotune_block if it ran for this grid, nev and precision, else
+ * nev + max(8, nev/2) rounded up to 8).  Returns 0 on invalid arguments. */
 size_t hkp_workspace_bytes(const hkp_grid* grid, const hkp_opts* opts, int32_t batch);
 
 /* Lowest opts->nev eigenpairs of H for one potential (paper Sec. II.B).
@@ -208,6 +209,23 @@ int hkp_hf_grad(int64_t N, int32_t nev, const void* psi, const double* w, int32_
 int hkp_autotune(const hkp_grid* grid, int32_t nb, int32_t precision, int32_t with_strain,
                  int32_t with_field, void* workspace, size_t ws_bytes, void* hip_stream,
                  hkp_tune* out);
+
+/* Block size by measurement: one complete solve of this Hamiltonian (opts:
+ * nev, tolerance, precision, degree, max_iter; nb and graph/X0 flags ignored)
+ * for each of the ncand (1..16) candidate block sizes, each nev < nb <=
+ * min(64, 6N), timed to convergence.  The fastest converged candidate is
+ * written to *nb_out and cached for the process per (grid, nev, precision):
+ * hkp_solve, hkp_solve_batch and hkp_workspace_bytes with opts->nb == 0 then
+ * use it.  seconds_out (host, ncand, may be NULL) receives each candidate's
+ * time (negated if it did not converge).  Needs workspace >=
+ * hkp_workspace_bytes(grid, opts{nb = largest candidate}, 1).  Returns
+ * HKP_OK, HKP_W_NOT_CONVERGED (no candidate converged; nothing cached) or an
+ * error. */
+int hkp_autotune_block(const hkp_grid* grid, const hkp_material* mat, const hkp_opts* opts,
+                       const double* V_eV, const double* strain, const double B_T[3],
+                       const int32_t* candidates, int32_t ncand, void* workspace,
+                       size_t ws_bytes, void* hip_stream, int32_t* nb_out,
+                       double* seconds_out);
 
 /* Thread-local message of the last error (never NULL). */
 const char* hkp_last_error(void);

@@ -10,7 +10,7 @@ in-tree libhkp.so and fails if it is missing.
 
 from ._lib import HkpError, lib  # noqa: F401
 from .api import (  # noqa: F401
-    SI, EigvalsFromPotential, SolveResult, apply, autotune, filter_step, gate_potential,
+    SI, EigvalsFromPotential, SolveResult, apply, autotune, autotune_block, filter_step, gate_potential,
     hf_grad, solve, solve_batch, workspace_bytes,
 )
 

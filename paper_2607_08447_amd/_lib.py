@@ -87,6 +87,9 @@ SIGNATURES = {
                               _P]),
     "hkp_autotune": (C.c_int, [C.POINTER(hkp_grid), C.c_int32, C.c_int32, C.c_int32, C.c_int32,
                                _P, C.c_size_t, _P, C.POINTER(hkp_tune)]),
+    "hkp_autotune_block": (C.c_int, [C.POINTER(hkp_grid), C.POINTER(hkp_material),
+                                     C.POINTER(hkp_opts), _P, _P, _D, C.POINTER(C.c_int32),
+                                     C.c_int32, _P, C.c_size_t, _P, C.POINTER(C.c_int32), _D]),
     "hkp_last_error": (C.c_char_p, []),
     "hkp_version": (C.c_int, []),
 }

@@ -245,6 +245,38 @@ def autotune(shape, h, nb, precision="fp64", with_strain=True, with_field=True):
                 gbps=t.gbps)
 
 
+def autotune_block(V, h, nev, strain=None, B=(0.0, 0.0, 0.0), candidates=None, tol=1e-8,
+                   precision="fp64", degree=0, max_iter=200, seed=1, material=None):
+    """Pick the block size by timing one complete solve of this Hamiltonian per
+    candidate (default: nev + 8, nev + 16, nev + 24, rounded up to 8, <= 64).
+    The choice is cached per (grid, nev, precision): later solve() and
+    solve_batch() calls with nb=0 use it.  Returns dict(nb=..., seconds={nb: s})."""
+    V = _dev(V, torch.float64)
+    shape = tuple(V.shape)
+    strain = _dev(strain, torch.float64)
+    g = _grid(shape, h)
+    if candidates is None:
+        candidates = sorted({min(64, (nev + d + 7) // 8 * 8) for d in (8, 16, 24)})
+        candidates = [c for c in candidates if c > nev]
+    cand = (C.c_int32 * len(candidates))(*[int(c) for c in candidates])
+    o = _opts(nev, max(candidates), degree, max_iter, tol, precision, 0, seed)
+    need = L.lib.hkp_workspace_bytes(C.byref(g), C.byref(o), 1)
+    if need == 0:
+        raise L.HkpError(L.HKP_E_ARG, L.lib.hkp_last_error().decode())
+    ws = torch.empty(need, dtype=torch.uint8, device="cuda")
+    o.nb = 0
+    nb_out = C.c_int32(0)
+    secs = (C.c_double * len(candidates))()
+    mat = _material(material)
+    code = L.lib.hkp_autotune_block(C.byref(g), C.byref(mat), C.byref(o), _ptr(V), _ptr(strain),
+                                    _B(B), cand, len(candidates), _ptr(ws), C.c_size_t(need),
+                                    _stream(), C.byref(nb_out), secs)
+    L.check(code)
+    if code != L.HKP_OK:
+        raise L.HkpError(code, L.lib.hkp_last_error().decode())
+    return dict(nb=int(nb_out.value), seconds={int(c): float(t) for c, t in zip(candidates, secs)})
+
+
 class EigvalsFromPotential(torch.autograd.Function):
     """Gate voltages -> lowest eigenvalues, with a Hellmann-Feynman backward.
 

@@ -74,7 +74,7 @@ int check_opts(const hkp_grid* g, const hkp_opts* o) {
     set_error("nev must satisfy 1 <= nev <= 6 N");
     return HKP_E_ARG;
   }
-  const int nb = o->nb > 0 ? o->nb : default_nb(o->nev, n6);
+  const int nb = block_size(*g, *o);
   if (o->nb < 0 || nb > HKP_NB_MAX || nb > n6 || nb <= o->nev) {
     set_error("block size must satisfy nev < nb <= min(64, 6 N)");
     return HKP_E_ARG;
@@ -365,6 +365,45 @@ int hkp_autotune(const hkp_grid* grid, int32_t nb, int32_t precision, int32_t wi
   return guarded([&]() {
     return run_autotune(*grid, nb, precision == HKP_PREC_MIXED, with_strain != 0,
                         with_field != 0, workspace, ws_bytes, hip_stream, out);
+  });
+}
+
+int hkp_autotune_block(const hkp_grid* grid, const hkp_material* mat, const hkp_opts* opts,
+                       const double* V_eV, const double* strain, const double B_T[3],
+                       const int32_t* candidates, int32_t ncand, void* workspace,
+                       size_t ws_bytes, void* hip_stream, int32_t* nb_out,
+                       double* seconds_out) {
+  HKP_TRY(check_grid(grid));
+  HKP_TRY(check_opts(grid, opts));
+  if (!mat || !V_eV || !B_T || !candidates || !workspace || !nb_out || ncand < 1 ||
+      ncand > 16) {
+    set_error("hkp_autotune_block: invalid arguments (1 <= ncand <= 16, pointers non-NULL)");
+    return HKP_E_ARG;
+  }
+  HKP_TRY(check_material(mat));
+  HKP_TRY(check_field(B_T));
+  const long long n6 = 6LL * grid->nx * grid->ny * grid->nz;
+  int cmax = 0;
+  for (int k = 0; k < ncand; ++k) {
+    if (candidates[k] <= opts->nev || candidates[k] > HKP_NB_MAX || candidates[k] > n6) {
+      set_error("hkp_autotune_block: every candidate must satisfy nev < nb <= min(64, 6 N)");
+      return HKP_E_ARG;
+    }
+    cmax = std::max(cmax, (int)candidates[k]);
+  }
+  {
+    hkp_opts o = *opts;
+    o.nb = cmax;
+    const size_t need = plan_bytes(make_plan(*grid, o, 1));
+    if (ws_bytes < need) {
+      set_error("workspace too small: need " + std::to_string(need) + " bytes");
+      return HKP_E_WORKSPACE;
+    }
+  }
+  HKP_TRY(check_device());
+  return guarded([&]() {
+    return run_autotune_block(*grid, *mat, *opts, V_eV, strain, B_T, candidates, ncand,
+                              workspace, ws_bytes, hip_stream, nb_out, seconds_out);
   });
 }
 

@@ -2,6 +2,7 @@
 // the caller's grid and block size with HIP events and caches the fastest per
 // (shape, nb, precision, strain, field) for the life of the process.
 #include <algorithm>
+#include <chrono>
 #include <cstdio>
 #include <cstdlib>
 #include <map>
@@ -32,7 +33,79 @@ bool forced(StencilTune* t) {
   return true;
 }
 
+// block size per (nx, ny, nz, nev, mixed), set by hkp_autotune_block
+std::map<Key, int> g_nb_cache;
+
 }  // namespace
+
+int block_size(const hkp_grid& g, const hkp_opts& o) {
+  if (o.nb > 0) return o.nb;
+  const long long n6 = 6LL * g.nx * g.ny * g.nz;
+  {
+    std::lock_guard<std::mutex> lk(g_mu);
+    auto it = g_nb_cache.find(
+        Key{g.nx, g.ny, g.nz, o.nev, o.precision == HKP_PREC_MIXED ? 1 : 0});
+    if (it != g_nb_cache.end()) return it->second;
+  }
+  return default_nb(o.nev, n6);
+}
+
+// Block size by measurement: one complete solve of the given Hamiltonian per
+// candidate (eager, outputs discarded), wall time to convergence; the fastest
+// converged candidate is cached for this grid, nev and precision.
+int run_autotune_block(const hkp_grid& g, const hkp_material& mat, const hkp_opts& o,
+                       const double* V, const double* strain, const double B[3],
+                       const int* cand, int ncand, void* ws, size_t ws_bytes, void* stream,
+                       int* nb_out, double* seconds_out) {
+  int best = 0;
+  double best_s = 1e300;
+  const char* dbg = std::getenv("HKP_TUNE_TRACE");
+  for (int k = 0; k < ncand; ++k) {
+    hkp_opts oc = o;
+    oc.nb = cand[k];
+    oc.flags &= ~(HKP_FLAG_GRAPH | HKP_FLAG_X0);
+    SolveArgs a{};
+    a.plan = make_plan(g, oc, 1);
+    if (plan_bytes(a.plan) > ws_bytes) {
+      set_error("hkp_autotune_block: workspace too small for block size " +
+                std::to_string(cand[k]));
+      return HKP_E_WORKSPACE;
+    }
+    a.mat = mat;
+    a.V = V;
+    a.strain = strain;
+    for (int i = 0; i < 3; ++i) a.B[i] = B[i];
+    a.workspace = ws;
+    a.stream = stream;
+    a.tol = oc.tol_eV;
+    a.max_iter = oc.max_iter;
+    a.flags = oc.flags;
+    a.seed = oc.seed;
+    a.st = autotuned(g, oc.nb, oc.precision == HKP_PREC_MIXED);
+    a.graph_chunk = 4;
+    const auto t0 = std::chrono::steady_clock::now();
+    const int rc = run_solve(a, nullptr);
+    const double s = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    if (rc < 0) return rc;
+    const double sc = rc == HKP_OK ? s : 1e300;   // a candidate that did not converge loses
+    if (seconds_out) seconds_out[k] = rc == HKP_OK ? s : -s;
+    if (dbg && dbg[0] == '1') std::fprintf(stderr, "[hkp tune] nb %d: %.4f s (status %d)\n", cand[k], s, rc);
+    if (sc < best_s) {
+      best_s = sc;
+      best = cand[k];
+    }
+  }
+  if (best == 0) {
+    set_error("hkp_autotune_block: no candidate converged within max_iter");
+    return HKP_W_NOT_CONVERGED;
+  }
+  {
+    std::lock_guard<std::mutex> lk(g_mu);
+    g_nb_cache[Key{g.nx, g.ny, g.nz, o.nev, o.precision == HKP_PREC_MIXED ? 1 : 0}] = best;
+  }
+  *nb_out = best;
+  return HKP_OK;
+}
 
 StencilTune autotuned(const hkp_grid& g, int nb, bool mixed) {
   StencilTune t;

@@ -470,7 +470,7 @@ Plan make_plan(const hkp_grid& g, const hkp_opts& o, int batch) {
   p.n6 = 6 * p.N;
   p.batch = batch;
   p.nev = o.nev;
-  p.nb = o.nb > 0 ? o.nb : default_nb(o.nev, p.n6);
+  p.nb = block_size(g, o);
   // degree 0: ramp 16 -> 32 -> m_max over the first outer iterations, so that
   // the amplification of the lowest components relative to the filter's cut
   // stays within the arithmetic's dynamic range while the interval settles

@@ -63,6 +63,13 @@ struct FilterArgs {
 };
 
 int default_nb(int nev, long long n6);
+// block size for opts->nb == 0: the autotuned one for this grid, nev and
+// precision if hkp_autotune_block ran in this process, else default_nb
+int block_size(const hkp_grid& g, const hkp_opts& o);
+int run_autotune_block(const hkp_grid& g, const hkp_material& mat, const hkp_opts& o,
+                       const double* V, const double* strain, const double B[3],
+                       const int* cand, int ncand, void* ws, size_t ws_bytes, void* stream,
+                       int* nb_out, double* seconds_out);
 Plan make_plan(const hkp_grid& g, const hkp_opts& o, int batch);
 size_t plan_bytes(const Plan& p);
 int run_solve(const SolveArgs& a, hkp_stats* stats);

@@ -118,3 +118,23 @@ def test_other_entry_points_validate():
     assert L.lib.hkp_hf_grad_workspace_bytes(0) == 0
     assert L.lib.hkp_hf_grad(100, 2, fake, fake, 3, fake, fake, fake, 8, None) == L.HKP_E_WORKSPACE
     assert L.lib.hkp_gate_potential(0, 1, fake, fake, fake, fake, None) == L.HKP_E_ARG
+
+
+def test_autotune_block_validates():
+    L, g, m, o = _structs()
+    fake = C.c_void_p(0x1000)
+    B = (C.c_double * 3)(0.0, 0.0, 0.0)
+    out = C.c_int32(0)
+    o.nev = 8
+    bad = (C.c_int32 * 2)(16, 8)      # 8 <= nev
+    assert L.lib.hkp_autotune_block(C.byref(g), C.byref(m), C.byref(o), fake, None, B, bad, 2,
+                                    fake, 1 << 30, None, C.byref(out), None) == L.HKP_E_ARG
+    big = (C.c_int32 * 1)(72)         # > 64
+    assert L.lib.hkp_autotune_block(C.byref(g), C.byref(m), C.byref(o), fake, None, B, big, 1,
+                                    fake, 1 << 30, None, C.byref(out), None) == L.HKP_E_ARG
+    ok = (C.c_int32 * 2)(16, 24)
+    assert L.lib.hkp_autotune_block(C.byref(g), C.byref(m), C.byref(o), fake, None, B, ok, 0,
+                                    fake, 1 << 30, None, C.byref(out), None) == L.HKP_E_ARG
+    # the workspace must hold the largest candidate's solver state
+    assert L.lib.hkp_autotune_block(C.byref(g), C.byref(m), C.byref(o), fake, None, B, ok, 2,
+                                    fake, 64, None, C.byref(out), None) == L.HKP_E_WORKSPACE

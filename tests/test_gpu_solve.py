@@ -102,3 +102,23 @@ def test_soft_locking_same_result_less_filtering(precision, tol, tol_E):
     print(f"filtered vector-steps with locking {work[0]}, without {work[1]}; "
           f"iterations {on.stats['iters']} / {off.stats['iters']}", flush=True)
     assert work[0] < work[1]
+
+
+def test_autotuned_block_size_is_used_and_correct():
+    """hkp_autotune_block times one solve per candidate block size and caches
+    the fastest; a later solve with nb = 0 runs with it and still matches the
+    oracle."""
+    import torch
+    import paper_2607_08447_amd as hkp
+    w = workload("dqd_small")
+    nev = 8
+    H = hamiltonian_ls(Grid(*w.shape, w.h), SI_MATERIAL, w.V, w.strain.reshape(-1, 6), w.B)
+    E_ref, _ = lowest_arpack(H, nev, tol=1e-13)
+    t = hkp.autotune_block(torch.from_numpy(w.V), w.h, nev, strain=torch.from_numpy(w.strain),
+                           B=w.B, candidates=[16, 24], tol=1e-9)
+    print(f"autotuned block {t}", flush=True)
+    assert t["nb"] in (16, 24) and all(s > 0 for s in t["seconds"].values())
+    assert t["seconds"][t["nb"]] == min(t["seconds"].values())
+    res = _gpu_solve(w, nev=nev, nb=0, tol=1e-9)
+    assert res.status == 0 and res.stats["nb"] == t["nb"]
+    _check_pairs(w, res, E_ref, 1e-8, 1e-9)
