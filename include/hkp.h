@@ -17,7 +17,8 @@
  *  Hole picture: H = -H_valence, so bound hole states are the LOWEST
  *  eigenvalues.
  *  Grid: interior points r = ((i+1)h, (j+1)h, (k+1)h), 0 <= i < nx, ...;
- *  psi = 0 one spacing outside the grid (hard wall).
+ *  psi = 0 one spacing outside the grid (hard wall).  nx, ny, nz >= 1 and
+ *  N = nx ny nz <= 2^31 / 6 (larger grids are rejected with HKP_E_ARG).
  *  Scalar fields (V, lever arms): double [nx][ny][nz], C order (z fastest).
  *  Strain: double [nx][ny][nz][6], symmetric tensor components in the order
  *  xx, yy, zz, yz, xz, xy (tensor, not engineering, shear).
@@ -137,6 +138,11 @@ void hkp_default_opts(hkp_opts* o);
 size_t hkp_workspace_bytes(const hkp_grid* grid, const hkp_opts* opts, int32_t batch);
 
 /* Lowest opts->nev eigenpairs of H for one potential (paper Sec. II.B).
+ * The block (opts->nb) must exceed nev by at least one degenerate cluster
+ * above the wanted states (a Kramers pair at B = 0): the filter's lower cut
+ * is the block's largest Ritz value, and a block that ends inside a
+ * degenerate level cannot separate it (the solve then returns
+ * HKP_W_NOT_CONVERGED with the best Ritz pairs found).
  *   V_eV      device double [nx][ny][nz]
  *   strain    device double [nx][ny][nz][6] or NULL (no strain)
  *   B_T       host double[3], magnetic field (T)
@@ -169,7 +175,7 @@ size_t hkp_apply_workspace_bytes(const hkp_grid* grid, int32_t nvec);
 
 /* Y = alpha (H - shift) X + beta Y_old  on nvec spinors (one Chebyshev
  * recurrence step; alpha = 1, shift = beta = 0 gives Y = H X).
- *   X, Y      device complex double [nvec][nx][ny][nz][6]
+ *   X, Y      device complex double [nvec][nx][ny][nz][6], nvec >= 1
  *   Y_old     device, same layout, or NULL when beta == 0; may alias Y
  *   precision HKP_PREC_FP64 or HKP_PREC_MIXED (operands rounded to FP32 and
  *             the stencil evaluated in FP32; result returned in FP64) */

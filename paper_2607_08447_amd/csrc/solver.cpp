@@ -511,7 +511,7 @@ int run_solve(const SolveArgs& A, hkp_stats* stats) {
   const Plan& p = c.p;
   const bool eager = !(A.flags & HKP_FLAG_GRAPH);
   const char* tr = std::getenv("HKP_TRACE");
-  const bool trace = tr && tr[0] == '1';
+  const bool trace = tr && tr[0] == '1';   // HKP_TRACE=1: per iteration; 12: also per vector
   const bool timed = eager && stats != nullptr;
   Timer t_setup(timed), t_filter(timed), t_orth(timed), t_rr(timed), t_res(timed);
   sst.timed = timed;
@@ -649,8 +649,15 @@ int run_solve(const SolveArgs& A, hkp_stats* stats) {
       if (trace) {
         double bd[4];
         HKP_CHECK(hipMemcpy(bd, c.at<double>(c.L.bounds), 32, hipMemcpyDeviceToHost));
-        std::fprintf(stderr, "[hkp] it %d nconv %d rmax %.3e a_cut %.6f a0 %.6f fp64 %d\n", iters,
-                     hflags[4], bd[3], bd[1], bd[2], hflags[1]);
+        std::fprintf(stderr, "[hkp] it %d m %d nconv %d lock %d rmax %.3e b %.6f a_cut %.6f a0 %.6f fp64 %d\n",
+                     iters, m_cur, hflags[4], hflags[6], bd[3], bd[0], bd[1], bd[2], hflags[1]);
+        if (tr[0] == '1' && tr[1] == '2') {   // HKP_TRACE=12: Ritz values and residuals
+          std::vector<double> th(p.nb), r2(p.nb);
+          HKP_CHECK(hipMemcpy(th.data(), c.at<double>(c.L.theta), p.nb * 8, hipMemcpyDeviceToHost));
+          HKP_CHECK(hipMemcpy(r2.data(), c.at<double>(c.L.r2), p.nb * 8, hipMemcpyDeviceToHost));
+          for (int j = 0; j < p.nb; ++j)
+            std::fprintf(stderr, "[hkp]   %d %.12e %.3e\n", j, th[j], std::sqrt(r2[j]));
+        }
       }
       t_filter.collect();
       t_orth.collect();

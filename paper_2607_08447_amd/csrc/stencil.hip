@@ -216,7 +216,7 @@ stencil_kernel(KArgs<T> a) {
 
   const int nx = a.nx, ny = a.ny, nz = a.nz;
   const unsigned nxy = (unsigned)nx * (unsigned)ny;
-  const unsigned N = nxy * (unsigned)nz;   // < 2^28 (checked on the host)
+  const unsigned N = nxy * (unsigned)nz;   // 6 N < 2^31 (checked on the host)
   const int lx = threadIdx.x, ly = threadIdx.y;
   // the spin is uniform across a wave (64 consecutive threads share threadIdx.z)
   const int sp = __builtin_amdgcn_readfirstlane(threadIdx.z);

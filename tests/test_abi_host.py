@@ -138,3 +138,22 @@ def test_autotune_block_validates():
     # the workspace must hold the largest candidate's solver state
     assert L.lib.hkp_autotune_block(C.byref(g), C.byref(m), C.byref(o), fake, None, B, ok, 2,
                                     fake, 64, None, C.byref(out), None) == L.HKP_E_WORKSPACE
+
+
+def test_empty_and_oversized_inputs_are_rejected():
+    L, g, m, o = _structs()
+    fake = C.c_void_p(0x1000)
+    B = (C.c_double * 3)(0.0, 0.0, 0.0)
+    # no vectors
+    assert L.lib.hkp_apply(C.byref(g), C.byref(m), fake, None, B, 0, fake, fake, 0, fake,
+                           1 << 30, None) == L.HKP_E_ARG
+    # 6 N must stay below 2^31
+    huge = L.hkp_grid(1024, 1024, 1024, 0.4)
+    o.nev = 8
+    assert L.lib.hkp_workspace_bytes(C.byref(huge), C.byref(o), 1) == 0
+    assert b"too large" in L.lib.hkp_last_error()
+    # a zero-size batch
+    o.nb = 16
+    st = L.hkp_stats()
+    assert L.lib.hkp_solve_batch(C.byref(g), C.byref(m), C.byref(o), 0, fake, None, B, fake,
+                                 None, None, fake, 1 << 30, None, C.byref(st)) == L.HKP_E_ARG

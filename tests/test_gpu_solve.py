@@ -122,3 +122,73 @@ def test_autotuned_block_size_is_used_and_correct():
     res = _gpu_solve(w, nev=nev, nb=0, tol=1e-9)
     assert res.status == 0 and res.stats["nb"] == t["nb"]
     _check_pairs(w, res, E_ref, 1e-8, 1e-9)
+
+
+def test_minimal_block_one_state():
+    """nev = 1 with the smallest block that holds a guard pair above the
+    Kramers-degenerate ground pair (nb = 4) on the harmonic well."""
+    w = workload("harmonic_10x8x8")
+    H = hamiltonian_ls(Grid(*w.shape, w.h), SI_MATERIAL, w.V)
+    E_ref, _ = lowest_dense(H, 1)
+    res = _gpu_solve(w, nev=1, nb=4, tol=1e-9)
+    assert res.status == 0
+    _check_pairs(w, res, E_ref, 1e-8, 1e-9)
+
+
+def test_block_without_guard_pair_reports_not_converged():
+    """At B = 0 every level is a Kramers pair; a block of exactly one pair
+    (nev = 1, nb = 2) puts the filter's cut on the wanted eigenvalue, so the
+    iteration cannot separate it.  The solver must say so (warning status)
+    and still return finite Ritz values and their true residuals."""
+    w = workload("harmonic_10x8x8")
+    H = hamiltonian_ls(Grid(*w.shape, w.h), SI_MATERIAL, w.V)
+    E_ref, _ = lowest_dense(H, 1)
+    res = _gpu_solve(w, nev=1, nb=2, tol=1e-9, max_iter=12)
+    assert res.status == 1   # HKP_W_NOT_CONVERGED
+    E = res.E.cpu().numpy()
+    R = res.resid.cpu().numpy()
+    assert np.isfinite(E).all() and np.isfinite(R).all()
+    assert R[0] > 1e-9
+    # the Ritz value is an upper bound within its residual of the true level
+    assert E[0] >= E_ref[0] - 1e-12 and E[0] - E_ref[0] <= R[0] + 1e-12
+
+
+def test_single_point_grid():
+    """A 1 x 1 x 1 grid: H is the 6 x 6 on-site block (kinetic centre,
+    strain, spin-orbit, Zeeman); every eigenvalue against numpy's eigh."""
+    import torch
+    import paper_2607_08447_amd as hkp
+    V = np.array([[[0.013]]])
+    e = np.array([[[[1e-3, -2e-3, 3e-3, 4e-4, -5e-4, 6e-4]]]])
+    B = (0.7, -0.4, 1.1)
+    H = hamiltonian_j(Grid(1, 1, 1, 0.5), SI_MATERIAL, V.ravel(), e.reshape(-1, 6), B).toarray()
+    E_ref = np.linalg.eigvalsh(H)[:4]
+    res = hkp.solve(torch.from_numpy(V), 0.5, 4, strain=torch.from_numpy(e), B=B, nb=6, tol=1e-9)
+    assert res.status == 0
+    assert np.abs(res.E.cpu().numpy() - E_ref).max() <= 1e-8
+    psi = res.psi.cpu().numpy().reshape(4, 6).T
+    E = res.E.cpu().numpy()
+    assert np.linalg.norm(H @ psi - psi * E[None, :], axis=0).max() <= 1e-8
+
+
+def test_largest_block():
+    """The largest block the ABI allows (nb = 64) with 48 states."""
+    from synth.inputs import build
+    w = build("fin_small", small_shape=(24, 10, 10))
+    nev = 48
+    H = hamiltonian_ls(Grid(*w.shape, w.h), SI_MATERIAL, w.V, w.strain.reshape(-1, 6), w.B)
+    E_ref, _ = lowest_arpack(H, nev, tol=1e-13)
+    res = _gpu_solve(w, nev=nev, nb=64, tol=1e-9)
+    assert res.status == 0
+    _check_pairs(w, res, E_ref, 1e-8, 1e-9)
+
+
+def test_batch_of_one_equals_single_solve():
+    import torch
+    import paper_2607_08447_amd as hkp
+    w = workload("dqd_small")
+    kw = dict(strain=torch.from_numpy(w.strain), B=w.B, nb=16, tol=1e-9)
+    rb = hkp.solve_batch(torch.from_numpy(w.V[None]), w.h, 8, graph=True, **kw)
+    r1 = hkp.solve(torch.from_numpy(w.V), w.h, 8, **kw)
+    assert rb.status == 0 and r1.status == 0
+    assert np.abs(rb.E.cpu().numpy()[0] - r1.E.cpu().numpy()).max() <= 1e-9
