@@ -23,6 +23,9 @@ SOURCES = ["stencil.hip", "fields.hip", "blas.hip", "eig.hip", "solver.cpp", "ab
 
 FLAGS = ["--offload-arch=gfx950", "-O3", "-fPIC", "-std=c++17",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+         # MFMA accumulators in VGPRs: the AGPR form made the compiler copy every
+         # loop-carried accumulator AGPR <-> VGPR around each MFMA
+         "-mllvm", "-amdgpu-mfma-vgpr-form",
          "-I", os.path.join(ROOT, "include"), "-I", SRC, "-Wall", "-Wno-unused-function",
          "-Wno-unused-variable", "-Wno-unused-but-set-variable"]
 

@@ -237,25 +237,45 @@ gram_reduce_kernel(int nchunks, int nba, int nbb, int hermitian, const int* acti
 // MFMA: M = 16 real output columns (8 output vectors: (w, re), (w, im), ...),
 // N = 16 elements, K = 4 real input columns (2 input vectors x (re, im)).
 // Each wave owns 16 consecutive elements; it loads all its X values before
-// storing, so Y may alias X.  Q lives in LDS.
+// storing, so Y may alias X.  The MFMA A operand depends only on (output
+// tile m, k-step s, lane), not on the element tile, so each workgroup first
+// lays it out in LDS as qt[m][s][lane] (signs applied, zero outside nin x
+// nout); the inner loop is then plain conflict-free LDS reads feeding MFMAs.
 // ---------------------------------------------------------------------------
 constexpr int kRotWaves = 4;
 
-template <int NBIN_MAX>
+template <int NB8>   // nin rounded up to a multiple of 8 (zero padding beyond nin, nout)
 __global__ void __launch_bounds__(64 * kRotWaves)
 rotate_kernel(const double* X, long long x_bstride, double* Y, long long y_bstride, long long n,
               int nin, int nout, const double* Q, const int* active) {
-  extern __shared__ double qs[];   // [nin][nout] complex
+  constexpr int KS = NB8 / 2;            // k-steps of 2 input vectors
+  constexpr int MT = NB8 / 8;            // M tiles of 8 output vectors
+  extern __shared__ double qt[];         // [MT][KS][64]
   const int b = blockIdx.y;
   if (active && !active[b]) return;
   const double* Qb = Q + 2 * ((long long)b * nin * nout);
-  for (int t = threadIdx.x; t < 2 * nin * nout; t += blockDim.x) qs[t] = Qb[t];
+  for (int t = threadIdx.x; t < MT * KS * 64; t += blockDim.x) {
+    const int l = t & 63, s = (t >> 6) % KS, m = (t >> 6) / KS;
+    const int rr = l & 15, qq = l >> 4;
+    // row mrow of the MFMA result lands in lane group mrow % 4, register
+    // mrow / 4; rows are ordered so that every lane ends up holding
+    // (w, re), (w, im), (w+1, re), (w+1, im)
+    const int w = m * 8 + 2 * (rr & 3) + (rr >> 3);
+    const int op = (rr >> 2) & 1;
+    const int v = 2 * s + (qq >> 1);
+    const int ip = qq & 1;
+    double a = 0.0;
+    if (v < nin && w < nout) {
+      const double qr = Qb[2 * (v * nout + w)], qi = Qb[2 * (v * nout + w) + 1];
+      // Yr += Xr Qr - Xi Qi ; Yi += Xr Qi + Xi Qr
+      a = op == 0 ? (ip == 0 ? qr : -qi) : (ip == 0 ? qi : qr);
+    }
+    qt[t] = a;
+  }
   __syncthreads();
   const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int r = lane & 15, q = lane >> 4;
-  constexpr int KS = NBIN_MAX / 2;       // k-steps of 2 input vectors
-  const int ks = (nin + 1) / 2;
-  const int mt = (nout + 7) / 8;          // M tiles of 8 output vectors
+  const int mt = (nout + 7) / 8;
   const double* xb = X + 2 * ((long long)b * x_bstride);
   double* yb = Y + 2 * ((long long)b * y_bstride);
   const long long ntile = (n + 15) / 16;
@@ -267,36 +287,15 @@ rotate_kernel(const double* X, long long x_bstride, double* Y, long long y_bstri
     double xv[KS];
 #pragma unroll
     for (int s = 0; s < KS; ++s) {
-      if (s < ks) {
-        const int v = 2 * s + (q >> 1);
-        xv[s] = (eok && v < nin) ? xb[2 * ((long long)v * n + e) + (q & 1)] : 0.0;
-      } else {
-        xv[s] = 0.0;
-      }
+      const int v = 2 * s + (q >> 1);
+      xv[s] = (eok && v < nin) ? xb[2 * ((long long)v * n + e) + (q & 1)] : 0.0;
     }
     for (int m = 0; m < mt; ++m) {
+      const double* qm = qt + m * KS * 64 + lane;
       d4 acc = d4{0, 0, 0, 0};
-      // A operand: Qhat^T[mrow][k]; row mrow of the result lands in lane
-      // group mrow % 4, register mrow / 4, so order the rows as
-      // mrow -> (w = 8m + 2 (mrow % 4) + (mrow / 8), part = (mrow / 4) % 2)
-      // and every lane ends up holding (w, re), (w, im), (w+1, re), (w+1, im)
-      const int w = m * 8 + 2 * (r & 3) + (r >> 3);
-      const int op = (r >> 2) & 1;
 #pragma unroll
-      for (int s = 0; s < KS; ++s) {
-        if (s < ks) {
-          const int v = 2 * s + (q >> 1);
-          const int ip = q & 1;
-          double a = 0.0;
-          if (v < nin && w < nout) {
-            const double qr = qs[2 * (v * nout + w)], qi = qs[2 * (v * nout + w) + 1];
-            // Yr += Xr Qr - Xi Qi ; Yi += Xr Qi + Xi Qr
-            a = op == 0 ? (ip == 0 ? qr : -qi) : (ip == 0 ? qi : qr);
-          }
-          acc = mfma(a, xv[s], acc);
-        }
-      }
-      // D[mrow][e]: lane holds rows 4 k + l/16 -> (w0, re), (w0, im), (w0+1, re), (w0+1, im)
+      for (int s = 0; s < KS; ++s) acc = mfma(qm[s * 64], xv[s], acc);
+      // D[mrow][e]: lane holds (w0, re), (w0, im), (w0+1, re), (w0+1, im)
       const int w0 = m * 8 + 2 * q;
       if (eok) {
         if (w0 < nout)
@@ -552,15 +551,22 @@ hipError_t launch_rotate(const BlockDesc& X, const BlockDesc& Y, int nin, int no
   const long long cap = 4096 / (batch > 0 ? batch : 1) + 1;
   if (g > cap) g = cap;
   dim3 grid((unsigned)g, (unsigned)batch);
-  const size_t lds = (size_t)nin * nout * 16;
-  if (nin <= 16)
-    rotate_kernel<16><<<grid, 64 * kRotWaves, lds, s>>>(X.ptr, X.bstride, Y.ptr, Y.bstride, X.n, nin, nout, Q, active);
-  else if (nin <= 32)
-    rotate_kernel<32><<<grid, 64 * kRotWaves, lds, s>>>(X.ptr, X.bstride, Y.ptr, Y.bstride, X.n, nin, nout, Q, active);
-  else if (nin <= 48)
-    rotate_kernel<48><<<grid, 64 * kRotWaves, lds, s>>>(X.ptr, X.bstride, Y.ptr, Y.bstride, X.n, nin, nout, Q, active);
-  else
-    rotate_kernel<64><<<grid, 64 * kRotWaves, lds, s>>>(X.ptr, X.bstride, Y.ptr, Y.bstride, X.n, nin, nout, Q, active);
+  // operand table [NB8/8][NB8/2][64] doubles, NB8 = nin rounded up to 8
+  const int nb8 = (nin + 7) / 8 * 8;
+  const size_t lds = (size_t)(nb8 / 8) * (nb8 / 2) * 64 * 8;
+#define HKP_ROT(NB8) rotate_kernel<NB8><<<grid, 64 * kRotWaves, lds, s>>>(X.ptr, X.bstride, Y.ptr, Y.bstride, X.n, nin, nout, Q, active)
+  switch (nb8) {
+    case 8: HKP_ROT(8); break;
+    case 16: HKP_ROT(16); break;
+    case 24: HKP_ROT(24); break;
+    case 32: HKP_ROT(32); break;
+    case 40: HKP_ROT(40); break;
+    case 48: HKP_ROT(48); break;
+    case 56: HKP_ROT(56); break;
+    case 64: HKP_ROT(64); break;
+    default: return hipErrorInvalidValue;
+  }
+#undef HKP_ROT
   return hipGetLastError();
 }
 

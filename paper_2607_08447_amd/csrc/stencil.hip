@@ -62,19 +62,6 @@ __device__ __forceinline__ cx<T> conj(cx<T> a) { return {a.r, -a.i}; }
 // i * a
 template <typename T>
 __device__ __forceinline__ cx<T> mul_i(cx<T> a) { return {-a.i, a.r}; }
-// w a - conj(w) b
-template <typename T>
-__device__ __forceinline__ cx<T> wdiff(cx<T> w, cx<T> a, cx<T> b) {
-  // w a - conj(w) b = wr (a - b) + i wi (a + b)
-  cx<T> d = sub(a, b), s = add(a, b);
-  return {fma(w.r, d.r, -w.i * s.i), fma(w.r, d.i, w.i * s.r)};
-}
-// w a + conj(w) b
-template <typename T>
-__device__ __forceinline__ cx<T> wsum(cx<T> w, cx<T> a, cx<T> b) {
-  cx<T> d = sub(a, b), s = add(a, b);
-  return {fma(w.r, s.r, -w.i * d.i), fma(w.r, s.i, w.i * d.r)};
-}
 // acc + c a + conj(c) b  (c carries a real stencil coefficient times a link phase)
 template <typename T>
 __device__ __forceinline__ cx<T> wsum_acc(cx<T> acc, cx<T> c, cx<T> a, cx<T> b) {
@@ -93,11 +80,6 @@ __device__ __forceinline__ cx<T> ld(const T* p) {
   typename V2<T>::type v = *reinterpret_cast<const typename V2<T>::type*>(p);
   return {v.x, v.y};
 }
-template <typename T>
-__device__ __forceinline__ cx<T> ldg(const void* base, long long idx) {
-  return ld(reinterpret_cast<const T*>(base) + 2 * idx);
-}
-
 template <typename TW, typename T>
 __device__ __forceinline__ void stg(void* base, long long idx, cx<T> v) {
   typename V2<TW>::type o;
