@@ -23,12 +23,13 @@ std::map<Key, StencilTune> g_cache;
 
 size_t al(size_t x) { return (x + 255) & ~(size_t)255; }
 
-// HKP_STENCIL="tile_y,vgroup,dma" forces one launch shape (tests of a variant)
+// HKP_STENCIL="tile_y,vgroup,dma[,zsplit]" forces one launch shape (tests of a variant)
 bool forced(StencilTune* t) {
   const char* e = std::getenv("HKP_STENCIL");
   if (!e || !e[0]) return false;
   StencilTune f;
-  if (std::sscanf(e, "%d,%d,%d", &f.tile_y, &f.vgroup, &f.dma) != 3) return false;
+  const int n = std::sscanf(e, "%d,%d,%d,%d", &f.tile_y, &f.vgroup, &f.dma, &f.zsplit);
+  if (n < 3) return false;
   *t = f;
   return true;
 }

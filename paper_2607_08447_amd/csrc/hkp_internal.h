@@ -81,6 +81,7 @@ struct StencilLaunch {
   int tile_y;            // 1, 2, 4
   int vgroup;            // vectors of one tile side by side (1 vector-major, nvec tile-major)
   int dma;               // 1: rows staged global -> LDS directly (needs nx % 64 == 0)
+  int zsplit;            // z ranges per (vector, tile): 0 never, 1 for small launches, 2 always
   int fp64;              // kernel type
 };
 

@@ -254,6 +254,7 @@ StencilLaunch base_launch(const Ctx& c, bool fp64, int nvec) {
   a.tile_y = c.p.st.tile_y;
   a.vgroup = c.p.st.vgroup;
   a.dma = c.p.st.dma;
+  a.zsplit = c.p.st.zsplit;
   a.fp64 = fp64;
   a.coef.coef = nullptr;
   a.coef.alpha = 1.0;
@@ -813,6 +814,7 @@ int run_filter_step(const FilterArgs& A) {
   a.tile_y = A.st.tile_y;
   a.vgroup = A.st.vgroup;
   a.dma = A.st.dma;
+  a.zsplit = A.st.zsplit;
   a.fp64 = fp64;
   HKP_CHECK(launch_stencil(a, make_consts(A.mat, g.h_nm, A.B), s));
   HKP_CHECK(launch_internal_to_abi(g.nx, g.ny, g.nz, g.h_nm, A.B, A.nvec, 1, Yi, 0, A.Y, 0, s));

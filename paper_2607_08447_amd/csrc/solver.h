@@ -13,6 +13,7 @@ struct StencilTune {
   int tile_y = 4;
   int vgroup = 1;
   int dma = 0;
+  int zsplit = 1;   // 0 never, 1 when a launch has few live workgroups, 2 always
 };
 
 struct Plan {

@@ -25,6 +25,9 @@
 // is complete after plane z has been pushed and is written straight to HBM
 // (alpha, beta and the old block fused in).  Workgroups are mapped to XCDs in
 // contiguous runs so that the vectors of one tile share an L2.
+#include <map>
+#include <mutex>
+
 #include "hkp_internal.h"
 
 namespace hkp {
@@ -115,6 +118,7 @@ struct KArgs {
   const int* lock;
   const int* work;
   int batch;
+  int zsplit, split_below;
   int nx, ny, nz, nvec;
   int tiles_x, tiles_y;
   int vgroup;   // vectors of one tile run side by side (1: vector-major)
@@ -166,12 +170,21 @@ stencil_kernel(KArgs<T> a) {
   // so the halo rows they share hit in L2).  vgroup = 1 is vector-major order,
   // vgroup = nvec tile-major order.  With a work table the order runs over the
   // live (virtual) vectors of all members and the rest of the grid exits.
-  int b, vec, tile;
+  // Launches with few live workgroups (locked vectors, converged members,
+  // small grids) split every (vector, tile) into zs z-ranges so that more
+  // workgroups share the chip; a range recomputes one plane on each side.
+  // The grid holds zsplit x the unsplit count; the split is decided from the
+  // live count, uniformly for the whole launch.
+  int b, vec, tile, zs = 1, zc = 0;
   if (a.work) {
     const int nv = a.work[a.batch];
-    const int nlive = nv * ntiles;
+    const int nlw = nv * ntiles;
+    if (a.zsplit > 1 && nlw < a.split_below && a.nz >= 8) zs = a.zsplit;
+    const int nlive = nlw * zs;
     if ((int)blockIdx.x >= nlive) return;
-    const int logical = xcd_remap(blockIdx.x, nlive);
+    int logical = xcd_remap(blockIdx.x, nlive);
+    zc = logical / nlw;   // z range outermost: one range of all tiles per XCD run
+    logical -= zc * nlw;
     const int g = logical / (a.vgroup * ntiles);
     const int within = logical - g * a.vgroup * ntiles;
     const int gsize = min(a.vgroup, nv - g * a.vgroup);
@@ -181,7 +194,13 @@ stencil_kernel(KArgs<T> a) {
     while (a.work[b + 1] <= u) ++b;
     vec = (a.lock ? a.lock[b] : 0) + (u - a.work[b]);
   } else {
-    const int logical = xcd_remap(blockIdx.x, gridDim.x);
+    const int nlw = (int)gridDim.x / a.zsplit;
+    if (a.zsplit > 1 && nlw < a.split_below && a.nz >= 8) zs = a.zsplit;
+    const int nlive = nlw * zs;
+    if ((int)blockIdx.x >= nlive) return;
+    int logical = xcd_remap(blockIdx.x, nlive);
+    zc = logical / nlw;
+    logical -= zc * nlw;
     const int per_b = ntiles * a.nvec;
     b = logical / per_b;
     const int r = logical - b * per_b;
@@ -197,6 +216,9 @@ stencil_kernel(KArgs<T> a) {
   const int ty0 = (tile / a.tiles_x) * TY;
 
   const int nx = a.nx, ny = a.ny, nz = a.nz;
+  // output planes [o0, o1) of this range; input planes p0..p1 feed them
+  const int o0 = (zc * nz) / zs, o1 = ((zc + 1) * nz) / zs;
+  const int p0 = o0 > 0 ? o0 - 1 : 0, p1 = o1 < nz ? o1 : nz - 1;
   const unsigned nxy = (unsigned)nx * (unsigned)ny;
   const unsigned N = nxy * (unsigned)nz;   // 6 N < 2^31 (checked on the host)
   const int lx = threadIdx.x, ly = threadIdx.y;
@@ -350,14 +372,16 @@ stencil_kernel(KArgs<T> a) {
   const int xcp = gxc + 1 < nx ? gxc + 1 : gxc, xcm = gxc > 0 ? gxc - 1 : 0;
   cx<T> pw[3], pv[3], pvxp, pvxm;
   if constexpr (PH != 0) {
-    const int z1 = nz > 1 ? 1 : 0;
-    pw[0] = pw[1] = ld(a.wtab);
+    const int zm = p0 > 0 ? p0 - 1 : 0, z1 = p0 + 1 < nz ? p0 + 1 : nz - 1;
+    pw[0] = ld(a.wtab + 2 * zm);
+    pw[1] = ld(a.wtab + 2 * p0);
     pw[2] = ld(a.wtab + 2 * z1);
-    pv[0] = pv[1] = ld(a.vtab + 2 * xc);
+    pv[0] = ld(a.vtab + 2 * (zm * nx + xc));
+    pv[1] = ld(a.vtab + 2 * (p0 * nx + xc));
     pv[2] = ld(a.vtab + 2 * (z1 * nx + xc));
     if constexpr (PH == 2) {
-      pvxp = ld(a.vtab + 2 * xcp);
-      pvxm = ld(a.vtab + 2 * xcm);
+      pvxp = ld(a.vtab + 2 * (p0 * nx + xcp));
+      pvxm = ld(a.vtab + 2 * (p0 * nx + xcm));
     }
   }
 
@@ -370,7 +394,7 @@ stencil_kernel(KArgs<T> a) {
     for (int i = 0; i < ND; ++i) d[i] = D[(unsigned)i * N + pz];
   };
   T cd[ND];
-  load_d(0, cd);
+  load_d(p0, cd);
 
   auto step = [&](int z, auto BUF) {
     constexpr int cur = decltype(BUF)::value;
@@ -395,10 +419,10 @@ stencil_kernel(KArgs<T> a) {
     constexpr bool late = sizeof(T) == 4;
     T nd[ND];
     load_d(z + 1 < nz ? z + 1 : z, nd);
-    if (z >= 1) load_old(z - 1);
+    if (z - 1 >= o0) load_old(z - 1);
     cx<T> nxt[DMA ? 1 : NS][6];
     cx<T> hv = mk<T>(0, 0);
-    const bool more = z + 1 < nz;
+    const bool more = z + 1 <= p1;
     if constexpr (!DMA) {
       if (more) {
         fetch(z + 1, nxt);
@@ -551,7 +575,7 @@ stencil_kernel(KArgs<T> a) {
       acc1[2] = add(acc1[2], r2v);
     }
 
-    if (z >= 1) finalize(z - 1);
+    if (z - 1 >= o0) finalize(z - 1);
     if constexpr (DMA) {
       if (more) halo_commit(hv, IC<1 - cur>{});
     } else if constexpr (late) {
@@ -586,20 +610,44 @@ stencil_kernel(KArgs<T> a) {
       lds1[i] = mk<T>(0, 0);
     }
     __syncthreads();
-    halo_commit(halo_load(0), IC<0>{});
-    dma_plane(0, IC<0>{});
+    halo_commit(halo_load(p0), IC<0>{});
+    dma_plane(p0, IC<0>{});
   } else {
     cx<T> first[NS][6];
-    fetch(0, first);
+    fetch(p0, first);
     commit(first, IC<0>{});
   }
   __syncthreads();
-  for (int z = 0; z < nz; z += 2) {
+  for (int z = p0; z <= p1; z += 2) {
     step(z, IC<0>{});
-    if (z + 1 < nz) step(z + 1, IC<1>{});
+    if (z + 1 <= p1) step(z + 1, IC<1>{});
   }
-  load_old(nz - 1);
-  finalize(nz - 1);
+  if (o1 == nz) {   // the last plane has no successor to complete it
+    load_old(nz - 1);
+    finalize(nz - 1);
+  }
+}
+
+// workgroups of this kernel resident on the whole device at once (occupancy
+// query, cached per kernel)
+template <typename K>
+int resident_workgroups(K kernel, int threads) {
+  static std::mutex mu;
+  static std::map<const void*, int> cache;
+  const void* key = reinterpret_cast<const void*>(kernel);
+  std::lock_guard<std::mutex> lk(mu);
+  auto it = cache.find(key);
+  if (it != cache.end()) return it->second;
+  int per_cu = 0, dev = 0, cus = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, threads, 0) != hipSuccess ||
+      hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) {
+    (void)hipGetLastError();
+    return 0;   // unknown: never split
+  }
+  const int r = per_cu * cus;
+  cache[key] = r;
+  return r;
 }
 
 template <typename T, typename TO, typename TW, int PH, bool STR>
@@ -635,21 +683,29 @@ hipError_t launch_t(const StencilLaunch& L, const StencilConsts<double>& c, hipS
   a.tiles_y = (L.ny + ty - 1) / ty;
   const long long nwg = (long long)a.tiles_x * a.tiles_y * L.nvec * L.batch;
   if (nwg <= 0) return hipSuccess;
-  if (nwg > 0x7fffffffLL) return hipErrorInvalidValue;
-  dim3 grid((unsigned)nwg);
+  // z split: 0 never, 1 when fewer live workgroups than three resident waves,
+  // 2 always (tests)
+  a.zsplit = L.zsplit > 0 ? 2 : 1;
+  if (nwg * a.zsplit > 0x7fffffffLL) return hipErrorInvalidValue;
+  dim3 grid((unsigned)(nwg * a.zsplit));
+  auto go = [&](auto kernel, dim3 block) {
+    a.split_below = L.zsplit >= 2 ? 0x7fffffff
+                  : (L.zsplit == 1 ? 3 * resident_workgroups(kernel, (int)(block.x * block.y * block.z)) : 0);
+    kernel<<<grid, block, 0, s>>>(a);
+  };
   if (L.dma && L.nx % 64 == 0) {
     switch (ty) {
-      case 1: stencil_kernel<T, TO, TW, PH, STR, 1, true><<<grid, dim3(64, 1, 2), 0, s>>>(a); break;
-      case 2: stencil_kernel<T, TO, TW, PH, STR, 2, true><<<grid, dim3(64, 2, 2), 0, s>>>(a); break;
-      case 4: stencil_kernel<T, TO, TW, PH, STR, 4, true><<<grid, dim3(64, 4, 2), 0, s>>>(a); break;
+      case 1: go(stencil_kernel<T, TO, TW, PH, STR, 1, true>, dim3(64, 1, 2)); break;
+      case 2: go(stencil_kernel<T, TO, TW, PH, STR, 2, true>, dim3(64, 2, 2)); break;
+      case 4: go(stencil_kernel<T, TO, TW, PH, STR, 4, true>, dim3(64, 4, 2)); break;
       default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
   }
   switch (ty) {
-    case 1: stencil_kernel<T, TO, TW, PH, STR, 1, false><<<grid, dim3(64, 1, 2), 0, s>>>(a); break;
-    case 2: stencil_kernel<T, TO, TW, PH, STR, 2, false><<<grid, dim3(64, 2, 2), 0, s>>>(a); break;
-    case 4: stencil_kernel<T, TO, TW, PH, STR, 4, false><<<grid, dim3(64, 4, 2), 0, s>>>(a); break;
+    case 1: go(stencil_kernel<T, TO, TW, PH, STR, 1, false>, dim3(64, 1, 2)); break;
+    case 2: go(stencil_kernel<T, TO, TW, PH, STR, 2, false>, dim3(64, 2, 2)); break;
+    case 4: go(stencil_kernel<T, TO, TW, PH, STR, 4, false>, dim3(64, 4, 2)); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();

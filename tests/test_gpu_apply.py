@@ -99,25 +99,29 @@ def test_apply_full_size_sampled_rows():
     assert err < 1e-13
 
 
-VARIANTS = [(ty, vg, dma) for dma in (0, 1) for vg in (1, 2, 4) for ty in (1, 2, 4)]
+VARIANTS = [(ty, vg, dma, zs) for zs in (0, 2) for dma in (0, 1) for vg in (1, 2, 4)
+            for ty in (1, 2, 4)]
 VARIANT_SHAPES = [
-    # x spans whole 64-wide tiles (the row-DMA variant applies); y ragged for every tile height
+    # x spans whole 64-wide tiles (the row-DMA variant applies); y ragged for every tile
+    # height; nz >= 8 on two grids so that a forced z split takes effect (odd and even nz)
     ((128, 7, 5), 0.4, True, (0.5, 0.0, 0.0)),
-    ((64, 9, 4), 0.5, True, (0.7, -1.1, 0.9)),
-    ((192, 3, 3), 0.4, False, (0.0, 0.0, 0.0)),
+    ((64, 9, 11), 0.5, True, (0.7, -1.1, 0.9)),
+    ((192, 3, 8), 0.4, False, (0.0, 0.0, 0.0)),
 ]
 
 
-@pytest.mark.parametrize("ty,vg,dma", VARIANTS, ids=[f"ty{v[0]}_g{v[1]}_dma{v[2]}" for v in VARIANTS])
+@pytest.mark.parametrize("ty,vg,dma,zs", VARIANTS,
+                         ids=[f"ty{v[0]}_g{v[1]}_dma{v[2]}_z{v[3]}" for v in VARIANTS])
 @pytest.mark.parametrize("precision,tol", [("fp64", 1e-13), ("mixed", 3e-6)])
-def test_stencil_launch_variants(ty, vg, dma, precision, tol, monkeypatch):
-    """Every launch shape the autotuner may pick (tile height, vectors per tile
-    group -- 3 vectors, so groups of 2 leave a ragged last group and 4 clamps to
-    tile-major -- and global->LDS row staging) gives the oracle's
+def test_stencil_launch_variants(ty, vg, dma, zs, precision, tol, monkeypatch):
+    """Every launch shape the stencil may run with (tile height, vectors per
+    tile group -- 3 vectors, so groups of 2 leave a ragged last group and 4
+    clamps to tile-major --, global->LDS row staging, and the split of each
+    column march into two z ranges) gives the oracle's
     alpha (H - shift) X + beta Y_old."""
     import torch
     import paper_2607_08447_amd as hkp
-    monkeypatch.setenv("HKP_STENCIL", f"{ty},{vg},{dma}")
+    monkeypatch.setenv("HKP_STENCIL", f"{ty},{vg},{dma},{zs}")
     for k, (shape, h, strain, B) in enumerate(VARIANT_SHAPES):
         V, e = _fields(shape, h, strain, 10 + k)
         N = int(np.prod(shape))
@@ -125,7 +129,8 @@ def test_stencil_launch_variants(ty, vg, dma, precision, tol, monkeypatch):
         X = random_block(N * 6, nvec, seed=20 + k)
         Yold = random_block(N * 6, nvec, seed=30 + k)
         alpha, shift, beta = 0.6, 1.3, -0.5
-        print(f"variant ty {ty} vgroup {vg} dma {dma} {precision} shape {shape}", flush=True)
+        print(f"variant ty {ty} vgroup {vg} dma {dma} zsplit {zs} {precision} shape {shape}",
+              flush=True)
         Y = hkp.filter_step(torch.from_numpy(V), h,
                             torch.from_numpy(X.reshape((nvec,) + shape + (6,))),
                             torch.from_numpy(Yold.reshape((nvec,) + shape + (6,))), alpha, shift,
