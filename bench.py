@@ -148,8 +148,9 @@ def copy_bandwidth(torch, nbytes=2 << 30, reps=5):
 
 
 def sweep_measure(torch, hkp, workload):
-    """Barrier sweep: 64 Hamiltonians batched (mixed, one hipGraph) vs a loop
-    of FP64 solves over 8 of them (evenly spaced), both to residual 1e-5 eV.
+    """Barrier sweep: 64 Hamiltonians batched (mixed, one hipGraph), the same
+    by continuation (solve_sweep), and a loop of FP64 solves over 8 of them
+    (evenly spaced), all to residual 1e-5 eV.
     Block size and stencil launch shape are autotuned on the first member."""
     w = workload("sweep64_dqd_192x40x40")
     V = torch.from_numpy(w.V).cuda()
@@ -166,6 +167,11 @@ def sweep_measure(torch, hkp, workload):
     rb = hkp.solve_batch(V, w.h, w.nev, precision="mixed", graph=True, **kw)
     torch.cuda.synchronize()
     t_batch = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    rc = hkp.solve_sweep(V, w.h, w.nev, precision="mixed", graph=True, stride=8, **kw)
+    torch.cuda.synchronize()
+    t_cont = time.perf_counter() - t0
+    err_cont = float((rc.E - rb.E).abs().max())
     idx = list(range(0, 64, 9))
     t0 = time.perf_counter()
     errs = []
@@ -181,7 +187,10 @@ def sweep_measure(torch, hkp, workload):
             "s_per_hamiltonian_looped_fp64": round(t_loop, 5),
             "looped_sample": f"{len(idx)} of 64 (indices {idx[0]}..{idx[-1]} step 9)",
             "speedup": round(t_loop / (t_batch / 64), 3),
-            "status_batched": rb.status,
+            "s_per_hamiltonian_continuation_mixed_graph": round(t_cont / 64, 5),
+            "continuation": "every 8th member cold, the rest from the nearest one's psi",
+            "max_abs_dE_continuation_vs_batched_eV": err_cont,
+            "status_batched": rb.status, "status_continuation": rc.status,
             "max_abs_dE_batched_vs_looped_eV": max(errs)}
 
 

@@ -67,6 +67,9 @@ extern "C" {
 #define HKP_FLAG_GRAPH 2        /* record outer iterations once in a hipGraph and replay */
 #define HKP_FLAG_NO_FP64_POLISH 4 /* mixed: never switch the filter to FP64 */
 #define HKP_FLAG_NO_LOCK 8      /* filter every vector of the block, converged or not */
+#define HKP_FLAG_X0_NEV 16      /* with HKP_FLAG_X0: X0 holds nev vectors per member (a
+                                 * previous solve's psi); the block's other nb - nev
+                                 * vectors are drawn at random from the seed */
 
 /* Grid: nx, ny, nz >= 1 points, spacing h (nm) > 0. */
 typedef struct {
@@ -147,7 +150,10 @@ size_t hkp_workspace_bytes(const hkp_grid* grid, const hkp_opts* opts, int32_t b
  *   strain    device double [nx][ny][nz][6] or NULL (no strain)
  *   B_T       host double[3], magnetic field (T)
  *   X0        device complex double [nb][nx][ny][nz][6] used when
- *             opts->flags & HKP_FLAG_X0, else ignored (may be NULL)
+ *             opts->flags & HKP_FLAG_X0, else ignored (may be NULL);
+ *             [nev][nx][ny][nz][6] with HKP_FLAG_X0_NEV as well (restart
+ *             from a neighbouring solve's psi, as between the iterations
+ *             of a Schroedinger-Poisson loop, Fig. 2a)
  *   eig_eV    device double [nev], ascending
  *   psi       device complex double [nev][nx][ny][nz][6] (may be NULL)
  *   resid_eV  device double [nev], ||H psi_n - E_n psi_n||_2 (may be NULL)
@@ -160,15 +166,18 @@ int hkp_solve(const hkp_grid* grid, const hkp_material* mat, const hkp_opts* opt
               void* workspace, size_t ws_bytes, void* hip_stream, hkp_stats* stats);
 
 /* The same for `batch` Hamiltonians that differ only in the potential (a
- * gate-voltage sweep, Fig. 2f): V_eV is [batch][nx][ny][nz]; eig_eV
- * [batch][nev], psi [batch][nev][nx][ny][nz][6], resid_eV [batch][nev].
+ * gate-voltage sweep, Fig. 2f): V_eV is [batch][nx][ny][nz]; X0 (with
+ * HKP_FLAG_X0) [batch][nb][nx][ny][nz][6], or [batch][nev][nx][ny][nz][6]
+ * with HKP_FLAG_X0_NEV; eig_eV [batch][nev], psi
+ * [batch][nev][nx][ny][nz][6], resid_eV [batch][nev]; batch <= 65535.
  * Every kernel of an outer iteration covers the whole batch in one launch;
  * with HKP_FLAG_GRAPH the iterations are recorded once as a hipGraph and
  * replayed, converged members turning into no-ops on the device. */
 int hkp_solve_batch(const hkp_grid* grid, const hkp_material* mat, const hkp_opts* opts,
                     int32_t batch, const double* V_eV, const double* strain,
-                    const double B_T[3], double* eig_eV, void* psi, double* resid_eV,
-                    void* workspace, size_t ws_bytes, void* hip_stream, hkp_stats* stats);
+                    const double B_T[3], const void* X0, double* eig_eV, void* psi,
+                    double* resid_eV, void* workspace, size_t ws_bytes, void* hip_stream,
+                    hkp_stats* stats);
 
 /* Workspace of hkp_apply / hkp_filter_step for nvec vectors. */
 size_t hkp_apply_workspace_bytes(const hkp_grid* grid, int32_t nvec);

@@ -25,6 +25,7 @@ HKP_FLAG_X0 = 1
 HKP_FLAG_GRAPH = 2
 HKP_FLAG_NO_FP64_POLISH = 4
 HKP_FLAG_NO_LOCK = 8
+HKP_FLAG_X0_NEV = 16
 
 
 class hkp_grid(C.Structure):
@@ -74,7 +75,7 @@ SIGNATURES = {
                             C.POINTER(hkp_stats)]),
     "hkp_solve_batch": (C.c_int, [C.POINTER(hkp_grid), C.POINTER(hkp_material),
                                   C.POINTER(hkp_opts), C.c_int32, _P, _P, _D, _P, _P, _P, _P,
-                                  C.c_size_t, _P, C.POINTER(hkp_stats)]),
+                                  _P, C.c_size_t, _P, C.POINTER(hkp_stats)]),
     "hkp_apply_workspace_bytes": (C.c_size_t, [C.POINTER(hkp_grid), C.c_int32]),
     "hkp_filter_step": (C.c_int, [C.POINTER(hkp_grid), C.POINTER(hkp_material), _P, _P, _D,
                                   C.c_int32, _P, _P, _P, C.c_double, C.c_double, C.c_double,

@@ -88,20 +88,41 @@ def workspace_bytes(shape, h, nev, nb=0, degree=0, precision="fp64", batch=1):
     return int(n)
 
 
+def _x0(X0, lead, nev, nb, shape):
+    """Initial-block flags and block size for X0 of shape lead + [k, nx, ny, nz, 6]:
+    k = nev is a previous solve's psi (the rest of the block drawn at random),
+    any other k is the whole block (nb = k)."""
+    X0d = _dev(X0, torch.complex128)
+    if X0d is None:
+        return None, 0, nb
+    if X0d.dim() != len(lead) + 5 or tuple(X0d.shape[:len(lead)]) != lead \
+            or tuple(X0d.shape[len(lead) + 1:]) != shape + (6,):
+        raise ValueError(f"X0 must be {list(lead)} + [nev or nb, nx, ny, nz, 6]")
+    k = X0d.shape[len(lead)]
+    if k == nev:
+        return X0d, L.HKP_FLAG_X0 | L.HKP_FLAG_X0_NEV, nb
+    if nb and k != nb:
+        raise ValueError(f"X0 holds {k} vectors: nev ({nev}) or nb ({nb}) expected")
+    return X0d, L.HKP_FLAG_X0, k
+
+
 def solve(V, h, nev, strain=None, B=(0.0, 0.0, 0.0), nb=0, degree=0, tol=1e-8,
           precision="fp64", max_iter=200, seed=1, X0=None, graph=False, material=None,
           return_psi=True, workspace=None, polish=True, lock=True):
     """Lowest `nev` eigenpairs of H for the potential V (float64 [nx, ny, nz], eV).
 
-    lock=False filters every vector of the block in every iteration (no soft
-    locking of converged Kramers pairs)."""
+    X0 (optional, complex128): the whole initial block [nb, nx, ny, nz, 6], or
+    [nev, nx, ny, nz, 6] -- a previous solve's psi -- completed with random
+    vectors.  lock=False filters every vector of the block in every iteration
+    (no soft locking of converged Kramers pairs)."""
     V = _dev(V, torch.float64)
     shape = tuple(V.shape)
     if len(shape) != 3:
         raise ValueError("V must be [nx, ny, nz]")
     strain = _dev(strain, torch.float64)
     g = _grid(shape, h)
-    flags = (L.HKP_FLAG_GRAPH if graph else 0) | (L.HKP_FLAG_X0 if X0 is not None else 0)
+    X0d, xflags, nb = _x0(X0, (), nev, nb, shape)
+    flags = (L.HKP_FLAG_GRAPH if graph else 0) | xflags
     if not polish:
         flags |= L.HKP_FLAG_NO_FP64_POLISH
     if not lock:
@@ -117,7 +138,6 @@ def solve(V, h, nev, strain=None, B=(0.0, 0.0, 0.0), nb=0, degree=0, tol=1e-8,
     R = torch.empty(nev, dtype=torch.float64, device="cuda")
     psi = torch.empty((nev,) + shape + (6,), dtype=torch.complex128, device="cuda") \
         if return_psi else None
-    X0d = _dev(X0, torch.complex128)
     st = L.hkp_stats()
     stream_ctx = torch.cuda.Stream() if graph else None
     mat = _material(material)
@@ -138,8 +158,9 @@ def solve(V, h, nev, strain=None, B=(0.0, 0.0, 0.0), nb=0, degree=0, tol=1e-8,
 
 def solve_batch(V, h, nev, strain=None, B=(0.0, 0.0, 0.0), nb=0, degree=0, tol=1e-8,
                 precision="fp64", max_iter=200, seed=1, graph=True, material=None,
-                return_psi=False, workspace=None, polish=True, lock=True):
-    """Lowest eigenpairs of `batch` Hamiltonians differing in V ([batch, nx, ny, nz])."""
+                return_psi=False, workspace=None, polish=True, lock=True, X0=None):
+    """Lowest eigenpairs of `batch` Hamiltonians differing in V ([batch, nx, ny, nz]).
+    X0 (optional, complex128): [batch, nb or nev, nx, ny, nz, 6], as in solve()."""
     V = _dev(V, torch.float64)
     if V.dim() != 4:
         raise ValueError("V must be [batch, nx, ny, nz]")
@@ -147,7 +168,8 @@ def solve_batch(V, h, nev, strain=None, B=(0.0, 0.0, 0.0), nb=0, degree=0, tol=1
     shape = tuple(V.shape[1:])
     strain = _dev(strain, torch.float64)
     g = _grid(shape, h)
-    flags = L.HKP_FLAG_GRAPH if graph else 0
+    X0d, xflags, nb = _x0(X0, (batch,), nev, nb, shape)
+    flags = (L.HKP_FLAG_GRAPH if graph else 0) | xflags
     if not polish:
         flags |= L.HKP_FLAG_NO_FP64_POLISH
     if not lock:
@@ -169,11 +191,56 @@ def solve_batch(V, h, nev, strain=None, B=(0.0, 0.0, 0.0), nb=0, degree=0, tol=1
     s.wait_stream(torch.cuda.current_stream())
     with torch.cuda.stream(s):
         code = L.lib.hkp_solve_batch(C.byref(g), C.byref(mat), C.byref(o), batch, _ptr(V),
-                                     _ptr(strain), _B(B), _ptr(E), _ptr(psi), _ptr(R), _ptr(ws),
-                                     C.c_size_t(ws.numel()), _stream(s), C.byref(st))
+                                     _ptr(strain), _B(B), _ptr(X0d), _ptr(E), _ptr(psi), _ptr(R),
+                                     _ptr(ws), C.c_size_t(ws.numel()), _stream(s),
+                                     C.byref(st))
     torch.cuda.current_stream().wait_stream(s)
     L.check(code)
     return SolveResult(E, psi, R, st.as_dict(), code)
+
+
+def solve_sweep(V, h, nev, strain=None, B=(0.0, 0.0, 0.0), nb=0, degree=0, tol=1e-8,
+                precision="fp64", max_iter=200, seed=1, stride=8, graph=True, material=None,
+                return_psi=False, polish=True, lock=True):
+    """A sweep solved by continuation: the members 0, stride, 2 stride, ... in one
+    batched solve from random blocks, then every other member in a second
+    batched solve started from the nearest of those members' eigenvectors
+    (adjacent sweep points have close eigenvectors, so fewer filter passes are
+    needed).  Same arguments and result layout as solve_batch."""
+    V = _dev(V, torch.float64)
+    if V.dim() != 4:
+        raise ValueError("V must be [batch, nx, ny, nz]")
+    if stride < 1:
+        raise ValueError("stride must be >= 1")
+    batch = V.shape[0]
+    kw = dict(strain=strain, B=B, nb=nb, degree=degree, tol=tol, precision=precision,
+              max_iter=max_iter, seed=seed, graph=graph, material=material, polish=polish,
+              lock=lock)
+    anchors = list(range(0, batch, stride))
+    rest = [i for i in range(batch) if i % stride]
+    ra = solve_batch(V[anchors], h, nev, return_psi=True, **kw)
+    E = torch.empty((batch, nev), dtype=torch.float64, device="cuda")
+    R = torch.empty_like(E)
+    psi = torch.empty((batch,) + ra.psi.shape[1:], dtype=torch.complex128, device="cuda") \
+        if return_psi else None
+    ia = torch.tensor(anchors, device="cuda")
+    E[ia], R[ia] = ra.E, ra.resid
+    if psi is not None:
+        psi[ia] = ra.psi
+    stats = {"anchors": ra.stats}
+    status = ra.status
+    if rest:
+        near = [min(round(i / stride), len(anchors) - 1) for i in rest]
+        X0 = ra.psi[torch.tensor(near, device="cuda")]
+        rr = solve_batch(V[rest], h, nev, X0=X0, return_psi=return_psi, **kw)
+        ir = torch.tensor(rest, device="cuda")
+        E[ir], R[ir] = rr.E, rr.resid
+        if psi is not None:
+            psi[ir] = rr.psi
+        stats["rest"] = rr.stats
+        status = max(status, rr.status)
+    del ra
+    return SolveResult(E, psi, R, stats, status)
 
 
 def filter_step(V, h, X, Y_old=None, alpha=1.0, shift=0.0, beta=0.0, strain=None,

@@ -133,16 +133,16 @@ int solve_common(const hkp_grid* grid, const hkp_material* mat, const hkp_opts* 
   HKP_TRY(check_material(mat));
   HKP_TRY(check_field(B));
   HKP_TRY(check_opts(grid, opts));
-  if (batch < 1) {
-    set_error("batch must be >= 1");
+  if (batch < 1 || batch > 65535) {
+    set_error("batch must be in 1..65535");
     return HKP_E_ARG;
   }
   if (!V || !eig || !ws) {
     set_error("V, eig_eV and workspace must not be NULL");
     return HKP_E_ARG;
   }
-  if ((opts->flags & HKP_FLAG_X0) && (!X0 || batch != 1)) {
-    set_error("HKP_FLAG_X0 needs X0 and batch == 1");
+  if ((opts->flags & HKP_FLAG_X0) && !X0) {
+    set_error("HKP_FLAG_X0 needs X0");
     return HKP_E_ARG;
   }
   if ((opts->flags & HKP_FLAG_GRAPH) && stream == nullptr) {
@@ -213,8 +213,8 @@ void hkp_default_opts(hkp_opts* o) {
 
 size_t hkp_workspace_bytes(const hkp_grid* grid, const hkp_opts* opts, int32_t batch) {
   if (check_grid(grid) != HKP_OK || check_opts(grid, opts) != HKP_OK) return 0;
-  if (batch < 1) {
-    set_error("batch must be >= 1");
+  if (batch < 1 || batch > 65535) {
+    set_error("batch must be in 1..65535");
     return 0;
   }
   return plan_bytes(make_plan(*grid, *opts, batch));
@@ -230,13 +230,9 @@ int hkp_solve(const hkp_grid* grid, const hkp_material* mat, const hkp_opts* opt
 
 int hkp_solve_batch(const hkp_grid* grid, const hkp_material* mat, const hkp_opts* opts,
                     int32_t batch, const double* V_eV, const double* strain, const double B_T[3],
-                    double* eig_eV, void* psi, double* resid_eV, void* workspace,
-                    size_t ws_bytes, void* hip_stream, hkp_stats* stats) {
-  if (opts && (opts->flags & HKP_FLAG_X0)) {
-    set_error("hkp_solve_batch takes no initial block");
-    return HKP_E_ARG;
-  }
-  return solve_common(grid, mat, opts, batch, V_eV, strain, B_T, nullptr, eig_eV, psi, resid_eV,
+                    const void* X0, double* eig_eV, void* psi, double* resid_eV,
+                    void* workspace, size_t ws_bytes, void* hip_stream, hkp_stats* stats) {
+  return solve_common(grid, mat, opts, batch, V_eV, strain, B_T, X0, eig_eV, psi, resid_eV,
                       workspace, ws_bytes, hip_stream, stats);
 }
 

@@ -255,14 +255,24 @@ hipError_t launch_abi_to_internal(int nx, int ny, int nz, double h, const double
                                   int nvec, const void* abi, void* internal, int to_fp32,
                                   hipStream_t s) {
   const long long N = (long long)nx * ny * nz;
-  dim3 grid((unsigned)((N + 255) / 256), (unsigned)nvec);
-  if (to_fp32)
-    abi_to_internal_kernel<float><<<grid, 256, 0, s>>>(
-        nx, ny, nz, h, B[0], B[1], B[2], (const double2*)abi, (float*)internal);
-  else
-    abi_to_internal_kernel<double><<<grid, 256, 0, s>>>(
-        nx, ny, nz, h, B[0], B[1], B[2], (const double2*)abi, (double*)internal);
-  return hipGetLastError();
+  // vectors in chunks: the grid's y extent stays within the launch limit
+  constexpr int kChunk = 32768;
+  for (int v0 = 0; v0 < nvec; v0 += kChunk) {
+    const int nv = nvec - v0 < kChunk ? nvec - v0 : kChunk;
+    const long long off = (long long)v0 * N * 6;   // complex entries before the chunk
+    dim3 grid((unsigned)((N + 255) / 256), (unsigned)nv);
+    if (to_fp32)
+      abi_to_internal_kernel<float><<<grid, 256, 0, s>>>(
+          nx, ny, nz, h, B[0], B[1], B[2], (const double2*)abi + off,
+          (float*)internal + 2 * off);
+    else
+      abi_to_internal_kernel<double><<<grid, 256, 0, s>>>(
+          nx, ny, nz, h, B[0], B[1], B[2], (const double2*)abi + off,
+          (double*)internal + 2 * off);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 hipError_t launch_internal_to_abi(int nx, int ny, int nz, double h, const double B[3],

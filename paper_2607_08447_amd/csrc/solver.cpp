@@ -557,9 +557,19 @@ int run_solve(const SolveArgs& A, hkp_stats* stats) {
   }
 
   // ---- initial block: caller's X0 or random; SVQB; Rayleigh-Ritz
-  if (A.X0) {
-    HKP_CHECK(launch_abi_to_internal(p.nx, p.ny, p.nz, p.h, A.B, p.nb, A.X0,
+  if (A.X0 && !(A.flags & HKP_FLAG_X0_NEV)) {
+    // [batch][nb] vectors, contiguous in both layouts (member stride nb n6)
+    HKP_CHECK(launch_abi_to_internal(p.nx, p.ny, p.nz, p.h, A.B, p.nb * p.batch, A.X0,
                                      c.at<double>(c.L.X), 0, c.s));
+  } else if (A.X0) {
+    // [batch][nev] given vectors lead each member's block; the rest are random
+    HKP_CHECK(launch_random_block(c.at<double>(c.L.X), p.n6, p.nb, p.batch, c.bstride(),
+                                  A.seed, c.s));
+    for (int b = 0; b < p.batch; ++b)
+      HKP_CHECK(launch_abi_to_internal(
+          p.nx, p.ny, p.nz, p.h, A.B, p.nev,
+          static_cast<const double*>(A.X0) + 2 * (size_t)b * p.nev * p.n6,
+          c.at<double>(c.L.X) + 2 * (size_t)b * c.bstride(), 0, c.s));
   } else {
     HKP_CHECK(launch_random_block(c.at<double>(c.L.X), p.n6, p.nb, p.batch, c.bstride(),
                                   A.seed, c.s));

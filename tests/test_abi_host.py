@@ -155,5 +155,13 @@ def test_empty_and_oversized_inputs_are_rejected():
     # a zero-size batch
     o.nb = 16
     st = L.hkp_stats()
-    assert L.lib.hkp_solve_batch(C.byref(g), C.byref(m), C.byref(o), 0, fake, None, B, fake,
-                                 None, None, fake, 1 << 30, None, C.byref(st)) == L.HKP_E_ARG
+    assert L.lib.hkp_solve_batch(C.byref(g), C.byref(m), C.byref(o), 0, fake, None, B, None,
+                                 fake, None, None, fake, 1 << 30, None,
+                                 C.byref(st)) == L.HKP_E_ARG
+    # HKP_FLAG_X0 without an initial block
+    o.flags = L.HKP_FLAG_X0
+    assert L.lib.hkp_solve_batch(C.byref(g), C.byref(m), C.byref(o), 2, fake, None, B, None,
+                                 fake, None, None, fake, 1 << 30, None,
+                                 C.byref(st)) == L.HKP_E_ARG
+    assert b"X0" in L.lib.hkp_last_error()
+    o.flags = 0

@@ -69,3 +69,72 @@ def test_graph_single_equals_eager():
                   tol=1e-9, graph=True)
     assert a.status == 0 and b.status == 0
     assert np.abs(a.E.cpu().numpy() - b.E.cpu().numpy()).max() <= 1e-9
+
+
+def test_batch_warm_start_equals_cold():
+    """A batch restarted from its own eigenvectors (HKP_FLAG_X0_NEV: nev given
+    vectors, the rest of each block random) and from whole given blocks
+    reaches the cold-start eigenvalues, the warm restart in fewer iterations."""
+    import torch
+    import paper_2607_08447_amd as hkp
+    w, Vs = _sweep(3)
+    nev, nb = 8, 16
+    S = torch.from_numpy(w.strain)
+    print("batch warm start (nev and nb initial vectors)", flush=True)
+    cold = hkp.solve_batch(torch.from_numpy(Vs), w.h, nev, strain=S, B=w.B, nb=nb, tol=1e-9,
+                           graph=False, return_psi=True)
+    assert cold.status == 0
+    warm = hkp.solve_batch(torch.from_numpy(Vs), w.h, nev, strain=S, B=w.B, nb=nb, tol=1e-9,
+                           graph=False, X0=cold.psi)
+    assert warm.status == 0
+    assert np.abs(warm.E.cpu().numpy() - cold.E.cpu().numpy()).max() <= 1e-8
+    assert warm.resid.cpu().numpy().max() <= 1e-9
+    assert warm.stats["iters"] < cold.stats["iters"]
+    g = torch.Generator(device="cuda").manual_seed(5)
+    blk = torch.randn((Vs.shape[0], nb) + w.shape + (6,), dtype=torch.complex128, device="cuda",
+                      generator=g)
+    full = hkp.solve_batch(torch.from_numpy(Vs), w.h, nev, strain=S, B=w.B, nb=nb, tol=1e-9,
+                           graph=True, X0=blk)
+    assert full.status == 0
+    assert np.abs(full.E.cpu().numpy() - cold.E.cpu().numpy()).max() <= 1e-8
+
+
+def test_single_warm_start_from_neighbour():
+    """One solve started from the eigenvectors of a neighbouring potential (as
+    between Schroedinger-Poisson iterations) equals the cold solve."""
+    import torch
+    import paper_2607_08447_amd as hkp
+    w, Vs = _sweep(2)
+    S = torch.from_numpy(w.strain)
+    r0 = hkp.solve(torch.from_numpy(Vs[0]), w.h, 8, strain=S, B=w.B, nb=16, tol=1e-9)
+    cold = hkp.solve(torch.from_numpy(Vs[1]), w.h, 8, strain=S, B=w.B, nb=16, tol=1e-9)
+    warm = hkp.solve(torch.from_numpy(Vs[1]), w.h, 8, strain=S, B=w.B, nb=16, tol=1e-9,
+                     X0=r0.psi)
+    assert r0.status == 0 and cold.status == 0 and warm.status == 0
+    assert np.abs(warm.E.cpu().numpy() - cold.E.cpu().numpy()).max() <= 1e-8
+    assert warm.resid.cpu().numpy().max() <= 1e-9
+
+
+@pytest.mark.parametrize("precision,tol,bar", [("fp64", 1e-9, 1e-8), ("mixed", 1e-6, 1e-6)])
+def test_sweep_continuation_equals_batch(precision, tol, bar):
+    """solve_sweep (every 3rd member cold, the others warm-started from the
+    nearest of them) against the cold batched solve of the same sweep."""
+    import torch
+    import paper_2607_08447_amd as hkp
+    w, Vs = _sweep(7)
+    S = torch.from_numpy(w.strain)
+    print(f"sweep continuation {precision}", flush=True)
+    ref = hkp.solve_batch(torch.from_numpy(Vs), w.h, 8, strain=S, B=w.B, nb=16, tol=1e-10,
+                          graph=False)
+    sw = hkp.solve_sweep(torch.from_numpy(Vs), w.h, 8, strain=S, B=w.B, nb=16, tol=tol,
+                         precision=precision, stride=3, return_psi=True)
+    assert sw.status == 0
+    assert set(sw.stats) == {"anchors", "rest"}
+    assert np.abs(sw.E.cpu().numpy() - ref.E.cpu().numpy()).max() <= bar
+    assert sw.resid.cpu().numpy().max() <= tol
+    # member k's returned vectors are its own eigenvectors
+    for k in (1, 5):
+        Hpsi = hkp.apply(torch.from_numpy(Vs[k]), w.h, sw.psi[k], strain=S, B=w.B)
+        r = torch.linalg.vector_norm((Hpsi - sw.E[k][:, None, None, None, None] * sw.psi[k])
+                                     .reshape(8, -1), dim=1)
+        assert float(r.max()) <= tol * 1.01
