@@ -70,6 +70,9 @@ extern "C" {
 #define HKP_FLAG_X0_NEV 16      /* with HKP_FLAG_X0: X0 holds nev vectors per member (a
                                  * previous solve's psi); the block's other nb - nev
                                  * vectors are drawn at random from the seed */
+#define HKP_FLAG_PSI_BLOCK 32   /* psi receives the whole final block of nb Ritz vectors
+                                 * (ascending Ritz values; eig and resid still nev), the
+                                 * initial block of a restart that keeps the guard vectors */
 
 /* Grid: nx, ny, nz >= 1 points, spacing h (nm) > 0. */
 typedef struct {
@@ -140,6 +143,11 @@ void hkp_default_opts(hkp_opts* o);
  * nev + max(8, nev/2) rounded up to 8).  Returns 0 on invalid arguments. */
 size_t hkp_workspace_bytes(const hkp_grid* grid, const hkp_opts* opts, int32_t batch);
 
+/* The block size a solve with these arguments uses (opts->nb, or with nb = 0
+ * the autotuned or default value above): the leading extent of psi with
+ * HKP_FLAG_PSI_BLOCK.  Returns 0 on invalid arguments. */
+int32_t hkp_block_size(const hkp_grid* grid, const hkp_opts* opts);
+
 /* Lowest opts->nev eigenpairs of H for one potential (paper Sec. II.B).
  * The block (opts->nb) must exceed nev by at least one degenerate cluster
  * above the wanted states (a Kramers pair at B = 0): the filter's lower cut
@@ -155,7 +163,8 @@ size_t hkp_workspace_bytes(const hkp_grid* grid, const hkp_opts* opts, int32_t b
  *             from a neighbouring solve's psi, as between the iterations
  *             of a Schroedinger-Poisson loop, Fig. 2a)
  *   eig_eV    device double [nev], ascending
- *   psi       device complex double [nev][nx][ny][nz][6] (may be NULL)
+ *   psi       device complex double [nev][nx][ny][nz][6] (may be NULL);
+ *             [nb][nx][ny][nz][6] with HKP_FLAG_PSI_BLOCK
  *   resid_eV  device double [nev], ||H psi_n - E_n psi_n||_2 (may be NULL)
  *   workspace device, ws_bytes >= hkp_workspace_bytes(grid, opts, 1)
  *   stats     host, may be NULL
@@ -169,7 +178,8 @@ int hkp_solve(const hkp_grid* grid, const hkp_material* mat, const hkp_opts* opt
  * gate-voltage sweep, Fig. 2f): V_eV is [batch][nx][ny][nz]; X0 (with
  * HKP_FLAG_X0) [batch][nb][nx][ny][nz][6], or [batch][nev][nx][ny][nz][6]
  * with HKP_FLAG_X0_NEV; eig_eV [batch][nev], psi
- * [batch][nev][nx][ny][nz][6], resid_eV [batch][nev]; batch <= 65535.
+ * [batch][nev][nx][ny][nz][6] ([batch][nb]... with HKP_FLAG_PSI_BLOCK),
+ * resid_eV [batch][nev]; batch <= 65535.
  * Every kernel of an outer iteration covers the whole batch in one launch;
  * with HKP_FLAG_GRAPH the iterations are recorded once as a hipGraph and
  * replayed, converged members turning into no-ops on the device. */

@@ -26,6 +26,7 @@ HKP_FLAG_GRAPH = 2
 HKP_FLAG_NO_FP64_POLISH = 4
 HKP_FLAG_NO_LOCK = 8
 HKP_FLAG_X0_NEV = 16
+HKP_FLAG_PSI_BLOCK = 32
 
 
 class hkp_grid(C.Structure):
@@ -70,6 +71,7 @@ SIGNATURES = {
     "hkp_default_material": (None, [C.POINTER(hkp_material)]),
     "hkp_default_opts": (None, [C.POINTER(hkp_opts)]),
     "hkp_workspace_bytes": (C.c_size_t, [C.POINTER(hkp_grid), C.POINTER(hkp_opts), C.c_int32]),
+    "hkp_block_size": (C.c_int32, [C.POINTER(hkp_grid), C.POINTER(hkp_opts)]),
     "hkp_solve": (C.c_int, [C.POINTER(hkp_grid), C.POINTER(hkp_material), C.POINTER(hkp_opts),
                             _P, _P, _D, _P, _P, _P, _P, _P, C.c_size_t, _P,
                             C.POINTER(hkp_stats)]),

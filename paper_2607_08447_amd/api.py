@@ -106,15 +106,24 @@ def _x0(X0, lead, nev, nb, shape):
     return X0d, L.HKP_FLAG_X0, k
 
 
+def _npsi(g, o, nev, block):
+    """Vectors written to psi: nev, or with block the whole block (flag set on o)."""
+    if not block:
+        return nev
+    o.flags |= L.HKP_FLAG_PSI_BLOCK
+    return int(L.lib.hkp_block_size(C.byref(g), C.byref(o)))
+
+
 def solve(V, h, nev, strain=None, B=(0.0, 0.0, 0.0), nb=0, degree=0, tol=1e-8,
           precision="fp64", max_iter=200, seed=1, X0=None, graph=False, material=None,
-          return_psi=True, workspace=None, polish=True, lock=True):
+          return_psi=True, workspace=None, polish=True, lock=True, psi_block=False):
     """Lowest `nev` eigenpairs of H for the potential V (float64 [nx, ny, nz], eV).
 
     X0 (optional, complex128): the whole initial block [nb, nx, ny, nz, 6], or
     [nev, nx, ny, nz, 6] -- a previous solve's psi -- completed with random
-    vectors.  lock=False filters every vector of the block in every iteration
-    (no soft locking of converged Kramers pairs)."""
+    vectors.  psi_block=True returns all nb final Ritz vectors as psi (the
+    initial block of a later restart).  lock=False filters every vector of the
+    block in every iteration (no soft locking of converged Kramers pairs)."""
     V = _dev(V, torch.float64)
     shape = tuple(V.shape)
     if len(shape) != 3:
@@ -131,12 +140,13 @@ def solve(V, h, nev, strain=None, B=(0.0, 0.0, 0.0), nb=0, degree=0, tol=1e-8,
     need = L.lib.hkp_workspace_bytes(C.byref(g), C.byref(o), 1)
     if need == 0:
         raise L.HkpError(L.HKP_E_ARG, L.lib.hkp_last_error().decode())
+    npsi = _npsi(g, o, nev, return_psi and psi_block)
     ws = workspace
     if ws is None or ws.numel() < need:
         ws = torch.empty(need, dtype=torch.uint8, device="cuda")
     E = torch.empty(nev, dtype=torch.float64, device="cuda")
     R = torch.empty(nev, dtype=torch.float64, device="cuda")
-    psi = torch.empty((nev,) + shape + (6,), dtype=torch.complex128, device="cuda") \
+    psi = torch.empty((npsi,) + shape + (6,), dtype=torch.complex128, device="cuda") \
         if return_psi else None
     st = L.hkp_stats()
     stream_ctx = torch.cuda.Stream() if graph else None
@@ -158,9 +168,11 @@ def solve(V, h, nev, strain=None, B=(0.0, 0.0, 0.0), nb=0, degree=0, tol=1e-8,
 
 def solve_batch(V, h, nev, strain=None, B=(0.0, 0.0, 0.0), nb=0, degree=0, tol=1e-8,
                 precision="fp64", max_iter=200, seed=1, graph=True, material=None,
-                return_psi=False, workspace=None, polish=True, lock=True, X0=None):
+                return_psi=False, workspace=None, polish=True, lock=True, X0=None,
+                psi_block=False):
     """Lowest eigenpairs of `batch` Hamiltonians differing in V ([batch, nx, ny, nz]).
-    X0 (optional, complex128): [batch, nb or nev, nx, ny, nz, 6], as in solve()."""
+    X0 (optional, complex128): [batch, nb or nev, nx, ny, nz, 6]; X0 and
+    psi_block as in solve()."""
     V = _dev(V, torch.float64)
     if V.dim() != 4:
         raise ValueError("V must be [batch, nx, ny, nz]")
@@ -178,12 +190,13 @@ def solve_batch(V, h, nev, strain=None, B=(0.0, 0.0, 0.0), nb=0, degree=0, tol=1
     need = L.lib.hkp_workspace_bytes(C.byref(g), C.byref(o), batch)
     if need == 0:
         raise L.HkpError(L.HKP_E_ARG, L.lib.hkp_last_error().decode())
+    npsi = _npsi(g, o, nev, return_psi and psi_block)
     ws = workspace
     if ws is None or ws.numel() < need:
         ws = torch.empty(need, dtype=torch.uint8, device="cuda")
     E = torch.empty((batch, nev), dtype=torch.float64, device="cuda")
     R = torch.empty((batch, nev), dtype=torch.float64, device="cuda")
-    psi = torch.empty((batch, nev) + shape + (6,), dtype=torch.complex128, device="cuda") \
+    psi = torch.empty((batch, npsi) + shape + (6,), dtype=torch.complex128, device="cuda") \
         if return_psi else None
     st = L.hkp_stats()
     mat = _material(material)
@@ -204,9 +217,10 @@ def solve_sweep(V, h, nev, strain=None, B=(0.0, 0.0, 0.0), nb=0, degree=0, tol=1
                 return_psi=False, polish=True, lock=True):
     """A sweep solved by continuation: the members 0, stride, 2 stride, ... in one
     batched solve from random blocks, then every other member in a second
-    batched solve started from the nearest of those members' eigenvectors
-    (adjacent sweep points have close eigenvectors, so fewer filter passes are
-    needed).  Same arguments and result layout as solve_batch."""
+    batched solve started from the nearest of those members' final blocks, guard
+    vectors included (adjacent sweep points have close eigenvectors, so fewer
+    filter passes are needed).  Same arguments and result layout as
+    solve_batch."""
     V = _dev(V, torch.float64)
     if V.dim() != 4:
         raise ValueError("V must be [batch, nx, ny, nz]")
@@ -218,15 +232,15 @@ def solve_sweep(V, h, nev, strain=None, B=(0.0, 0.0, 0.0), nb=0, degree=0, tol=1
               lock=lock)
     anchors = list(range(0, batch, stride))
     rest = [i for i in range(batch) if i % stride]
-    ra = solve_batch(V[anchors], h, nev, return_psi=True, **kw)
+    ra = solve_batch(V[anchors], h, nev, return_psi=True, psi_block=True, **kw)
     E = torch.empty((batch, nev), dtype=torch.float64, device="cuda")
     R = torch.empty_like(E)
-    psi = torch.empty((batch,) + ra.psi.shape[1:], dtype=torch.complex128, device="cuda") \
+    psi = torch.empty((batch, nev) + ra.psi.shape[2:], dtype=torch.complex128, device="cuda") \
         if return_psi else None
     ia = torch.tensor(anchors, device="cuda")
     E[ia], R[ia] = ra.E, ra.resid
     if psi is not None:
-        psi[ia] = ra.psi
+        psi[ia] = ra.psi[:, :nev]
     stats = {"anchors": ra.stats}
     status = ra.status
     if rest:

@@ -211,6 +211,11 @@ void hkp_default_opts(hkp_opts* o) {
   o->seed = 1;
 }
 
+int32_t hkp_block_size(const hkp_grid* grid, const hkp_opts* opts) {
+  if (check_grid(grid) != HKP_OK || check_opts(grid, opts) != HKP_OK) return 0;
+  return block_size(*grid, *opts);
+}
+
 size_t hkp_workspace_bytes(const hkp_grid* grid, const hkp_opts* opts, int32_t batch) {
   if (check_grid(grid) != HKP_OK || check_opts(grid, opts) != HKP_OK) return 0;
   if (batch < 1 || batch > 65535) {

@@ -637,8 +637,11 @@ int run_solve(const SolveArgs& A, hkp_stats* stats) {
     t_rr.stop(c.s);
     t_res.start(c.s);
     residuals(c, act);
+    // stagnation toward the FP32 floor is judged on full-degree iterations
+    // only: during the degree ramp a slow decrease is the low degree's
     HKP_CHECK(launch_control(c.control(), p.batch, p.nb, p.nev, kKmax, kKmax, A.tol,
-                             p.mixed, !(A.flags & HKP_FLAG_NO_FP64_POLISH),
+                             p.mixed,
+                             !(A.flags & HKP_FLAG_NO_FP64_POLISH) && m_cur >= p.degree,
                              !(A.flags & HKP_FLAG_NO_LOCK), it, c.s));
     t_res.stop(c.s);
   };
@@ -715,10 +718,11 @@ int run_solve(const SolveArgs& A, hkp_stats* stats) {
   // ---- outputs
   HKP_CHECK(launch_finish(c.at<double>(c.L.theta), c.at<double>(c.L.r2), p.nb, p.nev, p.batch,
                           A.eig, A.resid, c.s));
+  const int npsi = (A.flags & HKP_FLAG_PSI_BLOCK) ? p.nb : p.nev;
   if (A.psi)
-    HKP_CHECK(launch_internal_to_abi(p.nx, p.ny, p.nz, p.h, A.B, p.nev, p.batch,
+    HKP_CHECK(launch_internal_to_abi(p.nx, p.ny, p.nz, p.h, A.B, npsi, p.batch,
                                      c.at<double>(c.L.X), c.bstride(), A.psi,
-                                     (long long)p.nev * p.n6, c.s));
+                                     (long long)npsi * p.n6, c.s));
   HKP_CHECK(hipStreamSynchronize(c.s));
   int all = 1, minconv = p.nev, maxit = 0, sw = -1;
   for (int b = 0; b < p.batch; ++b) {

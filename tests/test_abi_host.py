@@ -68,6 +68,22 @@ def test_workspace_query_and_argument_errors():
     assert L.lib.hkp_workspace_bytes(C.byref(bad), C.byref(o), 1) == 0
 
 
+def test_block_size_query():
+    """nb = 0 gives nev + max(8, nev / 2) rounded up to 8; an explicit nb is
+    returned as given; invalid arguments give 0."""
+    L, g, m, o = _structs()
+    for nev, nb in ((8, 16), (16, 24), (20, 32), (32, 48)):
+        o.nev, o.nb = nev, 0
+        assert L.lib.hkp_block_size(C.byref(g), C.byref(o)) == nb
+    o.nev, o.nb = 8, 24
+    assert L.lib.hkp_block_size(C.byref(g), C.byref(o)) == 24
+    o.nb = 8
+    assert L.lib.hkp_block_size(C.byref(g), C.byref(o)) == 0
+    bad = L.hkp_grid(0, 8, 8, 0.5)
+    o.nb = 16
+    assert L.lib.hkp_block_size(C.byref(bad), C.byref(o)) == 0
+
+
 def test_solve_rejects_before_any_gpu_work():
     L, g, m, o = _structs()
     fake = C.c_void_p(0x1000)   # never dereferenced: validation fails first

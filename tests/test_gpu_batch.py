@@ -82,14 +82,26 @@ def test_batch_warm_start_equals_cold():
     S = torch.from_numpy(w.strain)
     print("batch warm start (nev and nb initial vectors)", flush=True)
     cold = hkp.solve_batch(torch.from_numpy(Vs), w.h, nev, strain=S, B=w.B, nb=nb, tol=1e-9,
-                           graph=False, return_psi=True)
+                           graph=False, return_psi=True, psi_block=True)
     assert cold.status == 0
+    assert tuple(cold.psi.shape) == (Vs.shape[0], nb) + w.shape + (6,)
+    # the whole final block is orthonormal
+    for k in range(Vs.shape[0]):
+        Q = cold.psi[k].reshape(nb, -1)
+        G = Q.conj() @ Q.T
+        assert float((G - torch.eye(nb, dtype=G.dtype, device=G.device)).abs().max()) <= 1e-10
     warm = hkp.solve_batch(torch.from_numpy(Vs), w.h, nev, strain=S, B=w.B, nb=nb, tol=1e-9,
-                           graph=False, X0=cold.psi)
+                           graph=False, X0=cold.psi[:, :nev])
     assert warm.status == 0
     assert np.abs(warm.E.cpu().numpy() - cold.E.cpu().numpy()).max() <= 1e-8
     assert warm.resid.cpu().numpy().max() <= 1e-9
     assert warm.stats["iters"] < cold.stats["iters"]
+    # restarted from its own converged blocks a batch is done after the first
+    # Rayleigh-Ritz step
+    again = hkp.solve_batch(torch.from_numpy(Vs), w.h, nev, strain=S, B=w.B, nb=nb, tol=1e-9,
+                            graph=False, X0=cold.psi)
+    assert again.status == 0 and again.stats["iters"] == 0
+    assert np.abs(again.E.cpu().numpy() - cold.E.cpu().numpy()).max() <= 1e-10
     g = torch.Generator(device="cuda").manual_seed(5)
     blk = torch.randn((Vs.shape[0], nb) + w.shape + (6,), dtype=torch.complex128, device="cuda",
                       generator=g)
@@ -106,13 +118,18 @@ def test_single_warm_start_from_neighbour():
     import paper_2607_08447_amd as hkp
     w, Vs = _sweep(2)
     S = torch.from_numpy(w.strain)
-    r0 = hkp.solve(torch.from_numpy(Vs[0]), w.h, 8, strain=S, B=w.B, nb=16, tol=1e-9)
+    r0 = hkp.solve(torch.from_numpy(Vs[0]), w.h, 8, strain=S, B=w.B, nb=16, tol=1e-9,
+                   psi_block=True)
+    assert tuple(r0.psi.shape) == (16,) + w.shape + (6,)
     cold = hkp.solve(torch.from_numpy(Vs[1]), w.h, 8, strain=S, B=w.B, nb=16, tol=1e-9)
-    warm = hkp.solve(torch.from_numpy(Vs[1]), w.h, 8, strain=S, B=w.B, nb=16, tol=1e-9,
-                     X0=r0.psi)
-    assert r0.status == 0 and cold.status == 0 and warm.status == 0
-    assert np.abs(warm.E.cpu().numpy() - cold.E.cpu().numpy()).max() <= 1e-8
-    assert warm.resid.cpu().numpy().max() <= 1e-9
+    assert r0.status == 0 and cold.status == 0
+    for X0 in (r0.psi[:8], r0.psi):      # nev vectors + random, the whole block
+        warm = hkp.solve(torch.from_numpy(Vs[1]), w.h, 8, strain=S, B=w.B, nb=16, tol=1e-9,
+                         X0=X0)
+        assert warm.status == 0
+        assert np.abs(warm.E.cpu().numpy() - cold.E.cpu().numpy()).max() <= 1e-8
+        assert warm.resid.cpu().numpy().max() <= 1e-9
+        assert warm.stats["iters"] < cold.stats["iters"]
 
 
 @pytest.mark.parametrize("precision,tol,bar", [("fp64", 1e-9, 1e-8), ("mixed", 1e-6, 1e-6)])
