@@ -36,3 +36,7 @@ from .solve import (  # noqa: F401
     lowest_dense, lowest_arpack, residuals, hf_gradient, gate_potential,
     solve_lowest,
 )
+from .poisson import (  # noqa: F401
+    E_OVER_EPS0, KB, link_permittivity, poisson_operator, poisson_solve, occupancy,
+    hole_density, embed, restrict, sp_loop,
+)

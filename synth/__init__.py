@@ -4,5 +4,6 @@ none of the eigensolver's arithmetic.
 """
 
 from .inputs import (  # noqa: F401
-    Workload, WORKLOADS, workload, smooth_field, fin_potential, random_block,
+    Workload, WORKLOADS, workload, smooth_field, fin_potential, random_block, SPDevice,
+    sp_device,
 )

@@ -197,3 +197,74 @@ WORKLOADS = ("harmonic_10x8x8", "fin_qd_128x40x40", "dqd_256x48x48",
 
 def workload(name, **kw):
     return build(name, **kw)
+
+
+# ---------------------------------------------------------------------------
+# Self-consistent Schroedinger-Poisson devices
+# ---------------------------------------------------------------------------
+@dataclass
+class SPDevice:
+    """A gated fin for the self-consistent loop: the Schroedinger grid (shape, h)
+    sits at `offset` inside the Poisson box `pshape` (same spacing)."""
+    name: str
+    shape: tuple
+    h: float
+    pshape: tuple
+    offset: tuple
+    V_off: np.ndarray          # [nx,ny,nz] band offset (oxide step), eV
+    strain: Optional[np.ndarray]
+    B: tuple
+    eps_r: np.ndarray          # [px,py,pz]
+    dirichlet: np.ndarray      # [px,py,pz] uint8, 1 = electrode node
+    phi_fixed: np.ndarray      # [px,py,pz] electrode potentials (V), 0 elsewhere
+    n_holes: float
+    T: float
+    nev: int
+    nb: int
+    gates: dict = field(default_factory=dict)
+
+
+def sp_device(name):
+    """Recipe: the fin of the other workloads (4.5 eV oxide step outside a 10 x 20 nm
+    cross-section) with its Schroedinger grid padded on every side inside the
+    Poisson box; eps_r = 11.7 (Si) where V_off = 0 and 3.9 (SiO2) elsewhere.
+    Electrodes: the bottom face of the box is a grounded substrate contact; on the
+    top face, strips across y of 10 nm along x: two plungers at x_c -+ 15 nm and a
+    barrier gate at x_c (these Dirichlet patches are the gates of Fig. 1, with
+    the rest of every outer face field-free).  Two holes at 1.5 K (Sec. II.C)."""
+    cfg = {
+        # name: (S shape, pad (x, y, z-below, z-above), gate volts (plunger, barrier),
+        #        strain, B, nev, nb)
+        "sp_tiny": ((12, 6, 6), (2, 2, 2, 3), (-0.30, -0.05), False, (0.0, 0.0, 0.0), 8, 16),
+        "sp_dqd_small": ((24, 8, 8), (3, 3, 2, 4), (-0.30, -0.05), False, (0.0, 0.0, 0.0),
+                         8, 16),
+        "sp_dqd_256x48x48": ((256, 48, 48), (8, 8, 16, 24), (-0.30, -0.05), True,
+                             (0.5, 0.0, 0.0), 8, 16),
+    }
+    if name not in cfg:
+        raise KeyError(name)
+    shape, pad, (vp, vb), with_strain, B, nev, nb = cfg[name]
+    h = 0.4
+    px_, py_, pzb, pza = pad
+    pshape = (shape[0] + 2 * px_, shape[1] + 2 * py_, shape[2] + pzb + pza)
+    offset = (px_, py_, pzb)
+    V_off = fin_potential(shape, h)
+    eps = np.full(pshape, 3.9)
+    ox, oy, oz = offset
+    eps[ox:ox + shape[0], oy:oy + shape[1], oz:oz + shape[2]] = np.where(V_off == 0.0, 11.7,
+                                                                         3.9)
+    dirichlet = np.zeros(pshape, dtype=np.uint8)
+    phi_fixed = np.zeros(pshape)
+    dirichlet[:, :, 0] = 1                              # substrate contact, 0 V
+    xP = (np.arange(pshape[0]) + 1.0) * h
+    xc = (ox + (shape[0] + 1) / 2.0) * h                # fin centre in box coordinates
+    strips = {"P1": (xc - 15.0, vp), "B": (xc, vb), "P2": (xc + 15.0, vp)}
+    if shape[0] * h < 40.0:                             # short fins: one plunger, centred
+        strips = {"P1": (xc, vp)}
+    for xg, v in strips.values():
+        on = np.abs(xP - xg) <= 5.0 + 1e-6 * h          # edges on a node count (both sides)
+        dirichlet[on, :, -1] = 1
+        phi_fixed[on, :, -1] = v
+    strain = strain_field(shape, h, _rng(21, 1)) if with_strain else None
+    return SPDevice(name, shape, h, pshape, offset, V_off, strain, B, eps, dirichlet,
+                    phi_fixed, 2.0, 1.5, nev, nb, gates=strips)
