@@ -144,6 +144,22 @@ def restrict(big, small_shape, offset):
     return big[ox:ox + nx, oy:oy + ny, oz:oz + nz]
 
 
+class Anderson:
+    """Anderson mixing with a history of the last m (input, residual) pairs."""
+
+    def __init__(self, mixing, m):
+        self.mixing, self.m = mixing, m
+        self.hist_x, self.hist_F = [], []
+
+    def step(self, x, F):
+        nxt = anderson_step(x, F, self.hist_x, self.hist_F, self.mixing, self.m)
+        self.hist_x.append(x)
+        self.hist_F.append(F)
+        excess = max(0, len(self.hist_x) - self.m)
+        del self.hist_x[:excess], self.hist_F[:excess]
+        return nxt
+
+
 def anderson_step(x, F, hist_x, hist_F, mixing, m):
     """Next input from the current input x and residual F, given the previous
     inputs and residuals (lists, oldest first; at most m are used)."""
@@ -178,7 +194,7 @@ def sp_loop(grid, nev, V_off, pshape, offset, eps_r, dirichlet, phi_fixed, n_hol
     else:
         phi_in = np.array(phi0, dtype=float)
     delta = np.inf
-    hist_x, hist_F = [], []
+    mixer = Anderson(mixing, history)
     for it in range(1, max_iter + 1):
         V = np.asarray(V_off, dtype=float) + restrict(phi_in, sshape, offset)
         E, psi, _ = solve_lowest(grid, material, nev, V=V, strain=strain, B=B, method=method)
@@ -191,10 +207,5 @@ def sp_loop(grid, nev, V_off, pshape, offset, eps_r, dirichlet, phi_fixed, n_hol
                    delta=delta, converged=delta <= tol)
         if out["converged"]:
             break
-        F = phi_out - phi_in
-        nxt = anderson_step(phi_in, F, hist_x, hist_F, mixing, history)
-        hist_x.append(phi_in)
-        hist_F.append(F)
-        del hist_x[:len(hist_x) - history], hist_F[:len(hist_F) - history]
-        phi_in = nxt
+        phi_in = mixer.step(phi_in, phi_out - phi_in)
     return out

@@ -137,6 +137,29 @@ def test_occupancy_closed_forms():
             assert abs(f.sum() - n_h) < 1e-12
 
 
+def test_anderson_on_a_linear_map():
+    """On a linear fixed-point problem x = M x + c in n dimensions, Anderson mixing
+    with a history of at least n terminates after n + 1 steps (it is then GMRES;
+    Walker and Ni, SIAM J. Numer. Anal. 49, 1715 (2011)); with no history it is
+    plain damped iteration x + a F."""
+    from oracle.poisson import Anderson
+    rng = np.random.default_rng(7)
+    n = 4
+    M = rng.normal(0.0, 0.6, (n, n))
+    c = rng.normal(size=n)
+    exact = np.linalg.solve(np.eye(n) - M, c)
+    mixer = Anderson(0.5, 5)
+    x = np.zeros(n)
+    for _ in range(n + 1):
+        x = mixer.step(x, M @ x + c - x)
+    assert np.abs(x - exact).max() < 1e-9
+    assert len(mixer.hist_x) == 5
+    lin = Anderson(0.5, 0)
+    y = rng.normal(size=n)
+    F = M @ y + c - y
+    assert np.array_equal(lin.step(y, F), y + 0.5 * F)
+
+
 def test_hole_density_counts_the_holes_in_either_basis():
     """sum p h^3 = n_holes for normalised states; sum_c |psi_c|^2 is the same in the
     |L S> and |J m_j> bases (U is unitary)."""
