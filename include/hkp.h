@@ -132,6 +132,53 @@ typedef struct {
   double gbps;         /* algorithmic bytes / time */
 } hkp_tune;
 
+/* ---- Self-consistent Schroedinger-Poisson loop (Sec. II.B, Fig. 2a) ----
+ *
+ * Poisson box: px x py x pz points with the spacing h of the Schroedinger
+ * grid, which occupies the points ox <= i < ox + nx (and likewise in y, z).
+ * Box fields are double [px][py][pz], C order (z fastest).  The potential
+ * phi (V) solves -div(eps_r grad phi) = (e/eps0) rho with rho in e/nm^3
+ * (holes positive): 7-point finite differences, link permittivity the
+ * harmonic mean of the two nodes' eps_r, electrode (Dirichlet) nodes held at
+ * their given potential, no flux through any other outer face (Neumann).
+ * The hole potential energy on the Schroedinger grid is V = V_off + phi (eV).
+ * Each eigenstate holds at most one hole, with the Fermi-Dirac occupation
+ * f_n = 1 / (1 + exp((E_n - mu) / kT)) and mu fixed by sum f_n = n_holes;
+ * the hole density is p = sum_n f_n sum_c |psi_n,c|^2 / h^3 (nm^-3). */
+typedef struct {
+  int32_t px, py, pz;   /* Poisson box points, each >= 1, px py pz <= 2^31 */
+  int32_t ox, oy, oz;   /* offset of the Schroedinger grid inside the box */
+} hkp_pgrid;
+
+#define HKP_SP_PHI0 1   /* start from the caller's phi (else the hole-free potential) */
+
+typedef struct {
+  double n_holes;        /* holes in the computed states, 0 <= n_holes <= nev */
+  double temperature_K;  /* > 0 */
+  double mixing;         /* Anderson damping a, 0 < a <= 1 */
+  int32_t history;       /* Anderson history m, 0..8 (0: linear mixing) */
+  int32_t max_iter;      /* loop iterations, >= 1 */
+  double tol_V;          /* stop when max |phi_out - phi_in| <= tol_V (V), > 0 */
+  double cg_tol;         /* Poisson CG: stop at |r| <= cg_tol |b|, > 0 */
+  int32_t cg_max_iter;   /* CG iterations per Poisson solve, >= 1 */
+  int32_t flags;         /* HKP_SP_* */
+} hkp_sp_opts;
+
+typedef struct {
+  int32_t iters;              /* loop iterations (Schroedinger + Poisson passes) */
+  int32_t converged;          /* 1 if max |phi_out - phi_in| <= tol_V */
+  double delta_V;             /* last max |phi_out - phi_in| */
+  double mu_eV;               /* Fermi level of the last iteration */
+  double f_last;              /* occupation of the highest computed state (nev too
+                                 small for the filling if it is not ~0) */
+  int64_t cg_iters;           /* conjugate-gradient iterations, all Poisson solves */
+  int32_t schroedinger_iters; /* eigensolver outer iterations, all solves */
+  int32_t solve_status;       /* worst eigensolver status (HKP_OK or a warning) */
+  int32_t poisson_status;     /* worst Poisson status (HKP_OK or a warning) */
+  int32_t nb;                 /* eigensolver block size used */
+  double seconds, t_schroedinger, t_poisson;   /* wall time: total, and by half */
+} hkp_sp_stats;
+
 /* Silicon parameters of Table I with gamma3 = 1.446. */
 void hkp_default_material(hkp_material* m);
 /* nev 8, nb 0, degree 0, max_iter 200, tol 1e-8 eV, FP64, flags 0, seed 1. */
@@ -251,6 +298,68 @@ int hkp_autotune_block(const hkp_grid* grid, const hkp_material* mat, const hkp_
                        const int32_t* candidates, int32_t ncand, void* workspace,
                        size_t ws_bytes, void* hip_stream, int32_t* nb_out,
                        double* seconds_out);
+
+/* Workspace of hkp_poisson for this box. */
+size_t hkp_poisson_workspace_bytes(const hkp_pgrid* pgrid);
+
+/* One Poisson solve on the box (offsets unused): Jacobi-preconditioned
+ * conjugate gradients from the guess in phi.
+ *   eps_r, phi_fixed, rho  device double [px][py][pz] (rho may be NULL: 0)
+ *   dirichlet  device uint8 [px][py][pz], 1 = electrode node; at least one
+ *              (a box without one is reported as HKP_E_ARG after the
+ *              coefficient pass, the only check that reads device data)
+ *   phi        device double [px][py][pz]; in: finite guess, out: solution
+ *              (electrode nodes set to phi_fixed)
+ *   cg_iters, cg_relres  host, may be NULL: iterations and final |r|/|b|
+ * Returns HKP_OK, HKP_W_NOT_CONVERGED (cg_max_iter reached) or an error. */
+int hkp_poisson(const hkp_pgrid* pgrid, double h_nm, const double* eps_r,
+                const uint8_t* dirichlet, const double* phi_fixed, const double* rho,
+                double* phi, double cg_tol, int32_t cg_max_iter, void* workspace,
+                size_t ws_bytes, void* hip_stream, int32_t* cg_iters, double* cg_relres);
+
+/* Fermi-Dirac occupations of nev (1..64) hole levels E_eV (device) holding
+ * n_holes (0..nev) at temperature T_K > 0: f (device [nev]) and mu_eV (device
+ * double, may be NULL); mu by 200 bisection steps on sum f = n_holes. */
+int hkp_occupancy(int32_t nev, const double* E_eV, double n_holes, double T_K, double* f,
+                  double* mu_eV, void* hip_stream);
+
+/* Hole density on the Schroedinger grid, density (device double [nx][ny][nz],
+ * nm^-3) = sum_n f[n] sum_c |psi_n,c|^2 / h^3; psi device complex double
+ * [nev][nx][ny][nz][6] (either basis), f device double [nev], nev >= 1. */
+int hkp_hole_density(const hkp_grid* grid, int32_t nev, const void* psi, const double* f,
+                     double* density, void* hip_stream);
+
+/* Workspace of hkp_sp_solve. */
+size_t hkp_sp_workspace_bytes(const hkp_grid* grid, const hkp_opts* opts,
+                              const hkp_pgrid* pgrid, const hkp_sp_opts* sp);
+
+/* The self-consistent loop (Fig. 2a): from phi_in (the hole-free potential,
+ * or the caller's phi with HKP_SP_PHI0) each iteration solves for the lowest
+ * opts->nev eigenpairs of H(V_off + phi_in) (hkp_solve with opts; from the
+ * second iteration on restarted from the previous iteration's whole block),
+ * occupies them, forms the hole density and solves Poisson for phi_out;
+ * it stops when max |phi_out - phi_in| <= tol_V, otherwise the next phi_in
+ * comes from Anderson mixing: phi_in + a F - (dX + a dF) g with F = phi_out -
+ * phi_in, dX and dF the differences to the m previous inputs and residuals,
+ * and g the least-squares minimiser of |F - dF g|.
+ *   V_off      device double [nx][ny][nz], band offset (e.g. the oxide step), eV
+ *   strain, B_T as in hkp_solve
+ *   eps_r, dirichlet, phi_fixed  as in hkp_poisson; rho_fixed device [px][py][pz]
+ *              fixed charge (e/nm^3, e.g. ionised dopants) or NULL
+ *   phi        device double [px][py][pz]; out: the last phi_in, the potential
+ *              the returned eigenpairs belong to
+ *   eig_eV, psi, resid_eV  as in hkp_solve (psi, resid may be NULL)
+ *   density    device double [nx][ny][nz] hole density of the last iteration, or NULL
+ *   stats      host, may be NULL
+ * opts->flags: HKP_FLAG_GRAPH, HKP_FLAG_NO_FP64_POLISH, HKP_FLAG_NO_LOCK apply to
+ * every eigensolve; X0 flags are ignored.  Returns HKP_OK, HKP_W_NOT_CONVERGED
+ * (max_iter reached, or an eigensolve did not converge) or an error. */
+int hkp_sp_solve(const hkp_grid* grid, const hkp_material* mat, const hkp_opts* opts,
+                 const hkp_pgrid* pgrid, const hkp_sp_opts* sp, const double* V_off_eV,
+                 const double* strain, const double B_T[3], const double* eps_r,
+                 const uint8_t* dirichlet, const double* phi_fixed, const double* rho_fixed,
+                 double* phi, double* eig_eV, void* psi, double* resid_eV, double* density,
+                 void* workspace, size_t ws_bytes, void* hip_stream, hkp_sp_stats* stats);
 
 /* Thread-local message of the last error (never NULL). */
 const char* hkp_last_error(void);

@@ -11,7 +11,8 @@ in-tree libhkp.so and fails if it is missing.
 from ._lib import HkpError, lib  # noqa: F401
 from .api import (  # noqa: F401
     SI, EigvalsFromPotential, SolveResult, apply, autotune, autotune_block, filter_step, gate_potential,
-    hf_grad, solve, solve_batch, solve_sweep, workspace_bytes,
+    hf_grad, solve, solve_batch, solve_sweep, workspace_bytes, poisson, occupancy, hole_density,
+    sp_solve, SPResult,
 )
 
 __version__ = "1.0.0"

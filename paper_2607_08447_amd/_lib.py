@@ -27,6 +27,7 @@ HKP_FLAG_NO_FP64_POLISH = 4
 HKP_FLAG_NO_LOCK = 8
 HKP_FLAG_X0_NEV = 16
 HKP_FLAG_PSI_BLOCK = 32
+HKP_SP_PHI0 = 1
 
 
 class hkp_grid(C.Structure):
@@ -64,6 +65,28 @@ class hkp_tune(C.Structure):
                 ("reserved", C.c_int32), ("us_per_step", C.c_double), ("gbps", C.c_double)]
 
 
+class hkp_pgrid(C.Structure):
+    _fields_ = [("px", C.c_int32), ("py", C.c_int32), ("pz", C.c_int32), ("ox", C.c_int32),
+                ("oy", C.c_int32), ("oz", C.c_int32)]
+
+
+class hkp_sp_opts(C.Structure):
+    _fields_ = [("n_holes", C.c_double), ("temperature_K", C.c_double), ("mixing", C.c_double),
+                ("history", C.c_int32), ("max_iter", C.c_int32), ("tol_V", C.c_double),
+                ("cg_tol", C.c_double), ("cg_max_iter", C.c_int32), ("flags", C.c_int32)]
+
+
+class hkp_sp_stats(C.Structure):
+    _fields_ = [("iters", C.c_int32), ("converged", C.c_int32), ("delta_V", C.c_double),
+                ("mu_eV", C.c_double), ("f_last", C.c_double), ("cg_iters", C.c_int64),
+                ("schroedinger_iters", C.c_int32), ("solve_status", C.c_int32),
+                ("poisson_status", C.c_int32), ("nb", C.c_int32), ("seconds", C.c_double),
+                ("t_schroedinger", C.c_double), ("t_poisson", C.c_double)]
+
+    def as_dict(self):
+        return {name: getattr(self, name) for name, _ in self._fields_}
+
+
 _P = C.c_void_p
 _D = C.POINTER(C.c_double)
 
@@ -93,6 +116,17 @@ SIGNATURES = {
     "hkp_autotune_block": (C.c_int, [C.POINTER(hkp_grid), C.POINTER(hkp_material),
                                      C.POINTER(hkp_opts), _P, _P, _D, C.POINTER(C.c_int32),
                                      C.c_int32, _P, C.c_size_t, _P, C.POINTER(C.c_int32), _D]),
+    "hkp_poisson_workspace_bytes": (C.c_size_t, [C.POINTER(hkp_pgrid)]),
+    "hkp_poisson": (C.c_int, [C.POINTER(hkp_pgrid), C.c_double, _P, _P, _P, _P, _P, C.c_double,
+                              C.c_int32, _P, C.c_size_t, _P, C.POINTER(C.c_int32), _D]),
+    "hkp_occupancy": (C.c_int, [C.c_int32, _P, C.c_double, C.c_double, _P, _P, _P]),
+    "hkp_hole_density": (C.c_int, [C.POINTER(hkp_grid), C.c_int32, _P, _P, _P, _P]),
+    "hkp_sp_workspace_bytes": (C.c_size_t, [C.POINTER(hkp_grid), C.POINTER(hkp_opts),
+                                            C.POINTER(hkp_pgrid), C.POINTER(hkp_sp_opts)]),
+    "hkp_sp_solve": (C.c_int, [C.POINTER(hkp_grid), C.POINTER(hkp_material), C.POINTER(hkp_opts),
+                               C.POINTER(hkp_pgrid), C.POINTER(hkp_sp_opts), _P, _P, _D, _P, _P,
+                               _P, _P, _P, _P, _P, _P, _P, _P, C.c_size_t, _P,
+                               C.POINTER(hkp_sp_stats)]),
     "hkp_last_error": (C.c_char_p, []),
     "hkp_version": (C.c_int, []),
 }

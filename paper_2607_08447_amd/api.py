@@ -314,6 +314,135 @@ def hf_grad(psi, w, Lg):
     return grad
 
 
+# ---------------------------------------------------------------------------
+# self-consistent Schroedinger-Poisson loop
+# ---------------------------------------------------------------------------
+def _pgrid(pshape, offset=(0, 0, 0)):
+    px, py, pz = (int(v) for v in pshape)
+    ox, oy, oz = (int(v) for v in offset)
+    return L.hkp_pgrid(px, py, pz, ox, oy, oz)
+
+
+def poisson(eps_r, dirichlet, phi_fixed, rho, h, phi0=None, tol=1e-12, max_iter=20000):
+    """phi (V) on the Poisson box [px, py, pz] from -div(eps_r grad phi) = (e/eps0) rho
+    (rho in e/nm^3, may be None), electrode nodes (dirichlet != 0) at phi_fixed.
+    Returns (phi, cg_iterations, final |r|/|b|, status)."""
+    eps_r = _dev(eps_r, torch.float64)
+    shape = tuple(eps_r.shape)
+    dirichlet = _dev(dirichlet, torch.uint8)
+    phi_fixed = _dev(phi_fixed, torch.float64)
+    rho = _dev(rho, torch.float64)
+    for t in (dirichlet, phi_fixed) + ((rho,) if rho is not None else ()):
+        if tuple(t.shape) != shape:
+            raise ValueError("eps_r, dirichlet, phi_fixed and rho must share one [px, py, pz] shape")
+    pg = _pgrid(shape)
+    need = L.lib.hkp_poisson_workspace_bytes(C.byref(pg))
+    if need == 0:
+        raise L.HkpError(L.HKP_E_ARG, L.lib.hkp_last_error().decode())
+    ws = torch.empty(need, dtype=torch.uint8, device="cuda")
+    phi = torch.zeros(shape, dtype=torch.float64, device="cuda") if phi0 is None \
+        else _dev(phi0, torch.float64).clone()
+    it = C.c_int32(0)
+    rel = C.c_double(0.0)
+    code = L.lib.hkp_poisson(C.byref(pg), float(h), _ptr(eps_r), _ptr(dirichlet), _ptr(phi_fixed),
+                             _ptr(rho), _ptr(phi), float(tol), int(max_iter), _ptr(ws),
+                             C.c_size_t(need), _stream(), C.byref(it), C.byref(rel))
+    L.check(code)
+    return phi, it.value, rel.value, code
+
+
+def occupancy(E, n_holes, T):
+    """Fermi-Dirac occupations of the hole levels E (eV) holding n_holes at T (K):
+    returns (f, mu) as device tensors."""
+    E = _dev(E, torch.float64)
+    f = torch.empty_like(E)
+    mu = torch.empty(1, dtype=torch.float64, device="cuda")
+    L.check(L.lib.hkp_occupancy(E.numel(), _ptr(E), float(n_holes), float(T), _ptr(f), _ptr(mu),
+                                _stream()))
+    return f, mu[0]
+
+
+def hole_density(psi, f, h):
+    """sum_n f_n sum_c |psi_n,c|^2 / h^3 (nm^-3) for psi [nev, nx, ny, nz, 6]."""
+    psi = _dev(psi, torch.complex128)
+    f = _dev(f, torch.float64)
+    shape = tuple(psi.shape[1:4])
+    g = _grid(shape, h)
+    out = torch.empty(shape, dtype=torch.float64, device="cuda")
+    L.check(L.lib.hkp_hole_density(C.byref(g), psi.shape[0], _ptr(psi), _ptr(f), _ptr(out),
+                                   _stream()))
+    return out
+
+
+@dataclass
+class SPResult:
+    phi: torch.Tensor        # [px, py, pz] V, the potential of the returned eigenpairs
+    E: torch.Tensor          # [nev] eV
+    psi: torch.Tensor        # [nev, nx, ny, nz, 6] or None
+    resid: torch.Tensor      # [nev] eV
+    density: torch.Tensor    # [nx, ny, nz] nm^-3
+    stats: dict
+    status: int
+
+
+def sp_solve(V_off, h, nev, pshape, offset, eps_r, dirichlet, phi_fixed, n_holes, T,
+             strain=None, B=(0.0, 0.0, 0.0), rho_fixed=None, phi0=None, nb=0, degree=0,
+             tol=1e-8, precision="fp64", max_iter=200, seed=1, graph=False, material=None,
+             mixing=0.3, history=5, tol_V=1e-8, sp_max_iter=100, cg_tol=1e-12,
+             cg_max_iter=20000, return_psi=True):
+    """Self-consistent Schroedinger-Poisson loop: V_off [nx, ny, nz] (eV) at `offset`
+    inside the Poisson box `pshape`; eps_r, dirichlet, phi_fixed (and rho_fixed)
+    on the box.  phi0: start from this potential instead of the hole-free one."""
+    V_off = _dev(V_off, torch.float64)
+    shape = tuple(V_off.shape)
+    strain = _dev(strain, torch.float64)
+    eps_r = _dev(eps_r, torch.float64)
+    dirichlet = _dev(dirichlet, torch.uint8)
+    phi_fixed = _dev(phi_fixed, torch.float64)
+    rho_fixed = _dev(rho_fixed, torch.float64)
+    pshape = tuple(int(v) for v in pshape)
+    for t in (eps_r, dirichlet, phi_fixed) + ((rho_fixed,) if rho_fixed is not None else ()):
+        if tuple(t.shape) != pshape:
+            raise ValueError("box fields must be [px, py, pz]")
+    g = _grid(shape, h)
+    pg = _pgrid(pshape, offset)
+    flags = L.HKP_FLAG_GRAPH if graph else 0
+    o = _opts(nev, nb, degree, max_iter, tol, precision, flags, seed)
+    sp = L.hkp_sp_opts(float(n_holes), float(T), float(mixing), int(history), int(sp_max_iter),
+                       float(tol_V), float(cg_tol), int(cg_max_iter),
+                       L.HKP_SP_PHI0 if phi0 is not None else 0)
+    need = L.lib.hkp_sp_workspace_bytes(C.byref(g), C.byref(o), C.byref(pg), C.byref(sp))
+    if need == 0:
+        raise L.HkpError(L.HKP_E_ARG, L.lib.hkp_last_error().decode())
+    ws = torch.empty(need, dtype=torch.uint8, device="cuda")
+    phi = torch.zeros(pshape, dtype=torch.float64, device="cuda") if phi0 is None \
+        else _dev(phi0, torch.float64).clone()
+    E = torch.empty(nev, dtype=torch.float64, device="cuda")
+    R = torch.empty(nev, dtype=torch.float64, device="cuda")
+    dens = torch.empty(shape, dtype=torch.float64, device="cuda")
+    psi = torch.empty((nev,) + shape + (6,), dtype=torch.complex128, device="cuda") \
+        if return_psi else None
+    st = L.hkp_sp_stats()
+    mat = _material(material)
+    s = torch.cuda.Stream() if graph else None
+    if s is not None:
+        s.wait_stream(torch.cuda.current_stream())
+        ctx = torch.cuda.stream(s)
+    else:
+        ctx = None
+    args = (C.byref(g), C.byref(mat), C.byref(o), C.byref(pg), C.byref(sp), _ptr(V_off),
+            _ptr(strain), _B(B), _ptr(eps_r), _ptr(dirichlet), _ptr(phi_fixed), _ptr(rho_fixed),
+            _ptr(phi), _ptr(E), _ptr(psi), _ptr(R), _ptr(dens), _ptr(ws), C.c_size_t(need))
+    if ctx is not None:
+        with ctx:
+            code = L.lib.hkp_sp_solve(*args, _stream(s), C.byref(st))
+        torch.cuda.current_stream().wait_stream(s)
+    else:
+        code = L.lib.hkp_sp_solve(*args, _stream(), C.byref(st))
+    L.check(code)
+    return SPResult(phi, E, psi, R, dens, st.as_dict(), code)
+
+
 def autotune(shape, h, nb, precision="fp64", with_strain=True, with_field=True):
     g = _grid(shape, h)
     prec = L.HKP_PREC_MIXED if precision in ("mixed", 1) else L.HKP_PREC_FP64

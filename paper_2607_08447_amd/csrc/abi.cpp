@@ -119,6 +119,46 @@ int check_device() {
   return HKP_OK;
 }
 
+int check_pgrid(const hkp_pgrid* pg, const hkp_grid* g) {
+  if (!pg) {
+    set_error("pgrid is NULL");
+    return HKP_E_ARG;
+  }
+  if (pg->px < 1 || pg->py < 1 || pg->pz < 1) {
+    set_error("Poisson box needs px, py, pz >= 1");
+    return HKP_E_ARG;
+  }
+  if ((long long)pg->px * pg->py * pg->pz > (1LL << 31)) {
+    set_error("Poisson box too large");
+    return HKP_E_ARG;
+  }
+  if (g && (pg->ox < 0 || pg->oy < 0 || pg->oz < 0 || pg->ox + g->nx > pg->px ||
+            pg->oy + g->ny > pg->py || pg->oz + g->nz > pg->pz)) {
+    set_error("the Schroedinger grid must lie inside the Poisson box");
+    return HKP_E_ARG;
+  }
+  return HKP_OK;
+}
+
+int check_sp_opts(const hkp_sp_opts* sp, int nev) {
+  if (!sp) {
+    set_error("sp opts is NULL");
+    return HKP_E_ARG;
+  }
+  if (!(sp->n_holes >= 0.0 && sp->n_holes <= nev)) {
+    set_error("n_holes must satisfy 0 <= n_holes <= nev");
+    return HKP_E_ARG;
+  }
+  if (!finite_pos(sp->temperature_K) || !(sp->mixing > 0.0 && sp->mixing <= 1.0) ||
+      sp->history < 0 || sp->history > 8 || sp->max_iter < 1 || !finite_pos(sp->tol_V) ||
+      !finite_pos(sp->cg_tol) || sp->cg_max_iter < 1) {
+    set_error("sp opts: T > 0, 0 < mixing <= 1, history 0..8, max_iter >= 1, tol_V > 0, "
+              "cg_tol > 0, cg_max_iter >= 1");
+    return HKP_E_ARG;
+  }
+  return HKP_OK;
+}
+
 #define HKP_TRY(x)            \
   do {                        \
     int r_ = (x);             \
@@ -410,6 +450,148 @@ int hkp_autotune_block(const hkp_grid* grid, const hkp_material* mat, const hkp_
 
 const char* hkp_last_error(void) { return g_err.c_str(); }
 
-int hkp_version(void) { return 100; }
+size_t hkp_poisson_workspace_bytes(const hkp_pgrid* pgrid) {
+  if (check_pgrid(pgrid, nullptr) != HKP_OK) return 0;
+  return poisson_bytes(*pgrid);
+}
+
+int hkp_poisson(const hkp_pgrid* pgrid, double h_nm, const double* eps_r,
+                const uint8_t* dirichlet, const double* phi_fixed, const double* rho,
+                double* phi, double cg_tol, int32_t cg_max_iter, void* workspace,
+                size_t ws_bytes, void* hip_stream, int32_t* cg_iters, double* cg_relres) {
+  HKP_TRY(check_pgrid(pgrid, nullptr));
+  if (!finite_pos(h_nm) || !finite_pos(cg_tol) || cg_max_iter < 1) {
+    set_error("hkp_poisson: h > 0, cg_tol > 0, cg_max_iter >= 1");
+    return HKP_E_ARG;
+  }
+  if (!eps_r || !dirichlet || !phi_fixed || !phi || !workspace) {
+    set_error("hkp_poisson: eps_r, dirichlet, phi_fixed, phi and workspace must not be NULL");
+    return HKP_E_ARG;
+  }
+  if (ws_bytes < poisson_bytes(*pgrid)) {
+    set_error("workspace too small: need " + std::to_string(poisson_bytes(*pgrid)) + " bytes");
+    return HKP_E_WORKSPACE;
+  }
+  HKP_TRY(check_device());
+  PoissonArgs a{};
+  a.pg = *pgrid;
+  a.h = h_nm;
+  a.eps = eps_r;
+  a.dir = dirichlet;
+  a.phi_fixed = phi_fixed;
+  a.rho = rho;
+  a.phi = phi;
+  a.tol = cg_tol;
+  a.max_iter = cg_max_iter;
+  a.workspace = workspace;
+  a.stream = hip_stream;
+  int it = 0;
+  double rr = 0.0;
+  const int rc = guarded([&]() { return run_poisson(a, &it, &rr); });
+  if (cg_iters) *cg_iters = it;
+  if (cg_relres) *cg_relres = rr;
+  return rc;
+}
+
+int hkp_occupancy(int32_t nev, const double* E_eV, double n_holes, double T_K, double* f,
+                  double* mu_eV, void* hip_stream) {
+  if (nev < 1 || nev > 64 || !E_eV || !f || !(n_holes >= 0.0 && n_holes <= nev) ||
+      !finite_pos(T_K)) {
+    set_error("hkp_occupancy: 1 <= nev <= 64, 0 <= n_holes <= nev, T > 0, non-NULL E and f");
+    return HKP_E_ARG;
+  }
+  HKP_TRY(check_device());
+  return guarded([&]() {
+    hipError_t e = launch_occupancy(nev, E_eV, n_holes, kBoltzmann * T_K, f, mu_eV,
+                                    (hipStream_t)hip_stream);
+    if (e != hipSuccess) {
+      set_error(hipGetErrorString(e));
+      return HKP_E_HIP;
+    }
+    return HKP_OK;
+  });
+}
+
+int hkp_hole_density(const hkp_grid* grid, int32_t nev, const void* psi, const double* f,
+                     double* density, void* hip_stream) {
+  HKP_TRY(check_grid(grid));
+  if (nev < 1 || !psi || !f || !density) {
+    set_error("hkp_hole_density: nev >= 1 and non-NULL psi, f, density");
+    return HKP_E_ARG;
+  }
+  HKP_TRY(check_device());
+  return guarded([&]() {
+    const PGeom g{grid->nx, grid->ny, grid->nz, (long long)grid->nx * grid->ny * grid->nz};
+    const double h = grid->h_nm;
+    hipError_t e = launch_rho(g, 0, 0, 0, grid->nx, grid->ny, grid->nz, nev, psi, 6 * g.NP, f,
+                              1.0 / (h * h * h), nullptr, nullptr, density,
+                              (hipStream_t)hip_stream);
+    if (e != hipSuccess) {
+      set_error(hipGetErrorString(e));
+      return HKP_E_HIP;
+    }
+    return HKP_OK;
+  });
+}
+
+size_t hkp_sp_workspace_bytes(const hkp_grid* grid, const hkp_opts* opts,
+                              const hkp_pgrid* pgrid, const hkp_sp_opts* sp) {
+  if (check_grid(grid) != HKP_OK || check_opts(grid, opts) != HKP_OK ||
+      check_pgrid(pgrid, grid) != HKP_OK || check_sp_opts(sp, opts->nev) != HKP_OK)
+    return 0;
+  return sp_bytes(*grid, *opts, *pgrid, *sp);
+}
+
+int hkp_sp_solve(const hkp_grid* grid, const hkp_material* mat, const hkp_opts* opts,
+                 const hkp_pgrid* pgrid, const hkp_sp_opts* sp, const double* V_off_eV,
+                 const double* strain, const double B_T[3], const double* eps_r,
+                 const uint8_t* dirichlet, const double* phi_fixed, const double* rho_fixed,
+                 double* phi, double* eig_eV, void* psi, double* resid_eV, double* density,
+                 void* workspace, size_t ws_bytes, void* hip_stream, hkp_sp_stats* stats) {
+  HKP_TRY(check_grid(grid));
+  HKP_TRY(check_material(mat));
+  HKP_TRY(check_field(B_T));
+  HKP_TRY(check_opts(grid, opts));
+  HKP_TRY(check_pgrid(pgrid, grid));
+  HKP_TRY(check_sp_opts(sp, opts->nev));
+  if (!V_off_eV || !eps_r || !dirichlet || !phi_fixed || !phi || !eig_eV || !workspace) {
+    set_error("hkp_sp_solve: V_off, eps_r, dirichlet, phi_fixed, phi, eig and workspace "
+              "must not be NULL");
+    return HKP_E_ARG;
+  }
+  if ((opts->flags & HKP_FLAG_GRAPH) && hip_stream == nullptr) {
+    set_error("HKP_FLAG_GRAPH needs a non-default stream (the legacy stream cannot be captured)");
+    return HKP_E_ARG;
+  }
+  const size_t need = sp_bytes(*grid, *opts, *pgrid, *sp);
+  if (ws_bytes < need) {
+    set_error("workspace too small: need " + std::to_string(need) + " bytes");
+    return HKP_E_WORKSPACE;
+  }
+  HKP_TRY(check_device());
+  SPArgs a{};
+  a.grid = *grid;
+  a.mat = *mat;
+  a.opts = *opts;
+  a.pg = *pgrid;
+  a.sp = *sp;
+  a.V_off = V_off_eV;
+  a.strain = strain;
+  for (int i = 0; i < 3; ++i) a.B[i] = B_T[i];
+  a.eps = eps_r;
+  a.dir = dirichlet;
+  a.phi_fixed = phi_fixed;
+  a.rho_fixed = rho_fixed;
+  a.phi = phi;
+  a.eig = eig_eV;
+  a.psi = psi;
+  a.resid = resid_eV;
+  a.density = density;
+  a.workspace = workspace;
+  a.stream = hip_stream;
+  return guarded([&]() { return run_sp(a, stats); });
+}
+
+int hkp_version(void) { return 110; }
 
 }  // extern "C"

@@ -189,4 +189,62 @@ hipError_t launch_fill_int(int* p, int count, int value, hipStream_t s);
 hipError_t launch_init_coef(const Control& c, int batch, int degree, int kmax,
                             hipStream_t s);
 
+// ---------------------------------------------------------------------------
+// self-consistent loop: Poisson (conjugate gradients), occupancy, density,
+// Anderson mixing.  Poisson-box arrays are real [px][py][pz] (z fastest).
+// ---------------------------------------------------------------------------
+constexpr int kRedBlocks = 2048;   // workgroups of the grid-stride kernels (max)
+constexpr double kEoverEps0 = 1.602176634e-19 / 8.8541878128e-12 * 1e9;   // V nm
+constexpr double kBoltzmann = 8.617333262e-5;                             // eV/K
+
+struct PGeom {
+  int px, py, pz;
+  long long NP;
+};
+
+// conjugate-gradient scalars, device resident (no host round trip per step)
+struct CGState {
+  double rz, rr, bb, thr, alpha, beta;
+  int it, done, breakdown, pad;
+};
+
+int sp_blocks(long long n);
+size_t sp_partial_doubles();   // partial-sum scratch every SP launcher needs
+// link coefficients cx, cy, cz (+x, +y, +z links), D^-1 (0 on electrodes) and
+// the number of electrode nodes (*n_dir, device)
+hipError_t launch_pcoef(const PGeom& g, double h, const double* eps, const uint8_t* dir,
+                        double* cx, double* cy, double* cz, double* dinv, double* partial,
+                        double* n_dir, hipStream_t s);
+// phi (in: guess) gets its electrode values; r = b - L phi, z = D^-1 r, p = 0, and
+// the CG state (stop when |r| <= tol |b|)
+hipError_t launch_cg_init(const PGeom& g, const double* cx, const double* cy, const double* cz,
+                          const double* dinv, const uint8_t* dir, const double* phi_fixed,
+                          const double* rho, double scale, double* phi, double* r, double* z,
+                          double* p, double* partial, double tol, CGState* st, hipStream_t s);
+// one CG iteration (no-op once st->done): p_new = z + beta p_old, q = L p_new,
+// phi += alpha p_new, r -= alpha q, z = D^-1 r
+hipError_t launch_cg_iter(const PGeom& g, const double* cx, const double* cy, const double* cz,
+                          const double* dinv, const uint8_t* dir, double* z,
+                          const double* p_old, double* p_new, double* q, double* phi,
+                          double* r, double* partial, int max_iter, CGState* st,
+                          hipStream_t s);
+hipError_t launch_occupancy(int nev, const double* E, double n_holes, double kT, double* f,
+                            double* mu, hipStream_t s);
+// rho (P grid, may be null) = rho_fixed (may be null) + hole density embedded at
+// (ox, oy, oz); density (S grid, nm^-3, may be null).  psi: ABI layout
+// [nev][nx][ny][nz][6] complex with vstride complex entries between vectors.
+hipError_t launch_rho(const PGeom& g, int ox, int oy, int oz, int nx, int ny, int nz, int nev,
+                      const void* psi, long long vstride, const double* f, double inv_h3,
+                      const double* rho_fixed, double* rho, double* density, hipStream_t s);
+hipError_t launch_extract(int nx, int ny, int nz, const PGeom& g, int ox, int oy, int oz,
+                          const double* V_off, const double* phi, double* V, hipStream_t s);
+// F = phi_out - phi_in, *delta = max |F| (device)
+hipError_t launch_residual_max(const PGeom& g, const double* phi_in, const double* phi_out,
+                               double* F, double* partial, double* delta, hipStream_t s);
+// Anderson step over k stored entries (slots 0..k-1) of an m-slot history; the
+// current (x, F) is stored at `slot`; m = 0: linear mixing
+hipError_t launch_anderson(const PGeom& g, int k, int m, int slot, double mixing, double* x,
+                           const double* F, double* histX, double* histF, double* G,
+                           double* dots, double* gamma, double* partial, hipStream_t s);
+
 }  // namespace hkp

@@ -34,10 +34,6 @@ namespace hkp {
 
 namespace {
 
-struct HipError : std::runtime_error {
-  using std::runtime_error::runtime_error;
-};
-
 #define HKP_CHECK(x)                                                                   \
   do {                                                                                 \
     hipError_t e_ = (x);                                                               \

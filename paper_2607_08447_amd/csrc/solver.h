@@ -2,10 +2,16 @@
 #pragma once
 
 #include <functional>
+#include <stdexcept>
 
 #include "hkp_internal.h"
 
 namespace hkp {
+
+// a failed HIP call inside the host orchestration (mapped to HKP_E_HIP)
+struct HipError : std::runtime_error {
+  using std::runtime_error::runtime_error;
+};
 
 // launch shape of the stencil kernel: rows per tile, vectors of one tile run
 // side by side (1: vector-major order), rows staged global -> LDS directly
@@ -80,5 +86,47 @@ int guarded(const std::function<int()>& f);
 StencilTune autotuned(const hkp_grid& g, int nb, bool mixed);
 int run_autotune(const hkp_grid& g, int nb, bool mixed, bool strain, bool field, void* ws,
                  size_t ws_bytes, void* stream, hkp_tune* out);
+
+// ---- self-consistent loop and its Poisson solve
+struct PoissonArgs {
+  hkp_pgrid pg;           // offsets unused
+  double h;
+  const double* eps;
+  const uint8_t* dir;
+  const double* phi_fixed;
+  const double* rho;
+  double* phi;            // in: guess, out: solution
+  double tol;
+  int max_iter;
+  void* workspace;
+  void* stream;
+};
+size_t poisson_bytes(const hkp_pgrid& pg);
+int run_poisson(const PoissonArgs& a, int* iters, double* relres);
+
+struct SPArgs {
+  hkp_grid grid;
+  hkp_material mat;
+  hkp_opts opts;
+  hkp_pgrid pg;
+  hkp_sp_opts sp;
+  const double* V_off;
+  const double* strain;
+  double B[3];
+  const double* eps;
+  const uint8_t* dir;
+  const double* phi_fixed;
+  const double* rho_fixed;
+  double* phi;
+  double* eig;
+  void* psi;
+  double* resid;
+  double* density;
+  void* workspace;
+  void* stream;
+};
+size_t sp_bytes(const hkp_grid& g, const hkp_opts& o, const hkp_pgrid& pg,
+                const hkp_sp_opts& sp);
+int run_sp(const SPArgs& a, hkp_sp_stats* stats);
 
 }  // namespace hkp

@@ -1,0 +1,599 @@
+// Kernels of the self-consistent Schroedinger-Poisson loop (paper Sec. II.B,
+// Fig. 2a): the electrostatic potential from Poisson's equation by
+// Jacobi-preconditioned conjugate gradients, Fermi-Dirac occupancy of the hole
+// states, the hole density, and Anderson mixing of the potential.
+//
+// Poisson box layout (device, HBM): real [px][py][pz], x slowest and z fastest
+// (the ABI layout, so nothing is transposed on the way in or out).  Link
+// coefficients c = eps_link / h^2 are stored per node for its +x, +y and +z
+// links (eps_link: harmonic mean of the two nodes' eps_r, zero for a link that
+// would leave the box -- the field-free outer faces).  Electrode nodes keep
+// their potential; every CG vector is zero on them.
+//
+// All of these kernels stream through memory once per call: they are HBM-bound
+// and run one node per thread with grid-stride loops over a fixed grid of
+// kRedBlocks workgroups, whose per-workgroup partial sums are reduced in a fixed
+// order by one workgroup (the results do not depend on timing).
+#include <hip/hip_runtime.h>
+
+#include "hkp_internal.h"
+
+namespace hkp {
+
+namespace {
+
+constexpr int kThreads = 256;
+
+struct Geo {
+  int px, py, pz;
+  long long sx;   // py * pz (x stride)
+  int sy;         // pz (y stride)
+};
+
+__device__ __forceinline__ Geo geo(int px, int py, int pz) {
+  return Geo{px, py, pz, (long long)py * pz, pz};
+}
+
+__device__ __forceinline__ double harmonic(double a, double b) { return 2.0 * a * b / (a + b); }
+
+// block sum of up to 4 values; thread 0 writes them to out[0..n)
+template <int NV>
+__device__ __forceinline__ void block_sums(double (&v)[NV], double* out) {
+  __shared__ double sh[NV][kThreads / 64];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll
+  for (int k = 0; k < NV; ++k) {
+    double s = v[k];
+    for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
+    if (lane == 0) sh[k][w] = s;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int k = 0; k < NV; ++k) {
+      double s = 0.0;
+      for (int i = 0; i < kThreads / 64; ++i) s += sh[k][i];
+      out[k] = s;
+    }
+  }
+}
+
+// sums of nblk partial rows (stride NV) by one workgroup, fixed order
+template <int NV>
+__device__ __forceinline__ void reduce_partials(const double* partial, int nblk, double* out) {
+  double v[NV];
+#pragma unroll
+  for (int k = 0; k < NV; ++k) v[k] = 0.0;
+  for (int b = threadIdx.x; b < nblk; b += kThreads)
+#pragma unroll
+    for (int k = 0; k < NV; ++k) v[k] += partial[(long long)b * NV + k];
+  block_sums<NV>(v, out);
+}
+
+// ---------------------------------------------------------------------------
+// Poisson: link coefficients and the Jacobi preconditioner
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(kThreads)
+pcoef_kernel(long long NP, int px, int py, int pz, double inv_h2, const double* __restrict__ eps,
+             const uint8_t* __restrict__ dir, double* cx, double* cy, double* cz, double* dinv,
+             double* partial) {
+  const Geo g = geo(px, py, pz);
+  double nd = 0.0;   // electrode nodes (checked on the host: at least one)
+  for (long long i = (long long)blockIdx.x * kThreads + threadIdx.x; i < NP;
+       i += (long long)gridDim.x * kThreads) {
+    const int x = (int)(i / g.sx), y = (int)((i / g.sy) % py), z = (int)(i % pz);
+    const double e = eps[i];
+    const double ax = x + 1 < px ? harmonic(e, eps[i + g.sx]) * inv_h2 : 0.0;
+    const double ay = y + 1 < py ? harmonic(e, eps[i + g.sy]) * inv_h2 : 0.0;
+    const double az = z + 1 < pz ? harmonic(e, eps[i + 1]) * inv_h2 : 0.0;
+    const double bx = x > 0 ? harmonic(e, eps[i - g.sx]) * inv_h2 : 0.0;
+    const double by = y > 0 ? harmonic(e, eps[i - g.sy]) * inv_h2 : 0.0;
+    const double bz = z > 0 ? harmonic(e, eps[i - 1]) * inv_h2 : 0.0;
+    cx[i] = ax;
+    cy[i] = ay;
+    cz[i] = az;
+    const double diag = ax + ay + az + bx + by + bz;
+    dinv[i] = (dir[i] || !(diag > 0.0)) ? 0.0 : 1.0 / diag;
+    nd += dir[i] ? 1.0 : 0.0;
+  }
+  double v[1] = {nd};
+  block_sums<1>(v, partial + blockIdx.x);
+}
+
+// sum over the in-box links of node i of c (u_i - u_j), with u_j from `val`
+template <typename F>
+__device__ __forceinline__ double link_sum(long long i, int x, int y, int z, const Geo& g,
+                                           const double* __restrict__ cx,
+                                           const double* __restrict__ cy,
+                                           const double* __restrict__ cz, double ui, F val) {
+  double s = 0.0;
+  if (x + 1 < g.px) s += cx[i] * (ui - val(i + g.sx));
+  if (x > 0) s += cx[i - g.sx] * (ui - val(i - g.sx));
+  if (y + 1 < g.py) s += cy[i] * (ui - val(i + g.sy));
+  if (y > 0) s += cy[i - g.sy] * (ui - val(i - g.sy));
+  if (z + 1 < g.pz) s += cz[i] * (ui - val(i + 1));
+  if (z > 0) s += cz[i - 1] * (ui - val(i - 1));
+  return s;
+}
+
+// r = b - L phi on free nodes, b = (e/eps0) rho + electrode couplings; electrode
+// nodes take their fixed potential (free nodes read the fixed values of their
+// electrode neighbours, so nothing here reads what another thread writes);
+// z = D^-1 r; p = 0.  Partials: r.z, r.r, b.b.
+__global__ void __launch_bounds__(kThreads)
+cg_init_kernel(long long NP, int px, int py, int pz, const double* __restrict__ cx,
+               const double* __restrict__ cy, const double* __restrict__ cz,
+               const double* __restrict__ dinv, const uint8_t* __restrict__ dir,
+               const double* __restrict__ phi_fixed, const double* __restrict__ rho,
+               double scale, double* phi, double* r, double* zv, double* p, double* partial) {
+  const Geo g = geo(px, py, pz);
+  double acc[3] = {0.0, 0.0, 0.0};
+  for (long long i = (long long)blockIdx.x * kThreads + threadIdx.x; i < NP;
+       i += (long long)gridDim.x * kThreads) {
+    p[i] = 0.0;
+    if (dir[i]) {
+      phi[i] = phi_fixed[i];
+      r[i] = 0.0;
+      zv[i] = 0.0;
+      continue;
+    }
+    const int x = (int)(i / g.sx), y = (int)((i / g.sy) % py), z = (int)(i % pz);
+    const double ui = phi[i];
+    const double f = rho ? scale * rho[i] : 0.0;   // no charge array: rho = 0
+    const double lphi = link_sum(i, x, y, z, g, cx, cy, cz, ui, [&](long long j) {
+      return dir[j] ? phi_fixed[j] : phi[j];
+    });
+    // electrode couplings of b: sum over electrode neighbours of c phi_fixed
+    const double bdir = link_sum(i, x, y, z, g, cx, cy, cz, 0.0, [&](long long j) {
+      return dir[j] ? -phi_fixed[j] : 0.0;
+    });
+    const double ri = f - lphi;
+    const double zi = dinv[i] * ri;
+    r[i] = ri;
+    zv[i] = zi;
+    const double b = f + bdir;
+    acc[0] += ri * zi;
+    acc[1] += ri * ri;
+    acc[2] += b * b;
+  }
+  block_sums<3>(acc, partial + 3LL * blockIdx.x);
+}
+
+__global__ void __launch_bounds__(kThreads)
+cg_start_kernel(const double* partial, int nblk, double tol, CGState* st) {
+  __shared__ double s[3];
+  reduce_partials<3>(partial, nblk, s);
+  if (threadIdx.x == 0) {
+    st->rz = s[0];
+    st->rr = s[1];
+    st->bb = s[2];
+    st->thr = tol * tol * s[2];
+    st->beta = 0.0;
+    st->alpha = 0.0;
+    st->it = 0;
+    st->breakdown = 0;
+    st->done = s[1] <= st->thr ? 1 : 0;
+  }
+}
+
+// p_new = z + beta p_old (at the node and its neighbours: the old direction is
+// not overwritten, p_new goes to the other buffer); q = L p_new; partial p.q
+__global__ void __launch_bounds__(kThreads)
+cg_matvec_kernel(long long NP, int px, int py, int pz, const double* __restrict__ cx,
+                 const double* __restrict__ cy, const double* __restrict__ cz,
+                 const uint8_t* __restrict__ dir, const double* __restrict__ zv,
+                 const double* __restrict__ p_old, double* __restrict__ p_new,
+                 double* __restrict__ q, double* partial, const CGState* st) {
+  if (st->done) return;
+  const double beta = st->beta;
+  const Geo g = geo(px, py, pz);
+  double acc[1] = {0.0};
+  for (long long i = (long long)blockIdx.x * kThreads + threadIdx.x; i < NP;
+       i += (long long)gridDim.x * kThreads) {
+    if (dir[i]) {
+      p_new[i] = 0.0;
+      q[i] = 0.0;
+      continue;
+    }
+    const int x = (int)(i / g.sx), y = (int)((i / g.sy) % py), z = (int)(i % pz);
+    const double pi = zv[i] + beta * p_old[i];
+    // electrode neighbours hold z = p_old = 0, so their p_new is 0 as well
+    const double qi = link_sum(i, x, y, z, g, cx, cy, cz, pi, [&](long long j) {
+      return zv[j] + beta * p_old[j];
+    });
+    p_new[i] = pi;
+    q[i] = qi;
+    acc[0] += pi * qi;
+  }
+  block_sums<1>(acc, partial + blockIdx.x);
+}
+
+__global__ void __launch_bounds__(kThreads)
+cg_alpha_kernel(const double* partial, int nblk, CGState* st) {
+  if (st->done) return;
+  __shared__ double s[1];
+  reduce_partials<1>(partial, nblk, s);
+  if (threadIdx.x == 0) {
+    if (!(s[0] > 0.0)) {   // the operator is not positive definite on this vector
+      st->breakdown = 1;
+      st->done = 1;
+    } else {
+      st->alpha = st->rz / s[0];
+    }
+  }
+}
+
+// phi += alpha p; r -= alpha q; z = D^-1 r; partials r.z, r.r
+__global__ void __launch_bounds__(kThreads)
+cg_update_kernel(long long NP, const double* __restrict__ dinv, const double* __restrict__ p,
+                 const double* __restrict__ q, double* phi, double* r, double* zv,
+                 double* partial, const CGState* st) {
+  if (st->done) return;
+  const double alpha = st->alpha;
+  double acc[2] = {0.0, 0.0};
+  for (long long i = (long long)blockIdx.x * kThreads + threadIdx.x; i < NP;
+       i += (long long)gridDim.x * kThreads) {
+    const double pi = p[i];
+    phi[i] += alpha * pi;
+    const double ri = r[i] - alpha * q[i];
+    const double zi = dinv[i] * ri;
+    r[i] = ri;
+    zv[i] = zi;
+    acc[0] += ri * zi;
+    acc[1] += ri * ri;
+  }
+  block_sums<2>(acc, partial + 2LL * blockIdx.x);
+}
+
+__global__ void __launch_bounds__(kThreads)
+cg_beta_kernel(const double* partial, int nblk, int max_iter, CGState* st) {
+  if (st->done) return;
+  __shared__ double s[2];
+  reduce_partials<2>(partial, nblk, s);
+  if (threadIdx.x == 0) {
+    st->beta = st->rz > 0.0 ? s[0] / st->rz : 0.0;
+    st->rz = s[0];
+    st->rr = s[1];
+    st->it += 1;
+    st->done = (s[1] <= st->thr || st->it >= max_iter) ? 1 : 0;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// occupancy, density, potential on the Schroedinger grid
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double wave_sum(double v) {
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+__device__ __forceinline__ double wave_min(double v) {
+  for (int off = 32; off > 0; off >>= 1) v = fmin(v, __shfl_xor(v, off, 64));
+  return v;
+}
+__device__ __forceinline__ double wave_max(double v) {
+  for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));
+  return v;
+}
+
+// one wave; lane j holds state j (nev <= 64).  f = 1 / (1 + exp((E - mu) / kT))
+// written as (1 - tanh((E - mu) / 2kT)) / 2; mu by bisection on sum f = n_holes.
+__global__ void __launch_bounds__(64)
+occupancy_kernel(int nev, const double* __restrict__ E, double n_holes, double kT, double* f,
+                 double* mu_out) {
+  const int j = threadIdx.x;
+  const bool has = j < nev;
+  const double e = has ? E[j] : 0.0;
+  double lo = wave_min(has ? e : 1e300) - 60.0 * kT - 1.0;
+  double hi = wave_max(has ? e : -1e300) + 60.0 * kT + 1.0;
+  const double inv2kT = 0.5 / kT;
+  for (int it = 0; it < 200; ++it) {
+    const double mid = 0.5 * (lo + hi);
+    const double s = wave_sum(has ? 0.5 * (1.0 - tanh((e - mid) * inv2kT)) : 0.0);
+    if (s > n_holes) hi = mid; else lo = mid;
+  }
+  const double mu = 0.5 * (lo + hi);
+  if (has) f[j] = 0.5 * (1.0 - tanh((e - mu) * inv2kT));
+  if (j == 0 && mu_out) *mu_out = mu;
+}
+
+// rho (P grid) = rho_fixed + embedded hole density; density (S grid) =
+// sum_n f_n sum_c |psi_n,c|^2 / h^3 with psi [nev][nx][ny][nz][6] (vector
+// stride vstride complex entries)
+__global__ void __launch_bounds__(kThreads)
+rho_kernel(long long NP, int px, int py, int pz, int ox, int oy, int oz, int nx, int ny, int nz,
+           int nev, const double2* __restrict__ psi, long long vstride,
+           const double* __restrict__ f, double inv_h3, const double* __restrict__ rho_fixed,
+           double* rho, double* density) {
+  const Geo g = geo(px, py, pz);
+  for (long long i = (long long)blockIdx.x * kThreads + threadIdx.x; i < NP;
+       i += (long long)gridDim.x * kThreads) {
+    const int x = (int)(i / g.sx) - ox, y = (int)((i / g.sy) % py) - oy, z = (int)(i % pz) - oz;
+    double v = rho_fixed ? rho_fixed[i] : 0.0;
+    if (x >= 0 && x < nx && y >= 0 && y < ny && z >= 0 && z < nz) {
+      const long long s = ((long long)x * ny + y) * nz + z;
+      double d = 0.0;
+      for (int n = 0; n < nev; ++n) {
+        const double2* q = psi + n * vstride + 6 * s;
+        double a = 0.0;
+#pragma unroll
+        for (int c = 0; c < 6; ++c) a += q[c].x * q[c].x + q[c].y * q[c].y;
+        d += f[n] * a;
+      }
+      d *= inv_h3;
+      v += d;
+      if (density) density[s] = d;
+    }
+    if (rho) rho[i] = v;
+  }
+}
+
+// V (S grid) = V_off + phi at the embedded nodes
+__global__ void __launch_bounds__(kThreads)
+extract_kernel(long long NS, int nx, int ny, int nz, int py, int pz, int ox, int oy, int oz,
+               const double* __restrict__ V_off, const double* __restrict__ phi, double* V) {
+  for (long long s = (long long)blockIdx.x * kThreads + threadIdx.x; s < NS;
+       s += (long long)gridDim.x * kThreads) {
+    const int x = (int)(s / ((long long)ny * nz)), y = (int)((s / nz) % ny), z = (int)(s % nz);
+    V[s] = V_off[s] + phi[((long long)(x + ox) * py + (y + oy)) * pz + (z + oz)];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Anderson mixing
+// ---------------------------------------------------------------------------
+// F = phi_out - phi_in; partial max |F|
+__global__ void __launch_bounds__(kThreads)
+residual_kernel(long long NP, const double* __restrict__ phi_in,
+                const double* __restrict__ phi_out, double* F, double* partial) {
+  double m = 0.0;
+  for (long long i = (long long)blockIdx.x * kThreads + threadIdx.x; i < NP;
+       i += (long long)gridDim.x * kThreads) {
+    const double d = phi_out[i] - phi_in[i];
+    F[i] = d;
+    m = fmax(m, fabs(d));
+  }
+  __shared__ double sh[kThreads / 64];
+  for (int off = 32; off > 0; off >>= 1) m = fmax(m, __shfl_down(m, off, 64));
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = m;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double r = 0.0;
+    for (int k = 0; k < kThreads / 64; ++k) r = fmax(r, sh[k]);
+    partial[blockIdx.x] = r;
+  }
+}
+
+__global__ void __launch_bounds__(kThreads)
+max_reduce_kernel(const double* partial, int nblk, double* out) {
+  double m = 0.0;
+  for (int b = threadIdx.x; b < nblk; b += kThreads) m = fmax(m, partial[b]);
+  __shared__ double sh[kThreads / 64];
+  for (int off = 32; off > 0; off >>= 1) m = fmax(m, __shfl_down(m, off, 64));
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = m;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double r = 0.0;
+    for (int k = 0; k < kThreads / 64; ++k) r = fmax(r, sh[k]);
+    *out = r;
+  }
+}
+
+// partials of F.F and F.F_j for the k stored residuals (slots listed in order)
+template <int K>
+__global__ void __launch_bounds__(kThreads)
+anderson_dots_kernel(long long NP, const double* __restrict__ F,
+                     const double* __restrict__ histF, double* partial) {
+  double acc[K + 1];
+#pragma unroll
+  for (int j = 0; j <= K; ++j) acc[j] = 0.0;
+  for (long long i = (long long)blockIdx.x * kThreads + threadIdx.x; i < NP;
+       i += (long long)gridDim.x * kThreads) {
+    const double fi = F[i];
+    acc[0] += fi * fi;
+#pragma unroll
+    for (int j = 0; j < K; ++j) acc[j + 1] += fi * histF[(long long)j * NP + i];
+  }
+  block_sums<K + 1>(acc, partial + (long long)(K + 1) * blockIdx.x);
+}
+
+template <int K>
+__global__ void __launch_bounds__(kThreads)
+anderson_dots_reduce_kernel(const double* partial, int nblk, double* dots) {
+  __shared__ double s[K + 1];
+  reduce_partials<K + 1>(partial, nblk, s);
+  __syncthreads();
+  if (threadIdx.x <= K) dots[threadIdx.x] = s[threadIdx.x];
+}
+
+// Least squares over the k stored (x_j, F_j): minimise |F - sum_j g_j (F - F_j)|
+// through the normal equations (k <= 8, a relative 1e-12 ridge keeps them
+// solvable when two stored residuals nearly coincide); then record the new
+// entry's row of the stored Gram matrix G[j][l] = F_j . F_l at `slot`.
+__global__ void anderson_coef_kernel(int k, int m, int slot, const double* __restrict__ dots,
+                                     double* G, double* gamma) {
+  if (threadIdx.x != 0) return;
+  const double FF = dots[0];
+  double A[8][9];
+  for (int j = 0; j < k; ++j) {
+    for (int l = 0; l < k; ++l)
+      A[j][l] = FF - dots[1 + j] - dots[1 + l] + G[j * m + l];
+    A[j][k] = FF - dots[1 + j];
+  }
+  double tr = 0.0;
+  for (int j = 0; j < k; ++j) tr += A[j][j];
+  const double ridge = 1e-12 * (tr > 0.0 ? tr / (k > 0 ? k : 1) : 1.0);
+  for (int j = 0; j < k; ++j) A[j][j] += ridge;
+  // Gaussian elimination with partial pivoting
+  for (int c = 0; c < k; ++c) {
+    int piv = c;
+    for (int r = c + 1; r < k; ++r)
+      if (fabs(A[r][c]) > fabs(A[piv][c])) piv = r;
+    if (piv != c)
+      for (int l = 0; l <= k; ++l) {
+        const double t = A[c][l];
+        A[c][l] = A[piv][l];
+        A[piv][l] = t;
+      }
+    const double d = A[c][c];
+    for (int r = c + 1; r < k; ++r) {
+      const double fct = d != 0.0 ? A[r][c] / d : 0.0;
+      for (int l = c; l <= k; ++l) A[r][l] -= fct * A[c][l];
+    }
+  }
+  for (int c = k - 1; c >= 0; --c) {
+    double s = A[c][k];
+    for (int l = c + 1; l < k; ++l) s -= A[c][l] * gamma[l];
+    gamma[c] = A[c][c] != 0.0 ? s / A[c][c] : 0.0;
+  }
+  // the new entry (current x, F) replaces `slot`; its dots with the other
+  // stored residuals are the ones just computed (slot j holds stored entry j)
+  for (int j = 0; j < m; ++j) {
+    if (j == slot) continue;
+    if (j < k) {
+      G[slot * m + j] = dots[1 + j];
+      G[j * m + slot] = dots[1 + j];
+    }
+  }
+  G[slot * m + slot] = FF;
+}
+
+// x <- x + a F - sum_j g_j ((x - x_j) + a (F - F_j)); the current (x, F) is
+// then stored in `slot` (after every stored entry has been read at this node)
+template <int K>
+__global__ void __launch_bounds__(kThreads)
+anderson_update_kernel(long long NP, int slot, double a, const double* __restrict__ gamma,
+                       double* x, const double* __restrict__ F, double* histX, double* histF) {
+  double g[K > 0 ? K : 1];
+#pragma unroll
+  for (int j = 0; j < K; ++j) g[j] = gamma[j];
+  for (long long i = (long long)blockIdx.x * kThreads + threadIdx.x; i < NP;
+       i += (long long)gridDim.x * kThreads) {
+    const double xi = x[i], fi = F[i];
+    double v = xi + a * fi;
+#pragma unroll
+    for (int j = 0; j < K; ++j)
+      v -= g[j] * ((xi - histX[(long long)j * NP + i]) + a * (fi - histF[(long long)j * NP + i]));
+    if (slot >= 0) {
+      histX[(long long)slot * NP + i] = xi;
+      histF[(long long)slot * NP + i] = fi;
+    }
+    x[i] = v;
+  }
+}
+
+__global__ void __launch_bounds__(kThreads)
+sum1_kernel(const double* partial, int nblk, double* out) {
+  __shared__ double s[1];
+  reduce_partials<1>(partial, nblk, s);
+  if (threadIdx.x == 0) *out = s[0];
+}
+
+template <int K>
+void anderson_k(const PGeom& g, int nb, int m, int slot, double mixing, double* x,
+                const double* F, double* histX, double* histF, double* G, double* dots,
+                double* gamma, double* partial, hipStream_t s) {
+  if (m > 0) {
+    anderson_dots_kernel<K><<<nb, kThreads, 0, s>>>(g.NP, F, histF, partial);
+    anderson_dots_reduce_kernel<K><<<1, kThreads, 0, s>>>(partial, nb, dots);
+    anderson_coef_kernel<<<1, 64, 0, s>>>(K, m, slot, dots, G, gamma);
+  }
+  anderson_update_kernel<K><<<nb, kThreads, 0, s>>>(g.NP, m > 0 ? slot : -1, mixing, gamma, x,
+                                                     F, histX, histF);
+}
+
+}  // namespace
+
+int sp_blocks(long long n) {
+  const long long b = (n + kThreads - 1) / kThreads;
+  return (int)(b < kRedBlocks ? (b > 0 ? b : 1) : kRedBlocks);
+}
+
+size_t sp_partial_doubles() { return (size_t)kRedBlocks * 9; }
+
+hipError_t launch_pcoef(const PGeom& g, double h, const double* eps, const uint8_t* dir,
+                        double* cx, double* cy, double* cz, double* dinv, double* partial,
+                        double* n_dir, hipStream_t s) {
+  const int nb = sp_blocks(g.NP);
+  pcoef_kernel<<<nb, kThreads, 0, s>>>(g.NP, g.px, g.py, g.pz, 1.0 / (h * h), eps, dir, cx, cy,
+                                       cz, dinv, partial);
+  sum1_kernel<<<1, kThreads, 0, s>>>(partial, nb, n_dir);
+  return hipGetLastError();
+}
+
+hipError_t launch_cg_init(const PGeom& g, const double* cx, const double* cy, const double* cz,
+                          const double* dinv, const uint8_t* dir, const double* phi_fixed,
+                          const double* rho, double scale, double* phi, double* r, double* z,
+                          double* p, double* partial, double tol, CGState* st, hipStream_t s) {
+  const int nb = sp_blocks(g.NP);
+  cg_init_kernel<<<nb, kThreads, 0, s>>>(g.NP, g.px, g.py, g.pz, cx, cy, cz, dinv, dir,
+                                         phi_fixed, rho, scale, phi, r, z, p, partial);
+  cg_start_kernel<<<1, kThreads, 0, s>>>(partial, nb, tol, st);
+  return hipGetLastError();
+}
+
+hipError_t launch_cg_iter(const PGeom& g, const double* cx, const double* cy, const double* cz,
+                          const double* dinv, const uint8_t* dir, double* z,
+                          const double* p_old, double* p_new, double* q, double* phi,
+                          double* r, double* partial, int max_iter, CGState* st,
+                          hipStream_t s) {
+  const int nb = sp_blocks(g.NP);
+  cg_matvec_kernel<<<nb, kThreads, 0, s>>>(g.NP, g.px, g.py, g.pz, cx, cy, cz, dir, z, p_old,
+                                           p_new, q, partial, st);
+  cg_alpha_kernel<<<1, kThreads, 0, s>>>(partial, nb, st);
+  cg_update_kernel<<<nb, kThreads, 0, s>>>(g.NP, dinv, p_new, q, phi, r, z, partial, st);
+  cg_beta_kernel<<<1, kThreads, 0, s>>>(partial, nb, max_iter, st);
+  return hipGetLastError();
+}
+
+hipError_t launch_occupancy(int nev, const double* E, double n_holes, double kT, double* f,
+                            double* mu, hipStream_t s) {
+  if (nev < 1 || nev > 64) return hipErrorInvalidValue;
+  occupancy_kernel<<<1, 64, 0, s>>>(nev, E, n_holes, kT, f, mu);
+  return hipGetLastError();
+}
+
+hipError_t launch_rho(const PGeom& g, int ox, int oy, int oz, int nx, int ny, int nz, int nev,
+                      const void* psi, long long vstride, const double* f, double inv_h3,
+                      const double* rho_fixed, double* rho, double* density, hipStream_t s) {
+  rho_kernel<<<sp_blocks(g.NP), kThreads, 0, s>>>(g.NP, g.px, g.py, g.pz, ox, oy, oz, nx, ny, nz,
+                                                  nev, (const double2*)psi, vstride, f, inv_h3,
+                                                  rho_fixed, rho, density);
+  return hipGetLastError();
+}
+
+hipError_t launch_extract(int nx, int ny, int nz, const PGeom& g, int ox, int oy, int oz,
+                          const double* V_off, const double* phi, double* V, hipStream_t s) {
+  const long long NS = (long long)nx * ny * nz;
+  extract_kernel<<<sp_blocks(NS), kThreads, 0, s>>>(NS, nx, ny, nz, g.py, g.pz, ox, oy, oz,
+                                                    V_off, phi, V);
+  return hipGetLastError();
+}
+
+hipError_t launch_residual_max(const PGeom& g, const double* phi_in, const double* phi_out,
+                               double* F, double* partial, double* delta, hipStream_t s) {
+  const int nb = sp_blocks(g.NP);
+  residual_kernel<<<nb, kThreads, 0, s>>>(g.NP, phi_in, phi_out, F, partial);
+  max_reduce_kernel<<<1, kThreads, 0, s>>>(partial, nb, delta);
+  return hipGetLastError();
+}
+
+hipError_t launch_anderson(const PGeom& g, int k, int m, int slot, double mixing, double* x,
+                           const double* F, double* histX, double* histF, double* G,
+                           double* dots, double* gamma, double* partial, hipStream_t s) {
+  if (k < 0 || k > 8 || k > m || m > 8) return hipErrorInvalidValue;
+  const int nb = sp_blocks(g.NP);
+  switch (k) {
+    case 0: anderson_k<0>(g, nb, m, slot, mixing, x, F, histX, histF, G, dots, gamma, partial, s); break;
+    case 1: anderson_k<1>(g, nb, m, slot, mixing, x, F, histX, histF, G, dots, gamma, partial, s); break;
+    case 2: anderson_k<2>(g, nb, m, slot, mixing, x, F, histX, histF, G, dots, gamma, partial, s); break;
+    case 3: anderson_k<3>(g, nb, m, slot, mixing, x, F, histX, histF, G, dots, gamma, partial, s); break;
+    case 4: anderson_k<4>(g, nb, m, slot, mixing, x, F, histX, histF, G, dots, gamma, partial, s); break;
+    case 5: anderson_k<5>(g, nb, m, slot, mixing, x, F, histX, histF, G, dots, gamma, partial, s); break;
+    case 6: anderson_k<6>(g, nb, m, slot, mixing, x, F, histX, histF, G, dots, gamma, partial, s); break;
+    case 7: anderson_k<7>(g, nb, m, slot, mixing, x, F, histX, histF, G, dots, gamma, partial, s); break;
+    default: anderson_k<8>(g, nb, m, slot, mixing, x, F, histX, histF, G, dots, gamma, partial, s); break;
+  }
+  return hipGetLastError();
+}
+
+}  // namespace hkp

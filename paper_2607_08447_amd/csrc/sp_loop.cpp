@@ -1,0 +1,318 @@
+// Host orchestration of the self-consistent Schroedinger-Poisson loop (paper
+// Sec. II.B, Fig. 2a) and of the stand-alone Poisson call.  Every step runs in
+// the kernels of sp.hip and the eigensolver; the host only sequences launches
+// and reads back one convergence scalar per conjugate-gradient chunk and per
+// loop iteration.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <string>
+
+#include "hkp_internal.h"
+#include "solver.h"
+
+#define HKP_CHECK(x)                                                              \
+  do {                                                                            \
+    hipError_t e_ = (x);                                                          \
+    if (e_ != hipSuccess)                                                         \
+      throw HipError(std::string(#x) + ": " + hipGetErrorString(e_));             \
+  } while (0)
+
+namespace hkp {
+
+namespace {
+
+size_t al(size_t x) { return (x + 255) & ~size_t(255); }
+
+struct Carve {
+  char* base;
+  size_t off = 0;
+  template <typename T>
+  T* take(size_t count) {
+    T* p = reinterpret_cast<T*>(base ? base + off : nullptr);
+    off += al(count * sizeof(T));
+    return p;
+  }
+};
+
+struct PoissonWS {
+  double *cx, *cy, *cz, *dinv, *r, *z, *p0, *p1, *q, *partial, *n_dir;
+  CGState* st;
+};
+
+PoissonWS carve_poisson(Carve& c, long long NP) {
+  PoissonWS w;
+  w.cx = c.take<double>(NP);
+  w.cy = c.take<double>(NP);
+  w.cz = c.take<double>(NP);
+  w.dinv = c.take<double>(NP);
+  w.r = c.take<double>(NP);
+  w.z = c.take<double>(NP);
+  w.p0 = c.take<double>(NP);
+  w.p1 = c.take<double>(NP);
+  w.q = c.take<double>(NP);
+  w.partial = c.take<double>(sp_partial_doubles());
+  w.n_dir = c.take<double>(1);
+  w.st = c.take<CGState>(1);
+  return w;
+}
+
+PGeom geom(const hkp_pgrid& pg) {
+  return PGeom{pg.px, pg.py, pg.pz, (long long)pg.px * pg.py * pg.pz};
+}
+
+// link coefficients and preconditioner; fails without an electrode node
+int poisson_prepare(const PGeom& g, double h, const double* eps, const uint8_t* dir,
+                    const PoissonWS& w, hipStream_t s) {
+  HKP_CHECK(launch_pcoef(g, h, eps, dir, w.cx, w.cy, w.cz, w.dinv, w.partial, w.n_dir, s));
+  double nd = 0.0;
+  HKP_CHECK(hipMemcpyAsync(&nd, w.n_dir, sizeof(double), hipMemcpyDeviceToHost, s));
+  HKP_CHECK(hipStreamSynchronize(s));
+  if (!(nd > 0.0)) {
+    set_error("the Poisson box has no electrode (Dirichlet) node");
+    return HKP_E_ARG;
+  }
+  return HKP_OK;
+}
+
+// conjugate gradients from the guess in phi; launches run in chunks, the host
+// reads the device state once per chunk (iterations after convergence are no-ops)
+int poisson_cg(const PGeom& g, const uint8_t* dir, const double* phi_fixed, const double* rho,
+               double* phi, double tol, int max_iter, const PoissonWS& w, hipStream_t s,
+               int* iters, double* relres) {
+  HKP_CHECK(launch_cg_init(g, w.cx, w.cy, w.cz, w.dinv, dir, phi_fixed, rho, kEoverEps0, phi,
+                           w.r, w.z, w.p0, w.partial, tol, w.st, s));
+  CGState h{};
+  long long launched = 0;
+  constexpr int kChunk = 32;
+  for (;;) {
+    HKP_CHECK(hipMemcpyAsync(&h, w.st, sizeof(CGState), hipMemcpyDeviceToHost, s));
+    HKP_CHECK(hipStreamSynchronize(s));
+    if (h.done || launched >= max_iter) break;
+    for (int c = 0; c < kChunk; ++c, ++launched) {
+      const bool even = (launched % 2) == 0;
+      double* po = even ? w.p0 : w.p1;
+      double* pn = even ? w.p1 : w.p0;
+      HKP_CHECK(launch_cg_iter(g, w.cx, w.cy, w.cz, w.dinv, dir, w.z, po, pn, w.q, phi, w.r,
+                               w.partial, max_iter, w.st, s));
+    }
+  }
+  if (iters) *iters = h.it;
+  if (relres) *relres = h.bb > 0.0 ? std::sqrt(h.rr / h.bb) : 0.0;
+  if (h.breakdown) {
+    set_error("Poisson CG breakdown: the operator is not positive definite (a free region "
+              "without a path to an electrode?)");
+    return HKP_E_NUMERICAL;
+  }
+  return h.rr <= h.thr ? HKP_OK : HKP_W_NOT_CONVERGED;
+}
+
+double seconds_since(std::chrono::steady_clock::time_point t0) {
+  return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+}
+
+}  // namespace
+
+size_t poisson_bytes(const hkp_pgrid& pg) {
+  Carve c{nullptr};
+  carve_poisson(c, geom(pg).NP);
+  return c.off;
+}
+
+int run_poisson(const PoissonArgs& a, int* iters, double* relres) {
+  const PGeom g = geom(a.pg);
+  hipStream_t s = reinterpret_cast<hipStream_t>(a.stream);
+  Carve c{reinterpret_cast<char*>(a.workspace)};
+  const PoissonWS w = carve_poisson(c, g.NP);
+  const int rc = poisson_prepare(g, a.h, a.eps, a.dir, w, s);
+  if (rc != HKP_OK) return rc;
+  return poisson_cg(g, a.dir, a.phi_fixed, a.rho, a.phi, a.tol, a.max_iter, w, s, iters,
+                    relres);
+}
+
+namespace {
+
+struct SPLayout {
+  size_t solver;   // eigensolver workspace (first, at offset 0)
+  double2* block;  // [nb][nx][ny][nz][6] ABI spinors: restart block and psi
+  double *V, *eig, *resid, *f, *mu;
+  PoissonWS pw;
+  double *phi_out, *rho, *F, *histX, *histF, *G, *dots, *gamma, *delta;
+  size_t total;
+};
+
+SPLayout carve_sp(char* base, const Plan& p, const hkp_pgrid& pg, int m) {
+  SPLayout L;
+  Carve c{base};
+  L.solver = al(plan_bytes(p));
+  c.off = L.solver;
+  const long long NP = geom(pg).NP;
+  L.block = c.take<double2>((size_t)p.nb * p.n6);
+  L.V = c.take<double>(p.N);
+  L.eig = c.take<double>(p.nb);
+  L.resid = c.take<double>(p.nb);
+  L.f = c.take<double>(p.nb);
+  L.mu = c.take<double>(1);
+  L.pw = carve_poisson(c, NP);
+  L.phi_out = c.take<double>(NP);
+  L.rho = c.take<double>(NP);
+  L.F = c.take<double>(NP);
+  L.histX = c.take<double>((size_t)std::max(m, 1) * NP);
+  L.histF = c.take<double>((size_t)std::max(m, 1) * NP);
+  L.G = c.take<double>(64);
+  L.dots = c.take<double>(16);
+  L.gamma = c.take<double>(8);
+  L.delta = c.take<double>(1);
+  L.total = c.off;
+  return L;
+}
+
+}  // namespace
+
+size_t sp_bytes(const hkp_grid& g, const hkp_opts& o, const hkp_pgrid& pg,
+                const hkp_sp_opts& sp) {
+  return carve_sp(nullptr, make_plan(g, o, 1), pg, sp.history).total;
+}
+
+int run_sp(const SPArgs& a, hkp_sp_stats* stats) {
+  const auto t_start = std::chrono::steady_clock::now();
+  hipStream_t s = reinterpret_cast<hipStream_t>(a.stream);
+  const Plan p = make_plan(a.grid, a.opts, 1);
+  const PGeom g = geom(a.pg);
+  const int m = a.sp.history;
+  char* base = reinterpret_cast<char*>(a.workspace);
+  const SPLayout L = carve_sp(base, p, a.pg, m);
+  const int ox = a.pg.ox, oy = a.pg.oy, oz = a.pg.oz;
+  const double h = a.grid.h_nm;
+
+  hkp_sp_stats st{};
+  st.solve_status = HKP_OK;
+  st.f_last = 0.0;
+  double t_sch = 0.0, t_poi = 0.0;
+
+  int rc = poisson_prepare(g, h, a.eps, a.dir, L.pw, s);
+  if (rc != HKP_OK) return rc;
+  // the fixed charge alone (the hole part of rho is added every iteration)
+  HKP_CHECK(launch_rho(g, ox, oy, oz, p.nx, p.ny, p.nz, 0, nullptr, 0, nullptr, 0.0,
+                       a.rho_fixed, L.rho, nullptr, s));
+  if (!(a.sp.flags & HKP_SP_PHI0)) {
+    // start from the hole-free potential
+    HKP_CHECK(hipMemsetAsync(a.phi, 0, (size_t)g.NP * sizeof(double), s));
+    int it = 0;
+    const auto t0 = std::chrono::steady_clock::now();
+    rc = poisson_cg(g, a.dir, a.phi_fixed, L.rho, a.phi, a.sp.cg_tol, a.sp.cg_max_iter, L.pw, s,
+                    &it, nullptr);
+    t_poi += seconds_since(t0);
+    st.cg_iters += it;
+    if (rc < 0) return rc;
+  } else {
+    // the caller's potential, with the electrode values imposed
+    HKP_CHECK(launch_cg_init(g, L.pw.cx, L.pw.cy, L.pw.cz, L.pw.dinv, a.dir, a.phi_fixed, L.rho,
+                             kEoverEps0, a.phi, L.pw.r, L.pw.z, L.pw.p0, L.pw.partial, 1.0,
+                             L.pw.st, s));
+  }
+
+  SolveArgs sa{};
+  sa.plan = p;
+  sa.mat = a.mat;
+  sa.V = L.V;
+  sa.strain = a.strain;
+  for (int i = 0; i < 3; ++i) sa.B[i] = a.B[i];
+  sa.eig = L.eig;
+  sa.psi = L.block;
+  sa.resid = L.resid;
+  sa.workspace = base;
+  sa.stream = a.stream;
+  sa.tol = a.opts.tol_eV;
+  sa.max_iter = a.opts.max_iter;
+  sa.seed = a.opts.seed;
+  sa.st = autotuned(a.grid, p.nb, p.mixed);
+  sa.graph_chunk = 4;
+  const int base_flags = (a.opts.flags & ~(HKP_FLAG_X0 | HKP_FLAG_X0_NEV)) | HKP_FLAG_PSI_BLOCK;
+
+  const double kT = kBoltzmann * a.sp.temperature_K;
+  int count = 0;   // entries pushed into the Anderson history
+  bool converged = false;
+  double delta = 0.0;
+  int it = 0;
+  for (it = 1; it <= a.sp.max_iter; ++it) {
+    // Schroedinger: V = V_off + phi on the embedded grid; restart from the last block
+    auto t0 = std::chrono::steady_clock::now();
+    HKP_CHECK(launch_extract(p.nx, p.ny, p.nz, g, ox, oy, oz, a.V_off, a.phi, L.V, s));
+    sa.X0 = it > 1 ? L.block : nullptr;
+    sa.flags = base_flags | (it > 1 ? HKP_FLAG_X0 : 0);
+    hkp_stats sst{};
+    rc = run_solve(sa, &sst);
+    if (rc < 0) return rc;
+    if (rc != HKP_OK) st.solve_status = rc;
+    st.schroedinger_iters += sst.iters;
+    t_sch += seconds_since(t0);
+
+    // occupancy, hole density, Poisson from the current potential
+    t0 = std::chrono::steady_clock::now();
+    HKP_CHECK(launch_occupancy(p.nev, L.eig, a.sp.n_holes, kT, L.f, L.mu, s));
+    HKP_CHECK(launch_rho(g, ox, oy, oz, p.nx, p.ny, p.nz, p.nev, L.block, p.n6, L.f,
+                         1.0 / (h * h * h), a.rho_fixed, L.rho, nullptr, s));
+    HKP_CHECK(hipMemcpyAsync(L.phi_out, a.phi, (size_t)g.NP * sizeof(double),
+                             hipMemcpyDeviceToDevice, s));
+    int cgit = 0;
+    rc = poisson_cg(g, a.dir, a.phi_fixed, L.rho, L.phi_out, a.sp.cg_tol, a.sp.cg_max_iter,
+                    L.pw, s, &cgit, nullptr);
+    st.cg_iters += cgit;
+    if (rc < 0) return rc;
+    if (rc != HKP_OK) st.poisson_status = rc;
+    HKP_CHECK(launch_residual_max(g, a.phi, L.phi_out, L.F, L.pw.partial, L.delta, s));
+    HKP_CHECK(hipMemcpyAsync(&delta, L.delta, sizeof(double), hipMemcpyDeviceToHost, s));
+    HKP_CHECK(hipStreamSynchronize(s));
+    t_poi += seconds_since(t0);
+    if (!std::isfinite(delta)) {
+      set_error("self-consistent loop diverged (non-finite potential update)");
+      return HKP_E_NUMERICAL;
+    }
+    if (delta <= a.sp.tol_V) {
+      converged = true;
+      break;
+    }
+    if (it == a.sp.max_iter) break;
+    // next input potential
+    const int k = std::min(count, m);
+    const int slot = m > 0 ? count % m : -1;
+    HKP_CHECK(launch_anderson(g, k, m, slot, a.sp.mixing, a.phi, L.F, L.histX, L.histF, L.G,
+                              L.dots, L.gamma, L.pw.partial, s));
+    ++count;
+  }
+  if (it > a.sp.max_iter) it = a.sp.max_iter;
+
+  // outputs: the eigenpairs and density of the last input potential
+  HKP_CHECK(hipMemcpyAsync(a.eig, L.eig, (size_t)p.nev * sizeof(double),
+                           hipMemcpyDeviceToDevice, s));
+  if (a.resid)
+    HKP_CHECK(hipMemcpyAsync(a.resid, L.resid, (size_t)p.nev * sizeof(double),
+                             hipMemcpyDeviceToDevice, s));
+  if (a.psi)
+    HKP_CHECK(hipMemcpyAsync(a.psi, L.block, (size_t)p.nev * p.n6 * sizeof(double2),
+                             hipMemcpyDeviceToDevice, s));
+  if (a.density)
+    HKP_CHECK(launch_rho(g, ox, oy, oz, p.nx, p.ny, p.nz, p.nev, L.block, p.n6, L.f,
+                         1.0 / (h * h * h), nullptr, nullptr, a.density, s));
+  double mu = 0.0;
+  double flast = 0.0;
+  HKP_CHECK(hipMemcpyAsync(&mu, L.mu, sizeof(double), hipMemcpyDeviceToHost, s));
+  HKP_CHECK(hipMemcpyAsync(&flast, L.f + (p.nev - 1), sizeof(double), hipMemcpyDeviceToHost, s));
+  HKP_CHECK(hipStreamSynchronize(s));
+
+  st.iters = it;
+  st.converged = converged ? 1 : 0;
+  st.delta_V = delta;
+  st.mu_eV = mu;
+  st.f_last = flast;
+  st.nb = p.nb;
+  st.seconds = seconds_since(t_start);
+  st.t_schroedinger = t_sch;
+  st.t_poisson = t_poi;
+  if (stats) *stats = st;
+  if (!converged) return HKP_W_NOT_CONVERGED;
+  return st.solve_status != HKP_OK ? st.solve_status : HKP_OK;
+}
+
+}  // namespace hkp

@@ -181,3 +181,49 @@ def test_empty_and_oversized_inputs_are_rejected():
                                  C.byref(st)) == L.HKP_E_ARG
     assert b"X0" in L.lib.hkp_last_error()
     o.flags = 0
+
+
+def test_sp_entry_points_reject_bad_arguments():
+    """The Poisson / occupancy / density / self-consistent entry points validate
+    sizes, options and pointers before any GPU work."""
+    L, g, m, o = _structs()
+    fake = C.c_void_p(0x1000)
+    B = (C.c_double * 3)(0.0, 0.0, 0.0)
+    o.nev, o.nb = 8, 16
+    pg = L.hkp_pgrid(14, 12, 12, 2, 2, 2)
+    sp = L.hkp_sp_opts(2.0, 1.5, 0.3, 5, 50, 1e-8, 1e-12, 1000, 0)
+    assert L.lib.hkp_sp_workspace_bytes(C.byref(g), C.byref(o), C.byref(pg), C.byref(sp)) > 0
+    assert L.lib.hkp_poisson_workspace_bytes(C.byref(pg)) > 9 * 14 * 12 * 12 * 8
+    # the Schroedinger grid (10 x 8 x 8) must fit inside the box at the offset
+    for bad in (L.hkp_pgrid(11, 12, 12, 2, 2, 2), L.hkp_pgrid(14, 12, 12, -1, 0, 0),
+                L.hkp_pgrid(0, 12, 12, 0, 0, 0)):
+        assert L.lib.hkp_sp_workspace_bytes(C.byref(g), C.byref(o), C.byref(bad),
+                                            C.byref(sp)) == 0
+    assert b"inside" in L.lib.hkp_last_error() or b">= 1" in L.lib.hkp_last_error()
+    for field, value in (("n_holes", 9.0), ("n_holes", -1.0), ("temperature_K", 0.0),
+                         ("mixing", 0.0), ("mixing", 1.5), ("history", 9), ("max_iter", 0),
+                         ("tol_V", 0.0), ("cg_tol", -1.0), ("cg_max_iter", 0)):
+        bad = L.hkp_sp_opts(2.0, 1.5, 0.3, 5, 50, 1e-8, 1e-12, 1000, 0)
+        setattr(bad, field, value)
+        assert L.lib.hkp_sp_workspace_bytes(C.byref(g), C.byref(o), C.byref(pg),
+                                            C.byref(bad)) == 0, field
+    st = L.hkp_sp_stats()
+    # NULL required pointer, then a too small workspace
+    assert L.lib.hkp_sp_solve(C.byref(g), C.byref(m), C.byref(o), C.byref(pg), C.byref(sp),
+                              None, None, B, fake, fake, fake, None, fake, fake, None, None,
+                              None, fake, 1 << 40, None, C.byref(st)) == L.HKP_E_ARG
+    assert L.lib.hkp_sp_solve(C.byref(g), C.byref(m), C.byref(o), C.byref(pg), C.byref(sp),
+                              fake, None, B, fake, fake, fake, None, fake, fake, None, None,
+                              None, fake, 64, None, C.byref(st)) == L.HKP_E_WORKSPACE
+    it = C.c_int32(0)
+    rel = C.c_double(0.0)
+    assert L.lib.hkp_poisson(C.byref(pg), 0.4, fake, None, fake, None, fake, 1e-12, 100, fake,
+                             1 << 40, None, C.byref(it), C.byref(rel)) == L.HKP_E_ARG
+    assert L.lib.hkp_poisson(C.byref(pg), 0.4, fake, fake, fake, None, fake, 0.0, 100, fake,
+                             1 << 40, None, C.byref(it), C.byref(rel)) == L.HKP_E_ARG
+    assert L.lib.hkp_poisson(C.byref(pg), 0.4, fake, fake, fake, None, fake, 1e-12, 100, fake,
+                             16, None, C.byref(it), C.byref(rel)) == L.HKP_E_WORKSPACE
+    assert L.lib.hkp_occupancy(65, fake, 2.0, 1.5, fake, None, None) == L.HKP_E_ARG
+    assert L.lib.hkp_occupancy(8, fake, 9.0, 1.5, fake, None, None) == L.HKP_E_ARG
+    assert L.lib.hkp_occupancy(8, fake, 2.0, 0.0, fake, None, None) == L.HKP_E_ARG
+    assert L.lib.hkp_hole_density(C.byref(g), 0, fake, fake, fake, None) == L.HKP_E_ARG
