@@ -151,6 +151,7 @@ typedef struct {
 } hkp_pgrid;
 
 #define HKP_SP_PHI0 1   /* start from the caller's phi (else the hole-free potential) */
+#define HKP_SP_EXACT_EIG 2  /* every eigensolve to opts->tol (else: see hkp_sp_solve) */
 
 typedef struct {
   double n_holes;        /* holes in the computed states, 0 <= n_holes <= nev */
@@ -341,7 +342,13 @@ size_t hkp_sp_workspace_bytes(const hkp_grid* grid, const hkp_opts* opts,
  * it stops when max |phi_out - phi_in| <= tol_V, otherwise the next phi_in
  * comes from Anderson mixing: phi_in + a F - (dX + a dF) g with F = phi_out -
  * phi_in, dX and dF the differences to the m previous inputs and residuals,
- * and g the least-squares minimiser of |F - dF g|.
+ * and g the least-squares minimiser of |F - dF g|.  Unless HKP_SP_EXACT_EIG is
+ * set, an eigensolve stops at the residual max(opts->tol, min(1e-4 eV, 0.01 x
+ * the previous max |phi_out - phi_in|)) (the first one at 1e-4 eV from the
+ * hole-free start, at opts->tol from a caller's phi), and a Poisson solve at
+ * max(cg_tol, min(1e-6, 0.01 x that change)); when the loop meets tol_V after
+ * such looser solves it makes one more pass at the same potential with
+ * opts->tol and cg_tol, so the returned results always meet both.
  *   V_off      device double [nx][ny][nz], band offset (e.g. the oxide step), eV
  *   strain, B_T as in hkp_solve
  *   eps_r, dirichlet, phi_fixed  as in hkp_poisson; rho_fixed device [px][py][pz]

@@ -286,10 +286,17 @@ __global__ void control_kernel(Control c, int nb, int nev, int degree, int kmax,
   if (mixed && allow_switch && !fl[1] && !fl[0]) {
     const double prev = bd[3];
     const double near_floor = 30.0 * 5.96e-8 * bd[0];
-    if (prev > 0.0 && rmax > 0.7 * prev && rmax < near_floor) fl[2] += 1; else fl[2] = 0;
-    if (fl[2] >= 2) {
+    if (iter == 0 && rmax < near_floor && tol < 3.0 * 5.96e-8 * bd[0]) {
+      // a restart that already starts near the floor, with a target below it,
+      // gains nothing from FP32 filtering: FP64 from the first iteration
       fl[1] = 1;
-      fl[5] = it + 1;
+      fl[5] = 1;
+    } else {
+      if (prev > 0.0 && rmax > 0.7 * prev && rmax < near_floor) fl[2] += 1; else fl[2] = 0;
+      if (fl[2] >= 2) {
+        fl[1] = 1;
+        fl[5] = it + 1;
+      }
     }
   }
   bd[3] = rmax;

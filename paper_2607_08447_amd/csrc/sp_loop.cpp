@@ -231,16 +231,25 @@ int run_sp(const SPArgs& a, hkp_sp_stats* stats) {
   const int base_flags = (a.opts.flags & ~(HKP_FLAG_X0 | HKP_FLAG_X0_NEV)) | HKP_FLAG_PSI_BLOCK;
 
   const double kT = kBoltzmann * a.sp.temperature_K;
+  const bool adaptive = !(a.sp.flags & HKP_SP_EXACT_EIG);
   int count = 0;   // entries pushed into the Anderson history
-  bool converged = false;
-  double delta = 0.0;
+  bool converged = false, final_pass = false;
+  // a caller's starting potential may already be converged: its first
+  // eigensolve goes to opts->tol (from the hole-free start, to 1e-4 eV)
+  double delta = 0.0, delta_prev = (a.sp.flags & HKP_SP_PHI0) ? 0.0 : HUGE_VAL;
   int it = 0;
   for (it = 1; it <= a.sp.max_iter; ++it) {
-    // Schroedinger: V = V_off + phi on the embedded grid; restart from the last block
+    // Schroedinger: V = V_off + phi on the embedded grid; restart from the last block.
+    // Eigensolves stop at a residual tied to how far the potential still moves
+    // (an eigenvector error of r / gap moves the Hartree potential far less than
+    // the loop's own step while r <= 0.01 delta); the final pass uses opts->tol.
     auto t0 = std::chrono::steady_clock::now();
     HKP_CHECK(launch_extract(p.nx, p.ny, p.nz, g, ox, oy, oz, a.V_off, a.phi, L.V, s));
     sa.X0 = it > 1 ? L.block : nullptr;
     sa.flags = base_flags | (it > 1 ? HKP_FLAG_X0 : 0);
+    sa.tol = (adaptive && !final_pass)
+                 ? std::max(a.opts.tol_eV, std::min(1e-4, 0.01 * delta_prev))
+                 : a.opts.tol_eV;
     hkp_stats sst{};
     rc = run_solve(sa, &sst);
     if (rc < 0) return rc;
@@ -256,8 +265,13 @@ int run_sp(const SPArgs& a, hkp_sp_stats* stats) {
     HKP_CHECK(hipMemcpyAsync(L.phi_out, a.phi, (size_t)g.NP * sizeof(double),
                              hipMemcpyDeviceToDevice, s));
     int cgit = 0;
-    rc = poisson_cg(g, a.dir, a.phi_fixed, L.rho, L.phi_out, a.sp.cg_tol, a.sp.cg_max_iter,
-                    L.pw, s, &cgit, nullptr);
+    // the Poisson solve, like the eigensolve, need not be tighter than the
+    // loop's own step until the final pass
+    const double cg_tol = (adaptive && !final_pass)
+                              ? std::max(a.sp.cg_tol, std::min(1e-6, 1e-2 * delta_prev))
+                              : a.sp.cg_tol;
+    rc = poisson_cg(g, a.dir, a.phi_fixed, L.rho, L.phi_out, cg_tol, a.sp.cg_max_iter, L.pw, s,
+                    &cgit, nullptr);
     st.cg_iters += cgit;
     if (rc < 0) return rc;
     if (rc != HKP_OK) st.poisson_status = rc;
@@ -270,9 +284,16 @@ int run_sp(const SPArgs& a, hkp_sp_stats* stats) {
       return HKP_E_NUMERICAL;
     }
     if (delta <= a.sp.tol_V) {
-      converged = true;
-      break;
+      if (sa.tol <= a.opts.tol_eV && cg_tol <= a.sp.cg_tol) {
+        converged = true;
+        break;
+      }
+      // met with a looser eigensolve: one more pass at this potential and opts->tol
+      final_pass = true;
+      continue;
     }
+    final_pass = false;
+    delta_prev = delta;
     if (it == a.sp.max_iter) break;
     // next input potential
     const int k = std::min(count, m);

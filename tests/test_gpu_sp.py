@@ -176,8 +176,15 @@ def test_sp_loop_without_holes_and_not_converged():
     d = sp_device("sp_tiny")
     r = hkp.sp_solve(_t(d.V_off), d.h, d.nev, d.pshape, d.offset, _t(d.eps_r),
                      _t(d.dirichlet), _t(d.phi_fixed), 0.0, d.T, nb=d.nb, tol=1e-10,
-                     tol_V=1e-9, cg_tol=1e-13)
+                     tol_V=1e-9, cg_tol=1e-13, exact_eig=True)
     assert r.status == 0 and r.stats["iters"] == 1
+    # with eigensolves tied to the potential's motion: a loose first pass, then
+    # the final pass at the full tolerance
+    r2 = hkp.sp_solve(_t(d.V_off), d.h, d.nev, d.pshape, d.offset, _t(d.eps_r),
+                      _t(d.dirichlet), _t(d.phi_fixed), 0.0, d.T, nb=d.nb, tol=1e-10,
+                      tol_V=1e-9, cg_tol=1e-13)
+    assert r2.status == 0 and r2.stats["iters"] == 2
+    assert np.abs(r2.E.cpu().numpy() - r.E.cpu().numpy()).max() <= 1e-9
     ref = poisson_solve(d.pshape, d.h, d.eps_r, d.dirichlet, d.phi_fixed, np.zeros(d.pshape))
     assert np.abs(r.phi.cpu().numpy() - ref).max() <= 1e-10
     g = Grid(*d.shape, d.h)
