@@ -15,11 +15,14 @@ roofline = the FP32 filter-step stencil (the dominant kernel): its algorithmic
 
 Also reported (same JSON line): the device copy bandwidth; the 64-Hamiltonian
 barrier sweep (192 x 40 x 40 each) as seconds per Hamiltonian, batched mixed
-precision in one hipGraph vs a loop of FP64 solves; the Hellmann-Feynman
-backward of the 192 x 40 x 40 adjoint workload (time, error against central
-finite differences).
+precision in one hipGraph vs a loop of FP64 solves, and by continuation
+(solve_sweep); the Hellmann-Feynman backward of the 192 x 40 x 40 adjoint
+workload (time, error against central finite differences); the self-consistent
+Schroedinger-Poisson loop on the 256 x 48 x 48 fin in a 272 x 64 x 88 Poisson box
+(iterations, time, Poisson CG rate against the HBM roofline).
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-extra]
+       python bench.py --sp-only          (only the self-consistent loop measurement)
        python bench.py --traffic-from FETCH_CSV WRITE_CSV   (writes the HBM traffic
            summary of the FP32 stencil from two rocprofv3 --pmc runs of
            `bench.py --copy-calibration --no-cpu --no-extra --steps 1 --warmup 0`)
@@ -255,21 +258,7 @@ def sp_measure(torch, hkp):
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     st = r.stats
-    # Poisson CG rate: fixed iteration count (unreachable tolerance), events on the stream
     NP = int(np.prod(d.pshape))
-    rho = torch.zeros(d.pshape, dtype=torch.float64, device="cuda")
-    rho[d.offset[0]:d.offset[0] + d.shape[0], d.offset[1]:d.offset[1] + d.shape[1],
-        d.offset[2]:d.offset[2] + d.shape[2]] = r.density
-    hkp.poisson(eps, dirm, phif, rho, d.h, tol=1e-30, max_iter=64)   # warm-up
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
-    iters = 1024
-    e0.record()
-    _, it, _, _ = hkp.poisson(eps, dirm, phif, rho, d.h, tol=1e-30, max_iter=iters)
-    e1.record()
-    e1.synchronize()
-    t_it = e0.elapsed_time(e1) * 1e-3 / it
-    gbps = CG_BYTES_PER_NODE * NP / t_it / 1e9
     return {"workload": "sp_dqd_256x48x48", "grid": list(d.shape), "poisson_box": list(d.pshape),
             "poisson_nodes": NP, "n_holes": d.n_holes, "T_K": d.T, "nev": d.nev, "nb": d.nb,
             "precision": "mixed", "stop": "max |phi_out - phi_in| <= 1e-6 V, eigen tol 1e-7 eV",
@@ -280,10 +269,36 @@ def sp_measure(torch, hkp):
             "t_poisson_s": round(st["t_poisson"], 3), "cg_iterations": st["cg_iters"],
             "eigensolver_iterations": st["schroedinger_iters"],
             "E0_eV": float(r.E[0]), "mu_eV": st["mu_eV"],
-            "poisson_cg": {"us_per_iteration": round(t_it * 1e6, 2),
-                           "bytes_per_node": CG_BYTES_PER_NODE,
-                           "achieved_gbps": round(gbps, 1), "peak_gbps": 8000.0,
-                           "frac": round(gbps / 8000.0, 4), "iterations_timed": it}}
+            "poisson_cg": poisson_measure(torch, hkp, d, r.density)}
+
+
+def poisson_measure(torch, hkp, d=None, density=None, iters=1024):
+    """Poisson CG on the 272 x 64 x 88 box: time per iteration of a fixed iteration
+    count (unreachable tolerance), HIP events on the library's stream, against the
+    HBM roofline at CG_BYTES_PER_NODE algorithmic bytes per node."""
+    from synth import sp_device
+    d = d or sp_device("sp_dqd_256x48x48")
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
+    eps, dirm, phif = t(d.eps_r), t(d.dirichlet), t(d.phi_fixed)
+    NP = int(np.prod(d.pshape))
+    rho = torch.zeros(d.pshape, dtype=torch.float64, device="cuda")
+    if density is None:   # two holes spread over the fin
+        density = torch.full(d.shape, d.n_holes / (np.prod(d.shape) * d.h ** 3),
+                             dtype=torch.float64, device="cuda")
+    rho[d.offset[0]:d.offset[0] + d.shape[0], d.offset[1]:d.offset[1] + d.shape[1],
+        d.offset[2]:d.offset[2] + d.shape[2]] = density
+    hkp.poisson(eps, dirm, phif, rho, d.h, tol=1e-30, max_iter=64)   # warm-up
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    _, it, _, _ = hkp.poisson(eps, dirm, phif, rho, d.h, tol=1e-30, max_iter=iters)
+    e1.record()
+    e1.synchronize()
+    t_it = e0.elapsed_time(e1) * 1e-3 / it
+    gbps = CG_BYTES_PER_NODE * NP / t_it / 1e9
+    return {"nodes": NP, "us_per_iteration": round(t_it * 1e6, 2),
+            "bytes_per_node": CG_BYTES_PER_NODE, "achieved_gbps": round(gbps, 1),
+            "peak_gbps": 8000.0, "frac": round(gbps / 8000.0, 4), "iterations_timed": it}
 
 
 def cpu_baseline(w, seconds=15.0):
@@ -330,6 +345,11 @@ def main():
                     help="use this stencil launch shape instead of autotuning (profiled runs)")
     ap.add_argument("--nb", type=int, default=0,
                     help="use this block size instead of autotuning it (profiled runs)")
+    ap.add_argument("--sp-only", action="store_true",
+                    help="run only the self-consistent loop measurement (profiled runs); "
+                         "prints its JSON object")
+    ap.add_argument("--poisson-only", action="store_true",
+                    help="run only the Poisson CG rate measurement (profiled runs)")
     args = ap.parse_args()
     if args.traffic_from:
         if not args.stencil or not args.nb:
@@ -355,6 +375,13 @@ def main():
         torch.cuda.synchronize()
         log("copy calibration: 1 GiB read + 1 GiB written")
         del src_buf, dst_buf
+
+    if args.sp_only:
+        print(json.dumps(sp_measure(torch, hkp)), flush=True)
+        return
+    if args.poisson_only:
+        print(json.dumps(poisson_measure(torch, hkp)), flush=True)
+        return
 
     w = workload(WORKLOAD)
     nev, tol = 32, 1e-5

@@ -25,6 +25,14 @@ namespace hkp {
 
 void set_error(const std::string& msg);   // thread-local message for hkp_last_error
 
+// The hardware places workgroup wg on XCD wg % 8; this gives every XCD a
+// contiguous run of logical workgroups (neighbouring data then shares an L2).
+__device__ __forceinline__ int xcd_remap(int wg, int nwg) {
+  const int x = wg & 7, idx = wg >> 3;
+  const int per = nwg >> 3, rem = nwg & 7;
+  return x * per + (x < rem ? x : rem) + idx;
+}
+
 constexpr double kE0 = 0.0380998212;          // hbar^2/(2 m0), eV nm^2
 constexpr double kMuB = 5.7883818060e-5;      // eV/T
 constexpr double kEoverHbar = 1.519267447e-3; // 1/(T nm^2)
@@ -193,7 +201,7 @@ hipError_t launch_init_coef(const Control& c, int batch, int degree, int kmax,
 // self-consistent loop: Poisson (conjugate gradients), occupancy, density,
 // Anderson mixing.  Poisson-box arrays are real [px][py][pz] (z fastest).
 // ---------------------------------------------------------------------------
-constexpr int kRedBlocks = 2048;   // workgroups of the grid-stride kernels (max)
+constexpr int kRedBlocks = 16384;  // workgroups of the grid-stride kernels (max)
 constexpr double kEoverEps0 = 1.602176634e-19 / 8.8541878128e-12 * 1e9;   // V nm
 constexpr double kBoltzmann = 8.617333262e-5;                             // eV/K
 

@@ -11,9 +11,11 @@
 // their potential; every CG vector is zero on them.
 //
 // All of these kernels stream through memory once per call: they are HBM-bound
-// and run one node per thread with grid-stride loops over a fixed grid of
-// kRedBlocks workgroups, whose per-workgroup partial sums are reduced in a fixed
-// order by one workgroup (the results do not depend on timing).
+// and run one node per thread (grid-stride beyond kRedBlocks workgroups); the
+// stencil-shaped ones give every XCD a contiguous range of nodes, so that the
+// x- and y-neighbours a node reads are in the L2 its neighbours filled.
+// Per-workgroup partial sums are reduced in a fixed order by one workgroup
+// (the results do not depend on timing).
 #include <hip/hip_runtime.h>
 
 #include "hkp_internal.h"
@@ -26,12 +28,32 @@ constexpr int kThreads = 256;
 
 struct Geo {
   int px, py, pz;
-  long long sx;   // py * pz (x stride)
-  int sy;         // pz (y stride)
+  unsigned sx;    // py * pz (x stride; boxes hold < 2^31 nodes)
+  unsigned sy;    // pz (y stride)
+  double ipy, ipz;   // 1 / py, 1 / pz (host-computed)
 };
 
-__device__ __forceinline__ Geo geo(int px, int py, int pz) {
-  return Geo{px, py, pz, (long long)py * pz, pz};
+__device__ __forceinline__ Geo geo(int px, int py, int pz, double ipy, double ipz) {
+  return Geo{px, py, pz, (unsigned)py * (unsigned)pz, (unsigned)pz, ipy, ipz};
+}
+
+// n / d for n < 2^31 from a double reciprocal, corrected to the exact floor
+// (the product is within a tiny fraction of n / d, so one step either way
+// suffices); integer division by a runtime divisor costs far more
+__device__ __forceinline__ unsigned udiv(unsigned n, unsigned d, double inv) {
+  unsigned q = (unsigned)((double)n * inv);
+  const unsigned long long qd = (unsigned long long)q * d;
+  if (qd > n) --q;
+  else if (qd + d <= n) ++q;
+  return q;
+}
+
+// (x, y, z) of box node i
+__device__ __forceinline__ void coords(unsigned i, const Geo& g, int& x, int& y, int& z) {
+  const unsigned q = udiv(i, g.sy, g.ipz);   // x * py + y
+  z = (int)(i - q * g.sy);
+  x = (int)udiv(q, (unsigned)g.py, g.ipy);
+  y = (int)(q - (unsigned)x * (unsigned)g.py);
 }
 
 __device__ __forceinline__ double harmonic(double a, double b) { return 2.0 * a * b / (a + b); }
@@ -74,14 +96,15 @@ __device__ __forceinline__ void reduce_partials(const double* partial, int nblk,
 // Poisson: link coefficients and the Jacobi preconditioner
 // ---------------------------------------------------------------------------
 __global__ void __launch_bounds__(kThreads)
-pcoef_kernel(long long NP, int px, int py, int pz, double inv_h2, const double* __restrict__ eps,
-             const uint8_t* __restrict__ dir, double* cx, double* cy, double* cz, double* dinv,
-             double* partial) {
-  const Geo g = geo(px, py, pz);
+pcoef_kernel(unsigned NP, int px, int py, int pz, double ipy, double ipz, double inv_h2,
+             const double* __restrict__ eps, const uint8_t* __restrict__ dir, double* cx,
+             double* cy, double* cz, double* dinv, double* partial) {
+  const Geo g = geo(px, py, pz, ipy, ipz);
   double nd = 0.0;   // electrode nodes (checked on the host: at least one)
-  for (long long i = (long long)blockIdx.x * kThreads + threadIdx.x; i < NP;
-       i += (long long)gridDim.x * kThreads) {
-    const int x = (int)(i / g.sx), y = (int)((i / g.sy) % py), z = (int)(i % pz);
+  for (unsigned i = xcd_remap(blockIdx.x, gridDim.x) * kThreads + threadIdx.x; i < NP;
+       i += gridDim.x * kThreads) {
+    int x, y, z;
+    coords(i, g, x, y, z);
     const double e = eps[i];
     const double ax = x + 1 < px ? harmonic(e, eps[i + g.sx]) * inv_h2 : 0.0;
     const double ay = y + 1 < py ? harmonic(e, eps[i + g.sy]) * inv_h2 : 0.0;
@@ -102,7 +125,7 @@ pcoef_kernel(long long NP, int px, int py, int pz, double inv_h2, const double* 
 
 // sum over the in-box links of node i of c (u_i - u_j), with u_j from `val`
 template <typename F>
-__device__ __forceinline__ double link_sum(long long i, int x, int y, int z, const Geo& g,
+__device__ __forceinline__ double link_sum(unsigned i, int x, int y, int z, const Geo& g,
                                            const double* __restrict__ cx,
                                            const double* __restrict__ cy,
                                            const double* __restrict__ cz, double ui, F val) {
@@ -121,15 +144,16 @@ __device__ __forceinline__ double link_sum(long long i, int x, int y, int z, con
 // electrode neighbours, so nothing here reads what another thread writes);
 // z = D^-1 r; p = 0.  Partials: r.z, r.r, b.b.
 __global__ void __launch_bounds__(kThreads)
-cg_init_kernel(long long NP, int px, int py, int pz, const double* __restrict__ cx,
+cg_init_kernel(unsigned NP, int px, int py, int pz, double ipy, double ipz,
+               const double* __restrict__ cx,
                const double* __restrict__ cy, const double* __restrict__ cz,
                const double* __restrict__ dinv, const uint8_t* __restrict__ dir,
                const double* __restrict__ phi_fixed, const double* __restrict__ rho,
                double scale, double* phi, double* r, double* zv, double* p, double* partial) {
-  const Geo g = geo(px, py, pz);
+  const Geo g = geo(px, py, pz, ipy, ipz);
   double acc[3] = {0.0, 0.0, 0.0};
-  for (long long i = (long long)blockIdx.x * kThreads + threadIdx.x; i < NP;
-       i += (long long)gridDim.x * kThreads) {
+  for (unsigned i = xcd_remap(blockIdx.x, gridDim.x) * kThreads + threadIdx.x; i < NP;
+       i += gridDim.x * kThreads) {
     p[i] = 0.0;
     if (dir[i]) {
       phi[i] = phi_fixed[i];
@@ -137,14 +161,15 @@ cg_init_kernel(long long NP, int px, int py, int pz, const double* __restrict__ 
       zv[i] = 0.0;
       continue;
     }
-    const int x = (int)(i / g.sx), y = (int)((i / g.sy) % py), z = (int)(i % pz);
+    int x, y, z;
+    coords(i, g, x, y, z);
     const double ui = phi[i];
     const double f = rho ? scale * rho[i] : 0.0;   // no charge array: rho = 0
-    const double lphi = link_sum(i, x, y, z, g, cx, cy, cz, ui, [&](long long j) {
+    const double lphi = link_sum(i, x, y, z, g, cx, cy, cz, ui, [&](unsigned j) {
       return dir[j] ? phi_fixed[j] : phi[j];
     });
     // electrode couplings of b: sum over electrode neighbours of c phi_fixed
-    const double bdir = link_sum(i, x, y, z, g, cx, cy, cz, 0.0, [&](long long j) {
+    const double bdir = link_sum(i, x, y, z, g, cx, cy, cz, 0.0, [&](unsigned j) {
       return dir[j] ? -phi_fixed[j] : 0.0;
     });
     const double ri = f - lphi;
@@ -179,26 +204,28 @@ cg_start_kernel(const double* partial, int nblk, double tol, CGState* st) {
 // p_new = z + beta p_old (at the node and its neighbours: the old direction is
 // not overwritten, p_new goes to the other buffer); q = L p_new; partial p.q
 __global__ void __launch_bounds__(kThreads)
-cg_matvec_kernel(long long NP, int px, int py, int pz, const double* __restrict__ cx,
+cg_matvec_kernel(unsigned NP, int px, int py, int pz, double ipy, double ipz,
+                 const double* __restrict__ cx,
                  const double* __restrict__ cy, const double* __restrict__ cz,
                  const uint8_t* __restrict__ dir, const double* __restrict__ zv,
                  const double* __restrict__ p_old, double* __restrict__ p_new,
                  double* __restrict__ q, double* partial, const CGState* st) {
   if (st->done) return;
   const double beta = st->beta;
-  const Geo g = geo(px, py, pz);
+  const Geo g = geo(px, py, pz, ipy, ipz);
   double acc[1] = {0.0};
-  for (long long i = (long long)blockIdx.x * kThreads + threadIdx.x; i < NP;
-       i += (long long)gridDim.x * kThreads) {
+  for (unsigned i = xcd_remap(blockIdx.x, gridDim.x) * kThreads + threadIdx.x; i < NP;
+       i += gridDim.x * kThreads) {
     if (dir[i]) {
       p_new[i] = 0.0;
       q[i] = 0.0;
       continue;
     }
-    const int x = (int)(i / g.sx), y = (int)((i / g.sy) % py), z = (int)(i % pz);
+    int x, y, z;
+    coords(i, g, x, y, z);
     const double pi = zv[i] + beta * p_old[i];
     // electrode neighbours hold z = p_old = 0, so their p_new is 0 as well
-    const double qi = link_sum(i, x, y, z, g, cx, cy, cz, pi, [&](long long j) {
+    const double qi = link_sum(i, x, y, z, g, cx, cy, cz, pi, [&](unsigned j) {
       return zv[j] + beta * p_old[j];
     });
     p_new[i] = pi;
@@ -300,14 +327,19 @@ occupancy_kernel(int nev, const double* __restrict__ E, double n_holes, double k
 // sum_n f_n sum_c |psi_n,c|^2 / h^3 with psi [nev][nx][ny][nz][6] (vector
 // stride vstride complex entries)
 __global__ void __launch_bounds__(kThreads)
-rho_kernel(long long NP, int px, int py, int pz, int ox, int oy, int oz, int nx, int ny, int nz,
+rho_kernel(unsigned NP, int px, int py, int pz, double ipy, double ipz, int ox, int oy, int oz,
+           int nx, int ny, int nz,
            int nev, const double2* __restrict__ psi, long long vstride,
            const double* __restrict__ f, double inv_h3, const double* __restrict__ rho_fixed,
            double* rho, double* density) {
-  const Geo g = geo(px, py, pz);
-  for (long long i = (long long)blockIdx.x * kThreads + threadIdx.x; i < NP;
-       i += (long long)gridDim.x * kThreads) {
-    const int x = (int)(i / g.sx) - ox, y = (int)((i / g.sy) % py) - oy, z = (int)(i % pz) - oz;
+  const Geo g = geo(px, py, pz, ipy, ipz);
+  for (unsigned i = xcd_remap(blockIdx.x, gridDim.x) * kThreads + threadIdx.x; i < NP;
+       i += gridDim.x * kThreads) {
+    int x, y, z;
+    coords(i, g, x, y, z);
+    x -= ox;
+    y -= oy;
+    z -= oz;
     double v = rho_fixed ? rho_fixed[i] : 0.0;
     if (x >= 0 && x < nx && y >= 0 && y < ny && z >= 0 && z < nz) {
       const long long s = ((long long)x * ny + y) * nz + z;
@@ -514,8 +546,8 @@ hipError_t launch_pcoef(const PGeom& g, double h, const double* eps, const uint8
                         double* cx, double* cy, double* cz, double* dinv, double* partial,
                         double* n_dir, hipStream_t s) {
   const int nb = sp_blocks(g.NP);
-  pcoef_kernel<<<nb, kThreads, 0, s>>>(g.NP, g.px, g.py, g.pz, 1.0 / (h * h), eps, dir, cx, cy,
-                                       cz, dinv, partial);
+  pcoef_kernel<<<nb, kThreads, 0, s>>>((unsigned)g.NP, g.px, g.py, g.pz, 1.0 / g.py, 1.0 / g.pz,
+                                       1.0 / (h * h), eps, dir, cx, cy, cz, dinv, partial);
   sum1_kernel<<<1, kThreads, 0, s>>>(partial, nb, n_dir);
   return hipGetLastError();
 }
@@ -525,8 +557,9 @@ hipError_t launch_cg_init(const PGeom& g, const double* cx, const double* cy, co
                           const double* rho, double scale, double* phi, double* r, double* z,
                           double* p, double* partial, double tol, CGState* st, hipStream_t s) {
   const int nb = sp_blocks(g.NP);
-  cg_init_kernel<<<nb, kThreads, 0, s>>>(g.NP, g.px, g.py, g.pz, cx, cy, cz, dinv, dir,
-                                         phi_fixed, rho, scale, phi, r, z, p, partial);
+  cg_init_kernel<<<nb, kThreads, 0, s>>>((unsigned)g.NP, g.px, g.py, g.pz, 1.0 / g.py,
+                                         1.0 / g.pz, cx, cy, cz, dinv, dir, phi_fixed, rho,
+                                         scale, phi, r, z, p, partial);
   cg_start_kernel<<<1, kThreads, 0, s>>>(partial, nb, tol, st);
   return hipGetLastError();
 }
@@ -537,8 +570,9 @@ hipError_t launch_cg_iter(const PGeom& g, const double* cx, const double* cy, co
                           double* r, double* partial, int max_iter, CGState* st,
                           hipStream_t s) {
   const int nb = sp_blocks(g.NP);
-  cg_matvec_kernel<<<nb, kThreads, 0, s>>>(g.NP, g.px, g.py, g.pz, cx, cy, cz, dir, z, p_old,
-                                           p_new, q, partial, st);
+  cg_matvec_kernel<<<nb, kThreads, 0, s>>>((unsigned)g.NP, g.px, g.py, g.pz, 1.0 / g.py,
+                                           1.0 / g.pz, cx, cy, cz, dir, z, p_old, p_new, q,
+                                           partial, st);
   cg_alpha_kernel<<<1, kThreads, 0, s>>>(partial, nb, st);
   cg_update_kernel<<<nb, kThreads, 0, s>>>(g.NP, dinv, p_new, q, phi, r, z, partial, st);
   cg_beta_kernel<<<1, kThreads, 0, s>>>(partial, nb, max_iter, st);
@@ -555,8 +589,9 @@ hipError_t launch_occupancy(int nev, const double* E, double n_holes, double kT,
 hipError_t launch_rho(const PGeom& g, int ox, int oy, int oz, int nx, int ny, int nz, int nev,
                       const void* psi, long long vstride, const double* f, double inv_h3,
                       const double* rho_fixed, double* rho, double* density, hipStream_t s) {
-  rho_kernel<<<sp_blocks(g.NP), kThreads, 0, s>>>(g.NP, g.px, g.py, g.pz, ox, oy, oz, nx, ny, nz,
-                                                  nev, (const double2*)psi, vstride, f, inv_h3,
+  rho_kernel<<<sp_blocks(g.NP), kThreads, 0, s>>>((unsigned)g.NP, g.px, g.py, g.pz, 1.0 / g.py,
+                                                  1.0 / g.pz, ox, oy, oz, nx, ny, nz, nev,
+                                                  (const double2*)psi, vstride, f, inv_h3,
                                                   rho_fixed, rho, density);
   return hipGetLastError();
 }

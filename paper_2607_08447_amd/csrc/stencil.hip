@@ -91,13 +91,6 @@ __device__ __forceinline__ void stg(void* base, long long idx, cx<T> v) {
   reinterpret_cast<typename V2<TW>::type*>(base)[idx] = o;
 }
 
-__device__ __forceinline__ int xcd_remap(int wg, int nwg) {
-  // hardware places workgroup wg on XCD wg % 8; give every XCD a contiguous
-  // run of logical workgroups
-  const int x = wg & 7, idx = wg >> 3;
-  const int per = nwg >> 3, rem = nwg & 7;
-  return x * per + (x < rem ? x : rem) + idx;
-}
 
 template <typename T>
 struct KArgs {
