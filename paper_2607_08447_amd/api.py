@@ -323,10 +323,12 @@ def _pgrid(pshape, offset=(0, 0, 0)):
     return L.hkp_pgrid(px, py, pz, ox, oy, oz)
 
 
-def poisson(eps_r, dirichlet, phi_fixed, rho, h, phi0=None, tol=1e-12, max_iter=20000):
+def poisson(eps_r, dirichlet, phi_fixed, rho, h, phi0=None, tol=1e-12, max_iter=20000,
+            graph=True):
     """phi (V) on the Poisson box [px, py, pz] from -div(eps_r grad phi) = (e/eps0) rho
     (rho in e/nm^3, may be None), electrode nodes (dirichlet != 0) at phi_fixed.
-    Returns (phi, cg_iterations, final |r|/|b|, status)."""
+    graph: run on a private stream, where the library replays its CG iterations
+    as a recorded hipGraph.  Returns (phi, cg_iterations, final |r|/|b|, status)."""
     eps_r = _dev(eps_r, torch.float64)
     shape = tuple(eps_r.shape)
     dirichlet = _dev(dirichlet, torch.uint8)
@@ -344,9 +346,16 @@ def poisson(eps_r, dirichlet, phi_fixed, rho, h, phi0=None, tol=1e-12, max_iter=
         else _dev(phi0, torch.float64).clone()
     it = C.c_int32(0)
     rel = C.c_double(0.0)
-    code = L.lib.hkp_poisson(C.byref(pg), float(h), _ptr(eps_r), _ptr(dirichlet), _ptr(phi_fixed),
-                             _ptr(rho), _ptr(phi), float(tol), int(max_iter), _ptr(ws),
-                             C.c_size_t(need), _stream(), C.byref(it), C.byref(rel))
+    args = (C.byref(pg), float(h), _ptr(eps_r), _ptr(dirichlet), _ptr(phi_fixed), _ptr(rho),
+            _ptr(phi), float(tol), int(max_iter), _ptr(ws), C.c_size_t(need))
+    if graph:
+        s = torch.cuda.Stream()
+        s.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(s):
+            code = L.lib.hkp_poisson(*args, _stream(s), C.byref(it), C.byref(rel))
+        torch.cuda.current_stream().wait_stream(s)
+    else:
+        code = L.lib.hkp_poisson(*args, _stream(), C.byref(it), C.byref(rel))
     L.check(code)
     return phi, it.value, rel.value, code
 

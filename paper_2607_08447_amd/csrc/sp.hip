@@ -58,10 +58,12 @@ __device__ __forceinline__ void coords(unsigned i, const Geo& g, int& x, int& y,
 
 __device__ __forceinline__ double harmonic(double a, double b) { return 2.0 * a * b / (a + b); }
 
-// block sum of up to 4 values; thread 0 writes them to out[0..n)
-template <int NV>
+constexpr int kRedThreads = 1024;   // the one workgroup that reduces partial sums
+
+// block sum of NV values over NT threads; thread 0 writes them to out[0..NV)
+template <int NV, int NT = kThreads>
 __device__ __forceinline__ void block_sums(double (&v)[NV], double* out) {
-  __shared__ double sh[NV][kThreads / 64];
+  __shared__ double sh[NV][NT / 64];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
 #pragma unroll
   for (int k = 0; k < NV; ++k) {
@@ -74,22 +76,22 @@ __device__ __forceinline__ void block_sums(double (&v)[NV], double* out) {
 #pragma unroll
     for (int k = 0; k < NV; ++k) {
       double s = 0.0;
-      for (int i = 0; i < kThreads / 64; ++i) s += sh[k][i];
+      for (int i = 0; i < NT / 64; ++i) s += sh[k][i];
       out[k] = s;
     }
   }
 }
 
-// sums of nblk partial rows (stride NV) by one workgroup, fixed order
+// sums of nblk partial rows (stride NV) by one workgroup of kRedThreads, fixed order
 template <int NV>
 __device__ __forceinline__ void reduce_partials(const double* partial, int nblk, double* out) {
   double v[NV];
 #pragma unroll
   for (int k = 0; k < NV; ++k) v[k] = 0.0;
-  for (int b = threadIdx.x; b < nblk; b += kThreads)
+  for (int b = threadIdx.x; b < nblk; b += kRedThreads)
 #pragma unroll
     for (int k = 0; k < NV; ++k) v[k] += partial[(long long)b * NV + k];
-  block_sums<NV>(v, out);
+  block_sums<NV, kRedThreads>(v, out);
 }
 
 // ---------------------------------------------------------------------------
@@ -184,7 +186,7 @@ cg_init_kernel(unsigned NP, int px, int py, int pz, double ipy, double ipz,
   block_sums<3>(acc, partial + 3LL * blockIdx.x);
 }
 
-__global__ void __launch_bounds__(kThreads)
+__global__ void __launch_bounds__(kRedThreads)
 cg_start_kernel(const double* partial, int nblk, double tol, CGState* st) {
   __shared__ double s[3];
   reduce_partials<3>(partial, nblk, s);
@@ -235,7 +237,7 @@ cg_matvec_kernel(unsigned NP, int px, int py, int pz, double ipy, double ipz,
   block_sums<1>(acc, partial + blockIdx.x);
 }
 
-__global__ void __launch_bounds__(kThreads)
+__global__ void __launch_bounds__(kRedThreads)
 cg_alpha_kernel(const double* partial, int nblk, CGState* st) {
   if (st->done) return;
   __shared__ double s[1];
@@ -272,7 +274,7 @@ cg_update_kernel(long long NP, const double* __restrict__ dinv, const double* __
   block_sums<2>(acc, partial + 2LL * blockIdx.x);
 }
 
-__global__ void __launch_bounds__(kThreads)
+__global__ void __launch_bounds__(kRedThreads)
 cg_beta_kernel(const double* partial, int nblk, int max_iter, CGState* st) {
   if (st->done) return;
   __shared__ double s[2];
@@ -429,7 +431,7 @@ anderson_dots_kernel(long long NP, const double* __restrict__ F,
 }
 
 template <int K>
-__global__ void __launch_bounds__(kThreads)
+__global__ void __launch_bounds__(kRedThreads)
 anderson_dots_reduce_kernel(const double* partial, int nblk, double* dots) {
   __shared__ double s[K + 1];
   reduce_partials<K + 1>(partial, nblk, s);
@@ -513,7 +515,7 @@ anderson_update_kernel(long long NP, int slot, double a, const double* __restric
   }
 }
 
-__global__ void __launch_bounds__(kThreads)
+__global__ void __launch_bounds__(kRedThreads)
 sum1_kernel(const double* partial, int nblk, double* out) {
   __shared__ double s[1];
   reduce_partials<1>(partial, nblk, s);
@@ -526,7 +528,7 @@ void anderson_k(const PGeom& g, int nb, int m, int slot, double mixing, double* 
                 double* gamma, double* partial, hipStream_t s) {
   if (m > 0) {
     anderson_dots_kernel<K><<<nb, kThreads, 0, s>>>(g.NP, F, histF, partial);
-    anderson_dots_reduce_kernel<K><<<1, kThreads, 0, s>>>(partial, nb, dots);
+    anderson_dots_reduce_kernel<K><<<1, kRedThreads, 0, s>>>(partial, nb, dots);
     anderson_coef_kernel<<<1, 64, 0, s>>>(K, m, slot, dots, G, gamma);
   }
   anderson_update_kernel<K><<<nb, kThreads, 0, s>>>(g.NP, m > 0 ? slot : -1, mixing, gamma, x,
@@ -548,7 +550,7 @@ hipError_t launch_pcoef(const PGeom& g, double h, const double* eps, const uint8
   const int nb = sp_blocks(g.NP);
   pcoef_kernel<<<nb, kThreads, 0, s>>>((unsigned)g.NP, g.px, g.py, g.pz, 1.0 / g.py, 1.0 / g.pz,
                                        1.0 / (h * h), eps, dir, cx, cy, cz, dinv, partial);
-  sum1_kernel<<<1, kThreads, 0, s>>>(partial, nb, n_dir);
+  sum1_kernel<<<1, kRedThreads, 0, s>>>(partial, nb, n_dir);
   return hipGetLastError();
 }
 
@@ -560,7 +562,7 @@ hipError_t launch_cg_init(const PGeom& g, const double* cx, const double* cy, co
   cg_init_kernel<<<nb, kThreads, 0, s>>>((unsigned)g.NP, g.px, g.py, g.pz, 1.0 / g.py,
                                          1.0 / g.pz, cx, cy, cz, dinv, dir, phi_fixed, rho,
                                          scale, phi, r, z, p, partial);
-  cg_start_kernel<<<1, kThreads, 0, s>>>(partial, nb, tol, st);
+  cg_start_kernel<<<1, kRedThreads, 0, s>>>(partial, nb, tol, st);
   return hipGetLastError();
 }
 
@@ -573,9 +575,9 @@ hipError_t launch_cg_iter(const PGeom& g, const double* cx, const double* cy, co
   cg_matvec_kernel<<<nb, kThreads, 0, s>>>((unsigned)g.NP, g.px, g.py, g.pz, 1.0 / g.py,
                                            1.0 / g.pz, cx, cy, cz, dir, z, p_old, p_new, q,
                                            partial, st);
-  cg_alpha_kernel<<<1, kThreads, 0, s>>>(partial, nb, st);
+  cg_alpha_kernel<<<1, kRedThreads, 0, s>>>(partial, nb, st);
   cg_update_kernel<<<nb, kThreads, 0, s>>>(g.NP, dinv, p_new, q, phi, r, z, partial, st);
-  cg_beta_kernel<<<1, kThreads, 0, s>>>(partial, nb, max_iter, st);
+  cg_beta_kernel<<<1, kRedThreads, 0, s>>>(partial, nb, max_iter, st);
   return hipGetLastError();
 }
 

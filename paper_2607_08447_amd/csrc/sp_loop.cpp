@@ -75,27 +75,71 @@ int poisson_prepare(const PGeom& g, double h, const double* eps, const uint8_t* 
   return HKP_OK;
 }
 
-// conjugate gradients from the guess in phi; launches run in chunks, the host
-// reads the device state once per chunk (iterations after convergence are no-ops)
+// A chunk of CG iterations recorded once as a hipGraph (kernels only) and
+// replayed: the launches of one iteration are short, so their gaps matter.
+// Reused while the solution buffer and the iteration cap stay the same.
+struct CGGraph {
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  const double* phi = nullptr;
+  int max_iter = -1;
+  void reset() {
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+    exec = nullptr;
+    graph = nullptr;
+  }
+  ~CGGraph() { reset(); }
+};
+
+constexpr int kCGChunk = 32;   // even: every chunk starts from the same direction buffer
+
+void launch_cg_chunk(const PGeom& g, const uint8_t* dir, double* phi, int max_iter,
+                     const PoissonWS& w, hipStream_t s) {
+  for (int c = 0; c < kCGChunk; ++c) {
+    double* po = (c % 2 == 0) ? w.p0 : w.p1;
+    double* pn = (c % 2 == 0) ? w.p1 : w.p0;
+    HKP_CHECK(launch_cg_iter(g, w.cx, w.cy, w.cz, w.dinv, dir, w.z, po, pn, w.q, phi, w.r,
+                             w.partial, max_iter, w.st, s));
+  }
+}
+
+// conjugate gradients from the guess in phi; launches run in chunks (recorded as
+// a graph when the stream can be captured), the host reads the device state once
+// per chunk (iterations after convergence are no-ops)
 int poisson_cg(const PGeom& g, const uint8_t* dir, const double* phi_fixed, const double* rho,
                double* phi, double tol, int max_iter, const PoissonWS& w, hipStream_t s,
-               int* iters, double* relres) {
+               int* iters, double* relres, CGGraph* gc = nullptr) {
   HKP_CHECK(launch_cg_init(g, w.cx, w.cy, w.cz, w.dinv, dir, phi_fixed, rho, kEoverEps0, phi,
                            w.r, w.z, w.p0, w.partial, tol, w.st, s));
+  if (gc && s != nullptr && (gc->phi != phi || gc->max_iter != max_iter || !gc->exec)) {
+    gc->reset();
+    HKP_CHECK(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+    try {
+      launch_cg_chunk(g, dir, phi, max_iter, w, s);
+    } catch (...) {
+      hipGraph_t g2 = nullptr;
+      (void)hipStreamEndCapture(s, &g2);
+      if (g2) (void)hipGraphDestroy(g2);
+      throw;
+    }
+    HKP_CHECK(hipStreamEndCapture(s, &gc->graph));
+    HKP_CHECK(hipGraphInstantiate(&gc->exec, gc->graph, nullptr, nullptr, 0));
+    gc->phi = phi;
+    gc->max_iter = max_iter;
+  }
+  const bool use_graph = gc && s != nullptr && gc->exec;
   CGState h{};
   long long launched = 0;
-  constexpr int kChunk = 32;
   for (;;) {
     HKP_CHECK(hipMemcpyAsync(&h, w.st, sizeof(CGState), hipMemcpyDeviceToHost, s));
     HKP_CHECK(hipStreamSynchronize(s));
     if (h.done || launched >= max_iter) break;
-    for (int c = 0; c < kChunk; ++c, ++launched) {
-      const bool even = (launched % 2) == 0;
-      double* po = even ? w.p0 : w.p1;
-      double* pn = even ? w.p1 : w.p0;
-      HKP_CHECK(launch_cg_iter(g, w.cx, w.cy, w.cz, w.dinv, dir, w.z, po, pn, w.q, phi, w.r,
-                               w.partial, max_iter, w.st, s));
-    }
+    if (use_graph)
+      HKP_CHECK(hipGraphLaunch(gc->exec, s));
+    else
+      launch_cg_chunk(g, dir, phi, max_iter, w, s);
+    launched += kCGChunk;
   }
   if (iters) *iters = h.it;
   if (relres) *relres = h.bb > 0.0 ? std::sqrt(h.rr / h.bb) : 0.0;
@@ -126,8 +170,9 @@ int run_poisson(const PoissonArgs& a, int* iters, double* relres) {
   const PoissonWS w = carve_poisson(c, g.NP);
   const int rc = poisson_prepare(g, a.h, a.eps, a.dir, w, s);
   if (rc != HKP_OK) return rc;
+  CGGraph gc;
   return poisson_cg(g, a.dir, a.phi_fixed, a.rho, a.phi, a.tol, a.max_iter, w, s, iters,
-                    relres);
+                    relres, &gc);
 }
 
 namespace {
@@ -192,6 +237,7 @@ int run_sp(const SPArgs& a, hkp_sp_stats* stats) {
 
   int rc = poisson_prepare(g, h, a.eps, a.dir, L.pw, s);
   if (rc != HKP_OK) return rc;
+  CGGraph cg_graph;
   // the fixed charge alone (the hole part of rho is added every iteration)
   HKP_CHECK(launch_rho(g, ox, oy, oz, p.nx, p.ny, p.nz, 0, nullptr, 0, nullptr, 0.0,
                        a.rho_fixed, L.rho, nullptr, s));
@@ -201,7 +247,7 @@ int run_sp(const SPArgs& a, hkp_sp_stats* stats) {
     int it = 0;
     const auto t0 = std::chrono::steady_clock::now();
     rc = poisson_cg(g, a.dir, a.phi_fixed, L.rho, a.phi, a.sp.cg_tol, a.sp.cg_max_iter, L.pw, s,
-                    &it, nullptr);
+                    &it, nullptr, &cg_graph);
     t_poi += seconds_since(t0);
     st.cg_iters += it;
     if (rc < 0) return rc;
@@ -271,7 +317,7 @@ int run_sp(const SPArgs& a, hkp_sp_stats* stats) {
                               ? std::max(a.sp.cg_tol, std::min(1e-6, 1e-2 * delta_prev))
                               : a.sp.cg_tol;
     rc = poisson_cg(g, a.dir, a.phi_fixed, L.rho, L.phi_out, cg_tol, a.sp.cg_max_iter, L.pw, s,
-                    &cgit, nullptr);
+                    &cgit, nullptr, &cg_graph);
     st.cg_iters += cgit;
     if (rc < 0) return rc;
     if (rc != HKP_OK) st.poisson_status = rc;

@@ -48,6 +48,11 @@ def test_poisson_vs_oracle(shape):
     assert code == 0 and rel <= 1e-13
     ref = poisson_solve(shape, 0.4, eps, dirichlet, phi_fixed, rho)
     assert np.abs(phi.cpu().numpy() - ref).max() <= 1e-9 * max(1.0, np.abs(ref).max())
+    # the iterations replayed from a recorded graph and launched one by one are the
+    # same kernels in the same order: identical results
+    phi_e, it_e, _, _ = hkp.poisson(_t(eps), _t(dirichlet), _t(phi_fixed), _t(rho), 0.4,
+                                    tol=1e-13, graph=False)
+    assert it_e == it and np.array_equal(phi_e.cpu().numpy(), phi.cpu().numpy())
 
 
 def test_poisson_warm_start_and_no_charge():
