@@ -40,3 +40,4 @@ from .poisson import (  # noqa: F401
     E_OVER_EPS0, KB, link_permittivity, poisson_operator, poisson_solve, occupancy,
     hole_density, embed, restrict, sp_loop,
 )
+from .spinfree import h0_orbital, soi_matrix, single_particle  # noqa: F401
