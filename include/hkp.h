@@ -70,6 +70,10 @@ extern "C" {
 #define HKP_FLAG_X0_NEV 16      /* with HKP_FLAG_X0: X0 holds nev vectors per member (a
                                  * previous solve's psi); the block's other nb - nev
                                  * vectors are drawn at random from the seed */
+#define HKP_FLAG_SPIN_FREE 64   /* the spin-free orbital problem H_0 = H_DKK + V + H'_PB
+                                 * (Eq. H0, Sec. II.D): no spin-orbit term (delta_so is
+                                 * taken as 0), B_T must be zero; each orbital level once;
+                                 * X0 and psi are complex [n][nx][ny][nz][3] (X, Y, Z) */
 #define HKP_FLAG_PSI_BLOCK 32   /* psi receives the whole final block of nb Ritz vectors
                                  * (ascending Ritz values; eig and resid still nev), the
                                  * initial block of a restart that keeps the guard vectors */
@@ -299,6 +303,23 @@ int hkp_autotune_block(const hkp_grid* grid, const hkp_material* mat, const hkp_
                        const int32_t* candidates, int32_t ncand, void* workspace,
                        size_t ws_bytes, void* hip_stream, int32_t* nb_out,
                        double* seconds_out);
+
+/* Workspace of hkp_soi_matrix for M orbitals on `grid`. */
+size_t hkp_soi_workspace_bytes(const hkp_grid* grid, int32_t M);
+
+/* Spin-orbit matrix of M spin-free orbitals (Eq. H1, Fig. 2d-e): out[2i+s][2j+t] =
+ * <phi_i s| H_SO |phi_j t> with H_SO = (delta_so / 3)(1 - sum_a sigma_a (x) L_a) on
+ * every grid point, (L_a)_bc = -i eps_abc on (X, Y, Z), s = 0 up, 1 down; plus
+ * E_i on the diagonal when E is given (the single-particle part of the
+ * configuration-interaction Hamiltonian in the basis phi_i (x) s).
+ *   phi   device complex double [M][nx][ny][nz][3] (hkp_solve with
+ *         HKP_FLAG_SPIN_FREE), 1 <= M <= 21
+ *   E_eV  device double [M] or NULL
+ *   out   device complex double [2M][2M]
+ * The component overlaps are reduced in a fixed order (deterministic). */
+int hkp_soi_matrix(const hkp_grid* grid, int32_t M, const void* phi, const double* E_eV,
+                   double delta_so_eV, void* out, void* workspace, size_t ws_bytes,
+                   void* hip_stream);
 
 /* Workspace of hkp_poisson for this box. */
 size_t hkp_poisson_workspace_bytes(const hkp_pgrid* pgrid);

@@ -27,6 +27,7 @@ HKP_FLAG_NO_FP64_POLISH = 4
 HKP_FLAG_NO_LOCK = 8
 HKP_FLAG_X0_NEV = 16
 HKP_FLAG_PSI_BLOCK = 32
+HKP_FLAG_SPIN_FREE = 64
 HKP_SP_PHI0 = 1
 HKP_SP_EXACT_EIG = 2
 
@@ -117,6 +118,9 @@ SIGNATURES = {
     "hkp_autotune_block": (C.c_int, [C.POINTER(hkp_grid), C.POINTER(hkp_material),
                                      C.POINTER(hkp_opts), _P, _P, _D, C.POINTER(C.c_int32),
                                      C.c_int32, _P, C.c_size_t, _P, C.POINTER(C.c_int32), _D]),
+    "hkp_soi_workspace_bytes": (C.c_size_t, [C.POINTER(hkp_grid), C.c_int32]),
+    "hkp_soi_matrix": (C.c_int, [C.POINTER(hkp_grid), C.c_int32, _P, _P, C.c_double, _P, _P,
+                                 C.c_size_t, _P]),
     "hkp_poisson_workspace_bytes": (C.c_size_t, [C.POINTER(hkp_pgrid)]),
     "hkp_poisson": (C.c_int, [C.POINTER(hkp_pgrid), C.c_double, _P, _P, _P, _P, _P, C.c_double,
                               C.c_int32, _P, C.c_size_t, _P, C.POINTER(C.c_int32), _D]),

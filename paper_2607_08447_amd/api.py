@@ -88,16 +88,16 @@ def workspace_bytes(shape, h, nev, nb=0, degree=0, precision="fp64", batch=1):
     return int(n)
 
 
-def _x0(X0, lead, nev, nb, shape):
-    """Initial-block flags and block size for X0 of shape lead + [k, nx, ny, nz, 6]:
+def _x0(X0, lead, nev, nb, shape, ncomp=6):
+    """Initial-block flags and block size for X0 of shape lead + [k, nx, ny, nz, ncomp]:
     k = nev is a previous solve's psi (the rest of the block drawn at random),
     any other k is the whole block (nb = k)."""
     X0d = _dev(X0, torch.complex128)
     if X0d is None:
         return None, 0, nb
     if X0d.dim() != len(lead) + 5 or tuple(X0d.shape[:len(lead)]) != lead \
-            or tuple(X0d.shape[len(lead) + 1:]) != shape + (6,):
-        raise ValueError(f"X0 must be {list(lead)} + [nev or nb, nx, ny, nz, 6]")
+            or tuple(X0d.shape[len(lead) + 1:]) != shape + (ncomp,):
+        raise ValueError(f"X0 must be {list(lead)} + [nev or nb, nx, ny, nz, {ncomp}]")
     k = X0d.shape[len(lead)]
     if k == nev:
         return X0d, L.HKP_FLAG_X0 | L.HKP_FLAG_X0_NEV, nb
@@ -116,8 +116,13 @@ def _npsi(g, o, nev, block):
 
 def solve(V, h, nev, strain=None, B=(0.0, 0.0, 0.0), nb=0, degree=0, tol=1e-8,
           precision="fp64", max_iter=200, seed=1, X0=None, graph=False, material=None,
-          return_psi=True, workspace=None, polish=True, lock=True, psi_block=False):
+          return_psi=True, workspace=None, polish=True, lock=True, psi_block=False,
+          spin_free=False):
     """Lowest `nev` eigenpairs of H for the potential V (float64 [nx, ny, nz], eV).
+
+    spin_free=True solves the orbital problem H_0 without spin-orbit coupling
+    (B must be zero): each orbital level once, psi (and X0) [n, nx, ny, nz, 3]
+    holding the X, Y, Z components.
 
     X0 (optional, complex128): the whole initial block [nb, nx, ny, nz, 6], or
     [nev, nx, ny, nz, 6] -- a previous solve's psi -- completed with random
@@ -130,8 +135,9 @@ def solve(V, h, nev, strain=None, B=(0.0, 0.0, 0.0), nb=0, degree=0, tol=1e-8,
         raise ValueError("V must be [nx, ny, nz]")
     strain = _dev(strain, torch.float64)
     g = _grid(shape, h)
-    X0d, xflags, nb = _x0(X0, (), nev, nb, shape)
-    flags = (L.HKP_FLAG_GRAPH if graph else 0) | xflags
+    ncomp = 3 if spin_free else 6
+    X0d, xflags, nb = _x0(X0, (), nev, nb, shape, ncomp)
+    flags = (L.HKP_FLAG_GRAPH if graph else 0) | xflags | (L.HKP_FLAG_SPIN_FREE if spin_free else 0)
     if not polish:
         flags |= L.HKP_FLAG_NO_FP64_POLISH
     if not lock:
@@ -146,7 +152,7 @@ def solve(V, h, nev, strain=None, B=(0.0, 0.0, 0.0), nb=0, degree=0, tol=1e-8,
         ws = torch.empty(need, dtype=torch.uint8, device="cuda")
     E = torch.empty(nev, dtype=torch.float64, device="cuda")
     R = torch.empty(nev, dtype=torch.float64, device="cuda")
-    psi = torch.empty((npsi,) + shape + (6,), dtype=torch.complex128, device="cuda") \
+    psi = torch.empty((npsi,) + shape + (ncomp,), dtype=torch.complex128, device="cuda") \
         if return_psi else None
     st = L.hkp_stats()
     stream_ctx = torch.cuda.Stream() if graph else None
@@ -169,7 +175,7 @@ def solve(V, h, nev, strain=None, B=(0.0, 0.0, 0.0), nb=0, degree=0, tol=1e-8,
 def solve_batch(V, h, nev, strain=None, B=(0.0, 0.0, 0.0), nb=0, degree=0, tol=1e-8,
                 precision="fp64", max_iter=200, seed=1, graph=True, material=None,
                 return_psi=False, workspace=None, polish=True, lock=True, X0=None,
-                psi_block=False):
+                psi_block=False, spin_free=False):
     """Lowest eigenpairs of `batch` Hamiltonians differing in V ([batch, nx, ny, nz]).
     X0 (optional, complex128): [batch, nb or nev, nx, ny, nz, 6]; X0 and
     psi_block as in solve()."""
@@ -180,8 +186,9 @@ def solve_batch(V, h, nev, strain=None, B=(0.0, 0.0, 0.0), nb=0, degree=0, tol=1
     shape = tuple(V.shape[1:])
     strain = _dev(strain, torch.float64)
     g = _grid(shape, h)
-    X0d, xflags, nb = _x0(X0, (batch,), nev, nb, shape)
-    flags = (L.HKP_FLAG_GRAPH if graph else 0) | xflags
+    ncomp = 3 if spin_free else 6
+    X0d, xflags, nb = _x0(X0, (batch,), nev, nb, shape, ncomp)
+    flags = (L.HKP_FLAG_GRAPH if graph else 0) | xflags | (L.HKP_FLAG_SPIN_FREE if spin_free else 0)
     if not polish:
         flags |= L.HKP_FLAG_NO_FP64_POLISH
     if not lock:
@@ -196,7 +203,7 @@ def solve_batch(V, h, nev, strain=None, B=(0.0, 0.0, 0.0), nb=0, degree=0, tol=1
         ws = torch.empty(need, dtype=torch.uint8, device="cuda")
     E = torch.empty((batch, nev), dtype=torch.float64, device="cuda")
     R = torch.empty((batch, nev), dtype=torch.float64, device="cuda")
-    psi = torch.empty((batch, npsi) + shape + (6,), dtype=torch.complex128, device="cuda") \
+    psi = torch.empty((batch, npsi) + shape + (ncomp,), dtype=torch.complex128, device="cuda") \
         if return_psi else None
     st = L.hkp_stats()
     mat = _material(material)
@@ -312,6 +319,29 @@ def hf_grad(psi, w, Lg):
     L.check(L.lib.hkp_hf_grad(N, nev, _ptr(psi), _ptr(w), G, _ptr(Lg), _ptr(grad), _ptr(ws),
                               C.c_size_t(need), _stream()))
     return grad
+
+
+def soi_matrix(phi, delta_so=None, E=None, material=None):
+    """[2M, 2M] spin-orbit matrix <phi_i s| H_SO |phi_j t> (index 2 i + s) of M
+    spin-free orbitals phi [M, nx, ny, nz, 3] (from solve(..., spin_free=True));
+    with E [M] the orbital energies go on the diagonal.  delta_so defaults to
+    the material's."""
+    phi = _dev(phi, torch.complex128)
+    if phi.dim() != 5 or phi.shape[-1] != 3:
+        raise ValueError("phi must be [M, nx, ny, nz, 3]")
+    M = phi.shape[0]
+    if delta_so is None:
+        delta_so = _material(material).delta_so_eV
+    g = _grid(tuple(phi.shape[1:4]), 1.0)
+    need = L.lib.hkp_soi_workspace_bytes(C.byref(g), M)
+    if need == 0:
+        raise L.HkpError(L.HKP_E_ARG, L.lib.hkp_last_error().decode())
+    ws = torch.empty(need, dtype=torch.uint8, device="cuda")
+    E = _dev(E, torch.float64)
+    out = torch.empty((2 * M, 2 * M), dtype=torch.complex128, device="cuda")
+    L.check(L.lib.hkp_soi_matrix(C.byref(g), M, _ptr(phi), _ptr(E), float(delta_so), _ptr(out),
+                                 _ptr(ws), C.c_size_t(need), _stream()))
+    return out
 
 
 # ---------------------------------------------------------------------------

@@ -18,7 +18,8 @@ OBJ = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libhkp.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
-SOURCES = ["stencil.hip", "fields.hip", "blas.hip", "eig.hip", "sp.hip", "solver.cpp",
+SOURCES = ["stencil.hip", "fields.hip", "blas.hip", "eig.hip", "sp.hip", "spinfree.hip",
+           "solver.cpp",
            "sp_loop.cpp", "abi.cpp", "autotune.cpp"]
 
 FLAGS = ["--offload-arch=gfx950", "-O3", "-fPIC", "-std=c++17",

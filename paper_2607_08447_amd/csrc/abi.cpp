@@ -189,6 +189,10 @@ int solve_common(const hkp_grid* grid, const hkp_material* mat, const hkp_opts* 
     set_error("HKP_FLAG_GRAPH needs a non-default stream (the legacy stream cannot be captured)");
     return HKP_E_ARG;
   }
+  if ((opts->flags & HKP_FLAG_SPIN_FREE) && (B[0] != 0.0 || B[1] != 0.0 || B[2] != 0.0)) {
+    set_error("HKP_FLAG_SPIN_FREE needs B = 0");
+    return HKP_E_ARG;
+  }
   Plan p = make_plan(*grid, *opts, batch);
   const size_t need = plan_bytes(p);
   if (ws_bytes < need) {
@@ -199,6 +203,7 @@ int solve_common(const hkp_grid* grid, const hkp_material* mat, const hkp_opts* 
   SolveArgs a{};
   a.plan = p;
   a.mat = *mat;
+  if (opts->flags & HKP_FLAG_SPIN_FREE) a.mat.delta_so_eV = 0.0;   // H_0 has no spin-orbit term
   a.V = V;
   a.strain = strain;
   for (int i = 0; i < 3; ++i) a.B[i] = B[i];
@@ -449,6 +454,53 @@ int hkp_autotune_block(const hkp_grid* grid, const hkp_material* mat, const hkp_
 }
 
 const char* hkp_last_error(void) { return g_err.c_str(); }
+
+size_t hkp_soi_workspace_bytes(const hkp_grid* grid, int32_t M) {
+  if (check_grid(grid) != HKP_OK) return 0;
+  if (M < 1 || 3 * M > HKP_NB_MAX) {
+    set_error("hkp_soi_matrix: 1 <= M <= 21");
+    return 0;
+  }
+  const long long N = (long long)grid->nx * grid->ny * grid->nz;
+  auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
+  return al((size_t)3 * M * N * 16) + al(gram_partial_bytes(3 * M, N, 1)) +
+         al((size_t)9 * M * M * 16);
+}
+
+int hkp_soi_matrix(const hkp_grid* grid, int32_t M, const void* phi, const double* E_eV,
+                   double delta_so_eV, void* out, void* workspace, size_t ws_bytes,
+                   void* hip_stream) {
+  HKP_TRY(check_grid(grid));
+  if (M < 1 || 3 * M > HKP_NB_MAX || !phi || !out || !workspace || !std::isfinite(delta_so_eV)) {
+    set_error("hkp_soi_matrix: 1 <= M <= 21, finite delta_so, non-NULL phi, out, workspace");
+    return HKP_E_ARG;
+  }
+  const size_t need = hkp_soi_workspace_bytes(grid, M);
+  if (ws_bytes < need) {
+    set_error("workspace too small: need " + std::to_string(need) + " bytes");
+    return HKP_E_WORKSPACE;
+  }
+  HKP_TRY(check_device());
+  return guarded([&]() {
+    const long long N = (long long)grid->nx * grid->ny * grid->nz;
+    auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
+    char* w = static_cast<char*>(workspace);
+    double* comp = reinterpret_cast<double*>(w);
+    double* partial = reinterpret_cast<double*>(w + al((size_t)3 * M * N * 16));
+    double* O = reinterpret_cast<double*>(w + al((size_t)3 * M * N * 16) +
+                                          al(gram_partial_bytes(3 * M, N, 1)));
+    hipStream_t s = (hipStream_t)hip_stream;
+    hipError_t e = launch_gather_components(N, M, phi, comp, s);
+    const BlockDesc A{comp, N, 3 * M, 3LL * M * N};
+    if (e == hipSuccess) e = launch_gram(A, A, 1, 1, partial, O, nullptr, s);
+    if (e == hipSuccess) e = launch_soi_assemble(M, O, E_eV, delta_so_eV, out, s);
+    if (e != hipSuccess) {
+      set_error(hipGetErrorString(e));
+      return HKP_E_HIP;
+    }
+    return HKP_OK;
+  });
+}
 
 size_t hkp_poisson_workspace_bytes(const hkp_pgrid* pgrid) {
   if (check_pgrid(pgrid, nullptr) != HKP_OK) return 0;

@@ -198,6 +198,22 @@ hipError_t launch_init_coef(const Control& c, int batch, int degree, int kmax,
                             hipStream_t s);
 
 // ---------------------------------------------------------------------------
+// spin-free basis (orbital vectors [v][x][y][z][3] complex) and spin-orbit matrix
+// ---------------------------------------------------------------------------
+hipError_t launch_orbital_to_internal(int nx, int ny, int nz, int nvec, const void* orb,
+                                      double* internal, hipStream_t s);
+hipError_t launch_zero_down(long long N, int nvec, double* internal, hipStream_t s);
+hipError_t launch_internal_to_orbital(int nx, int ny, int nz, int nvec, int batch,
+                                      const double* internal, long long in_bstride, void* orb,
+                                      long long out_bstride, hipStream_t s);
+// [M][N][3] -> [3M][N] (component b of orbital i is vector 3 i + b)
+hipError_t launch_gather_components(long long N, int M, const void* orb, double* comp,
+                                    hipStream_t s);
+// O: [3M][3M] complex overlaps; out: [2M][2M] complex, index 2 i + s; E may be null
+hipError_t launch_soi_assemble(int M, const double* O, const double* E, double delta_so,
+                               void* out, hipStream_t s);
+
+// ---------------------------------------------------------------------------
 // self-consistent loop: Poisson (conjugate gradients), occupancy, density,
 // Anderson mixing.  Poisson-box arrays are real [px][py][pz] (z fastest).
 // ---------------------------------------------------------------------------

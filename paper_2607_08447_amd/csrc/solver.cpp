@@ -553,7 +553,23 @@ int run_solve(const SolveArgs& A, hkp_stats* stats) {
   }
 
   // ---- initial block: caller's X0 or random; SVQB; Rayleigh-Ritz
-  if (A.X0 && !(A.flags & HKP_FLAG_X0_NEV)) {
+  const bool spin_free = (A.flags & HKP_FLAG_SPIN_FREE) != 0;
+  if (spin_free) {
+    // orbital blocks: the spin-down half of every vector stays exactly zero
+    double* X = c.at<double>(c.L.X);
+    if (A.X0 && !(A.flags & HKP_FLAG_X0_NEV)) {
+      HKP_CHECK(launch_orbital_to_internal(p.nx, p.ny, p.nz, p.nb * p.batch, A.X0, X, c.s));
+    } else {
+      HKP_CHECK(launch_random_block(X, p.n6, p.nb, p.batch, c.bstride(), A.seed, c.s));
+      HKP_CHECK(launch_zero_down(p.N, p.nb * p.batch, X, c.s));
+      if (A.X0)
+        for (int b = 0; b < p.batch; ++b)
+          HKP_CHECK(launch_orbital_to_internal(
+              p.nx, p.ny, p.nz, p.nev,
+              static_cast<const double*>(A.X0) + 2 * (size_t)b * p.nev * 3 * p.N,
+              X + 2 * (size_t)b * c.bstride(), c.s));
+    }
+  } else if (A.X0 && !(A.flags & HKP_FLAG_X0_NEV)) {
     // [batch][nb] vectors, contiguous in both layouts (member stride nb n6)
     HKP_CHECK(launch_abi_to_internal(p.nx, p.ny, p.nz, p.h, A.B, p.nb * p.batch, A.X0,
                                      c.at<double>(c.L.X), 0, c.s));
@@ -715,7 +731,10 @@ int run_solve(const SolveArgs& A, hkp_stats* stats) {
   HKP_CHECK(launch_finish(c.at<double>(c.L.theta), c.at<double>(c.L.r2), p.nb, p.nev, p.batch,
                           A.eig, A.resid, c.s));
   const int npsi = (A.flags & HKP_FLAG_PSI_BLOCK) ? p.nb : p.nev;
-  if (A.psi)
+  if (A.psi && spin_free)
+    HKP_CHECK(launch_internal_to_orbital(p.nx, p.ny, p.nz, npsi, p.batch, c.at<double>(c.L.X),
+                                         c.bstride(), A.psi, (long long)npsi * 3 * p.N, c.s));
+  else if (A.psi)
     HKP_CHECK(launch_internal_to_abi(p.nx, p.ny, p.nz, p.h, A.B, npsi, p.batch,
                                      c.at<double>(c.L.X), c.bstride(), A.psi,
                                      (long long)npsi * p.n6, c.s));

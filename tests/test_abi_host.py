@@ -227,3 +227,24 @@ def test_sp_entry_points_reject_bad_arguments():
     assert L.lib.hkp_occupancy(8, fake, 9.0, 1.5, fake, None, None) == L.HKP_E_ARG
     assert L.lib.hkp_occupancy(8, fake, 2.0, 0.0, fake, None, None) == L.HKP_E_ARG
     assert L.lib.hkp_hole_density(C.byref(g), 0, fake, fake, fake, None) == L.HKP_E_ARG
+
+
+def test_spin_free_entry_points_reject_bad_arguments():
+    L, g, m, o = _structs()
+    fake = C.c_void_p(0x1000)
+    assert L.lib.hkp_soi_workspace_bytes(C.byref(g), 21) > 0
+    assert L.lib.hkp_soi_workspace_bytes(C.byref(g), 22) == 0
+    assert L.lib.hkp_soi_workspace_bytes(C.byref(g), 0) == 0
+    assert L.lib.hkp_soi_matrix(C.byref(g), 22, fake, None, 0.044, fake, fake, 1 << 40,
+                                None) == L.HKP_E_ARG
+    assert L.lib.hkp_soi_matrix(C.byref(g), 4, fake, None, float("nan"), fake, fake, 1 << 40,
+                                None) == L.HKP_E_ARG
+    assert L.lib.hkp_soi_matrix(C.byref(g), 4, fake, None, 0.044, fake, fake, 16,
+                                None) == L.HKP_E_WORKSPACE
+    # the spin-free problem is defined at zero field only
+    o.nev, o.nb, o.flags = 8, 16, L.HKP_FLAG_SPIN_FREE
+    B = (C.c_double * 3)(0.0, 0.0, 0.1)
+    st = L.hkp_stats()
+    assert L.lib.hkp_solve(C.byref(g), C.byref(m), C.byref(o), fake, None, B, None, fake, None,
+                           None, fake, 1 << 40, None, C.byref(st)) == L.HKP_E_ARG
+    assert b"B = 0" in L.lib.hkp_last_error()
