@@ -69,14 +69,15 @@ int check_opts(const hkp_grid* g, const hkp_opts* o) {
     set_error("opts is NULL");
     return HKP_E_ARG;
   }
-  const long long n6 = 6LL * g->nx * g->ny * g->nz;
+  // unknowns per vector: 6 N, or 3 N for the spin-free orbital problem
+  const long long n6 = ((o->flags & HKP_FLAG_SPIN_FREE) ? 3LL : 6LL) * g->nx * g->ny * g->nz;
   if (o->nev < 1 || o->nev > n6) {
-    set_error("nev must satisfy 1 <= nev <= 6 N");
+    set_error("nev must satisfy 1 <= nev <= 6 N (3 N spin-free)");
     return HKP_E_ARG;
   }
   const int nb = block_size(*g, *o);
   if (o->nb < 0 || nb > HKP_NB_MAX || nb > n6 || nb <= o->nev) {
-    set_error("block size must satisfy nev < nb <= min(64, 6 N)");
+    set_error("block size must satisfy nev < nb <= min(64, 6 N) (3 N spin-free)");
     return HKP_E_ARG;
   }
   if (o->degree < 0 || o->degree > 200) {

@@ -91,6 +91,7 @@ struct StencilLaunch {
   int dma;               // 1: rows staged global -> LDS directly (needs nx % 64 == 0)
   int zsplit;            // z ranges per (vector, tile): 0 never, 1 for small launches, 2 always
   int fp64;              // kernel type
+  int ncomp = 6;         // components per vector: 6 (spinor) or 3 (spin-free orbital, no field)
 };
 
 hipError_t launch_stencil(const StencilLaunch& a, const StencilConsts<double>& c,
@@ -202,7 +203,6 @@ hipError_t launch_init_coef(const Control& c, int batch, int degree, int kmax,
 // ---------------------------------------------------------------------------
 hipError_t launch_orbital_to_internal(int nx, int ny, int nz, int nvec, const void* orb,
                                       double* internal, hipStream_t s);
-hipError_t launch_zero_down(long long N, int nvec, double* internal, hipStream_t s);
 hipError_t launch_internal_to_orbital(int nx, int ny, int nz, int nvec, int batch,
                                       const double* internal, long long in_bstride, void* orb,
                                       long long out_bstride, hipStream_t s);

@@ -161,7 +161,7 @@ struct StencilStats {
     const double sold = a.old ? (a.old_fp64 ? 16 : 8) : 0;
     const double sout = a.out_fp64 ? 16 : 8;
     if (nvec_done < 0) nvec_done = (double)active_members * a.nvec;
-    const double b = (double)N * 6 * nvec_done * (sin + sold + sout) +
+    const double b = (double)N * a.ncomp * nvec_done * (sin + sold + sout) +
                      (double)active_members * N * (a.strain ? 6 : 1) * (a.fp64 ? 8 : 4);
     hx_bytes += b;
     if (!timed) {
@@ -252,6 +252,7 @@ StencilLaunch base_launch(const Ctx& c, bool fp64, int nvec) {
   a.dma = c.p.st.dma;
   a.zsplit = c.p.st.zsplit;
   a.fp64 = fp64;
+  a.ncomp = c.p.ncomp;
   a.coef.coef = nullptr;
   a.coef.alpha = 1.0;
   a.coef.shift = 0.0;
@@ -464,7 +465,8 @@ Plan make_plan(const hkp_grid& g, const hkp_opts& o, int batch) {
   p.nz = g.nz;
   p.h = g.h_nm;
   p.N = (long long)g.nx * g.ny * g.nz;
-  p.n6 = 6 * p.N;
+  p.ncomp = (o.flags & HKP_FLAG_SPIN_FREE) ? 3 : 6;
+  p.n6 = p.ncomp * p.N;
   p.batch = batch;
   p.nev = o.nev;
   p.nb = block_size(g, o);
@@ -555,13 +557,12 @@ int run_solve(const SolveArgs& A, hkp_stats* stats) {
   // ---- initial block: caller's X0 or random; SVQB; Rayleigh-Ritz
   const bool spin_free = (A.flags & HKP_FLAG_SPIN_FREE) != 0;
   if (spin_free) {
-    // orbital blocks: the spin-down half of every vector stays exactly zero
+    // three-component orbital blocks
     double* X = c.at<double>(c.L.X);
     if (A.X0 && !(A.flags & HKP_FLAG_X0_NEV)) {
       HKP_CHECK(launch_orbital_to_internal(p.nx, p.ny, p.nz, p.nb * p.batch, A.X0, X, c.s));
     } else {
       HKP_CHECK(launch_random_block(X, p.n6, p.nb, p.batch, c.bstride(), A.seed, c.s));
-      HKP_CHECK(launch_zero_down(p.N, p.nb * p.batch, X, c.s));
       if (A.X0)
         for (int b = 0; b < p.batch; ++b)
           HKP_CHECK(launch_orbital_to_internal(

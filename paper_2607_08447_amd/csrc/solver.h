@@ -25,7 +25,8 @@ struct StencilTune {
 struct Plan {
   int nx, ny, nz;
   double h;
-  long long N, n6;   // grid points, complex unknowns per vector
+  long long N, n6;   // grid points, complex unknowns per vector (ncomp N)
+  int ncomp;         // 6 (spinor) or 3 (spin-free orbital)
   int batch, nev, nb, degree;   // degree: fixed value or the ramp's maximum
   bool degree_fixed;
   bool mixed;

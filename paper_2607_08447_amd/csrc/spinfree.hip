@@ -2,12 +2,12 @@
 // matrix (Eq. H1, Fig. 2d-e).
 //
 // Without spin-orbit coupling and magnetic field the |L S> Hamiltonian is two
-// identical, uncoupled 3 x 3 orbital blocks.  A spin-free solve keeps the
-// spin-down half of every block vector at exactly zero: the stencil never
-// couples the halves (every spin-flip coefficient is zero), so linear
-// combinations, the filter and Rayleigh-Ritz all stay in the spin-up half, and
-// each orbital level appears once.  The orbital vectors cross the boundary as
-// complex [v][x][y][z][3] (X, Y, Z), no basis change and no gauge (B = 0).
+// identical, uncoupled 3 x 3 orbital blocks.  A spin-free solve works on
+// three-component vectors (internal [v][c][z][y][x], c = X, Y, Z of one spin):
+// the stencil's spin-free variant touches half the bytes of a spinor, and the
+// block kernels (Gram, rotation, residuals) see vectors of 3N entries.  Each
+// orbital level appears once.  The orbital vectors cross the boundary as
+// complex [v][x][y][z][3], no basis change and no gauge (B = 0).
 //
 // The spin-orbit matrix of M orbitals is formed from their 3M x 3M component
 // overlaps <phi_i,b | phi_j,c> (the FP64 MFMA Gram kernel on the components
@@ -21,7 +21,7 @@ namespace hkp {
 
 namespace {
 
-// [v][x][y][z][3] -> internal [v][c][z][y][x] (spin-up components; spin-down zero)
+// [v][x][y][z][3] -> internal [v][c][z][y][x], c < 3
 __global__ void orbital_to_internal_kernel(int nx, int ny, int nz, const double2* orb,
                                            double2* internal) {
   const long long N = (long long)nx * ny * nz;
@@ -33,21 +33,11 @@ __global__ void orbital_to_internal_kernel(int nx, int ny, int nz, const double2
   const int z = (int)(p / ((long long)nx * ny));
   const long long a = ((long long)x * ny + y) * nz + z;
   const double2* src = orb + ((long long)v * N + a) * 3;
-  double2* dst = internal + (long long)v * 6 * N + p;
+  double2* dst = internal + (long long)v * 3 * N + p;
   for (int c = 0; c < 3; ++c) dst[(long long)c * N] = src[c];
-  for (int c = 3; c < 6; ++c) dst[(long long)c * N] = make_double2(0.0, 0.0);
 }
 
-// spin-down components of nvec internal vectors set to zero
-__global__ void zero_down_kernel(long long N, double2* internal) {
-  const long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  const int v = blockIdx.y;
-  if (p >= N) return;
-  double2* dst = internal + (long long)v * 6 * N + p;
-  for (int c = 3; c < 6; ++c) dst[(long long)c * N] = make_double2(0.0, 0.0);
-}
-
-// internal [b][v][c][z][y][x] -> [b][v][x][y][z][3] (spin-up components)
+// internal [b][v][c][z][y][x] -> [b][v][x][y][z][3]
 __global__ void internal_to_orbital_kernel(int nx, int ny, int nz, const double2* internal,
                                            long long in_bstride, double2* orb,
                                            long long out_bstride) {
@@ -59,7 +49,7 @@ __global__ void internal_to_orbital_kernel(int nx, int ny, int nz, const double2
   const int y = (int)((p / nx) % ny);
   const int z = (int)(p / ((long long)nx * ny));
   const long long a = ((long long)x * ny + y) * nz + z;
-  const double2* src = internal + (long long)b * in_bstride + (long long)v * 6 * N + p;
+  const double2* src = internal + (long long)b * in_bstride + (long long)v * 3 * N + p;
   double2* dst = orb + (long long)b * out_bstride + ((long long)v * N + a) * 3;
   for (int c = 0; c < 3; ++c) dst[c] = src[(long long)c * N];
 }
@@ -129,19 +119,7 @@ hipError_t launch_orbital_to_internal(int nx, int ny, int nz, int nvec, const vo
     const int nv = nvec - v0 < kChunk ? nvec - v0 : kChunk;
     orbital_to_internal_kernel<<<dim3(blocks(N), (unsigned)nv), 256, 0, s>>>(
         nx, ny, nz, static_cast<const double2*>(orb) + (long long)v0 * N * 3,
-        reinterpret_cast<double2*>(internal) + (long long)v0 * N * 6);
-    const hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-  }
-  return hipSuccess;
-}
-
-hipError_t launch_zero_down(long long N, int nvec, double* internal, hipStream_t s) {
-  constexpr int kChunk = 32768;
-  for (int v0 = 0; v0 < nvec; v0 += kChunk) {
-    const int nv = nvec - v0 < kChunk ? nvec - v0 : kChunk;
-    zero_down_kernel<<<dim3(blocks(N), (unsigned)nv), 256, 0, s>>>(
-        N, reinterpret_cast<double2*>(internal) + (long long)v0 * N * 6);
+        reinterpret_cast<double2*>(internal) + (long long)v0 * N * 3);
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }

@@ -136,9 +136,13 @@ struct IC {
 // row go global -> LDS directly (global_load_lds, no registers), issued one
 // plane ahead and waited for at the end of the step; the two x-halo columns
 // use ordinary loads.
-template <typename T, typename TO, typename TW, int PH, bool STR, int TY, bool DMA>
-__global__ void __launch_bounds__(128 * TY)
+// NC = 6: the full spinor (a wave per spin and row).  NC = 3: a spin-free orbital
+// vector (X, Y, Z of one spin; no spin-orbit or field terms, so nothing couples
+// it to the other spin): one wave per row and half the bytes.
+template <typename T, typename TO, typename TW, int PH, bool STR, int TY, bool DMA, int NC = 6>
+__global__ void __launch_bounds__(64 * TY * (NC / 3))
 stencil_kernel(KArgs<T> a) {
+  static_assert(NC == 6 || (NC == 3 && PH == 0), "spin-free vectors carry no field terms");
   // LDS row: [pad] left halo, 64 interior, right halo [pad]; with FP32 DMA the
   // interior starts on a 16-byte boundary (column 2 of a 68-wide row)
   constexpr int C0 = (DMA && sizeof(T) == 4) ? 2 : 1;   // column of x = tx0
@@ -146,12 +150,12 @@ stencil_kernel(KArgs<T> a) {
   constexpr int ROWS = TY + 2;
   constexpr int SLOTS = W * ROWS;
   constexpr int PLANE = SLOTS;        // elements per (buffer, component) plane
-  constexpr int NT = 128 * TY;        // (x, y, spin) threads
+  constexpr int NT = 64 * TY * (NC / 3);   // (x, y, spin) threads
   constexpr int NS = (SLOTS + NT - 1) / NT;
   // double-buffered plane: [component][row][col] each (two distinct arrays, so the
   // compiler can tell the buffer being read from the one being filled)
-  __shared__ cx<T> lds0[6 * PLANE];
-  __shared__ cx<T> lds1[6 * PLANE];
+  __shared__ cx<T> lds0[NC * PLANE];
+  __shared__ cx<T> lds1[NC * PLANE];
   auto bufp = [&](auto BUF) -> cx<T>* {
     if constexpr (decltype(BUF)::value == 0) return lds0; else return lds1;
   };
@@ -236,13 +240,13 @@ stencil_kernel(KArgs<T> a) {
   const bool has_old = a.old != nullptr && beta != (T)0;
 
   // uniform (scalar) bases; lane offsets are 32-bit element indices
-  const T* __restrict__ in = a.in + 2 * ((long long)b * a.in_bstride + (long long)vec * 6 * N);
+  const T* __restrict__ in = a.in + 2 * ((long long)b * a.in_bstride + (long long)vec * NC * N);
   const TO* __restrict__ oldp = has_old
       ? reinterpret_cast<const TO*>(a.old) +
-            2 * ((long long)b * a.old_bstride + (long long)vec * 6 * N + (long long)X * N)
+            2 * ((long long)b * a.old_bstride + (long long)vec * NC * N + (long long)X * N)
       : nullptr;
   TW* __restrict__ outp = reinterpret_cast<TW*>(a.out) +
-                          2 * ((long long)b * a.out_bstride + (long long)vec * 6 * N +
+                          2 * ((long long)b * a.out_bstride + (long long)vec * NC * N +
                                (long long)X * N);
   const T* __restrict__ D = a.D + (long long)b * a.D_bstride;
   const StencilConsts<T> k = a.k;
@@ -280,22 +284,22 @@ stencil_kernel(KArgs<T> a) {
 
   // next plane: loads issued before the current plane is computed, written to
   // the other LDS buffer after it (the wave's own arithmetic hides the latency)
-  auto fetch = [&](int z, cx<T> (&v)[NS][6]) {
+  auto fetch = [&](int z, cx<T> (&v)[NS][NC]) {
     const unsigned zo = (unsigned)z * nxy;
 #pragma unroll
     for (int s = 0; s < NS; ++s) {
       if (NS * NT > SLOTS && !sin_[s]) continue;
 #pragma unroll
-      for (int c = 0; c < 6; ++c) v[s][c] = ld(in + 2 * (size_t)((unsigned)c * N + zo + soff[s]));
+      for (int c = 0; c < NC; ++c) v[s][c] = ld(in + 2 * (size_t)((unsigned)c * N + zo + soff[s]));
     }
   };
-  auto commit = [&](cx<T> (&v)[NS][6], auto BUF) {
+  auto commit = [&](cx<T> (&v)[NS][NC], auto BUF) {
     cx<T>* dst = bufp(BUF);
 #pragma unroll
     for (int s = 0; s < NS; ++s) {
       if (NS * NT > SLOTS && !sin_[s]) continue;
 #pragma unroll
-      for (int c = 0; c < 6; ++c) {
+      for (int c = 0; c < NC; ++c) {
         cx<T> x = v[s][c];
         if (wmask[s] && !sval[s]) x = mk<T>(0, 0);
         dst[c * PLANE + sidx[s]] = x;
@@ -304,12 +308,12 @@ stencil_kernel(KArgs<T> a) {
   };
 
   // ---- DMA staging: row loads spread over the workgroup's waves
-  constexpr int NW = 2 * TY;
+  constexpr int NW = TY * (NC / 3);
   const int wave = __builtin_amdgcn_readfirstlane(ly + TY * sp);
   auto dma_plane = [&](int z, auto BUF) {
     cx<T>* dst = bufp(BUF);
     const unsigned zo = (unsigned)z * nxy;
-    for (int j = wave; j < 6 * ROWS; j += NW) {
+    for (int j = wave; j < NC * ROWS; j += NW) {
       const int c = j / ROWS, r = j % ROWS;
       const int y = ty0 + r - 1;
       if (y < 0 || y >= ny) continue;
@@ -322,8 +326,8 @@ stencil_kernel(KArgs<T> a) {
   };
   // x-halo columns: element e of 12 ROWS per plane (side, component, row)
   const int he = tid;
-  const bool hown = he < 12 * ROWS;
-  const int hside = he & 1, hc = (he >> 1) % 6, hr = (he >> 1) / 6;
+  const bool hown = he < 2 * NC * ROWS;
+  const int hside = he & 1, hc = (he >> 1) % NC, hr = (he >> 1) / NC;
   const int hx = hside ? tx0 + 64 : tx0 - 1, hy = ty0 + hr - 1;
   const bool hval = hown && hx >= 0 && hx < nx && hy >= 0 && hy < ny;
   const unsigned hoff = hval ? (unsigned)(hc * N + hy * nx + hx) : 0u;
@@ -413,7 +417,7 @@ stencil_kernel(KArgs<T> a) {
     T nd[ND];
     load_d(z + 1 < nz ? z + 1 : z, nd);
     if (z - 1 >= o0) load_old(z - 1);
-    cx<T> nxt[DMA ? 1 : NS][6];
+    cx<T> nxt[DMA ? 1 : NS][NC];
     cx<T> hv = mk<T>(0, 0);
     const bool more = z + 1 <= p1;
     if constexpr (!DMA) {
@@ -553,15 +557,17 @@ stencil_kernel(KArgs<T> a) {
       //            dn <- -d3 (-v_Z, -i v_Z, v_X + i v_Y) + (bx + i by) v   (v = up)
       // i.e. r_X += s d3 v_Z, r_Y += d3 i v_Z, r_Z += -d3 i v_Y - s d3 v_X with
       // s = -1 (up), +1 (down)
-      const cx<T> f0 = at(F, 0, 0), f1 = at(F + 1, 0, 0), f2 = at(F + 2, 0, 0);
-      r0v = fma_s(r0v, sd3, f2);
-      r1v = fma_s(r1v, k.d3, mul_i(f2));
-      r2v = fma_s(fma_s(r2v, -k.d3, mul_i(f1)), -sd3, f0);
-      if constexpr (PH != 0) {
-        const cx<T> bz = mk<T>(k.bx, sby);
-        r0v = add(r0v, mul(bz, f0));
-        r1v = add(r1v, mul(bz, f1));
-        r2v = add(r2v, mul(bz, f2));
+      if constexpr (NC == 6) {   // spin-free vectors have no other spin to couple to
+        const cx<T> f0 = at(F, 0, 0), f1 = at(F + 1, 0, 0), f2 = at(F + 2, 0, 0);
+        r0v = fma_s(r0v, sd3, f2);
+        r1v = fma_s(r1v, k.d3, mul_i(f2));
+        r2v = fma_s(fma_s(r2v, -k.d3, mul_i(f1)), -sd3, f0);
+        if constexpr (PH != 0) {
+          const cx<T> bz = mk<T>(k.bx, sby);
+          r0v = add(r0v, mul(bz, f0));
+          r1v = add(r1v, mul(bz, f1));
+          r2v = add(r2v, mul(bz, f2));
+        }
       }
       acc1[0] = add(acc1[0], r0v);
       acc1[1] = add(acc1[1], r1v);
@@ -598,7 +604,7 @@ stencil_kernel(KArgs<T> a) {
 
   if constexpr (DMA) {
     // rows outside the grid are never loaded: zero both buffers once
-    for (int i = tid; i < 6 * PLANE; i += NT) {
+    for (int i = tid; i < NC * PLANE; i += NT) {
       lds0[i] = mk<T>(0, 0);
       lds1[i] = mk<T>(0, 0);
     }
@@ -606,7 +612,7 @@ stencil_kernel(KArgs<T> a) {
     halo_commit(halo_load(p0), IC<0>{});
     dma_plane(p0, IC<0>{});
   } else {
-    cx<T> first[NS][6];
+    cx<T> first[NS][NC];
     fetch(p0, first);
     commit(first, IC<0>{});
   }
@@ -643,7 +649,7 @@ int resident_workgroups(K kernel, int threads) {
   return r;
 }
 
-template <typename T, typename TO, typename TW, int PH, bool STR>
+template <typename T, typename TO, typename TW, int PH, bool STR, int NC = 6>
 hipError_t launch_t(const StencilLaunch& L, const StencilConsts<double>& c, hipStream_t s) {
   KArgs<T> a;
   a.in = reinterpret_cast<const T*>(L.in);
@@ -686,19 +692,20 @@ hipError_t launch_t(const StencilLaunch& L, const StencilConsts<double>& c, hipS
                   : (L.zsplit == 1 ? 3 * resident_workgroups(kernel, (int)(block.x * block.y * block.z)) : 0);
     kernel<<<grid, block, 0, s>>>(a);
   };
+  constexpr unsigned NSP = NC / 3;   // spin waves per row
   if (L.dma && L.nx % 64 == 0) {
     switch (ty) {
-      case 1: go(stencil_kernel<T, TO, TW, PH, STR, 1, true>, dim3(64, 1, 2)); break;
-      case 2: go(stencil_kernel<T, TO, TW, PH, STR, 2, true>, dim3(64, 2, 2)); break;
-      case 4: go(stencil_kernel<T, TO, TW, PH, STR, 4, true>, dim3(64, 4, 2)); break;
+      case 1: go(stencil_kernel<T, TO, TW, PH, STR, 1, true, NC>, dim3(64, 1, NSP)); break;
+      case 2: go(stencil_kernel<T, TO, TW, PH, STR, 2, true, NC>, dim3(64, 2, NSP)); break;
+      case 4: go(stencil_kernel<T, TO, TW, PH, STR, 4, true, NC>, dim3(64, 4, NSP)); break;
       default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
   }
   switch (ty) {
-    case 1: go(stencil_kernel<T, TO, TW, PH, STR, 1, false>, dim3(64, 1, 2)); break;
-    case 2: go(stencil_kernel<T, TO, TW, PH, STR, 2, false>, dim3(64, 2, 2)); break;
-    case 4: go(stencil_kernel<T, TO, TW, PH, STR, 4, false>, dim3(64, 4, 2)); break;
+    case 1: go(stencil_kernel<T, TO, TW, PH, STR, 1, false, NC>, dim3(64, 1, NSP)); break;
+    case 2: go(stencil_kernel<T, TO, TW, PH, STR, 2, false, NC>, dim3(64, 2, NSP)); break;
+    case 4: go(stencil_kernel<T, TO, TW, PH, STR, 4, false, NC>, dim3(64, 4, NSP)); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -708,6 +715,11 @@ template <typename T, typename TO, typename TW>
 hipError_t launch_ph(const StencilLaunch& L, const StencilConsts<double>& c, hipStream_t s) {
   // 0: no field; 1: Bz = 0 (all link phases uniform over a z-plane); 2: general
   const int ph = L.wtab == nullptr ? 0 : (L.phase_general ? 2 : 1);
+  if (L.ncomp == 3) {   // spin-free orbital vectors: zero field only
+    if (ph != 0) return hipErrorInvalidValue;
+    return L.strain ? launch_t<T, TO, TW, 0, true, 3>(L, c, s)
+                    : launch_t<T, TO, TW, 0, false, 3>(L, c, s);
+  }
   if (ph == 2)
     return L.strain ? launch_t<T, TO, TW, 2, true>(L, c, s) : launch_t<T, TO, TW, 2, false>(L, c, s);
   if (ph == 1)

@@ -124,3 +124,20 @@ def test_spin_free_full_size_properties():
     # residuals (<= 1e-8 eV): pairs agree to that order
     assert np.abs(ev[0::2] - ev[1::2]).max() <= 1e-8
     assert abs(np.trace(H).real - (2 * E.sum() + 2 * 16 * d / 3)) <= 1e-9
+
+
+@pytest.mark.parametrize("shape,precision", [("1,1,1", "fp64"), ("2,2,1", "fp64"),
+                                             ("4,1,0", "fp64"), ("2,1,1,2", "fp64"),
+                                             ("2,1,1", "mixed"), ("1,4,0", "mixed")])
+def test_spin_free_stencil_launch_shapes(shape, precision, monkeypatch):
+    """Every launch shape of the spin-free (three-component) stencil -- tile height,
+    vector groups, row DMA, z split -- gives the oracle's orbital energies."""
+    import paper_2607_08447_amd as hkp
+    monkeypatch.setenv("HKP_STENCIL", shape)
+    w, g = _case("dqd_small")
+    tol, bar = (1e-9, 1e-8) if precision == "fp64" else (1e-6, 1e-6)
+    r = hkp.solve(_t(w.V), w.h, 8, strain=_t(w.strain), nb=16, tol=tol, precision=precision,
+                  spin_free=True, return_psi=False)
+    assert r.status == 0
+    E_ref, _ = lowest_arpack(h0_orbital(g, SI_MATERIAL, V=w.V, strain=w.strain), 8, tol=1e-14)
+    assert np.abs(r.E.cpu().numpy() - E_ref).max() <= bar
