@@ -301,6 +301,45 @@ def poisson_measure(torch, hkp, d=None, density=None, iters=1024):
             "peak_gbps": 8000.0, "frac": round(gbps / 8000.0, 4), "iterations_timed": it}
 
 
+def spin_free_measure(torch, hkp, workload):
+    """Spin-free single-particle basis on the 256 x 48 x 48 double dot at B = 0
+    (strain on): the 16 lowest orbitals of H_0 (three-component vectors) against
+    the 32 lowest spinor states of the full Hamiltonian at B = 0 (the same number
+    of states once spin is counted), both FP64 to residual 1e-8 eV, and the
+    spin-orbit matrix of the 16 orbitals (32 x 32)."""
+    w = workload(WORKLOAD)
+    V = torch.from_numpy(w.V).cuda()
+    S = torch.from_numpy(w.strain).cuda()
+    kw = dict(strain=S, tol=1e-8, return_psi=False)
+    for nb in (24, 40):   # stencil launch shapes for both block sizes (B = 0, strain)
+        hkp.autotune(w.shape, w.h, nb, "fp64", with_field=False)
+    hkp.solve(V, w.h, 16, nb=24, spin_free=True, **kw)   # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    r = hkp.solve(V, w.h, 16, nb=24, spin_free=True, strain=S, tol=1e-8)
+    torch.cuda.synchronize()
+    t_sf = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    full = hkp.solve(V, w.h, 32, nb=40, **kw)
+    torch.cuda.synchronize()
+    t_full = time.perf_counter() - t0
+    H = hkp.soi_matrix(r.psi, E=r.E)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(10):
+        H = hkp.soi_matrix(r.psi, E=r.E)
+    torch.cuda.synchronize()
+    t_soi = (time.perf_counter() - t0) / 10
+    ev = torch.linalg.eigvalsh(H).cpu().numpy()
+    return {"workload": WORKLOAD + " at B = 0", "orbitals": 16,
+            "s_spin_free_fp64": round(t_sf, 4), "iters_spin_free": r.stats["iters"],
+            "s_full_32_states_fp64": round(t_full, 4), "iters_full": full.stats["iters"],
+            "speedup": round(t_full / t_sf, 3), "s_soi_matrix_32x32": round(t_soi, 6),
+            "status": [r.status, full.status],
+            "lowest_single_particle_eV": [float(v) for v in ev[:4]],
+            "lowest_full_eV": [float(v) for v in full.E[:4].cpu().numpy()]}
+
+
 def cpu_baseline(w, seconds=15.0):
     """The CPU oracle's H.X (scipy CSR matvec on the assembled Hamiltonian) on a
     slab of the same workload, in the same algorithmic-bytes unit."""
@@ -350,6 +389,8 @@ def main():
                          "prints its JSON object")
     ap.add_argument("--poisson-only", action="store_true",
                     help="run only the Poisson CG rate measurement (profiled runs)")
+    ap.add_argument("--spin-free-only", action="store_true",
+                    help="run only the spin-free basis measurement (profiled runs)")
     args = ap.parse_args()
     if args.traffic_from:
         if not args.stencil or not args.nb:
@@ -381,6 +422,9 @@ def main():
         return
     if args.poisson_only:
         print(json.dumps(poisson_measure(torch, hkp)), flush=True)
+        return
+    if args.spin_free_only:
+        print(json.dumps(spin_free_measure(torch, hkp, workload)), flush=True)
         return
 
     w = workload(WORKLOAD)
@@ -460,6 +504,9 @@ def main():
         log("adjoint ...")
         extra["adjoint"] = adjoint_measure(torch, hkp, workload)
         log(f"adjoint {extra['adjoint']}")
+        log("spin-free basis ...")
+        extra["spin_free"] = spin_free_measure(torch, hkp, workload)
+        log(f"spin-free {extra['spin_free']}")
         log("self-consistent Schroedinger-Poisson loop ...")
         extra["sp"] = sp_measure(torch, hkp)
         log(f"sp {extra['sp']}")
