@@ -41,3 +41,6 @@ from .poisson import (  # noqa: F401
     hole_density, embed, restrict, sp_loop,
 )
 from .spinfree import h0_orbital, soi_matrix, single_particle  # noqa: F401
+from .ci import (  # noqa: F401
+    pair_densities, pair_potentials, coulomb_integrals, determinants, ci_hamiltonian, exchange,
+)
