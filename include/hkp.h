@@ -321,6 +321,43 @@ int hkp_soi_matrix(const hkp_grid* grid, int32_t M, const void* phi, const doubl
                    double delta_so_eV, void* out, void* workspace, size_t ws_bytes,
                    void* hip_stream);
 
+/* ---- Two-hole configuration interaction (Sec. II.D, Eq. Phi, Fig. 2d-f) ----
+ * Determinants |u v>, u < v (lexicographic), of the 2M spin-orbitals u = 2i + s
+ * of M spin-free orbitals.  Pair densities rho_ik = sum_b conj(phi_i,b) phi_k,b / h^3
+ * get their potentials V_ik from the Poisson problem of hkp_poisson with every
+ * electrode grounded (all M(M+1)/2 pairs solved together, real and imaginary
+ * parts as separate right-hand sides); (ik|jl) = sum_r h^3 rho_ik V_jl (eV);
+ * <uv|wx> = delta(s_u, s_w) delta(s_v, s_x) (i_u i_w | i_v i_x); the matrix is
+ * <uv|H|wx> = h_uw d_vx + h_vx d_uw - h_ux d_vw - h_vw d_ux + <uv|wx> - <uv|xw>
+ * with h = diag(E) (x) 1 + the spin-orbit matrix (hkp_soi_matrix), and
+ * J = mean(E_1, E_2, E_3) - E_0 of its ascending spectrum. */
+typedef struct {
+  int64_t cg_iters;        /* CG iterations of the batched pair-potential solve (max over systems) */
+  double cg_relres;        /* largest final |r| / |b| */
+  int32_t poisson_solves;  /* real right-hand sides solved together, M (M + 1) */
+  int32_t determinants;    /* K = M (2M - 1) */
+  double t_poisson, seconds;
+} hkp_ci_stats;
+
+/* Workspace of hkp_ci_solve. */
+size_t hkp_ci_workspace_bytes(const hkp_grid* grid, int32_t M, const hkp_pgrid* pgrid);
+
+/*   phi       device complex double [M][nx][ny][nz][3] orthonormal spin-free orbitals,
+ *             1 <= M <= 5 (K <= 45)
+ *   E_eV      device double [M] their energies
+ *   pgrid, eps_r, dirichlet  the Poisson box as in hkp_poisson / hkp_sp_solve
+ *   eig_eV    device double [K], ascending
+ *   vecs, H_ci  device complex double [K][K] or NULL: eigenvectors (column k =
+ *             eigenvector k, row-major) and the matrix itself
+ *   coulomb   device complex double [M][M][M][M] (ik|jl), or NULL
+ *   J_eV      device double [1] or NULL (written when K >= 4)
+ * Returns HKP_OK, HKP_W_NOT_CONVERGED (a pair potential missed cg_tol) or an error. */
+int hkp_ci_solve(const hkp_grid* grid, int32_t M, const void* phi, const double* E_eV,
+                 double delta_so_eV, const hkp_pgrid* pgrid, const double* eps_r,
+                 const uint8_t* dirichlet, double cg_tol, int32_t cg_max_iter, double* eig_eV,
+                 void* vecs, void* H_ci, void* coulomb, double* J_eV, void* workspace,
+                 size_t ws_bytes, void* hip_stream, hkp_ci_stats* stats);
+
 /* Workspace of hkp_poisson for this box. */
 size_t hkp_poisson_workspace_bytes(const hkp_pgrid* pgrid);
 

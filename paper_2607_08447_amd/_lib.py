@@ -89,6 +89,15 @@ class hkp_sp_stats(C.Structure):
         return {name: getattr(self, name) for name, _ in self._fields_}
 
 
+class hkp_ci_stats(C.Structure):
+    _fields_ = [("cg_iters", C.c_int64), ("cg_relres", C.c_double),
+                ("poisson_solves", C.c_int32), ("determinants", C.c_int32),
+                ("t_poisson", C.c_double), ("seconds", C.c_double)]
+
+    def as_dict(self):
+        return {name: getattr(self, name) for name, _ in self._fields_}
+
+
 _P = C.c_void_p
 _D = C.POINTER(C.c_double)
 
@@ -121,6 +130,11 @@ SIGNATURES = {
     "hkp_soi_workspace_bytes": (C.c_size_t, [C.POINTER(hkp_grid), C.c_int32]),
     "hkp_soi_matrix": (C.c_int, [C.POINTER(hkp_grid), C.c_int32, _P, _P, C.c_double, _P, _P,
                                  C.c_size_t, _P]),
+    "hkp_ci_workspace_bytes": (C.c_size_t, [C.POINTER(hkp_grid), C.c_int32,
+                                            C.POINTER(hkp_pgrid)]),
+    "hkp_ci_solve": (C.c_int, [C.POINTER(hkp_grid), C.c_int32, _P, _P, C.c_double,
+                               C.POINTER(hkp_pgrid), _P, _P, C.c_double, C.c_int32, _P, _P, _P,
+                               _P, _P, _P, C.c_size_t, _P, C.POINTER(hkp_ci_stats)]),
     "hkp_poisson_workspace_bytes": (C.c_size_t, [C.POINTER(hkp_pgrid)]),
     "hkp_poisson": (C.c_int, [C.POINTER(hkp_pgrid), C.c_double, _P, _P, _P, _P, _P, C.c_double,
                               C.c_int32, _P, C.c_size_t, _P, C.POINTER(C.c_int32), _D]),

@@ -344,6 +344,54 @@ def soi_matrix(phi, delta_so=None, E=None, material=None):
     return out
 
 
+@dataclass
+class CIResult:
+    E: torch.Tensor          # [K] two-hole energies, eV, ascending
+    J: float                 # mean(E_1..E_3) - E_0, eV (nan if K < 4)
+    vectors: torch.Tensor    # [K, K] complex (column k: state k) or None
+    H: torch.Tensor          # [K, K] complex determinant matrix or None
+    coulomb: torch.Tensor    # [M, M, M, M] complex (ik|jl) or None
+    stats: dict
+    status: int
+
+
+def ci_solve(phi, E, h, pshape, offset, eps_r, dirichlet, delta_so=None, material=None,
+             cg_tol=1e-12, cg_max_iter=20000, return_vectors=False, return_matrix=False,
+             return_coulomb=False):
+    """Two-hole configuration interaction in the determinants of the spin-orbitals
+    of M spin-free orbitals phi [M, nx, ny, nz, 3] (energies E [M]); the Coulomb
+    interaction comes from the device's Poisson problem (box `pshape`, the grid at
+    `offset`) with every electrode grounded."""
+    phi = _dev(phi, torch.complex128)
+    if phi.dim() != 5 or phi.shape[-1] != 3:
+        raise ValueError("phi must be [M, nx, ny, nz, 3]")
+    M = phi.shape[0]
+    E = _dev(E, torch.float64)
+    eps_r = _dev(eps_r, torch.float64)
+    dirichlet = _dev(dirichlet, torch.uint8)
+    if delta_so is None:
+        delta_so = _material(material).delta_so_eV
+    g = _grid(tuple(phi.shape[1:4]), h)
+    pg = _pgrid(pshape, offset)
+    need = L.lib.hkp_ci_workspace_bytes(C.byref(g), M, C.byref(pg))
+    if need == 0:
+        raise L.HkpError(L.HKP_E_ARG, L.lib.hkp_last_error().decode())
+    ws = torch.empty(need, dtype=torch.uint8, device="cuda")
+    K = M * (2 * M - 1)
+    ev = torch.empty(K, dtype=torch.float64, device="cuda")
+    J = torch.full((1,), float("nan"), dtype=torch.float64, device="cuda")
+    vec = torch.empty((K, K), dtype=torch.complex128, device="cuda") if return_vectors else None
+    Hm = torch.empty((K, K), dtype=torch.complex128, device="cuda") if return_matrix else None
+    Cc = torch.empty((M,) * 4, dtype=torch.complex128, device="cuda") if return_coulomb else None
+    st = L.hkp_ci_stats()
+    code = L.lib.hkp_ci_solve(C.byref(g), M, _ptr(phi), _ptr(E), float(delta_so), C.byref(pg),
+                              _ptr(eps_r), _ptr(dirichlet), float(cg_tol), int(cg_max_iter),
+                              _ptr(ev), _ptr(vec), _ptr(Hm), _ptr(Cc), _ptr(J), _ptr(ws),
+                              C.c_size_t(need), _stream(), C.byref(st))
+    L.check(code)
+    return CIResult(ev, float(J[0]), vec, Hm, Cc, st.as_dict(), code)
+
+
 # ---------------------------------------------------------------------------
 # self-consistent Schroedinger-Poisson loop
 # ---------------------------------------------------------------------------

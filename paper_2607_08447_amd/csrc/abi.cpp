@@ -503,6 +503,55 @@ int hkp_soi_matrix(const hkp_grid* grid, int32_t M, const void* phi, const doubl
   });
 }
 
+size_t hkp_ci_workspace_bytes(const hkp_grid* grid, int32_t M, const hkp_pgrid* pgrid) {
+  if (check_grid(grid) != HKP_OK || check_pgrid(pgrid, grid) != HKP_OK) return 0;
+  if (M < 1 || M > 5) {
+    set_error("hkp_ci_solve: 1 <= M <= 5");
+    return 0;
+  }
+  return ci_bytes(*grid, M, *pgrid);
+}
+
+int hkp_ci_solve(const hkp_grid* grid, int32_t M, const void* phi, const double* E_eV,
+                 double delta_so_eV, const hkp_pgrid* pgrid, const double* eps_r,
+                 const uint8_t* dirichlet, double cg_tol, int32_t cg_max_iter, double* eig_eV,
+                 void* vecs, void* H_ci, void* coulomb, double* J_eV, void* workspace,
+                 size_t ws_bytes, void* hip_stream, hkp_ci_stats* stats) {
+  HKP_TRY(check_grid(grid));
+  HKP_TRY(check_pgrid(pgrid, grid));
+  if (M < 1 || M > 5 || !phi || !E_eV || !eps_r || !dirichlet || !eig_eV || !workspace ||
+      !std::isfinite(delta_so_eV) || !finite_pos(cg_tol) || cg_max_iter < 1) {
+    set_error("hkp_ci_solve: 1 <= M <= 5, non-NULL phi, E, eps_r, dirichlet, eig, workspace, "
+              "finite delta_so, cg_tol > 0, cg_max_iter >= 1");
+    return HKP_E_ARG;
+  }
+  const size_t need = ci_bytes(*grid, M, *pgrid);
+  if (ws_bytes < need) {
+    set_error("workspace too small: need " + std::to_string(need) + " bytes");
+    return HKP_E_WORKSPACE;
+  }
+  HKP_TRY(check_device());
+  CIArgs a{};
+  a.grid = *grid;
+  a.M = M;
+  a.phi = phi;
+  a.E = E_eV;
+  a.delta_so = delta_so_eV;
+  a.pg = *pgrid;
+  a.eps = eps_r;
+  a.dir = dirichlet;
+  a.cg_tol = cg_tol;
+  a.cg_max_iter = cg_max_iter;
+  a.eig = eig_eV;
+  a.vecs = vecs;
+  a.H = H_ci;
+  a.coulomb = coulomb;
+  a.J = J_eV;
+  a.workspace = workspace;
+  a.stream = hip_stream;
+  return guarded([&]() { return run_ci(a, stats); });
+}
+
 size_t hkp_poisson_workspace_bytes(const hkp_pgrid* pgrid) {
   if (check_pgrid(pgrid, nullptr) != HKP_OK) return 0;
   return poisson_bytes(*pgrid);

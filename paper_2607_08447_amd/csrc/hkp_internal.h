@@ -233,25 +233,28 @@ struct CGState {
 };
 
 int sp_blocks(long long n);
-size_t sp_partial_doubles();   // partial-sum scratch every SP launcher needs
+size_t sp_partial_doubles(int nrhs = 1);   // partial-sum scratch of the SP launchers
 // link coefficients cx, cy, cz (+x, +y, +z links), D^-1 (0 on electrodes) and
 // the number of electrode nodes (*n_dir, device)
 hipError_t launch_pcoef(const PGeom& g, double h, const double* eps, const uint8_t* dir,
                         double* cx, double* cy, double* cz, double* dinv, double* partial,
                         double* n_dir, hipStream_t s);
-// phi (in: guess) gets its electrode values; r = b - L phi, z = D^-1 r, p = 0, and
-// the CG state (stop when |r| <= tol |b|)
+// phi (in: guess) gets its electrode values (phi_fixed null: grounded); r = b - L phi,
+// z = D^-1 r, p = 0, and the CG state (stop when |r| <= tol |b|).  nrhs systems at
+// once: rho, phi, r, z, p (and p_new, q below) hold nrhs vectors NP apart, st nrhs
+// states, partial sp_partial_doubles(nrhs)
 hipError_t launch_cg_init(const PGeom& g, const double* cx, const double* cy, const double* cz,
                           const double* dinv, const uint8_t* dir, const double* phi_fixed,
                           const double* rho, double scale, double* phi, double* r, double* z,
-                          double* p, double* partial, double tol, CGState* st, hipStream_t s);
+                          double* p, double* partial, double tol, CGState* st, hipStream_t s,
+                          int nrhs = 1);
 // one CG iteration (no-op once st->done): p_new = z + beta p_old, q = L p_new,
 // phi += alpha p_new, r -= alpha q, z = D^-1 r
 hipError_t launch_cg_iter(const PGeom& g, const double* cx, const double* cy, const double* cz,
                           const double* dinv, const uint8_t* dir, double* z,
                           const double* p_old, double* p_new, double* q, double* phi,
                           double* r, double* partial, int max_iter, CGState* st,
-                          hipStream_t s);
+                          hipStream_t s, int nrhs = 1);
 hipError_t launch_occupancy(int nev, const double* E, double n_holes, double kT, double* f,
                             double* mu, hipStream_t s);
 // rho (P grid, may be null) = rho_fixed (may be null) + hole density embedded at
@@ -262,6 +265,20 @@ hipError_t launch_rho(const PGeom& g, int ox, int oy, int oz, int nx, int ny, in
                       const double* rho_fixed, double* rho, double* density, hipStream_t s);
 hipError_t launch_extract(int nx, int ny, int nz, const PGeom& g, int ox, int oy, int oz,
                           const double* V_off, const double* phi, double* V, hipStream_t s);
+// configuration interaction: right-hand sides [2P][NP] of the P = M(M+1)/2 pair
+// densities (real, imaginary parts), the pair potentials at the Schroedinger grid
+// as complex [P][NS], pair products [M*M][NS], the determinant matrix [K][K] and
+// the full tensor (ik|jl) [M][M][M][M] (complex)
+hipError_t launch_pair_rhs(const PGeom& g, int ox, int oy, int oz, int nx, int ny, int nz, int M,
+                           const void* phi, double h, double* rhs, hipStream_t s);
+hipError_t launch_pair_potential_gather(const PGeom& g, int ox, int oy, int oz, int nx, int ny,
+                                        int nz, int P, const double* V, double* Vc,
+                                        hipStream_t s);
+hipError_t launch_pair_product(long long NS, int M, const void* phi, double* A, hipStream_t s);
+hipError_t launch_ci_assemble(int M, const double* hsp, const double* Cs, double* H,
+                              hipStream_t s);
+hipError_t launch_coulomb_expand(int M, const double* Cs, double* C, hipStream_t s);
+hipError_t launch_exchange(const double* E, double* J, hipStream_t s);
 // F = phi_out - phi_in, *delta = max |F| (device)
 hipError_t launch_residual_max(const PGeom& g, const double* phi_in, const double* phi_out,
                                double* F, double* partial, double* delta, hipStream_t s);

@@ -130,4 +130,27 @@ size_t sp_bytes(const hkp_grid& g, const hkp_opts& o, const hkp_pgrid& pg,
                 const hkp_sp_opts& sp);
 int run_sp(const SPArgs& a, hkp_sp_stats* stats);
 
+// ---- two-hole configuration interaction
+struct CIArgs {
+  hkp_grid grid;
+  int M;
+  const void* phi;
+  const double* E;
+  double delta_so;
+  hkp_pgrid pg;
+  const double* eps;
+  const uint8_t* dir;
+  double cg_tol;
+  int cg_max_iter;
+  double* eig;
+  void* vecs;
+  void* H;
+  void* coulomb;
+  double* J;
+  void* workspace;
+  void* stream;
+};
+size_t ci_bytes(const hkp_grid& g, int M, const hkp_pgrid& pg);
+int run_ci(const CIArgs& a, hkp_ci_stats* stats);
+
 }  // namespace hkp

@@ -141,10 +141,14 @@ __device__ __forceinline__ double link_sum(unsigned i, int x, int y, int z, cons
   return s;
 }
 
+// Every CG kernel solves blockIdx.y = 0 .. nrhs-1 systems at once (the same
+// operator, right-hand sides and vectors vs = NP apart, a CGState each); the
+// single-system solves are nrhs = 1.
+//
 // r = b - L phi on free nodes, b = (e/eps0) rho + electrode couplings; electrode
-// nodes take their fixed potential (free nodes read the fixed values of their
-// electrode neighbours, so nothing here reads what another thread writes);
-// z = D^-1 r; p = 0.  Partials: r.z, r.r, b.b.
+// nodes take their fixed potential (0 when phi_fixed is null: grounded; free
+// nodes read the fixed values of their electrode neighbours, so nothing here
+// reads what another thread writes); z = D^-1 r; p = 0.  Partials: r.z, r.r, b.b.
 __global__ void __launch_bounds__(kThreads)
 cg_init_kernel(unsigned NP, int px, int py, int pz, double ipy, double ipz,
                const double* __restrict__ cx,
@@ -153,12 +157,18 @@ cg_init_kernel(unsigned NP, int px, int py, int pz, double ipy, double ipz,
                const double* __restrict__ phi_fixed, const double* __restrict__ rho,
                double scale, double* phi, double* r, double* zv, double* p, double* partial) {
   const Geo g = geo(px, py, pz, ipy, ipz);
+  const long long vo = (long long)blockIdx.y * NP;
+  if (rho) rho += vo;
+  phi += vo;
+  r += vo;
+  zv += vo;
+  p += vo;
   double acc[3] = {0.0, 0.0, 0.0};
   for (unsigned i = xcd_remap(blockIdx.x, gridDim.x) * kThreads + threadIdx.x; i < NP;
        i += gridDim.x * kThreads) {
     p[i] = 0.0;
     if (dir[i]) {
-      phi[i] = phi_fixed[i];
+      phi[i] = phi_fixed ? phi_fixed[i] : 0.0;
       r[i] = 0.0;
       zv[i] = 0.0;
       continue;
@@ -168,11 +178,11 @@ cg_init_kernel(unsigned NP, int px, int py, int pz, double ipy, double ipz,
     const double ui = phi[i];
     const double f = rho ? scale * rho[i] : 0.0;   // no charge array: rho = 0
     const double lphi = link_sum(i, x, y, z, g, cx, cy, cz, ui, [&](unsigned j) {
-      return dir[j] ? phi_fixed[j] : phi[j];
+      return dir[j] ? (phi_fixed ? phi_fixed[j] : 0.0) : phi[j];
     });
     // electrode couplings of b: sum over electrode neighbours of c phi_fixed
     const double bdir = link_sum(i, x, y, z, g, cx, cy, cz, 0.0, [&](unsigned j) {
-      return dir[j] ? -phi_fixed[j] : 0.0;
+      return (dir[j] && phi_fixed) ? -phi_fixed[j] : 0.0;
     });
     const double ri = f - lphi;
     const double zi = dinv[i] * ri;
@@ -183,13 +193,14 @@ cg_init_kernel(unsigned NP, int px, int py, int pz, double ipy, double ipz,
     acc[1] += ri * ri;
     acc[2] += b * b;
   }
-  block_sums<3>(acc, partial + 3LL * blockIdx.x);
+  block_sums<3>(acc, partial + 3LL * ((long long)blockIdx.y * gridDim.x + blockIdx.x));
 }
 
 __global__ void __launch_bounds__(kRedThreads)
 cg_start_kernel(const double* partial, int nblk, double tol, CGState* st) {
   __shared__ double s[3];
-  reduce_partials<3>(partial, nblk, s);
+  st += blockIdx.y;
+  reduce_partials<3>(partial + 3LL * blockIdx.y * nblk, nblk, s);
   if (threadIdx.x == 0) {
     st->rz = s[0];
     st->rr = s[1];
@@ -212,9 +223,15 @@ cg_matvec_kernel(unsigned NP, int px, int py, int pz, double ipy, double ipz,
                  const uint8_t* __restrict__ dir, const double* __restrict__ zv,
                  const double* __restrict__ p_old, double* __restrict__ p_new,
                  double* __restrict__ q, double* partial, const CGState* st) {
+  st += blockIdx.y;
   if (st->done) return;
   const double beta = st->beta;
   const Geo g = geo(px, py, pz, ipy, ipz);
+  const long long vo = (long long)blockIdx.y * NP;
+  zv += vo;
+  p_old += vo;
+  p_new += vo;
+  q += vo;
   double acc[1] = {0.0};
   for (unsigned i = xcd_remap(blockIdx.x, gridDim.x) * kThreads + threadIdx.x; i < NP;
        i += gridDim.x * kThreads) {
@@ -234,14 +251,15 @@ cg_matvec_kernel(unsigned NP, int px, int py, int pz, double ipy, double ipz,
     q[i] = qi;
     acc[0] += pi * qi;
   }
-  block_sums<1>(acc, partial + blockIdx.x);
+  block_sums<1>(acc, partial + (long long)blockIdx.y * gridDim.x + blockIdx.x);
 }
 
 __global__ void __launch_bounds__(kRedThreads)
 cg_alpha_kernel(const double* partial, int nblk, CGState* st) {
+  st += blockIdx.y;
   if (st->done) return;
   __shared__ double s[1];
-  reduce_partials<1>(partial, nblk, s);
+  reduce_partials<1>(partial + (long long)blockIdx.y * nblk, nblk, s);
   if (threadIdx.x == 0) {
     if (!(s[0] > 0.0)) {   // the operator is not positive definite on this vector
       st->breakdown = 1;
@@ -257,8 +275,15 @@ __global__ void __launch_bounds__(kThreads)
 cg_update_kernel(long long NP, const double* __restrict__ dinv, const double* __restrict__ p,
                  const double* __restrict__ q, double* phi, double* r, double* zv,
                  double* partial, const CGState* st) {
+  st += blockIdx.y;
   if (st->done) return;
   const double alpha = st->alpha;
+  const long long vo = (long long)blockIdx.y * NP;
+  p += vo;
+  q += vo;
+  phi += vo;
+  r += vo;
+  zv += vo;
   double acc[2] = {0.0, 0.0};
   for (long long i = (long long)blockIdx.x * kThreads + threadIdx.x; i < NP;
        i += (long long)gridDim.x * kThreads) {
@@ -271,14 +296,15 @@ cg_update_kernel(long long NP, const double* __restrict__ dinv, const double* __
     acc[0] += ri * zi;
     acc[1] += ri * ri;
   }
-  block_sums<2>(acc, partial + 2LL * blockIdx.x);
+  block_sums<2>(acc, partial + 2LL * ((long long)blockIdx.y * gridDim.x + blockIdx.x));
 }
 
 __global__ void __launch_bounds__(kRedThreads)
 cg_beta_kernel(const double* partial, int nblk, int max_iter, CGState* st) {
+  st += blockIdx.y;
   if (st->done) return;
   __shared__ double s[2];
-  reduce_partials<2>(partial, nblk, s);
+  reduce_partials<2>(partial + 2LL * blockIdx.y * nblk, nblk, s);
   if (threadIdx.x == 0) {
     st->beta = st->rz > 0.0 ? s[0] / st->rz : 0.0;
     st->rz = s[0];
@@ -515,6 +541,148 @@ anderson_update_kernel(long long NP, int slot, double a, const double* __restric
   }
 }
 
+// ---------------------------------------------------------------------------
+// configuration interaction: pair densities, their potentials, integrals
+// ---------------------------------------------------------------------------
+// (j, l), j <= l, of pair q in lexicographic order over M orbitals
+__device__ __forceinline__ void pair_of(int q, int M, int& j, int& l) {
+  j = 0;
+  while (q >= M - j) {
+    q -= M - j;
+    ++j;
+  }
+  l = j + q;
+}
+
+// right-hand sides 2q (real part) and 2q+1 (imaginary part) of pair q:
+// rho_jl = sum_b conj(phi_j,b) phi_l,b / h^3 at the embedded nodes, 0 elsewhere
+__global__ void __launch_bounds__(kThreads)
+pair_rhs_kernel(unsigned NP, int px, int py, int pz, double ipy, double ipz, int ox, int oy,
+                int oz, int nx, int ny, int nz, int M, const double2* __restrict__ phi,
+                double inv_h3, double* rhs) {
+  const Geo g = geo(px, py, pz, ipy, ipz);
+  int j, l;
+  pair_of(blockIdx.y, M, j, l);
+  const long long NS = (long long)nx * ny * nz;
+  double* re = rhs + 2LL * blockIdx.y * NP;
+  double* im = re + NP;
+  for (unsigned i = blockIdx.x * kThreads + threadIdx.x; i < NP; i += gridDim.x * kThreads) {
+    int x, y, z;
+    coords(i, g, x, y, z);
+    x -= ox;
+    y -= oy;
+    z -= oz;
+    double a = 0.0, b = 0.0;
+    if (x >= 0 && x < nx && y >= 0 && y < ny && z >= 0 && z < nz) {
+      const long long s = ((long long)x * ny + y) * nz + z;
+      const double2* pj = phi + ((long long)j * NS + s) * 3;
+      const double2* pl = phi + ((long long)l * NS + s) * 3;
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {   // conj(pj) * pl
+        a += pj[c].x * pl[c].x + pj[c].y * pl[c].y;
+        b += pj[c].x * pl[c].y - pj[c].y * pl[c].x;
+      }
+    }
+    re[i] = a * inv_h3;
+    im[i] = b * inv_h3;
+  }
+}
+
+// Vc[q][s] = V[2q] + i V[2q+1] at the Schroedinger-grid nodes
+__global__ void __launch_bounds__(kThreads)
+pair_potential_gather_kernel(long long NS, int nx, int ny, int nz, long long NP, int py, int pz,
+                             int ox, int oy, int oz, const double* __restrict__ V, double2* Vc) {
+  const long long s = (long long)blockIdx.x * kThreads + threadIdx.x;
+  if (s >= NS) return;
+  const int q = blockIdx.y;
+  const int x = (int)(s / ((long long)ny * nz)), y = (int)((s / nz) % ny), z = (int)(s % nz);
+  const long long i = ((long long)(x + ox) * py + (y + oy)) * pz + (z + oz);
+  Vc[(long long)q * NS + s] = make_double2(V[2LL * q * NP + i], V[(2LL * q + 1) * NP + i]);
+}
+
+// A[(i, k)][s] = sum_b phi_i,b conj(phi_k,b) (so that conj(A) is the pair product)
+__global__ void __launch_bounds__(kThreads)
+pair_product_kernel(long long NS, int M, const double2* __restrict__ phi, double2* A) {
+  const long long s = (long long)blockIdx.x * kThreads + threadIdx.x;
+  if (s >= NS) return;
+  const int i = blockIdx.y / M, k = blockIdx.y % M;
+  const double2* pi = phi + ((long long)i * NS + s) * 3;
+  const double2* pk = phi + ((long long)k * NS + s) * 3;
+  double a = 0.0, b = 0.0;
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {   // pi * conj(pk)
+    a += pi[c].x * pk[c].x + pi[c].y * pk[c].y;
+    b += pi[c].y * pk[c].x - pi[c].x * pk[c].y;
+  }
+  A[(long long)blockIdx.y * NS + s] = make_double2(a, b);
+}
+
+// (ik|jl) from the stored pairs: Cs[(i, k)][q(j, l)] for j <= l, else
+// conj(Cs[(k, i)][q(l, j)]) (V_lj = conj(V_jl), conj(rho_ik) = rho_ki)
+__device__ double2 coulomb(const double2* Cs, int M, int P, int i, int k, int j, int l) {
+  if (j <= l) {
+    const int q = j * M - j * (j - 1) / 2 + (l - j);
+    return Cs[(long long)(i * M + k) * P + q];
+  }
+  const int q = l * M - l * (l - 1) / 2 + (j - l);
+  const double2 c = Cs[(long long)(k * M + i) * P + q];
+  return make_double2(c.x, -c.y);
+}
+
+// determinant a -> (u, v), u < v, lexicographic over n spin-orbitals
+__device__ void det_of(int a, int n, int& u, int& v) {
+  u = 0;
+  while (a >= n - 1 - u) {
+    a -= n - 1 - u;
+    ++u;
+  }
+  v = u + 1 + a;
+}
+
+__device__ double2 two_body(const double2* Cs, int M, int P, int u, int v, int w, int x) {
+  if ((u & 1) != (w & 1) || (v & 1) != (x & 1)) return make_double2(0.0, 0.0);
+  return coulomb(Cs, M, P, u >> 1, w >> 1, v >> 1, x >> 1);
+}
+
+// H[a][b] = h_uw d_vx + h_vx d_uw - h_ux d_vw - h_vw d_ux + <uv|wx> - <uv|xw>
+__global__ void __launch_bounds__(kThreads)
+ci_assemble_kernel(int M, int P, const double2* __restrict__ hsp, const double2* __restrict__ Cs,
+                   double2* H) {
+  const int n = 2 * M, K = n * (n - 1) / 2;
+  const int idx = blockIdx.x * kThreads + threadIdx.x;
+  if (idx >= K * K) return;
+  const int a = idx / K, b = idx % K;
+  int u, v, w, x;
+  det_of(a, n, u, v);
+  det_of(b, n, w, x);
+  double2 acc = make_double2(0.0, 0.0);
+  auto add = [&](double2 t, double sgn) {
+    acc.x += sgn * t.x;
+    acc.y += sgn * t.y;
+  };
+  if (v == x) add(hsp[u * n + w], 1.0);
+  if (u == w) add(hsp[v * n + x], 1.0);
+  if (v == w) add(hsp[u * n + x], -1.0);
+  if (u == x) add(hsp[v * n + w], -1.0);
+  add(two_body(Cs, M, P, u, v, w, x), 1.0);
+  add(two_body(Cs, M, P, u, v, x, w), -1.0);
+  H[idx] = acc;
+}
+
+// full tensor (ik|jl), [M][M][M][M] complex
+__global__ void __launch_bounds__(kThreads)
+coulomb_expand_kernel(int M, int P, const double2* __restrict__ Cs, double2* C) {
+  const int idx = blockIdx.x * kThreads + threadIdx.x;
+  if (idx >= M * M * M * M) return;
+  const int i = idx / (M * M * M), k = (idx / (M * M)) % M, j = (idx / M) % M, l = idx % M;
+  C[idx] = coulomb(Cs, M, P, i, k, j, l);
+}
+
+// J = mean(E_1, E_2, E_3) - E_0 of the ascending two-hole spectrum
+__global__ void exchange_kernel(const double* E, double* J) {
+  if (threadIdx.x == 0) J[0] = (E[1] + E[2] + E[3]) / 3.0 - E[0];
+}
+
 __global__ void __launch_bounds__(kRedThreads)
 sum1_kernel(const double* partial, int nblk, double* out) {
   __shared__ double s[1];
@@ -542,7 +710,7 @@ int sp_blocks(long long n) {
   return (int)(b < kRedBlocks ? (b > 0 ? b : 1) : kRedBlocks);
 }
 
-size_t sp_partial_doubles() { return (size_t)kRedBlocks * 9; }
+size_t sp_partial_doubles(int nrhs) { return (size_t)kRedBlocks * 9 * (nrhs > 0 ? nrhs : 1); }
 
 hipError_t launch_pcoef(const PGeom& g, double h, const double* eps, const uint8_t* dir,
                         double* cx, double* cy, double* cz, double* dinv, double* partial,
@@ -557,12 +725,13 @@ hipError_t launch_pcoef(const PGeom& g, double h, const double* eps, const uint8
 hipError_t launch_cg_init(const PGeom& g, const double* cx, const double* cy, const double* cz,
                           const double* dinv, const uint8_t* dir, const double* phi_fixed,
                           const double* rho, double scale, double* phi, double* r, double* z,
-                          double* p, double* partial, double tol, CGState* st, hipStream_t s) {
+                          double* p, double* partial, double tol, CGState* st, hipStream_t s,
+                          int nrhs) {
   const int nb = sp_blocks(g.NP);
-  cg_init_kernel<<<nb, kThreads, 0, s>>>((unsigned)g.NP, g.px, g.py, g.pz, 1.0 / g.py,
+  cg_init_kernel<<<dim3(nb, nrhs), kThreads, 0, s>>>((unsigned)g.NP, g.px, g.py, g.pz, 1.0 / g.py,
                                          1.0 / g.pz, cx, cy, cz, dinv, dir, phi_fixed, rho,
                                          scale, phi, r, z, p, partial);
-  cg_start_kernel<<<1, kRedThreads, 0, s>>>(partial, nb, tol, st);
+  cg_start_kernel<<<dim3(1, nrhs), kRedThreads, 0, s>>>(partial, nb, tol, st);
   return hipGetLastError();
 }
 
@@ -570,14 +739,15 @@ hipError_t launch_cg_iter(const PGeom& g, const double* cx, const double* cy, co
                           const double* dinv, const uint8_t* dir, double* z,
                           const double* p_old, double* p_new, double* q, double* phi,
                           double* r, double* partial, int max_iter, CGState* st,
-                          hipStream_t s) {
+                          hipStream_t s, int nrhs) {
   const int nb = sp_blocks(g.NP);
-  cg_matvec_kernel<<<nb, kThreads, 0, s>>>((unsigned)g.NP, g.px, g.py, g.pz, 1.0 / g.py,
+  cg_matvec_kernel<<<dim3(nb, nrhs), kThreads, 0, s>>>((unsigned)g.NP, g.px, g.py, g.pz, 1.0 / g.py,
                                            1.0 / g.pz, cx, cy, cz, dir, z, p_old, p_new, q,
                                            partial, st);
-  cg_alpha_kernel<<<1, kRedThreads, 0, s>>>(partial, nb, st);
-  cg_update_kernel<<<nb, kThreads, 0, s>>>(g.NP, dinv, p_new, q, phi, r, z, partial, st);
-  cg_beta_kernel<<<1, kRedThreads, 0, s>>>(partial, nb, max_iter, st);
+  cg_alpha_kernel<<<dim3(1, nrhs), kRedThreads, 0, s>>>(partial, nb, st);
+  cg_update_kernel<<<dim3(nb, nrhs), kThreads, 0, s>>>(g.NP, dinv, p_new, q, phi, r, z, partial,
+                                                       st);
+  cg_beta_kernel<<<dim3(1, nrhs), kRedThreads, 0, s>>>(partial, nb, max_iter, st);
   return hipGetLastError();
 }
 
@@ -630,6 +800,53 @@ hipError_t launch_anderson(const PGeom& g, int k, int m, int slot, double mixing
     case 7: anderson_k<7>(g, nb, m, slot, mixing, x, F, histX, histF, G, dots, gamma, partial, s); break;
     default: anderson_k<8>(g, nb, m, slot, mixing, x, F, histX, histF, G, dots, gamma, partial, s); break;
   }
+  return hipGetLastError();
+}
+
+hipError_t launch_pair_rhs(const PGeom& g, int ox, int oy, int oz, int nx, int ny, int nz, int M,
+                           const void* phi, double h, double* rhs, hipStream_t s) {
+  const int P = M * (M + 1) / 2;
+  pair_rhs_kernel<<<dim3(sp_blocks(g.NP), P), kThreads, 0, s>>>(
+      (unsigned)g.NP, g.px, g.py, g.pz, 1.0 / g.py, 1.0 / g.pz, ox, oy, oz, nx, ny, nz, M,
+      static_cast<const double2*>(phi), 1.0 / (h * h * h), rhs);
+  return hipGetLastError();
+}
+
+hipError_t launch_pair_potential_gather(const PGeom& g, int ox, int oy, int oz, int nx, int ny,
+                                        int nz, int P, const double* V, double* Vc,
+                                        hipStream_t s) {
+  const long long NS = (long long)nx * ny * nz;
+  pair_potential_gather_kernel<<<dim3((unsigned)((NS + kThreads - 1) / kThreads), P), kThreads, 0,
+                                 s>>>(NS, nx, ny, nz, g.NP, g.py, g.pz, ox, oy, oz, V,
+                                      reinterpret_cast<double2*>(Vc));
+  return hipGetLastError();
+}
+
+hipError_t launch_pair_product(long long NS, int M, const void* phi, double* A, hipStream_t s) {
+  pair_product_kernel<<<dim3((unsigned)((NS + kThreads - 1) / kThreads), M * M), kThreads, 0,
+                        s>>>(NS, M, static_cast<const double2*>(phi),
+                             reinterpret_cast<double2*>(A));
+  return hipGetLastError();
+}
+
+hipError_t launch_ci_assemble(int M, const double* hsp, const double* Cs, double* H,
+                              hipStream_t s) {
+  const int n = 2 * M, K = n * (n - 1) / 2, P = M * (M + 1) / 2;
+  ci_assemble_kernel<<<(K * K + kThreads - 1) / kThreads, kThreads, 0, s>>>(
+      M, P, reinterpret_cast<const double2*>(hsp), reinterpret_cast<const double2*>(Cs),
+      reinterpret_cast<double2*>(H));
+  return hipGetLastError();
+}
+
+hipError_t launch_coulomb_expand(int M, const double* Cs, double* C, hipStream_t s) {
+  const int P = M * (M + 1) / 2, n4 = M * M * M * M;
+  coulomb_expand_kernel<<<(n4 + kThreads - 1) / kThreads, kThreads, 0, s>>>(
+      M, P, reinterpret_cast<const double2*>(Cs), reinterpret_cast<double2*>(C));
+  return hipGetLastError();
+}
+
+hipError_t launch_exchange(const double* E, double* J, hipStream_t s) {
+  exchange_kernel<<<1, 64, 0, s>>>(E, J);
   return hipGetLastError();
 }
 

@@ -7,6 +7,7 @@
 #include <chrono>
 #include <cmath>
 #include <string>
+#include <vector>
 
 #include "hkp_internal.h"
 #include "solver.h"
@@ -40,20 +41,22 @@ struct PoissonWS {
   CGState* st;
 };
 
-PoissonWS carve_poisson(Carve& c, long long NP) {
+// coefficients once; CG vectors and states for nrhs systems solved together
+PoissonWS carve_poisson(Carve& c, long long NP, int nrhs = 1) {
   PoissonWS w;
+  const size_t nv = (size_t)nrhs * NP;
   w.cx = c.take<double>(NP);
   w.cy = c.take<double>(NP);
   w.cz = c.take<double>(NP);
   w.dinv = c.take<double>(NP);
-  w.r = c.take<double>(NP);
-  w.z = c.take<double>(NP);
-  w.p0 = c.take<double>(NP);
-  w.p1 = c.take<double>(NP);
-  w.q = c.take<double>(NP);
-  w.partial = c.take<double>(sp_partial_doubles());
+  w.r = c.take<double>(nv);
+  w.z = c.take<double>(nv);
+  w.p0 = c.take<double>(nv);
+  w.p1 = c.take<double>(nv);
+  w.q = c.take<double>(nv);
+  w.partial = c.take<double>(sp_partial_doubles(nrhs));
   w.n_dir = c.take<double>(1);
-  w.st = c.take<CGState>(1);
+  w.st = c.take<CGState>(nrhs);
   return w;
 }
 
@@ -83,6 +86,7 @@ struct CGGraph {
   hipGraphExec_t exec = nullptr;
   const double* phi = nullptr;
   int max_iter = -1;
+  int nrhs = 0;
   void reset() {
     if (exec) (void)hipGraphExecDestroy(exec);
     if (graph) (void)hipGraphDestroy(graph);
@@ -95,12 +99,12 @@ struct CGGraph {
 constexpr int kCGChunk = 32;   // even: every chunk starts from the same direction buffer
 
 void launch_cg_chunk(const PGeom& g, const uint8_t* dir, double* phi, int max_iter,
-                     const PoissonWS& w, hipStream_t s) {
+                     const PoissonWS& w, hipStream_t s, int nrhs) {
   for (int c = 0; c < kCGChunk; ++c) {
     double* po = (c % 2 == 0) ? w.p0 : w.p1;
     double* pn = (c % 2 == 0) ? w.p1 : w.p0;
     HKP_CHECK(launch_cg_iter(g, w.cx, w.cy, w.cz, w.dinv, dir, w.z, po, pn, w.q, phi, w.r,
-                             w.partial, max_iter, w.st, s));
+                             w.partial, max_iter, w.st, s, nrhs));
   }
 }
 
@@ -109,14 +113,15 @@ void launch_cg_chunk(const PGeom& g, const uint8_t* dir, double* phi, int max_it
 // per chunk (iterations after convergence are no-ops)
 int poisson_cg(const PGeom& g, const uint8_t* dir, const double* phi_fixed, const double* rho,
                double* phi, double tol, int max_iter, const PoissonWS& w, hipStream_t s,
-               int* iters, double* relres, CGGraph* gc = nullptr) {
+               int* iters, double* relres, CGGraph* gc = nullptr, int nrhs = 1) {
   HKP_CHECK(launch_cg_init(g, w.cx, w.cy, w.cz, w.dinv, dir, phi_fixed, rho, kEoverEps0, phi,
-                           w.r, w.z, w.p0, w.partial, tol, w.st, s));
-  if (gc && s != nullptr && (gc->phi != phi || gc->max_iter != max_iter || !gc->exec)) {
+                           w.r, w.z, w.p0, w.partial, tol, w.st, s, nrhs));
+  if (gc && s != nullptr &&
+      (gc->phi != phi || gc->max_iter != max_iter || gc->nrhs != nrhs || !gc->exec)) {
     gc->reset();
     HKP_CHECK(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
     try {
-      launch_cg_chunk(g, dir, phi, max_iter, w, s);
+      launch_cg_chunk(g, dir, phi, max_iter, w, s, nrhs);
     } catch (...) {
       hipGraph_t g2 = nullptr;
       (void)hipStreamEndCapture(s, &g2);
@@ -127,28 +132,39 @@ int poisson_cg(const PGeom& g, const uint8_t* dir, const double* phi_fixed, cons
     HKP_CHECK(hipGraphInstantiate(&gc->exec, gc->graph, nullptr, nullptr, 0));
     gc->phi = phi;
     gc->max_iter = max_iter;
+    gc->nrhs = nrhs;
   }
   const bool use_graph = gc && s != nullptr && gc->exec;
-  CGState h{};
+  std::vector<CGState> h((size_t)nrhs);
   long long launched = 0;
   for (;;) {
-    HKP_CHECK(hipMemcpyAsync(&h, w.st, sizeof(CGState), hipMemcpyDeviceToHost, s));
+    HKP_CHECK(hipMemcpyAsync(h.data(), w.st, sizeof(CGState) * nrhs, hipMemcpyDeviceToHost, s));
     HKP_CHECK(hipStreamSynchronize(s));
-    if (h.done || launched >= max_iter) break;
+    bool all = true;
+    for (const CGState& x : h) all = all && x.done;
+    if (all || launched >= max_iter) break;
     if (use_graph)
       HKP_CHECK(hipGraphLaunch(gc->exec, s));
     else
-      launch_cg_chunk(g, dir, phi, max_iter, w, s);
+      launch_cg_chunk(g, dir, phi, max_iter, w, s, nrhs);
     launched += kCGChunk;
   }
-  if (iters) *iters = h.it;
-  if (relres) *relres = h.bb > 0.0 ? std::sqrt(h.rr / h.bb) : 0.0;
-  if (h.breakdown) {
-    set_error("Poisson CG breakdown: the operator is not positive definite (a free region "
-              "without a path to an electrode?)");
-    return HKP_E_NUMERICAL;
+  // the worst system: most iterations, largest relative residual
+  int it = 0, rc = HKP_OK;
+  double rel = 0.0;
+  for (const CGState& x : h) {
+    it = std::max(it, x.it);
+    rel = std::max(rel, x.bb > 0.0 ? std::sqrt(x.rr / x.bb) : 0.0);
+    if (x.breakdown) {
+      set_error("Poisson CG breakdown: the operator is not positive definite (a free region "
+                "without a path to an electrode?)");
+      return HKP_E_NUMERICAL;
+    }
+    if (!(x.rr <= x.thr)) rc = HKP_W_NOT_CONVERGED;
   }
-  return h.rr <= h.thr ? HKP_OK : HKP_W_NOT_CONVERGED;
+  if (iters) *iters = it;
+  if (relres) *relres = rel;
+  return rc;
 }
 
 double seconds_since(std::chrono::steady_clock::time_point t0) {
@@ -380,6 +396,102 @@ int run_sp(const SPArgs& a, hkp_sp_stats* stats) {
   if (stats) *stats = st;
   if (!converged) return HKP_W_NOT_CONVERGED;
   return st.solve_status != HKP_OK ? st.solve_status : HKP_OK;
+}
+
+namespace {
+
+struct CILayout {
+  PoissonWS pw;
+  double *rhs, *V, *comp, *gpart, *hsp, *A, *Vc, *Cs, *H, *vecs, *evals;
+  int* status;
+  size_t total;
+};
+
+CILayout carve_ci(char* base, const hkp_grid& g, int M, const hkp_pgrid& pg) {
+  CILayout L;
+  Carve c{base};
+  const long long NP = geom(pg).NP, NS = (long long)g.nx * g.ny * g.nz;
+  const int P = M * (M + 1) / 2, K = M * (2 * M - 1);
+  L.pw = carve_poisson(c, NP, 2 * P);
+  L.rhs = c.take<double>((size_t)2 * P * NP);
+  L.V = c.take<double>((size_t)2 * P * NP);
+  L.comp = c.take<double>((size_t)2 * 3 * M * NS);
+  const int wide = std::max(std::max(3 * M, M * M), P);
+  L.gpart = c.take<double>(gram_partial_bytes(wide, NS, 1) / sizeof(double));
+  L.hsp = c.take<double>((size_t)2 * 4 * M * M);
+  L.A = c.take<double>((size_t)2 * M * M * NS);
+  L.Vc = c.take<double>((size_t)2 * P * NS);
+  L.Cs = c.take<double>((size_t)2 * M * M * P);
+  L.H = c.take<double>((size_t)2 * K * K);
+  L.vecs = c.take<double>((size_t)2 * K * K);
+  L.evals = c.take<double>(K);
+  L.status = c.take<int>(1);
+  L.total = c.off;
+  return L;
+}
+
+}  // namespace
+
+size_t ci_bytes(const hkp_grid& g, int M, const hkp_pgrid& pg) {
+  return carve_ci(nullptr, g, M, pg).total;
+}
+
+int run_ci(const CIArgs& a, hkp_ci_stats* stats) {
+  const auto t0 = std::chrono::steady_clock::now();
+  hipStream_t s = reinterpret_cast<hipStream_t>(a.stream);
+  const CILayout L = carve_ci(reinterpret_cast<char*>(a.workspace), a.grid, a.M, a.pg);
+  const PGeom g = geom(a.pg);
+  const int M = a.M, P = M * (M + 1) / 2, K = M * (2 * M - 1), nrhs = 2 * P;
+  const long long NS = (long long)a.grid.nx * a.grid.ny * a.grid.nz;
+  const int nx = a.grid.nx, ny = a.grid.ny, nz = a.grid.nz;
+  // single-particle matrix diag(E) (x) 1 + spin-orbit (component overlaps on the Gram kernel)
+  HKP_CHECK(launch_gather_components(NS, M, a.phi, L.comp, s));
+  const BlockDesc Bc{L.comp, NS, 3 * M, 3LL * M * NS};
+  HKP_CHECK(launch_gram(Bc, Bc, 1, 1, L.gpart, L.A, nullptr, s));   // overlaps into A (scratch)
+  HKP_CHECK(launch_soi_assemble(M, L.A, a.E, a.delta_so, L.hsp, s));
+  // pair densities -> potentials with every electrode grounded, all pairs at once
+  int rc = poisson_prepare(g, a.grid.h_nm, a.eps, a.dir, L.pw, s);
+  if (rc != HKP_OK) return rc;
+  HKP_CHECK(launch_pair_rhs(g, a.pg.ox, a.pg.oy, a.pg.oz, nx, ny, nz, M, a.phi, a.grid.h_nm,
+                            L.rhs, s));
+  HKP_CHECK(hipMemsetAsync(L.V, 0, (size_t)nrhs * g.NP * sizeof(double), s));
+  const auto tp = std::chrono::steady_clock::now();
+  int cgit = 0;
+  double rel = 0.0;
+  CGGraph gc;
+  rc = poisson_cg(g, a.dir, nullptr, L.rhs, L.V, a.cg_tol, a.cg_max_iter, L.pw, s, &cgit, &rel,
+                  &gc, nrhs);
+  const double t_poisson =
+      std::chrono::duration<double>(std::chrono::steady_clock::now() - tp).count();
+  if (rc < 0) return rc;
+  const int poisson_status = rc;
+  // Coulomb integrals (ik|jl) = sum over the grid of conj(A_ik) V_jl (Gram kernel)
+  HKP_CHECK(launch_pair_potential_gather(g, a.pg.ox, a.pg.oy, a.pg.oz, nx, ny, nz, P, L.V, L.Vc,
+                                         s));
+  HKP_CHECK(launch_pair_product(NS, M, a.phi, L.A, s));
+  const BlockDesc BA{L.A, NS, M * M, (long long)M * M * NS};
+  const BlockDesc BV{L.Vc, NS, P, (long long)P * NS};
+  HKP_CHECK(launch_gram(BA, BV, 0, 1, L.gpart, L.Cs, nullptr, s));
+  // determinant matrix, its spectrum, the exchange splitting
+  HKP_CHECK(launch_ci_assemble(M, L.hsp, L.Cs, L.H, s));
+  if (a.H)
+    HKP_CHECK(hipMemcpyAsync(a.H, L.H, (size_t)K * K * 16, hipMemcpyDeviceToDevice, s));
+  if (a.coulomb)
+    HKP_CHECK(launch_coulomb_expand(M, L.Cs, static_cast<double*>(a.coulomb), s));
+  HKP_CHECK(hipMemsetAsync(L.status, 0, sizeof(int), s));
+  HKP_CHECK(launch_heev(L.H, K, 1, (long long)K * K, a.eig,
+                        a.vecs ? static_cast<double*>(a.vecs) : L.vecs, 0, L.status, nullptr, s));
+  if (a.J && K >= 4) HKP_CHECK(launch_exchange(a.eig, a.J, s));
+  HKP_CHECK(hipStreamSynchronize(s));
+  if (stats) {
+    stats->cg_iters = cgit;
+    stats->cg_relres = rel;
+    stats->poisson_solves = nrhs;
+    stats->determinants = K;
+    stats->t_poisson = t_poisson;
+    stats->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  }
+  return poisson_status;
 }
 
 }  // namespace hkp
