@@ -340,6 +340,40 @@ def spin_free_measure(torch, hkp, workload):
             "lowest_full_eV": [float(v) for v in full.E[:4].cpu().numpy()]}
 
 
+def ci_measure(torch, hkp):
+    """Two-hole configuration interaction on the 256 x 48 x 48 double-dot fin in its
+    272 x 64 x 88 box (hole-free potential, B = 0, strain): 4 spin-free orbitals,
+    28 determinants, the 10 pair potentials (20 real right-hand sides) from one
+    batched CG solve to |r| <= 1e-11 |b|."""
+    from synth import sp_device
+    d = sp_device("sp_dqd_256x48x48")
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
+    eps, dirm = t(d.eps_r), t(d.dirichlet)
+    phi0, _, _, _ = hkp.poisson(eps, dirm, t(d.phi_fixed), None, d.h, tol=1e-12)
+    ox, oy, oz = d.offset
+    V = t(d.V_off) + phi0[ox:ox + d.shape[0], oy:oy + d.shape[1], oz:oz + d.shape[2]]
+    S = t(d.strain)
+    hkp.solve(V, d.h, 4, strain=S, nb=12, tol=1e-9, spin_free=True)   # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    r = hkp.solve(V, d.h, 4, strain=S, nb=12, tol=1e-9, spin_free=True)
+    torch.cuda.synchronize()
+    t_orb = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    ci = hkp.ci_solve(r.psi, r.E, d.h, d.pshape, d.offset, eps, dirm, cg_tol=1e-11)
+    torch.cuda.synchronize()
+    t_ci = time.perf_counter() - t0
+    st = ci.stats
+    per = st["t_poisson"] / max(1, st["cg_iters"] * st["poisson_solves"])   # per nonzero rhs
+    return {"workload": "sp_dqd_256x48x48, hole-free potential, B = 0", "orbitals": 4,
+            "determinants": st["determinants"], "s_orbitals": round(t_orb, 4),
+            "s_ci": round(t_ci, 4), "poisson_right_hand_sides": st["poisson_solves"],
+            "cg_iterations": st["cg_iters"], "s_poisson_batched": round(st["t_poisson"], 4),
+            "us_per_cg_iteration_per_rhs": round(per * 1e6, 2), "J_eV": ci.J,
+            "lowest_two_hole_eV": [float(v) for v in ci.E[:4].cpu().numpy()],
+            "status": ci.status}
+
+
 def cpu_baseline(w, seconds=15.0):
     """The CPU oracle's H.X (scipy CSR matvec on the assembled Hamiltonian) on a
     slab of the same workload, in the same algorithmic-bytes unit."""
@@ -391,6 +425,8 @@ def main():
                     help="run only the Poisson CG rate measurement (profiled runs)")
     ap.add_argument("--spin-free-only", action="store_true",
                     help="run only the spin-free basis measurement (profiled runs)")
+    ap.add_argument("--ci-only", action="store_true",
+                    help="run only the configuration-interaction measurement (profiled runs)")
     args = ap.parse_args()
     if args.traffic_from:
         if not args.stencil or not args.nb:
@@ -425,6 +461,9 @@ def main():
         return
     if args.spin_free_only:
         print(json.dumps(spin_free_measure(torch, hkp, workload)), flush=True)
+        return
+    if args.ci_only:
+        print(json.dumps(ci_measure(torch, hkp)), flush=True)
         return
 
     w = workload(WORKLOAD)
@@ -507,6 +546,9 @@ def main():
         log("spin-free basis ...")
         extra["spin_free"] = spin_free_measure(torch, hkp, workload)
         log(f"spin-free {extra['spin_free']}")
+        log("configuration interaction ...")
+        extra["ci"] = ci_measure(torch, hkp)
+        log(f"ci {extra['ci']}")
         log("self-consistent Schroedinger-Poisson loop ...")
         extra["sp"] = sp_measure(torch, hkp)
         log(f"sp {extra['sp']}")

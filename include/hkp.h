@@ -334,7 +334,8 @@ int hkp_soi_matrix(const hkp_grid* grid, int32_t M, const void* phi, const doubl
 typedef struct {
   int64_t cg_iters;        /* CG iterations of the batched pair-potential solve (max over systems) */
   double cg_relres;        /* largest final |r| / |b| */
-  int32_t poisson_solves;  /* real right-hand sides solved together, M (M + 1) */
+  int32_t poisson_solves;  /* nonzero real right-hand sides solved together, M^2 (the
+                              imaginary parts of the M self pairs vanish and stop at once) */
   int32_t determinants;    /* K = M (2M - 1) */
   double t_poisson, seconds;
 } hkp_ci_stats;

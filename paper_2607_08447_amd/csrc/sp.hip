@@ -584,7 +584,9 @@ pair_rhs_kernel(unsigned NP, int px, int py, int pz, double ipy, double ipz, int
       }
     }
     re[i] = a * inv_h3;
-    im[i] = b * inv_h3;
+    // a self pair density is real; with contracted multiply-adds the sum above
+    // leaves rounding noise there, which the solver would chase to tolerance
+    im[i] = j == l ? 0.0 : b * inv_h3;
   }
 }
 
