@@ -24,6 +24,10 @@ Pinning status (see tests/test_oracle_pins.py):
   * Hellmann-Feynman gradient  -- pinned (central finite differences)
   * Zeeman sign convention and absolute g-factors -- parity unpinned against the
     paper (the paper prints no Zeeman term); only the invariants above hold.
+  * g-matrices and the two-spin model (gmatrix.py) -- pinned (closed-form heavy-hole
+    and split-off g at one grid point, Zeeman splitting of the full H(B), gauge-origin
+    and basis invariance, mirror-image dots, the paper's t = Delta / sqrt(2) example,
+    closed forms of the effective Hamiltonian and of J_perp, J_par)
 """
 
 from .constants import E0, MU_B, E_OVER_HBAR, SI_MATERIAL  # noqa: F401
@@ -43,4 +47,9 @@ from .poisson import (  # noqa: F401
 from .spinfree import h0_orbital, soi_matrix, single_particle  # noqa: F401
 from .ci import (  # noqa: F401
     pair_densities, pair_potentials, coulomb_integrals, determinants, ci_hamiltonian, exchange,
+)
+from .gmatrix import (  # noqa: F401
+    field_derivative, g_matrix, symmetric_g, localise, double_dot_g, tunnel_coupling,
+    u_minus_eps, rotation, zeeman_fields, effective_hamiltonian, qubit_frame,
+    anisotropic_exchange, two_spin_model,
 )

@@ -64,10 +64,12 @@ def vector_potential(gauge, B, rel):
     raise ValueError(f"unknown gauge {gauge!r}")
 
 
-def link_phases(grid, axis, B, gauge="symmetric"):
-    """U_axis(r) for the link r -> r + h e_axis at every grid point (nx, ny, nz)."""
+def link_phases(grid, axis, B, gauge="symmetric", origin=None):
+    """U_axis(r) for the link r -> r + h e_axis at every grid point (nx, ny, nz).
+
+    origin: the gauge origin r0 as an offset (nm) from the box centre (None: the centre)."""
     x, y, z = grid.coords()
-    r0 = grid.centre()
+    r0 = grid.centre() + (0.0 if origin is None else np.asarray(origin, dtype=float))
     mid = [x - r0[0], y - r0[1], z - r0[2]]
     mid[axis] = mid[axis] + 0.5 * grid.h
     A = vector_potential(gauge, B, tuple(mid))
@@ -75,13 +77,13 @@ def link_phases(grid, axis, B, gauge="symmetric"):
                   * np.ones(grid.shape))
 
 
-def shift_operator(grid, axis, B=(0.0, 0.0, 0.0), gauge="symmetric"):
+def shift_operator(grid, axis, B=(0.0, 0.0, 0.0), gauge="symmetric", origin=None):
     """Sparse T_a with (T_a psi)(r) = U_a(r) psi(r + e_a); zero past a hard wall."""
     if grid.periodic and any(float(b) != 0.0 for b in B):
         raise ValueError("periodic grids are only supported at B = 0")
     n = grid.shape
     idx = np.arange(grid.npts).reshape(n)
-    phase = link_phases(grid, axis, B, gauge)
+    phase = link_phases(grid, axis, B, gauge, origin)
     if grid.periodic:
         rows = idx.ravel()
         cols = np.roll(idx, -1, axis=axis).ravel()
@@ -97,7 +99,7 @@ def shift_operator(grid, axis, B=(0.0, 0.0, 0.0), gauge="symmetric"):
     return sp.csr_matrix((vals, (rows, cols)), shape=(grid.npts, grid.npts))
 
 
-def kinetic_operators(grid, B=(0.0, 0.0, 0.0), gauge="symmetric"):
+def kinetic_operators(grid, B=(0.0, 0.0, 0.0), gauge="symmetric", origin=None):
     """The discrete k-operators of the finite-difference k.p Hamiltonian.
 
     Kaa[a]      = (2 - T_a - T_a^H) / h^2          (compact 3-point k_a^2)
@@ -107,7 +109,7 @@ def kinetic_operators(grid, B=(0.0, 0.0, 0.0), gauge="symmetric"):
     """
     h = grid.h
     eye = sp.identity(grid.npts, dtype=complex, format="csr")
-    T = [shift_operator(grid, a, B, gauge) for a in range(3)]
+    T = [shift_operator(grid, a, B, gauge, origin) for a in range(3)]
     Kaa = [((2.0 * eye - t - t.getH()) / h**2).tocsr() for t in T]
     Ka = [((-1j) * (t - t.getH()) / (2.0 * h)).tocsr() for t in T]
     Ksym = {}

@@ -190,12 +190,13 @@ def _assemble(blocks, N):
 
 
 def hamiltonian_j(grid, material, V=None, strain=None, B=(0.0, 0.0, 0.0),
-                  gauge="symmetric"):
-    """Sparse (6N x 6N) Hamiltonian in the |J m_j> basis (Form 2 above)."""
+                  gauge="symmetric", origin=None):
+    """Sparse (6N x 6N) Hamiltonian in the |J m_j> basis (Form 2 above); origin: the
+    symmetric gauge's origin as an offset from the box centre (nm), None for the centre."""
     g1, g2, g3 = material["gamma1"], material["gamma2"], material["gamma3"]
     V, strain = _check_fields(grid, V, strain)
     N = grid.npts
-    Kaa, _, Ksym = kinetic_operators(grid, B, gauge)
+    Kaa, _, Ksym = kinetic_operators(grid, B, gauge, origin)
     P = g1 * (Kaa[0] + Kaa[1] + Kaa[2])
     Q = g2 * (Kaa[0] + Kaa[1] - 2.0 * Kaa[2])
     R = _S3 * (-g2 * (Kaa[0] - Kaa[1]) + 2j * g3 * Ksym[(0, 1)])
