@@ -359,6 +359,71 @@ int hkp_ci_solve(const hkp_grid* grid, int32_t M, const void* phi, const double*
                  void* vecs, void* H_ci, void* coulomb, double* J_eV, void* workspace,
                  size_t ws_bytes, void* hip_stream, hkp_ci_stats* stats);
 
+/* ---- g-matrices of the double dot and the effective two-spin model
+ * (Sec. III: Eqs. HB, J_QD, J_anis) ----
+ * The g-matrix of a Kramers doublet {u1, u2}: to first order in B the
+ * Hamiltonian restricted to the doublet is (mu_B / 2) sum_ab sigma_a g_ab B_b,
+ * so g_ab = Re tr(sigma_a M_b) / mu_B with M_b = <u_i| dH/dB_b |u_j>.  dH/dB_b
+ * is the derivative of the whole Hamiltonian (Zeeman and Peierls terms) at
+ * B = 0, in the symmetric gauge about the doublet's own centre of charge.  The
+ * dots' doublets are the eigenvectors of the position x within the span of the
+ * bonding and antibonding doublets (lower x = left).  g depends on the basis of
+ * its doublet through a rotation on the left only; the symmetric g-tensor
+ * sgn(det g) (g^T g)^(1/2) and the singular values of g do not. */
+typedef struct {
+  double g[4][3][3];        /* bonding, antibonding, left, right: row a = Pauli, column b = field */
+  double g_sym[4][3][3];    /* symmetric g-tensors */
+  double centre_nm[4][3];   /* centres of charge, about the box centre */
+  double kramers[4][3];     /* tr M_b / mu_B: zero for a Kramers doublet */
+  double E_eV[4];           /* <psi_i|H|psi_i> of the four input states */
+  double delta_eV;          /* antibonding minus bonding doublet energy */
+  double t_eV;              /* tunnel coupling |Delta| / sqrt(2) */
+  double d_nm;              /* distance between the left and right centres */
+} hkp_gmatrix_result;
+
+/* Workspace of hkp_gmatrix: 44 spinor blocks of the grid plus small buffers. */
+size_t hkp_gmatrix_workspace_bytes(const hkp_grid* grid);
+
+/*   psi   device complex double [4][nx][ny][nz][6] (|J m_j>, as hkp_solve returns at
+ *         B = 0): the bonding doublet (states 0, 1) and the antibonding doublet
+ *         (states 2, 3), orthonormal; V_eV, strain (may be NULL) and mat as in hkp_solve
+ *   out   device hkp_gmatrix_result
+ * Returns HKP_OK or an error; nothing is allocated. */
+int hkp_gmatrix(const hkp_grid* grid, const hkp_material* mat, const double* V_eV,
+                const double* strain, const void* psi, void* out, void* workspace,
+                size_t ws_bytes, void* hip_stream);
+
+/* Effective two-spin model of Eq. HB for nB fields, one thread each, from the
+ * left and right symmetric g-tensors and t of an hkp_gmatrix_result:
+ *   R(theta) = rotation by theta about n_so, theta_so = d / lambda_so;
+ *   b_bar = mu_B (R(-theta_so) g_L + R(theta_so) g_R) B / 2, delta_b likewise with
+ *   a minus sign, delta E_Z = |delta_b|; U - eps = 2 t^2 / J;
+ *   the 5 x 5 matrix in the basis S(0,2), S(1,1), T+, T-, T0 and its spectrum;
+ *   J_hat = J R(-2 theta_so); J~ = R_L J_hat R_R^T, R_L the rotation about
+ *   n_L x z that takes n_L = g_L B / |g_L B| to z (the lab frame if g_L B = 0);
+ *   |J_perp| = |(J~xx + J~yy, J~xy - J~yx)| / 2, J_par = J~zz. */
+typedef struct {
+  double n_so[3];           /* spin-orbit axis, any nonzero length */
+  double lambda_so_nm;      /* spin-orbit length, > 0 */
+  double d_nm;              /* inter-dot distance; <= 0: the result's d_nm */
+} hkp_st_opts;
+
+typedef struct {
+  double bbar_eV[3], dbar_eV[3];   /* b_bar and delta_b */
+  double dEz_eV;                   /* |delta_b| */
+  double E_eV[5];                  /* spectrum of the 5 x 5 matrix, ascending */
+  double Jtilde_eV[3][3];          /* exchange matrix in the qubit frames */
+  double J_perp_eV, J_par_eV;
+} hkp_st_point;
+
+/*   gm    device hkp_gmatrix_result (from hkp_gmatrix)
+ *   J_eV  device double [1], the exchange at the detuning of interest (nonzero;
+ *         hkp_ci_solve writes one)
+ *   B_T   device double [nB][3], 1 <= nB <= 2^24
+ *   points device hkp_st_point [nB]; H device complex double [nB][5][5] or NULL */
+int hkp_st_model(const void* gm, const double* J_eV, const hkp_st_opts* opts, int32_t nB,
+                 const double* B_T, void* points, void* H, void* hip_stream);
+
 /* Workspace of hkp_poisson for this box. */
 size_t hkp_poisson_workspace_bytes(const hkp_pgrid* pgrid);
 

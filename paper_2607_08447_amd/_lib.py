@@ -98,6 +98,22 @@ class hkp_ci_stats(C.Structure):
         return {name: getattr(self, name) for name, _ in self._fields_}
 
 
+class hkp_gmatrix_result(C.Structure):
+    _fields_ = [("g", C.c_double * 36), ("g_sym", C.c_double * 36), ("centre_nm", C.c_double * 12),
+                ("kramers", C.c_double * 12), ("E_eV", C.c_double * 4), ("delta_eV", C.c_double),
+                ("t_eV", C.c_double), ("d_nm", C.c_double)]
+
+
+class hkp_st_opts(C.Structure):
+    _fields_ = [("n_so", C.c_double * 3), ("lambda_so_nm", C.c_double), ("d_nm", C.c_double)]
+
+
+class hkp_st_point(C.Structure):
+    _fields_ = [("bbar_eV", C.c_double * 3), ("dbar_eV", C.c_double * 3), ("dEz_eV", C.c_double),
+                ("E_eV", C.c_double * 5), ("Jtilde_eV", C.c_double * 9),
+                ("J_perp_eV", C.c_double), ("J_par_eV", C.c_double)]
+
+
 _P = C.c_void_p
 _D = C.POINTER(C.c_double)
 
@@ -146,6 +162,10 @@ SIGNATURES = {
                                C.POINTER(hkp_pgrid), C.POINTER(hkp_sp_opts), _P, _P, _D, _P, _P,
                                _P, _P, _P, _P, _P, _P, _P, _P, C.c_size_t, _P,
                                C.POINTER(hkp_sp_stats)]),
+    "hkp_gmatrix_workspace_bytes": (C.c_size_t, [C.POINTER(hkp_grid)]),
+    "hkp_gmatrix": (C.c_int, [C.POINTER(hkp_grid), C.POINTER(hkp_material), _P, _P, _P, _P, _P,
+                              C.c_size_t, _P]),
+    "hkp_st_model": (C.c_int, [_P, _P, C.POINTER(hkp_st_opts), C.c_int32, _P, _P, _P, _P]),
     "hkp_last_error": (C.c_char_p, []),
     "hkp_version": (C.c_int, []),
 }

@@ -393,6 +393,67 @@ def ci_solve(phi, E, h, pshape, offset, eps_r, dirichlet, delta_so=None, materia
 
 
 # ---------------------------------------------------------------------------
+# g-matrices and the effective two-spin model
+# ---------------------------------------------------------------------------
+@dataclass
+class GMatrixResult:
+    g: object            # numpy [4, 3, 3]: bonding, antibonding, left, right (row = Pauli)
+    g_sym: object        # numpy [4, 3, 3] symmetric g-tensors
+    centre: object       # numpy [4, 3] centres of charge, nm about the box centre
+    kramers: object      # numpy [4, 3] tr M_b / mu_B (zero for Kramers doublets)
+    E: object            # numpy [4] <psi_i|H|psi_i>, eV
+    delta: float         # antibonding - bonding, eV
+    t: float             # |delta| / sqrt(2), eV
+    d: float             # distance between the left and right centres, nm
+    raw: torch.Tensor    # the device hkp_gmatrix_result (input of two_spin_model)
+
+
+def g_matrices(psi, V, h, strain=None, material=None):
+    """g-matrices of the bonding (psi[0:2]) and antibonding (psi[2:4]) Kramers doublets
+    and of the dots' doublets they localise to; psi [4, nx, ny, nz, 6] from a B = 0 solve."""
+    psi = _dev(psi, torch.complex128)
+    V = _dev(V, torch.float64)
+    S = _dev(strain, torch.float64)
+    if psi.dim() != 5 or psi.shape[0] != 4 or psi.shape[-1] != 6 or \
+            tuple(psi.shape[1:4]) != tuple(V.shape):
+        raise ValueError("psi must be [4, nx, ny, nz, 6] on V's grid")
+    g = _grid(tuple(V.shape), h)
+    mat = _material(material)
+    need = L.lib.hkp_gmatrix_workspace_bytes(C.byref(g))
+    if need == 0:
+        raise L.HkpError(L.HKP_E_ARG, L.lib.hkp_last_error().decode())
+    ws = torch.empty(need, dtype=torch.uint8, device="cuda")
+    raw = torch.empty(C.sizeof(L.hkp_gmatrix_result) // 8, dtype=torch.float64, device="cuda")
+    L.check(L.lib.hkp_gmatrix(C.byref(g), C.byref(mat), _ptr(V), _ptr(S), _ptr(psi), _ptr(raw),
+                              _ptr(ws), C.c_size_t(need), _stream()))
+    r = L.hkp_gmatrix_result.from_buffer_copy(raw.cpu().numpy().tobytes())
+    import numpy as np
+    return GMatrixResult(np.array(r.g).reshape(4, 3, 3), np.array(r.g_sym).reshape(4, 3, 3),
+                         np.array(r.centre_nm).reshape(4, 3), np.array(r.kramers).reshape(4, 3),
+                         np.array(r.E_eV), r.delta_eV, r.t_eV, r.d_nm, raw)
+
+
+def two_spin_model(gm, J, B, n_so, lambda_so, d=0.0, return_matrix=False):
+    """Eq. HB and the anisotropic exchange for every field in B [nB, 3] (tesla), from
+    the left/right g-tensors and t of g_matrices(); J (eV, float or device [1]) is the
+    exchange at the detuning of interest; d <= 0 takes the dots' distance from gm."""
+    raw = gm.raw if isinstance(gm, GMatrixResult) else gm
+    Bt = _dev(B, torch.float64).reshape(-1, 3)
+    nB = Bt.shape[0]
+    Jt = J if torch.is_tensor(J) else torch.tensor([float(J)], dtype=torch.float64)
+    Jt = _dev(Jt, torch.float64).reshape(1)
+    o = L.hkp_st_opts((C.c_double * 3)(*[float(v) for v in n_so]), float(lambda_so), float(d))
+    width = C.sizeof(L.hkp_st_point) // 8
+    pts = torch.empty((nB, width), dtype=torch.float64, device="cuda")
+    H = torch.empty((nB, 5, 5), dtype=torch.complex128, device="cuda") if return_matrix else None
+    L.check(L.lib.hkp_st_model(_ptr(raw), _ptr(Jt), C.byref(o), int(nB), _ptr(Bt), _ptr(pts),
+                               _ptr(H), _stream()))
+    return {"bbar": pts[:, 0:3], "db": pts[:, 3:6], "dEz": pts[:, 6], "E": pts[:, 7:12],
+            "Jt": pts[:, 12:21].reshape(nB, 3, 3), "J_perp": pts[:, 21], "J_par": pts[:, 22],
+            "H": H}
+
+
+# ---------------------------------------------------------------------------
 # self-consistent Schroedinger-Poisson loop
 # ---------------------------------------------------------------------------
 def _pgrid(pshape, offset=(0, 0, 0)):

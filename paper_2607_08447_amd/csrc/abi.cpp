@@ -694,6 +694,65 @@ int hkp_sp_solve(const hkp_grid* grid, const hkp_material* mat, const hkp_opts* 
   return guarded([&]() { return run_sp(a, stats); });
 }
 
-int hkp_version(void) { return 110; }
+size_t hkp_gmatrix_workspace_bytes(const hkp_grid* grid) {
+  if (check_grid(grid) != HKP_OK) return 0;
+  return gmatrix_bytes(*grid);
+}
+
+int hkp_gmatrix(const hkp_grid* grid, const hkp_material* mat, const double* V_eV,
+                const double* strain, const void* psi, void* out, void* workspace,
+                size_t ws_bytes, void* hip_stream) {
+  HKP_TRY(check_grid(grid));
+  HKP_TRY(check_material(mat));
+  if (!V_eV || !psi || !out || !workspace) {
+    set_error("hkp_gmatrix: non-NULL V, psi, out, workspace required");
+    return HKP_E_ARG;
+  }
+  const size_t need = gmatrix_bytes(*grid);
+  if (ws_bytes < need) {
+    set_error("workspace too small: need " + std::to_string(need) + " bytes");
+    return HKP_E_WORKSPACE;
+  }
+  HKP_TRY(check_device());
+  GMatrixArgs a{};
+  a.grid = *grid;
+  a.mat = *mat;
+  a.V = V_eV;
+  a.strain = strain;
+  a.psi = psi;
+  a.out = out;
+  a.workspace = workspace;
+  a.stream = hip_stream;
+  a.st = autotuned(*grid, 16, false);
+  return guarded([&]() { return run_gmatrix(a); });
+}
+
+int hkp_st_model(const void* gm, const double* J_eV, const hkp_st_opts* opts, int32_t nB,
+                 const double* B_T, void* points, void* H, void* hip_stream) {
+  if (!gm || !J_eV || !opts || !B_T || !points || nB < 1 || nB > (1 << 24)) {
+    set_error("hkp_st_model: 1 <= nB <= 2^24 and non-NULL gm, J, opts, B, points required");
+    return HKP_E_ARG;
+  }
+  const double* n = opts->n_so;
+  const double nn = std::sqrt(n[0] * n[0] + n[1] * n[1] + n[2] * n[2]);
+  if (!(nn > 0.0) || !std::isfinite(nn) || !(opts->lambda_so_nm > 0.0) ||
+      !std::isfinite(opts->lambda_so_nm) || !std::isfinite(opts->d_nm)) {
+    set_error("hkp_st_model: nonzero finite n_so, finite lambda_so > 0 and finite d required");
+    return HKP_E_ARG;
+  }
+  HKP_TRY(check_device());
+  return guarded([&]() {
+    const double u[3] = {n[0] / nn, n[1] / nn, n[2] / nn};
+    const hipError_t e = launch_st_model(gm, J_eV, u, opts->lambda_so_nm, opts->d_nm, nB, B_T,
+                                         points, H, (hipStream_t)hip_stream);
+    if (e != hipSuccess) {
+      set_error(hipGetErrorString(e));
+      return HKP_E_HIP;
+    }
+    return HKP_OK;
+  });
+}
+
+int hkp_version(void) { return 111; }
 
 }  // extern "C"

@@ -851,6 +851,67 @@ int run_filter_step(const FilterArgs& A) {
   return HKP_OK;
 }
 
+// ---------------------------------------------------------------------------
+// g-matrices: psi, r_a psi (16 vectors) -> H_0 of them, Z_b psi -> one Gram product
+// ---------------------------------------------------------------------------
+constexpr int kGmSlots = 44;
+
+size_t gmatrix_bytes(const hkp_grid& g) {
+  const size_t N = (size_t)g.nx * g.ny * g.nz, n6 = 6 * N;
+  return align_up(6 * N * 8) + align_up((size_t)kGmSlots * n6 * 16) +
+         align_up(gram_partial_bytes(kGmSlots, (long long)n6, 1)) +
+         align_up((size_t)16 * kGmSlots * 16);
+}
+
+int run_gmatrix(const GMatrixArgs& A) {
+  const hkp_grid& g = A.grid;
+  const size_t N = (size_t)g.nx * g.ny * g.nz, n6 = 6 * N;
+  char* ws = reinterpret_cast<char*>(A.workspace);
+  hipStream_t s = reinterpret_cast<hipStream_t>(A.stream);
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    char* p = ws + off;
+    off += align_up(bytes);
+    return p;
+  };
+  double* D64 = (double*)take(6 * N * 8);
+  double* buf = (double*)take((size_t)kGmSlots * n6 * 16);
+  double* partial = (double*)take(gram_partial_bytes(kGmSlots, (long long)n6, 1));
+  double* G = (double*)take((size_t)16 * kGmSlots * 16);
+  const double B0[3] = {0.0, 0.0, 0.0};
+  HKP_CHECK(launch_onsite(A.mat, g.nx, g.ny, g.nz, 1, A.V, 0, A.strain, D64, nullptr, 0, s));
+  HKP_CHECK(launch_abi_to_internal(g.nx, g.ny, g.nz, g.h_nm, B0, 4, A.psi, buf, 0, s));
+  HKP_CHECK(launch_position_weight(g.nx, g.ny, g.nz, g.h_nm, buf, s));
+  StencilLaunch a{};
+  a.nx = g.nx;
+  a.ny = g.ny;
+  a.nz = g.nz;
+  a.nvec = 16;
+  a.batch = 1;
+  a.in = buf;
+  a.old = nullptr;
+  a.old_fp64 = 1;
+  a.out = buf + 2 * 16 * n6;   // slot 16 (two doubles per complex entry)
+  a.out_fp64 = 1;
+  a.D = D64;
+  a.strain = A.strain != nullptr;
+  a.coef.alpha = 1.0;
+  a.coef.shift = 0.0;
+  a.coef.beta = 0.0;
+  a.tile_y = A.st.tile_y;
+  a.vgroup = A.st.vgroup;
+  a.dma = A.st.dma;
+  a.zsplit = A.st.zsplit;
+  a.fp64 = 1;
+  HKP_CHECK(launch_stencil(a, make_consts(A.mat, g.h_nm, B0), s));
+  HKP_CHECK(launch_zeeman_derivative((long long)N, A.mat.kappa, buf, s));
+  const BlockDesc L{buf, (long long)n6, 16, 0};
+  const BlockDesc R{buf, (long long)n6, kGmSlots, 0};
+  HKP_CHECK(launch_gram(L, R, 0, 1, partial, G, nullptr, s));
+  HKP_CHECK(launch_gmatrix_post(G, A.out, s));
+  return HKP_OK;
+}
+
 // translate a HIP failure into the ABI error code
 int guarded(const std::function<int()>& f) {
   try {

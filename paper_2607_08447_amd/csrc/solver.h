@@ -153,4 +153,19 @@ struct CIArgs {
 size_t ci_bytes(const hkp_grid& g, int M, const hkp_pgrid& pg);
 int run_ci(const CIArgs& a, hkp_ci_stats* stats);
 
+// ---- g-matrices of the double dot's doublets
+struct GMatrixArgs {
+  hkp_grid grid;
+  hkp_material mat;
+  const double* V;
+  const double* strain;
+  const void* psi;
+  void* out;
+  void* workspace;
+  void* stream;
+  StencilTune st;
+};
+size_t gmatrix_bytes(const hkp_grid& g);
+int run_gmatrix(const GMatrixArgs& a);
+
 }  // namespace hkp
