@@ -340,11 +340,9 @@ def spin_free_measure(torch, hkp, workload):
             "lowest_full_eV": [float(v) for v in full.E[:4].cpu().numpy()]}
 
 
-def ci_measure(torch, hkp):
-    """Two-hole configuration interaction on the 256 x 48 x 48 double-dot fin in its
-    272 x 64 x 88 box (hole-free potential, B = 0, strain): 4 spin-free orbitals,
-    28 determinants, the 10 pair potentials (20 real right-hand sides) from one
-    batched CG solve to |r| <= 1e-11 |b|."""
+def _hole_free_device(torch, hkp):
+    """The 256 x 48 x 48 double-dot fin in its 272 x 64 x 88 box: the potential of
+    the gates alone (one Poisson solve), its strain, permittivity and electrodes."""
     from synth import sp_device
     d = sp_device("sp_dqd_256x48x48")
     t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
@@ -352,7 +350,15 @@ def ci_measure(torch, hkp):
     phi0, _, _, _ = hkp.poisson(eps, dirm, t(d.phi_fixed), None, d.h, tol=1e-12)
     ox, oy, oz = d.offset
     V = t(d.V_off) + phi0[ox:ox + d.shape[0], oy:oy + d.shape[1], oz:oz + d.shape[2]]
-    S = t(d.strain)
+    return d, V, t(d.strain), eps, dirm
+
+
+def ci_measure(torch, hkp, dev=None):
+    """Two-hole configuration interaction on the 256 x 48 x 48 double-dot fin in its
+    272 x 64 x 88 box (hole-free potential, B = 0, strain): 4 spin-free orbitals,
+    28 determinants, the 10 pair potentials (16 nonzero real right-hand sides) from
+    one batched CG solve to |r| <= 1e-11 |b|."""
+    d, V, S, eps, dirm = dev if dev is not None else _hole_free_device(torch, hkp)
     hkp.solve(V, d.h, 4, strain=S, nb=12, tol=1e-9, spin_free=True)   # warm-up
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -372,6 +378,51 @@ def ci_measure(torch, hkp):
             "us_per_cg_iteration_per_rhs": round(per * 1e6, 2), "J_eV": ci.J,
             "lowest_two_hole_eV": [float(v) for v in ci.E[:4].cpu().numpy()],
             "status": ci.status}
+
+
+def qubit_measure(torch, hkp, J=None, dev=None):
+    """g-matrices of the lowest two Kramers doublets (FP64 solve to 1e-10 at B = 0) on
+    the same hole-free potential as the CI, and the effective two-spin model over a
+    1-degree map of field orientations at |B| = 50 mT, with the CI's J.  The spin-orbit
+    axis and length come from measurements the paper cites and does not print; n_so = z
+    and lambda_so = 50 nm stand in for them."""
+    d, V, S, eps, dirm = dev if dev is not None else _hole_free_device(torch, hkp)
+    if J is None:
+        r = hkp.solve(V, d.h, 4, strain=S, nb=12, tol=1e-9, spin_free=True)
+        J = hkp.ci_solve(r.psi, r.E, d.h, d.pshape, d.offset, eps, dirm, cg_tol=1e-11).J
+    r = hkp.solve(V, d.h, 4, strain=S, tol=1e-10)
+    hkp.g_matrices(r.psi, V, d.h, strain=S)   # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    gm = hkp.g_matrices(r.psi, V, d.h, strain=S)
+    t_g = time.perf_counter() - t0
+    th = np.radians(np.arange(0, 181))
+    ph = np.radians(np.arange(0, 361))
+    T, P = np.meshgrid(th, ph, indexing="ij")
+    Bd = 0.05 * np.stack([np.sin(T) * np.cos(P), np.sin(T) * np.sin(P), np.cos(T)], -1)
+    Bt = torch.from_numpy(Bd.reshape(-1, 3)).cuda()
+    n_so, lam = (0.0, 0.0, 1.0), 50.0
+    hkp.two_spin_model(gm, J, Bt, n_so, lam)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    out = hkp.two_spin_model(gm, J, Bt, n_so, lam)
+    torch.cuda.synchronize()
+    t_m = time.perf_counter() - t0
+    jp = out["J_perp"].cpu().numpy().reshape(T.shape)
+    jl = out["J_par"].cpu().numpy().reshape(T.shape)
+    dz = out["dEz"].cpu().numpy().reshape(T.shape)
+    at = lambda k: [int(v) for v in np.unravel_index(k, T.shape)]
+    return {"workload": "sp_dqd_256x48x48, hole-free potential; |B| = 50 mT, 181 x 361 "
+                        "orientations", "s_g_matrices": round(t_g, 5),
+            "s_two_spin_model": round(t_m, 5), "orientations": int(Bt.shape[0]),
+            "g_left": np.round(gm.g_sym[2], 4).tolist(), "g_right": np.round(gm.g_sym[3], 4).tolist(),
+            "delta_eV": gm.delta, "t_eV": gm.t, "d_nm": round(gm.d, 3), "J_eV": J,
+            "U_minus_eps_eV": 2 * gm.t ** 2 / J if J else None,
+            "max_J_perp": [float(jp.max()), at(jp.argmax())],
+            "min_J_perp": [float(jp.min()), at(jp.argmin())],
+            "J_par_at_min_J_perp": float(jl.flat[jp.argmin()]),
+            "max_dEz_over_J_perp": float((dz / np.maximum(jp, 1e-300)).max()),
+            "kramers_defect": float(np.abs(gm.kramers[:2]).max())}
 
 
 def cpu_baseline(w, seconds=15.0):
@@ -427,6 +478,8 @@ def main():
                     help="run only the spin-free basis measurement (profiled runs)")
     ap.add_argument("--ci-only", action="store_true",
                     help="run only the configuration-interaction measurement (profiled runs)")
+    ap.add_argument("--qubit-only", action="store_true",
+                    help="run only the g-matrix / two-spin-model measurement (profiled runs)")
     args = ap.parse_args()
     if args.traffic_from:
         if not args.stencil or not args.nb:
@@ -464,6 +517,9 @@ def main():
         return
     if args.ci_only:
         print(json.dumps(ci_measure(torch, hkp)), flush=True)
+        return
+    if args.qubit_only:
+        print(json.dumps(qubit_measure(torch, hkp)), flush=True)
         return
 
     w = workload(WORKLOAD)
@@ -547,8 +603,12 @@ def main():
         extra["spin_free"] = spin_free_measure(torch, hkp, workload)
         log(f"spin-free {extra['spin_free']}")
         log("configuration interaction ...")
-        extra["ci"] = ci_measure(torch, hkp)
+        dev = _hole_free_device(torch, hkp)
+        extra["ci"] = ci_measure(torch, hkp, dev)
         log(f"ci {extra['ci']}")
+        log("g-matrices and the two-spin model ...")
+        extra["qubit"] = qubit_measure(torch, hkp, extra["ci"]["J_eV"], dev)
+        log(f"qubit {extra['qubit']}")
         log("self-consistent Schroedinger-Poisson loop ...")
         extra["sp"] = sp_measure(torch, hkp)
         log(f"sp {extra['sp']}")
