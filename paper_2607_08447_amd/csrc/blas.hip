@@ -195,6 +195,99 @@ gram_herm_kernel(const double* A, long long a_bstride, int nba, const double* B,
   }
 }
 
+// General (non-Hermitian) Gram A^H B, balanced as above: the four waves split the
+// chunk into four runs and each computes every (A tile, B tile) pair of its run.
+template <int NTA, int NTB>
+__global__ void __launch_bounds__(64 * 4)
+gram_gen_kernel(const double* A, long long a_bstride, int nba, const double* B,
+                long long b_bstride, int nbb, long long n, long long chunk, const int* active,
+                double* partial) {
+  __shared__ double2 red[4][16][17];
+  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int b = blockIdx.y;
+  if (active && !active[b]) return;
+  const int nchunks = gridDim.x;
+  const long long c0 = (long long)blockIdx.x * chunk;
+  long long c1 = c0 + chunk;
+  if (c1 > n) c1 = n;
+  long long q4 = ((c1 - c0 + 15) / 16) * 4;
+  long long e0 = c0 + wv * q4;
+  long long e1 = e0 + q4;
+  if (e1 > c1) e1 = c1;
+  if (e0 > c1) e0 = c1;
+  const int r = lane & 15, q = lane >> 4;
+  const double* pa[NTA];
+  const double* pb[NTB];
+  bool aok[NTA], bok[NTB];
+#pragma unroll
+  for (int t = 0; t < NTA; ++t) {
+    const int va = t * 16 + r;
+    aok[t] = va < nba;
+    pa[t] = A + 2 * ((long long)b * a_bstride + (long long)(aok[t] ? va : 0) * n);
+  }
+#pragma unroll
+  for (int t = 0; t < NTB; ++t) {
+    const int vb = t * 16 + r;
+    bok[t] = vb < nbb;
+    pb[t] = B + 2 * ((long long)b * b_bstride + (long long)(bok[t] ? vb : 0) * n);
+  }
+  d4 re[NTA * NTB], im[NTA * NTB];
+#pragma unroll
+  for (int k = 0; k < NTA * NTB; ++k) {
+    re[k] = d4{0, 0, 0, 0};
+    im[k] = re[k];
+  }
+  const long long nks = (e1 - e0 + 3) / 4;
+  for (long long st = 0; st < nks; ++st) {
+    const long long e = e0 + 4 * st + q;
+    const bool eok = e < e1;
+    double2 av[NTA], bv[NTB];
+#pragma unroll
+    for (int t = 0; t < NTA; ++t)
+      av[t] = (aok[t] && eok) ? *reinterpret_cast<const double2*>(pa[t] + 2 * e)
+                              : make_double2(0, 0);
+#pragma unroll
+    for (int t = 0; t < NTB; ++t)
+      bv[t] = (bok[t] && eok) ? *reinterpret_cast<const double2*>(pb[t] + 2 * e)
+                              : make_double2(0, 0);
+#pragma unroll
+    for (int ti = 0; ti < NTA; ++ti) {
+#pragma unroll
+      for (int tj = 0; tj < NTB; ++tj) {
+        const int k = ti * NTB + tj;
+        re[k] = mfma(av[ti].x, bv[tj].x, re[k]);
+        re[k] = mfma(av[ti].y, bv[tj].y, re[k]);
+        im[k] = mfma(av[ti].x, bv[tj].y, im[k]);
+        im[k] = mfma(-av[ti].y, bv[tj].x, im[k]);
+      }
+    }
+  }
+  double* out = partial + 2 * (((long long)b * nchunks + blockIdx.x) * nba * nbb);
+#pragma unroll
+  for (int ti = 0; ti < NTA; ++ti) {
+#pragma unroll
+    for (int tj = 0; tj < NTB; ++tj) {
+      const int k = ti * NTB + tj;
+#pragma unroll
+      for (int g = 0; g < 4; ++g) red[wv][4 * g + q][r] = make_double2(re[k][g], im[k][g]);
+      __syncthreads();
+      {
+        const int i = threadIdx.x >> 4, j = threadIdx.x & 15;
+        double2 sum = red[0][i][j];
+#pragma unroll
+        for (int w = 1; w < 4; ++w) {
+          sum.x += red[w][i][j].x;
+          sum.y += red[w][i][j].y;
+        }
+        const int gi = ti * 16 + i, gj = tj * 16 + j;
+        if (gi < nba && gj < nbb)
+          *reinterpret_cast<double2*>(out + 2 * ((long long)gi * nbb + gj)) = sum;
+      }
+      __syncthreads();
+    }
+  }
+}
+
 // fixed-order reduction of the chunk partials: one wave per output entry,
 // lane l sums chunks l, l+64, ..., then a shuffle tree (deterministic)
 __global__ void __launch_bounds__(256)
@@ -527,6 +620,31 @@ hipError_t launch_gram(const BlockDesc& A, const BlockDesc& B, int hermitian, in
       case 4: gram_herm_kernel<4><<<grid, 256, 0, s>>>(A.ptr, A.bstride, A.nvec, B.ptr, B.bstride, B.nvec, n, chunk, active, partial); break;
       default: return hipErrorInvalidValue;
     }
+  } else if (!hermitian) {
+    dim3 grid((unsigned)nchunks, (unsigned)batch);
+#define HKP_GEN(TA, TB)                                                                       \
+  gram_gen_kernel<TA, TB><<<grid, 256, 0, s>>>(A.ptr, A.bstride, A.nvec, B.ptr, B.bstride,    \
+                                               B.nvec, n, chunk, active, partial)
+    if (nta < 1 || nta > 4 || ntb < 1 || ntb > 4) return hipErrorInvalidValue;
+    switch (4 * (nta - 1) + (ntb - 1)) {
+      case 0: HKP_GEN(1, 1); break;
+      case 1: HKP_GEN(1, 2); break;
+      case 2: HKP_GEN(1, 3); break;
+      case 3: HKP_GEN(1, 4); break;
+      case 4: HKP_GEN(2, 1); break;
+      case 5: HKP_GEN(2, 2); break;
+      case 6: HKP_GEN(2, 3); break;
+      case 7: HKP_GEN(2, 4); break;
+      case 8: HKP_GEN(3, 1); break;
+      case 9: HKP_GEN(3, 2); break;
+      case 10: HKP_GEN(3, 3); break;
+      case 11: HKP_GEN(3, 4); break;
+      case 12: HKP_GEN(4, 1); break;
+      case 13: HKP_GEN(4, 2); break;
+      case 14: HKP_GEN(4, 3); break;
+      default: HKP_GEN(4, 4); break;
+    }
+#undef HKP_GEN
   } else {
     dim3 grid((unsigned)nchunks, (unsigned)((nta + 3) / 4), (unsigned)batch);
     switch (ntb) {

@@ -10,8 +10,7 @@
 // Z_b the on-site Zeeman matrix per tesla and R the position.  So everything
 // needed for four states psi_i comes from one B = 0 stencil apply to the 16
 // vectors {psi_i, R_x psi_i, R_y psi_i, R_z psi_i} and one Gram product of those
-// 16 against themselves, their images under H_0 and Z_b psi_i (rows 0-15 of the
-// 44 x 44 Gram matrix of all of them).  The
+// 16 against themselves, their images under H_0 and Z_b psi_i (16 x 44).  The
 // origin of each doublet's gauge is its own centre of charge, which enters the
 // small matrices only.  Everything after the Gram product is 4 x 4 algebra done
 // by one thread.
@@ -197,8 +196,8 @@ zeeman_derivative_kernel(long long N, double g_orb, double2* buf) {
   }
 }
 
-// 4 x 4 blocks of the Gram product G = [L, H_0 L, Z psi]^H [L, H_0 L, Z psi] (44 x 44,
-// row-major; only rows 0-15 are read): slot 4 c + i is r_c psi_i (c = 0: psi itself)
+// 4 x 4 blocks of the Gram product G = L^H [L, H_0 L, Z psi] (16 x 44, row-major):
+// slot 4 c + i is r_c psi_i (c = 0: psi itself)
 __device__ __forceinline__ double2 gW(const double2* G, int c, int i, int d, int j) {
   return G[(4 * c + i) * 44 + 16 + 4 * d + j];   // <r_c psi_i | H_0 | r_d psi_j>
 }
@@ -231,8 +230,11 @@ __device__ void sym_g(const double g[3][3], double out[3][3]) {
     }
 }
 
-__global__ void gmatrix_post_kernel(const double2* __restrict__ G, hkp_gmatrix_result* out) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+__global__ void gmatrix_post_kernel(const double2* __restrict__ Gg, hkp_gmatrix_result* out) {
+  __shared__ double2 G[16 * 44];   // the whole Gram block, staged once by the workgroup
+  for (int i = threadIdx.x; i < 16 * 44; i += blockDim.x) G[i] = Gg[i];
+  __syncthreads();
+  if (threadIdx.x != 0) return;
   // the dots' doublets: eigenvectors of x within the span, lower x first
   double2 Xx[4][4], C[4][4];
   double wx[4];

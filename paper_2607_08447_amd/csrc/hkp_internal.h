@@ -291,7 +291,7 @@ hipError_t launch_anderson(const PGeom& g, int k, int m, int slot, double mixing
 // g-matrices: an internal block of 44 spinors (LS, B = 0) whose slots 0-3 hold the
 // four states; slots 4 (a + 1) + v <- r_a psi_v (r about the box centre),
 // slots 32 + 4 b + v <- Z_b psi_v (Zeeman matrix per tesla); the post kernel turns
-// the Gram matrix of slots 0-43 (44 x 44; slots 16-31 = H_0 of 0-15, rows 0-15 read)
+// the 16 x 44 Gram product of slots 0-15 against 0-43 (slots 16-31 = H_0 of 0-15)
 // into an hkp_gmatrix_result
 hipError_t launch_position_weight(int nx, int ny, int nz, double h, double* buf, hipStream_t s);
 hipError_t launch_zeeman_derivative(long long N, double kappa, double* buf, hipStream_t s);

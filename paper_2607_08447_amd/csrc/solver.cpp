@@ -852,10 +852,9 @@ int run_filter_step(const FilterArgs& A) {
 }
 
 // ---------------------------------------------------------------------------
-// g-matrices: psi, r_a psi (16 vectors) -> H_0 of them, Z_b psi -> one Gram product.
-// Every entry needed (rows 0-15 of [L, H_0 L, Z psi]^H [L, H_0 L, Z psi]) lies in the
-// upper 16 x 16 tile pairs of the Hermitian 44 x 44 product, which the balanced
-// Hermitian Gram kernel forms reading each vector once.
+// g-matrices: psi, r_a psi (16 vectors) -> H_0 of them, Z_b psi -> one Gram product
+// L^H [L, H_0 L, Z psi] (16 x 44; L, the first 16 vectors of the block, is read twice
+// by the same workgroup, the second time from cache).
 // ---------------------------------------------------------------------------
 constexpr int kGmSlots = 44;
 
@@ -863,7 +862,7 @@ size_t gmatrix_bytes(const hkp_grid& g) {
   const size_t N = (size_t)g.nx * g.ny * g.nz, n6 = 6 * N;
   return align_up(6 * N * 8) + align_up((size_t)kGmSlots * n6 * 16) +
          align_up(gram_partial_bytes(kGmSlots, (long long)n6, 1)) +
-         align_up((size_t)kGmSlots * kGmSlots * 16);
+         align_up((size_t)16 * kGmSlots * 16);
 }
 
 int run_gmatrix(const GMatrixArgs& A) {
@@ -880,7 +879,7 @@ int run_gmatrix(const GMatrixArgs& A) {
   double* D64 = (double*)take(6 * N * 8);
   double* buf = (double*)take((size_t)kGmSlots * n6 * 16);
   double* partial = (double*)take(gram_partial_bytes(kGmSlots, (long long)n6, 1));
-  double* G = (double*)take((size_t)kGmSlots * kGmSlots * 16);
+  double* G = (double*)take((size_t)16 * kGmSlots * 16);
   const double B0[3] = {0.0, 0.0, 0.0};
   HKP_CHECK(launch_onsite(A.mat, g.nx, g.ny, g.nz, 1, A.V, 0, A.strain, D64, nullptr, 0, s));
   HKP_CHECK(launch_abi_to_internal(g.nx, g.ny, g.nz, g.h_nm, B0, 4, A.psi, buf, 0, s));
@@ -908,8 +907,9 @@ int run_gmatrix(const GMatrixArgs& A) {
   a.fp64 = 1;
   HKP_CHECK(launch_stencil(a, make_consts(A.mat, g.h_nm, B0), s));
   HKP_CHECK(launch_zeeman_derivative((long long)N, A.mat.kappa, buf, s));
+  const BlockDesc L{buf, (long long)n6, 16, 0};
   const BlockDesc R{buf, (long long)n6, kGmSlots, 0};
-  HKP_CHECK(launch_gram(R, R, 1, 1, partial, G, nullptr, s));
+  HKP_CHECK(launch_gram(L, R, 0, 1, partial, G, nullptr, s));
   HKP_CHECK(launch_gmatrix_post(G, A.out, s));
   return HKP_OK;
 }
