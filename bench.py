@@ -237,6 +237,12 @@ def adjoint_measure(torch, hkp, workload):
 # electrode mask, write p and L p) and the vector update (read D^-1, p, L p, phi,
 # r; write phi, r, z)
 CG_BYTES_PER_NODE = (8 + 8 + 24 + 1 + 8 + 8) + (5 * 8 + 3 * 8)
+# one multigrid-preconditioned CG iteration, per node of the box: the CG kernels without
+# the Jacobi z (operator 57, update: read p, q, phi, r, write phi, r = 48), the V-cycle's
+# finest level (restriction: read b, D^-1, diag, three link weights = 48; correction: the
+# same 48, the coarse correction 1, write z 8) and its coarser levels (the same pattern
+# on 1/8 + 1/64 + ... of the nodes, about 15)
+MG_PCG_BYTES_PER_NODE = (57 + 48) + (48 + 57) + 15
 
 
 def sp_measure(torch, hkp):
@@ -273,9 +279,12 @@ def sp_measure(torch, hkp):
 
 
 def poisson_measure(torch, hkp, d=None, density=None, iters=1024):
-    """Poisson CG on the 272 x 64 x 88 box: time per iteration of a fixed iteration
-    count (unreachable tolerance), HIP events on the library's stream, against the
-    HBM roofline at CG_BYTES_PER_NODE algorithmic bytes per node."""
+    """Poisson CG on the 272 x 64 x 88 box, timed with HIP events on the library's
+    stream: the multigrid-preconditioned solve to |r| <= 1e-12 |b| from zero (the
+    library's default), and the Jacobi-preconditioned one both to the same tolerance
+    and over a fixed iteration count (unreachable tolerance); per-iteration rates
+    against the HBM roofline at MG_PCG_BYTES_PER_NODE and CG_BYTES_PER_NODE
+    algorithmic bytes per node."""
     from synth import sp_device
     d = d or sp_device("sp_dqd_256x48x48")
     t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
@@ -287,18 +296,38 @@ def poisson_measure(torch, hkp, d=None, density=None, iters=1024):
                              dtype=torch.float64, device="cuda")
     rho[d.offset[0]:d.offset[0] + d.shape[0], d.offset[1]:d.offset[1] + d.shape[1],
         d.offset[2]:d.offset[2] + d.shape[2]] = density
-    hkp.poisson(eps, dirm, phif, rho, d.h, tol=1e-30, max_iter=64)   # warm-up
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
-    e0.record()
-    _, it, _, _ = hkp.poisson(eps, dirm, phif, rho, d.h, tol=1e-30, max_iter=iters)
-    e1.record()
-    e1.synchronize()
-    t_it = e0.elapsed_time(e1) * 1e-3 / it
-    gbps = CG_BYTES_PER_NODE * NP / t_it / 1e9
-    return {"nodes": NP, "us_per_iteration": round(t_it * 1e6, 2),
-            "bytes_per_node": CG_BYTES_PER_NODE, "achieved_gbps": round(gbps, 1),
-            "peak_gbps": 8000.0, "frac": round(gbps / 8000.0, 4), "iterations_timed": it}
+    def timed(**kw):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        _, it, rel, _ = hkp.poisson(eps, dirm, phif, rho, d.h, **kw)
+        e1.record()
+        e1.synchronize()
+        return e0.elapsed_time(e1) * 1e-3, it, rel
+
+    def rate(bpn, t_it):
+        g = bpn * NP / t_it / 1e9
+        return {"bytes_per_node": bpn, "achieved_gbps": round(g, 1), "peak_gbps": 8000.0,
+                "frac": round(g / 8000.0, 4)}
+
+    out = {"nodes": NP}
+    prev = hkp.poisson_preconditioner("multigrid")
+    try:
+        timed(tol=1e-12)   # warm-up (graph recording)
+        t, it, rel = timed(tol=1e-12)
+        out["multigrid"] = {"s_to_1e-12": round(t, 5), "iterations": it, "relres": rel,
+                            "us_per_iteration": round(t / it * 1e6, 2), **rate(MG_PCG_BYTES_PER_NODE, t / it)}
+        hkp.poisson_preconditioner("jacobi")
+        timed(tol=1e-30, max_iter=64)
+        t, it, rel = timed(tol=1e-12)
+        out["jacobi"] = {"s_to_1e-12": round(t, 5), "iterations": it, "relres": rel}
+        t, it, _ = timed(tol=1e-30, max_iter=iters)
+        out["jacobi"].update({"us_per_iteration": round(t / it * 1e6, 2),
+                              "iterations_timed": it, **rate(CG_BYTES_PER_NODE, t / it)})
+    finally:
+        hkp.poisson_preconditioner(prev)
+    out["speedup_to_solution"] = round(out["jacobi"]["s_to_1e-12"] / out["multigrid"]["s_to_1e-12"], 2)
+    return out
 
 
 def spin_free_measure(torch, hkp, workload):
@@ -331,7 +360,16 @@ def spin_free_measure(torch, hkp, workload):
     torch.cuda.synchronize()
     t_soi = (time.perf_counter() - t0) / 10
     ev = torch.linalg.eigvalsh(H).cpu().numpy()
+
+    def stencil_rate(st):   # the library's event-timed FP64 stencil launches of one solve
+        n, t, b = st["n_stencil64"], st["t_stencil64"], st["bytes_stencil64"]
+        return {"launches": n, "avg_us": round(1e6 * t / max(n, 1), 1),
+                "gbps": round(b / t / 1e9, 1) if t > 0 else None,
+                "frac": round(b / t / 8e12, 4) if t > 0 else None}
+
     return {"workload": WORKLOAD + " at B = 0", "orbitals": 16,
+            "stencil_fp64_orbital": stencil_rate(r.stats),
+            "stencil_fp64_spinor": stencil_rate(full.stats),
             "s_spin_free_fp64": round(t_sf, 4), "iters_spin_free": r.stats["iters"],
             "s_full_32_states_fp64": round(t_full, 4), "iters_full": full.stats["iters"],
             "speedup": round(t_full / t_sf, 3), "s_soi_matrix_32x32": round(t_soi, 6),
@@ -371,11 +409,17 @@ def ci_measure(torch, hkp, dev=None):
     t_ci = time.perf_counter() - t0
     st = ci.stats
     per = st["t_poisson"] / max(1, st["cg_iters"] * st["poisson_solves"])   # per nonzero rhs
+    nodes = int(np.prod(d.pshape))
+    cg_rate = MG_PCG_BYTES_PER_NODE * nodes / per   # algorithmic bytes per iteration and rhs
     return {"workload": "sp_dqd_256x48x48, hole-free potential, B = 0", "orbitals": 4,
             "determinants": st["determinants"], "s_orbitals": round(t_orb, 4),
             "s_ci": round(t_ci, 4), "poisson_right_hand_sides": st["poisson_solves"],
             "cg_iterations": st["cg_iters"], "s_poisson_batched": round(st["t_poisson"], 4),
-            "us_per_cg_iteration_per_rhs": round(per * 1e6, 2), "J_eV": ci.J,
+            "us_per_cg_iteration_per_rhs": round(per * 1e6, 2),
+            "cg_roofline": {"bound": "hbm", "bytes_per_node": MG_PCG_BYTES_PER_NODE,
+                            "achieved_gbps": round(cg_rate / 1e9, 1), "peak_gbps": 8000.0,
+                            "frac": round(cg_rate / 8e12, 4)},
+            "J_eV": ci.J,
             "lowest_two_hole_eV": [float(v) for v in ci.E[:4].cpu().numpy()],
             "status": ci.status}
 
@@ -412,8 +456,14 @@ def qubit_measure(torch, hkp, J=None, dev=None):
     jl = out["J_par"].cpu().numpy().reshape(T.shape)
     dz = out["dEz"].cpu().numpy().reshape(T.shape)
     at = lambda k: [int(v) for v in np.unravel_index(k, T.shape)]
+    # algorithmic bytes of one g-matrix call, in spinor blocks of 6 N complex doubles:
+    # 4 in + 4 out (layout), 4 + 12 (position weights), 16 + 16 (stencil), 4 + 12 (Zeeman),
+    # 44 (the Gram product reads each vector once)
+    blk = 6 * int(np.prod(d.shape)) * 16
+    g_bytes = 116 * blk
     return {"workload": "sp_dqd_256x48x48, hole-free potential; |B| = 50 mT, 181 x 361 "
                         "orientations", "s_g_matrices": round(t_g, 5),
+            "g_matrices_gbps_algorithmic": round(g_bytes / t_g / 1e9, 1),
             "s_two_spin_model": round(t_m, 5), "orientations": int(Bt.shape[0]),
             "g_left": np.round(gm.g_sym[2], 4).tolist(), "g_right": np.round(gm.g_sym[3], 4).tolist(),
             "delta_eV": gm.delta, "t_eV": gm.t, "d_nm": round(gm.d, 3), "J_eV": J,

@@ -424,6 +424,19 @@ typedef struct {
 int hkp_st_model(const void* gm, const double* J_eV, const hkp_st_opts* opts, int32_t nB,
                  const double* B_T, void* points, void* H, void* hip_stream);
 
+/* Preconditioner of every Poisson conjugate-gradient solve that follows in this
+ * process (hkp_poisson, hkp_sp_solve, hkp_ci_solve); the solution to the given
+ * tolerance does not depend on it, the iteration count does.
+ *   HKP_PRECOND_MULTIGRID (default): one V-cycle per iteration over 2 x 2 x 2
+ *     aggregation levels with Galerkin coarse operators and damped-Jacobi smoothing
+ *     (a symmetric positive-definite preconditioner).
+ *   HKP_PRECOND_JACOBI: the diagonal.
+ * Returns the previous choice, or HKP_E_ARG for an unknown kind.  Not to be
+ * changed while another thread runs a Poisson solve. */
+#define HKP_PRECOND_MULTIGRID 0
+#define HKP_PRECOND_JACOBI 1
+int hkp_poisson_preconditioner(int32_t kind);
+
 /* Workspace of hkp_poisson for this box. */
 size_t hkp_poisson_workspace_bytes(const hkp_pgrid* pgrid);
 

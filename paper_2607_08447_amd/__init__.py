@@ -13,6 +13,7 @@ from .api import (  # noqa: F401
     SI, EigvalsFromPotential, SolveResult, apply, autotune, autotune_block, filter_step, gate_potential,
     hf_grad, solve, solve_batch, solve_sweep, workspace_bytes, poisson, occupancy, hole_density,
     sp_solve, SPResult, soi_matrix, ci_solve, CIResult, g_matrices, GMatrixResult, two_spin_model,
+    poisson_preconditioner,
 )
 
 __version__ = "1.0.0"

@@ -21,6 +21,8 @@ HKP_E_UNSUPPORTED = -5
 HKP_NB_MAX = 64
 HKP_PREC_FP64 = 0
 HKP_PREC_MIXED = 1
+HKP_PRECOND_MULTIGRID = 0
+HKP_PRECOND_JACOBI = 1
 HKP_FLAG_X0 = 1
 HKP_FLAG_GRAPH = 2
 HKP_FLAG_NO_FP64_POLISH = 4
@@ -166,6 +168,7 @@ SIGNATURES = {
     "hkp_gmatrix": (C.c_int, [C.POINTER(hkp_grid), C.POINTER(hkp_material), _P, _P, _P, _P, _P,
                               C.c_size_t, _P]),
     "hkp_st_model": (C.c_int, [_P, _P, C.POINTER(hkp_st_opts), C.c_int32, _P, _P, _P, _P]),
+    "hkp_poisson_preconditioner": (C.c_int, [C.c_int32]),
     "hkp_last_error": (C.c_char_p, []),
     "hkp_version": (C.c_int, []),
 }

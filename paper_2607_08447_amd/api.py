@@ -462,6 +462,17 @@ def _pgrid(pshape, offset=(0, 0, 0)):
     return L.hkp_pgrid(px, py, pz, ox, oy, oz)
 
 
+def poisson_preconditioner(kind):
+    """Preconditioner of the Poisson CG solves that follow in this process:
+    "multigrid" (default) or "jacobi".  Returns the previous one."""
+    code = {"multigrid": L.HKP_PRECOND_MULTIGRID, "jacobi": L.HKP_PRECOND_JACOBI}.get(kind)
+    if code is None:
+        raise ValueError("kind must be 'multigrid' or 'jacobi'")
+    prev = L.lib.hkp_poisson_preconditioner(code)
+    L.check(min(prev, 0))
+    return "multigrid" if prev == L.HKP_PRECOND_MULTIGRID else "jacobi"
+
+
 def poisson(eps_r, dirichlet, phi_fixed, rho, h, phi0=None, tol=1e-12, max_iter=20000,
             graph=True):
     """phi (V) on the Poisson box [px, py, pz] from -div(eps_r grad phi) = (e/eps0) rho

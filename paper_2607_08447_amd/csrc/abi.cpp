@@ -753,6 +753,14 @@ int hkp_st_model(const void* gm, const double* J_eV, const hkp_st_opts* opts, in
   });
 }
 
-int hkp_version(void) { return 111; }
+int hkp_poisson_preconditioner(int32_t kind) {
+  if (kind != HKP_PRECOND_MULTIGRID && kind != HKP_PRECOND_JACOBI) {
+    set_error("hkp_poisson_preconditioner: HKP_PRECOND_MULTIGRID or HKP_PRECOND_JACOBI");
+    return HKP_E_ARG;
+  }
+  return set_poisson_precond(kind);
+}
+
+int hkp_version(void) { return 112; }
 
 }  // extern "C"

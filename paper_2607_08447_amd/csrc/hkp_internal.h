@@ -232,6 +232,42 @@ struct CGState {
   int it, done, breakdown, pad;
 };
 
+// multigrid preconditioner of the Poisson CG (2 x 2 x 2 aggregation, Galerkin
+// coarse operators; see sp.hip): levels down to at most kMGCoarsest nodes
+constexpr int kMGMaxLevels = 12;
+constexpr int kMGCoarsest = 256;
+constexpr double kMGOmega = 0.9;       // damped-Jacobi weight (D^-1 A has spectrum in [0, 2])
+constexpr double kMGAlpha = 1.8;       // finest-level scaling of the coarse correction
+constexpr int kMGCoarseSweeps = 30;    // even
+struct MGLevel {
+  int nx, ny, nz;
+  long long N;
+  long long off;    // offset of the level in the coefficient arrays
+  long long voff;   // offset of the level in a system's coarse vectors (levels >= 1)
+};
+struct MGPlan {
+  int nlev;
+  MGLevel lv[kMGMaxLevels];
+  long long total;    // coefficient entries over all levels
+  long long vtotal;   // coarse-vector entries of one system (levels >= 1)
+};
+struct MGData {
+  MGPlan plan;
+  double *ax, *ay, *az, *diag, *dinv;   // [plan.total]
+  double *b, *u;                        // [nrhs][plan.vtotal]
+  double* partial_rz;                   // [nrhs][kRedBlocks]
+};
+MGPlan mg_plan(const PGeom& g);
+// level 0 from the CG's link coefficients, then every coarser level
+hipError_t launch_mg_setup(const PGeom& g, const double* cx, const double* cy, const double* cz,
+                           const uint8_t* dir, const MGData& m, hipStream_t s);
+// z = V-cycle(r) for nrhs systems (skipping finished ones), partial sums of r.z
+hipError_t launch_mg_vcycle(const PGeom& g, const MGData& m, const double* r, double* z,
+                            const CGState* st, int nrhs, hipStream_t s);
+// after launch_cg_init: z and the starting r.z from the V-cycle
+hipError_t launch_mg_start(const PGeom& g, const MGData& m, const double* r, double* z,
+                           CGState* st, int nrhs, hipStream_t s);
+
 int sp_blocks(long long n);
 size_t sp_partial_doubles(int nrhs = 1);   // partial-sum scratch of the SP launchers
 // link coefficients cx, cy, cz (+x, +y, +z links), D^-1 (0 on electrodes) and
@@ -254,7 +290,7 @@ hipError_t launch_cg_iter(const PGeom& g, const double* cx, const double* cy, co
                           const double* dinv, const uint8_t* dir, double* z,
                           const double* p_old, double* p_new, double* q, double* phi,
                           double* r, double* partial, int max_iter, CGState* st,
-                          hipStream_t s, int nrhs = 1);
+                          hipStream_t s, int nrhs = 1, const struct MGData* mg = nullptr);
 hipError_t launch_occupancy(int nev, const double* E, double n_holes, double kT, double* f,
                             double* mu, hipStream_t s);
 // rho (P grid, may be null) = rho_fixed (may be null) + hole density embedded at

@@ -103,6 +103,7 @@ struct PoissonArgs {
   void* stream;
 };
 size_t poisson_bytes(const hkp_pgrid& pg);
+int set_poisson_precond(int kind);   // returns the previous kind
 int run_poisson(const PoissonArgs& a, int* iters, double* relres);
 
 struct SPArgs {

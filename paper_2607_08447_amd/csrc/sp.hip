@@ -270,7 +270,9 @@ cg_alpha_kernel(const double* partial, int nblk, CGState* st) {
   }
 }
 
-// phi += alpha p; r -= alpha q; z = D^-1 r; partials r.z, r.r
+// phi += alpha p; r -= alpha q; z = D^-1 r (Jacobi; with the multigrid
+// preconditioner z comes from the V-cycle afterwards); partials r.z, r.r
+template <bool JACOBI>
 __global__ void __launch_bounds__(kThreads)
 cg_update_kernel(long long NP, const double* __restrict__ dinv, const double* __restrict__ p,
                  const double* __restrict__ q, double* phi, double* r, double* zv,
@@ -290,10 +292,12 @@ cg_update_kernel(long long NP, const double* __restrict__ dinv, const double* __
     const double pi = p[i];
     phi[i] += alpha * pi;
     const double ri = r[i] - alpha * q[i];
-    const double zi = dinv[i] * ri;
     r[i] = ri;
-    zv[i] = zi;
-    acc[0] += ri * zi;
+    if (JACOBI) {
+      const double zi = dinv[i] * ri;
+      zv[i] = zi;
+      acc[0] += ri * zi;
+    }
     acc[1] += ri * ri;
   }
   block_sums<2>(acc, partial + 2LL * ((long long)blockIdx.y * gridDim.x + blockIdx.x));
@@ -312,6 +316,265 @@ cg_beta_kernel(const double* partial, int nblk, int max_iter, CGState* st) {
     st->it += 1;
     st->done = (s[1] <= st->thr || st->it >= max_iter) ? 1 : 0;
   }
+}
+
+// with the multigrid preconditioner: r.z from the V-cycle's partials, r.r from the
+// update's
+__global__ void __launch_bounds__(kRedThreads)
+cg_beta_mg_kernel(const double* partial, const double* partial_rz, int nblk, int max_iter,
+                  CGState* st) {
+  st += blockIdx.y;
+  if (st->done) return;
+  __shared__ double s[2], t[1];
+  reduce_partials<2>(partial + 2LL * blockIdx.y * nblk, nblk, s);
+  reduce_partials<1>(partial_rz + (long long)blockIdx.y * nblk, nblk, t);
+  if (threadIdx.x == 0) {
+    st->beta = st->rz > 0.0 ? t[0] / st->rz : 0.0;
+    st->rz = t[0];
+    st->rr = s[1];
+    st->it += 1;
+    st->done = (s[1] <= st->thr || st->it >= max_iter) ? 1 : 0;
+  }
+}
+
+// the starting r.z once the V-cycle has replaced the Jacobi z of cg_init
+__global__ void __launch_bounds__(kRedThreads)
+cg_rz_kernel(const double* partial_rz, int nblk, CGState* st) {
+  st += blockIdx.y;
+  if (st->done) return;
+  __shared__ double t[1];
+  reduce_partials<1>(partial_rz + (long long)blockIdx.y * nblk, nblk, t);
+  if (threadIdx.x == 0) st->rz = t[0];
+}
+
+// ---------------------------------------------------------------------------
+// Multigrid preconditioner of the Poisson CG.  On the free nodes the operator is
+// A u = diag u - sum_links a u_neighbour (a: free-free link weights; links to an
+// electrode only add to diag).  Level k + 1 aggregates 2 x 2 x 2 nodes of level k
+// (piecewise-constant prolongation P, restriction P^T): its operator P^T A P keeps
+// the same 7-point form, with link weights summed over the aggregates' shared
+// faces and diag = sum of the children's diag - 2 (internal link weights).  One
+// V-cycle: a damped-Jacobi pre-smoothing from zero (u = w D^-1 b, never stored),
+// residual restricted, the coarse problem, the correction prolonged (scaled by
+// alpha on the finest level only) and one damped-Jacobi post-smoothing; the
+// coarsest level (at most kMGCoarsest nodes) takes an even number of Jacobi
+// sweeps.  With w < 2 / lambda_max(D^-1 A) (here <= 2) and alpha < 2 every
+// level's cycle is a symmetric positive-definite map, so it preconditions CG.
+// ---------------------------------------------------------------------------
+struct MGGeo {
+  int nx, ny, nz;
+  double iny, inz;   // 1 / ny, 1 / nz
+};
+
+__device__ __forceinline__ void mg_coords(unsigned i, const MGGeo& g, int& x, int& y, int& z) {
+  const unsigned q = udiv(i, (unsigned)g.nz, g.inz);   // x ny + y
+  z = (int)(i - q * (unsigned)g.nz);
+  x = (int)udiv(q, (unsigned)g.ny, g.iny);
+  y = (int)(q - (unsigned)x * (unsigned)g.ny);
+}
+
+// level 0: free-free link weights, diagonal and D^-1 of the CG operator
+__global__ void __launch_bounds__(kThreads)
+mg_level0_kernel(unsigned NP, MGGeo g, const double* __restrict__ cx,
+                 const double* __restrict__ cy, const double* __restrict__ cz,
+                 const uint8_t* __restrict__ dir, double* ax, double* ay, double* az,
+                 double* diag, double* dinv) {
+  const unsigned sx = (unsigned)g.ny * g.nz, sy = (unsigned)g.nz;
+  for (unsigned i = blockIdx.x * kThreads + threadIdx.x; i < NP; i += gridDim.x * kThreads) {
+    int x, y, z;
+    mg_coords(i, g, x, y, z);
+    const bool f = !dir[i];
+    ax[i] = (f && x + 1 < g.nx && !dir[i + sx]) ? cx[i] : 0.0;
+    ay[i] = (f && y + 1 < g.ny && !dir[i + sy]) ? cy[i] : 0.0;
+    az[i] = (f && z + 1 < g.nz && !dir[i + 1]) ? cz[i] : 0.0;
+    double d = 0.0;
+    if (f) {
+      d = cx[i] + cy[i] + cz[i];
+      if (x > 0) d += cx[i - sx];
+      if (y > 0) d += cy[i - sy];
+      if (z > 0) d += cz[i - 1];
+    }
+    diag[i] = d;
+    dinv[i] = d > 0.0 ? 1.0 / d : 0.0;
+  }
+}
+
+// level k + 1 from level k (Galerkin with aggregation)
+__global__ void __launch_bounds__(kThreads)
+mg_coarsen_kernel(MGGeo f, MGGeo c, const double* __restrict__ fax,
+                  const double* __restrict__ fay, const double* __restrict__ faz,
+                  const double* __restrict__ fdiag, double* cax, double* cay, double* caz,
+                  double* cdiag, double* cdinv) {
+  const unsigned NC = (unsigned)c.nx * c.ny * c.nz;
+  for (unsigned I = blockIdx.x * kThreads + threadIdx.x; I < NC; I += gridDim.x * kThreads) {
+    int X, Y, Z;
+    mg_coords(I, c, X, Y, Z);
+    double d = 0.0, lx = 0.0, ly = 0.0, lz = 0.0;
+    for (int a = 0; a < 2; ++a)
+      for (int b = 0; b < 2; ++b)
+        for (int e = 0; e < 2; ++e) {
+          const int x = 2 * X + a, y = 2 * Y + b, z = 2 * Z + e;
+          if (x >= f.nx || y >= f.ny || z >= f.nz) continue;
+          const unsigned j = ((unsigned)x * f.ny + y) * f.nz + z;
+          d += fdiag[j];
+          if (x + 1 < f.nx) {
+            if (a == 0) d -= 2.0 * fax[j];   // link inside the aggregate
+            else lx += fax[j];               // link to the next aggregate along x
+          }
+          if (y + 1 < f.ny) {
+            if (b == 0) d -= 2.0 * fay[j];
+            else ly += fay[j];
+          }
+          if (z + 1 < f.nz) {
+            if (e == 0) d -= 2.0 * faz[j];
+            else lz += faz[j];
+          }
+        }
+    cax[I] = lx;
+    cay[I] = ly;
+    caz[I] = lz;
+    cdiag[I] = d;
+    cdinv[I] = d > 0.0 ? 1.0 / d : 0.0;
+  }
+}
+
+struct MGLevelArgs {
+  MGGeo g;
+  const double *ax, *ay, *az, *diag, *dinv;
+};
+
+// (A u)_j with u given by a functor of the node index
+template <typename F>
+__device__ __forceinline__ double mg_apply(unsigned j, int x, int y, int z, const MGLevelArgs& L,
+                                           double uj, F u) {
+  const unsigned sx = (unsigned)L.g.ny * L.g.nz, sy = (unsigned)L.g.nz;
+  double s = L.diag[j] * uj;
+  if (x + 1 < L.g.nx) s -= L.ax[j] * u(j + sx);
+  if (x > 0) s -= L.ax[j - sx] * u(j - sx);
+  if (y + 1 < L.g.ny) s -= L.ay[j] * u(j + sy);
+  if (y > 0) s -= L.ay[j - sy] * u(j - sy);
+  if (z + 1 < L.g.nz) s -= L.az[j] * u(j + 1);
+  if (z > 0) s -= L.az[j - 1] * u(j - 1);
+  return s;
+}
+
+// b_c[I] = sum over the children j of I of (b - A u)_j, u = w D^-1 b (pre-smoothing).
+// Eight consecutive lanes take the eight children of one coarse node (lane bits
+// 2, 1, 0 = x, y, z offsets) and sum them by shuffles, so the fine level runs one
+// node per thread.
+__global__ void __launch_bounds__(kThreads)
+mg_restrict_kernel(MGLevelArgs L, MGGeo c, double w, const double* __restrict__ b,
+                   long long b_stride, double* bc, long long bc_stride, const CGState* st) {
+  if (st[blockIdx.y].done) return;
+  b += blockIdx.y * b_stride;
+  bc += blockIdx.y * bc_stride;
+  const unsigned NC = (unsigned)c.nx * c.ny * c.nz;
+  auto u = [&](unsigned j) { return w * L.dinv[j] * b[j]; };
+  const unsigned ch = threadIdx.x & 7;
+  // trip counts are equal within each group of eight lanes (8 NC and the stride are
+  // multiples of eight), so every shuffle below sees its whole group
+  for (unsigned t = blockIdx.x * kThreads + threadIdx.x; t < 8 * NC; t += gridDim.x * kThreads) {
+    const unsigned I = t >> 3;
+    int X, Y, Z;
+    mg_coords(I, c, X, Y, Z);
+    const int x = 2 * X + (int)(ch >> 2), y = 2 * Y + (int)((ch >> 1) & 1),
+              z = 2 * Z + (int)(ch & 1);
+    double s = 0.0;
+    if (x < L.g.nx && y < L.g.ny && z < L.g.nz) {
+      const unsigned j = ((unsigned)x * L.g.ny + y) * L.g.nz + z;
+      if (L.dinv[j] != 0.0) s = b[j] - mg_apply(j, x, y, z, L, u(j), u);   // active node
+    }
+    s += __shfl_xor(s, 1, 8);
+    s += __shfl_xor(s, 2, 8);
+    s += __shfl_xor(s, 4, 8);
+    if (ch == 0) bc[I] = s;
+  }
+}
+
+// the coarsest level: sweeps (even) damped-Jacobi sweeps from zero, one workgroup
+__global__ void __launch_bounds__(kMGCoarsest)
+mg_coarsest_kernel(MGLevelArgs L, double w, int sweeps, const double* __restrict__ b,
+                   long long b_stride, double* u_out, long long u_stride, const CGState* st) {
+  if (st[blockIdx.y].done) return;
+  b += blockIdx.y * b_stride;
+  u_out += blockIdx.y * u_stride;
+  __shared__ double u[2][kMGCoarsest];
+  const unsigned n = (unsigned)L.g.nx * L.g.ny * L.g.nz;
+  const unsigned j = threadIdx.x;
+  // this node's row in registers: neighbour indices and weights (0 past the box)
+  unsigned nb[6] = {j, j, j, j, j, j};
+  double wt[6] = {0, 0, 0, 0, 0, 0}, dg = 0.0, wd = 0.0, bj = 0.0;
+  if (j < n) {
+    int x, y, z;
+    mg_coords(j, L.g, x, y, z);
+    const unsigned sx = (unsigned)L.g.ny * L.g.nz, sy = (unsigned)L.g.nz;
+    if (x + 1 < L.g.nx) { nb[0] = j + sx; wt[0] = L.ax[j]; }
+    if (x > 0) { nb[1] = j - sx; wt[1] = L.ax[j - sx]; }
+    if (y + 1 < L.g.ny) { nb[2] = j + sy; wt[2] = L.ay[j]; }
+    if (y > 0) { nb[3] = j - sy; wt[3] = L.ay[j - sy]; }
+    if (z + 1 < L.g.nz) { nb[4] = j + 1; wt[4] = L.az[j]; }
+    if (z > 0) { nb[5] = j - 1; wt[5] = L.az[j - 1]; }
+    dg = L.diag[j];
+    wd = w * L.dinv[j];
+    bj = b[j];
+  }
+  u[0][j] = 0.0;
+  __syncthreads();
+  for (int k = 0; k < sweeps; ++k) {
+    const double* uo = u[k & 1];
+    if (j < n) {
+      const double uj = uo[j];
+      double r = bj - dg * uj;
+#pragma unroll
+      for (int q = 0; q < 6; ++q) r += wt[q] * uo[nb[q]];
+      u[(k + 1) & 1][j] = uj + wd * r;
+    }
+    __syncthreads();
+  }
+  if (j < n) u_out[j] = u[sweeps & 1][j];
+}
+
+// u' = w D^-1 b + alpha P e (the pre-smoothed u plus the prolonged correction),
+// then one damped-Jacobi sweep: out = u' + w D^-1 (b - A u').  On level 0, out is
+// the CG's z and the partial sums of r.z go to partial_rz.
+template <bool FINEST>
+__global__ void __launch_bounds__(kThreads)
+mg_correct_kernel(MGLevelArgs L, MGGeo c, double w, double alpha, const double* __restrict__ b,
+                  long long b_stride, const double* __restrict__ e, long long e_stride,
+                  double* out, long long out_stride, double* partial_rz, const CGState* st) {
+  if (st[blockIdx.y].done) return;
+  b += blockIdx.y * b_stride;
+  e += blockIdx.y * e_stride;
+  out += blockIdx.y * out_stride;
+  const unsigned N = (unsigned)L.g.nx * L.g.ny * L.g.nz;
+  const unsigned sxc = (unsigned)c.ny * c.nz, sx = (unsigned)L.g.ny * L.g.nz,
+                 sy = (unsigned)L.g.nz;
+  // u' at node j with coordinates (x, y, z)
+  auto up = [&](unsigned j, int x, int y, int z) {
+    const unsigned P = (unsigned)(x >> 1) * sxc + (unsigned)(y >> 1) * c.nz + (unsigned)(z >> 1);
+    const double dj = L.dinv[j];
+    return dj == 0.0 ? 0.0 : w * dj * b[j] + alpha * e[P];
+  };
+  double acc[1] = {0.0};
+  for (unsigned j = blockIdx.x * kThreads + threadIdx.x; j < N; j += gridDim.x * kThreads) {
+    double o = 0.0;
+    if (L.dinv[j] != 0.0) {
+      int x, y, z;
+      mg_coords(j, L.g, x, y, z);
+      const double uj = up(j, x, y, z);
+      double au = L.diag[j] * uj;
+      if (x + 1 < L.g.nx) au -= L.ax[j] * up(j + sx, x + 1, y, z);
+      if (x > 0) au -= L.ax[j - sx] * up(j - sx, x - 1, y, z);
+      if (y + 1 < L.g.ny) au -= L.ay[j] * up(j + sy, x, y + 1, z);
+      if (y > 0) au -= L.ay[j - sy] * up(j - sy, x, y - 1, z);
+      if (z + 1 < L.g.nz) au -= L.az[j] * up(j + 1, x, y, z + 1);
+      if (z > 0) au -= L.az[j - 1] * up(j - 1, x, y, z - 1);
+      o = uj + w * L.dinv[j] * (b[j] - au);
+    }
+    out[j] = o;
+    if (FINEST) acc[0] += b[j] * o;
+  }
+  if (FINEST) block_sums<1>(acc, partial_rz + (long long)blockIdx.y * gridDim.x + blockIdx.x);
 }
 
 // ---------------------------------------------------------------------------
@@ -741,15 +1004,110 @@ hipError_t launch_cg_iter(const PGeom& g, const double* cx, const double* cy, co
                           const double* dinv, const uint8_t* dir, double* z,
                           const double* p_old, double* p_new, double* q, double* phi,
                           double* r, double* partial, int max_iter, CGState* st,
-                          hipStream_t s, int nrhs) {
+                          hipStream_t s, int nrhs, const MGData* mg) {
   const int nb = sp_blocks(g.NP);
   cg_matvec_kernel<<<dim3(nb, nrhs), kThreads, 0, s>>>((unsigned)g.NP, g.px, g.py, g.pz, 1.0 / g.py,
                                            1.0 / g.pz, cx, cy, cz, dir, z, p_old, p_new, q,
                                            partial, st);
   cg_alpha_kernel<<<dim3(1, nrhs), kRedThreads, 0, s>>>(partial, nb, st);
-  cg_update_kernel<<<dim3(nb, nrhs), kThreads, 0, s>>>(g.NP, dinv, p_new, q, phi, r, z, partial,
-                                                       st);
-  cg_beta_kernel<<<dim3(1, nrhs), kRedThreads, 0, s>>>(partial, nb, max_iter, st);
+  if (!mg) {
+    cg_update_kernel<true><<<dim3(nb, nrhs), kThreads, 0, s>>>(g.NP, dinv, p_new, q, phi, r, z,
+                                                               partial, st);
+    cg_beta_kernel<<<dim3(1, nrhs), kRedThreads, 0, s>>>(partial, nb, max_iter, st);
+    return hipGetLastError();
+  }
+  cg_update_kernel<false><<<dim3(nb, nrhs), kThreads, 0, s>>>(g.NP, dinv, p_new, q, phi, r, z,
+                                                              partial, st);
+  const hipError_t e = launch_mg_vcycle(g, *mg, r, z, st, nrhs, s);
+  if (e != hipSuccess) return e;
+  cg_beta_mg_kernel<<<dim3(1, nrhs), kRedThreads, 0, s>>>(partial, mg->partial_rz, nb, max_iter,
+                                                          st);
+  return hipGetLastError();
+}
+
+MGPlan mg_plan(const PGeom& g) {
+  MGPlan P{};
+  int nx = g.px, ny = g.py, nz = g.pz;
+  long long off = 0, voff = 0;
+  for (int k = 0; k < kMGMaxLevels; ++k) {
+    MGLevel& L = P.lv[k];
+    L.nx = nx;
+    L.ny = ny;
+    L.nz = nz;
+    L.N = (long long)nx * ny * nz;
+    L.off = off;
+    L.voff = k == 0 ? 0 : voff;
+    off += L.N;
+    if (k > 0) voff += L.N;
+    P.nlev = k + 1;
+    if ((k > 0 && L.N <= kMGCoarsest) || (nx == 1 && ny == 1 && nz == 1 && k > 0)) break;
+    nx = (nx + 1) / 2;
+    ny = (ny + 1) / 2;
+    nz = (nz + 1) / 2;
+  }
+  P.total = off;
+  P.vtotal = voff;
+  return P;
+}
+
+namespace {
+MGGeo mgeo(const MGLevel& L) { return MGGeo{L.nx, L.ny, L.nz, 1.0 / L.ny, 1.0 / L.nz}; }
+MGLevelArgs margs(const MGData& m, int k) {
+  const MGLevel& L = m.plan.lv[k];
+  return MGLevelArgs{mgeo(L), m.ax + L.off, m.ay + L.off, m.az + L.off, m.diag + L.off,
+                     m.dinv + L.off};
+}
+unsigned mg_blocks(long long n) { return (unsigned)sp_blocks(n); }
+}  // namespace
+
+hipError_t launch_mg_setup(const PGeom& g, const double* cx, const double* cy, const double* cz,
+                           const uint8_t* dir, const MGData& m, hipStream_t s) {
+  const MGPlan& P = m.plan;
+  if (P.lv[P.nlev - 1].N > kMGCoarsest || P.nlev < 2) return hipErrorInvalidValue;
+  mg_level0_kernel<<<mg_blocks(g.NP), kThreads, 0, s>>>((unsigned)g.NP, mgeo(P.lv[0]), cx, cy,
+                                                        cz, dir, m.ax, m.ay, m.az, m.diag,
+                                                        m.dinv);
+  for (int k = 0; k + 1 < P.nlev; ++k) {
+    const MGLevel &F = P.lv[k], &C = P.lv[k + 1];
+    mg_coarsen_kernel<<<mg_blocks(C.N), kThreads, 0, s>>>(
+        mgeo(F), mgeo(C), m.ax + F.off, m.ay + F.off, m.az + F.off, m.diag + F.off, m.ax + C.off,
+        m.ay + C.off, m.az + C.off, m.diag + C.off, m.dinv + C.off);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_mg_vcycle(const PGeom& g, const MGData& m, const double* r, double* z,
+                            const CGState* st, int nrhs, hipStream_t s) {
+  const MGPlan& P = m.plan;
+  const int L = P.nlev - 1;
+  const long long vs = P.vtotal;
+  auto bvec = [&](int k) { return k == 0 ? r : m.b + P.lv[k].voff; };
+  for (int k = 0; k < L; ++k) {
+    const MGLevel& C = P.lv[k + 1];
+    mg_restrict_kernel<<<dim3(mg_blocks(8 * C.N), nrhs), kThreads, 0, s>>>(
+        margs(m, k), mgeo(C), kMGOmega, bvec(k), k == 0 ? g.NP : vs, m.b + C.voff, vs, st);
+  }
+  mg_coarsest_kernel<<<dim3(1, nrhs), kMGCoarsest, 0, s>>>(margs(m, L), kMGOmega,
+                                                           kMGCoarseSweeps, m.b + P.lv[L].voff,
+                                                           vs, m.u + P.lv[L].voff, vs, st);
+  for (int k = L - 1; k >= 1; --k) {
+    const MGLevel &F = P.lv[k], &C = P.lv[k + 1];
+    mg_correct_kernel<false><<<dim3(mg_blocks(F.N), nrhs), kThreads, 0, s>>>(
+        margs(m, k), mgeo(C), kMGOmega, 1.0, m.b + F.voff, vs, m.u + C.voff, vs, m.u + F.voff,
+        vs, nullptr, st);
+  }
+  const MGLevel& C1 = P.lv[1];
+  mg_correct_kernel<true><<<dim3(sp_blocks(g.NP), nrhs), kThreads, 0, s>>>(
+      margs(m, 0), mgeo(C1), kMGOmega, kMGAlpha, r, g.NP, m.u + C1.voff, vs, z, g.NP,
+      m.partial_rz, st);
+  return hipGetLastError();
+}
+
+hipError_t launch_mg_start(const PGeom& g, const MGData& m, const double* r, double* z,
+                           CGState* st, int nrhs, hipStream_t s) {
+  const hipError_t e = launch_mg_vcycle(g, m, r, z, st, nrhs, s);
+  if (e != hipSuccess) return e;
+  cg_rz_kernel<<<dim3(1, nrhs), kRedThreads, 0, s>>>(m.partial_rz, sp_blocks(g.NP), st);
   return hipGetLastError();
 }
 

@@ -4,6 +4,7 @@
 // and reads back one convergence scalar per conjugate-gradient chunk and per
 // loop iteration.
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <cmath>
 #include <string>
@@ -39,11 +40,14 @@ struct Carve {
 struct PoissonWS {
   double *cx, *cy, *cz, *dinv, *r, *z, *p0, *p1, *q, *partial, *n_dir;
   CGState* st;
+  MGData mg;
 };
 
-// coefficients once; CG vectors and states for nrhs systems solved together
-PoissonWS carve_poisson(Carve& c, long long NP, int nrhs = 1) {
+// coefficients once; CG vectors and states for nrhs systems solved together; the
+// multigrid levels (used unless the Jacobi preconditioner is selected)
+PoissonWS carve_poisson(Carve& c, const PGeom& g, int nrhs = 1) {
   PoissonWS w;
+  const long long NP = g.NP;
   const size_t nv = (size_t)nrhs * NP;
   w.cx = c.take<double>(NP);
   w.cy = c.take<double>(NP);
@@ -57,8 +61,20 @@ PoissonWS carve_poisson(Carve& c, long long NP, int nrhs = 1) {
   w.partial = c.take<double>(sp_partial_doubles(nrhs));
   w.n_dir = c.take<double>(1);
   w.st = c.take<CGState>(nrhs);
+  MGData& m = w.mg;
+  m.plan = mg_plan(g);
+  m.ax = c.take<double>(m.plan.total);
+  m.ay = c.take<double>(m.plan.total);
+  m.az = c.take<double>(m.plan.total);
+  m.diag = c.take<double>(m.plan.total);
+  m.dinv = c.take<double>(m.plan.total);
+  m.b = c.take<double>((size_t)nrhs * m.plan.vtotal);
+  m.u = c.take<double>((size_t)nrhs * m.plan.vtotal);
+  m.partial_rz = c.take<double>(sp_partial_doubles(nrhs));
   return w;
 }
+
+std::atomic<int> g_precond{HKP_PRECOND_MULTIGRID};
 
 PGeom geom(const hkp_pgrid& pg) {
   return PGeom{pg.px, pg.py, pg.pz, (long long)pg.px * pg.py * pg.pz};
@@ -75,6 +91,8 @@ int poisson_prepare(const PGeom& g, double h, const double* eps, const uint8_t* 
     set_error("the Poisson box has no electrode (Dirichlet) node");
     return HKP_E_ARG;
   }
+  if (g_precond.load() == HKP_PRECOND_MULTIGRID)
+    HKP_CHECK(launch_mg_setup(g, w.cx, w.cy, w.cz, dir, w.mg, s));
   return HKP_OK;
 }
 
@@ -87,6 +105,7 @@ struct CGGraph {
   const double* phi = nullptr;
   int max_iter = -1;
   int nrhs = 0;
+  int precond = -1;
   void reset() {
     if (exec) (void)hipGraphExecDestroy(exec);
     if (graph) (void)hipGraphDestroy(graph);
@@ -96,15 +115,17 @@ struct CGGraph {
   ~CGGraph() { reset(); }
 };
 
-constexpr int kCGChunk = 32;   // even: every chunk starts from the same direction buffer
+// iterations per chunk, even (every chunk starts from the same direction buffer): a
+// multigrid-preconditioned solve needs tens of iterations, a Jacobi one hundreds
+int cg_chunk(bool mg) { return mg ? 8 : 32; }
 
 void launch_cg_chunk(const PGeom& g, const uint8_t* dir, double* phi, int max_iter,
-                     const PoissonWS& w, hipStream_t s, int nrhs) {
-  for (int c = 0; c < kCGChunk; ++c) {
+                     const PoissonWS& w, hipStream_t s, int nrhs, bool mg) {
+  for (int c = 0; c < cg_chunk(mg); ++c) {
     double* po = (c % 2 == 0) ? w.p0 : w.p1;
     double* pn = (c % 2 == 0) ? w.p1 : w.p0;
     HKP_CHECK(launch_cg_iter(g, w.cx, w.cy, w.cz, w.dinv, dir, w.z, po, pn, w.q, phi, w.r,
-                             w.partial, max_iter, w.st, s, nrhs));
+                             w.partial, max_iter, w.st, s, nrhs, mg ? &w.mg : nullptr));
   }
 }
 
@@ -114,14 +135,18 @@ void launch_cg_chunk(const PGeom& g, const uint8_t* dir, double* phi, int max_it
 int poisson_cg(const PGeom& g, const uint8_t* dir, const double* phi_fixed, const double* rho,
                double* phi, double tol, int max_iter, const PoissonWS& w, hipStream_t s,
                int* iters, double* relres, CGGraph* gc = nullptr, int nrhs = 1) {
+  const int precond = g_precond.load();
+  const bool mg = precond == HKP_PRECOND_MULTIGRID;
   HKP_CHECK(launch_cg_init(g, w.cx, w.cy, w.cz, w.dinv, dir, phi_fixed, rho, kEoverEps0, phi,
                            w.r, w.z, w.p0, w.partial, tol, w.st, s, nrhs));
+  if (mg) HKP_CHECK(launch_mg_start(g, w.mg, w.r, w.z, w.st, nrhs, s));
   if (gc && s != nullptr &&
-      (gc->phi != phi || gc->max_iter != max_iter || gc->nrhs != nrhs || !gc->exec)) {
+      (gc->phi != phi || gc->max_iter != max_iter || gc->nrhs != nrhs ||
+       gc->precond != precond || !gc->exec)) {
     gc->reset();
     HKP_CHECK(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
     try {
-      launch_cg_chunk(g, dir, phi, max_iter, w, s, nrhs);
+      launch_cg_chunk(g, dir, phi, max_iter, w, s, nrhs, mg);
     } catch (...) {
       hipGraph_t g2 = nullptr;
       (void)hipStreamEndCapture(s, &g2);
@@ -133,6 +158,7 @@ int poisson_cg(const PGeom& g, const uint8_t* dir, const double* phi_fixed, cons
     gc->phi = phi;
     gc->max_iter = max_iter;
     gc->nrhs = nrhs;
+    gc->precond = precond;
   }
   const bool use_graph = gc && s != nullptr && gc->exec;
   std::vector<CGState> h((size_t)nrhs);
@@ -146,8 +172,8 @@ int poisson_cg(const PGeom& g, const uint8_t* dir, const double* phi_fixed, cons
     if (use_graph)
       HKP_CHECK(hipGraphLaunch(gc->exec, s));
     else
-      launch_cg_chunk(g, dir, phi, max_iter, w, s, nrhs);
-    launched += kCGChunk;
+      launch_cg_chunk(g, dir, phi, max_iter, w, s, nrhs, mg);
+    launched += cg_chunk(mg);
   }
   // the worst system: most iterations, largest relative residual
   int it = 0, rc = HKP_OK;
@@ -173,9 +199,11 @@ double seconds_since(std::chrono::steady_clock::time_point t0) {
 
 }  // namespace
 
+int set_poisson_precond(int kind) { return g_precond.exchange(kind); }
+
 size_t poisson_bytes(const hkp_pgrid& pg) {
   Carve c{nullptr};
-  carve_poisson(c, geom(pg).NP);
+  carve_poisson(c, geom(pg));
   return c.off;
 }
 
@@ -183,7 +211,7 @@ int run_poisson(const PoissonArgs& a, int* iters, double* relres) {
   const PGeom g = geom(a.pg);
   hipStream_t s = reinterpret_cast<hipStream_t>(a.stream);
   Carve c{reinterpret_cast<char*>(a.workspace)};
-  const PoissonWS w = carve_poisson(c, g.NP);
+  const PoissonWS w = carve_poisson(c, g);
   const int rc = poisson_prepare(g, a.h, a.eps, a.dir, w, s);
   if (rc != HKP_OK) return rc;
   CGGraph gc;
@@ -214,7 +242,7 @@ SPLayout carve_sp(char* base, const Plan& p, const hkp_pgrid& pg, int m) {
   L.resid = c.take<double>(p.nb);
   L.f = c.take<double>(p.nb);
   L.mu = c.take<double>(1);
-  L.pw = carve_poisson(c, NP);
+  L.pw = carve_poisson(c, geom(pg));
   L.phi_out = c.take<double>(NP);
   L.rho = c.take<double>(NP);
   L.F = c.take<double>(NP);
@@ -412,7 +440,7 @@ CILayout carve_ci(char* base, const hkp_grid& g, int M, const hkp_pgrid& pg) {
   Carve c{base};
   const long long NP = geom(pg).NP, NS = (long long)g.nx * g.ny * g.nz;
   const int P = M * (M + 1) / 2, K = M * (2 * M - 1);
-  L.pw = carve_poisson(c, NP, 2 * P);
+  L.pw = carve_poisson(c, geom(pg), 2 * P);
   L.rhs = c.take<double>((size_t)2 * P * NP);
   L.V = c.take<double>((size_t)2 * P * NP);
   L.comp = c.take<double>((size_t)2 * 3 * M * NS);

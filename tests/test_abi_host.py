@@ -248,3 +248,26 @@ def test_spin_free_entry_points_reject_bad_arguments():
     assert L.lib.hkp_solve(C.byref(g), C.byref(m), C.byref(o), fake, None, B, None, fake, None,
                            None, fake, 1 << 40, None, C.byref(st)) == L.HKP_E_ARG
     assert b"B = 0" in L.lib.hkp_last_error()
+
+
+def test_poisson_preconditioner_choice_and_gmatrix_validation():
+    """The preconditioner switch returns the previous choice and rejects unknown kinds;
+    the g-matrix and two-spin-model entry points validate before any GPU work."""
+    L, g, m, o = _structs()
+    assert L.lib.hkp_poisson_preconditioner(L.HKP_PRECOND_JACOBI) == L.HKP_PRECOND_MULTIGRID
+    assert L.lib.hkp_poisson_preconditioner(L.HKP_PRECOND_MULTIGRID) == L.HKP_PRECOND_JACOBI
+    assert L.lib.hkp_poisson_preconditioner(7) == L.HKP_E_ARG
+    assert L.lib.hkp_poisson_preconditioner(L.HKP_PRECOND_MULTIGRID) == L.HKP_PRECOND_MULTIGRID
+    need = L.lib.hkp_gmatrix_workspace_bytes(C.byref(g))
+    assert need >= 44 * 6 * g.nx * g.ny * g.nz * 16
+    fake = C.c_void_p(0x1000)
+    assert L.lib.hkp_gmatrix(C.byref(g), C.byref(m), None, None, fake, fake, fake,
+                             C.c_size_t(need), None) == L.HKP_E_ARG
+    assert L.lib.hkp_gmatrix(C.byref(g), C.byref(m), fake, None, fake, fake, fake,
+                             C.c_size_t(need - 1), None) == L.HKP_E_WORKSPACE
+    opts = L.hkp_st_opts((C.c_double * 3)(0.0, 0.0, 1.0), 50.0, 0.0)
+    assert L.lib.hkp_st_model(fake, fake, C.byref(opts), 0, fake, fake, None, None) == L.HKP_E_ARG
+    for bad in (L.hkp_st_opts((C.c_double * 3)(0.0, 0.0, 0.0), 50.0, 0.0),
+                L.hkp_st_opts((C.c_double * 3)(0.0, 0.0, 1.0), 0.0, 0.0),
+                L.hkp_st_opts((C.c_double * 3)(0.0, 0.0, 1.0), float("nan"), 0.0)):
+        assert L.lib.hkp_st_model(fake, fake, C.byref(bad), 4, fake, fake, None, None) == L.HKP_E_ARG

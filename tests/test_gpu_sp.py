@@ -55,6 +55,37 @@ def test_poisson_vs_oracle(shape):
     assert it_e == it and np.array_equal(phi_e.cpu().numpy(), phi.cpu().numpy())
 
 
+@pytest.mark.parametrize("case", ["random_17x13x11", "sp_dqd_small"])
+def test_poisson_multigrid_and_jacobi_preconditioners(case):
+    """Both preconditioners reach the oracle's direct solution; the multigrid cycle
+    does so in a fraction of the iterations."""
+    import paper_2607_08447_amd as hkp
+    if case == "sp_dqd_small":
+        d = sp_device("sp_dqd_small")
+        x = np.arange(d.pshape[0])[:, None, None]
+        rho = 1e-3 * np.exp(-((x - d.pshape[0] / 3) / 5.0) ** 2) * np.ones(d.pshape)
+        shape, h, eps, dirichlet, phi_fixed = d.pshape, d.h, d.eps_r, d.dirichlet, d.phi_fixed
+    else:
+        shape, h = (17, 13, 11), 0.4
+        eps, dirichlet, phi_fixed, rho = _random_box(shape, 5)
+    ref = poisson_solve(shape, h, eps, dirichlet, phi_fixed, rho)
+    out = {}
+    prev = hkp.poisson_preconditioner("jacobi")
+    try:
+        for kind in ("jacobi", "multigrid"):
+            hkp.poisson_preconditioner(kind)
+            print(f"poisson {case} {kind}", flush=True)
+            phi, it, rel, code = hkp.poisson(_t(eps), _t(dirichlet), _t(phi_fixed), _t(rho), h,
+                                             tol=1e-13)
+            assert code == 0 and rel <= 1e-13
+            assert np.abs(phi.cpu().numpy() - ref).max() <= 1e-9 * max(1.0, np.abs(ref).max())
+            out[kind] = it
+    finally:
+        hkp.poisson_preconditioner(prev)
+    print(f"iterations {out}", flush=True)
+    assert out["multigrid"] * 3 <= out["jacobi"]
+
+
 def test_poisson_warm_start_and_no_charge():
     """Started from the solution, CG stops at once; without charge the solution
     is the Laplace potential of the electrodes."""
@@ -95,6 +126,7 @@ def test_poisson_full_box_properties():
                                      tol=1e-12)
     assert code == 0, (it, rel)
     print(f"cg iterations {it}, |r|/|b| {rel:.2e}", flush=True)
+    assert it <= 150   # multigrid-preconditioned (Jacobi alone needs about 1000 here)
     p = phi.cpu().numpy().ravel()
     Lop = poisson_operator(d.pshape, d.h, d.eps_r)
     dmask = d.dirichlet.ravel() == 1
