@@ -380,7 +380,7 @@ mg_level0_kernel(unsigned NP, MGGeo g, const double* __restrict__ cx,
                  const uint8_t* __restrict__ dir, double* ax, double* ay, double* az,
                  double* diag, double* dinv) {
   const unsigned sx = (unsigned)g.ny * g.nz, sy = (unsigned)g.nz;
-  for (unsigned i = blockIdx.x * kThreads + threadIdx.x; i < NP; i += gridDim.x * kThreads) {
+  for (unsigned i = xcd_remap(blockIdx.x, gridDim.x) * kThreads + threadIdx.x; i < NP; i += gridDim.x * kThreads) {
     int x, y, z;
     mg_coords(i, g, x, y, z);
     const bool f = !dir[i];
@@ -406,7 +406,7 @@ mg_coarsen_kernel(MGGeo f, MGGeo c, const double* __restrict__ fax,
                   const double* __restrict__ fdiag, double* cax, double* cay, double* caz,
                   double* cdiag, double* cdinv) {
   const unsigned NC = (unsigned)c.nx * c.ny * c.nz;
-  for (unsigned I = blockIdx.x * kThreads + threadIdx.x; I < NC; I += gridDim.x * kThreads) {
+  for (unsigned I = xcd_remap(blockIdx.x, gridDim.x) * kThreads + threadIdx.x; I < NC; I += gridDim.x * kThreads) {
     int X, Y, Z;
     mg_coords(I, c, X, Y, Z);
     double d = 0.0, lx = 0.0, ly = 0.0, lz = 0.0;
@@ -461,7 +461,8 @@ __device__ __forceinline__ double mg_apply(unsigned j, int x, int y, int z, cons
 // b_c[I] = sum over the children j of I of (b - A u)_j, u = w D^-1 b (pre-smoothing).
 // Eight consecutive lanes take the eight children of one coarse node (lane bits
 // 2, 1, 0 = x, y, z offsets) and sum them by shuffles, so the fine level runs one
-// node per thread.
+// node per thread.  Like the other level kernels it gives every XCD a contiguous
+// run of nodes (the x- and y-neighbours a node reads are then in that XCD's L2).
 __global__ void __launch_bounds__(kThreads)
 mg_restrict_kernel(MGLevelArgs L, MGGeo c, double w, const double* __restrict__ b,
                    long long b_stride, double* bc, long long bc_stride, const CGState* st) {
@@ -473,7 +474,7 @@ mg_restrict_kernel(MGLevelArgs L, MGGeo c, double w, const double* __restrict__ 
   const unsigned ch = threadIdx.x & 7;
   // trip counts are equal within each group of eight lanes (8 NC and the stride are
   // multiples of eight), so every shuffle below sees its whole group
-  for (unsigned t = blockIdx.x * kThreads + threadIdx.x; t < 8 * NC; t += gridDim.x * kThreads) {
+  for (unsigned t = xcd_remap(blockIdx.x, gridDim.x) * kThreads + threadIdx.x; t < 8 * NC; t += gridDim.x * kThreads) {
     const unsigned I = t >> 3;
     int X, Y, Z;
     mg_coords(I, c, X, Y, Z);
@@ -556,7 +557,7 @@ mg_correct_kernel(MGLevelArgs L, MGGeo c, double w, double alpha, const double* 
     return dj == 0.0 ? 0.0 : w * dj * b[j] + alpha * e[P];
   };
   double acc[1] = {0.0};
-  for (unsigned j = blockIdx.x * kThreads + threadIdx.x; j < N; j += gridDim.x * kThreads) {
+  for (unsigned j = xcd_remap(blockIdx.x, gridDim.x) * kThreads + threadIdx.x; j < N; j += gridDim.x * kThreads) {
     double o = 0.0;
     if (L.dinv[j] != 0.0) {
       int x, y, z;
