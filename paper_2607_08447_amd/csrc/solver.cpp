@@ -545,7 +545,10 @@ int run_solve(const SolveArgs& A, hkp_stats* stats) {
 
   // ---- spectral bound
   std::vector<double> bup;
-  lanczos_bounds(c, bup);
+  if (A.bound_hint > 0.0 && p.batch == 1)
+    bup.assign(1, A.bound_hint);
+  else
+    lanczos_bounds(c, bup);
   {
     std::vector<double> hb(4 * (size_t)p.batch, 0.0);
     for (int b = 0; b < p.batch; ++b) hb[4 * b] = bup[b];

@@ -51,6 +51,9 @@ struct SolveArgs {
   unsigned long long seed;
   StencilTune st;
   int graph_chunk;  // iterations per recorded graph
+  // > 0: an upper bound of the spectrum of H (one Hamiltonian), used instead of
+  // the Lanczos estimate (the self-consistent loop carries it across iterations)
+  double bound_hint = 0.0;
 };
 
 struct FilterArgs {

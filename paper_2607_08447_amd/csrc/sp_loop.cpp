@@ -224,7 +224,7 @@ namespace {
 struct SPLayout {
   size_t solver;   // eigensolver workspace (first, at offset 0)
   double2* block;  // [nb][nx][ny][nz][6] ABI spinors: restart block and psi
-  double *V, *eig, *resid, *f, *mu;
+  double *V, *Vref, *dV, *eig, *resid, *f, *mu;
   PoissonWS pw;
   double *phi_out, *rho, *F, *histX, *histF, *G, *dots, *gamma, *delta;
   size_t total;
@@ -238,6 +238,8 @@ SPLayout carve_sp(char* base, const Plan& p, const hkp_pgrid& pg, int m) {
   const long long NP = geom(pg).NP;
   L.block = c.take<double2>((size_t)p.nb * p.n6);
   L.V = c.take<double>(p.N);
+  L.Vref = c.take<double>(p.N);
+  L.dV = c.take<double>(1);
   L.eig = c.take<double>(p.nb);
   L.resid = c.take<double>(p.nb);
   L.f = c.take<double>(p.nb);
@@ -328,6 +330,7 @@ int run_sp(const SPArgs& a, hkp_sp_stats* stats) {
   // eigensolve goes to opts->tol (from the hole-free start, to 1e-4 eV)
   double delta = 0.0, delta_prev = (a.sp.flags & HKP_SP_PHI0) ? 0.0 : HUGE_VAL;
   int it = 0;
+  double bound = 0.0;   // the Lanczos upper spectral bound of H(V_ref)
   for (it = 1; it <= a.sp.max_iter; ++it) {
     // Schroedinger: V = V_off + phi on the embedded grid; restart from the last block.
     // Eigensolves stop at a residual tied to how far the potential still moves
@@ -335,6 +338,20 @@ int run_sp(const SPArgs& a, hkp_sp_stats* stats) {
     // the loop's own step while r <= 0.01 delta); the final pass uses opts->tol.
     auto t0 = std::chrono::steady_clock::now();
     HKP_CHECK(launch_extract(p.nx, p.ny, p.nz, g, ox, oy, oz, a.V_off, a.phi, L.V, s));
+    // only V changes between iterations: by Weyl's inequality the upper bound of the
+    // spectrum that the first solve's Lanczos run found, plus max |V - V_ref| (V_ref
+    // that solve's potential), bounds the new one; no Lanczos run after the first.
+    // (Adding each step's change to the last bound instead would grow with the path
+    // the loop takes, not with its distance from V_ref, and loosen the filter.)
+    sa.bound_hint = 0.0;
+    if (it > 1 && bound > 0.0) {
+      const PGeom gv{p.nx, p.ny, p.nz, p.N};   // elementwise over the Schroedinger grid
+      HKP_CHECK(launch_residual_max(gv, L.Vref, L.V, L.F, L.pw.partial, L.dV, s));
+      double dv = 0.0;
+      HKP_CHECK(hipMemcpyAsync(&dv, L.dV, sizeof(double), hipMemcpyDeviceToHost, s));
+      HKP_CHECK(hipStreamSynchronize(s));
+      if (std::isfinite(dv)) sa.bound_hint = bound + dv;
+    }
     sa.X0 = it > 1 ? L.block : nullptr;
     sa.flags = base_flags | (it > 1 ? HKP_FLAG_X0 : 0);
     sa.tol = (adaptive && !final_pass)
@@ -345,6 +362,11 @@ int run_sp(const SPArgs& a, hkp_sp_stats* stats) {
     if (rc < 0) return rc;
     if (rc != HKP_OK) st.solve_status = rc;
     st.schroedinger_iters += sst.iters;
+    if (sa.bound_hint == 0.0) {   // a Lanczos bound: the new reference
+      bound = sst.lambda_max_bound;
+      HKP_CHECK(hipMemcpyAsync(L.Vref, L.V, (size_t)p.N * sizeof(double),
+                               hipMemcpyDeviceToDevice, s));
+    }
     t_sch += seconds_since(t0);
 
     // occupancy, hole density, Poisson from the current potential
