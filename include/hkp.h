@@ -440,8 +440,8 @@ int hkp_poisson_preconditioner(int32_t kind);
 /* Workspace of hkp_poisson for this box. */
 size_t hkp_poisson_workspace_bytes(const hkp_pgrid* pgrid);
 
-/* One Poisson solve on the box (offsets unused): Jacobi-preconditioned
- * conjugate gradients from the guess in phi.
+/* One Poisson solve on the box (offsets unused): preconditioned conjugate
+ * gradients (hkp_poisson_preconditioner) from the guess in phi.
  *   eps_r, phi_fixed, rho  device double [px][py][pz] (rho may be NULL: 0)
  *   dirichlet  device uint8 [px][py][pz], 1 = electrode node; at least one
  *              (a box without one is reported as HKP_E_ARG after the

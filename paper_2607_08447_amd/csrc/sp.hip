@@ -1,6 +1,7 @@
 // Kernels of the self-consistent Schroedinger-Poisson loop (paper Sec. II.B,
 // Fig. 2a): the electrostatic potential from Poisson's equation by
-// Jacobi-preconditioned conjugate gradients, Fermi-Dirac occupancy of the hole
+// preconditioned conjugate gradients (a multigrid V-cycle, or the diagonal), the
+// configuration interaction's pair potentials, Fermi-Dirac occupancy of the hole
 // states, the hole density, and Anderson mixing of the potential.
 //
 // Poisson box layout (device, HBM): real [px][py][pz], x slowest and z fastest
