@@ -197,11 +197,14 @@ gram_herm_kernel(const double* A, long long a_bstride, int nba, const double* B,
 
 // General (non-Hermitian) Gram A^H B, balanced as above: the four waves split the
 // chunk into four runs and each computes every (A tile, B tile) pair of its run.
+// When A is the leading part of B, A's tiles are not loaded a second time.
 template <int NTA, int NTB>
 __global__ void __launch_bounds__(64 * 4)
 gram_gen_kernel(const double* A, long long a_bstride, int nba, const double* B,
                 long long b_bstride, int nbb, long long n, long long chunk, const int* active,
                 double* partial) {
+  // A is the leading part of B (the same vectors): its tiles come from B's loads
+  const bool a_is_b = A == B && a_bstride == b_bstride && nba <= nbb && NTA <= NTB;
   __shared__ double2 red[4][16][17];
   const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int b = blockIdx.y;
@@ -243,13 +246,14 @@ gram_gen_kernel(const double* A, long long a_bstride, int nba, const double* B,
     const bool eok = e < e1;
     double2 av[NTA], bv[NTB];
 #pragma unroll
-    for (int t = 0; t < NTA; ++t)
-      av[t] = (aok[t] && eok) ? *reinterpret_cast<const double2*>(pa[t] + 2 * e)
-                              : make_double2(0, 0);
-#pragma unroll
     for (int t = 0; t < NTB; ++t)
       bv[t] = (bok[t] && eok) ? *reinterpret_cast<const double2*>(pb[t] + 2 * e)
                               : make_double2(0, 0);
+#pragma unroll
+    for (int t = 0; t < NTA; ++t)
+      av[t] = a_is_b ? bv[t < NTB ? t : 0]
+                     : ((aok[t] && eok) ? *reinterpret_cast<const double2*>(pa[t] + 2 * e)
+                                        : make_double2(0, 0));
 #pragma unroll
     for (int ti = 0; ti < NTA; ++ti) {
 #pragma unroll

@@ -13,7 +13,7 @@
 // 16 against themselves, their images under H_0 and Z_b psi_i (16 x 44).  The
 // origin of each doublet's gauge is its own centre of charge, which enters the
 // small matrices only.  Everything after the Gram product is 4 x 4 algebra done
-// by one thread.
+// by a few threads of one workgroup.
 #include <hip/hip_runtime.h>
 
 #include "hkp_internal.h"
@@ -230,91 +230,111 @@ __device__ void sym_g(const double g[3][3], double out[3][3]) {
     }
 }
 
+// the doublet bases as columns over the four input states: bonding, antibonding,
+// then the localised left and right doublets (columns of C)
+__device__ void doublet_basis(int k, const double2 (&C)[4][4], double2 (&U)[4][2]) {
+  const double2 zero = make_double2(0.0, 0.0), one = make_double2(1.0, 0.0);
+  for (int i = 0; i < 4; ++i)
+    for (int m = 0; m < 2; ++m) U[i][m] = k < 2 ? ((i == 2 * k + m) ? one : zero) : C[i][2 * (k - 2) + m];
+}
+
+// Phases, one workgroup: thread 0 localises the dots (4 x 4 Jacobi); four threads
+// take the doublets' centres; twelve take one (doublet, field direction) column of
+// g each; four take the symmetric tensors.
 __global__ void gmatrix_post_kernel(const double2* __restrict__ Gg, hkp_gmatrix_result* out) {
   __shared__ double2 G[16 * 44];   // the whole Gram block, staged once by the workgroup
-  for (int i = threadIdx.x; i < 16 * 44; i += blockDim.x) G[i] = Gg[i];
+  __shared__ double2 sC[4][4];
+  __shared__ double sR0[4][3], sg[4][3][3];
+  const int t = threadIdx.x;
+  for (int i = t; i < 16 * 44; i += blockDim.x) G[i] = Gg[i];
   __syncthreads();
-  if (threadIdx.x != 0) return;
-  // the dots' doublets: eigenvectors of x within the span, lower x first
-  double2 Xx[4][4], C[4][4];
-  double wx[4];
-  for (int i = 0; i < 4; ++i)
-    for (int j = 0; j < 4; ++j) {
-      const double2 a = gX(G, 0, i, j), b = cconj(gX(G, 0, j, i));
-      Xx[i][j] = cscale(cadd(a, b), 0.5);
-    }
-  jacobi_herm<4>(Xx, C, wx);
-  for (int i = 0; i < 4; ++i) out->E_eV[i] = gW(G, 0, i, 0, i).x;
-  const double2 zero = make_double2(0.0, 0.0), one = make_double2(1.0, 0.0);
-  for (int k = 0; k < 4; ++k) {
-    // basis of doublet k as columns over the four input states
-    double2 U[4][2];
+  if (t == 0) {   // the dots' doublets: eigenvectors of x within the span, lower x first
+    double2 Xx[4][4], C[4][4];
+    double wx[4];
     for (int i = 0; i < 4; ++i)
-      for (int m = 0; m < 2; ++m) {
-        if (k < 2) U[i][m] = (i == 2 * k + m) ? one : zero;
-        else U[i][m] = C[i][2 * (k - 2) + m];
-      }
-    // centre of charge: tr(U^H X_a U) / 2
-    double r0[3];
+      for (int j = 0; j < 4; ++j)
+        Xx[i][j] = cscale(cadd(gX(G, 0, i, j), cconj(gX(G, 0, j, i))), 0.5);
+    jacobi_herm<4>(Xx, C, wx);
+    for (int i = 0; i < 4; ++i)
+      for (int j = 0; j < 4; ++j) sC[i][j] = C[i][j];
+    for (int i = 0; i < 4; ++i) out->E_eV[i] = gW(G, 0, i, 0, i).x;
+  }
+  __syncthreads();
+  if (t < 4) {   // centre of charge of doublet t: tr(U^H X_a U) / 2
+    double2 U[4][2];
+    doublet_basis(t, sC, U);
     for (int a = 0; a < 3; ++a) {
       double s = 0.0;
       for (int m = 0; m < 2; ++m)
         for (int i = 0; i < 4; ++i)
           for (int j = 0; j < 4; ++j) s += cmul(cconj(U[i][m]), cmul(gX(G, a, i, j), U[j][m])).x;
-      r0[a] = 0.5 * s;
-      out->centre_nm[k][a] = r0[a];
+      sR0[t][a] = 0.5 * s;
+      out->centre_nm[t][a] = 0.5 * s;
     }
-    double g[3][3];
-    for (int b = 0; b < 3; ++b) {
-      // D_b on the four states, gauge origin r0
-      double2 D[4][4];
-      for (int i = 0; i < 4; ++i)
-        for (int j = 0; j < 4; ++j) {
-          double2 orb = zero;
-          for (int c = 0; c < 3; ++c)
-            for (int d = 0; d < 3; ++d) {
-              const double e = levi(b, c, d);
-              if (e == 0.0) continue;
-              double2 w = gW(G, c + 1, i, d + 1, j);
-              w = csub(w, cscale(gW(G, 0, i, d + 1, j), r0[c]));
-              w = csub(w, cscale(gW(G, c + 1, i, 0, j), r0[d]));
-              orb = cadd(orb, cscale(w, e));
-            }
-          D[i][j] = cadd(gZ(G, b, i, j), cscale(times_i(orb), 0.5 * kEoverHbar));
-        }
-      // M_b = U^H D_b U
-      double2 M[2][2];
-      for (int m = 0; m < 2; ++m)
-        for (int n = 0; n < 2; ++n) {
-          double2 s = zero;
-          for (int i = 0; i < 4; ++i)
-            for (int j = 0; j < 4; ++j) s = cadd(s, cmul(cconj(U[i][m]), cmul(D[i][j], U[j][n])));
-          M[m][n] = s;
-        }
-      // g_ab = Re tr(sigma_a M_b) / mu_B: tr(sigma_x M) = M01 + M10,
-      // tr(sigma_y M) = i (M01 - M10), tr(sigma_z M) = M00 - M11
-      g[0][b] = (M[0][1].x + M[1][0].x) / kMuB;
-      g[1][b] = (M[1][0].y - M[0][1].y) / kMuB;
-      g[2][b] = (M[0][0].x - M[1][1].x) / kMuB;
-      out->kramers[k][b] = (M[0][0].x + M[1][1].x) / kMuB;
-    }
-    double gs[3][3];
+  }
+  __syncthreads();
+  if (t < 12) {   // column b of the g-matrix of doublet k
+    const int k = t / 3, b = t % 3;
+    double2 U[4][2];
+    doublet_basis(k, sC, U);
+    const double r0[3] = {sR0[k][0], sR0[k][1], sR0[k][2]};
+    // D_b on the four states, gauge origin r0
+    double2 D[4][4];
+    for (int i = 0; i < 4; ++i)
+      for (int j = 0; j < 4; ++j) {
+        double2 orb = make_double2(0.0, 0.0);
+        for (int c = 0; c < 3; ++c)
+          for (int d = 0; d < 3; ++d) {
+            const double e = levi(b, c, d);
+            if (e == 0.0) continue;
+            double2 w = gW(G, c + 1, i, d + 1, j);
+            w = csub(w, cscale(gW(G, 0, i, d + 1, j), r0[c]));
+            w = csub(w, cscale(gW(G, c + 1, i, 0, j), r0[d]));
+            orb = cadd(orb, cscale(w, e));
+          }
+        D[i][j] = cadd(gZ(G, b, i, j), cscale(times_i(orb), 0.5 * kEoverHbar));
+      }
+    // M_b = U^H D_b U
+    double2 M[2][2];
+    for (int m = 0; m < 2; ++m)
+      for (int n = 0; n < 2; ++n) {
+        double2 s2 = make_double2(0.0, 0.0);
+        for (int i = 0; i < 4; ++i)
+          for (int j = 0; j < 4; ++j) s2 = cadd(s2, cmul(cconj(U[i][m]), cmul(D[i][j], U[j][n])));
+        M[m][n] = s2;
+      }
+    // g_ab = Re tr(sigma_a M_b) / mu_B: tr(sigma_x M) = M01 + M10,
+    // tr(sigma_y M) = i (M01 - M10), tr(sigma_z M) = M00 - M11
+    sg[k][0][b] = (M[0][1].x + M[1][0].x) / kMuB;
+    sg[k][1][b] = (M[1][0].y - M[0][1].y) / kMuB;
+    sg[k][2][b] = (M[0][0].x - M[1][1].x) / kMuB;
+    out->kramers[k][b] = (M[0][0].x + M[1][1].x) / kMuB;
+  }
+  __syncthreads();
+  if (t < 4) {
+    double g[3][3], gs[3][3];
+    for (int a = 0; a < 3; ++a)
+      for (int b = 0; b < 3; ++b) g[a][b] = sg[t][a][b];
     sym_g(g, gs);
     for (int a = 0; a < 3; ++a)
       for (int b = 0; b < 3; ++b) {
-        out->g[k][a][b] = g[a][b];
-        out->g_sym[k][a][b] = gs[a][b];
+        out->g[t][a][b] = g[a][b];
+        out->g_sym[t][a][b] = gs[a][b];
       }
   }
-  const double delta = 0.5 * (out->E_eV[2] + out->E_eV[3]) - 0.5 * (out->E_eV[0] + out->E_eV[1]);
-  out->delta_eV = delta;
-  out->t_eV = fabs(delta) / sqrt(2.0);
-  double dd = 0.0;
-  for (int a = 0; a < 3; ++a) {
-    const double q = out->centre_nm[3][a] - out->centre_nm[2][a];
-    dd += q * q;
+  if (t == 0) {
+    double E[4];
+    for (int i = 0; i < 4; ++i) E[i] = gW(G, 0, i, 0, i).x;
+    const double delta = 0.5 * (E[2] + E[3]) - 0.5 * (E[0] + E[1]);
+    out->delta_eV = delta;
+    out->t_eV = fabs(delta) / sqrt(2.0);
+    double dd = 0.0;
+    for (int a = 0; a < 3; ++a) {
+      const double q = sR0[3][a] - sR0[2][a];
+      dd += q * q;
+    }
+    out->d_nm = sqrt(dd);
   }
-  out->d_nm = sqrt(dd);
 }
 
 // one thread per field: Eq. HB and the exchange in the qubit frames
