@@ -22,8 +22,10 @@ Pinning status (see tests/test_oracle_pins.py):
                                  Kramers degeneracy at B=0)
   * harmonic confinement       -- pinned (Richardson-extrapolated oscillator levels)
   * Hellmann-Feynman gradient  -- pinned (central finite differences)
-  * Zeeman sign convention and absolute g-factors -- parity unpinned against the
-    paper (the paper prints no Zeeman term); only the invariants above hold.
+  * Zeeman term -- its absolute g-factors are pinned by closed forms at one grid
+    point (heavy-hole doublet g = 6 kappa, split-off doublet 4 kappa - 2: the
+    Lande factors of 2 kappa mu_B B.J; tests/test_oracle_gmatrix.py); its form and
+    sign convention are a reading (the paper prints no Zeeman term).
   * g-matrices and the two-spin model (gmatrix.py) -- pinned (closed-form heavy-hole
     and split-off g at one grid point, Zeeman splitting of the full H(B), gauge-origin
     and basis invariance, mirror-image dots, the paper's t = Delta / sqrt(2) example,
