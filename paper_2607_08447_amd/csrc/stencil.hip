@@ -91,6 +91,29 @@ __device__ __forceinline__ void stg(void* base, long long idx, cx<T> v) {
   reinterpret_cast<typename V2<TW>::type*>(base)[idx] = o;
 }
 
+// Streams touched once per launch (the previous iterate, the output) go through
+// the cache with the non-temporal policy, so that they do not push the on-site
+// fields and the input rows, which later workgroups of the same XCD reuse, out
+// of the L2.
+typedef float nt_f2 __attribute__((ext_vector_type(2)));
+typedef double nt_d2 __attribute__((ext_vector_type(2)));
+template <typename T> struct NT2;
+template <> struct NT2<float> { using type = nt_f2; };
+template <> struct NT2<double> { using type = nt_d2; };
+template <typename T>
+__device__ __forceinline__ cx<T> ld_stream(const T* p) {
+  const typename NT2<T>::type v =
+      __builtin_nontemporal_load(reinterpret_cast<const typename NT2<T>::type*>(p));
+  return {v.x, v.y};
+}
+template <typename TW, typename T>
+__device__ __forceinline__ void stg_stream(void* base, long long idx, cx<T> v) {
+  typename NT2<TW>::type o;
+  o.x = static_cast<TW>(v.r);
+  o.y = static_cast<TW>(v.i);
+  __builtin_nontemporal_store(o, reinterpret_cast<typename NT2<TW>::type*>(base) + idx);
+}
+
 
 template <typename T>
 struct KArgs {
@@ -346,7 +369,7 @@ stencil_kernel(KArgs<T> a) {
     const unsigned o = (unsigned)z * nxy + col;
 #pragma unroll
     for (int i = 0; i < 3; ++i) {
-      cx<TO> q = ld(oldp + 2 * (size_t)((unsigned)i * N + o));
+      cx<TO> q = ld_stream(oldp + 2 * (size_t)((unsigned)i * N + o));
       oldv[i] = mk<T>((T)q.r, (T)q.i);
     }
   };
@@ -357,7 +380,7 @@ stencil_kernel(KArgs<T> a) {
     for (int i = 0; i < 3; ++i) {
       cx<T> r = scl(alpha, acc0[i]);
       if (has_old) r = fma_s(r, beta, oldv[i]);
-      stg<TW>(outp, (long long)((unsigned)i * N + o), r);
+      stg_stream<TW>(outp, (long long)((unsigned)i * N + o), r);
     }
   };
 
