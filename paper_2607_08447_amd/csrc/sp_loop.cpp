@@ -6,6 +6,8 @@
 #include <algorithm>
 #include <atomic>
 #include <chrono>
+#include <cstdio>
+#include <cstdlib>
 #include <cmath>
 #include <string>
 #include <vector>
@@ -331,6 +333,9 @@ int run_sp(const SPArgs& a, hkp_sp_stats* stats) {
   double delta = 0.0, delta_prev = (a.sp.flags & HKP_SP_PHI0) ? 0.0 : HUGE_VAL;
   int it = 0;
   double bound = 0.0;   // the Lanczos upper spectral bound of H(V_ref)
+  // HKP_SP_TRACE=1 prints one line per iteration to stderr (diagnostics)
+  const char* tr = std::getenv("HKP_SP_TRACE");
+  const bool trace = tr && tr[0] == '1';
   for (it = 1; it <= a.sp.max_iter; ++it) {
     // Schroedinger: V = V_off + phi on the embedded grid; restart from the last block.
     // Eigensolves stop at a residual tied to how far the potential still moves
@@ -395,6 +400,10 @@ int run_sp(const SPArgs& a, hkp_sp_stats* stats) {
       set_error("self-consistent loop diverged (non-finite potential update)");
       return HKP_E_NUMERICAL;
     }
+    if (trace)
+      std::fprintf(stderr, "[hkp sp] it %d  max|F| %.3e V  eig tol %.1e (%d iters)  cg tol %.1e "
+                   "(%d iters)  history %d\n", it, delta, sa.tol, sst.iters, cg_tol, cgit,
+                   std::min(count, m));
     if (delta <= a.sp.tol_V) {
       if (sa.tol <= a.opts.tol_eV && cg_tol <= a.sp.cg_tol) {
         converged = true;
