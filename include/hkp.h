@@ -94,11 +94,14 @@ typedef struct {
   double a_v_eV, b_eV, d_eV;
 } hkp_material;
 
-/* Solver options.  nb = 0 or degree = 0 selects the autotuned value. */
+/* Solver options.  nb = 0 selects the autotuned block size; degree = 0 the
+ * default degree schedule (16, then 32, then 64 in mixed precision or 96 in FP64
+ * over the first outer iterations). */
 typedef struct {
   int32_t nev;        /* eigenpairs wanted, 1 <= nev < nb */
   int32_t nb;         /* subspace block size, nev < nb <= HKP_NB_MAX, nb <= 6 N */
-  int32_t degree;     /* Chebyshev polynomial degree per outer iteration (2..200) */
+  int32_t degree;     /* Chebyshev polynomial degree per outer iteration, 0 or 1..200
+                         (an odd degree is raised to the next even one) */
   int32_t max_iter;   /* outer iterations before HKP_W_NOT_CONVERGED */
   double tol_eV;      /* convergence: ||H psi_n - E_n psi_n||_2 <= tol for n < nev */
   int32_t precision;  /* HKP_PREC_FP64 or HKP_PREC_MIXED */

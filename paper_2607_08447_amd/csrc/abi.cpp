@@ -81,7 +81,7 @@ int check_opts(const hkp_grid* g, const hkp_opts* o) {
     return HKP_E_ARG;
   }
   if (o->degree < 0 || o->degree > 200) {
-    set_error("degree must be 0 (auto) or 2..200");
+    set_error("degree must be 0 (default schedule) or 1..200");
     return HKP_E_ARG;
   }
   if (o->max_iter < 1) {

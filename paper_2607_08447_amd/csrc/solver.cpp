@@ -700,8 +700,15 @@ int run_solve(const SolveArgs& A, hkp_stats* stats) {
     // record a chunk of iterations once, replay until converged
     m_cur = p.degree;
     const int chunk = std::max(1, std::min(A.graph_chunk > 0 ? A.graph_chunk : 4, A.max_iter));
-    hipGraph_t graph = nullptr;
-    hipGraphExec_t exec = nullptr;
+    // destroyed on every exit, an error thrown by a replay included
+    struct Recorded {
+      hipGraph_t graph = nullptr;
+      hipGraphExec_t exec = nullptr;
+      ~Recorded() {
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (graph) (void)hipGraphDestroy(graph);
+      }
+    } rec;
     // byte accounting of a replay: the recorded chunk with every member active
     // and no vector locked (an upper estimate; the kernels skip on the device)
     const double bytes_before = sst.hx_bytes;
@@ -716,19 +723,17 @@ int run_solve(const SolveArgs& A, hkp_stats* stats) {
       if (g2) (void)hipGraphDestroy(g2);
       throw;
     }
-    HKP_CHECK(hipStreamEndCapture(c.s, &graph));
+    HKP_CHECK(hipStreamEndCapture(c.s, &rec.graph));
     const double chunk_bytes = sst.hx_bytes - bytes_before;
     sst.hx_bytes = bytes_before;
-    HKP_CHECK(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
+    HKP_CHECK(hipGraphInstantiate(&rec.exec, rec.graph, nullptr, nullptr, 0));
     while (iters < A.max_iter && !all_done()) {
       for (int k = 0; k < chunk; ++k) count_work();   // upper estimate per replay
       sst.hx_bytes += chunk_bytes;
-      HKP_CHECK(hipGraphLaunch(exec, c.s));
+      HKP_CHECK(hipGraphLaunch(rec.exec, c.s));
       iters += chunk;
       read_flags();
     }
-    (void)hipGraphExecDestroy(exec);
-    (void)hipGraphDestroy(graph);
   }
 
   // ---- outputs
