@@ -34,7 +34,8 @@ def _setup(name):
     return d, V
 
 
-@pytest.mark.parametrize("name,M", [("sp_tiny", 2), ("sp_tiny", 4), ("sp_dqd_small", 5)])
+@pytest.mark.parametrize("name,M", [("sp_tiny", 1), ("sp_tiny", 2), ("sp_tiny", 4),
+                                    ("sp_dqd_small", 5)])
 def test_ci_vs_oracle(name, M):
     import paper_2607_08447_amd as hkp
     d, V = _setup(name)
@@ -58,6 +59,8 @@ def test_ci_vs_oracle(name, M):
     assert np.abs(ci.E.cpu().numpy() - ev).max() <= 1e-9
     if M >= 2:
         assert abs(ci.J - exchange(ev)) <= 1e-9
+    else:   # one orbital: a single determinant, no exchange splitting to report
+        assert len(ev) == 1 and np.isnan(ci.J)
     U = ci.vectors.cpu().numpy()
     assert np.abs(U.conj().T @ U - np.eye(len(ev))).max() <= 1e-10
     assert np.abs(H @ U - U * ci.E.cpu().numpy()[None, :]).max() <= 1e-9
