@@ -53,6 +53,7 @@ heev_kernel(double* A, int nb, long long mat_stride, double* evals, double* out,
   __shared__ double lam[kNBP];
   __shared__ int rank[kNBP];
   __shared__ double red[kJacThreads / 64];
+  __shared__ int upair[(kNBP / 2) * (kNBP / 2 + 1) / 2];   // (P << 8) | Q, P <= Q
   __shared__ int any_rot;
 
   const int b = blockIdx.x;
@@ -70,6 +71,17 @@ heev_kernel(double* A, int nb, long long mat_stride, double* evals, double* out,
     if (i < nb && j < nb) x = Ab[(long long)i * nb + j];
     a[i][j] = x;
     v[i][j] = make_double2(i == j ? 1.0 : 0.0, 0.0);
+  }
+  // pair blocks on and above the block diagonal, row by row
+  const int h = n / 2;
+  const int nup = h * (h + 1) / 2;
+  for (int t = tid; t < nup; t += kJacThreads) {
+    int P = 0, rem = t;
+    while (rem >= h - P) {
+      rem -= h - P;
+      ++P;
+    }
+    upair[t] = (P << 8) | (P + rem);
   }
   __syncthreads();
   if (mode == 1) {
@@ -140,14 +152,15 @@ heev_kernel(double* A, int nb, long long mat_stride, double* evals, double* out,
       __syncthreads();
       // A <- N^H A N and V <- V N with N block diagonal over the pairs,
       // N_k = [[c, s], [-s e^{-i phi}, c e^{-i phi}]] on (p_k, q_k): every 2x2
-      // block of A (pair P rows, pair Q columns) and every (row, pair) slice of
-      // V is owned by one thread, so one phase updates everything in place
+      // block of A (pair P rows, pair Q columns) with P <= Q and every
+      // (row, pair) slice of V is owned by one thread, so one phase updates
+      // everything in place; the block (Q, P) is written as the conjugate
+      // transpose of (P, Q), which keeps A exactly Hermitian
       {
-        const int h = n / 2;
-        const int nblk = h * h;
-        for (int t = tid; t < nblk + n * h; t += kJacThreads) {
-          if (t < nblk) {
-            const Rot rp = rot[t / h], rq = rot[t % h];
+        for (int t = tid; t < nup + n * h; t += kJacThreads) {
+          if (t < nup) {
+            const int P = upair[t] >> 8, Q = upair[t] & 255;
+            const Rot rp = rot[P], rq = rot[Q];
             if (rp.s == 0.0 && rq.s == 0.0) continue;
             double2 a00 = a[rp.p][rq.p], a01 = a[rp.p][rq.q];
             double2 a10 = a[rp.q][rq.p], a11 = a[rp.q][rq.q];
@@ -171,7 +184,7 @@ heev_kernel(double* A, int nb, long long mat_stride, double* evals, double* out,
               const double2 u11 = make_double2(rp.s * a01.x + rp.c * e11.x, rp.s * a01.y + rp.c * e11.y);
               a00 = u00; a01 = u01; a10 = u10; a11 = u11;
             }
-            if (t / h == t % h) {
+            if (P == Q) {
               // the rotated pair itself: annihilated entry exactly zero, real diagonal
               a01 = make_double2(0, 0);
               a10 = make_double2(0, 0);
@@ -182,8 +195,14 @@ heev_kernel(double* A, int nb, long long mat_stride, double* evals, double* out,
             a[rp.p][rq.q] = a01;
             a[rp.q][rq.p] = a10;
             a[rp.q][rq.q] = a11;
+            if (P != Q) {
+              a[rq.p][rp.p] = make_double2(a00.x, -a00.y);
+              a[rq.q][rp.p] = make_double2(a01.x, -a01.y);
+              a[rq.p][rp.q] = make_double2(a10.x, -a10.y);
+              a[rq.q][rp.q] = make_double2(a11.x, -a11.y);
+            }
           } else {
-            const int u = t - nblk;
+            const int u = t - nup;
             const Rot rq = rot[u % h];
             if (rq.s == 0.0) continue;
             const int i = u / h;
