@@ -245,29 +245,36 @@ CG_BYTES_PER_NODE = (8 + 8 + 24 + 1 + 8 + 8) + (5 * 8 + 3 * 8)
 MG_PCG_BYTES_PER_NODE = (57 + 48) + (48 + 57) + 15
 
 
-def sp_measure(torch, hkp):
+def sp_measure(torch, hkp, anneal_K=15.0):
     """Self-consistent Schroedinger-Poisson loop on the 256 x 48 x 48 double-dot fin
     inside a 272 x 64 x 88 Poisson box (1.53M nodes), two holes at 1.5 K, mixed
-    precision eigensolves to 1e-7 eV, stopped at max |phi_out - phi_in| <= 1e-6 V;
-    and the Poisson CG iteration rate against the HBM roofline (HIP events around
-    a fixed number of iterations on the library's stream)."""
+    precision eigensolves to 1e-7 eV, stopped at max |phi_out - phi_in| <= 1e-6 V:
+    annealed from anneal_K (the main figures), then the direct loop at 1.5 K for
+    comparison; and the Poisson CG iteration rate against the HBM roofline (HIP
+    events around a fixed number of iterations on the library's stream)."""
     from synth import sp_device
     d = sp_device("sp_dqd_256x48x48")
     t = lambda a: None if a is None else torch.from_numpy(np.ascontiguousarray(a)).cuda()
     eps, dirm, phif = t(d.eps_r), t(d.dirichlet), t(d.phi_fixed)
     kw = dict(strain=t(d.strain), B=d.B, nb=d.nb, tol=1e-7, precision="mixed", graph=True,
               tol_V=1e-6, cg_tol=1e-12, mixing=0.3, history=5)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    r = hkp.sp_solve(t(d.V_off), d.h, d.nev, d.pshape, d.offset, eps, dirm, phif, d.n_holes, d.T,
-                     **kw)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
+
+    def loop(anneal_T):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r = hkp.sp_solve(t(d.V_off), d.h, d.nev, d.pshape, d.offset, eps, dirm, phif,
+                         d.n_holes, d.T, anneal_T=anneal_T, **kw)
+        torch.cuda.synchronize()
+        return r, time.perf_counter() - t0
+
+    r, wall = loop(anneal_K)
+    direct, wall_direct = loop(0.0)
     st = r.stats
     NP = int(np.prod(d.pshape))
     return {"workload": "sp_dqd_256x48x48", "grid": list(d.shape), "poisson_box": list(d.pshape),
             "poisson_nodes": NP, "n_holes": d.n_holes, "T_K": d.T, "nev": d.nev, "nb": d.nb,
             "precision": "mixed", "stop": "max |phi_out - phi_in| <= 1e-6 V, eigen tol 1e-7 eV",
+            "anneal_K": anneal_K, "anneal_iterations": st["anneal_iters"],
             "status": r.status, "sp_iterations": st["iters"], "converged": st["converged"],
             "delta_V": st["delta_V"], "seconds": round(wall, 3),
             "s_per_sp_iteration": round(wall / max(st["iters"], 1), 4),
@@ -275,6 +282,10 @@ def sp_measure(torch, hkp):
             "t_poisson_s": round(st["t_poisson"], 3), "cg_iterations": st["cg_iters"],
             "eigensolver_iterations": st["schroedinger_iters"],
             "E0_eV": float(r.E[0]), "mu_eV": st["mu_eV"],
+            "direct": {"sp_iterations": direct.stats["iters"],
+                       "converged": direct.stats["converged"], "seconds": round(wall_direct, 3),
+                       "max_abs_dE_vs_annealed_eV": float((direct.E - r.E).abs().max()),
+                       "max_abs_dphi_vs_annealed_V": float((direct.phi - r.phi).abs().max())},
             "poisson_cg": poisson_measure(torch, hkp, d, r.density)}
 
 

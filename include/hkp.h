@@ -170,6 +170,8 @@ typedef struct {
   double cg_tol;         /* Poisson CG: stop at |r| <= cg_tol |b|, > 0 */
   int32_t cg_max_iter;   /* CG iterations per Poisson solve, >= 1 */
   int32_t flags;         /* HKP_SP_* */
+  double anneal_K;       /* 0 (off) or a temperature above temperature_K at which the
+                            loop runs first; see hkp_sp_solve */
 } hkp_sp_opts;
 
 typedef struct {
@@ -185,6 +187,7 @@ typedef struct {
   int32_t poisson_status;     /* worst Poisson status (HKP_OK or a warning) */
   int32_t nb;                 /* eigensolver block size used */
   double seconds, t_schroedinger, t_poisson;   /* wall time: total, and by half */
+  int32_t anneal_iters;       /* iterations at anneal_K (included in iters) */
 } hkp_sp_stats;
 
 /* Silicon parameters of Table I with gamma3 = 1.446. */
@@ -489,6 +492,15 @@ size_t hkp_sp_workspace_bytes(const hkp_grid* grid, const hkp_opts* opts,
  * max(cg_tol, min(1e-6, 0.01 x that change)); when the loop meets tol_V after
  * such looser solves it makes one more pass at the same potential with
  * opts->tol and cg_tol, so the returned results always meet both.
+ * With sp->anneal_K > temperature_K the loop first runs at anneal_K until
+ * max |phi_out - phi_in| <= max(tol_V, 1 mV), then goes on at temperature_K from
+ * that potential (the eigensolves keep restarting from the last block; the
+ * Anderson history starts afresh).  It converges to the same fixed point; a
+ * higher temperature makes the occupations of nearly degenerate levels, and so
+ * the map from potential to density, smooth, which keeps the mixing from
+ * wandering between near-degenerate charge configurations (for two holes in a
+ * double dot at 1.5 K, anneal_K = 15 K).  Iterations at both temperatures count
+ * towards max_iter.
  *   V_off      device double [nx][ny][nz], band offset (e.g. the oxide step), eV
  *   strain, B_T as in hkp_solve
  *   eps_r, dirichlet, phi_fixed  as in hkp_poisson; rho_fixed device [px][py][pz]

@@ -77,7 +77,8 @@ class hkp_pgrid(C.Structure):
 class hkp_sp_opts(C.Structure):
     _fields_ = [("n_holes", C.c_double), ("temperature_K", C.c_double), ("mixing", C.c_double),
                 ("history", C.c_int32), ("max_iter", C.c_int32), ("tol_V", C.c_double),
-                ("cg_tol", C.c_double), ("cg_max_iter", C.c_int32), ("flags", C.c_int32)]
+                ("cg_tol", C.c_double), ("cg_max_iter", C.c_int32), ("flags", C.c_int32),
+                ("anneal_K", C.c_double)]
 
 
 class hkp_sp_stats(C.Structure):
@@ -85,7 +86,8 @@ class hkp_sp_stats(C.Structure):
                 ("mu_eV", C.c_double), ("f_last", C.c_double), ("cg_iters", C.c_int64),
                 ("schroedinger_iters", C.c_int32), ("solve_status", C.c_int32),
                 ("poisson_status", C.c_int32), ("nb", C.c_int32), ("seconds", C.c_double),
-                ("t_schroedinger", C.c_double), ("t_poisson", C.c_double)]
+                ("t_schroedinger", C.c_double), ("t_poisson", C.c_double),
+                ("anneal_iters", C.c_int32)]
 
     def as_dict(self):
         return {name: getattr(self, name) for name, _ in self._fields_}

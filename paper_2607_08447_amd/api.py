@@ -548,12 +548,14 @@ def sp_solve(V_off, h, nev, pshape, offset, eps_r, dirichlet, phi_fixed, n_holes
              strain=None, B=(0.0, 0.0, 0.0), rho_fixed=None, phi0=None, nb=0, degree=0,
              tol=1e-8, precision="fp64", max_iter=200, seed=1, graph=False, material=None,
              mixing=0.3, history=5, tol_V=1e-8, sp_max_iter=100, cg_tol=1e-12,
-             cg_max_iter=20000, return_psi=True, exact_eig=False):
+             cg_max_iter=20000, return_psi=True, exact_eig=False, anneal_T=0.0):
     """Self-consistent Schroedinger-Poisson loop: V_off [nx, ny, nz] (eV) at `offset`
     inside the Poisson box `pshape`; eps_r, dirichlet, phi_fixed (and rho_fixed)
     on the box.  phi0: start from this potential instead of the hole-free one.
     exact_eig: every eigensolve to `tol` (default: looser while the potential
-    still moves, `tol` for the final pass)."""
+    still moves, `tol` for the final pass).
+    anneal_T: if above T, the loop first converges at this temperature and then
+    goes on at T from that potential (0: off)."""
     V_off = _dev(V_off, torch.float64)
     shape = tuple(V_off.shape)
     strain = _dev(strain, torch.float64)
@@ -572,7 +574,7 @@ def sp_solve(V_off, h, nev, pshape, offset, eps_r, dirichlet, phi_fixed, n_holes
     sp = L.hkp_sp_opts(float(n_holes), float(T), float(mixing), int(history), int(sp_max_iter),
                        float(tol_V), float(cg_tol), int(cg_max_iter),
                        (L.HKP_SP_PHI0 if phi0 is not None else 0)
-                       | (L.HKP_SP_EXACT_EIG if exact_eig else 0))
+                       | (L.HKP_SP_EXACT_EIG if exact_eig else 0), float(anneal_T))
     need = L.lib.hkp_sp_workspace_bytes(C.byref(g), C.byref(o), C.byref(pg), C.byref(sp))
     if need == 0:
         raise L.HkpError(L.HKP_E_ARG, L.lib.hkp_last_error().decode())

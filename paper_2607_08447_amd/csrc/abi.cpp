@@ -152,9 +152,10 @@ int check_sp_opts(const hkp_sp_opts* sp, int nev) {
   }
   if (!finite_pos(sp->temperature_K) || !(sp->mixing > 0.0 && sp->mixing <= 1.0) ||
       sp->history < 0 || sp->history > 8 || sp->max_iter < 1 || !finite_pos(sp->tol_V) ||
-      !finite_pos(sp->cg_tol) || sp->cg_max_iter < 1) {
+      !finite_pos(sp->cg_tol) || sp->cg_max_iter < 1 ||
+      !(std::isfinite(sp->anneal_K) && sp->anneal_K >= 0.0)) {
     set_error("sp opts: T > 0, 0 < mixing <= 1, history 0..8, max_iter >= 1, tol_V > 0, "
-              "cg_tol > 0, cg_max_iter >= 1");
+              "cg_tol > 0, cg_max_iter >= 1, finite anneal_K >= 0");
     return HKP_E_ARG;
   }
   return HKP_OK;
@@ -761,6 +762,6 @@ int hkp_poisson_preconditioner(int32_t kind) {
   return set_poisson_precond(kind);
 }
 
-int hkp_version(void) { return 112; }
+int hkp_version(void) { return 113; }
 
 }  // extern "C"

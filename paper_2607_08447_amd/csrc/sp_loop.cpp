@@ -324,7 +324,15 @@ int run_sp(const SPArgs& a, hkp_sp_stats* stats) {
   sa.graph_chunk = 4;
   const int base_flags = (a.opts.flags & ~(HKP_FLAG_X0 | HKP_FLAG_X0_NEV)) | HKP_FLAG_PSI_BLOCK;
 
-  const double kT = kBoltzmann * a.sp.temperature_K;
+  // annealing: the loop first runs at anneal_K, where the thermal spread of the
+  // occupations exceeds the small level splittings near the Fermi level and the
+  // density answers the potential smoothly; from that fixed point it goes on at
+  // the requested temperature (same potential, eigenvector block and bound; the
+  // Anderson history is cleared)
+  bool annealing = a.sp.anneal_K > a.sp.temperature_K;
+  double kT = kBoltzmann * (annealing ? a.sp.anneal_K : a.sp.temperature_K);
+  // the annealing stage only has to reach the basin of the final fixed point
+  const double anneal_tol = std::max(a.sp.tol_V, 1e-3);
   const bool adaptive = !(a.sp.flags & HKP_SP_EXACT_EIG);
   int count = 0;   // entries pushed into the Anderson history
   bool converged = false, final_pass = false;
@@ -402,9 +410,19 @@ int run_sp(const SPArgs& a, hkp_sp_stats* stats) {
     }
     if (trace)
       std::fprintf(stderr, "[hkp sp] it %d  max|F| %.3e V  eig tol %.1e (%d iters)  cg tol %.1e "
-                   "(%d iters)  history %d\n", it, delta, sa.tol, sst.iters, cg_tol, cgit,
-                   std::min(count, m));
-    if (delta <= a.sp.tol_V) {
+                   "(%d iters)  history %d%s\n", it, delta, sa.tol, sst.iters, cg_tol, cgit,
+                   std::min(count, m), annealing ? "  (annealing)" : "");
+    if (annealing) {
+      if (delta <= anneal_tol) {
+        // the next iteration evaluates the same potential at the requested temperature
+        annealing = false;
+        kT = kBoltzmann * a.sp.temperature_K;
+        st.anneal_iters = it;
+        count = 0;
+        delta_prev = delta;
+        continue;
+      }
+    } else if (delta <= a.sp.tol_V) {
       if (sa.tol <= a.opts.tol_eV && cg_tol <= a.sp.cg_tol) {
         converged = true;
         break;
@@ -444,6 +462,7 @@ int run_sp(const SPArgs& a, hkp_sp_stats* stats) {
   HKP_CHECK(hipStreamSynchronize(s));
 
   st.iters = it;
+  if (annealing) st.anneal_iters = it;   // never left the annealing temperature
   st.converged = converged ? 1 : 0;
   st.delta_V = delta;
   st.mu_eV = mu;

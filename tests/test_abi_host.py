@@ -202,7 +202,9 @@ def test_sp_entry_points_reject_bad_arguments():
     assert b"inside" in L.lib.hkp_last_error() or b">= 1" in L.lib.hkp_last_error()
     for field, value in (("n_holes", 9.0), ("n_holes", -1.0), ("temperature_K", 0.0),
                          ("mixing", 0.0), ("mixing", 1.5), ("history", 9), ("max_iter", 0),
-                         ("tol_V", 0.0), ("cg_tol", -1.0), ("cg_max_iter", 0)):
+                         ("tol_V", 0.0), ("cg_tol", -1.0), ("cg_max_iter", 0),
+                         ("anneal_K", -1.0), ("anneal_K", float("nan")),
+                         ("anneal_K", float("inf"))):
         bad = L.hkp_sp_opts(2.0, 1.5, 0.3, 5, 50, 1e-8, 1e-12, 1000, 0)
         setattr(bad, field, value)
         assert L.lib.hkp_sp_workspace_bytes(C.byref(g), C.byref(o), C.byref(pg),

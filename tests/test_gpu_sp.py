@@ -191,6 +191,17 @@ def test_sp_loop_vs_oracle(name):
     dens = r.density.cpu().numpy()
     assert abs(dens.sum() * d.h ** 3 - d.n_holes) <= 1e-9
     assert np.abs(dens - ref["density"]).max() <= 1e-5 * ref["density"].max()
+    # annealed from 15 K: a different path to the same fixed point
+    a = _gpu_loop(hkp, d, tol=1e-10, tol_V=1e-9, mixing=0.3, history=5, cg_tol=1e-13,
+                  anneal_T=15.0)
+    assert a.status == 0 and a.stats["converged"] == 1
+    assert 1 <= a.stats["anneal_iters"] < a.stats["iters"]
+    dphi = np.abs(a.phi.cpu().numpy() - ref["phi"]).max()
+    dE = np.abs(a.E.cpu().numpy() - ref["E"]).max()
+    print(f"annealed: iterations {a.stats['anneal_iters']} + "
+          f"{a.stats['iters'] - a.stats['anneal_iters']}: max |dphi| {dphi:.2e} V, "
+          f"max |dE| {dE:.2e} eV", flush=True)
+    assert dphi <= 1e-7 and dE <= 1e-8
 
 
 def test_sp_loop_restart_from_converged_potential():
@@ -262,3 +273,10 @@ def test_sp_loop_full_size_properties():
                   return_psi=False)
     assert np.abs(e.E.cpu().numpy() - r.E.cpu().numpy()).max() <= 1e-6
     assert torch.all(r.resid <= 1e-7)
+    # annealed from 15 K: the same fixed point within the loop's tolerance
+    a = _gpu_loop(hkp, d, tol=1e-7, tol_V=tol_V, cg_tol=1e-12, precision="mixed", graph=True,
+                  anneal_T=15.0)
+    print({k: a.stats[k] for k in ("iters", "anneal_iters", "seconds")}, flush=True)
+    assert a.status == 0 and a.stats["converged"] == 1 and a.stats["anneal_iters"] >= 1
+    assert float((a.phi - r.phi).abs().max()) <= 5 * tol_V
+    assert np.abs(a.E.cpu().numpy() - r.E.cpu().numpy()).max() <= 5e-7
