@@ -233,6 +233,13 @@ def test_sp_loop_without_holes_and_not_converged():
                       tol_V=1e-9, cg_tol=1e-13)
     assert r2.status == 0 and r2.stats["iters"] == 2
     assert np.abs(r2.E.cpu().numpy() - r.E.cpu().numpy()).max() <= 1e-9
+    # annealing without holes: one pass at the higher temperature, then the same result
+    r3 = hkp.sp_solve(_t(d.V_off), d.h, d.nev, d.pshape, d.offset, _t(d.eps_r),
+                      _t(d.dirichlet), _t(d.phi_fixed), 0.0, d.T, nb=d.nb, tol=1e-10,
+                      tol_V=1e-9, cg_tol=1e-13, anneal_T=15.0)
+    assert r3.status == 0 and r3.stats["converged"] == 1 and r3.stats["anneal_iters"] == 1
+    assert 2 <= r3.stats["iters"] <= 3
+    assert np.abs(r3.E.cpu().numpy() - r.E.cpu().numpy()).max() <= 1e-9
     ref = poisson_solve(d.pshape, d.h, d.eps_r, d.dirichlet, d.phi_fixed, np.zeros(d.pshape))
     assert np.abs(r.phi.cpu().numpy() - ref).max() <= 1e-10
     g = Grid(*d.shape, d.h)
