@@ -326,9 +326,9 @@ int run_sp(const SPArgs& a, hkp_sp_stats* stats) {
 
   // annealing: the loop first runs at anneal_K, where the thermal spread of the
   // occupations exceeds the small level splittings near the Fermi level and the
-  // density answers the potential smoothly; from that fixed point it goes on at
-  // the requested temperature (same potential, eigenvector block and bound; the
-  // Anderson history is cleared)
+  // density answers the potential smoothly; once that stage is within 1 mV of
+  // its fixed point the loop goes on at the requested temperature (same
+  // potential, eigenvector block and bound; the Anderson history is cleared)
   bool annealing = a.sp.anneal_K > a.sp.temperature_K;
   double kT = kBoltzmann * (annealing ? a.sp.anneal_K : a.sp.temperature_K);
   // the annealing stage only has to reach the basin of the final fixed point
