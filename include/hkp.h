@@ -190,8 +190,15 @@ typedef struct {
   int32_t anneal_iters;       /* iterations at anneal_K (included in iters) */
 } hkp_sp_stats;
 
-/* Silicon parameters of Table I with gamma3 = 1.446. */
+/* Silicon parameters of Table I (Appendix A) with gamma3 = 1.446 in place of
+ * the table's 1.21: gamma1 4.285, gamma2 0.339, Delta_0 0.044 eV, kappa -0.42,
+ * a_v 2.46 eV, b -2.35 eV, d -5.32 eV. */
 void hkp_default_material(hkp_material* m);
+/* The unit constants the library computes with (host, no GPU work):
+ * out[0] = hbar^2/(2 m0) in eV nm^2 (the kinetic scale of Eq. LK),
+ * out[1] = mu_B in eV/T (Zeeman term), out[2] = e/hbar in 1/(T nm^2) (Peierls
+ * phases); CODATA 2018 values to ten significant digits.  NULL is ignored. */
+void hkp_unit_constants(double out[3]);
 /* nev 8, nb 0, degree 0, max_iter 200, tol 1e-8 eV, FP64, flags 0, seed 1. */
 void hkp_default_opts(hkp_opts* o);
 
@@ -250,8 +257,11 @@ int hkp_solve_batch(const hkp_grid* grid, const hkp_material* mat, const hkp_opt
 /* Workspace of hkp_apply / hkp_filter_step for nvec vectors. */
 size_t hkp_apply_workspace_bytes(const hkp_grid* grid, int32_t nvec);
 
-/* Y = alpha (H - shift) X + beta Y_old  on nvec spinors (one Chebyshev
- * recurrence step; alpha = 1, shift = beta = 0 gives Y = H X).
+/* Y = alpha (H - shift) X + beta Y_old  on nvec spinors: one step of the
+ * Chebyshev filter of the Rayleigh-Chebyshev eigensolver (Sec. II.B), with H
+ * the discretised H_NI of Eq. HNI (Sec. II.C: Luttinger-Kohn kinetic term,
+ * Bir-Pikus strain, Zeeman and Peierls terms, potential V) on the grid of
+ * Sec. II.B; alpha = 1, shift = beta = 0 gives Y = H X.
  *   X, Y      device complex double [nvec][nx][ny][nz][6], nvec >= 1
  *   Y_old     device, same layout, or NULL when beta == 0; may alias Y
  *   precision HKP_PREC_FP64 or HKP_PREC_MIXED (operands rounded to FP32 and
@@ -262,20 +272,24 @@ int hkp_filter_step(const hkp_grid* grid, const hkp_material* mat, const double*
                     double beta, int32_t precision, void* workspace, size_t ws_bytes,
                     void* hip_stream);
 
-/* Y = H X (hkp_filter_step with alpha 1, shift 0, beta 0). */
+/* Y = H X with H the discretised Hamiltonian H_NI of Eq. HNI (Sec. II.C) on
+ * the grid of Sec. II.B (hkp_filter_step with alpha 1, shift 0, beta 0). */
 int hkp_apply(const hkp_grid* grid, const hkp_material* mat, const double* V_eV,
               const double* strain, const double B_T[3], int32_t nvec, const void* X,
               void* Y, int32_t precision, void* workspace, size_t ws_bytes,
               void* hip_stream);
 
-/* V_out = V_bg + sum_g Vg[g] L[g]  (the linear gate -> potential map).
+/* V_out = V_bg + sum_g Vg[g] L[g]: a linear gate -> potential map producing the
+ * V_DQD term of Eq. HNI (Sec. II.C) from gate voltages (lever-arm fields L_g).
  *   V_bg, V_out device double [N]; L device double [G][N]; Vg device double [G]. */
 int hkp_gate_potential(int64_t N, int32_t G, const double* V_bg, const double* L,
                        const double* Vg, double* V_out, void* hip_stream);
 
 /* Hellmann-Feynman gradient: grad[g] = sum_n w[n] sum_r sum_c |psi_{n,c}(r)|^2 L[g](r),
- * the derivative of sum_n w_n E_n with respect to the gate voltages, since
- * dH/dV_g = L_g(r) times the identity on the spinor components.
+ * the derivative of sum_n w_n E_n with respect to the gate voltages.  V_DQD
+ * enters Eq. HNI (Sec. II.C) as a diagonal term, and with the linear gate map
+ * of hkp_gate_potential dH/dV_g = L_g(r) times the identity on the spinor
+ * components, so dE_n/dV_g = <psi_n| L_g |psi_n>.
  *   psi  device complex double [nev][N][6]; w device double [nev];
  *   L    device double [G][N] (1 <= G <= 16); grad device double [G];
  *   workspace device, ws_bytes >= hkp_hf_grad_workspace_bytes(G) (block
@@ -286,8 +300,13 @@ int hkp_hf_grad(int64_t N, int32_t nev, const void* psi, const double* w, int32_
                 const double* L, double* grad, void* workspace, size_t ws_bytes,
                 void* hip_stream);
 
-/* Time the filter-step kernel variants for this shape and block size, cache
- * the fastest (per process, keyed by shape, nb and precision) and report it.
+/* Time the filter-step kernel's launch shapes for this grid and block size,
+ * cache the fastest and report it.  The stencil variant timed: strain on or
+ * off (with_strain), and with_field 0 (B = 0), 1 (B along x: link phases
+ * uniform over a z-plane) or 2 (B with a z component: the general phase
+ * kernel).  The cache lives for the process, keyed by shape, nb, precision
+ * and variant; a solve or filter step whose variant was not tuned uses the
+ * shape tuned for another variant of the same shape, nb and precision.
  * Needs workspace >= hkp_workspace_bytes(grid, opts{nb}, 1). */
 int hkp_autotune(const hkp_grid* grid, int32_t nb, int32_t precision, int32_t with_strain,
                  int32_t with_field, void* workspace, size_t ws_bytes, void* hip_stream,

@@ -123,6 +123,7 @@ _D = C.POINTER(C.c_double)
 
 SIGNATURES = {
     "hkp_default_material": (None, [C.POINTER(hkp_material)]),
+    "hkp_unit_constants": (None, [C.POINTER(C.c_double)]),
     "hkp_default_opts": (None, [C.POINTER(hkp_opts)]),
     "hkp_workspace_bytes": (C.c_size_t, [C.POINTER(hkp_grid), C.POINTER(hkp_opts), C.c_int32]),
     "hkp_block_size": (C.c_int32, [C.POINTER(hkp_grid), C.POINTER(hkp_opts)]),

@@ -667,6 +667,7 @@ class EigvalsFromPotential(torch.autograd.Function):
         kw = dict(cfg)
         h = kw.pop("h")
         nev = kw.pop("nev")
+        kw.pop("degenerate_tol", None)   # a backward setting, not a solve() argument
         res = solve(V, h, nev, **kw)
         if res.status != L.HKP_OK:
             raise L.HkpError(res.status, "eigensolver did not converge")

@@ -219,7 +219,7 @@ int solve_common(const hkp_grid* grid, const hkp_material* mat, const hkp_opts* 
   a.max_iter = opts->max_iter;
   a.flags = opts->flags;
   a.seed = opts->seed;
-  a.st = autotuned(*grid, p.nb, p.mixed);
+  a.st = autotuned(*grid, p.nb, p.mixed, stencil_variant(strain != nullptr, B));
   a.graph_chunk = 4;
   return guarded([&]() { return run_solve(a, stats); });
 }
@@ -244,6 +244,13 @@ void hkp_default_material(hkp_material* m) {
   m->a_v_eV = 2.46;
   m->b_eV = -2.35;
   m->d_eV = -5.32;
+}
+
+void hkp_unit_constants(double out[3]) {
+  if (!out) return;
+  out[0] = kE0;
+  out[1] = kMuB;
+  out[2] = kEoverHbar;
 }
 
 void hkp_default_opts(hkp_opts* o) {
@@ -341,7 +348,8 @@ int hkp_filter_step(const hkp_grid* grid, const hkp_material* mat, const double*
   a.precision = precision;
   a.workspace = workspace;
   a.stream = hip_stream;
-  a.st = autotuned(*grid, nvec, precision == HKP_PREC_MIXED);
+  a.st = autotuned(*grid, nvec, precision == HKP_PREC_MIXED,
+                   stencil_variant(strain != nullptr, B_T));
   return guarded([&]() { return run_filter_step(a); });
 }
 
@@ -404,7 +412,7 @@ int hkp_autotune(const hkp_grid* grid, int32_t nb, int32_t precision, int32_t wi
                  int32_t with_field, void* workspace, size_t ws_bytes, void* hip_stream,
                  hkp_tune* out) {
   HKP_TRY(check_grid(grid));
-  if (nb < 1 || nb > HKP_NB_MAX || !workspace || !out ||
+  if (nb < 1 || nb > HKP_NB_MAX || !workspace || !out || with_field < 0 || with_field > 2 ||
       (precision != HKP_PREC_FP64 && precision != HKP_PREC_MIXED)) {
     set_error("hkp_autotune: invalid arguments");
     return HKP_E_ARG;
@@ -412,7 +420,7 @@ int hkp_autotune(const hkp_grid* grid, int32_t nb, int32_t precision, int32_t wi
   HKP_TRY(check_device());
   return guarded([&]() {
     return run_autotune(*grid, nb, precision == HKP_PREC_MIXED, with_strain != 0,
-                        with_field != 0, workspace, ws_bytes, hip_stream, out);
+                        with_field, workspace, ws_bytes, hip_stream, out);
   });
 }
 
@@ -637,10 +645,23 @@ int hkp_hole_density(const hkp_grid* grid, int32_t nev, const void* psi, const d
   });
 }
 
+namespace {
+// the loop's density is formed from six-component spinors: the spin-free
+// orbital problem (three components per vector) is not a loop option
+int check_sp_flags(const hkp_opts* o) {
+  if (o->flags & HKP_FLAG_SPIN_FREE) {
+    set_error("hkp_sp_solve: HKP_FLAG_SPIN_FREE is not supported in the self-consistent loop");
+    return HKP_E_ARG;
+  }
+  return HKP_OK;
+}
+}  // namespace
+
 size_t hkp_sp_workspace_bytes(const hkp_grid* grid, const hkp_opts* opts,
                               const hkp_pgrid* pgrid, const hkp_sp_opts* sp) {
   if (check_grid(grid) != HKP_OK || check_opts(grid, opts) != HKP_OK ||
-      check_pgrid(pgrid, grid) != HKP_OK || check_sp_opts(sp, opts->nev) != HKP_OK)
+      check_pgrid(pgrid, grid) != HKP_OK || check_sp_opts(sp, opts->nev) != HKP_OK ||
+      check_sp_flags(opts) != HKP_OK)
     return 0;
   return sp_bytes(*grid, *opts, *pgrid, *sp);
 }
@@ -657,6 +678,7 @@ int hkp_sp_solve(const hkp_grid* grid, const hkp_material* mat, const hkp_opts* 
   HKP_TRY(check_opts(grid, opts));
   HKP_TRY(check_pgrid(pgrid, grid));
   HKP_TRY(check_sp_opts(sp, opts->nev));
+  HKP_TRY(check_sp_flags(opts));
   if (!V_off_eV || !eps_r || !dirichlet || !phi_fixed || !phi || !eig_eV || !workspace) {
     set_error("hkp_sp_solve: V_off, eps_r, dirichlet, phi_fixed, phi, eig and workspace "
               "must not be NULL");
@@ -724,7 +746,10 @@ int hkp_gmatrix(const hkp_grid* grid, const hkp_material* mat, const double* V_e
   a.out = out;
   a.workspace = workspace;
   a.stream = hip_stream;
-  a.st = autotuned(*grid, 16, false);
+  {
+    const double B0[3] = {0.0, 0.0, 0.0};
+    a.st = autotuned(*grid, 16, false, stencil_variant(strain != nullptr, B0));
+  }
   return guarded([&]() { return run_gmatrix(a); });
 }
 

@@ -1,6 +1,9 @@
 // Autotuner for the stencil (Chebyshev step) kernel: times the tile shapes on
 // the caller's grid and block size with HIP events and caches the fastest per
-// (shape, nb, precision, strain, field) for the life of the process.
+// (shape, nb, precision, stencil variant) for the life of the process; the
+// variant is strain on/off and the link-phase kind (none, Bz = 0, general).
+// A launch whose own variant was never tuned takes the shape tuned for
+// another variant of the same shape, nb and precision, else the default.
 #include <algorithm>
 #include <chrono>
 #include <cstdio>
@@ -17,9 +20,10 @@ namespace hkp {
 
 namespace {
 
-using Key = std::tuple<int, int, int, int, int>;   // nx, ny, nz, nb, mixed
+using Key = std::tuple<int, int, int, int, int>;   // nx, ny, nz, nb|nev, mixed
+using TuneKey = std::tuple<int, int, int, int, int, int>;   // ... + variant
 std::mutex g_mu;
-std::map<Key, StencilTune> g_cache;
+std::map<TuneKey, StencilTune> g_cache;
 
 size_t al(size_t x) { return (x + 255) & ~(size_t)255; }
 
@@ -82,7 +86,7 @@ int run_autotune_block(const hkp_grid& g, const hkp_material& mat, const hkp_opt
     a.max_iter = oc.max_iter;
     a.flags = oc.flags;
     a.seed = oc.seed;
-    a.st = autotuned(g, oc.nb, oc.precision == HKP_PREC_MIXED);
+    a.st = autotuned(g, oc.nb, oc.precision == HKP_PREC_MIXED, stencil_variant(strain != nullptr, B));
     a.graph_chunk = 4;
     const auto t0 = std::chrono::steady_clock::now();
     const int rc = run_solve(a, nullptr);
@@ -108,12 +112,22 @@ int run_autotune_block(const hkp_grid& g, const hkp_material& mat, const hkp_opt
   return HKP_OK;
 }
 
-StencilTune autotuned(const hkp_grid& g, int nb, bool mixed) {
+int stencil_variant(bool strain, const double B[3]) {
+  const int ph = (B[0] == 0.0 && B[1] == 0.0 && B[2] == 0.0) ? 0 : (B[2] != 0.0 ? 2 : 1);
+  return (strain ? 1 : 0) | (ph << 1);
+}
+
+StencilTune autotuned(const hkp_grid& g, int nb, bool mixed, int variant) {
   StencilTune t;
   if (forced(&t)) return t;
   std::lock_guard<std::mutex> lk(g_mu);
-  auto it = g_cache.find(Key{g.nx, g.ny, g.nz, nb, mixed ? 1 : 0});
+  const int m = mixed ? 1 : 0;
+  auto it = g_cache.find(TuneKey{g.nx, g.ny, g.nz, nb, m, variant});
   if (it != g_cache.end()) return it->second;
+  for (int v = 0; v < 6; ++v) {
+    it = g_cache.find(TuneKey{g.nx, g.ny, g.nz, nb, m, v});
+    if (it != g_cache.end()) return it->second;
+  }
   // untuned default (the fastest shape measured on the fin and double-dot
   // grids): two-row tiles, rows staged global -> LDS directly when tiles are
   // full along x
@@ -122,7 +136,7 @@ StencilTune autotuned(const hkp_grid& g, int nb, bool mixed) {
   return t;
 }
 
-int run_autotune(const hkp_grid& g, int nb, bool mixed, bool strain, bool field, void* ws,
+int run_autotune(const hkp_grid& g, int nb, bool mixed, bool strain, int field, void* ws,
                  size_t ws_bytes, void* stream, hkp_tune* out) {
   const long long N = (long long)g.nx * g.ny * g.nz, n6 = 6 * N;
   const size_t esz = mixed ? 8 : 16;
@@ -150,7 +164,9 @@ int run_autotune(const hkp_grid& g, int nb, bool mixed, bool strain, bool field,
   if (hipMemsetAsync(p, 0, off, s) != hipSuccess) return HKP_E_HIP;
   hkp_material m;
   hkp_default_material(&m);
-  const double B[3] = {field ? 0.5 : 0.0, 0.0, 0.0};
+  // field 1: B along x (link phases uniform over a z-plane); 2: B with a z
+  // component (the general phase kernel)
+  const double B[3] = {field ? 0.5 : 0.0, 0.0, field == 2 ? 0.5 : 0.0};
   const StencilConsts<double> c = make_consts(m, g.h_nm, B);
   hipEvent_t e0, e1;
   if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return HKP_E_HIP;
@@ -180,6 +196,7 @@ int run_autotune(const hkp_grid& g, int nb, bool mixed, bool strain, bool field,
     a.strain = strain;
     a.wtab = field ? wt : nullptr;
     a.vtab = field ? vt : nullptr;
+    a.phase_general = field == 2;
     a.coef.alpha = 1.0;
     a.coef.shift = 0.5;
     a.coef.beta = -1.0;
@@ -209,7 +226,7 @@ int run_autotune(const hkp_grid& g, int nb, bool mixed, bool strain, bool field,
   (void)hipEventDestroy(e1);
   {
     std::lock_guard<std::mutex> lk(g_mu);
-    g_cache[Key{g.nx, g.ny, g.nz, nb, mixed ? 1 : 0}] = best;
+    g_cache[TuneKey{g.nx, g.ny, g.nz, nb, mixed ? 1 : 0, stencil_variant(strain, B)}] = best;
   }
   out->tile_y = best.tile_y;
   out->vgroup = best.vgroup;

@@ -33,9 +33,11 @@ __device__ __forceinline__ int xcd_remap(int wg, int nwg) {
   return x * per + (x < rem ? x : rem) + idx;
 }
 
-constexpr double kE0 = 0.0380998212;          // hbar^2/(2 m0), eV nm^2
-constexpr double kMuB = 5.7883818060e-5;      // eV/T
-constexpr double kEoverHbar = 1.519267447e-3; // 1/(T nm^2)
+// unit constants from CODATA 2018 (h, e exact; m0 = 9.1093837015e-31 kg),
+// ten significant digits
+constexpr double kE0 = 0.03809982116;         // hbar^2/(2 m0), eV nm^2
+constexpr double kMuB = 5.788381806e-5;       // e hbar/(2 m0), eV/T
+constexpr double kEoverHbar = 1.519267448e-3; // e/hbar, 1/(T nm^2)
 
 // ---------------------------------------------------------------------------
 // stencil constants (host-computed in double, converted to the kernel type)

@@ -87,8 +87,10 @@ int run_solve(const SolveArgs& a, hkp_stats* stats);
 size_t apply_bytes(const hkp_grid& g, int nvec);
 int run_filter_step(const FilterArgs& a);
 int guarded(const std::function<int()>& f);
-StencilTune autotuned(const hkp_grid& g, int nb, bool mixed);
-int run_autotune(const hkp_grid& g, int nb, bool mixed, bool strain, bool field, void* ws,
+// stencil variant of a launch: strain on/off and the link-phase kind
+int stencil_variant(bool strain, const double B[3]);
+StencilTune autotuned(const hkp_grid& g, int nb, bool mixed, int variant);
+int run_autotune(const hkp_grid& g, int nb, bool mixed, bool strain, int field, void* ws,
                  size_t ws_bytes, void* stream, hkp_tune* out);
 
 // ---- self-consistent loop and its Poisson solve

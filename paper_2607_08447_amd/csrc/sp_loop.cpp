@@ -320,7 +320,7 @@ int run_sp(const SPArgs& a, hkp_sp_stats* stats) {
   sa.tol = a.opts.tol_eV;
   sa.max_iter = a.opts.max_iter;
   sa.seed = a.opts.seed;
-  sa.st = autotuned(a.grid, p.nb, p.mixed);
+  sa.st = autotuned(a.grid, p.nb, p.mixed, stencil_variant(a.strain != nullptr, a.B));
   sa.graph_chunk = 4;
   const int base_flags = (a.opts.flags & ~(HKP_FLAG_X0 | HKP_FLAG_X0_NEV)) | HKP_FLAG_PSI_BLOCK;
 

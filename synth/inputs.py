@@ -28,7 +28,7 @@ import numpy as np
 from scipy.ndimage import gaussian_filter
 
 # constants of the input recipe (harmonic well only)
-_E0 = 0.0380998212      # hbar^2/(2 m0), eV nm^2
+_E0 = 0.03809982116     # hbar^2/(2 m0), eV nm^2
 _GAMMA1 = 4.285         # Si, Table I
 _FWHM_TO_SIGMA = 1.0 / (2.0 * np.sqrt(2.0 * np.log(2.0)))
 

@@ -229,6 +229,24 @@ def test_sp_entry_points_reject_bad_arguments():
     assert L.lib.hkp_occupancy(8, fake, 9.0, 1.5, fake, None, None) == L.HKP_E_ARG
     assert L.lib.hkp_occupancy(8, fake, 2.0, 0.0, fake, None, None) == L.HKP_E_ARG
     assert L.lib.hkp_hole_density(C.byref(g), 0, fake, fake, fake, None) == L.HKP_E_ARG
+    # the loop's density needs six-component spinors: the spin-free flag is rejected
+    o.flags = L.HKP_FLAG_SPIN_FREE
+    assert L.lib.hkp_sp_workspace_bytes(C.byref(g), C.byref(o), C.byref(pg), C.byref(sp)) == 0
+    assert b"SPIN_FREE" in L.lib.hkp_last_error()
+    assert L.lib.hkp_sp_solve(C.byref(g), C.byref(m), C.byref(o), C.byref(pg), C.byref(sp),
+                              fake, None, B, fake, fake, fake, None, fake, fake, None, None,
+                              None, fake, 1 << 40, None, C.byref(st)) == L.HKP_E_ARG
+    assert b"SPIN_FREE" in L.lib.hkp_last_error()
+    o.flags = 0
+
+
+def test_autotune_rejects_unknown_field_kind():
+    L, g, m, o = _structs()
+    fake = C.c_void_p(0x1000)
+    t = L.hkp_tune()
+    for wf in (-1, 3):
+        assert L.lib.hkp_autotune(C.byref(g), 16, 0, 1, wf, fake, 1 << 40, None,
+                                  C.byref(t)) == L.HKP_E_ARG
 
 
 def test_spin_free_entry_points_reject_bad_arguments():

@@ -74,3 +74,28 @@ def test_unequal_weights_in_kramers_pair_raise():
                                        torch.from_numpy(w.V).cuda(), cfg)
     with pytest.raises(ValueError):
         E[0].backward()
+
+
+def test_degenerate_tol_setting_reaches_the_backward():
+    """cfg['degenerate_tol'] is a backward setting: the forward must not pass it
+    to the solve, and the backward must use it to group degenerate levels."""
+    import torch
+    import paper_2607_08447_amd as hkp
+    w = _small_adjoint()
+    Ld = torch.from_numpy(w.extra["L"]).cuda()
+    cfg = dict(h=w.h, nev=4, strain=torch.from_numpy(w.strain), B=w.B, nb=12, tol=1e-9,
+               degenerate_tol=1e-7)
+    Vg = torch.zeros(5, dtype=torch.float64, device="cuda", requires_grad=True)
+    E = hkp.EigvalsFromPotential.apply(Vg, Ld, torch.from_numpy(w.V).cuda(), cfg)
+    E.sum().backward()
+    ref = hkp.hf_grad(hkp.solve(torch.from_numpy(w.V).cuda(), w.h, 4, strain=cfg["strain"],
+                                B=w.B, nb=12, tol=1e-9).psi,
+                      torch.ones(4, dtype=torch.float64, device="cuda"),
+                      Ld.reshape(5, -1)).cpu().numpy()
+    g = Vg.grad.cpu().numpy()
+    assert np.abs(g - ref).max() <= 1e-7 * np.abs(ref).max()
+    # the setting groups the Kramers pairs: unequal weights inside one still raise
+    Vg1 = torch.zeros(5, dtype=torch.float64, device="cuda", requires_grad=True)
+    E1 = hkp.EigvalsFromPotential.apply(Vg1, Ld, torch.from_numpy(w.V).cuda(), cfg)
+    with pytest.raises(ValueError):
+        E1[0].backward()
