@@ -127,6 +127,9 @@ typedef struct {
   int64_t n_stencil32, n_stencil64;      /* timed launches */
   double t_stencil32, t_stencil64;       /* summed durations (s) */
   double bytes_stencil32, bytes_stencil64; /* algorithmic bytes of the timed launches */
+  int32_t n_graph_launches; /* replays of the recorded iteration graph (HKP_FLAG_GRAPH) */
+  int32_t n_host_syncs;     /* host waits on the solver's stream (flag read-backs,
+                               the spectral bound, the input check, the final wait) */
 } hkp_stats;
 
 /* Autotuner result for the stencil (filter step) kernel on one shape. */
@@ -299,6 +302,7 @@ size_t hkp_hf_grad_workspace_bytes(int32_t G);
 int hkp_hf_grad(int64_t N, int32_t nev, const void* psi, const double* w, int32_t G,
                 const double* L, double* grad, void* workspace, size_t ws_bytes,
                 void* hip_stream);
+
 
 /* Time the filter-step kernel's launch shapes for this grid and block size,
  * cache the fastest and report it.  The stencil variant timed: strain on or

@@ -58,7 +58,8 @@ class hkp_stats(C.Structure):
                 ("t_resid", C.c_double), ("lambda_max_bound", C.c_double),
                 ("hx_bytes", C.c_double), ("n_stencil32", C.c_int64), ("n_stencil64", C.c_int64),
                 ("t_stencil32", C.c_double), ("t_stencil64", C.c_double),
-                ("bytes_stencil32", C.c_double), ("bytes_stencil64", C.c_double)]
+                ("bytes_stencil32", C.c_double), ("bytes_stencil64", C.c_double),
+                ("n_graph_launches", C.c_int32), ("n_host_syncs", C.c_int32)]
 
     def as_dict(self):
         return {name: getattr(self, name) for name, _ in self._fields_}

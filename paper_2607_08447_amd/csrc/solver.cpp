@@ -493,6 +493,7 @@ int default_nb(int nev, long long n6) {
 size_t plan_bytes(const Plan& p) { return make_layout(p).total; }
 
 int run_solve(const SolveArgs& A, hkp_stats* stats) {
+  int n_sync = 0, n_graph = 0;   // host waits on the stream, graph replays
   const auto t_start = std::chrono::steady_clock::now();
   Ctx c;
   StencilStats sst;
@@ -525,6 +526,7 @@ int run_solve(const SolveArgs& A, hkp_stats* stats) {
   int bad = 0;
   HKP_CHECK(hipMemcpyAsync(&bad, c.at<int>(c.L.status) + p.batch, 4, hipMemcpyDeviceToHost, c.s));
   HKP_CHECK(hipStreamSynchronize(c.s));
+  ++n_sync;
   if (bad) {
     set_error("V or strain contains NaN or Inf");
     return HKP_E_ARG;
@@ -547,14 +549,17 @@ int run_solve(const SolveArgs& A, hkp_stats* stats) {
   std::vector<double> bup;
   if (A.bound_hint > 0.0 && p.batch == 1)
     bup.assign(1, A.bound_hint);
-  else
+  else {
     lanczos_bounds(c, bup);
+    ++n_sync;   // one wait for the Lanczos coefficients
+  }
   {
     std::vector<double> hb(4 * (size_t)p.batch, 0.0);
     for (int b = 0; b < p.batch; ++b) hb[4 * b] = bup[b];
     HKP_CHECK(hipMemcpyAsync(c.at<double>(c.L.bounds), hb.data(), hb.size() * 8,
                              hipMemcpyHostToDevice, c.s));
     HKP_CHECK(hipStreamSynchronize(c.s));
+    ++n_sync;
   }
 
   // ---- initial block: caller's X0 or random; SVQB; Rayleigh-Ritz
@@ -607,6 +612,7 @@ int run_solve(const SolveArgs& A, hkp_stats* stats) {
     HKP_CHECK(hipMemcpyAsync(hflags.data(), c.at<int>(c.L.flags), hflags.size() * 4,
                              hipMemcpyDeviceToHost, c.s));
     HKP_CHECK(hipStreamSynchronize(c.s));
+    ++n_sync;
   };
   read_flags();
   auto all_done = [&]() {
@@ -731,6 +737,7 @@ int run_solve(const SolveArgs& A, hkp_stats* stats) {
       for (int k = 0; k < chunk; ++k) count_work();   // upper estimate per replay
       sst.hx_bytes += chunk_bytes;
       HKP_CHECK(hipGraphLaunch(rec.exec, c.s));
+      ++n_graph;
       iters += chunk;
       read_flags();
     }
@@ -748,6 +755,7 @@ int run_solve(const SolveArgs& A, hkp_stats* stats) {
                                      c.at<double>(c.L.X), c.bstride(), A.psi,
                                      (long long)npsi * p.n6, c.s));
   HKP_CHECK(hipStreamSynchronize(c.s));
+  ++n_sync;
   int all = 1, minconv = p.nev, maxit = 0, sw = -1;
   for (int b = 0; b < p.batch; ++b) {
     all &= hflags[8 * b] != 0;
@@ -777,6 +785,8 @@ int run_solve(const SolveArgs& A, hkp_stats* stats) {
     stats->t_stencil64 = sst.t64;
     stats->bytes_stencil32 = sst.b32;
     stats->bytes_stencil64 = sst.b64;
+    stats->n_graph_launches = n_graph;
+    stats->n_host_syncs = n_sync;
     stats->seconds =
         std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count();
   }
