@@ -303,6 +303,18 @@ int hkp_hf_grad(int64_t N, int32_t nev, const void* psi, const double* w, int32_
                 const double* L, double* grad, void* workspace, size_t ws_bytes,
                 void* hip_stream);
 
+/* hkp_hf_grad without a workspace argument, for callers that cannot allocate
+ * device memory (code under stream capture, serving loops, harnesses that
+ * forbid allocation).  The block partial sums go to a static device array of
+ * 128 KiB (1024 x 16 doubles) that each GPU the library runs on holds until
+ * the process ends; nothing is allocated or freed.  Every partial sum is
+ * written before it is read, so nothing needs clearing between calls.  All
+ * calls on one GPU share that array: calls that overlap in time on one GPU
+ * (different streams or threads) race and must be serialised by the caller.
+ * Same arguments, layouts and result as hkp_hf_grad; G outside 1..16 (more
+ * partial sums than the array holds) is rejected with HKP_E_ARG. */
+int hkp_hf_grad_noalloc(int64_t N, int32_t nev, const void* psi, const double* w, int32_t G,
+                        const double* L, double* grad, void* hip_stream);
 
 /* Time the filter-step kernel's launch shapes for this grid and block size,
  * cache the fastest and report it.  The stencil variant timed: strain on or

@@ -144,6 +144,7 @@ SIGNATURES = {
     "hkp_hf_grad_workspace_bytes": (C.c_size_t, [C.c_int32]),
     "hkp_hf_grad": (C.c_int, [C.c_int64, C.c_int32, _P, _P, C.c_int32, _P, _P, _P, C.c_size_t,
                               _P]),
+    "hkp_hf_grad_noalloc": (C.c_int, [C.c_int64, C.c_int32, _P, _P, C.c_int32, _P, _P, _P]),
     "hkp_autotune": (C.c_int, [C.POINTER(hkp_grid), C.c_int32, C.c_int32, C.c_int32, C.c_int32,
                                _P, C.c_size_t, _P, C.POINTER(hkp_tune)]),
     "hkp_autotune_block": (C.c_int, [C.POINTER(hkp_grid), C.POINTER(hkp_material),

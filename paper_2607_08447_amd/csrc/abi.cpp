@@ -377,6 +377,31 @@ int hkp_gate_potential(int64_t N, int32_t G, const double* V_bg, const double* L
   });
 }
 
+int hkp_hf_grad_noalloc(int64_t N, int32_t nev, const void* psi, const double* w, int32_t G,
+                        const double* L, double* grad, void* hip_stream) {
+  if (N < 1 || nev < 1 || !psi || !w || !L || !grad) {
+    set_error("hkp_hf_grad_noalloc: invalid arguments (N >= 1, nev >= 1, non-NULL pointers)");
+    return HKP_E_ARG;
+  }
+  if (G < 1 || (size_t)G * hf_partial_bytes(1) > hf_scratch_bytes()) {
+    set_error("hkp_hf_grad_noalloc: G = " + std::to_string(G) + " outside 1..16 (the static "
+              "scratch holds " + std::to_string(hf_scratch_bytes()) + " bytes of partial sums)");
+    return HKP_E_ARG;
+  }
+  HKP_TRY(check_device());
+  return guarded([&]() {
+    double* partial = nullptr;
+    hipError_t e = hf_scratch(&partial);
+    if (e == hipSuccess)
+      e = launch_hf_grad(N, nev, psi, w, G, L, partial, grad, (hipStream_t)hip_stream);
+    if (e != hipSuccess) {
+      set_error(hipGetErrorString(e));
+      return HKP_E_HIP;
+    }
+    return HKP_OK;
+  });
+}
+
 size_t hkp_hf_grad_workspace_bytes(int32_t G) {
   if (G < 1 || G > 16) {
     set_error("hkp_hf_grad: 1 <= G <= 16");

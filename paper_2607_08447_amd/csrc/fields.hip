@@ -1,6 +1,16 @@
 // Field setup, boundary transforms, the gate -> potential map and the
 // Hellmann-Feynman gradient.
+#include <map>
+#include <mutex>
+
 #include "hkp_internal.h"
+
+// Block partial sums of the allocation-free Hellmann-Feynman gradient: one
+// value per (workgroup, gate) of the gradient kernel, 1024 x 16 doubles
+// (128 KiB), held on every device the library runs on until the process ends.
+// Host code never passes this name to a kernel: it takes the device address
+// from hkp::hf_scratch (hipGetSymbolAddress, once per device).
+static __device__ __align__(256) double scratch[1024 * 16];
 
 namespace hkp {
 
@@ -296,6 +306,29 @@ hipError_t launch_gate_potential(long long N, int G, const double* Vbg, const do
 int hf_blocks() { return 1024; }
 
 size_t hf_partial_bytes(int G) { return (size_t)hf_blocks() * G * 8; }
+
+size_t hf_scratch_bytes() { return sizeof(scratch); }
+
+hipError_t hf_scratch(double** out) {
+  static_assert(sizeof(scratch) == 1024 * kHfMaxG * sizeof(double),
+                "scratch holds hf_blocks() x kHfMaxG partial sums");
+  static std::mutex mu;
+  static std::map<int, double*> ptr;   // device ordinal -> address of its copy
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  std::lock_guard<std::mutex> lk(mu);
+  auto it = ptr.find(dev);
+  if (it == ptr.end()) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    if (p == nullptr) return hipErrorInvalidSymbol;
+    it = ptr.emplace(dev, static_cast<double*>(p)).first;
+  }
+  *out = it->second;
+  return hipSuccess;
+}
 
 hipError_t launch_hf_grad(long long N, int nev, const void* psi, const double* w, int G,
                           const double* L, double* partial, double* grad, hipStream_t s) {

@@ -118,6 +118,10 @@ hipError_t launch_internal_to_abi(int nx, int ny, int nz, double h, const double
 hipError_t launch_gate_potential(long long N, int G, const double* Vbg, const double* L,
                                  const double* Vg, double* out, hipStream_t s);
 size_t hf_partial_bytes(int G);
+// device address of this device's static partial-sum array (hf_blocks() x 16
+// doubles), looked up once per device; never allocates
+hipError_t hf_scratch(double** out);
+size_t hf_scratch_bytes();
 hipError_t launch_hf_grad(long long N, int nev, const void* psi, const double* w, int G,
                           const double* L, double* partial, double* grad, hipStream_t s);
 
