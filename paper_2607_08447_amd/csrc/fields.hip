@@ -194,33 +194,63 @@ __global__ void gate_kernel(long long N, int G, const double* Vbg, const double*
 constexpr int kHfThreads = 256;
 constexpr int kHfMaxG = 16;
 
-// grad partials: one value per (block, g); the density is formed on the fly
+// grad partials: one value per (block, g).  Items are (state n, point p) pairs
+// in state-major order, so consecutive threads read consecutive 96-byte
+// spinors (one contiguous sweep of psi per state); each thread takes two items
+// per loop trip with all their loads issued together.  p and n advance by the
+// grid stride without divisions.
 __global__ void __launch_bounds__(kHfThreads)
 hf_partial_kernel(long long N, int nev, const double2* psi, const double* w, int G,
                   const double* L, double* partial) {
   double acc[kHfMaxG];
-  for (int g = 0; g < kHfMaxG; ++g) acc[g] = 0.0;
-  for (long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x; p < N;
-       p += (long long)gridDim.x * blockDim.x) {
-    double dens = 0.0;
-    for (int n = 0; n < nev; ++n) {
-      const double2* q = psi + ((long long)n * N + p) * 6;
-      double s = 0.0;
 #pragma unroll
-      for (int c = 0; c < 6; ++c) {
-        const double2 v = q[c];
-        s = fma(v.x, v.x, fma(v.y, v.y, s));
-      }
-      dens = fma(w[n], s, dens);
+  for (int g = 0; g < kHfMaxG; ++g) acc[g] = 0.0;
+  const long long total = (long long)nev * N;
+  const long long stride = (long long)gridDim.x * blockDim.x;
+  long long j = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  long long n = j / N, p = j - n * N;
+  auto advance = [&](long long& nn, long long& pp) {
+    pp += stride;
+    while (pp >= N) {
+      pp -= N;
+      ++nn;
     }
-    for (int g = 0; g < G; ++g) acc[g] = fma(dens, L[(long long)g * N + p], acc[g]);
+  };
+  auto item = [&](long long jj, long long nn, long long pp) {
+    const double2* q = psi + jj * 6;
+    double2 v[6];
+#pragma unroll
+    for (int c = 0; c < 6; ++c) v[c] = q[c];
+    double Lg[kHfMaxG];
+#pragma unroll
+    for (int g = 0; g < kHfMaxG; ++g) Lg[g] = g < G ? L[(long long)g * N + pp] : 0.0;
+    double s = 0.0;
+#pragma unroll
+    for (int c = 0; c < 6; ++c) s = fma(v[c].x, v[c].x, fma(v[c].y, v[c].y, s));
+    const double ws = w[nn] * s;
+#pragma unroll
+    for (int g = 0; g < kHfMaxG; ++g)
+      if (g < G) acc[g] = fma(ws, Lg[g], acc[g]);
+  };
+  for (; j + stride < total; j += 2 * stride) {
+    long long n2 = n, p2 = p;
+    advance(n2, p2);
+    item(j, n, p);
+    item(j + stride, n2, p2);
+    n = n2;
+    p = p2;
+    advance(n, p);
   }
+  if (j < total) item(j, n, p);
   __shared__ double red[kHfThreads / 64][kHfMaxG];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  for (int g = 0; g < G; ++g) {
-    double v = acc[g];
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
-    if (lane == 0) red[wv][g] = v;
+#pragma unroll
+  for (int g = 0; g < kHfMaxG; ++g) {
+    if (g < G) {
+      double v = acc[g];
+      for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+      if (lane == 0) red[wv][g] = v;
+    }
   }
   __syncthreads();
   if (threadIdx.x < G) {
