@@ -195,6 +195,204 @@ gram_herm_kernel(const double* A, long long a_bstride, int nba, const double* B,
   }
 }
 
+// Hermitian Gram A^H B for blocks of nb = 16 T + 8 P vectors (P = 0 or 1), with
+// less MFMA work than gram_herm_kernel (which pads nb to whole 16-vector tiles
+// and spends four real products on every tile pair):
+//  * the last 8 vectors form one packed 16-column operand [re | im], so a pair
+//    (full tile, packed tile) costs two MFMAs and (packed, packed) one, their
+//    results combined as Re = Ar'Br + Ai'Bi, Im = Ar'Bi - Ai'Br across halves;
+//  * with A == B a diagonal tile pair needs Ar'Ar + Ai'Ai for the real part and
+//    M = Ar'Ai for the imaginary part, Im = M - M' (three MFMAs instead of four);
+//  * the next k-step's elements are loaded while the current one is multiplied.
+// For nb = 40 (A == B) a k-step costs 15 MFMAs instead of 24.  Work split and
+// the fixed-order reduction of the four waves' runs as in gram_herm_kernel.
+template <int T, int P, bool SAME>
+__global__ void __launch_bounds__(64 * 4)
+gram_hp_kernel(const double* A, long long a_bstride, const double* B, long long b_bstride,
+               long long n, long long chunk, const int* active, double* partial) {
+  constexpr int nb = 16 * T + 8 * P;
+  constexpr int NF = T * (T + 1) / 2;           // full tile pairs, ti <= tj
+  // accumulators: full pairs two each (re, im; on the diagonal with A == B: re, M),
+  // (full, packed) pairs two each (F1 = Ar'Pb, F2 = Ai'Pb), (packed, packed) one
+  constexpr int NACC = 2 * NF + 2 * T * P + P;
+  __shared__ double stage[4][2][16][17];
+  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int b = blockIdx.y;
+  if (active && !active[b]) return;
+  const int nchunks = gridDim.x;
+  const long long c0 = (long long)blockIdx.x * chunk;
+  long long c1 = c0 + chunk;
+  if (c1 > n) c1 = n;
+  long long q4 = ((c1 - c0 + 15) / 16) * 4;
+  long long e0 = c0 + wv * q4;
+  long long e1 = e0 + q4;
+  if (e1 > c1) e1 = c1;
+  if (e0 > c1) e0 = c1;
+  const int r = lane & 15, q = lane >> 4;
+  const double* pa[T + P];
+  const double* pb[T + P];
+#pragma unroll
+  for (int t = 0; t < T + P; ++t) {
+    const int v = t < T ? t * 16 + r : 16 * T + (r & 7);
+    pa[t] = A + 2 * ((long long)b * a_bstride + (long long)v * n);
+    pb[t] = B + 2 * ((long long)b * b_bstride + (long long)v * n);
+  }
+  const bool hi = r >= 8;   // packed operand: this lane supplies the imaginary half
+  d4 acc[NACC];
+#pragma unroll
+  for (int k = 0; k < NACC; ++k) acc[k] = d4{0, 0, 0, 0};
+
+  // Two k-steps per loop trip: lane (r, q) loads elements e, e + 1 (e = 8 trip + 2 q)
+  // of its vectors with one 32-byte load, so a wave's load instruction covers 8
+  // consecutive elements (128 bytes) of each of 16 vectors; k-step u of the trip
+  // multiplies element e + u.  The next trip's loads are issued before this
+  // trip's MFMAs.
+  constexpr int U = 2;
+  typedef double dv4 __attribute__((ext_vector_type(4)));
+  double2 av[U][T + P], bv[U][T + P];
+  // Full trips load without masks and without branches, so that the waits for
+  // the next trip's data come only where it is used (a select or a branch right
+  // after a load makes the compiler wait for it there); a last, partial trip
+  // clamps its addresses into the vector (n >= 2 elements) and zeroes the values
+  // past the run's end.
+  const long long elast = n >= 2 ? n - 2 : 0;
+  auto load = [&](long long trip, bool masked, double2 (&xa)[U][T + P],
+                  double2 (&xb)[U][T + P]) {
+    const long long e = e0 + 8 * trip + 2 * q;
+    const long long ec = masked ? (e < elast ? e : elast) : e;
+    const bool ok = !masked || e < e1, ok2 = !masked || e + 1 < e1;
+#pragma unroll
+    for (int t = 0; t < T + P; ++t) {
+      const dv4 va = *reinterpret_cast<const dv4*>(pa[t] + 2 * ec);
+      xa[0][t] = make_double2(ok ? va.x : 0.0, ok ? va.y : 0.0);
+      xa[1][t] = make_double2(ok2 ? va.z : 0.0, ok2 ? va.w : 0.0);
+      if constexpr (!SAME) {
+        const dv4 vb = *reinterpret_cast<const dv4*>(pb[t] + 2 * ec);
+        xb[0][t] = make_double2(ok ? vb.x : 0.0, ok ? vb.y : 0.0);
+        xb[1][t] = make_double2(ok2 ? vb.z : 0.0, ok2 ? vb.w : 0.0);
+      } else {
+        xb[0][t] = xa[0][t];
+        xb[1][t] = xa[1][t];
+      }
+    }
+  };
+  auto step = [&](const double2 (&xa)[T + P], const double2 (&xb)[T + P]) {
+    const double pbv = P ? (hi ? xb[T + P - 1].y : xb[T + P - 1].x) : 0.0;
+    const double pav = P ? (hi ? xa[T + P - 1].y : xa[T + P - 1].x) : 0.0;
+#pragma unroll
+    for (int pass = 0; pass < 2; ++pass) {
+      int k = 0;
+#pragma unroll
+      for (int ti = 0; ti < T; ++ti) {
+#pragma unroll
+        for (int tj = ti; tj < T; ++tj, k += 2) {
+          if (pass == 0) {
+            acc[k] = mfma(xa[ti].x, xb[tj].x, acc[k]);
+            acc[k + 1] = mfma(xa[ti].x, xb[tj].y, acc[k + 1]);   // A == B, diagonal: M
+          } else {
+            acc[k] = mfma(xa[ti].y, xb[tj].y, acc[k]);
+            if (!(SAME && ti == tj)) acc[k + 1] = mfma(-xa[ti].y, xb[tj].x, acc[k + 1]);
+          }
+        }
+      }
+      if constexpr (P) {
+        if (pass == 0) {
+#pragma unroll
+          for (int ti = 0; ti < T; ++ti, k += 2) {
+            acc[k] = mfma(xa[ti].x, pbv, acc[k]);
+            acc[k + 1] = mfma(xa[ti].y, pbv, acc[k + 1]);
+          }
+          acc[k] = mfma(pav, pbv, acc[k]);
+        }
+      }
+    }
+  };
+  const long long nfull = (e1 - e0) / 8;   // trips of 8 elements inside the run
+  // three register sets in rotation: the loads of trip t + 2 are issued while
+  // trip t is multiplied (trip indices past the run reload its last trip: the
+  // loads need no branch; their products are skipped)
+  double2 a1[U][T + P], b1[U][T + P], a2[U][T + P], b2[U][T + P];
+  auto clampt = [&](long long t) { return t < nfull ? t : (nfull > 0 ? nfull - 1 : 0); };
+  if (nfull > 0) {
+    load(0, false, av, bv);
+    load(clampt(1), false, a1, b1);
+  }
+  for (long long tr = 0; tr < nfull; tr += 3) {
+    load(clampt(tr + 2), false, a2, b2);
+#pragma unroll
+    for (int u = 0; u < U; ++u) step(av[u], bv[u]);
+    load(clampt(tr + 3), false, av, bv);
+    if (tr + 1 < nfull) {
+#pragma unroll
+      for (int u = 0; u < U; ++u) step(a1[u], b1[u]);
+    }
+    load(clampt(tr + 4), false, a1, b1);
+    if (tr + 2 < nfull) {
+#pragma unroll
+      for (int u = 0; u < U; ++u) step(a2[u], b2[u]);
+    }
+  }
+  if (e0 + 8 * nfull < e1) {   // the partial last trip
+    load(nfull, true, av, bv);
+#pragma unroll
+    for (int u = 0; u < U; ++u) step(av[u], bv[u]);
+  }
+
+  // stage one pair's accumulators (this wave's run), then sum the four runs and
+  // write the pair's entries of partial[b][chunk][i][j] (complex)
+  double* out = partial + 2 * (((long long)b * nchunks + blockIdx.x) * nb * nb);
+  const int ti_ = threadIdx.x >> 4, tj_ = threadIdx.x & 15;   // entry of this thread
+  auto put = [&](int m, const d4& v) {
+#pragma unroll
+    for (int g = 0; g < 4; ++g) stage[wv][m][4 * g + q][r] = v[g];
+  };
+  auto sum = [&](int m, int i, int j) {
+    double s = stage[0][m][i][j];
+#pragma unroll
+    for (int w = 1; w < 4; ++w) s += stage[w][m][i][j];
+    return s;
+  };
+  auto emit = [&](int gi, int gj, double re, double im) {
+    *reinterpret_cast<double2*>(out + 2 * ((long long)gi * nb + gj)) = make_double2(re, im);
+  };
+  int k = 0;
+#pragma unroll
+  for (int ti = 0; ti < T; ++ti) {
+#pragma unroll
+    for (int tj = ti; tj < T; ++tj, k += 2) {
+      put(0, acc[k]);
+      put(1, acc[k + 1]);
+      __syncthreads();
+      const double re = sum(0, ti_, tj_);
+      const double im = (SAME && ti == tj) ? sum(1, ti_, tj_) - sum(1, tj_, ti_)
+                                           : sum(1, ti_, tj_);
+      emit(16 * ti + ti_, 16 * tj + tj_, re, im);
+      __syncthreads();
+    }
+  }
+  if constexpr (P) {
+#pragma unroll
+    for (int ti = 0; ti < T; ++ti, k += 2) {
+      put(0, acc[k]);
+      put(1, acc[k + 1]);
+      __syncthreads();
+      if (tj_ < 8) {
+        const double re = sum(0, ti_, tj_) + sum(1, ti_, tj_ + 8);
+        const double im = sum(0, ti_, tj_ + 8) - sum(1, ti_, tj_);
+        emit(16 * ti + ti_, 16 * T + tj_, re, im);
+      }
+      __syncthreads();
+    }
+    put(0, acc[k]);
+    __syncthreads();
+    if (ti_ < 8 && tj_ < 8) {
+      const double re = sum(0, ti_, tj_) + sum(0, ti_ + 8, tj_ + 8);
+      const double im = sum(0, ti_, tj_ + 8) - sum(0, ti_ + 8, tj_);
+      emit(16 * T + ti_, 16 * T + tj_, re, im);
+    }
+  }
+}
+
 // General (non-Hermitian) Gram A^H B, balanced as above: the four waves split the
 // chunk into four runs and each computes every (A tile, B tile) pair of its run.
 // When A is the leading part of B, A's tiles are not loaded a second time.
@@ -615,7 +813,26 @@ hipError_t launch_gram(const BlockDesc& A, const BlockDesc& B, int hermitian, in
   long long chunk = (n + nchunks - 1) / nchunks;
   chunk = (chunk + 15) & ~15LL;
   const int nta = (A.nvec + 15) / 16, ntb = (B.nvec + 15) / 16;
-  if (hermitian && A.nvec == B.nvec) {
+  const bool same = A.ptr == B.ptr && A.bstride == B.bstride;
+  if (hermitian && A.nvec == B.nvec && A.nvec % 8 == 0 && A.nvec >= 16 && A.nvec <= 64) {
+    dim3 grid((unsigned)nchunks, (unsigned)batch);
+#define HKP_HP(T, P)                                                                          \
+  (same ? gram_hp_kernel<T, P, true><<<grid, 256, 0, s>>>(A.ptr, A.bstride, B.ptr, B.bstride,  \
+                                                          n, chunk, active, partial)          \
+        : gram_hp_kernel<T, P, false><<<grid, 256, 0, s>>>(A.ptr, A.bstride, B.ptr,           \
+                                                           B.bstride, n, chunk, active,        \
+                                                           partial))
+    switch (A.nvec / 8) {
+      case 2: HKP_HP(1, 0); break;
+      case 3: HKP_HP(1, 1); break;
+      case 4: HKP_HP(2, 0); break;
+      case 5: HKP_HP(2, 1); break;
+      case 6: HKP_HP(3, 0); break;
+      case 7: HKP_HP(3, 1); break;
+      default: HKP_HP(4, 0); break;
+    }
+#undef HKP_HP
+  } else if (hermitian && A.nvec == B.nvec) {
     dim3 grid((unsigned)nchunks, (unsigned)batch);
     switch (nta) {
       case 1: gram_herm_kernel<1><<<grid, 256, 0, s>>>(A.ptr, A.bstride, A.nvec, B.ptr, B.bstride, B.nvec, n, chunk, active, partial); break;
