@@ -127,6 +127,10 @@ typedef struct {
   int64_t n_stencil32, n_stencil64;      /* timed launches */
   double t_stencil32, t_stencil64;       /* summed durations (s) */
   double bytes_stencil32, bytes_stencil64; /* algorithmic bytes of the timed launches */
+  /* FP32 passes that perform two recurrence steps each (timed as above; bytes:
+   * those of the two steps, each counted as a one-step launch counts them) */
+  int64_t n_stencil32x2;
+  double t_stencil32x2, bytes_stencil32x2;
   int32_t n_graph_launches; /* replays of the recorded iteration graph (HKP_FLAG_GRAPH) */
   int32_t n_host_syncs;     /* host waits on the solver's stream (flag read-backs,
                                the spectral bound, the input check, the final wait) */
@@ -137,9 +141,12 @@ typedef struct {
   int32_t tile_y;      /* rows of the x-y tile (the tile is 64 x tile_y) */
   int32_t vgroup;      /* vectors of one tile run side by side (1: vector-major) */
   int32_t dma;         /* 1: halo-tile rows copied global -> LDS directly */
+  int32_t two_step_tx; /* FP32: tile of the two-step pass (two recurrence steps per */
+  int32_t two_step_ty; /* pass) if it beats two one-step passes, else 0 x 0 */
   int32_t reserved;
   double us_per_step;  /* measured time of one filter step over the block */
   double gbps;         /* algorithmic bytes / time */
+  double us_per_step_two; /* per recurrence step with two-step passes (0: not chosen) */
 } hkp_tune;
 
 /* ---- Self-consistent Schroedinger-Poisson loop (Sec. II.B, Fig. 2a) ----
@@ -274,6 +281,27 @@ int hkp_filter_step(const hkp_grid* grid, const hkp_material* mat, const double*
                     const void* X, const void* Y_old, void* Y, double alpha, double shift,
                     double beta, int32_t precision, void* workspace, size_t ws_bytes,
                     void* hip_stream);
+
+/* Two consecutive steps of the Chebyshev filter (Sec. II.B) in complex FP32
+ * arithmetic, H as in hkp_filter_step:
+ *     Y1 = alpha[0] (H - shift[0]) X  + beta[0] Y_old
+ *     Y2 = alpha[1] (H - shift[1]) Y1 + beta[1] X
+ * in one pass over the grid (temporal blocking: X and Y_old read once, Y1 and
+ * Y2 written once) when the two-step kernel supports the grid and field (nx a
+ * multiple of 16, B_T[2] == 0), else as two one-step passes.
+ *   X, Y1, Y2 device complex double [nvec][nx][ny][nz][6]; Y_old the same or
+ *             NULL when beta[0] == 0; Y1, Y2 distinct from each other and from
+ *             X and Y_old (HKP_E_ARG otherwise).  Operands are rounded to FP32
+ *             and the results returned in FP64.
+ *   alpha, shift, beta  host double[2], finite
+ *   workspace device, ws_bytes >= hkp_filter_step2_workspace_bytes(grid, nvec)
+ *   passes    host, may be NULL: receives 1 (one two-step pass) or 2. */
+size_t hkp_filter_step2_workspace_bytes(const hkp_grid* grid, int32_t nvec);
+int hkp_filter_step2(const hkp_grid* grid, const hkp_material* mat, const double* V_eV,
+                     const double* strain, const double B_T[3], int32_t nvec, const void* X,
+                     const void* Y_old, void* Y1, void* Y2, const double alpha[2],
+                     const double shift[2], const double beta[2], void* workspace,
+                     size_t ws_bytes, void* hip_stream, int32_t* passes);
 
 /* Y = H X with H the discretised Hamiltonian H_NI of Eq. HNI (Sec. II.C) on
  * the grid of Sec. II.B (hkp_filter_step with alpha 1, shift 0, beta 0). */

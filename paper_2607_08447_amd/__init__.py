@@ -10,7 +10,8 @@ in-tree libhkp.so and fails if it is missing.
 
 from ._lib import HkpError, lib  # noqa: F401
 from .api import (  # noqa: F401
-    SI, EigvalsFromPotential, SolveResult, apply, autotune, autotune_block, filter_step, gate_potential,
+    SI, EigvalsFromPotential, SolveResult, apply, autotune, autotune_block, filter_step,
+    filter_step2, gate_potential,
     hf_grad, solve, solve_batch, solve_sweep, workspace_bytes, poisson, occupancy, hole_density,
     sp_solve, SPResult, soi_matrix, ci_solve, CIResult, g_matrices, GMatrixResult, two_spin_model,
     poisson_preconditioner,

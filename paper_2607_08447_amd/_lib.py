@@ -59,6 +59,8 @@ class hkp_stats(C.Structure):
                 ("hx_bytes", C.c_double), ("n_stencil32", C.c_int64), ("n_stencil64", C.c_int64),
                 ("t_stencil32", C.c_double), ("t_stencil64", C.c_double),
                 ("bytes_stencil32", C.c_double), ("bytes_stencil64", C.c_double),
+                ("n_stencil32x2", C.c_int64), ("t_stencil32x2", C.c_double),
+                ("bytes_stencil32x2", C.c_double),
                 ("n_graph_launches", C.c_int32), ("n_host_syncs", C.c_int32)]
 
     def as_dict(self):
@@ -67,7 +69,9 @@ class hkp_stats(C.Structure):
 
 class hkp_tune(C.Structure):
     _fields_ = [("tile_y", C.c_int32), ("vgroup", C.c_int32), ("dma", C.c_int32),
-                ("reserved", C.c_int32), ("us_per_step", C.c_double), ("gbps", C.c_double)]
+                ("two_step_tx", C.c_int32), ("two_step_ty", C.c_int32),
+                ("reserved", C.c_int32), ("us_per_step", C.c_double), ("gbps", C.c_double),
+                ("us_per_step_two", C.c_double)]
 
 
 class hkp_pgrid(C.Structure):
@@ -138,6 +142,12 @@ SIGNATURES = {
     "hkp_filter_step": (C.c_int, [C.POINTER(hkp_grid), C.POINTER(hkp_material), _P, _P, _D,
                                   C.c_int32, _P, _P, _P, C.c_double, C.c_double, C.c_double,
                                   C.c_int32, _P, C.c_size_t, _P]),
+    "hkp_filter_step2_workspace_bytes": (C.c_size_t, [C.POINTER(hkp_grid), C.c_int32]),
+    "hkp_filter_step2": (C.c_int, [C.POINTER(hkp_grid), C.POINTER(hkp_material), _P, _P,
+                                   C.POINTER(C.c_double), C.c_int32, _P, _P, _P, _P,
+                                   C.POINTER(C.c_double), C.POINTER(C.c_double),
+                                   C.POINTER(C.c_double), _P, C.c_size_t, _P,
+                                   C.POINTER(C.c_int32)]),
     "hkp_apply": (C.c_int, [C.POINTER(hkp_grid), C.POINTER(hkp_material), _P, _P, _D, C.c_int32,
                             _P, _P, C.c_int32, _P, C.c_size_t, _P]),
     "hkp_gate_potential": (C.c_int, [C.c_int64, C.c_int32, _P, _P, _P, _P, _P]),

@@ -287,6 +287,33 @@ def filter_step(V, h, X, Y_old=None, alpha=1.0, shift=0.0, beta=0.0, strain=None
     return Y
 
 
+def filter_step2(V, h, X, Y_old=None, alpha=(1.0, 1.0), shift=(0.0, 0.0), beta=(0.0, 0.0),
+                 strain=None, B=(0.0, 0.0, 0.0), material=None):
+    """Two Chebyshev steps in FP32 arithmetic: Y1 = alpha0 (H - shift0) X + beta0 Y_old,
+    Y2 = alpha1 (H - shift1) Y1 + beta1 X on complex128 blocks [nvec, nx, ny, nz, 6].
+    Returns (Y1, Y2, passes) with passes = 1 when one two-step pass did both."""
+    V = _dev(V, torch.float64)
+    shape = tuple(V.shape)
+    X = _dev(X, torch.complex128)
+    nvec = X.shape[0]
+    if tuple(X.shape[1:]) != shape + (6,):
+        raise ValueError("X must be [nvec, nx, ny, nz, 6]")
+    Y_old = _dev(Y_old, torch.complex128)
+    strain = _dev(strain, torch.float64)
+    g = _grid(shape, h)
+    need = L.lib.hkp_filter_step2_workspace_bytes(C.byref(g), nvec)
+    ws = torch.empty(need, dtype=torch.uint8, device="cuda")
+    Y1 = torch.empty_like(X)
+    Y2 = torch.empty_like(X)
+    two = lambda v: (C.c_double * 2)(*[float(x) for x in v])
+    passes = C.c_int32(0)
+    L.check(L.lib.hkp_filter_step2(C.byref(g), C.byref(_material(material)), _ptr(V),
+                                   _ptr(strain), _B(B), nvec, _ptr(X), _ptr(Y_old), _ptr(Y1),
+                                   _ptr(Y2), two(alpha), two(shift), two(beta), _ptr(ws),
+                                   C.c_size_t(need), _stream(), C.byref(passes)))
+    return Y1, Y2, int(passes.value)
+
+
 def apply(V, h, X, strain=None, B=(0.0, 0.0, 0.0), precision="fp64", material=None):
     """Y = H X."""
     return filter_step(V, h, X, None, 1.0, 0.0, 0.0, strain, B, precision, material)
@@ -616,7 +643,8 @@ def autotune(shape, h, nb, precision="fp64", with_strain=True, with_field=True):
     L.check(L.lib.hkp_autotune(C.byref(g), nb, prec, int(with_strain), int(with_field), _ptr(ws),
                                C.c_size_t(need), _stream(), C.byref(t)))
     return dict(tile_y=t.tile_y, vgroup=t.vgroup, dma=t.dma, us_per_step=t.us_per_step,
-                gbps=t.gbps)
+                gbps=t.gbps, two_step=(t.two_step_tx, t.two_step_ty),
+                us_per_step_two=t.us_per_step_two)
 
 
 def autotune_block(V, h, nev, strain=None, B=(0.0, 0.0, 0.0), candidates=None, tol=1e-8,

@@ -18,7 +18,7 @@ OBJ = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libhkp.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
-SOURCES = ["stencil.hip", "fields.hip", "blas.hip", "eig.hip", "sp.hip", "spinfree.hip",
+SOURCES = ["stencil.hip", "stencil2.hip", "fields.hip", "blas.hip", "eig.hip", "sp.hip", "spinfree.hip",
            "gmatrix.hip",
            "solver.cpp",
            "sp_loop.cpp", "abi.cpp", "autotune.cpp"]

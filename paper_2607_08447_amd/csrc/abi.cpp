@@ -353,6 +353,71 @@ int hkp_filter_step(const hkp_grid* grid, const hkp_material* mat, const double*
   return guarded([&]() { return run_filter_step(a); });
 }
 
+size_t hkp_filter_step2_workspace_bytes(const hkp_grid* grid, int32_t nvec) {
+  if (check_grid(grid) != HKP_OK) return 0;
+  if (nvec < 1) {
+    set_error("nvec >= 1 required");
+    return 0;
+  }
+  return apply2_bytes(*grid, nvec);
+}
+
+int hkp_filter_step2(const hkp_grid* grid, const hkp_material* mat, const double* V_eV,
+                     const double* strain, const double B_T[3], int32_t nvec, const void* X,
+                     const void* Y_old, void* Y1, void* Y2, const double alpha[2],
+                     const double shift[2], const double beta[2], void* workspace,
+                     size_t ws_bytes, void* hip_stream, int32_t* passes) {
+  HKP_TRY(check_grid(grid));
+  HKP_TRY(check_material(mat));
+  HKP_TRY(check_field(B_T));
+  if (nvec < 1 || !V_eV || !X || !Y1 || !Y2 || !workspace || !alpha || !shift || !beta) {
+    set_error("nvec >= 1 and non-NULL V, X, Y1, Y2, alpha, shift, beta, workspace required");
+    return HKP_E_ARG;
+  }
+  for (int i = 0; i < 2; ++i)
+    if (!std::isfinite(alpha[i]) || !std::isfinite(shift[i]) || !std::isfinite(beta[i])) {
+      set_error("alpha, shift, beta must be finite");
+      return HKP_E_ARG;
+    }
+  if (beta[0] != 0.0 && !Y_old) {
+    set_error("beta[0] != 0 needs Y_old");
+    return HKP_E_ARG;
+  }
+  if (Y1 == Y2 || Y1 == X || Y2 == X || (Y_old && (Y1 == Y_old || Y2 == Y_old))) {
+    set_error("Y1 and Y2 must be distinct from each other and from X and Y_old");
+    return HKP_E_ARG;
+  }
+  if (ws_bytes < apply2_bytes(*grid, nvec)) {
+    set_error("workspace too small: need " + std::to_string(apply2_bytes(*grid, nvec)) +
+              " bytes");
+    return HKP_E_WORKSPACE;
+  }
+  HKP_TRY(check_device());
+  Filter2Args a{};
+  a.grid = *grid;
+  a.mat = *mat;
+  a.V = V_eV;
+  a.strain = strain;
+  for (int i = 0; i < 3; ++i) a.B[i] = B_T[i];
+  a.nvec = nvec;
+  a.X = X;
+  a.Y_old = Y_old;
+  a.Y1 = Y1;
+  a.Y2 = Y2;
+  for (int i = 0; i < 2; ++i) {
+    a.alpha[i] = alpha[i];
+    a.shift[i] = shift[i];
+    a.beta[i] = beta[i];
+  }
+  a.workspace = workspace;
+  a.stream = hip_stream;
+  a.st = autotuned(*grid, nvec, true, stencil_variant(strain != nullptr, B_T));
+  int np = 0;
+  const int rc = guarded([&]() { return run_filter_step2(a, &np); });
+  if (passes) *passes = np;
+  return rc;
+}
+
 int hkp_apply(const hkp_grid* grid, const hkp_material* mat, const double* V_eV,
               const double* strain, const double B_T[3], int32_t nvec, const void* X, void* Y,
               int32_t precision, void* workspace, size_t ws_bytes, void* hip_stream) {

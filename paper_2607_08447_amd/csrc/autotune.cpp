@@ -18,6 +18,8 @@
 
 namespace hkp {
 
+StencilTune autotuned_shape(const hkp_grid& g, int nb, bool mixed, int variant);
+
 namespace {
 
 using Key = std::tuple<int, int, int, int, int>;   // nx, ny, nz, nb|nev, mixed
@@ -27,7 +29,8 @@ std::map<TuneKey, StencilTune> g_cache;
 
 size_t al(size_t x) { return (x + 255) & ~(size_t)255; }
 
-// HKP_STENCIL="tile_y,vgroup,dma[,zsplit]" forces one launch shape (tests of a variant)
+// HKP_STENCIL="tile_y,vgroup,dma[,zsplit]" forces one launch shape (tests of a variant);
+// HKP_STENCIL2="tile_x,tile_y" the two-step kernel's tile ("0,0": one step per pass)
 bool forced(StencilTune* t) {
   const char* e = std::getenv("HKP_STENCIL");
   if (!e || !e[0]) return false;
@@ -36,6 +39,15 @@ bool forced(StencilTune* t) {
   if (n < 3) return false;
   *t = f;
   return true;
+}
+void forced2(StencilTune* t) {
+  const char* e = std::getenv("HKP_STENCIL2");
+  if (!e || !e[0]) return;
+  int tx = 0, ty = 0;
+  if (std::sscanf(e, "%d,%d", &tx, &ty) == 2) {
+    t->t2x = tx;
+    t->t2y = ty;
+  }
 }
 
 // block size per (nx, ny, nz, nev, mixed), set by hkp_autotune_block
@@ -118,6 +130,25 @@ int stencil_variant(bool strain, const double B[3]) {
 }
 
 StencilTune autotuned(const hkp_grid& g, int nb, bool mixed, int variant) {
+  StencilTune t = autotuned_shape(g, nb, mixed, variant);
+  forced2(&t);
+  return t;
+}
+
+bool two_step_tuned(const hkp_grid& g, int nb) {
+  StencilTune f;
+  forced2(&f);
+  if (f.t2x > 0) return true;
+  if (std::getenv("HKP_STENCIL2")) return false;   // forced off ("0,0")
+  std::lock_guard<std::mutex> lk(g_mu);
+  for (int v = 0; v < 6; ++v) {
+    auto it = g_cache.find(TuneKey{g.nx, g.ny, g.nz, nb, 1, v});
+    if (it != g_cache.end() && it->second.t2x > 0) return true;
+  }
+  return false;
+}
+
+StencilTune autotuned_shape(const hkp_grid& g, int nb, bool mixed, int variant) {
   StencilTune t;
   if (forced(&t)) return t;
   std::lock_guard<std::mutex> lk(g_mu);
@@ -222,6 +253,58 @@ int run_autotune(const hkp_grid& g, int nb, bool mixed, bool strain, int field, 
       best.dma = dma;
     }
   }
+  // two-step passes (FP32 filter): faster than two one-step passes of the best shape?
+  double best2_us = 0.0;
+  if (mixed && field != 2 && two_step_grid(g.nx, 6)) {
+    void* Y1 = take((size_t)nb * n6 * esz);
+    void* Y2 = take((size_t)nb * n6 * esz);
+    if (off <= ws_bytes) {
+      if (hipMemsetAsync(Y1, 0, 2 * al((size_t)nb * n6 * esz), s) != hipSuccess) return HKP_E_HIP;
+      double b2 = 2.0 * best_us;
+      for (int tx : {16, 32})
+      for (int ty : {8, 12}) {
+        Stencil2Launch a{};
+        a.nx = g.nx;
+        a.ny = g.ny;
+        a.nz = g.nz;
+        a.nvec = nb;
+        a.batch = 1;
+        a.in = X;
+        a.old = O;
+        a.out1 = Y1;
+        a.out2 = Y2;
+        a.D = D;
+        a.strain = strain;
+        a.wtab = field ? wt : nullptr;
+        a.vtab = field ? vt : nullptr;
+        a.host1[0] = a.host2[0] = 1.0;
+        a.host1[1] = a.host2[1] = 0.5;
+        a.host1[2] = a.host2[2] = -1.0;
+        a.tile_x = tx;
+        a.tile_y = ty;
+        a.vgroup = best.vgroup;
+        if (!stencil2_supported(a)) continue;
+        if (launch_stencil2(a, c, s) != hipSuccess) continue;   // warm-up
+        const int reps = 5;
+        (void)hipEventRecord(e0, s);
+        for (int r = 0; r < reps; ++r) (void)launch_stencil2(a, c, s);
+        (void)hipEventRecord(e1, s);
+        (void)hipEventSynchronize(e1);
+        float ms = 0;
+        (void)hipEventElapsedTime(&ms, e0, e1);
+        const double us = 1e3 * ms / reps;
+        if (dbg && dbg[0] == '1')
+          std::fprintf(stderr, "[hkp tune] two-step %d x %d: %.1f us (one-step pair %.1f us)\n",
+                       tx, ty, us, 2.0 * best_us);
+        if (us < b2) {
+          b2 = us;
+          best.t2x = tx;
+          best.t2y = ty;
+          best2_us = us;
+        }
+      }
+    }
+  }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   {
@@ -231,7 +314,10 @@ int run_autotune(const hkp_grid& g, int nb, bool mixed, bool strain, int field, 
   out->tile_y = best.tile_y;
   out->vgroup = best.vgroup;
   out->dma = best.dma;
+  out->two_step_tx = best.t2x;
+  out->two_step_ty = best.t2y;
   out->reserved = 0;
+  out->us_per_step_two = best2_us > 0 ? best2_us / 2.0 : 0.0;
   out->us_per_step = best_us;
   // algorithmic bytes of one filter step: read X and Y_old, write Y, plus fields
   const double bytes = 3.0 * nb * n6 * esz + (double)N * (mixed ? 28 : 56);

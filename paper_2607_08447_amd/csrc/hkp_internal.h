@@ -99,6 +99,37 @@ struct StencilLaunch {
 hipError_t launch_stencil(const StencilLaunch& a, const StencilConsts<double>& c,
                           hipStream_t s);
 
+// Two Chebyshev steps in one pass (FP32): Y1 = alpha1 (H - shift1) Y0 + beta1 Y_old,
+// Y2 = alpha2 (H - shift2) Y1 + beta2 Y0, coefficients per member from the device
+// table.  Y1 and Y2 must be distinct from Y0 and Y_old.
+struct Stencil2Launch {
+  int nx, ny, nz;
+  int nvec, batch;
+  const void* in;        // Y0, complex float
+  const void* old;       // Y_old
+  void* out1;            // Y1
+  void* out2;            // Y2
+  long long bstride;     // complex elements between Hamiltonians (all four blocks)
+  const void* D;         // on-site fields, float
+  long long D_bstride;
+  int strain;
+  const void* wtab;      // float phase tables, or null (B = 0)
+  const void* vtab;
+  int phase_general;     // Bz != 0: not supported by this kernel
+  const double* coef1;   // [batch][...]: alpha, shift, beta of the first step, or null
+  const double* coef2;   // of the second (both null: host1 / host2 below)
+  int coef_stride;
+  double host1[3], host2[3];
+  const int* active;
+  const int* lock;
+  const int* work;
+  int tile_x, tile_y;    // 16 x 12, 16 x 8 or 32 x 8; nx % tile_x == 0
+  int vgroup;
+};
+bool stencil2_supported(const Stencil2Launch& a);
+hipError_t launch_stencil2(const Stencil2Launch& a, const StencilConsts<double>& c,
+                           hipStream_t s);
+
 // ---------------------------------------------------------------------------
 // field setup and boundary transforms
 // ---------------------------------------------------------------------------

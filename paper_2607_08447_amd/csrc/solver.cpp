@@ -49,8 +49,9 @@ constexpr int kDotParts = 256;
 constexpr int kResParts = 64;
 
 struct Layout {
-  size_t D64, D32, w64, v64, w32, v32, X, W, A32, B32, gram, mat1, mat2, theta, lam, r2, rpart,
-      coef, bounds, flags, active, act32, act64, lock, work, again, status, lal, lnrm, lpart, total;
+  size_t D64, D32, w64, v64, w32, v32, X, W, A32, B32, C32, E32, gram, mat1, mat2, theta, lam,
+      r2, rpart, coef, bounds, flags, active, act32, act64, lock, work, again, status, lal, lnrm,
+      lpart, total;
 };
 
 Layout make_layout(const Plan& p) {
@@ -74,6 +75,10 @@ Layout make_layout(const Plan& p) {
   if (p.mixed) {
     L.A32 = take(B * p.nb * n6 * 8);
     L.B32 = take(B * p.nb * n6 * 8);
+    if (p.two_step) {   // the two outputs of a two-step pass
+      L.C32 = take(B * p.nb * n6 * 8);
+      L.E32 = take(B * p.nb * n6 * 8);
+    }
   }
   L.gram = take(gram_partial_bytes(p.nb, n6, p.batch));
   L.mat1 = take(B * p.nb * p.nb * 16);
@@ -148,8 +153,8 @@ struct StencilStats {
   std::vector<int> kind;        // 0: FP32 stencil, 1: FP64
   std::vector<double> bytes;
   size_t used = 0;
-  double hx_bytes = 0, t32 = 0, t64 = 0, b32 = 0, b64 = 0;
-  long long n32 = 0, n64 = 0;
+  double hx_bytes = 0, t32 = 0, t64 = 0, b32 = 0, b64 = 0, t32x2 = 0, b32x2 = 0;
+  long long n32 = 0, n64 = 0, n32x2 = 0;
   ~StencilStats() {
     for (auto e : ev) (void)hipEventDestroy(e);
   }
@@ -184,13 +189,45 @@ struct StencilStats {
     bytes[used] = b;
     ++used;
   }
+  // a two-step pass: algorithmic bytes of the two recurrence steps it performs
+  // (each step: its blocks read and written plus the fields, as a one-step pass)
+  void launch2(const Stencil2Launch& a, const StencilConsts<double>& c, hipStream_t s,
+               long long N, int active_members, double nvec_done = -1) {
+    if (nvec_done < 0) nvec_done = (double)active_members * a.nvec;
+    const double b = 2.0 * ((double)N * 6 * nvec_done * 3 * 8 +
+                            (double)active_members * N * (a.strain ? 6 : 1) * 4);
+    hx_bytes += b;
+    if (!timed) {
+      HKP_CHECK(launch_stencil2(a, c, s));
+      return;
+    }
+    if (2 * used + 2 > ev.size()) {
+      hipEvent_t e0, e1;
+      HKP_CHECK(hipEventCreate(&e0));
+      HKP_CHECK(hipEventCreate(&e1));
+      ev.push_back(e0);
+      ev.push_back(e1);
+      kind.push_back(0);
+      bytes.push_back(0);
+    }
+    HKP_CHECK(hipEventRecord(ev[2 * used], s));
+    HKP_CHECK(launch_stencil2(a, c, s));
+    HKP_CHECK(hipEventRecord(ev[2 * used + 1], s));
+    kind[used] = 2;
+    bytes[used] = b;
+    ++used;
+  }
   void collect() {
     if (!timed || used == 0) return;
     HKP_CHECK(hipEventSynchronize(ev[2 * used - 1]));
     for (size_t i = 0; i < used; ++i) {
       float ms = 0;
       HKP_CHECK(hipEventElapsedTime(&ms, ev[2 * i], ev[2 * i + 1]));
-      if (kind[i]) {
+      if (kind[i] == 2) {
+        t32x2 += ms * 1e-3;
+        b32x2 += bytes[i];
+        ++n32x2;
+      } else if (kind[i]) {
         t64 += ms * 1e-3;
         b64 += bytes[i];
         ++n64;
@@ -309,12 +346,40 @@ void filter32(const Ctx& c, const int* active, int m) {
   HKP_CHECK(launch_cheb_first(c.blk(c.L.X, c.p.nb), c.blk(c.L.W, c.p.nb), A, 0, c.bstride(),
                               c.p.batch, c.at<double>(c.L.coef), kstride, active,
                               c.at<int>(c.L.lock), c.s));
+  // two-step passes for the middle of the recurrence when tuned for this grid
+  Stencil2Launch t2{};
+  bool two = false;
+  if (c.p.two_step && c.p.st.t2x > 0) {
+    t2.nx = c.p.nx;
+    t2.ny = c.p.ny;
+    t2.nz = c.p.nz;
+    t2.nvec = c.p.nb;
+    t2.batch = c.p.batch;
+    t2.bstride = c.bstride();
+    t2.D = c.at<float>(c.L.D32);
+    t2.D_bstride = 6LL * c.p.N;
+    t2.strain = c.strain;
+    if (c.field) {
+      t2.wtab = c.at<float>(c.L.w32);
+      t2.vtab = c.at<float>(c.L.v32);
+      t2.phase_general = c.field_z;
+    }
+    t2.coef_stride = kstride;
+    t2.active = active;
+    t2.lock = c.at<int>(c.L.lock);
+    t2.work = c.work(0);
+    t2.tile_x = c.p.st.t2x;
+    t2.tile_y = c.p.st.t2y;
+    t2.vgroup = c.p.st.vgroup;
+    two = stencil2_supported(t2);
+  }
+  float* spare[2] = {two ? c.at<float>(c.L.C32) : nullptr, two ? c.at<float>(c.L.E32) : nullptr};
   // step k: in = Y_k (FP32), old = Y_{k-1} (X in FP64 for k = 1), out = Y_{k+1}
   const void* in = A;
   const void* old = c.at<double>(c.L.X);
   int old64 = 1;
   float* free32 = Bf;
-  for (int k = 1; k < m; ++k) {
+  auto one_step = [&](int k) {
     const bool last = k == m - 1;
     StencilLaunch a = base_launch(c, false, c.p.nb);
     a.in = in;
@@ -335,7 +400,31 @@ void filter32(const Ctx& c, const int* active, int m) {
     old = in;
     old64 = 0;
     in = out;
+  };
+  int k = 1;
+  if (k < m) one_step(k++);   // reads X (FP64) as Y_0
+  if (two) {
+    // steps 2 .. m-2 in pairs (one step first when their count is odd); a pair
+    // writes the two FP32 blocks it does not read
+    if (((m - 3) & 1) && k < m - 1) one_step(k++);
+    while (k + 1 < m - 1) {
+      t2.in = in;
+      t2.old = old;
+      t2.out1 = spare[0];
+      t2.out2 = spare[1];
+      t2.coef1 = c.at<double>(c.L.coef) + 4 * k;
+      t2.coef2 = c.at<double>(c.L.coef) + 4 * (k + 1);
+      c.ss->launch2(t2, c.consts, c.s, c.p.N, c.active_members, c.filtered_vectors);
+      float* was_in = (float*)in;
+      float* was_old = (float*)old;
+      old = spare[0];
+      in = spare[1];
+      spare[0] = was_in;
+      spare[1] = was_old;
+      k += 2;
+    }
   }
+  while (k < m) one_step(k++);
 }
 
 // one SVQB pass on X; `again` (optional) receives the per-member need for a second pass
@@ -479,6 +568,7 @@ Plan make_plan(const hkp_grid& g, const hkp_opts& o, int batch) {
   if (m > kKmax) m = kKmax;
   p.degree = m;
   p.mixed = o.precision == HKP_PREC_MIXED;
+  p.two_step = p.mixed && two_step_grid(p.nx, p.ncomp) && two_step_tuned(g, p.nb);
   return p;
 }
 
@@ -785,6 +875,9 @@ int run_solve(const SolveArgs& A, hkp_stats* stats) {
     stats->t_stencil64 = sst.t64;
     stats->bytes_stencil32 = sst.b32;
     stats->bytes_stencil64 = sst.b64;
+    stats->n_stencil32x2 = sst.n32x2;
+    stats->t_stencil32x2 = sst.t32x2;
+    stats->bytes_stencil32x2 = sst.b32x2;
     stats->n_graph_launches = n_graph;
     stats->n_host_syncs = n_sync;
     stats->seconds =
@@ -866,6 +959,125 @@ int run_filter_step(const FilterArgs& A) {
   a.fp64 = fp64;
   HKP_CHECK(launch_stencil(a, make_consts(A.mat, g.h_nm, A.B), s));
   HKP_CHECK(launch_internal_to_abi(g.nx, g.ny, g.nz, g.h_nm, A.B, A.nvec, 1, Yi, 0, A.Y, 0, s));
+  return HKP_OK;
+}
+
+// two recurrence steps (FP32) in the ABI layout: X, Y_old -> Y1, Y2
+size_t apply2_bytes(const hkp_grid& g, int nvec) {
+  const size_t N = (size_t)g.nx * g.ny * g.nz;
+  const size_t n6 = 6 * N;
+  size_t b = 0;
+  b += align_up(6 * N * 8) + align_up(6 * N * 4);                     // D64, D32
+  b += align_up((size_t)g.nz * 16) + align_up((size_t)g.nz * g.nx * 16);
+  b += align_up((size_t)g.nz * 8) + align_up((size_t)g.nz * g.nx * 8);
+  b += 4 * align_up((size_t)nvec * n6 * 8);                           // X, Old, Y1, Y2 (FP32)
+  b += align_up((size_t)nvec * n6 * 16);                              // FP64 staging
+  return b;
+}
+
+int run_filter_step2(const Filter2Args& A, int* passes) {
+  const hkp_grid& g = A.grid;
+  const size_t N = (size_t)g.nx * g.ny * g.nz, n6 = 6 * N;
+  char* ws = reinterpret_cast<char*>(A.workspace);
+  hipStream_t s = reinterpret_cast<hipStream_t>(A.stream);
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    char* p = ws + off;
+    off += align_up(bytes);
+    return p;
+  };
+  double* D64 = (double*)take(6 * N * 8);
+  float* D32 = (float*)take(6 * N * 4);
+  double* w64 = (double*)take((size_t)g.nz * 16);
+  double* v64 = (double*)take((size_t)g.nz * g.nx * 16);
+  float* w32 = (float*)take((size_t)g.nz * 8);
+  float* v32 = (float*)take((size_t)g.nz * g.nx * 8);
+  float* Xf = (float*)take((size_t)A.nvec * n6 * 8);
+  float* Of = (float*)take((size_t)A.nvec * n6 * 8);
+  float* Y1f = (float*)take((size_t)A.nvec * n6 * 8);
+  float* Y2f = (float*)take((size_t)A.nvec * n6 * 8);
+  double* Yd = (double*)take((size_t)A.nvec * n6 * 16);
+  const bool field = A.B[0] != 0.0 || A.B[1] != 0.0 || A.B[2] != 0.0;
+  const StencilConsts<double> consts = make_consts(A.mat, g.h_nm, A.B);
+  HKP_CHECK(launch_onsite(A.mat, g.nx, g.ny, g.nz, 1, A.V, 0, A.strain, D64, D32, 0, s));
+  if (field) HKP_CHECK(launch_phase_tables(g.nx, g.nz, g.h_nm, A.B, w64, v64, w32, v32, s));
+  HKP_CHECK(launch_abi_to_internal(g.nx, g.ny, g.nz, g.h_nm, A.B, A.nvec, A.X, Xf, 1, s));
+  const bool has_old = A.Y_old != nullptr && A.beta[0] != 0.0;
+  if (has_old)
+    HKP_CHECK(launch_abi_to_internal(g.nx, g.ny, g.nz, g.h_nm, A.B, A.nvec, A.Y_old, Of, 1, s));
+
+  Stencil2Launch t2{};
+  t2.nx = g.nx;
+  t2.ny = g.ny;
+  t2.nz = g.nz;
+  t2.nvec = A.nvec;
+  t2.batch = 1;
+  t2.in = Xf;
+  t2.old = has_old ? Of : Xf;   // not read when beta[0] == 0
+  t2.out1 = Y1f;
+  t2.out2 = Y2f;
+  t2.bstride = 0;
+  t2.D = D32;
+  t2.D_bstride = 0;
+  t2.strain = A.strain != nullptr;
+  if (field) {
+    t2.wtab = w32;
+    t2.vtab = v32;
+    t2.phase_general = A.B[2] != 0.0;
+  }
+  for (int i = 0; i < 3; ++i) {
+    t2.host1[i] = i == 0 ? A.alpha[0] : (i == 1 ? A.shift[0] : (has_old ? A.beta[0] : 0.0));
+    t2.host2[i] = i == 0 ? A.alpha[1] : (i == 1 ? A.shift[1] : A.beta[1]);
+  }
+  t2.tile_x = A.st.t2x > 0 ? A.st.t2x : 16;
+  t2.tile_y = A.st.t2x > 0 ? A.st.t2y : (g.ny >= 12 ? 12 : 8);
+  t2.vgroup = A.st.vgroup;
+  if (two_step_grid(g.nx, 6) && stencil2_supported(t2)) {
+    HKP_CHECK(launch_stencil2(t2, consts, s));
+    *passes = 1;
+  } else {
+    // two one-step passes, FP32 throughout
+    StencilLaunch a{};
+    a.nx = g.nx;
+    a.ny = g.ny;
+    a.nz = g.nz;
+    a.nvec = A.nvec;
+    a.batch = 1;
+    a.D = D32;
+    a.strain = A.strain != nullptr;
+    if (field) {
+      a.wtab = w32;
+      a.vtab = v32;
+      a.phase_general = A.B[2] != 0.0;
+    }
+    a.tile_y = A.st.tile_y;
+    a.vgroup = A.st.vgroup;
+    a.dma = A.st.dma;
+    a.zsplit = A.st.zsplit;
+    a.fp64 = 0;
+    a.in = Xf;
+    a.old = has_old ? Of : nullptr;
+    a.old_fp64 = 0;
+    a.out = Y1f;
+    a.out_fp64 = 0;
+    a.coef.alpha = A.alpha[0];
+    a.coef.shift = A.shift[0];
+    a.coef.beta = has_old ? A.beta[0] : 0.0;
+    HKP_CHECK(launch_stencil(a, consts, s));
+    a.in = Y1f;
+    a.old = Xf;
+    a.out = Y2f;
+    a.coef.alpha = A.alpha[1];
+    a.coef.shift = A.shift[1];
+    a.coef.beta = A.beta[1];
+    HKP_CHECK(launch_stencil(a, consts, s));
+    *passes = 2;
+  }
+  const long long cnt = 2LL * A.nvec * (long long)n6;   // real scalars
+  HKP_CHECK(launch_cast(Y1f, 0, Yd, 1, cnt, s));
+  HKP_CHECK(launch_internal_to_abi(g.nx, g.ny, g.nz, g.h_nm, A.B, A.nvec, 1, Yd, 0, A.Y1, 0, s));
+  HKP_CHECK(launch_cast(Y2f, 0, Yd, 1, cnt, s));
+  HKP_CHECK(launch_internal_to_abi(g.nx, g.ny, g.nz, g.h_nm, A.B, A.nvec, 1, Yd, 0, A.Y2, 0, s));
   return HKP_OK;
 }
 

@@ -20,7 +20,14 @@ struct StencilTune {
   int vgroup = 1;
   int dma = 0;
   int zsplit = 1;   // 0 never, 1 when a launch has few live workgroups, 2 always
+  // FP32 filter: tile of the two-step kernel (two recurrence steps per pass),
+  // 0 = one step per pass
+  int t2x = 0, t2y = 0;
 };
+
+// the FP32 filter of this grid may run two steps per pass (spinor vectors,
+// nx a multiple of the two-step kernel's tile width)
+inline bool two_step_grid(int nx, int ncomp) { return ncomp == 6 && nx % 16 == 0; }
 
 struct Plan {
   int nx, ny, nz;
@@ -30,6 +37,7 @@ struct Plan {
   int batch, nev, nb, degree;   // degree: fixed value or the ramp's maximum
   bool degree_fixed;
   bool mixed;
+  bool two_step;   // FP32 filter in two-step passes (the workspace holds their outputs)
   StencilTune st;
 };
 
@@ -86,10 +94,33 @@ size_t plan_bytes(const Plan& p);
 int run_solve(const SolveArgs& a, hkp_stats* stats);
 size_t apply_bytes(const hkp_grid& g, int nvec);
 int run_filter_step(const FilterArgs& a);
+// two recurrence steps in FP32 (one pass when the two-step kernel supports the
+// grid and field, else two); *passes receives 1 or 2
+struct Filter2Args {
+  hkp_grid grid;
+  hkp_material mat;
+  const double* V;
+  const double* strain;
+  double B[3];
+  int nvec;
+  const void* X;
+  const void* Y_old;
+  void* Y1;
+  void* Y2;
+  double alpha[2], shift[2], beta[2];
+  void* workspace;
+  void* stream;
+  StencilTune st;
+};
+size_t apply2_bytes(const hkp_grid& g, int nvec);
+int run_filter_step2(const Filter2Args& A, int* passes);
 int guarded(const std::function<int()>& f);
 // stencil variant of a launch: strain on/off and the link-phase kind
 int stencil_variant(bool strain, const double B[3]);
 StencilTune autotuned(const hkp_grid& g, int nb, bool mixed, int variant);
+// the FP32 filter of this grid and block size runs in two-step passes: the
+// autotuner chose them for some variant (or HKP_STENCIL2 forces a tile)
+bool two_step_tuned(const hkp_grid& g, int nb);
 int run_autotune(const hkp_grid& g, int nb, bool mixed, bool strain, int field, void* ws,
                  size_t ws_bytes, void* stream, hkp_tune* out);
 

@@ -291,3 +291,26 @@ def test_poisson_preconditioner_choice_and_gmatrix_validation():
                 L.hkp_st_opts((C.c_double * 3)(0.0, 0.0, 1.0), 0.0, 0.0),
                 L.hkp_st_opts((C.c_double * 3)(0.0, 0.0, 1.0), float("nan"), 0.0)):
         assert L.lib.hkp_st_model(fake, fake, C.byref(bad), 4, fake, fake, None, None) == L.HKP_E_ARG
+
+
+def test_two_step_filter_rejects_bad_arguments():
+    """hkp_filter_step2 checks its outputs for aliasing, beta[0] without Y_old
+    and the workspace size before any GPU work."""
+    L, g, m, o = _structs()
+    fake = C.c_void_p(0x1000)
+    other = C.c_void_p(0x2000)
+    third = C.c_void_p(0x3000)
+    two = lambda a, b: (C.c_double * 2)(a, b)
+    B = (C.c_double * 3)(0.0, 0.0, 0.0)
+    need = L.lib.hkp_filter_step2_workspace_bytes(C.byref(g), 2)
+    assert need > 4 * 2 * 6 * 640 * 8
+    args = lambda X, Yo, Y1, Y2, beta, ws: (C.byref(g), C.byref(m), fake, None, B, 2, X, Yo, Y1,
+                                             Y2, two(1, 1), two(0, 0), beta, fake, ws, None,
+                                             None)
+    assert L.lib.hkp_filter_step2(*args(fake, None, other, other, two(0, 0), need)) == L.HKP_E_ARG
+    assert b"distinct" in L.lib.hkp_last_error()
+    assert L.lib.hkp_filter_step2(*args(fake, None, fake, other, two(0, 0), need)) == L.HKP_E_ARG
+    assert L.lib.hkp_filter_step2(*args(fake, None, other, third, two(0.5, 0), need)) == L.HKP_E_ARG
+    assert b"Y_old" in L.lib.hkp_last_error()
+    assert L.lib.hkp_filter_step2(*args(fake, None, other, third, two(0, 0),
+                                        need - 1)) == L.HKP_E_WORKSPACE
