@@ -275,6 +275,7 @@ int run_autotune(const hkp_grid& g, int nb, bool mixed, bool strain, int field, 
         a.out2 = Y2;
         a.D = D;
         a.strain = strain;
+        a.zero = X;   // the timing blocks are all zero
         a.wtab = field ? wt : nullptr;
         a.vtab = field ? vt : nullptr;
         a.host1[0] = a.host2[0] = 1.0;

@@ -113,6 +113,7 @@ struct Stencil2Launch {
   const void* D;         // on-site fields, float
   long long D_bstride;
   int strain;
+  const void* zero;      // >= 16 bytes of zeros in device memory
   const void* wtab;      // float phase tables, or null (B = 0)
   const void* vtab;
   int phase_general;     // Bz != 0: not supported by this kernel

@@ -51,7 +51,7 @@ constexpr int kResParts = 64;
 struct Layout {
   size_t D64, D32, w64, v64, w32, v32, X, W, A32, B32, C32, E32, gram, mat1, mat2, theta, lam,
       r2, rpart, coef, bounds, flags, active, act32, act64, lock, work, again, status, lal, lnrm,
-      lpart, total;
+      lpart, zero, total;
 };
 
 Layout make_layout(const Plan& p) {
@@ -100,6 +100,7 @@ Layout make_layout(const Plan& p) {
   L.lal = take((size_t)kLanczosSteps * B * 16);
   L.lnrm = take((size_t)(kLanczosSteps + 1) * B * 16);
   L.lpart = take(B * kDotParts * 16);
+  L.zero = take(256);   // zeros (the hard wall's values for the two-step copies)
   L.total = off;
   return L;
 }
@@ -365,6 +366,7 @@ void filter32(const Ctx& c, const int* active, int m) {
       t2.phase_general = c.field_z;
     }
     t2.coef_stride = kstride;
+    t2.zero = c.at<float>(c.L.zero);
     t2.active = active;
     t2.lock = c.at<int>(c.L.lock);
     t2.work = c.work(0);
@@ -629,6 +631,7 @@ int run_solve(const SolveArgs& A, hkp_stats* stats) {
                                   c.at<double>(c.L.v64), c.at<float>(c.L.w32),
                                   c.at<float>(c.L.v32), c.s));
   HKP_CHECK(launch_fill_int(c.at<int>(c.L.flags), 8 * p.batch, 0, c.s));
+  HKP_CHECK(launch_fill_int(c.at<int>(c.L.zero), 64, 0, c.s));
   HKP_CHECK(launch_fill_int(c.at<int>(c.L.active), p.batch, 1, c.s));
   HKP_CHECK(launch_fill_int(c.at<int>(c.L.act32), p.batch, p.mixed ? 1 : 0, c.s));
   HKP_CHECK(launch_fill_int(c.at<int>(c.L.act64), p.batch, p.mixed ? 0 : 1, c.s));
@@ -972,6 +975,7 @@ size_t apply2_bytes(const hkp_grid& g, int nvec) {
   b += align_up((size_t)g.nz * 8) + align_up((size_t)g.nz * g.nx * 8);
   b += 4 * align_up((size_t)nvec * n6 * 8);                           // X, Old, Y1, Y2 (FP32)
   b += align_up((size_t)nvec * n6 * 16);                              // FP64 staging
+  b += align_up(256);                                                 // zeros
   return b;
 }
 
@@ -997,7 +1001,9 @@ int run_filter_step2(const Filter2Args& A, int* passes) {
   float* Y1f = (float*)take((size_t)A.nvec * n6 * 8);
   float* Y2f = (float*)take((size_t)A.nvec * n6 * 8);
   double* Yd = (double*)take((size_t)A.nvec * n6 * 16);
+  int* zero = (int*)take(256);
   const bool field = A.B[0] != 0.0 || A.B[1] != 0.0 || A.B[2] != 0.0;
+  HKP_CHECK(launch_fill_int(zero, 64, 0, s));
   const StencilConsts<double> consts = make_consts(A.mat, g.h_nm, A.B);
   HKP_CHECK(launch_onsite(A.mat, g.nx, g.ny, g.nz, 1, A.V, 0, A.strain, D64, D32, 0, s));
   if (field) HKP_CHECK(launch_phase_tables(g.nx, g.nz, g.h_nm, A.B, w64, v64, w32, v32, s));
@@ -1019,6 +1025,7 @@ int run_filter_step2(const Filter2Args& A, int* passes) {
   t2.bstride = 0;
   t2.D = D32;
   t2.D_bstride = 0;
+  t2.zero = zero;
   t2.strain = A.strain != nullptr;
   if (field) {
     t2.wtab = w32;

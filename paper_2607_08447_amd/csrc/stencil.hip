@@ -373,6 +373,11 @@ stencil_kernel(KArgs<T> a) {
                                          pvxp, pvxm, d00, d11, d22, d12, d02, d01, acc0, acc1,
                                          acc2);
 
+    // the output plane's stores (and the wait for the old block, which the
+    // compiler extends to every load in flight, the next plane's copy included)
+    // after all of this plane's arithmetic
+    settle(acc1);
+    settle(acc2);
     if (z - 1 >= o0) finalize(z - 1);
     if constexpr (DMA) {
       if (more) halo_commit(hv, IC<1 - cur>{});

@@ -43,6 +43,7 @@ struct K2Args {
   long long bstride;   // complex elements between members (all four blocks)
   const float* D;
   long long D_bstride;
+  const float* zero;   // 16 bytes of zeros in device memory (the wall's values)
   const float* wtab;   // [nz] x-link phases (complex)
   const float* vtab;   // [nz][nx] y-link phases (complex; uniform over x here)
   const double* coef1;   // per member [alpha, shift, beta] of the first step, or null:
@@ -79,8 +80,10 @@ stencil2_kernel(K2Args a) {
   constexpr int CPR = IW / 2;               // 16-byte chunks per row
   constexpr int NCH = 6 * IH * CPR;         // chunks per plane
   constexpr int NR = (NCH + NT - 1) / NT;   // copy rounds per plane
-  __shared__ cx<T> y0a[6 * IPL];
-  __shared__ cx<T> y0b[6 * IPL];
+  // Y0 planes, padded to the copy rounds' chunks (lanes past the plane copy zeros
+  // into the padding)
+  __shared__ cx<T> y0a[2 * NR * NT];
+  __shared__ cx<T> y0b[2 * NR * NT];
   __shared__ cx<T> y1a[6 * EPL];
   __shared__ cx<T> y1b[6 * EPL];
   auto bufp = [&](auto BUF) -> cx<T>* {
@@ -146,6 +149,7 @@ stencil2_kernel(K2Args a) {
   const bool in2 = v2 && gx2 < nx && gy2 < ny;
   const unsigned col2 = in2 ? (unsigned)(gy2 * nx + gx2) : 0u;
   const int lb2 = (oy + 1) * EW + (ox + 1);   // centre in the Y1 plane
+  const int lk2 = (oy + 2) * IW + (ox + 2);   // same column in a Y0 plane
 
   T alpha1 = (T)a.h1[0], shift1 = (T)a.h1[1], beta1 = (T)a.h1[2];
   T alpha2 = (T)a.h2[0], shift2 = (T)a.h2[1], beta2 = (T)a.h2[2];
@@ -176,7 +180,9 @@ stencil2_kernel(K2Args a) {
 
   // ---- Y0 plane copies: chunk q of a plane is 16 bytes (two points) of row
   // (component, iy) at column pair ic, and lands at byte 16 q of the LDS plane.
-  // Chunks outside the grid are never copied: their slots stay zero.
+  // Chunks outside the grid (and lanes past the plane) copy 16 zero bytes from
+  // a.zero: every lane of every wave issues the same copies, with no branch,
+  // so that waits for the loads issued before them never wait for the copies.
   const int wave = __builtin_amdgcn_readfirstlane(t >> 6);
   unsigned coff[NR];
   bool cval[NR];
@@ -194,8 +200,8 @@ stencil2_kernel(K2Args a) {
     const unsigned zo = (unsigned)z * nxy;
 #pragma unroll
     for (int r = 0; r < NR; ++r) {
-      if (NT * r + 64 * wave >= NCH) continue;   // the whole wave is past the plane
-      if (cval[r]) dma16(in + 2 * (size_t)(coff[r] + zo), dst + 2 * (NT * r + 64 * wave));
+      const T* src = cval[r] ? in + 2 * (size_t)(coff[r] + zo) : a.zero;
+      dma16(src, dst + 2 * (NT * r + 64 * wave));
     }
   };
 
@@ -224,22 +230,19 @@ stencil2_kernel(K2Args a) {
   }
 
   // accumulators of Y1 planes z-1, z, z+1 (acc) and of Y2 planes z-3, z-2,
-  // z-1 (bcc)
+  // z-1 (bcc); this column's Y0 of planes z-3, z-2, z-1 for the beta term of Y2
   cx<T> acc0[3], acc1[3], acc2[3], bcc0[3], bcc1[3], bcc2[3], oldv[3];
+  cx<T> ka[3], kb[3], kc[3];
 #pragma unroll
-  for (int i = 0; i < 3; ++i)
+  for (int i = 0; i < 3; ++i) {
     acc0[i] = acc1[i] = acc2[i] = bcc0[i] = bcc1[i] = bcc2[i] = oldv[i] = zero;
+    ka[i] = kb[i] = kc[i] = zero;
+  }
   T d1[ND], d2[ND];
   load_d(0, col1, d1);
 #pragma unroll
   for (int i = 0; i < ND; ++i) d2[i] = (T)0;
 
-  // rows outside the grid are never copied: zero both Y0 buffers once
-  for (int i = t; i < 6 * IPL; i += NT) {
-    y0a[i] = zero;
-    y0b[i] = zero;
-  }
-  __syncthreads();
   copy_plane(0, IC<0>{});
   __syncthreads();
 
@@ -248,17 +251,14 @@ stencil2_kernel(K2Args a) {
   // in the previous iteration) completes Y2 plane z - 3.  One barrier per plane.
   auto iteration = [&](int z, auto BUF) {
     constexpr int cur = decltype(BUF)::value;
-    // loads in the order they are needed: the next Y0 plane's rows go to the
-    // other buffer; fields for the next iteration; the old block for Y1(z-1)
-    if (z + 1 < nz) copy_plane(z + 1, IC<1 - cur>{});
+    // loads in the order they are needed (the memory counter retires them in
+    // order, so a wait for an early load does not wait for the copy of the next
+    // plane): fields and phases for the next iteration, the old block for
+    // Y1(z-1) (column 0 for threads off the grid: no branch), then the next
+    // Y0 plane's rows into the other buffer
     T n1[ND], n2[ND];
     load_d(z + 1 < nz ? z + 1 : nz - 1, col1, n1);
     load_d(z - 1 < 0 ? 0 : (z - 1 < nz ? z - 1 : nz - 1), col2, n2);
-    if (has_old && in1 && z >= 1 && z - 1 < nz) {
-      const unsigned o = (unsigned)(z - 1) * nxy + col1;
-#pragma unroll
-      for (int i = 0; i < 3; ++i) oldv[i] = ld_stream(oldp + 2 * (size_t)((unsigned)i * N + o));
-    }
     cx<T> nw1 = zero, nv1 = zero, nw2 = zero, nv2 = zero;
     if constexpr (PH != 0) {
       nw1 = wph(z + 2);
@@ -266,6 +266,14 @@ stencil2_kernel(K2Args a) {
       nw2 = wph(z);
       nv2 = vph(z);
     }
+    {   // read even when beta1 == 0 (a valid block; the value is then unused)
+      const int zo = z - 1 < 0 ? 0 : (z - 1 < nz ? z - 1 : nz - 1);
+      const unsigned o = (unsigned)zo * nxy + col1;
+#pragma unroll
+      for (int i = 0; i < 3; ++i) oldv[i] = ld_stream(oldp + 2 * (size_t)((unsigned)i * N + o));
+    }
+    // past the last plane the copy repeats it into the buffer no longer read
+    copy_plane(z + 1 < nz ? z + 1 : nz - 1, IC<1 - cur>{});
 
     // ---- step one: push Y0 plane z (tile + ring)
     if (z < nz) {
@@ -278,6 +286,32 @@ stencil2_kernel(K2Args a) {
                                          pv1, zero, zero, d00, d11, d22, d12, d02, d01, acc0,
                                          acc1, acc2);
     }
+    // this thread's tile column of Y0 plane z (own spin), for Y2's beta term
+    cx<T> kd[3];
+    {
+      const cx<T>* K = bufp(IC<cur>{}) + lk2;
+#pragma unroll
+      for (int i = 0; i < 3; ++i) kd[i] = K[(X + i) * IPL];
+    }
+    // ---- step two: push Y1 plane z - 2 (tile)
+    const bool s2 = z >= 2 && z - 2 < nz;
+    if (s2) {
+      const cx<T>* L = buf1(IC<cur>{}) + lb2;
+      const T d00 = d2[0], d11 = d2[STR ? 1 : 0], d22 = d2[STR ? 2 : 0];
+      const T d12 = STR ? d2[STR ? 3 : 0] : (T)0;
+      const T d02 = STR ? d2[STR ? 4 : 0] : (T)0;
+      const T d01 = STR ? d2[STR ? 5 : 0] : (T)0;
+      push_plane<T, PH, STR, 6, EPL, EW>(L, X, F, k, dgs, ax, ay, az, sd3, sby, shift2, pw2,
+                                         pv2, zero, zero, d00, d11, d22, d12, d02, d01, bcc0,
+                                         bcc1, bcc2);
+    }
+    // both steps' arithmetic is done before the stores below: their wait for the
+    // old block also waits for the next plane's copy, which is then in flight
+    // during all of it (the Y1 plane goes to the buffer step two does not read)
+    settle(acc1);
+    settle(acc2);
+    settle(bcc1);
+    settle(bcc2);
     // ---- Y1 plane z - 1 is complete: to LDS (zero off the grid) and HBM
     if (z >= 1 && z - 1 < nz && v1) {
       cx<T>* Y1 = buf1(IC<1 - cur>{});
@@ -299,26 +333,13 @@ stencil2_kernel(K2Args a) {
       }
     }
 
-    // ---- step two: push Y1 plane z - 2 (tile)
-    const bool s2 = z >= 2 && z - 2 < nz;
-    if (s2) {
-      const cx<T>* L = buf1(IC<cur>{}) + lb2;
-      const T d00 = d2[0], d11 = d2[STR ? 1 : 0], d22 = d2[STR ? 2 : 0];
-      const T d12 = STR ? d2[STR ? 3 : 0] : (T)0;
-      const T d02 = STR ? d2[STR ? 4 : 0] : (T)0;
-      const T d01 = STR ? d2[STR ? 5 : 0] : (T)0;
-      push_plane<T, PH, STR, 6, EPL, EW>(L, X, F, k, dgs, ax, ay, az, sd3, sby, shift2, pw2,
-                                         pv2, zero, zero, d00, d11, d22, d12, d02, d01, bcc0,
-                                         bcc1, bcc2);
-    }
-    // ---- Y2 plane z - 3 is complete; its beta term reads Y0 plane z - 3 again
-    // (copied to LDS three planes ago, so normally still in the L2)
+    // ---- Y2 plane z - 3 is complete
     if (z >= 3 && in2) {
       const unsigned o = (unsigned)(z - 3) * nxy + col2;
 #pragma unroll
       for (int i = 0; i < 3; ++i) {
         cx<T> r = scl(alpha2, bcc0[i]);
-        r = fma_s(r, beta2, ld(in + 2 * (size_t)((unsigned)(X + i) * N + o)));
+        r = fma_s(r, beta2, ka[i]);
         stg_stream<T>(o2, (long long)((unsigned)i * N + o), r);
       }
     }
@@ -328,6 +349,12 @@ stencil2_kernel(K2Args a) {
         bcc0[i] = bcc1[i];
         bcc1[i] = bcc2[i];
       }
+    }
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      ka[i] = kb[i];
+      kb[i] = kc[i];
+      kc[i] = kd[i];
     }
 #pragma unroll
     for (int i = 0; i < ND; ++i) {
@@ -374,7 +401,7 @@ bool stencil2_supported(const Stencil2Launch& L) {
 
 hipError_t launch_stencil2(const Stencil2Launch& L, const StencilConsts<double>& c,
                            hipStream_t s) {
-  if (!stencil2_supported(L) || (!L.coef1) != (!L.coef2)) return hipErrorInvalidValue;
+  if (!stencil2_supported(L) || (!L.coef1) != (!L.coef2) || !L.zero) return hipErrorInvalidValue;
   K2Args a;
   for (int i = 0; i < 3; ++i) {
     a.h1[i] = L.host1[i];
@@ -387,6 +414,7 @@ hipError_t launch_stencil2(const Stencil2Launch& L, const StencilConsts<double>&
   a.bstride = L.bstride;
   a.D = static_cast<const float*>(L.D);
   a.D_bstride = L.D_bstride;
+  a.zero = static_cast<const float*>(L.zero);
   a.wtab = static_cast<const float*>(L.wtab);
   a.vtab = static_cast<const float*>(L.vtab);
   a.coef1 = L.coef1;

@@ -100,6 +100,18 @@ __device__ __forceinline__ void dma16(const void* g, void* lds) {
 #endif
 }
 
+// Ends the computation of these accumulators here: an empty asm statement that
+// takes them as register inputs (it emits nothing), placed before a plane's
+// output stores, stops the compiler from sinking this plane's arithmetic past
+// the stores.  The stores need the old block, and the wait for it also waits for
+// the next plane's copy issued after it; with the arithmetic done first, that
+// copy is in flight during all of it.
+template <typename T>
+__device__ __forceinline__ void settle(const cx<T> (&a)[3]) {
+#pragma unroll
+  for (int i = 0; i < 3; ++i) asm volatile("" ::"v"(a[i].r), "v"(a[i].i));
+}
+
 template <int V>
 struct IC {
   static constexpr int value = V;
