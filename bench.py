@@ -81,12 +81,14 @@ def _traffic_for(kernel_src_hash, shape):
     return entry.get("hbm_bytes_per_launch") if entry else None
 
 
-def traffic_from(fetch_csv, write_csv, stencil, nb):
-    """HBM bytes per launch of the FP32 filter-step stencil from rocprofv3
+def traffic_from(fetch_csv, write_csv, stencil, nb, precision="fp32"):
+    """HBM bytes per launch of the FP32 (or FP64) stencil from rocprofv3
     FETCH_SIZE and WRITE_SIZE (KiB per dispatch) collection files.  Each
     counter is scaled by what it reads for the 1 GiB device copy the profiled
-    run makes first (1 GiB read + 1 GiB written)."""
+    run makes first (1 GiB read + 1 GiB written).  FP32 entries go to the JSON
+    the benchmark reads; FP64 ones are printed only."""
     import csv
+    tag = "stencil_kernel<float" if precision == "fp32" else "stencil_kernel<double"
 
     def per_kernel(path, counter):
         copy, sten = [], []
@@ -98,10 +100,10 @@ def traffic_from(fetch_csv, write_csv, stencil, nb):
                 name = r["Kernel_Name"]
                 if "copyBuffer" in name and not copy:
                     copy.append(v)
-                elif "stencil_kernel<float" in name:
+                elif tag in name:
                     sten.append(v)
         if not copy or not sten:
-            raise SystemExit(f"{path}: no copy calibration or no FP32 stencil dispatches")
+            raise SystemExit(f"{path}: no copy calibration or no {precision} stencil dispatches")
         return copy[0], sten
 
     cf, sf = per_kernel(fetch_csv, "FETCH_SIZE")
@@ -111,6 +113,13 @@ def traffic_from(fetch_csv, write_csv, stencil, nb):
     gib = float(1 << 30)
     kf, kw = gib / cf, gib / cw
     per_launch = [kf * a + kw * b for a, b in zip(sf, sw)]
+    if precision != "fp32":
+        print(json.dumps({"kernel": tag, "dispatches": len(per_launch),
+                          "hbm_bytes_per_launch": sum(per_launch) / len(per_launch),
+                          "fetch_bytes_per_launch": kf * sum(sf) / len(sf),
+                          "write_bytes_per_launch": kw * sum(sw) / len(sw),
+                          "copy_calibration": {"fetch_factor": kf, "write_factor": kw}}, indent=1))
+        return
     d = {}
     if os.path.exists(TRAFFIC_JSON):
         with open(TRAFFIC_JSON) as f:
@@ -664,12 +673,19 @@ def main():
                     help="run only the configuration-interaction measurement (profiled runs)")
     ap.add_argument("--qubit-only", action="store_true",
                     help="run only the g-matrix / two-spin-model measurement (profiled runs)")
+    ap.add_argument("--adjoint-only", action="store_true",
+                    help="run only the Hellmann-Feynman backward measurement (profiled runs)")
+    ap.add_argument("--fp64-solve-only", action="store_true",
+                    help="one FP64 solve of the benchmark workload (residual 1e-5 eV) and its "
+                         "FP64 stencil statistics (profiled runs of the FP64 stencil)")
+    ap.add_argument("--precision", default="fp32", choices=["fp32", "fp64"],
+                    help="with --traffic-from: which stencil's dispatches to summarise")
     args = ap.parse_args()
     if args.traffic_from:
         if not args.stencil or not args.nb:
             raise SystemExit("--traffic-from needs --stencil TY,VGROUP,DMA and --nb NB "
                              "(the profiled launch shape and block size)")
-        traffic_from(*args.traffic_from, args.stencil, args.nb)
+        traffic_from(*args.traffic_from, args.stencil, args.nb, args.precision)
         return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); this build has no "
@@ -704,6 +720,21 @@ def main():
         return
     if args.qubit_only:
         print(json.dumps(qubit_measure(torch, hkp)), flush=True)
+        return
+    if args.adjoint_only:
+        print(json.dumps(adjoint_measure(torch, hkp, workload)), flush=True)
+        return
+    if args.fp64_solve_only:
+        w = workload(WORKLOAD)
+        r = hkp.solve(torch.from_numpy(w.V).cuda(), w.h, 32, strain=torch.from_numpy(w.strain).cuda(),
+                      B=w.B, nb=args.nb or 40, tol=1e-5, precision="fp64", return_psi=False)
+        torch.cuda.synchronize()
+        st = r.stats
+        print(json.dumps({"status": r.status, "iters": st["iters"],
+                          "n_stencil64": st["n_stencil64"],
+                          "algorithmic_bytes_per_launch": st["bytes_stencil64"] / max(st["n_stencil64"], 1),
+                          "avg_launch_us": 1e6 * st["t_stencil64"] / max(st["n_stencil64"], 1)}),
+              flush=True)
         return
 
     w = workload(WORKLOAD)

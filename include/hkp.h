@@ -236,7 +236,12 @@ int32_t hkp_block_size(const hkp_grid* grid, const hkp_opts* opts);
  *             opts->flags & HKP_FLAG_X0, else ignored (may be NULL);
  *             [nev][nx][ny][nz][6] with HKP_FLAG_X0_NEV as well (restart
  *             from a neighbouring solve's psi, as between the iterations
- *             of a Schroedinger-Poisson loop, Fig. 2a)
+ *             of a Schroedinger-Poisson loop, Fig. 2a); its columns must be
+ *             linearly independent: a starting block whose first
+ *             orthonormalisation breaks down (repeated or dependent columns)
+ *             gives HKP_E_NUMERICAL
+ *   V_eV, strain: NaN or Inf anywhere gives HKP_E_ARG (checked on the device
+ *             before the solve starts)
  *   eig_eV    device double [nev], ascending
  *   psi       device complex double [nev][nx][ny][nz][6] (may be NULL);
  *             [nb][nx][ny][nz][6] with HKP_FLAG_PSI_BLOCK

@@ -9,7 +9,9 @@ import ctypes as C
 import os
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libhkp.so")
+# HKP_LIB selects another build of the library (the sanitizer build in the
+# CPU tests of the host-side argument checks)
+LIB_PATH = os.environ.get("HKP_LIB") or os.path.join(_HERE, "libhkp.so")
 
 HKP_OK = 0
 HKP_W_NOT_CONVERGED = 1

@@ -45,6 +45,42 @@ def _compile(src):
     return out, warn
 
 
+# host sources whose argument validation the sanitizer build checks
+ASAN_SOURCES = ["abi.cpp", "autotune.cpp", "solver.cpp", "sp_loop.cpp"]
+ASAN_FLAGS = ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
+              "-Xarch_host", "-fno-omit-frame-pointer", "-Xarch_host", "-fno-sanitize-recover=all"]
+ASAN_LIB = os.path.join(HERE, "libhkp_asan.so")
+
+
+def _compile_asan(src):
+    out = os.path.join(OBJ, "asan_" + os.path.splitext(src)[0] + ".o")
+    cmd = [HIPCC] + FLAGS + ASAN_FLAGS + ["-x", "hip", "-c", os.path.join(SRC, src), "-o", out]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"compile failed: {src}\n{' '.join(cmd)}\n{r.stdout}\n{r.stderr}")
+    return out
+
+
+def build_asan():
+    """libhkp_asan.so: the host sources above built with AddressSanitizer and
+    UndefinedBehaviorSanitizer (host code only), linked with the kernels' objects
+    of the normal build (build() first).  Loaded by a CPU test in a process that
+    preloads the sanitizer runtime."""
+    os.makedirs(OBJ, exist_ok=True)
+    with ThreadPoolExecutor(max_workers=len(ASAN_SOURCES)) as ex:
+        objs = list(ex.map(_compile_asan, ASAN_SOURCES))
+    plain = [os.path.join(OBJ, os.path.splitext(s)[0] + ".o") for s in SOURCES
+             if s not in ASAN_SOURCES]
+    tmp = ASAN_LIB + ".tmp"
+    cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-fsanitize=address,undefined",
+           "-shared-libsan", "-o", tmp] + objs + plain
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"link failed\n{' '.join(cmd)}\n{r.stdout}\n{r.stderr}")
+    os.replace(tmp, ASAN_LIB)
+    return ASAN_LIB
+
+
 def build(verbose=False):
     os.makedirs(OBJ, exist_ok=True)
     with ThreadPoolExecutor(max_workers=min(8, len(SOURCES))) as ex:

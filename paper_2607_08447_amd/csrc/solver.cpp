@@ -708,6 +708,20 @@ int run_solve(const SolveArgs& A, hkp_stats* stats) {
     ++n_sync;
   };
   read_flags();
+  {
+    // the starting block must span nb directions: a breakdown of its first
+    // orthonormalisation (a Gram eigenvalue below 1e-15 of the largest, e.g. an
+    // X0 with repeated or dependent columns) is an error.  Later passes keep
+    // their floor: a strongly filtered block may be nearly dependent.
+    std::vector<int> st0(p.batch);
+    HKP_CHECK(hipMemcpy(st0.data(), c.at<int>(c.L.status), p.batch * 4, hipMemcpyDeviceToHost));
+    for (int b = 0; b < p.batch; ++b)
+      if (st0[b]) {
+        set_error("the initial block is rank deficient (member " + std::to_string(b) +
+                  "): X0 columns must be linearly independent");
+        return HKP_E_NUMERICAL;
+      }
+  }
   auto all_done = [&]() {
     for (int b = 0; b < p.batch; ++b)
       if (!hflags[8 * b]) return false;
