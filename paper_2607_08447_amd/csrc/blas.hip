@@ -308,11 +308,12 @@ gram_hp_kernel(const double* A, long long a_bstride, const double* B, long long 
     }
   };
   const long long nfull = (e1 - e0) / 8;   // trips of 8 elements inside the run
+  auto clampt = [&](long long t) { return t < nfull ? t : (nfull > 0 ? nfull - 1 : 0); };
   // three register sets in rotation: the loads of trip t + 2 are issued while
   // trip t is multiplied (trip indices past the run reload its last trip: the
-  // loads need no branch; their products are skipped)
+  // loads need no branch; their products are skipped).  With two blocks (A != B)
+  // this leaves one wave per SIMD, still faster than two with one set fewer.
   double2 a1[U][T + P], b1[U][T + P], a2[U][T + P], b2[U][T + P];
-  auto clampt = [&](long long t) { return t < nfull ? t : (nfull > 0 ? nfull - 1 : 0); };
   if (nfull > 0) {
     load(0, false, av, bv);
     load(clampt(1), false, a1, b1);
