@@ -260,12 +260,22 @@ hf_partial_kernel(long long N, int nev, const double2* psi, const double* w, int
   }
 }
 
-__global__ void hf_reduce_kernel(int nblk, int G, const double* partial, double* grad) {
-  const int g = threadIdx.x;
-  if (g >= G) return;
+// one workgroup per g: each thread sums a strided slice of the block partials,
+// then waves and workgroup reduce in a fixed order (deterministic)
+__global__ void __launch_bounds__(kHfThreads)
+hf_reduce_kernel(int nblk, int G, const double* partial, double* grad) {
+  const int g = blockIdx.x;
   double v = 0.0;
-  for (int k = 0; k < nblk; ++k) v += partial[(long long)k * G + g];
-  grad[g] = v;
+  for (int k = threadIdx.x; k < nblk; k += kHfThreads) v += partial[(long long)k * G + g];
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+  __shared__ double red[kHfThreads / 64];
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = 0.0;
+    for (int k = 0; k < kHfThreads / 64; ++k) t += red[k];
+    grad[g] = t;
+  }
 }
 
 }  // namespace
@@ -365,7 +375,7 @@ hipError_t launch_hf_grad(long long N, int nev, const void* psi, const double* w
   if (G > kHfMaxG) return hipErrorInvalidValue;
   const int nblk = hf_blocks();
   hf_partial_kernel<<<nblk, kHfThreads, 0, s>>>(N, nev, (const double2*)psi, w, G, L, partial);
-  hf_reduce_kernel<<<1, 64, 0, s>>>(nblk, G, partial, grad);
+  hf_reduce_kernel<<<G, kHfThreads, 0, s>>>(nblk, G, partial, grad);
   return hipGetLastError();
 }
 
