@@ -27,9 +27,10 @@ oracle solve of the 10 x 8 x 8 workload).
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-extra]
        python bench.py --sp-only          (only the self-consistent loop measurement)
-       python bench.py --traffic-from FETCH_CSV WRITE_CSV   (writes the HBM traffic
-           summary of the FP32 stencil from two rocprofv3 --pmc runs of
-           `bench.py --copy-calibration --no-cpu --no-extra --steps 1 --warmup 0`)
+       python bench.py --traffic-from FETCH_CSV WRITE_CSV --stencil S --nb NB --bench-log LOG
+           (writes the HBM traffic summary of the FP32 stencil from two rocprofv3
+           --pmc runs of `bench.py --copy-calibration --no-cpu --no-extra --steps 1
+           --warmup 0 --stencil S --nb NB`, LOG the stdout of the first)
 """
 
 import argparse
@@ -66,11 +67,13 @@ def _shape_key(tune, nb):
     return f"{tune['tile_y']},{tune['vgroup']},{tune['dma']}/nb{nb}"
 
 
-def _traffic_for(kernel_src_hash, shape):
+def _traffic_for(kernel_src_hash, shape, alg_bytes_per_launch):
     """HBM bytes per launch of the dominant kernel from the committed rocprofv3
     counter summary, if it was taken on the current kernel source with the
     launch shape (tile height, vector group, row DMA) and block size this run
-    uses."""
+    uses, over launches of the same average size (algorithmic bytes per launch
+    within 1%: the solver's schedule decides how many vectors a launch
+    filters)."""
     if not os.path.exists(TRAFFIC_JSON):
         return None
     with open(TRAFFIC_JSON) as f:
@@ -78,15 +81,30 @@ def _traffic_for(kernel_src_hash, shape):
     if d.get("stencil_src_sha256") != kernel_src_hash:
         return None
     entry = d.get("by_launch", {}).get(shape)
-    return entry.get("hbm_bytes_per_launch") if entry else None
+    if not entry:
+        return None
+    alg = entry.get("algorithmic_bytes_per_launch")
+    if not alg or abs(alg - alg_bytes_per_launch) > 0.01 * alg_bytes_per_launch:
+        return None
+    return entry.get("hbm_bytes_per_launch")
 
 
-def traffic_from(fetch_csv, write_csv, stencil, nb, precision="fp32"):
+def _bench_alg_bytes(log):
+    """Algorithmic bytes per FP32 stencil launch printed by a benchmark run."""
+    with open(log) as f:
+        for line in f:
+            if line.startswith("{") and '"roofline"' in line:
+                return json.loads(line)["roofline"]["algorithmic_bytes_per_launch"]
+    raise SystemExit(f"{log}: no benchmark line")
+
+
+def traffic_from(fetch_csv, write_csv, stencil, nb, precision="fp32", bench_log=None):
     """HBM bytes per launch of the FP32 (or FP64) stencil from rocprofv3
     FETCH_SIZE and WRITE_SIZE (KiB per dispatch) collection files.  Each
     counter is scaled by what it reads for the 1 GiB device copy the profiled
     run makes first (1 GiB read + 1 GiB written).  FP32 entries go to the JSON
-    the benchmark reads; FP64 ones are printed only."""
+    the benchmark reads, with the algorithmic bytes per launch the profiled
+    benchmark run printed (bench_log, its stdout); FP64 ones are printed only."""
     import csv
     tag = "stencil_kernel<float" if precision == "fp32" else "stencil_kernel<double"
 
@@ -129,8 +147,13 @@ def traffic_from(fetch_csv, write_csv, stencil, nb, precision="fp32"):
     d["kernel"] = ("stencil_kernel<float, ...> (FP32 Chebyshev filter step), dqd_256x48x48; "
                    "entries keyed by tile height, vector group, row DMA / block size")
     d["stencil_src_sha256"] = _src_hash()
+    if bench_log is None:
+        raise SystemExit("FP32 traffic needs --bench-log (the profiled run's stdout)")
+    alg = _bench_alg_bytes(bench_log)
     d["by_launch"][f"{stencil}/nb{nb}"] = {
         "dispatches": len(per_launch),
+        "algorithmic_bytes_per_launch": alg,
+        "ratio": sum(per_launch) / len(per_launch) / alg,
         "hbm_bytes_per_launch": sum(per_launch) / len(per_launch),
         "fetch_bytes_per_launch": kf * sum(sf) / len(sf),
         "write_bytes_per_launch": kw * sum(sw) / len(sw),
@@ -140,7 +163,7 @@ def traffic_from(fetch_csv, write_csv, stencil, nb, precision="fp32"):
                     f"--no-extra --steps 1 --warmup 0 --stencil {stencil} --nb {nb}",
                     "rocprofv3 --pmc WRITE_SIZE -- (same)",
                     f"python bench.py --traffic-from <fetch csv> <write csv> --stencil {stencil} "
-                    f"--nb {nb}"],
+                    f"--nb {nb} --bench-log <stdout of the FETCH_SIZE run>"],
     }
     with open(TRAFFIC_JSON, "w") as f:
         json.dump(d, f, indent=1)
@@ -678,6 +701,8 @@ def main():
     ap.add_argument("--fp64-solve-only", action="store_true",
                     help="one FP64 solve of the benchmark workload (residual 1e-5 eV) and its "
                          "FP64 stencil statistics (profiled runs of the FP64 stencil)")
+    ap.add_argument("--bench-log", default=None,
+                    help="with --traffic-from: stdout of the profiled benchmark run")
     ap.add_argument("--precision", default="fp32", choices=["fp32", "fp64"],
                     help="with --traffic-from: which stencil's dispatches to summarise")
     args = ap.parse_args()
@@ -685,7 +710,7 @@ def main():
         if not args.stencil or not args.nb:
             raise SystemExit("--traffic-from needs --stencil TY,VGROUP,DMA and --nb NB "
                              "(the profiled launch shape and block size)")
-        traffic_from(*args.traffic_from, args.stencil, args.nb, args.precision)
+        traffic_from(*args.traffic_from, args.stencil, args.nb, args.precision, args.bench_log)
         return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); this build has no "
@@ -810,7 +835,7 @@ def main():
     bytes_per_launch = b32 / max(n32, 1)
     avg_launch = t32 / max(n32, 1)
     achieved = bytes_per_launch / avg_launch / 1e9
-    traffic = _traffic_for(_src_hash(), _shape_key(tune32, nbs["mixed"]))
+    traffic = _traffic_for(_src_hash(), _shape_key(tune32, nbs["mixed"]), bytes_per_launch)
     extra = {}
     if not args.no_extra:
         log("copy bandwidth ...")

@@ -95,8 +95,8 @@ typedef struct {
 } hkp_material;
 
 /* Solver options.  nb = 0 selects the autotuned block size; degree = 0 the
- * default degree schedule (16, then 32, then 64 in mixed precision or 96 in FP64
- * over the first outer iterations). */
+ * default degree schedule over the first outer iterations: 16, then 32, then
+ * 96 in FP64, or in mixed precision 48 + nb bounded to [64, 96] (88 at nb 40). */
 typedef struct {
   int32_t nev;        /* eigenpairs wanted, 1 <= nev < nb */
   int32_t nb;         /* subspace block size, nev < nb <= HKP_NB_MAX, nb <= 6 N */
@@ -117,7 +117,9 @@ typedef struct {
   int32_t fp64_switch_iter; /* mixed: first outer iteration filtered in FP64, -1 none */
   int32_t nb, degree;       /* values used (after autotuning) */
   double seconds;           /* wall time of the call */
-  double t_setup, t_filter, t_orth, t_rr, t_resid; /* event-timed phases (eager mode) */
+  double t_setup, t_filter, t_orth, t_rr, t_resid; /* event-timed phases (eager mode); the
+                                          residual norms are formed inside the Rayleigh-Ritz
+                                          phase (t_rr), t_resid times the convergence control */
   double lambda_max_bound;  /* upper spectral bound used by the filter (eV) */
   /* stencil launches (filter steps and H X): algorithmic bytes moved -- the
    * spinor blocks read and written plus the on-site fields once per launch --

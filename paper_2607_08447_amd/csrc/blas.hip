@@ -4,8 +4,8 @@
 //   Gram     C = A^H B (nb x nb)          FP64 MFMA (v_mfma_f64_16x16x4f64),
 //                                         split over K, fixed-order reduction
 //   rotate   X <- X Q                     FP64 MFMA, in place
-//   resid    r_j^2 = || W_j - theta_j X_j ||^2
-//   cheb     Y1 = alpha (W - shift X)     first filter step from W = H X
+//   Ritz     W Q, not stored: r_j^2 = || (W Q)_j - theta_j (X Q)_j ||^2 and the
+//            first filter step Y1 = alpha (W Q - shift X Q)
 //   Lanczos  dots, three-term update, normalisation (spectral bound)
 //
 // The complex products are evaluated as real products of the (re, im)
@@ -540,10 +540,26 @@ gram_reduce_kernel(int nchunks, int nba, int nbb, int hermitian, const int* acti
 // ---------------------------------------------------------------------------
 constexpr int kRotWaves = 4;
 
-template <int NB8>   // nin rounded up to a multiple of 8 (zero padding beyond nin, nout)
+// The Rayleigh-Ritz form of the rotation of W = H X (RITZ): with Q the Ritz
+// vectors and X already rotated (XQ = X Q), every output column w of W Q gives
+//   r2_w += |(W Q)_w - theta_w XQ_w|^2        (residual norm, partial sums)
+//   Y1_w  = alpha ((W Q)_w - c XQ_w)          (the filter's first Chebyshev step)
+// and W Q itself is not stored.  Y1 is FP32 (into out32) for members whose
+// filter runs in FP32 (f32[b]), else FP64 in place into W.
+struct RitzArgs {
+  const double* XQ;       // rotated X, strides of W
+  const double* theta;    // [batch][nb] Ritz values (ascending)
+  const double* bounds;   // [batch][4]: upper spectral bound first
+  const int* f32;         // [batch] FP32 output
+  float* out32;           // FP32 Y1, strides of W
+  double* partial;        // [batch][nb][gridDim.x] residual partial sums
+  int nb;
+};
+
+template <int NB8, bool RITZ>   // NB8: nin rounded up to a multiple of 8 (zero padding beyond nin, nout)
 __global__ void __launch_bounds__(64 * kRotWaves)
 rotate_kernel(const double* X, long long x_bstride, double* Y, long long y_bstride, long long n,
-              int nin, int nout, const double* Q, const int* active) {
+              int nin, int nout, const double* Q, const int* active, RitzArgs ra) {
   constexpr int KS = NB8 / 2;            // k-steps of 2 input vectors
   constexpr int MT = NB8 / 8;            // M tiles of 8 output vectors
   extern __shared__ double qt[];         // [MT][KS][64]
@@ -568,6 +584,11 @@ rotate_kernel(const double* X, long long x_bstride, double* Y, long long y_bstri
     }
     qt[t] = a;
   }
+  // RITZ: residual sums per wave and output vector (lanes 16 q add theirs)
+  __shared__ double red[RITZ ? kRotWaves : 1][RITZ ? NB8 : 1];
+  if constexpr (RITZ) {
+    for (int t = threadIdx.x; t < kRotWaves * NB8; t += blockDim.x) (&red[0][0])[t] = 0.0;
+  }
   __syncthreads();
   const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int r = lane & 15, q = lane >> 4;
@@ -575,6 +596,20 @@ rotate_kernel(const double* X, long long x_bstride, double* Y, long long y_bstri
   const double* xb = X + 2 * ((long long)b * x_bstride);
   double* yb = Y + 2 * ((long long)b * y_bstride);
   const long long ntile = (n + 15) / 16;
+  // RITZ: this member's first-step coefficients (the control kernel computes the
+  // same ones from the same Ritz values), output precision, residual sums
+  double r_alpha = 0.0, r_shift = 0.0;
+  bool r_f32 = false;
+  const double* thb = nullptr;
+  const double* xqb = nullptr;
+  float* o32 = nullptr;
+  if constexpr (RITZ) {
+    thb = ra.theta + (long long)b * ra.nb;
+    cheb_first_coef(ra.bounds[4 * b], thb[0], thb[ra.nb - 1], &r_alpha, &r_shift);
+    r_f32 = ra.f32 && ra.f32[b];
+    xqb = ra.XQ + 2 * ((long long)b * y_bstride);
+    o32 = ra.out32 ? ra.out32 + 2 * ((long long)b * y_bstride) : nullptr;
+  }
   for (long long tile = (long long)blockIdx.x * kRotWaves + wv; tile < ntile;
        tile += (long long)gridDim.x * kRotWaves) {
     const long long e = tile * 16 + r;
@@ -586,65 +621,83 @@ rotate_kernel(const double* X, long long x_bstride, double* Y, long long y_bstri
       const int v = 2 * s + (q >> 1);
       xv[s] = (eok && v < nin) ? xb[2 * ((long long)v * n + e) + (q & 1)] : 0.0;
     }
-    for (int m = 0; m < mt; ++m) {
+    auto out_tile = [&](int m) {
       const double* qm = qt + m * KS * 64 + lane;
       d4 acc = d4{0, 0, 0, 0};
 #pragma unroll
       for (int s = 0; s < KS; ++s) acc = mfma(qm[s * 64], xv[s], acc);
       // D[mrow][e]: lane holds (w0, re), (w0, im), (w0+1, re), (w0+1, im)
       const int w0 = m * 8 + 2 * q;
-      if (eok) {
-        if (w0 < nout)
-          *reinterpret_cast<double2*>(yb + 2 * ((long long)w0 * n + e)) = make_double2(acc[0], acc[1]);
-        if (w0 + 1 < nout)
-          *reinterpret_cast<double2*>(yb + 2 * ((long long)(w0 + 1) * n + e)) = make_double2(acc[2], acc[3]);
+      if constexpr (!RITZ) {
+        if (eok) {
+          if (w0 < nout)
+            *reinterpret_cast<double2*>(yb + 2 * ((long long)w0 * n + e)) = make_double2(acc[0], acc[1]);
+          if (w0 + 1 < nout)
+            *reinterpret_cast<double2*>(yb + 2 * ((long long)(w0 + 1) * n + e)) = make_double2(acc[2], acc[3]);
+        }
+      } else {
+        double d2[2];
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+          const int w = w0 + j;
+          d2[j] = 0.0;
+          if (eok && w < nout) {
+            const long long o = 2 * ((long long)w * n + e);
+            const double2 xq = *reinterpret_cast<const double2*>(xqb + o);
+            const double ar = acc[2 * j], ai = acc[2 * j + 1], th = thb[w];
+            const double dr = ar - th * xq.x, di = ai - th * xq.y;
+            d2[j] = fma(dr, dr, di * di);
+            const double yr = r_alpha * (ar - r_shift * xq.x), yi = r_alpha * (ai - r_shift * xq.y);
+            if (r_f32)
+              *reinterpret_cast<float2*>(o32 + o) = make_float2((float)yr, (float)yi);
+            else
+              *reinterpret_cast<double2*>(yb + o) = make_double2(yr, yi);
+          }
+        }
+        // this tile's sums over the 16 elements of each lane group, added by
+        // lane 16 q to the wave's running sums of w0 and w0 + 1
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+          for (int off = 1; off < 16; off <<= 1) d2[j] += __shfl_xor(d2[j], off, 64);
+        if (r == 0) {
+          red[wv][w0] += d2[0];
+          red[wv][w0 + 1] += d2[1];
+        }
       }
+    };
+    for (int m = 0; m < mt; ++m) out_tile(m);
+  }
+  if constexpr (RITZ) {
+    // the waves' sums in a fixed order
+    __syncthreads();
+    if ((int)threadIdx.x < nout) {
+      double t = 0.0;
+#pragma unroll
+      for (int k = 0; k < kRotWaves; ++k) t += red[k][threadIdx.x];
+      ra.partial[((long long)b * ra.nb + threadIdx.x) * gridDim.x + blockIdx.x] = t;
     }
   }
 }
 
-// ---------------------------------------------------------------------------
-// residual partial sums: r2[b][j] = sum_e |W_j(e) - theta_j X_j(e)|^2
-// ---------------------------------------------------------------------------
-constexpr int kResThreads = 256;
-
-__global__ void __launch_bounds__(kResThreads)
-resid_partial_kernel(const double* X, const double* W, long long bstride, long long n, int nb,
-                     const double* theta, const int* active, double* partial) {
-  const int j = blockIdx.y, b = blockIdx.z;
+// out[b][j] = sum of the nparts partial sums of (b, j), one workgroup each, in a
+// fixed order
+__global__ void __launch_bounds__(256)
+sum_rows_kernel(int nparts, const double* partial, double* out, const int* active, int per_batch) {
+  const int j = blockIdx.x, b = blockIdx.y;
   if (active && !active[b]) return;
-  const double th = theta[(long long)b * nb + j];
-  const double2* x = reinterpret_cast<const double2*>(X) + (long long)b * bstride + (long long)j * n;
-  const double2* w = reinterpret_cast<const double2*>(W) + (long long)b * bstride + (long long)j * n;
-  double s = 0.0;
-  for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < n;
-       e += (long long)gridDim.x * blockDim.x) {
-    const double2 xv = x[e], wv = w[e];
-    const double dr = wv.x - th * xv.x, di = wv.y - th * xv.y;
-    s = fma(dr, dr, fma(di, di, s));
-  }
-  __shared__ double red[kResThreads / 64];
-  for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
-  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+  const long long row = (long long)b * per_batch + j;
+  double v = 0.0;
+  for (int k = threadIdx.x; k < nparts; k += 256) v += partial[row * nparts + k];
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+  __shared__ double red[4];
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
   __syncthreads();
-  if (threadIdx.x == 0) {
-    double t = 0.0;
-    for (int k = 0; k < kResThreads / 64; ++k) t += red[k];
-    partial[((long long)b * nb + j) * gridDim.x + blockIdx.x] = t;
-  }
-}
-
-__global__ void sum_partials_kernel(int nparts, int count, const double* partial, double* out,
-                                    const int* active, int per_batch) {
-  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= count) return;
-  if (active && !active[idx / per_batch]) return;
-  double s = 0.0;
-  for (int k = 0; k < nparts; ++k) s += partial[(long long)idx * nparts + k];
-  out[idx] = s;
+  if (threadIdx.x == 0) out[row] = red[0] + red[1] + red[2] + red[3];
 }
 
 // complex dots conj(a_b) . b_b for one vector per batch member: out[b] = (re, im)
+constexpr int kResThreads = 256;
+
 __global__ void __launch_bounds__(kResThreads)
 dot_partial_kernel(const double* A, const double* B, long long bstride, long long n,
                    double* partial) {
@@ -732,25 +785,6 @@ __global__ void scale_kernel(double* v, long long n, long long bstride, const do
   }
 }
 
-template <typename TO>
-__global__ void cheb_first_kernel(const double* X, const double* W, long long bstride,
-                                  long long count, TO* out, long long out_bstride,
-                                  const double* coef, int coef_stride, const int* active,
-                                  const int* lock, long long n) {
-  const int b = blockIdx.y;
-  if (active && !active[b]) return;
-  const double al = coef[(long long)b * coef_stride], sh = coef[(long long)b * coef_stride + 1];
-  const double2* x = reinterpret_cast<const double2*>(X) + (long long)b * bstride;
-  const double2* w = reinterpret_cast<const double2*>(W) + (long long)b * bstride;
-  TO* o = out + 2 * (long long)b * out_bstride;
-  const long long e0 = lock ? (long long)lock[b] * n : 0;   // locked vectors are not filtered
-  for (long long e = e0 + (long long)blockIdx.x * blockDim.x + threadIdx.x; e < count;
-       e += (long long)gridDim.x * blockDim.x) {
-    const double2 xv = x[e], wv = w[e];
-    o[2 * e] = (TO)(al * (wv.x - sh * xv.x));
-    o[2 * e + 1] = (TO)(al * (wv.y - sh * xv.y));
-  }
-}
 
 template <typename TI, typename TO>
 __global__ void cast_kernel(const TI* in, TO* out, long long count) {
@@ -883,18 +917,25 @@ hipError_t launch_gram(const BlockDesc& A, const BlockDesc& B, int hermitian, in
   return hipGetLastError();
 }
 
-hipError_t launch_rotate(const BlockDesc& X, const BlockDesc& Y, int nin, int nout,
-                         const double* Q, int batch, const int* active, hipStream_t s) {
-  if (nin > HKP_NB_MAX || nout > nin) return hipErrorInvalidValue;
-  const long long ntile = (X.n + 15) / 16;
+int rotate_blocks(long long n, int batch) {
+  const long long ntile = (n + 15) / 16;
   long long g = (ntile + kRotWaves - 1) / kRotWaves;
   const long long cap = 4096 / (batch > 0 ? batch : 1) + 1;
   if (g > cap) g = cap;
-  dim3 grid((unsigned)g, (unsigned)batch);
+  return (int)(g < 1 ? 1 : g);
+}
+
+namespace {
+template <bool RITZ>
+hipError_t rotate_any(const BlockDesc& X, const BlockDesc& Y, int nin, int nout,
+                      const double* Q, int batch, const int* active, const RitzArgs& ra,
+                      hipStream_t s) {
+  if (nin > HKP_NB_MAX || nout > nin) return hipErrorInvalidValue;
+  dim3 grid((unsigned)rotate_blocks(X.n, batch), (unsigned)batch);
   // operand table [NB8/8][NB8/2][64] doubles, NB8 = nin rounded up to 8
   const int nb8 = (nin + 7) / 8 * 8;
   const size_t lds = (size_t)(nb8 / 8) * (nb8 / 2) * 64 * 8;
-#define HKP_ROT(NB8) rotate_kernel<NB8><<<grid, 64 * kRotWaves, lds, s>>>(X.ptr, X.bstride, Y.ptr, Y.bstride, X.n, nin, nout, Q, active)
+#define HKP_ROT(NB8) rotate_kernel<NB8, RITZ><<<grid, 64 * kRotWaves, lds, s>>>(X.ptr, X.bstride, Y.ptr, Y.bstride, X.n, nin, nout, Q, active, ra)
   switch (nb8) {
     case 8: HKP_ROT(8); break;
     case 16: HKP_ROT(16); break;
@@ -909,41 +950,27 @@ hipError_t launch_rotate(const BlockDesc& X, const BlockDesc& Y, int nin, int no
 #undef HKP_ROT
   return hipGetLastError();
 }
+}  // namespace
 
-int resid_parts(long long n) {
-  long long p = (n + 4095) / 4096;
-  if (p > 64) p = 64;
-  if (p < 1) p = 1;
-  return (int)p;
+hipError_t launch_rotate(const BlockDesc& X, const BlockDesc& Y, int nin, int nout,
+                         const double* Q, int batch, const int* active, hipStream_t s) {
+  return rotate_any<false>(X, Y, nin, nout, Q, batch, active, RitzArgs{}, s);
 }
 
-hipError_t launch_resid(const BlockDesc& X, const BlockDesc& W, const double* theta, int batch,
-                        double* partial, double* r, const int* active, hipStream_t s) {
-  const int parts = resid_parts(X.n);
-  dim3 grid((unsigned)parts, (unsigned)X.nvec, (unsigned)batch);
-  resid_partial_kernel<<<grid, kResThreads, 0, s>>>(X.ptr, W.ptr, X.bstride, X.n, X.nvec, theta,
-                                                     active, partial);
-  const int cnt = batch * X.nvec;
-  sum_partials_kernel<<<(cnt + 255) / 256, 256, 0, s>>>(parts, cnt, partial, r, active, X.nvec);
+hipError_t launch_ritz_w(const BlockDesc& W, const BlockDesc& XQ, int nb, const double* Q,
+                         const double* theta, const double* bounds, const int* f32,
+                         float* out32, int batch, double* partial, double* r2,
+                         const int* active, hipStream_t s) {
+  if (W.bstride != XQ.bstride || W.n != XQ.n || W.nvec < nb || XQ.nvec < nb)
+    return hipErrorInvalidValue;
+  const RitzArgs ra{XQ.ptr, theta, bounds, f32, out32, partial, nb};
+  hipError_t e = rotate_any<true>(W, W, nb, nb, Q, batch, active, ra, s);
+  if (e != hipSuccess) return e;
+  sum_rows_kernel<<<dim3((unsigned)nb, (unsigned)batch), 256, 0, s>>>(
+      rotate_blocks(W.n, batch), partial, r2, active, nb);
   return hipGetLastError();
 }
 
-hipError_t launch_cheb_first(const BlockDesc& X, const BlockDesc& W, void* out, int out_fp64,
-                             long long out_bstride, int batch, const double* coef,
-                             int coef_stride, const int* active, const int* lock,
-                             hipStream_t s) {
-  const long long count = X.n * X.nvec;
-  dim3 grid(grid_for(count, 256, 8192 / (batch > 0 ? batch : 1) + 1), (unsigned)batch);
-  if (out_fp64)
-    cheb_first_kernel<double><<<grid, 256, 0, s>>>(X.ptr, W.ptr, X.bstride, count, (double*)out,
-                                                   out_bstride, coef, coef_stride, active, lock,
-                                                   X.n);
-  else
-    cheb_first_kernel<float><<<grid, 256, 0, s>>>(X.ptr, W.ptr, X.bstride, count, (float*)out,
-                                                  out_bstride, coef, coef_stride, active, lock,
-                                                  X.n);
-  return hipGetLastError();
-}
 
 hipError_t launch_cast(const void* in, int in_fp64, void* out, int out_fp64, long long count,
                        hipStream_t s) {

@@ -276,11 +276,13 @@ __global__ void control_kernel(Control c, int nb, int nev, int degree, int kmax,
   const int b = blockIdx.x;
   if (threadIdx.x != 0) return;
   int* fl = c.flags + 8 * b;
+  const int was32 = c.act32[b];
   if (fl[0]) {   // done before this iteration: keep its results
     c.active[b] = 0;
     c.act32[b] = 0;
     c.act64[b] = 0;
     c.lock[b] = 0;
+    c.sw[b] = 0;
     return;
   }
   const double* th = c.theta + (long long)b * nb;
@@ -322,6 +324,7 @@ __global__ void control_kernel(Control c, int nb, int nev, int degree, int kmax,
   c.active[b] = fl[0] ? 0 : 1;
   c.act32[b] = (!fl[0] && mixed && !fl[1]) ? 1 : 0;
   c.act64[b] = (!fl[0] && !(mixed && !fl[1])) ? 1 : 0;
+  c.sw[b] = (was32 && c.act64[b]) ? 1 : 0;
   // soft locking: the leading run of converged states, whole Kramers pairs,
   // is left out of the next filter (it stays in the block, so orthonormalisation
   // and Rayleigh-Ritz still see it, and it is released if its residual grows)
@@ -331,13 +334,11 @@ __global__ void control_kernel(Control c, int nb, int nev, int degree, int kmax,
   fl[6] = c.lock[b];
   // next filter: damp [a_cut, b_up], scaled to 1 at a0 = lowest Ritz value
   const double bup = bd[0];
-  double acut = th[nb - 1];
   const double a0 = th[0];
-  if (acut - a0 < 1e-9 * (bup - a0)) acut = a0 + 1e-9 * (bup - a0);
+  double acut = th[nb - 1], e, cc, sigma1;
+  cheb_interval(bup, a0, acut, &e, &cc, &sigma1);
   bd[1] = acut;
   bd[2] = a0;
-  const double e = 0.5 * (bup - acut), cc = 0.5 * (bup + acut);
-  const double sigma1 = e / (a0 - cc);
   double* co = c.coef + (long long)b * kmax * 4;
   double sig = sigma1;
   co[0] = sigma1 / e;

@@ -176,15 +176,17 @@ hipError_t launch_gram(const BlockDesc& A, const BlockDesc& B, int hermitian, in
 // output), in place allowed
 hipError_t launch_rotate(const BlockDesc& X, const BlockDesc& Y, int nin, int nout,
                          const double* Q, int batch, const int* active, hipStream_t s);
-// r[b][j] = || W_j - theta_j X_j ||^2 partial sums -> r
-hipError_t launch_resid(const BlockDesc& X, const BlockDesc& W, const double* theta,
-                        int batch, double* partial, double* r, const int* active,
-                        hipStream_t s);
-// Y1 = alpha (W - shift X) (first filter step from a known W = H X)
-hipError_t launch_cheb_first(const BlockDesc& X, const BlockDesc& W, void* out, int out_fp64,
-                             long long out_bstride, int batch, const double* coef,
-                             int coef_stride, const int* active, const int* lock,
-                             hipStream_t s);
+// workgroups per member of a rotation (and partial sums per vector of launch_ritz_w)
+int rotate_blocks(long long n, int batch);
+// Rayleigh-Ritz step on W = H X with Ritz vectors Q, X already rotated (XQ = X Q):
+// r2[b][j] = || (W Q)_j - theta_j XQ_j ||^2 and the first filter step
+// Y1 = alpha ((W Q) - shift XQ) (coefficients from theta and the upper bound),
+// FP32 into out32 where f32[b], else FP64 in place into W; partial holds
+// batch x nb x rotate_blocks(n, batch) doubles
+hipError_t launch_ritz_w(const BlockDesc& W, const BlockDesc& XQ, int nb, const double* Q,
+                         const double* theta, const double* bounds, const int* f32,
+                         float* out32, int batch, double* partial, double* r2,
+                         const int* active, hipStream_t s);
 hipError_t launch_cast(const void* in, int in_fp64, void* out, int out_fp64, long long count,
                        hipStream_t s);
 hipError_t launch_random_block(double* X, long long n, int nvec, int batch, long long bstride,
@@ -210,6 +212,25 @@ hipError_t launch_heev(double* A, int nb, int batch, long long mat_stride, doubl
                        double* out, int mode, int* status, const int* active, hipStream_t s,
                        int* again = nullptr);
 
+// first step of the scaled Chebyshev filter: damp [a_cut, b_up], value 1 at the
+// lowest Ritz value a0; Y1 = alpha (H - shift) X (the later steps' coefficients
+// follow from the same e, c and sigma_1)
+// (acut: the largest Ritz value, kept at least 1e-9 of the interval above a0)
+__device__ __forceinline__ void cheb_interval(double bup, double a0, double& acut, double* e,
+                                              double* c, double* sigma1) {
+  if (acut - a0 < 1e-9 * (bup - a0)) acut = a0 + 1e-9 * (bup - a0);
+  *e = 0.5 * (bup - acut);
+  *c = 0.5 * (bup + acut);
+  *sigma1 = *e / (a0 - *c);
+}
+__device__ __forceinline__ void cheb_first_coef(double bup, double a0, double acut,
+                                                double* alpha, double* shift) {
+  double e, c, s1;
+  cheb_interval(bup, a0, acut, &e, &c, &s1);
+  *alpha = s1 / e;
+  *shift = c;
+}
+
 // control: convergence flags, next Chebyshev coefficients
 struct Control {
   double* theta;     // [batch][nb]
@@ -221,6 +242,8 @@ struct Control {
   int* act32;        // [batch] not converged, FP32 filter
   int* act64;        // [batch] not converged, FP64 filter
   int* lock;         // [batch] leading vectors left out of the filter (converged pairs)
+  int* sw;           // [batch] next filter FP64 but its first step was written in FP32
+                     // (the member left the FP32 filter at this control step)
   int* work;         // [3][batch + 1] prefix sums of vectors to process per member:
                      // FP32 filter, FP64 filter (both after the lock), whole block
 };

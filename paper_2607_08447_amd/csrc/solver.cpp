@@ -8,8 +8,10 @@
 //                     normalised at the lowest Ritz value) -- m fused stencil
 //                     steps, FP64 or FP32 (mixed precision)
 //            orth:    SVQB twice (Gram, Jacobi eig, rotate), FP64
-//            RR:      W = H X (FP64), X^H W, Jacobi eig, X <- X Q, W <- W Q
-//            resid:   ||W_j - theta_j X_j||, convergence and next interval
+//            RR:      W = H X (FP64), X^H W, Jacobi eig, X <- X Q; one pass over
+//                     W forming W Q gives ||(W Q)_j - theta_j X_j|| and the next
+//                     filter's first step alpha (W Q - c X) (W Q is not stored)
+//            control: convergence, locking, precision and the next interval
 //   until    the nev lowest residuals are <= tol
 //
 // All per-iteration decisions (convergence, precision switch, filter
@@ -46,11 +48,11 @@ size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
 constexpr int kLanczosSteps = 40;
 constexpr int kKmax = 200;       // largest Chebyshev degree
 constexpr int kDotParts = 256;
-constexpr int kResParts = 64;
 
 struct Layout {
   size_t D64, D32, w64, v64, w32, v32, X, W, A32, B32, C32, E32, gram, mat1, mat2, theta, lam,
-      r2, rpart, coef, bounds, flags, active, act32, act64, lock, work, again, status, lal, lnrm,
+      r2, rpart, coef, bounds, flags, active, act32, act64, lock, sw, work, again, status, lal,
+      lnrm,
       lpart, zero, total;
 };
 
@@ -86,7 +88,7 @@ Layout make_layout(const Plan& p) {
   L.theta = take(B * p.nb * 8);
   L.lam = take(B * p.nb * 8);
   L.r2 = take(B * p.nb * 8);
-  L.rpart = take(B * p.nb * kResParts * 8);
+  L.rpart = take(B * p.nb * (size_t)rotate_blocks(p.n6, p.batch) * 8);   // residual partials
   L.coef = take(B * kKmax * 4 * 8);
   L.bounds = take(B * 4 * 8);
   L.flags = take(B * 8 * 4);
@@ -94,6 +96,7 @@ Layout make_layout(const Plan& p) {
   L.act32 = take(B * 4);
   L.act64 = take(B * 4);
   L.lock = take(B * 4);
+  L.sw = take(B * 4);
   L.work = take(3 * (B + 1) * 4);
   L.again = take(B * 4);
   L.status = take(B * 4 + 4);
@@ -266,7 +269,7 @@ struct Ctx {
     return Control{at<double>(L.theta), at<double>(L.r2),     at<double>(L.coef),
                    at<double>(L.bounds), at<int>(L.flags),    at<int>(L.active),
                    at<int>(L.act32),     at<int>(L.act64),    at<int>(L.lock),
-                   at<int>(L.work)};
+                   at<int>(L.sw),        at<int>(L.work)};
   }
 };
 
@@ -311,12 +314,25 @@ void apply_block(const Ctx& c, size_t x_off, size_t w_off, const int* active) {
   c.ss->launch(a, c.consts, c.s, c.p.N, c.active_members);
 }
 
-// Chebyshev filter of degree m (even) in FP64: the filtered block ends in X
+// Chebyshev filter of degree m (even) in FP64: the filtered block ends in X.
+// The first step Y1 = alpha (H - c) X is already in W (written by the
+// Rayleigh-Ritz step), except for members that have just left the FP32 filter
+// (their Y1 went to the FP32 buffer): for those one stencil pass computes it.
 void filter64(const Ctx& c, const int* active, int m) {
   const int kstride = kKmax * 4;
-  HKP_CHECK(launch_cheb_first(c.blk(c.L.X, c.p.nb), c.blk(c.L.W, c.p.nb), c.at<double>(c.L.W),
-                              1, c.bstride(), c.p.batch, c.at<double>(c.L.coef), kstride, active,
-                              c.at<int>(c.L.lock), c.s));
+  if (c.p.mixed) {
+    StencilLaunch a = base_launch(c, true, c.p.nb);
+    a.in = c.at<double>(c.L.X);
+    a.in_bstride = c.bstride();
+    a.out = c.at<double>(c.L.W);
+    a.out_fp64 = 1;
+    a.out_bstride = c.bstride();
+    a.coef.coef = c.at<double>(c.L.coef);
+    a.coef.stride = kstride;
+    a.active = c.at<int>(c.L.sw);
+    a.lock = c.at<int>(c.L.lock);
+    HKP_CHECK(launch_stencil(a, c.consts, c.s));
+  }
   size_t cur = c.L.W, oth = c.L.X;
   for (int k = 1; k < m; ++k) {
     StencilLaunch a = base_launch(c, true, c.p.nb);
@@ -338,15 +354,13 @@ void filter64(const Ctx& c, const int* active, int m) {
   }
 }
 
-// Chebyshev filter in FP32 (mixed precision): X (FP64) and W = H X start it,
-// the last step writes FP64 into X
+// Chebyshev filter in FP32 (mixed precision): the first step Y1 (FP32, written
+// by the Rayleigh-Ritz step) and X (FP64) start it, the last step writes FP64
+// into X
 void filter32(const Ctx& c, const int* active, int m) {
   const int kstride = kKmax * 4;
   float* A = c.at<float>(c.L.A32);
   float* Bf = c.at<float>(c.L.B32);
-  HKP_CHECK(launch_cheb_first(c.blk(c.L.X, c.p.nb), c.blk(c.L.W, c.p.nb), A, 0, c.bstride(),
-                              c.p.batch, c.at<double>(c.L.coef), kstride, active,
-                              c.at<int>(c.L.lock), c.s));
   // two-step passes for the middle of the recurrence when tuned for this grid
   Stencil2Launch t2{};
   bool two = false;
@@ -448,6 +462,10 @@ void orthonormalise(const Ctx& c, const int* active) {
   svqb(c, again);
 }
 
+// Rayleigh-Ritz: W = H X, X^H W, its eigenpairs (theta, Q), X <- X Q; then one
+// pass over W gives the residual norms ||W Q_j - theta_j X_j|| and the next
+// filter's first step alpha (W Q - c X) (FP32 for members filtered in FP32,
+// else FP64 into W), without storing W Q
 void rayleigh_ritz(const Ctx& c, const int* active) {
   BlockDesc X = c.blk(c.L.X, c.p.nb), W = c.blk(c.L.W, c.p.nb);
   apply_block(c, c.L.X, c.L.W, active);
@@ -457,12 +475,10 @@ void rayleigh_ritz(const Ctx& c, const int* active) {
                         c.at<double>(c.L.theta), c.at<double>(c.L.mat2), 0, nullptr, active,
                         c.s));
   HKP_CHECK(launch_rotate(X, X, c.p.nb, c.p.nb, c.at<double>(c.L.mat2), c.p.batch, active, c.s));
-  HKP_CHECK(launch_rotate(W, W, c.p.nb, c.p.nb, c.at<double>(c.L.mat2), c.p.batch, active, c.s));
-}
-
-void residuals(const Ctx& c, const int* active) {
-  HKP_CHECK(launch_resid(c.blk(c.L.X, c.p.nb), c.blk(c.L.W, c.p.nb), c.at<double>(c.L.theta),
-                         c.p.batch, c.at<double>(c.L.rpart), c.at<double>(c.L.r2), active, c.s));
+  HKP_CHECK(launch_ritz_w(W, X, c.p.nb, c.at<double>(c.L.mat2), c.at<double>(c.L.theta),
+                          c.at<double>(c.L.bounds), c.at<int>(c.L.act32),
+                          c.p.mixed ? c.at<float>(c.L.A32) : nullptr, c.p.batch,
+                          c.at<double>(c.L.rpart), c.at<double>(c.L.r2), active, c.s));
 }
 
 // k-step Lanczos per Hamiltonian: upper spectral bound (theta_max + beta_k)
@@ -563,9 +579,14 @@ Plan make_plan(const hkp_grid& g, const hkp_opts& o, int batch) {
   p.nb = block_size(g, o);
   // degree 0: ramp 16 -> 32 -> m_max over the first outer iterations, so that
   // the amplification of the lowest components relative to the filter's cut
-  // stays within the arithmetic's dynamic range while the interval settles
+  // stays within the arithmetic's dynamic range while the interval settles.
+  // m_max: 96 in FP64; in FP32 it grows with the block, 48 + nb within
+  // [64, 96], since the per-iteration orthonormalisation and Rayleigh-Ritz cost
+  // grows faster with the block than a filter step does (measured optimum 88 at
+  // block 40 and 64 at block 16)
   p.degree_fixed = o.degree > 0;
-  int m = o.degree > 0 ? o.degree : (o.precision == HKP_PREC_MIXED ? 64 : 96);
+  int m = o.degree > 0 ? o.degree
+                       : (o.precision == HKP_PREC_MIXED ? std::min(96, std::max(64, 48 + p.nb)) : 96);
   if (m & 1) ++m;
   if (m > kKmax) m = kKmax;
   p.degree = m;
@@ -636,6 +657,7 @@ int run_solve(const SolveArgs& A, hkp_stats* stats) {
   HKP_CHECK(launch_fill_int(c.at<int>(c.L.act32), p.batch, p.mixed ? 1 : 0, c.s));
   HKP_CHECK(launch_fill_int(c.at<int>(c.L.act64), p.batch, p.mixed ? 0 : 1, c.s));
   HKP_CHECK(launch_fill_int(c.at<int>(c.L.lock), p.batch, 0, c.s));
+  HKP_CHECK(launch_fill_int(c.at<int>(c.L.sw), p.batch, 0, c.s));
   HKP_CHECK(launch_worktable(c.control(), p.batch, p.nb, c.s));
 
   // ---- spectral bound
@@ -691,7 +713,6 @@ int run_solve(const SolveArgs& A, hkp_stats* stats) {
   const int* act = c.at<int>(c.L.active);
   orthonormalise(c, act);
   rayleigh_ritz(c, act);
-  residuals(c, act);
   HKP_CHECK(launch_control(c.control(), p.batch, p.nb, p.nev, kKmax, kKmax, A.tol, p.mixed,
                            !(A.flags & HKP_FLAG_NO_FP64_POLISH), !(A.flags & HKP_FLAG_NO_LOCK), 0,
                            c.s));
@@ -765,12 +786,13 @@ int run_solve(const SolveArgs& A, hkp_stats* stats) {
     rayleigh_ritz(c, act);
     t_rr.stop(c.s);
     t_res.start(c.s);
-    residuals(c, act);
-    // stagnation toward the FP32 floor is judged on full-degree iterations
-    // only: during the degree ramp a slow decrease is the low degree's
+    // stagnation toward the FP32 floor is judged after the degree ramp only
+    // (during the ramp a slow decrease is the low degree's); graph replays
+    // (it < 0) come after it
+    const bool past_ramp = it < 0 || it > 2 || m_cur >= p.degree;
     HKP_CHECK(launch_control(c.control(), p.batch, p.nb, p.nev, kKmax, kKmax, A.tol,
                              p.mixed,
-                             !(A.flags & HKP_FLAG_NO_FP64_POLISH) && m_cur >= p.degree,
+                             !(A.flags & HKP_FLAG_NO_FP64_POLISH) && past_ramp,
                              !(A.flags & HKP_FLAG_NO_LOCK), it, c.s));
     t_res.stop(c.s);
   };
