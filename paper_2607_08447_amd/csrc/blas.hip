@@ -540,14 +540,14 @@ gram_reduce_kernel(int nchunks, int nba, int nbb, int hermitian, const int* acti
 // ---------------------------------------------------------------------------
 constexpr int kRotWaves = 4;
 
-// The Rayleigh-Ritz form of the rotation of W = H X (RITZ): with Q the Ritz
-// vectors and X already rotated (XQ = X Q), every output column w of W Q gives
-//   r2_w += |(W Q)_w - theta_w XQ_w|^2        (residual norm, partial sums)
-//   Y1_w  = alpha ((W Q)_w - c XQ_w)          (the filter's first Chebyshev step)
+// The Rayleigh-Ritz form (RITZ): X <- X Q in place and, in the same pass, W Q
+// for W = H X (same strides), kept in registers: every output column w gives
+//   r2_w += |(W Q)_w - theta_w (X Q)_w|^2       (residual norm, partial sums)
+//   Y1_w  = alpha ((W Q)_w - c (X Q)_w)         (the filter's first Chebyshev step)
 // and W Q itself is not stored.  Y1 is FP32 (into out32) for members whose
 // filter runs in FP32 (f32[b]), else FP64 in place into W.
 struct RitzArgs {
-  const double* XQ;       // rotated X, strides of W
+  double* W;              // H X, strides of X
   const double* theta;    // [batch][nb] Ritz values (ascending)
   const double* bounds;   // [batch][4]: upper spectral bound first
   const int* f32;         // [batch] FP32 output
@@ -584,10 +584,14 @@ rotate_kernel(const double* X, long long x_bstride, double* Y, long long y_bstri
     }
     qt[t] = a;
   }
-  // RITZ: residual sums per wave and output vector (lanes 16 q add theirs)
+  // RITZ: residual sums per wave and output vector (lanes 16 q add theirs) and
+  // the Ritz values
   __shared__ double red[RITZ ? kRotWaves : 1][RITZ ? NB8 : 1];
+  __shared__ double ths[RITZ ? NB8 : 1];
   if constexpr (RITZ) {
     for (int t = threadIdx.x; t < kRotWaves * NB8; t += blockDim.x) (&red[0][0])[t] = 0.0;
+    for (int t = threadIdx.x; t < NB8; t += blockDim.x)
+      ths[t] = t < ra.nb ? ra.theta[(long long)b * ra.nb + t] : 0.0;
   }
   __syncthreads();
   const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -596,62 +600,86 @@ rotate_kernel(const double* X, long long x_bstride, double* Y, long long y_bstri
   const double* xb = X + 2 * ((long long)b * x_bstride);
   double* yb = Y + 2 * ((long long)b * y_bstride);
   const long long ntile = (n + 15) / 16;
-  // RITZ: this member's first-step coefficients (the control kernel computes the
-  // same ones from the same Ritz values), output precision, residual sums
-  double r_alpha = 0.0, r_shift = 0.0;
-  bool r_f32 = false;
-  const double* thb = nullptr;
-  const double* xqb = nullptr;
-  float* o32 = nullptr;
-  if constexpr (RITZ) {
-    thb = ra.theta + (long long)b * ra.nb;
-    cheb_first_coef(ra.bounds[4 * b], thb[0], thb[ra.nb - 1], &r_alpha, &r_shift);
-    r_f32 = ra.f32 && ra.f32[b];
-    xqb = ra.XQ + 2 * ((long long)b * y_bstride);
-    o32 = ra.out32 ? ra.out32 + 2 * ((long long)b * y_bstride) : nullptr;
+  // loads need no branch: an element past n reads element n - 1 (its results
+  // are not stored) and an input vector past nin reads vector nin - 1 (its
+  // operand entries are zero), so all of a tile's loads issue back to back
+  int vcl[KS];
+#pragma unroll
+  for (int s = 0; s < KS; ++s) {
+    const int v = 2 * s + (q >> 1);
+    vcl[s] = v < nin ? v : nin - 1;
   }
-  for (long long tile = (long long)blockIdx.x * kRotWaves + wv; tile < ntile;
-       tile += (long long)gridDim.x * kRotWaves) {
-    const long long e = tile * 16 + r;
-    const bool eok = e < n;
-    // B operand: X^T[k][e], k = 2 v + part
-    double xv[KS];
+  if constexpr (!RITZ) {
+    for (long long tile = (long long)blockIdx.x * kRotWaves + wv; tile < ntile;
+         tile += (long long)gridDim.x * kRotWaves) {
+      const long long e = tile * 16 + r;
+      const bool eok = e < n;
+      const long long ec = eok ? e : n - 1;
+      // B operand: X^T[k][e], k = 2 v + part
+      double xv[KS];
 #pragma unroll
-    for (int s = 0; s < KS; ++s) {
-      const int v = 2 * s + (q >> 1);
-      xv[s] = (eok && v < nin) ? xb[2 * ((long long)v * n + e) + (q & 1)] : 0.0;
-    }
-    auto out_tile = [&](int m) {
-      const double* qm = qt + m * KS * 64 + lane;
-      d4 acc = d4{0, 0, 0, 0};
+      for (int s = 0; s < KS; ++s) xv[s] = xb[2 * ((long long)vcl[s] * n + ec) + (q & 1)];
+      for (int m = 0; m < mt; ++m) {
+        const double* qm = qt + m * KS * 64 + lane;
+        d4 acc = d4{0, 0, 0, 0};
 #pragma unroll
-      for (int s = 0; s < KS; ++s) acc = mfma(qm[s * 64], xv[s], acc);
-      // D[mrow][e]: lane holds (w0, re), (w0, im), (w0+1, re), (w0+1, im)
-      const int w0 = m * 8 + 2 * q;
-      if constexpr (!RITZ) {
+        for (int s = 0; s < KS; ++s) acc = mfma(qm[s * 64], xv[s], acc);
+        // D[mrow][e]: lane holds (w0, re), (w0, im), (w0+1, re), (w0+1, im)
+        const int w0 = m * 8 + 2 * q;
         if (eok) {
           if (w0 < nout)
             *reinterpret_cast<double2*>(yb + 2 * ((long long)w0 * n + e)) = make_double2(acc[0], acc[1]);
           if (w0 + 1 < nout)
             *reinterpret_cast<double2*>(yb + 2 * ((long long)(w0 + 1) * n + e)) = make_double2(acc[2], acc[3]);
         }
-      } else {
+      }
+    }
+  } else {
+    // this member's first-step coefficients (the control kernel computes the
+    // same ones from the same Ritz values) and output precision; here
+    // nout = nin, so every one of the MT output tiles exists
+    double r_alpha, r_shift;
+    cheb_first_coef(ra.bounds[4 * b], ths[0], ths[ra.nb - 1], &r_alpha, &r_shift);
+    const bool r_f32 = ra.f32 && ra.f32[b];
+    double* wb = ra.W + 2 * ((long long)b * x_bstride);
+    float* o32 = ra.out32 ? ra.out32 + 2 * ((long long)b * x_bstride) : nullptr;
+    for (long long tile = (long long)blockIdx.x * kRotWaves + wv; tile < ntile;
+         tile += (long long)gridDim.x * kRotWaves) {
+      const long long e = tile * 16 + r;
+      const bool eok = e < n;
+      const long long ec = eok ? e : n - 1;
+      double xv[KS], wvv[KS];
+#pragma unroll
+      for (int s = 0; s < KS; ++s) xv[s] = xb[2 * ((long long)vcl[s] * n + ec) + (q & 1)];
+#pragma unroll
+      for (int s = 0; s < KS; ++s) wvv[s] = wb[2 * ((long long)vcl[s] * n + ec) + (q & 1)];
+      for (int m = 0; m < mt; ++m) {
+        const double* qm = qt + m * KS * 64 + lane;
+        d4 ax = d4{0, 0, 0, 0}, aw = d4{0, 0, 0, 0};
+#pragma unroll
+        for (int s = 0; s < KS; ++s) {
+          const double qv = qm[s * 64];
+          ax = mfma(qv, xv[s], ax);
+          aw = mfma(qv, wvv[s], aw);
+        }
+        const int w0 = m * 8 + 2 * q;
         double d2[2];
 #pragma unroll
         for (int j = 0; j < 2; ++j) {
           const int w = w0 + j;
-          d2[j] = 0.0;
-          if (eok && w < nout) {
+          const bool ok = eok && w < nout;
+          const double xr = ax[2 * j], xi = ax[2 * j + 1];
+          const double ar = aw[2 * j], ai = aw[2 * j + 1], th = ths[w];
+          const double dr = ar - th * xr, di = ai - th * xi;
+          d2[j] = ok ? fma(dr, dr, di * di) : 0.0;
+          const double yr = r_alpha * (ar - r_shift * xr), yi = r_alpha * (ai - r_shift * xi);
+          if (ok) {
             const long long o = 2 * ((long long)w * n + e);
-            const double2 xq = *reinterpret_cast<const double2*>(xqb + o);
-            const double ar = acc[2 * j], ai = acc[2 * j + 1], th = thb[w];
-            const double dr = ar - th * xq.x, di = ai - th * xq.y;
-            d2[j] = fma(dr, dr, di * di);
-            const double yr = r_alpha * (ar - r_shift * xq.x), yi = r_alpha * (ai - r_shift * xq.y);
+            *reinterpret_cast<double2*>(yb + o) = make_double2(xr, xi);
             if (r_f32)
               *reinterpret_cast<float2*>(o32 + o) = make_float2((float)yr, (float)yi);
             else
-              *reinterpret_cast<double2*>(yb + o) = make_double2(yr, yi);
+              *reinterpret_cast<double2*>(wb + o) = make_double2(yr, yi);
           }
         }
         // this tile's sums over the 16 elements of each lane group, added by
@@ -664,10 +692,7 @@ rotate_kernel(const double* X, long long x_bstride, double* Y, long long y_bstri
           red[wv][w0 + 1] += d2[1];
         }
       }
-    };
-    for (int m = 0; m < mt; ++m) out_tile(m);
-  }
-  if constexpr (RITZ) {
+    }
     // the waves' sums in a fixed order
     __syncthreads();
     if ((int)threadIdx.x < nout) {
@@ -957,17 +982,17 @@ hipError_t launch_rotate(const BlockDesc& X, const BlockDesc& Y, int nin, int no
   return rotate_any<false>(X, Y, nin, nout, Q, batch, active, RitzArgs{}, s);
 }
 
-hipError_t launch_ritz_w(const BlockDesc& W, const BlockDesc& XQ, int nb, const double* Q,
-                         const double* theta, const double* bounds, const int* f32,
-                         float* out32, int batch, double* partial, double* r2,
-                         const int* active, hipStream_t s) {
-  if (W.bstride != XQ.bstride || W.n != XQ.n || W.nvec < nb || XQ.nvec < nb)
+hipError_t launch_ritz(const BlockDesc& X, const BlockDesc& W, int nb, const double* Q,
+                       const double* theta, const double* bounds, const int* f32,
+                       float* out32, int batch, double* partial, double* r2,
+                       const int* active, hipStream_t s) {
+  if (W.bstride != X.bstride || W.n != X.n || W.nvec < nb || X.nvec < nb)
     return hipErrorInvalidValue;
-  const RitzArgs ra{XQ.ptr, theta, bounds, f32, out32, partial, nb};
-  hipError_t e = rotate_any<true>(W, W, nb, nb, Q, batch, active, ra, s);
+  const RitzArgs ra{W.ptr, theta, bounds, f32, out32, partial, nb};
+  hipError_t e = rotate_any<true>(X, X, nb, nb, Q, batch, active, ra, s);
   if (e != hipSuccess) return e;
   sum_rows_kernel<<<dim3((unsigned)nb, (unsigned)batch), 256, 0, s>>>(
-      rotate_blocks(W.n, batch), partial, r2, active, nb);
+      rotate_blocks(X.n, batch), partial, r2, active, nb);
   return hipGetLastError();
 }
 

@@ -444,6 +444,74 @@ hipError_t launch_fill_int(int* p, int count, int value, hipStream_t s) {
   return hipGetLastError();
 }
 
+namespace {
+
+// small complex products of the block step, one workgroup per member, operands
+// in LDS: C = op(A) B (op: A, or A^H), or with unit set C = I.  Row-major nb x nb.
+constexpr int kGemmThreads = 256;
+
+__global__ void __launch_bounds__(kGemmThreads)
+small_gemm_kernel(const double* A, int adj, const double* B, double* C, int nb,
+                  long long mat_stride, int herm, const int* active) {
+  const int b = blockIdx.x;
+  if (active && !active[b]) return;
+  __shared__ double2 sa[kNBP * kNBP], sb[kNBP * kNBP];
+  const double2* Ab = reinterpret_cast<const double2*>(A + 2 * (long long)b * mat_stride);
+  const double2* Bb = reinterpret_cast<const double2*>(B + 2 * (long long)b * mat_stride);
+  double2* Cb = reinterpret_cast<double2*>(C + 2 * (long long)b * mat_stride);
+  const int nn = nb * nb;
+  for (int t = threadIdx.x; t < nn; t += kGemmThreads) {
+    sa[t] = Ab[t];
+    sb[t] = Bb[t];
+  }
+  __syncthreads();
+  // C[i][j] = sum_k op(A)[i][k] B[k][j]; op(A)[i][k] = A[i][k] or conj(A[k][i])
+  auto entry = [&](int i, int j) {
+    double re = 0.0, im = 0.0;
+    for (int k = 0; k < nb; ++k) {
+      const double2 a = adj ? make_double2(sa[k * nb + i].x, -sa[k * nb + i].y) : sa[i * nb + k];
+      const double2 v = sb[k * nb + j];
+      re = fma(a.x, v.x, fma(-a.y, v.y, re));
+      im = fma(a.x, v.y, fma(a.y, v.x, im));
+    }
+    return make_double2(re, im);
+  };
+  for (int t = threadIdx.x; t < nn; t += kGemmThreads) {
+    const int i = t / nb, j = t - (t / nb) * nb;
+    double2 c = entry(i, j);
+    if (herm) {   // the Hermitian part (the product is Hermitian up to rounding)
+      const double2 d = entry(j, i);
+      c = make_double2(0.5 * (c.x + d.x), 0.5 * (c.y - d.y));
+      if (i == j) c.y = 0.0;
+    }
+    Cb[t] = c;
+  }
+}
+
+__global__ void set_identity_kernel(double* C, int nb, long long mat_stride, const int* active) {
+  const int b = blockIdx.x;
+  if (active && !active[b]) return;
+  double2* Cb = reinterpret_cast<double2*>(C + 2 * (long long)b * mat_stride);
+  for (int t = threadIdx.x; t < nb * nb; t += blockDim.x)
+    Cb[t] = make_double2(t / nb == t % nb ? 1.0 : 0.0, 0.0);
+}
+
+}  // namespace
+
+hipError_t launch_small_gemm(const double* A, int adj, const double* B, double* C, int nb,
+                             int batch, long long mat_stride, int herm, const int* active,
+                             hipStream_t s) {
+  if (nb > HKP_NB_MAX || nb < 1 || C == A || C == B) return hipErrorInvalidValue;
+  small_gemm_kernel<<<batch, kGemmThreads, 0, s>>>(A, adj, B, C, nb, mat_stride, herm, active);
+  return hipGetLastError();
+}
+
+hipError_t launch_set_identity(double* C, int nb, int batch, long long mat_stride,
+                               const int* active, hipStream_t s) {
+  set_identity_kernel<<<batch, 256, 0, s>>>(C, nb, mat_stride, active);
+  return hipGetLastError();
+}
+
 hipError_t launch_heev(double* A, int nb, int batch, long long mat_stride, double* evals,
                        double* out, int mode, int* status, const int* active, hipStream_t s,
                        int* again) {

@@ -176,17 +176,17 @@ hipError_t launch_gram(const BlockDesc& A, const BlockDesc& B, int hermitian, in
 // output), in place allowed
 hipError_t launch_rotate(const BlockDesc& X, const BlockDesc& Y, int nin, int nout,
                          const double* Q, int batch, const int* active, hipStream_t s);
-// workgroups per member of a rotation (and partial sums per vector of launch_ritz_w)
+// workgroups per member of a rotation (and partial sums per vector of launch_ritz)
 int rotate_blocks(long long n, int batch);
-// Rayleigh-Ritz step on W = H X with Ritz vectors Q, X already rotated (XQ = X Q):
-// r2[b][j] = || (W Q)_j - theta_j XQ_j ||^2 and the first filter step
-// Y1 = alpha ((W Q) - shift XQ) (coefficients from theta and the upper bound),
-// FP32 into out32 where f32[b], else FP64 in place into W; partial holds
-// batch x nb x rotate_blocks(n, batch) doubles
-hipError_t launch_ritz_w(const BlockDesc& W, const BlockDesc& XQ, int nb, const double* Q,
-                         const double* theta, const double* bounds, const int* f32,
-                         float* out32, int batch, double* partial, double* r2,
-                         const int* active, hipStream_t s);
+// Rayleigh-Ritz rotation with Ritz vectors Q of X^H W (W = H X): X <- X Q in
+// place, r2[b][j] = || (W Q)_j - theta_j (X Q)_j ||^2 and the first filter step
+// Y1 = alpha (W Q - shift X Q) (coefficients from theta and the upper bound),
+// FP32 into out32 where f32[b], else FP64 in place into W; W Q is not stored.
+// partial holds batch x nb x rotate_blocks(n, batch) doubles
+hipError_t launch_ritz(const BlockDesc& X, const BlockDesc& W, int nb, const double* Q,
+                       const double* theta, const double* bounds, const int* f32,
+                       float* out32, int batch, double* partial, double* r2,
+                       const int* active, hipStream_t s);
 hipError_t launch_cast(const void* in, int in_fp64, void* out, int out_fp64, long long count,
                        hipStream_t s);
 hipError_t launch_random_block(double* X, long long n, int nvec, int batch, long long bstride,
@@ -208,6 +208,13 @@ hipError_t launch_scale(double* v, long long n, int batch, long long bstride,
 // mode 1 (SVQB): A = Gram S -> T = D U diag(lambda)^-1/2, D = diag(S)^-1/2
 // SVQB mode: again[b] (if given) is set to 1 when the Gram matrix is so ill
 // conditioned that a second pass is needed (and the member is active)
+// C = op(A) B per member (op: A if adj = 0, A^H if adj = 1), nb x nb complex
+// row-major; herm: store the Hermitian part; C must not alias A or B
+hipError_t launch_small_gemm(const double* A, int adj, const double* B, double* C, int nb,
+                             int batch, long long mat_stride, int herm, const int* active,
+                             hipStream_t s);
+hipError_t launch_set_identity(double* C, int nb, int batch, long long mat_stride,
+                               const int* active, hipStream_t s);
 hipError_t launch_heev(double* A, int nb, int batch, long long mat_stride, double* evals,
                        double* out, int mode, int* status, const int* active, hipStream_t s,
                        int* again = nullptr);

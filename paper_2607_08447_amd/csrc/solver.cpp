@@ -8,9 +8,9 @@
 //                     normalised at the lowest Ritz value) -- m fused stencil
 //                     steps, FP64 or FP32 (mixed precision)
 //            orth:    SVQB twice (Gram, Jacobi eig, rotate), FP64
-//            RR:      W = H X (FP64), X^H W, Jacobi eig, X <- X Q; one pass over
-//                     W forming W Q gives ||(W Q)_j - theta_j X_j|| and the next
-//                     filter's first step alpha (W Q - c X) (W Q is not stored)
+//            RR:      W = H X (FP64), X^H W, Jacobi eig; one pass over X and W
+//                     gives X <- X Q, ||(W Q)_j - theta_j (X Q)_j|| and the next
+//                     filter's first step alpha (W Q - c X Q) (W Q is not stored)
 //            control: convergence, locking, precision and the next interval
 //   until    the nev lowest residuals are <= tol
 //
@@ -50,7 +50,8 @@ constexpr int kKmax = 200;       // largest Chebyshev degree
 constexpr int kDotParts = 256;
 
 struct Layout {
-  size_t D64, D32, w64, v64, w32, v32, X, W, A32, B32, C32, E32, gram, mat1, mat2, theta, lam,
+  size_t D64, D32, w64, v64, w32, v32, X, W, A32, B32, C32, E32, gram, mat1, mat2, mat3, mat4,
+      theta, lam,
       r2, rpart, coef, bounds, flags, active, act32, act64, lock, sw, work, again, status, lal,
       lnrm,
       lpart, zero, total;
@@ -85,6 +86,8 @@ Layout make_layout(const Plan& p) {
   L.gram = take(gram_partial_bytes(p.nb, n6, p.batch));
   L.mat1 = take(B * p.nb * p.nb * 16);
   L.mat2 = take(B * p.nb * p.nb * 16);
+  L.mat3 = take(B * p.nb * p.nb * 16);
+  L.mat4 = take(B * p.nb * p.nb * 16);
   L.theta = take(B * p.nb * 8);
   L.lam = take(B * p.nb * 8);
   L.r2 = take(B * p.nb * 8);
@@ -443,42 +446,55 @@ void filter32(const Ctx& c, const int* active, int m) {
   while (k < m) one_step(k++);
 }
 
-// one SVQB pass on X; `again` (optional) receives the per-member need for a second pass
-void svqb(const Ctx& c, const int* active, int* again = nullptr) {
+// SVQB factor of X: S = D U diag(lambda)^-1/2 from X^H X (X S orthonormal) into
+// `out`; `again` (optional) receives the per-member need for a second pass
+void svqb_factor(const Ctx& c, const int* active, size_t out, int* again = nullptr) {
   BlockDesc X = c.blk(c.L.X, c.p.nb);
   HKP_CHECK(launch_gram(X, X, 1, c.p.batch, c.at<double>(c.L.gram), c.at<double>(c.L.mat1),
                         active, c.s));
   HKP_CHECK(launch_heev(c.at<double>(c.L.mat1), c.p.nb, c.p.batch, (long long)c.p.nb * c.p.nb,
-                        c.at<double>(c.L.lam), c.at<double>(c.L.mat2), 1, c.at<int>(c.L.status),
+                        c.at<double>(c.L.lam), c.at<double>(out), 1, c.at<int>(c.L.status),
                         active, c.s, again));
-  HKP_CHECK(launch_rotate(X, X, c.p.nb, c.p.nb, c.at<double>(c.L.mat2), c.p.batch, active, c.s));
 }
 
-// orthonormalise X: SVQB, repeated (only for the members that need it) when
-// the first Gram matrix was ill conditioned
+// orthonormalise X by SVQB: its factor S goes to mat3 and is applied by the
+// Rayleigh-Ritz rotation (X S Q in one pass over the block).  Members whose Gram
+// matrix was ill conditioned (one pass would leave an orthogonality error
+// ~ eps kappa) are rotated now and take a second pass; their mat3 is I.
 void orthonormalise(const Ctx& c, const int* active) {
   int* again = c.at<int>(c.L.again);
-  svqb(c, active, again);
-  svqb(c, again);
+  const long long ms = (long long)c.p.nb * c.p.nb;
+  BlockDesc X = c.blk(c.L.X, c.p.nb);
+  svqb_factor(c, active, c.L.mat3, again);
+  HKP_CHECK(launch_rotate(X, X, c.p.nb, c.p.nb, c.at<double>(c.L.mat3), c.p.batch, again, c.s));
+  svqb_factor(c, again, c.L.mat2);
+  HKP_CHECK(launch_rotate(X, X, c.p.nb, c.p.nb, c.at<double>(c.L.mat2), c.p.batch, again, c.s));
+  HKP_CHECK(launch_set_identity(c.at<double>(c.L.mat3), c.p.nb, c.p.batch, ms, again, c.s));
 }
 
-// Rayleigh-Ritz: W = H X, X^H W, its eigenpairs (theta, Q), X <- X Q; then one
-// pass over W gives the residual norms ||W Q_j - theta_j X_j|| and the next
-// filter's first step alpha (W Q - c X) (FP32 for members filtered in FP32,
-// else FP64 into W), without storing W Q
+// Rayleigh-Ritz on the span of X S (S in mat3, the SVQB factor or I): W = H X,
+// the projection S^H (X^H W) S, its eigenpairs (theta, Q), T = S Q; then one
+// pass over X and W gives X <- X T, the residual norms ||(W T)_j - theta_j
+// (X T)_j|| and the next filter's first step alpha (W T - c X T) (FP32 for
+// members filtered in FP32, else FP64 into W), without storing W T
 void rayleigh_ritz(const Ctx& c, const int* active) {
   BlockDesc X = c.blk(c.L.X, c.p.nb), W = c.blk(c.L.W, c.p.nb);
+  const long long ms = (long long)c.p.nb * c.p.nb;
+  double* S = c.at<double>(c.L.mat3);
+  double* M = c.at<double>(c.L.mat1);
+  double* Q = c.at<double>(c.L.mat2);
+  double* tmp = c.at<double>(c.L.mat4);
   apply_block(c, c.L.X, c.L.W, active);
-  HKP_CHECK(launch_gram(X, W, 1, c.p.batch, c.at<double>(c.L.gram), c.at<double>(c.L.mat1),
+  HKP_CHECK(launch_gram(X, W, 1, c.p.batch, c.at<double>(c.L.gram), M, active, c.s));
+  HKP_CHECK(launch_small_gemm(M, 0, S, tmp, c.p.nb, c.p.batch, ms, 0, active, c.s));
+  HKP_CHECK(launch_small_gemm(S, 1, tmp, M, c.p.nb, c.p.batch, ms, 1, active, c.s));
+  HKP_CHECK(launch_heev(M, c.p.nb, c.p.batch, ms, c.at<double>(c.L.theta), tmp, 0, nullptr,
                         active, c.s));
-  HKP_CHECK(launch_heev(c.at<double>(c.L.mat1), c.p.nb, c.p.batch, (long long)c.p.nb * c.p.nb,
-                        c.at<double>(c.L.theta), c.at<double>(c.L.mat2), 0, nullptr, active,
-                        c.s));
-  HKP_CHECK(launch_rotate(X, X, c.p.nb, c.p.nb, c.at<double>(c.L.mat2), c.p.batch, active, c.s));
-  HKP_CHECK(launch_ritz_w(W, X, c.p.nb, c.at<double>(c.L.mat2), c.at<double>(c.L.theta),
-                          c.at<double>(c.L.bounds), c.at<int>(c.L.act32),
-                          c.p.mixed ? c.at<float>(c.L.A32) : nullptr, c.p.batch,
-                          c.at<double>(c.L.rpart), c.at<double>(c.L.r2), active, c.s));
+  HKP_CHECK(launch_small_gemm(S, 0, tmp, Q, c.p.nb, c.p.batch, ms, 0, active, c.s));
+  HKP_CHECK(launch_ritz(X, W, c.p.nb, c.at<double>(c.L.mat2), c.at<double>(c.L.theta),
+                        c.at<double>(c.L.bounds), c.at<int>(c.L.act32),
+                        c.p.mixed ? c.at<float>(c.L.A32) : nullptr, c.p.batch,
+                        c.at<double>(c.L.rpart), c.at<double>(c.L.r2), active, c.s));
 }
 
 // k-step Lanczos per Hamiltonian: upper spectral bound (theta_max + beta_k)
