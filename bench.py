@@ -788,11 +788,11 @@ def main():
                          hkp.workspace_bytes(w.shape, w.h, nev, nb=nbs["fp64"], precision="fp64")),
                      dtype=torch.uint8, device="cuda")
 
-    def solve(prec, t):
+    def solve(prec, t, product=False):
         # eigenvectors returned (|J m_j> basis, symmetric gauge, ABI layout): the
         # output step is part of every timed solve
         return hkp.solve(V, w.h, nev, strain=S, B=w.B, nb=nbs[prec], tol=t, precision=prec,
-                         workspace=ws, return_psi=True)
+                         workspace=ws, return_psi=True, cheb_product=product)
 
     t0 = time.perf_counter()
     ref = solve("fp64", 1e-8)
@@ -827,6 +827,43 @@ def main():
     err_fp64 = float(np.abs(r64.E.cpu().numpy() - E_ref).max())
     per_fp64 = np.abs(r64.E.cpu().numpy() - E_oracle)
     log(f"FP64 solve (tol {tol}): {t_fp64:.3f} s, max |dE| {err_fp64:.2e}")
+
+    # the same solves with the filter in product form (the same polynomial over
+    # its roots: one block read and one written per step instead of two read)
+    log("product-form filter ...")
+    solve("mixed", tol, product=True)
+    torch.cuda.synchronize()
+    pstats, perrs, pstatus = [], [], []
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        r = solve("mixed", tol, product=True)
+        pstats.append(r.stats)
+        perrs.append(r.E)
+        pstatus.append(int(r.status))
+    torch.cuda.synchronize()
+    t_prod = (time.perf_counter() - t0) / args.steps
+    t0 = time.perf_counter()
+    r64p = solve("fp64", tol, product=True)
+    torch.cuda.synchronize()
+    t_prod64 = time.perf_counter() - t0
+    pn32 = sum(s["n_stencil32"] for s in pstats)
+    pb32 = sum(s["bytes_stencil32"] for s in pstats) / max(pn32, 1)
+    pt32 = sum(s["t_stencil32"] for s in pstats) / max(pn32, 1)
+    product_form = {
+        "s_per_solve_mixed": round(t_prod, 4),
+        "s_per_solve_fp64": round(t_prod64, 4),
+        "hx_gbps": round(sum(s["hx_bytes"] for s in pstats) / (t_prod * args.steps) / 1e9, 1),
+        "iters_mixed": pstats[-1]["iters"], "iters_fp64": r64p.stats["iters"],
+        "max_err_mixed_vs_oracle_eV": float(max(np.abs(e.cpu().numpy() - E_oracle).max()
+                                                for e in perrs)),
+        "max_err_fp64_vs_oracle_eV": float(np.abs(r64p.E.cpu().numpy() - E_oracle).max()),
+        "stencil_fp32": {"launches": pn32, "algorithmic_bytes_per_launch": pb32,
+                         "avg_launch_us": round(pt32 * 1e6, 1),
+                         "gbps": round(pb32 / max(pt32, 1e-12) / 1e9, 1),
+                         "frac": round(pb32 / max(pt32, 1e-12) / 1e9 / HBM_PEAK_GBPS, 4)},
+        "status_mixed": max(pstatus), "status_fp64": int(r64p.status),
+    }
+    log(f"product form {product_form}")
 
     hx_bytes = sum(s["hx_bytes"] for s in stats)
     n32 = sum(s["n_stencil32"] for s in stats)
@@ -910,6 +947,8 @@ def main():
                               if "triad_gbps" in extra else None),
         },
         "stencil_launch": {"fp32": tune32, "fp64": tune64},
+        "filter": "three-term recurrence (Y_k+1 = alpha (H - c) Y_k + beta Y_k-1)",
+        "product_form": product_form,
         "fp64_stencil_gbps": round(r64.stats["bytes_stencil64"] /
                                    max(r64.stats["t_stencil64"], 1e-12) / 1e9, 1),
     }

@@ -77,6 +77,13 @@ extern "C" {
 #define HKP_FLAG_PSI_BLOCK 32   /* psi receives the whole final block of nb Ritz vectors
                                  * (ascending Ritz values; eig and resid still nev), the
                                  * initial block of a restart that keeps the guard vectors */
+#define HKP_FLAG_CHEB_PRODUCT 128 /* evaluate the Chebyshev filter in product form over its
+                                 * roots (Leja order; each step reads Y_k and writes
+                                 * Y_k+1) instead of the scaled three-term recurrence
+                                 * (each step reads Y_k and Y_k-1, writes Y_k+1): the
+                                 * same polynomial (Sec. II.B) with a third fewer bytes
+                                 * per step; its FP32 residual floor is about 2x the
+                                 * recurrence's */
 
 /* Grid: nx, ny, nz >= 1 points, spacing h (nm) > 0. */
 typedef struct {

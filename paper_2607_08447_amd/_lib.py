@@ -32,6 +32,7 @@ HKP_FLAG_NO_LOCK = 8
 HKP_FLAG_X0_NEV = 16
 HKP_FLAG_PSI_BLOCK = 32
 HKP_FLAG_SPIN_FREE = 64
+HKP_FLAG_CHEB_PRODUCT = 128
 HKP_SP_PHI0 = 1
 HKP_SP_EXACT_EIG = 2
 

@@ -117,7 +117,7 @@ def _npsi(g, o, nev, block):
 def solve(V, h, nev, strain=None, B=(0.0, 0.0, 0.0), nb=0, degree=0, tol=1e-8,
           precision="fp64", max_iter=200, seed=1, X0=None, graph=False, material=None,
           return_psi=True, workspace=None, polish=True, lock=True, psi_block=False,
-          spin_free=False):
+          spin_free=False, cheb_product=False):
     """Lowest `nev` eigenpairs of H for the potential V (float64 [nx, ny, nz], eV).
 
     spin_free=True solves the orbital problem H_0 without spin-orbit coupling
@@ -128,7 +128,10 @@ def solve(V, h, nev, strain=None, B=(0.0, 0.0, 0.0), nb=0, degree=0, tol=1e-8,
     [nev, nx, ny, nz, 6] -- a previous solve's psi -- completed with random
     vectors.  psi_block=True returns all nb final Ritz vectors as psi (the
     initial block of a later restart).  lock=False filters every vector of the
-    block in every iteration (no soft locking of converged Kramers pairs)."""
+    block in every iteration (no soft locking of converged Kramers pairs).
+    cheb_product=True evaluates the Chebyshev filter in product form over its
+    roots instead of the three-term recurrence (the same polynomial; two blocks
+    moved per step instead of three)."""
     V = _dev(V, torch.float64)
     shape = tuple(V.shape)
     if len(shape) != 3:
@@ -142,6 +145,8 @@ def solve(V, h, nev, strain=None, B=(0.0, 0.0, 0.0), nb=0, degree=0, tol=1e-8,
         flags |= L.HKP_FLAG_NO_FP64_POLISH
     if not lock:
         flags |= L.HKP_FLAG_NO_LOCK
+    if cheb_product:
+        flags |= L.HKP_FLAG_CHEB_PRODUCT
     o = _opts(nev, nb, degree, max_iter, tol, precision, flags, seed)
     need = L.lib.hkp_workspace_bytes(C.byref(g), C.byref(o), 1)
     if need == 0:
@@ -175,10 +180,10 @@ def solve(V, h, nev, strain=None, B=(0.0, 0.0, 0.0), nb=0, degree=0, tol=1e-8,
 def solve_batch(V, h, nev, strain=None, B=(0.0, 0.0, 0.0), nb=0, degree=0, tol=1e-8,
                 precision="fp64", max_iter=200, seed=1, graph=True, material=None,
                 return_psi=False, workspace=None, polish=True, lock=True, X0=None,
-                psi_block=False, spin_free=False):
+                psi_block=False, spin_free=False, cheb_product=False):
     """Lowest eigenpairs of `batch` Hamiltonians differing in V ([batch, nx, ny, nz]).
     X0 (optional, complex128): [batch, nb or nev, nx, ny, nz, 6]; X0 and
-    psi_block as in solve()."""
+    psi_block, cheb_product as in solve()."""
     V = _dev(V, torch.float64)
     if V.dim() != 4:
         raise ValueError("V must be [batch, nx, ny, nz]")
@@ -193,6 +198,8 @@ def solve_batch(V, h, nev, strain=None, B=(0.0, 0.0, 0.0), nb=0, degree=0, tol=1
         flags |= L.HKP_FLAG_NO_FP64_POLISH
     if not lock:
         flags |= L.HKP_FLAG_NO_LOCK
+    if cheb_product:
+        flags |= L.HKP_FLAG_CHEB_PRODUCT
     o = _opts(nev, nb, degree, max_iter, tol, precision, flags, seed)
     need = L.lib.hkp_workspace_bytes(C.byref(g), C.byref(o), batch)
     if need == 0:

@@ -551,6 +551,7 @@ struct RitzArgs {
   const double* theta;    // [batch][nb] Ritz values (ascending)
   const double* bounds;   // [batch][4]: upper spectral bound first
   const int* f32;         // [batch] FP32 output
+  const double* roots;    // product form's roots (null: recurrence)
   float* out32;           // FP32 Y1, strides of W
   double* partial;        // [batch][nb][gridDim.x] residual partial sums
   int nb;
@@ -639,7 +640,7 @@ rotate_kernel(const double* X, long long x_bstride, double* Y, long long y_bstri
     // same ones from the same Ritz values) and output precision; here
     // nout = nin, so every one of the MT output tiles exists
     double r_alpha, r_shift;
-    cheb_first_coef(ra.bounds[4 * b], ths[0], ths[ra.nb - 1], &r_alpha, &r_shift);
+    cheb_first_coef(ra.bounds[4 * b], ths[0], ths[ra.nb - 1], ra.roots, &r_alpha, &r_shift);
     const bool r_f32 = ra.f32 && ra.f32[b];
     double* wb = ra.W + 2 * ((long long)b * x_bstride);
     float* o32 = ra.out32 ? ra.out32 + 2 * ((long long)b * x_bstride) : nullptr;
@@ -983,12 +984,12 @@ hipError_t launch_rotate(const BlockDesc& X, const BlockDesc& Y, int nin, int no
 }
 
 hipError_t launch_ritz(const BlockDesc& X, const BlockDesc& W, int nb, const double* Q,
-                       const double* theta, const double* bounds, const int* f32,
-                       float* out32, int batch, double* partial, double* r2,
+                       const double* theta, const double* bounds, const double* roots,
+                       const int* f32, float* out32, int batch, double* partial, double* r2,
                        const int* active, hipStream_t s) {
   if (W.bstride != X.bstride || W.n != X.n || W.nvec < nb || X.nvec < nb)
     return hipErrorInvalidValue;
-  const RitzArgs ra{W.ptr, theta, bounds, f32, out32, partial, nb};
+  const RitzArgs ra{W.ptr, theta, bounds, f32, roots, out32, partial, nb};
   hipError_t e = rotate_any<true>(X, X, nb, nb, Q, batch, active, ra, s);
   if (e != hipSuccess) return e;
   sum_rows_kernel<<<dim3((unsigned)nb, (unsigned)batch), 256, 0, s>>>(

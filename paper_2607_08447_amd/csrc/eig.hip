@@ -340,6 +340,17 @@ __global__ void control_kernel(Control c, int nb, int nev, int degree, int kmax,
   bd[1] = acut;
   bd[2] = a0;
   double* co = c.coef + (long long)b * kmax * 4;
+  if (c.roots) {
+    // product form: step k is (H - r_k) / (a0 - r_k), r_k the k-th root (Leja
+    // order) mapped onto [a_cut, b_up]; degree = the next filter's m
+    for (int k = 0; k < degree && k < kmax; ++k) {
+      const double r = cc + e * c.roots[k];
+      co[4 * k] = 1.0 / (a0 - r);
+      co[4 * k + 1] = r;
+      co[4 * k + 2] = 0.0;
+    }
+    return;
+  }
   double sig = sigma1;
   co[0] = sigma1 / e;
   co[1] = cc;
@@ -374,28 +385,6 @@ __global__ void worktable_kernel(Control c, int batch, int nb) {
   t32[batch] = s32;
   t64[batch] = s64;
   tall[batch] = sall;
-}
-
-// first filter coefficients from the bounds alone (before any Rayleigh-Ritz)
-__global__ void init_coef_kernel(Control c, int degree, int kmax) {
-  const int b = blockIdx.x;
-  if (threadIdx.x != 0) return;
-  double* bd = c.bounds + 4 * b;
-  const double bup = bd[0], acut = bd[1], a0 = bd[2];
-  const double e = 0.5 * (bup - acut), cc = 0.5 * (bup + acut);
-  const double sigma1 = e / (a0 - cc);
-  double* co = c.coef + (long long)b * kmax * 4;
-  double sig = sigma1;
-  co[0] = sigma1 / e;
-  co[1] = cc;
-  co[2] = 0.0;
-  for (int k = 1; k < degree && k < kmax; ++k) {
-    const double sn = 1.0 / (2.0 / sigma1 - sig);
-    co[4 * k] = 2.0 * sn / e;
-    co[4 * k + 1] = cc;
-    co[4 * k + 2] = -sig * sn;
-    sig = sn;
-  }
 }
 
 // eig[b][j] = theta[b][j], resid[b][j] = sqrt(r2[b][j]) for j < nev
@@ -488,6 +477,10 @@ small_gemm_kernel(const double* A, int adj, const double* B, double* C, int nb,
   }
 }
 
+__global__ void set_roots_kernel(double* dst, RootTable t, int m) {
+  for (int k = threadIdx.x; k < m; k += blockDim.x) dst[k] = t.x[k];
+}
+
 __global__ void set_identity_kernel(double* C, int nb, long long mat_stride, const int* active) {
   const int b = blockIdx.x;
   if (active && !active[b]) return;
@@ -503,6 +496,12 @@ hipError_t launch_small_gemm(const double* A, int adj, const double* B, double* 
                              hipStream_t s) {
   if (nb > HKP_NB_MAX || nb < 1 || C == A || C == B) return hipErrorInvalidValue;
   small_gemm_kernel<<<batch, kGemmThreads, 0, s>>>(A, adj, B, C, nb, mat_stride, herm, active);
+  return hipGetLastError();
+}
+
+hipError_t launch_set_roots(double* dst, const RootTable& t, int m, hipStream_t s) {
+  if (m < 1 || m > kMaxDegree) return hipErrorInvalidValue;
+  set_roots_kernel<<<1, 256, 0, s>>>(dst, t, m);
   return hipGetLastError();
 }
 
@@ -532,11 +531,6 @@ hipError_t launch_control(const Control& c, int batch, int nb, int nev, int degr
 
 hipError_t launch_worktable(const Control& c, int batch, int nb, hipStream_t s) {
   worktable_kernel<<<1, 64, 0, s>>>(c, batch, nb);
-  return hipGetLastError();
-}
-
-hipError_t launch_init_coef(const Control& c, int batch, int degree, int kmax, hipStream_t s) {
-  init_coef_kernel<<<batch, 64, 0, s>>>(c, degree, kmax);
   return hipGetLastError();
 }
 

@@ -180,12 +180,13 @@ hipError_t launch_rotate(const BlockDesc& X, const BlockDesc& Y, int nin, int no
 int rotate_blocks(long long n, int batch);
 // Rayleigh-Ritz rotation with Ritz vectors Q of X^H W (W = H X): X <- X Q in
 // place, r2[b][j] = || (W Q)_j - theta_j (X Q)_j ||^2 and the first filter step
-// Y1 = alpha (W Q - shift X Q) (coefficients from theta and the upper bound),
+// Y1 = alpha (W Q - shift X Q) (coefficients from theta, the upper bound and,
+// for the product form, its first root),
 // FP32 into out32 where f32[b], else FP64 in place into W; W Q is not stored.
 // partial holds batch x nb x rotate_blocks(n, batch) doubles
 hipError_t launch_ritz(const BlockDesc& X, const BlockDesc& W, int nb, const double* Q,
-                       const double* theta, const double* bounds, const int* f32,
-                       float* out32, int batch, double* partial, double* r2,
+                       const double* theta, const double* bounds, const double* roots,
+                       const int* f32, float* out32, int batch, double* partial, double* r2,
                        const int* active, hipStream_t s);
 hipError_t launch_cast(const void* in, int in_fp64, void* out, int out_fp64, long long count,
                        hipStream_t s);
@@ -210,6 +211,12 @@ hipError_t launch_scale(double* v, long long n, int batch, long long bstride,
 // conditioned that a second pass is needed (and the member is active)
 // C = op(A) B per member (op: A if adj = 0, A^H if adj = 1), nb x nb complex
 // row-major; herm: store the Hermitian part; C must not alias A or B
+// the product form's roots (Leja order, on [-1, 1]) into the device table
+constexpr int kMaxDegree = 200;
+struct RootTable {
+  double x[kMaxDegree];
+};
+hipError_t launch_set_roots(double* dst, const RootTable& t, int m, hipStream_t s);
 hipError_t launch_small_gemm(const double* A, int adj, const double* B, double* C, int nb,
                              int batch, long long mat_stride, int herm, const int* active,
                              hipStream_t s);
@@ -230,12 +237,22 @@ __device__ __forceinline__ void cheb_interval(double bup, double a0, double& acu
   *c = 0.5 * (bup + acut);
   *sigma1 = *e / (a0 - *c);
 }
+// first step Y1 = alpha (H - shift) X: of the recurrence, or (roots != null) the
+// first factor of the product form, (H - r_0) / (a0 - r_0) with r_0 the first
+// root mapped onto [a_cut, b_up]
 __device__ __forceinline__ void cheb_first_coef(double bup, double a0, double acut,
-                                                double* alpha, double* shift) {
+                                                const double* roots, double* alpha,
+                                                double* shift) {
   double e, c, s1;
   cheb_interval(bup, a0, acut, &e, &c, &s1);
-  *alpha = s1 / e;
-  *shift = c;
+  if (roots) {
+    const double r = c + e * roots[0];
+    *alpha = 1.0 / (a0 - r);
+    *shift = r;
+  } else {
+    *alpha = s1 / e;
+    *shift = c;
+  }
 }
 
 // control: convergence flags, next Chebyshev coefficients
@@ -251,6 +268,8 @@ struct Control {
   int* lock;         // [batch] leading vectors left out of the filter (converged pairs)
   int* sw;           // [batch] next filter FP64 but its first step was written in FP32
                      // (the member left the FP32 filter at this control step)
+  const double* roots;   // product form: the next filter's m Chebyshev roots on [-1, 1]
+                         // in Leja order (null: three-term recurrence)
   int* work;         // [3][batch + 1] prefix sums of vectors to process per member:
                      // FP32 filter, FP64 filter (both after the lock), whole block
 };
@@ -263,8 +282,6 @@ hipError_t launch_finish(const double* theta, const double* r2, int nb, int nev,
                          double* eig, double* resid, hipStream_t s);
 hipError_t launch_check_finite(const double* x, long long count, int* flag, hipStream_t s);
 hipError_t launch_fill_int(int* p, int count, int value, hipStream_t s);
-hipError_t launch_init_coef(const Control& c, int batch, int degree, int kmax,
-                            hipStream_t s);
 
 // ---------------------------------------------------------------------------
 // spin-free basis (orbital vectors [v][x][y][z][3] complex) and spin-orbit matrix

@@ -54,7 +54,7 @@ struct Layout {
       theta, lam,
       r2, rpart, coef, bounds, flags, active, act32, act64, lock, sw, work, again, status, lal,
       lnrm,
-      lpart, zero, total;
+      lpart, zero, roots, total;
 };
 
 Layout make_layout(const Plan& p) {
@@ -107,6 +107,7 @@ Layout make_layout(const Plan& p) {
   L.lnrm = take((size_t)(kLanczosSteps + 1) * B * 16);
   L.lpart = take(B * kDotParts * 16);
   L.zero = take(256);   // zeros (the hard wall's values for the two-step copies)
+  L.roots = take(kKmax * 8);   // the product form's roots on [-1, 1], Leja order
   L.total = off;
   return L;
 }
@@ -272,7 +273,8 @@ struct Ctx {
     return Control{at<double>(L.theta), at<double>(L.r2),     at<double>(L.coef),
                    at<double>(L.bounds), at<int>(L.flags),    at<int>(L.active),
                    at<int>(L.act32),     at<int>(L.act64),    at<int>(L.lock),
-                   at<int>(L.sw),        at<int>(L.work)};
+                   at<int>(L.sw),        p.product ? at<double>(L.roots) : nullptr,
+                   at<int>(L.work)};
   }
 };
 
@@ -317,6 +319,33 @@ void apply_block(const Ctx& c, size_t x_off, size_t w_off, const int* active) {
   c.ss->launch(a, c.consts, c.s, c.p.N, c.active_members);
 }
 
+// The roots of the degree-m Chebyshev polynomial on [-1, 1], cos((2i - 1) pi / 2m),
+// in Leja order: the largest first, then each maximising the product of its
+// distances to those before it (log sums; ties to the lower index).  Applied in
+// this order the scaled factors (H - r) / (a0 - r) keep every partial product
+// small on the damped interval, so the product form runs in FP32 as the
+// recurrence does.  The order is invariant under the affine map onto [a_cut, b].
+RootTable leja_cheb_roots(int m) {
+  RootTable t{};
+  std::vector<double> x(m), logp(m, 0.0);
+  std::vector<char> used(m, 0);
+  for (int i = 0; i < m; ++i) x[i] = std::cos((2.0 * i + 1.0) * M_PI / (2.0 * m));
+  for (int k = 0; k < m; ++k) {
+    int best = -1;
+    for (int i = 0; i < m; ++i) {
+      if (used[i]) continue;
+      const double score = k == 0 ? std::fabs(x[i]) : logp[i];
+      const double bs = best < 0 ? 0.0 : (k == 0 ? std::fabs(x[best]) : logp[best]);
+      if (best < 0 || score > bs) best = i;
+    }
+    used[best] = 1;
+    t.x[k] = x[best];
+    for (int i = 0; i < m; ++i)
+      if (!used[i]) logp[i] += std::log(std::fabs(x[i] - x[best]));
+  }
+  return t;
+}
+
 // Chebyshev filter of degree m (even) in FP64: the filtered block ends in X.
 // The first step Y1 = alpha (H - c) X is already in W (written by the
 // Rayleigh-Ritz step), except for members that have just left the FP32 filter
@@ -341,7 +370,7 @@ void filter64(const Ctx& c, const int* active, int m) {
     StencilLaunch a = base_launch(c, true, c.p.nb);
     a.in = c.at<double>(cur);
     a.in_bstride = c.bstride();
-    a.old = c.at<double>(oth);
+    a.old = c.p.product ? nullptr : c.at<double>(oth);
     a.old_fp64 = 1;
     a.old_bstride = c.bstride();
     a.out = c.at<double>(oth);
@@ -391,6 +420,29 @@ void filter32(const Ctx& c, const int* active, int m) {
     t2.tile_y = c.p.st.t2y;
     t2.vgroup = c.p.st.vgroup;
     two = stencil2_supported(t2);
+  }
+  if (c.p.product) {
+    // product form: step k maps Y_k to Y_{k+1} (FP32 buffers in turn), the last
+    // step writes FP64 into X
+    float* buf[2] = {A, Bf};
+    int cur = 0;
+    for (int k = 1; k < m; ++k) {
+      const bool last = k == m - 1;
+      StencilLaunch a = base_launch(c, false, c.p.nb);
+      a.in = buf[cur];
+      a.in_bstride = c.bstride();
+      a.out = last ? (void*)c.at<double>(c.L.X) : (void*)buf[1 - cur];
+      a.out_fp64 = last ? 1 : 0;
+      a.out_bstride = c.bstride();
+      a.coef.coef = c.at<double>(c.L.coef) + 4 * k;
+      a.coef.stride = kstride;
+      a.active = active;
+      a.lock = c.at<int>(c.L.lock);
+      a.work = c.work(0);
+      c.ss->launch(a, c.consts, c.s, c.p.N, c.active_members, c.filtered_vectors);
+      cur = 1 - cur;
+    }
+    return;
   }
   float* spare[2] = {two ? c.at<float>(c.L.C32) : nullptr, two ? c.at<float>(c.L.E32) : nullptr};
   // step k: in = Y_k (FP32), old = Y_{k-1} (X in FP64 for k = 1), out = Y_{k+1}
@@ -492,7 +544,8 @@ void rayleigh_ritz(const Ctx& c, const int* active) {
                         active, c.s));
   HKP_CHECK(launch_small_gemm(S, 0, tmp, Q, c.p.nb, c.p.batch, ms, 0, active, c.s));
   HKP_CHECK(launch_ritz(X, W, c.p.nb, c.at<double>(c.L.mat2), c.at<double>(c.L.theta),
-                        c.at<double>(c.L.bounds), c.at<int>(c.L.act32),
+                        c.at<double>(c.L.bounds),
+                        c.p.product ? c.at<double>(c.L.roots) : nullptr, c.at<int>(c.L.act32),
                         c.p.mixed ? c.at<float>(c.L.A32) : nullptr, c.p.batch,
                         c.at<double>(c.L.rpart), c.at<double>(c.L.r2), active, c.s));
 }
@@ -607,7 +660,9 @@ Plan make_plan(const hkp_grid& g, const hkp_opts& o, int batch) {
   if (m > kKmax) m = kKmax;
   p.degree = m;
   p.mixed = o.precision == HKP_PREC_MIXED;
-  p.two_step = p.mixed && two_step_grid(p.nx, p.ncomp) && two_step_tuned(g, p.nb);
+  p.product = (o.flags & HKP_FLAG_CHEB_PRODUCT) != 0;
+  // the two-step pass carries the recurrence's old block
+  p.two_step = p.mixed && !p.product && two_step_grid(p.nx, p.ncomp) && two_step_tuned(g, p.nb);
   return p;
 }
 
@@ -727,9 +782,18 @@ int run_solve(const SolveArgs& A, hkp_stats* stats) {
                                   A.seed, c.s));
   }
   const int* act = c.at<int>(c.L.active);
+  // the product form's roots for the next filter's degree (set when it changes)
+  int roots_m = 0;
+  auto prepare = [&](int m_next) {
+    if (!p.product || m_next == roots_m) return;
+    HKP_CHECK(launch_set_roots(c.at<double>(c.L.roots), leja_cheb_roots(m_next), m_next, c.s));
+    roots_m = m_next;
+  };
+  const int m_first = p.degree_fixed ? p.degree : std::min(16, p.degree);
+  prepare(m_first);
   orthonormalise(c, act);
   rayleigh_ritz(c, act);
-  HKP_CHECK(launch_control(c.control(), p.batch, p.nb, p.nev, kKmax, kKmax, A.tol, p.mixed,
+  HKP_CHECK(launch_control(c.control(), p.batch, p.nb, p.nev, m_first, kKmax, A.tol, p.mixed,
                            !(A.flags & HKP_FLAG_NO_FP64_POLISH), !(A.flags & HKP_FLAG_NO_LOCK), 0,
                            c.s));
   t_setup.stop(c.s);
@@ -784,7 +848,7 @@ int run_solve(const SolveArgs& A, hkp_stats* stats) {
     }
   };
 
-  auto iteration = [&](int it, bool single_path_known, bool f32_only) {
+  auto iteration = [&](int it, bool single_path_known, bool f32_only, int m_next) {
     t_filter.start(c.s);
     if (!single_path_known) {
       if (p.mixed) filter32(c, c.at<int>(c.L.act32), m_cur);
@@ -799,6 +863,7 @@ int run_solve(const SolveArgs& A, hkp_stats* stats) {
     orthonormalise(c, act);
     t_orth.stop(c.s);
     t_rr.start(c.s);
+    prepare(m_next);
     rayleigh_ritz(c, act);
     t_rr.stop(c.s);
     t_res.start(c.s);
@@ -806,7 +871,7 @@ int run_solve(const SolveArgs& A, hkp_stats* stats) {
     // (during the ramp a slow decrease is the low degree's); graph replays
     // (it < 0) come after it
     const bool past_ramp = it < 0 || it > 2 || m_cur >= p.degree;
-    HKP_CHECK(launch_control(c.control(), p.batch, p.nb, p.nev, kKmax, kKmax, A.tol,
+    HKP_CHECK(launch_control(c.control(), p.batch, p.nb, p.nev, m_next, kKmax, A.tol,
                              p.mixed,
                              !(A.flags & HKP_FLAG_NO_FP64_POLISH) && past_ramp,
                              !(A.flags & HKP_FLAG_NO_LOCK), it, c.s));
@@ -822,9 +887,9 @@ int run_solve(const SolveArgs& A, hkp_stats* stats) {
       count_work();
       if (p.batch == 1) {
         const bool f32 = p.mixed && !hflags[1];
-        iteration(iters, true, f32);
+        iteration(iters, true, f32, degree_at(iters + 1));
       } else {
-        iteration(iters, false, false);
+        iteration(iters, false, false, degree_at(iters + 1));
       }
       read_flags();
       if (trace) {
@@ -867,7 +932,7 @@ int run_solve(const SolveArgs& A, hkp_stats* stats) {
     c.filtered_vectors = -1;
     HKP_CHECK(hipStreamBeginCapture(c.s, hipStreamCaptureModeThreadLocal));
     try {
-      for (int k = 0; k < chunk; ++k) iteration(-1, false, false);
+      for (int k = 0; k < chunk; ++k) iteration(-1, false, false, p.degree);
     } catch (...) {
       hipGraph_t g2 = nullptr;
       (void)hipStreamEndCapture(c.s, &g2);

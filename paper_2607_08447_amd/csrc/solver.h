@@ -38,6 +38,7 @@ struct Plan {
   bool degree_fixed;
   bool mixed;
   bool two_step;   // FP32 filter in two-step passes (the workspace holds their outputs)
+  bool product;    // filter in product form over the polynomial's roots (else recurrence)
   StencilTune st;
 };
 

@@ -101,8 +101,9 @@ def test_two_step_tiles(tx, ty, monkeypatch):
 @pytest.mark.parametrize("tile", ["16,8", "16,12"])
 def test_mixed_solve_with_two_step_passes(tile, monkeypatch):
     """A mixed-precision solve whose FP32 filter runs in two-step passes (forced
-    tile) gives the oracle's eigenvalues within 1 ueV (dense LAPACK on the
-    assembled H), and the passes were used."""
+    tile; the passes carry the three-term recurrence, the default) gives the oracle's
+    eigenvalues within 1 ueV (dense LAPACK on the assembled H), and the passes
+    were used."""
     import torch
     import paper_2607_08447_amd as hkp
     monkeypatch.setenv("HKP_STENCIL2", tile)

@@ -59,23 +59,27 @@ def test_harmonic_fp64_vs_dense():
         assert np.abs(dg - do).max() < 1e-9 * max(1.0, do.max() * 1e6)
 
 
+@pytest.mark.parametrize("product", [False, True], ids=["recurrence", "product"])
 @pytest.mark.parametrize("name", ["fin_small", "dqd_small"])
-def test_fin_dqd_small_fp64_vs_arpack(name):
+def test_fin_dqd_small_fp64_vs_arpack(name, product):
+    """Both evaluations of the Chebyshev filter: the three-term recurrence
+    (default) and the product form over its roots."""
     w = workload(name)
     nev = 12
     H = hamiltonian_ls(Grid(*w.shape, w.h), SI_MATERIAL, w.V, w.strain.reshape(-1, 6), w.B)
     E_ref, _ = lowest_arpack(H, nev, tol=1e-13)
-    res = _gpu_solve(w, nev=nev, nb=24, tol=1e-9)
+    res = _gpu_solve(w, nev=nev, nb=24, tol=1e-9, cheb_product=product)
     assert res.status == 0
     _check_pairs(w, res, E_ref, 1e-8, 1e-8)
 
 
-def test_mixed_precision_within_1ueV():
+@pytest.mark.parametrize("product", [False, True], ids=["recurrence", "product"])
+def test_mixed_precision_within_1ueV(product):
     w = workload("fin_small")
     nev = 12
     H = hamiltonian_ls(Grid(*w.shape, w.h), SI_MATERIAL, w.V, w.strain.reshape(-1, 6), w.B)
     E_ref, _ = lowest_arpack(H, nev, tol=1e-13)
-    res = _gpu_solve(w, nev=nev, nb=24, tol=1e-6, precision="mixed")
+    res = _gpu_solve(w, nev=nev, nb=24, tol=1e-6, precision="mixed", cheb_product=product)
     assert res.status == 0
     E = res.E.cpu().numpy()
     assert np.abs(E - E_ref).max() <= 1e-6
