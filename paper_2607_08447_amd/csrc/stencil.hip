@@ -27,6 +27,7 @@
 // contiguous runs so that the vectors of one tile share an L2.
 #include <map>
 #include <mutex>
+#include <type_traits>
 
 #include "hkp_internal.h"
 #include "stencil_ops.h"
@@ -70,8 +71,10 @@ struct KArgs {
 // NC = 6: the full spinor (a wave per spin and row).  NC = 3: a spin-free orbital
 // vector (X, Y, Z of one spin; no spin-orbit or field terms, so nothing couples
 // it to the other spin): one wave per row and half the bytes.
+// (FP32 steps without an old block are held to 128 VGPRs: four waves per SIMD)
 template <typename T, typename TO, typename TW, int PH, bool STR, int TY, bool DMA, int NC = 6>
-__global__ void __launch_bounds__(64 * TY * (NC / 3))
+__global__ void __launch_bounds__(64 * TY * (NC / 3),
+                                  (sizeof(T) == 4 && std::is_same<TO, void>::value && TY == 2) ? 4 : 1)
 stencil_kernel(KArgs<T> a) {
   static_assert(NC == 6 || (NC == 3 && PH == 0), "spin-free vectors carry no field terms");
   // LDS row: [pad] left halo, 64 interior, right halo [pad]; with FP32 DMA the
@@ -168,12 +171,16 @@ stencil_kernel(KArgs<T> a) {
     shift = (T)a.shift;
     beta = (T)a.beta;
   }
-  const bool has_old = a.old != nullptr && beta != (T)0;
+  // TO = void: a launch without an old block (a step of the product-form filter,
+  // or H X), compiled without its loads
+  constexpr bool kOld = !std::is_same<TO, void>::value;
+  using TOv = std::conditional_t<kOld, TO, T>;
+  const bool has_old = kOld && a.old != nullptr && beta != (T)0;
 
   // uniform (scalar) bases; lane offsets are 32-bit element indices
   const T* __restrict__ in = a.in + 2 * ((long long)b * a.in_bstride + (long long)vec * NC * N);
-  const TO* __restrict__ oldp = has_old
-      ? reinterpret_cast<const TO*>(a.old) +
+  const TOv* __restrict__ oldp = has_old
+      ? reinterpret_cast<const TOv*>(a.old) +
             2 * ((long long)b * a.old_bstride + (long long)vec * NC * N + (long long)X * N)
       : nullptr;
   TW* __restrict__ outp = reinterpret_cast<TW*>(a.out) +
@@ -273,11 +280,11 @@ stencil_kernel(KArgs<T> a) {
   };
 
   auto load_old = [&](int z) {
-    if (!has_old || !mine) return;
+    if (!kOld || !has_old || !mine) return;
     const unsigned o = (unsigned)z * nxy + col;
 #pragma unroll
     for (int i = 0; i < 3; ++i) {
-      cx<TO> q = ld_stream(oldp + 2 * (size_t)((unsigned)i * N + o));
+      cx<TOv> q = ld_stream(oldp + 2 * (size_t)((unsigned)i * N + o));
       oldv[i] = mk<T>((T)q.r, (T)q.i);
     }
   };
@@ -287,7 +294,7 @@ stencil_kernel(KArgs<T> a) {
 #pragma unroll
     for (int i = 0; i < 3; ++i) {
       cx<T> r = scl(alpha, acc0[i]);
-      if (has_old) r = fma_s(r, beta, oldv[i]);
+      if (kOld && has_old) r = fma_s(r, beta, oldv[i]);
       stg_stream<TW>(outp, (long long)((unsigned)i * N + o), r);
     }
   };
@@ -577,8 +584,12 @@ hipError_t launch_stencil(const StencilLaunch& L, const StencilConsts<double>& c
                           hipStream_t s) {
   if (L.fp64) {
     if (!L.out_fp64) return hipErrorInvalidValue;
-    return launch_ph<double, double, double>(L, c, s);
+    return L.old ? launch_ph<double, double, double>(L, c, s)
+                 : launch_ph<double, void, double>(L, c, s);
   }
+  if (!L.old)   // no old block: H X, or a step of the product-form filter
+    return L.out_fp64 ? launch_ph<float, void, double>(L, c, s)
+                      : launch_ph<float, void, float>(L, c, s);
   // FP32 stencil: old may be FP64 (the first recurrence step reads X) and the
   // output FP64 (the last step feeds the FP64 orthonormalisation)
   if (L.old_fp64) {
