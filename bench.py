@@ -106,6 +106,8 @@ def traffic_from(fetch_csv, write_csv, stencil, nb, precision="fp32", bench_log=
     the benchmark reads, with the algorithmic bytes per launch the profiled
     benchmark run printed (bench_log, its stdout); FP64 ones are printed only."""
     import csv
+    # the recurrence's steps (the benchmark's headline filter); launches without
+    # an old block (product-form steps, H X) are the `void` variants
     tag = "stencil_kernel<float" if precision == "fp32" else "stencil_kernel<double"
 
     def per_kernel(path, counter):
@@ -118,7 +120,7 @@ def traffic_from(fetch_csv, write_csv, stencil, nb, precision="fp32", bench_log=
                 name = r["Kernel_Name"]
                 if "copyBuffer" in name and not copy:
                     copy.append(v)
-                elif tag in name:
+                elif tag in name and (tag + ", void") not in name:
                     sten.append(v)
         if not copy or not sten:
             raise SystemExit(f"{path}: no copy calibration or no {precision} stencil dispatches")

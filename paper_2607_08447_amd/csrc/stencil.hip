@@ -74,7 +74,7 @@ struct KArgs {
 // (FP32 steps without an old block are held to 128 VGPRs: four waves per SIMD)
 template <typename T, typename TO, typename TW, int PH, bool STR, int TY, bool DMA, int NC = 6>
 __global__ void __launch_bounds__(64 * TY * (NC / 3),
-                                  (sizeof(T) == 4 && std::is_same<TO, void>::value && TY == 2) ? 4 : 1)
+                                  (sizeof(T) == 4 && std::is_same<TO, void>::value && TY >= 2) ? 4 : 1)
 stencil_kernel(KArgs<T> a) {
   static_assert(NC == 6 || (NC == 3 && PH == 0), "spin-free vectors carry no field terms");
   // LDS row: [pad] left halo, 64 interior, right halo [pad]; with FP32 DMA the
