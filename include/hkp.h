@@ -387,6 +387,28 @@ int hkp_autotune_block(const hkp_grid* grid, const hkp_material* mat, const hkp_
                        size_t ws_bytes, void* hip_stream, int32_t* nb_out,
                        double* seconds_out);
 
+/* The launch shape a solve or filter step on this grid and block size would
+ * use (the autotuned one for this variant, else one tuned for another variant
+ * of the same shape, nb and precision, else the default), without timing
+ * anything; host only.  with_strain, with_field as in hkp_autotune; the us and
+ * gbps fields of out are 0.  Returns HKP_OK or HKP_E_ARG. */
+int hkp_tuned_shape(const hkp_grid* grid, int32_t nb, int32_t precision, int32_t with_strain,
+                    int32_t with_field, hkp_tune* out);
+
+/* The autotuners' choices across processes: hkp_tune_cache_save writes every
+ * cached launch shape (hkp_autotune) and block size (hkp_autotune_block) to a
+ * text file, keyed by grid, block size or nev, precision and stencil variant,
+ * under the current device's architecture name; hkp_tune_cache_load reads such
+ * a file and takes the entries written for the current device's architecture
+ * (others are skipped: a choice timed on one device is not carried to
+ * another).  Host only; the caller owns the path.  Both return the number of
+ * entries written or taken (>= 0), or HKP_E_ARG (NULL path, file not
+ * readable/writable, malformed line: nothing is taken from a malformed file).
+ * hkp_tune_cache_clear empties both caches of this process. */
+int hkp_tune_cache_save(const char* path);
+int hkp_tune_cache_load(const char* path);
+void hkp_tune_cache_clear(void);
+
 /* Workspace of hkp_soi_matrix for M orbitals on `grid`. */
 size_t hkp_soi_workspace_bytes(const hkp_grid* grid, int32_t M);
 

@@ -14,7 +14,7 @@ from .api import (  # noqa: F401
     filter_step2, gate_potential,
     hf_grad, solve, solve_batch, solve_sweep, workspace_bytes, poisson, occupancy, hole_density,
     sp_solve, SPResult, soi_matrix, ci_solve, CIResult, g_matrices, GMatrixResult, two_spin_model,
-    poisson_preconditioner,
+    poisson_preconditioner, tuned_shape, tune_cache_save, tune_cache_load, tune_cache_clear,
 )
 
 __version__ = "1.0.0"

@@ -163,6 +163,11 @@ SIGNATURES = {
     "hkp_autotune_block": (C.c_int, [C.POINTER(hkp_grid), C.POINTER(hkp_material),
                                      C.POINTER(hkp_opts), _P, _P, _D, C.POINTER(C.c_int32),
                                      C.c_int32, _P, C.c_size_t, _P, C.POINTER(C.c_int32), _D]),
+    "hkp_tuned_shape": (C.c_int, [C.POINTER(hkp_grid), C.c_int32, C.c_int32, C.c_int32,
+                                  C.c_int32, C.POINTER(hkp_tune)]),
+    "hkp_tune_cache_save": (C.c_int, [C.c_char_p]),
+    "hkp_tune_cache_load": (C.c_int, [C.c_char_p]),
+    "hkp_tune_cache_clear": (None, []),
     "hkp_soi_workspace_bytes": (C.c_size_t, [C.POINTER(hkp_grid), C.c_int32]),
     "hkp_soi_matrix": (C.c_int, [C.POINTER(hkp_grid), C.c_int32, _P, _P, C.c_double, _P, _P,
                                  C.c_size_t, _P]),

@@ -7,6 +7,7 @@ the |J m_j> basis and the symmetric gauge.
 """
 
 import ctypes as C
+import os
 from dataclasses import dataclass
 
 import torch
@@ -652,6 +653,38 @@ def autotune(shape, h, nb, precision="fp64", with_strain=True, with_field=True):
     return dict(tile_y=t.tile_y, vgroup=t.vgroup, dma=t.dma, us_per_step=t.us_per_step,
                 gbps=t.gbps, two_step=(t.two_step_tx, t.two_step_ty),
                 us_per_step_two=t.us_per_step_two)
+
+
+def tuned_shape(shape, h, nb, precision="fp64", with_strain=True, with_field=True):
+    """The launch shape a solve on this grid and block size would use (tuned,
+    cached or default), without timing anything."""
+    g = _grid(shape, h)
+    prec = L.HKP_PREC_MIXED if precision in ("mixed", 1) else L.HKP_PREC_FP64
+    t = L.hkp_tune()
+    L.check(L.lib.hkp_tuned_shape(C.byref(g), nb, prec, int(with_strain), int(with_field),
+                                  C.byref(t)))
+    return dict(tile_y=t.tile_y, vgroup=t.vgroup, dma=t.dma,
+                two_step=(t.two_step_tx, t.two_step_ty))
+
+
+def tune_cache_save(path):
+    """Write the autotuners' cached choices (launch shapes, block sizes) to `path`
+    under this device's architecture; returns the number of entries."""
+    rc = L.lib.hkp_tune_cache_save(os.fsencode(path))
+    L.check(rc)
+    return rc
+
+
+def tune_cache_load(path):
+    """Take the entries of a cache file written for this device's architecture;
+    returns the number taken (0 for another architecture's file)."""
+    rc = L.lib.hkp_tune_cache_load(os.fsencode(path))
+    L.check(rc)
+    return rc
+
+
+def tune_cache_clear():
+    L.lib.hkp_tune_cache_clear()
 
 
 def autotune_block(V, h, nev, strain=None, B=(0.0, 0.0, 0.0), candidates=None, tol=1e-8,

@@ -514,6 +514,36 @@ int hkp_autotune(const hkp_grid* grid, int32_t nb, int32_t precision, int32_t wi
   });
 }
 
+int hkp_tuned_shape(const hkp_grid* grid, int32_t nb, int32_t precision, int32_t with_strain,
+                    int32_t with_field, hkp_tune* out) {
+  HKP_TRY(check_grid(grid));
+  if (nb < 1 || nb > HKP_NB_MAX || !out || with_field < 0 || with_field > 2 ||
+      (precision != HKP_PREC_FP64 && precision != HKP_PREC_MIXED)) {
+    set_error("hkp_tuned_shape: invalid arguments");
+    return HKP_E_ARG;
+  }
+  const double B[3] = {with_field ? 0.5 : 0.0, 0.0, with_field == 2 ? 0.5 : 0.0};
+  const StencilTune t = autotuned(*grid, nb, precision == HKP_PREC_MIXED,
+                                  stencil_variant(with_strain != 0, B));
+  std::memset(out, 0, sizeof(*out));
+  out->tile_y = t.tile_y;
+  out->vgroup = t.vgroup;
+  out->dma = t.dma;
+  out->two_step_tx = t.t2x;
+  out->two_step_ty = t.t2y;
+  return HKP_OK;
+}
+
+int hkp_tune_cache_save(const char* path) {
+  return guarded([&]() { return tune_cache_save(path); });
+}
+
+int hkp_tune_cache_load(const char* path) {
+  return guarded([&]() { return tune_cache_load(path); });
+}
+
+void hkp_tune_cache_clear(void) { tune_cache_clear(); }
+
 int hkp_autotune_block(const hkp_grid* grid, const hkp_material* mat, const hkp_opts* opts,
                        const double* V_eV, const double* strain, const double B_T[3],
                        const int32_t* candidates, int32_t ncand, void* workspace,

@@ -8,8 +8,12 @@
 #include <chrono>
 #include <cstdio>
 #include <cstdlib>
+#include <cstring>
+#include <fstream>
 #include <map>
 #include <mutex>
+#include <sstream>
+#include <string>
 #include <tuple>
 #include <vector>
 
@@ -133,6 +137,135 @@ StencilTune autotuned(const hkp_grid& g, int nb, bool mixed, int variant) {
   StencilTune t = autotuned_shape(g, nb, mixed, variant);
   forced2(&t);
   return t;
+}
+
+// ---- the caches in a file, keyed by the device architecture
+namespace {
+std::string current_arch() {
+  int n = 0, dev = 0;
+  if (hipGetDeviceCount(&n) != hipSuccess || n < 1 || hipGetDevice(&dev) != hipSuccess) {
+    (void)hipGetLastError();
+    return "none";
+  }
+  hipDeviceProp_t p;
+  if (hipGetDeviceProperties(&p, dev) != hipSuccess) {
+    (void)hipGetLastError();
+    return "none";
+  }
+  std::string a = p.gcnArchName;
+  return a.empty() ? "none" : a;
+}
+}  // namespace
+
+int tune_cache_save(const char* path) {
+  if (!path) {
+    set_error("hkp_tune_cache_save: NULL path");
+    return HKP_E_ARG;
+  }
+  std::ostringstream o;
+  o << "# hkp autotune cache 1\n";
+  o << "arch " << current_arch() << "\n";
+  int n = 0;
+  {
+    std::lock_guard<std::mutex> lk(g_mu);
+    for (const auto& kv : g_cache) {
+      const auto& k = kv.first;
+      const StencilTune& t = kv.second;
+      o << "stencil " << std::get<0>(k) << ' ' << std::get<1>(k) << ' ' << std::get<2>(k) << ' '
+        << std::get<3>(k) << ' ' << std::get<4>(k) << ' ' << std::get<5>(k) << ' ' << t.tile_y
+        << ' ' << t.vgroup << ' ' << t.dma << ' ' << t.zsplit << ' ' << t.t2x << ' ' << t.t2y
+        << "\n";
+      ++n;
+    }
+    for (const auto& kv : g_nb_cache) {
+      const auto& k = kv.first;
+      o << "block " << std::get<0>(k) << ' ' << std::get<1>(k) << ' ' << std::get<2>(k) << ' '
+        << std::get<3>(k) << ' ' << std::get<4>(k) << ' ' << kv.second << "\n";
+      ++n;
+    }
+  }
+  std::ofstream f(path, std::ios::trunc);
+  if (!f || !(f << o.str()) || !f.flush()) {
+    set_error(std::string("hkp_tune_cache_save: cannot write ") + path);
+    return HKP_E_ARG;
+  }
+  return n;
+}
+
+int tune_cache_load(const char* path) {
+  if (!path) {
+    set_error("hkp_tune_cache_load: NULL path");
+    return HKP_E_ARG;
+  }
+  std::ifstream f(path);
+  if (!f) {
+    set_error(std::string("hkp_tune_cache_load: cannot read ") + path);
+    return HKP_E_ARG;
+  }
+  // parse everything first: a malformed file changes nothing
+  std::string arch;
+  std::vector<std::pair<TuneKey, StencilTune>> sten;
+  std::vector<std::pair<Key, int>> blocks;
+  std::string line;
+  int lineno = 0;
+  auto bad = [&](const std::string& why) {
+    set_error("hkp_tune_cache_load: " + std::string(path) + " line " + std::to_string(lineno) +
+              ": " + why);
+    return HKP_E_ARG;
+  };
+  while (std::getline(f, line)) {
+    ++lineno;
+    if (line.empty() || line[0] == '#') continue;
+    std::istringstream is(line);
+    std::string kind;
+    is >> kind;
+    if (kind == "arch") {
+      if (!(is >> arch)) return bad("arch without a name");
+    } else if (kind == "stencil") {
+      int v[12];
+      for (int& x : v)
+        if (!(is >> x)) return bad("stencil entry needs 12 integers");
+      StencilTune t;
+      t.tile_y = v[6];
+      t.vgroup = v[7];
+      t.dma = v[8];
+      t.zsplit = v[9];
+      t.t2x = v[10];
+      t.t2y = v[11];
+      const bool ok = v[0] > 0 && v[1] > 0 && v[2] > 0 && v[3] >= 1 && v[3] <= HKP_NB_MAX &&
+                      (v[4] == 0 || v[4] == 1) && v[5] >= 0 && v[5] < 6 &&
+                      (t.tile_y == 1 || t.tile_y == 2 || t.tile_y == 4) && t.vgroup >= 1 &&
+                      (t.dma == 0 || t.dma == 1) && t.zsplit >= 0 && t.zsplit <= 2 &&
+                      t.t2x >= 0 && t.t2y >= 0;
+      if (!ok) return bad("stencil entry out of range");
+      sten.push_back({TuneKey{v[0], v[1], v[2], v[3], v[4], v[5]}, t});
+    } else if (kind == "block") {
+      int v[6];
+      for (int& x : v)
+        if (!(is >> x)) return bad("block entry needs 6 integers");
+      if (v[0] < 1 || v[1] < 1 || v[2] < 1 || v[3] < 1 || (v[4] != 0 && v[4] != 1) ||
+          v[5] <= v[3] || v[5] > HKP_NB_MAX)
+        return bad("block entry out of range");
+      blocks.push_back({Key{v[0], v[1], v[2], v[3], v[4]}, v[5]});
+    } else {
+      return bad("unknown entry '" + kind + "'");
+    }
+  }
+  if (arch.empty()) {
+    lineno = 0;
+    return bad("no arch line");
+  }
+  if (arch != current_arch()) return 0;   // another device's choices
+  std::lock_guard<std::mutex> lk(g_mu);
+  for (const auto& e : sten) g_cache[e.first] = e.second;
+  for (const auto& e : blocks) g_nb_cache[e.first] = e.second;
+  return (int)(sten.size() + blocks.size());
+}
+
+void tune_cache_clear() {
+  std::lock_guard<std::mutex> lk(g_mu);
+  g_cache.clear();
+  g_nb_cache.clear();
 }
 
 bool two_step_tuned(const hkp_grid& g, int nb) {

@@ -122,6 +122,10 @@ StencilTune autotuned(const hkp_grid& g, int nb, bool mixed, int variant);
 // the FP32 filter of this grid and block size runs in two-step passes: the
 // autotuner chose them for some variant (or HKP_STENCIL2 forces a tile)
 bool two_step_tuned(const hkp_grid& g, int nb);
+// the autotuners' caches in a text file (hkp_tune_cache_save / _load / _clear)
+int tune_cache_save(const char* path);
+int tune_cache_load(const char* path);
+void tune_cache_clear();
 int run_autotune(const hkp_grid& g, int nb, bool mixed, bool strain, int field, void* ws,
                  size_t ws_bytes, void* stream, hkp_tune* out);
 

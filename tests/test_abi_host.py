@@ -314,3 +314,65 @@ def test_two_step_filter_rejects_bad_arguments():
     assert b"Y_old" in L.lib.hkp_last_error()
     assert L.lib.hkp_filter_step2(*args(fake, None, other, third, two(0, 0),
                                         need - 1)) == L.HKP_E_WORKSPACE
+
+
+def test_tune_cache_file_round_trip_and_errors(tmp_path):
+    """The autotuners' cache file: entries written for this host's device
+    architecture ("none" without a GPU) are taken and used by the queries;
+    another architecture's entries are skipped; a malformed file, a missing file
+    and a NULL path are HKP_E_ARG and change nothing."""
+    L, g, m, o = _structs()
+    L.lib.hkp_tune_cache_clear()
+    empty = tmp_path / "empty.txt"
+    assert L.lib.hkp_tune_cache_save(str(empty).encode()) == 0
+    arch = [ln.split()[1] for ln in empty.read_text().splitlines() if ln.startswith("arch ")][0]
+    t = L.hkp_tune()
+    assert L.lib.hkp_tuned_shape(C.byref(g), 16, 1, 1, 1, C.byref(t)) == 0
+    default = (t.tile_y, t.vgroup, t.dma)
+    o.nev, o.nb = 8, 0
+    assert L.lib.hkp_block_size(C.byref(g), C.byref(o)) == 16   # the default rule
+
+    f = tmp_path / "tune.txt"
+    # grid 10 x 8 x 8, nb 16, mixed, variant 3 (strain, field along x): 4-row tiles,
+    # groups of 2, no DMA; block size 24 for nev 8 in mixed precision
+    f.write_text("# test\narch %s\nstencil 10 8 8 16 1 3 4 2 0 0 0 0\nblock 10 8 8 8 1 24\n" % arch)
+    assert L.lib.hkp_tune_cache_load(str(f).encode()) == 2
+    assert L.lib.hkp_tuned_shape(C.byref(g), 16, 1, 1, 1, C.byref(t)) == 0
+    assert (t.tile_y, t.vgroup, t.dma) == (4, 2, 0)
+    o.precision = 1
+    assert L.lib.hkp_block_size(C.byref(g), C.byref(o)) == 24
+    o.precision = 0
+    assert L.lib.hkp_block_size(C.byref(g), C.byref(o)) == 16   # FP64: not cached
+
+    out = tmp_path / "saved.txt"
+    assert L.lib.hkp_tune_cache_save(str(out).encode()) == 2
+    lines = out.read_text().splitlines()
+    assert "arch %s" % arch in lines
+    assert "stencil 10 8 8 16 1 3 4 2 0 0 0 0" in lines and "block 10 8 8 8 1 24" in lines
+
+    L.lib.hkp_tune_cache_clear()
+    assert L.lib.hkp_tuned_shape(C.byref(g), 16, 1, 1, 1, C.byref(t)) == 0
+    assert (t.tile_y, t.vgroup, t.dma) == default
+    other = tmp_path / "other.txt"
+    other.write_text("arch gfx000-not-this-one\nstencil 10 8 8 16 1 3 4 2 0 0 0 0\n")
+    assert L.lib.hkp_tune_cache_load(str(other).encode()) == 0
+    assert L.lib.hkp_tuned_shape(C.byref(g), 16, 1, 1, 1, C.byref(t)) == 0
+    assert (t.tile_y, t.vgroup, t.dma) == default
+    assert L.lib.hkp_tune_cache_load(str(out).encode()) == 2   # the saved file reloads
+
+    L.lib.hkp_tune_cache_clear()
+    for bad in ("arch %s\nstencil 10 8 8 16 1 3 4 2 0\n" % arch,          # too few numbers
+                "arch %s\nstencil 10 8 8 16 1 3 3 2 0 0 0 0\n" % arch,    # tile height 3
+                "arch %s\nblock 10 8 8 8 1 8\n" % arch,                   # nb <= nev
+                "arch %s\nshape 1 2 3\n" % arch,                          # unknown entry
+                "stencil 10 8 8 16 1 3 4 2 0 0 0 0\n"):                   # no arch line
+        f.write_text(bad.replace("\n", "\nblock 10 8 8 8 1 24\n", 1))   # one valid line too
+        assert L.lib.hkp_tune_cache_load(str(f).encode()) == L.HKP_E_ARG, bad
+        assert L.lib.hkp_last_error()
+    o.precision = 1
+    assert L.lib.hkp_block_size(C.byref(g), C.byref(o)) == 16   # nothing was taken
+    assert L.lib.hkp_tune_cache_load(str(tmp_path / "missing.txt").encode()) == L.HKP_E_ARG
+    assert L.lib.hkp_tune_cache_load(None) == L.HKP_E_ARG
+    assert L.lib.hkp_tune_cache_save(None) == L.HKP_E_ARG
+    assert L.lib.hkp_tuned_shape(C.byref(g), 0, 1, 1, 1, C.byref(t)) == L.HKP_E_ARG
+    assert L.lib.hkp_tuned_shape(C.byref(g), 16, 1, 1, 3, C.byref(t)) == L.HKP_E_ARG
