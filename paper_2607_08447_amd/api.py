@@ -48,6 +48,20 @@ def _ptr(t):
     return C.c_void_p(t.data_ptr()) if t is not None else C.c_void_p(0)
 
 
+_PRIVATE_STREAMS = {}
+
+
+def _private_stream():
+    """The library's own stream on the current device (default priority), made once:
+    a stream's first use costs milliseconds, so calls do not take a new one each
+    time.  Capturing a stream needs one that is not the legacy default stream."""
+    dev = torch.cuda.current_device()
+    s = _PRIVATE_STREAMS.get(dev)
+    if s is None:
+        s = _PRIVATE_STREAMS[dev] = torch.cuda.Stream(device=dev)
+    return s
+
+
 def _stream(stream=None):
     s = stream if stream is not None else torch.cuda.current_stream()
     return C.c_void_p(s.cuda_stream)
@@ -161,7 +175,7 @@ def solve(V, h, nev, strain=None, B=(0.0, 0.0, 0.0), nb=0, degree=0, tol=1e-8,
     psi = torch.empty((npsi,) + shape + (ncomp,), dtype=torch.complex128, device="cuda") \
         if return_psi else None
     st = L.hkp_stats()
-    stream_ctx = torch.cuda.Stream() if graph else None
+    stream_ctx = _private_stream() if graph else None
     mat = _material(material)
     if stream_ctx is not None:
         stream_ctx.wait_stream(torch.cuda.current_stream())
@@ -215,7 +229,7 @@ def solve_batch(V, h, nev, strain=None, B=(0.0, 0.0, 0.0), nb=0, degree=0, tol=1
         if return_psi else None
     st = L.hkp_stats()
     mat = _material(material)
-    s = torch.cuda.Stream()
+    s = _private_stream()
     s.wait_stream(torch.cuda.current_stream())
     with torch.cuda.stream(s):
         code = L.lib.hkp_solve_batch(C.byref(g), C.byref(mat), C.byref(o), batch, _ptr(V),
@@ -534,7 +548,7 @@ def poisson(eps_r, dirichlet, phi_fixed, rho, h, phi0=None, tol=1e-12, max_iter=
     args = (C.byref(pg), float(h), _ptr(eps_r), _ptr(dirichlet), _ptr(phi_fixed), _ptr(rho),
             _ptr(phi), float(tol), int(max_iter), _ptr(ws), C.c_size_t(need))
     if graph:
-        s = torch.cuda.Stream()
+        s = _private_stream()
         s.wait_stream(torch.cuda.current_stream())
         with torch.cuda.stream(s):
             code = L.lib.hkp_poisson(*args, _stream(s), C.byref(it), C.byref(rel))
@@ -623,7 +637,7 @@ def sp_solve(V_off, h, nev, pshape, offset, eps_r, dirichlet, phi_fixed, n_holes
         if return_psi else None
     st = L.hkp_sp_stats()
     mat = _material(material)
-    s = torch.cuda.Stream() if graph else None
+    s = _private_stream() if graph else None
     if s is not None:
         s.wait_stream(torch.cuda.current_stream())
         ctx = torch.cuda.stream(s)

@@ -1,6 +1,7 @@
 // C ABI entry points (include/hkp.h): argument validation, workspace checks
 // and translation of failures into return codes.  No exception crosses the
 // ABI; nothing is enqueued on the GPU before the arguments have been checked.
+#include <atomic>
 #include <cmath>
 #include <cstring>
 #include <map>
@@ -99,6 +100,12 @@ int check_opts(const hkp_grid* g, const hkp_opts* o) {
   return HKP_OK;
 }
 
+// The current device must be a gfx950.  The architecture check reads the device
+// properties, which takes milliseconds; a device found to be a gfx950 is
+// remembered (per device index), so later calls only ask for the current device.
+constexpr int kMaxDevices = 64;
+std::atomic<bool> g_device_ok[kMaxDevices] = {};
+
 int check_device() {
   int dev = 0;
   hipError_t e = hipGetDevice(&dev);
@@ -106,6 +113,8 @@ int check_device() {
     set_error(std::string("no HIP device: ") + hipGetErrorString(e));
     return HKP_E_UNSUPPORTED;
   }
+  if (dev >= 0 && dev < kMaxDevices && g_device_ok[dev].load(std::memory_order_relaxed))
+    return HKP_OK;
   hipDeviceProp_t prop;
   e = hipGetDeviceProperties(&prop, dev);
   if (e != hipSuccess) {
@@ -117,6 +126,7 @@ int check_device() {
               " (built for gfx950)");
     return HKP_E_UNSUPPORTED;
   }
+  if (dev >= 0 && dev < kMaxDevices) g_device_ok[dev].store(true, std::memory_order_relaxed);
   return HKP_OK;
 }
 

@@ -324,6 +324,10 @@ constexpr int kMGCoarsest = 256;
 constexpr double kMGOmega = 0.9;       // damped-Jacobi weight (D^-1 A has spectrum in [0, 2])
 constexpr double kMGAlpha = 1.8;       // finest-level scaling of the coarse correction
 constexpr int kMGCoarseSweeps = 30;    // even
+// the coarse tail of the V-cycle: up to kMGTailLevels levels of at most
+// kMGTailNodes nodes each (the last is the coarsest), solved by one workgroup
+constexpr int kMGTailLevels = 3;
+constexpr int kMGTailNodes = 1024;
 struct MGLevel {
   int nx, ny, nz;
   long long N;
@@ -335,6 +339,7 @@ struct MGPlan {
   MGLevel lv[kMGMaxLevels];
   long long total;    // coefficient entries over all levels
   long long vtotal;   // coarse-vector entries of one system (levels >= 1)
+  int tail;           // first level of the tail (1 <= tail <= nlev - 1)
 };
 struct MGData {
   MGPlan plan;
@@ -346,9 +351,6 @@ MGPlan mg_plan(const PGeom& g);
 // level 0 from the CG's link coefficients, then every coarser level
 hipError_t launch_mg_setup(const PGeom& g, const double* cx, const double* cy, const double* cz,
                            const uint8_t* dir, const MGData& m, hipStream_t s);
-// z = V-cycle(r) for nrhs systems (skipping finished ones), partial sums of r.z
-hipError_t launch_mg_vcycle(const PGeom& g, const MGData& m, const double* r, double* z,
-                            const CGState* st, int nrhs, hipStream_t s);
 // after launch_cg_init: z and the starting r.z from the V-cycle
 hipError_t launch_mg_start(const PGeom& g, const MGData& m, const double* r, double* z,
                            CGState* st, int nrhs, hipStream_t s);
@@ -370,7 +372,9 @@ hipError_t launch_cg_init(const PGeom& g, const double* cx, const double* cy, co
                           double* p, double* partial, double tol, CGState* st, hipStream_t s,
                           int nrhs = 1);
 // one CG iteration (no-op once st->done): p_new = z + beta p_old, q = L p_new,
-// phi += alpha p_new, r -= alpha q, z = D^-1 r
+// phi += alpha p_new, r -= alpha q, z = D^-1 r (Jacobi, in place) or z = V-cycle(r)
+// (multigrid: the new r is written to z's buffer and the new z to r's, so the
+// next iteration takes the two buffers the other way round)
 hipError_t launch_cg_iter(const PGeom& g, const double* cx, const double* cy, const double* cz,
                           const double* dinv, const uint8_t* dir, double* z,
                           const double* p_old, double* p_new, double* q, double* phi,

@@ -271,9 +271,8 @@ cg_alpha_kernel(const double* partial, int nblk, CGState* st) {
   }
 }
 
-// phi += alpha p; r -= alpha q; z = D^-1 r (Jacobi; with the multigrid
-// preconditioner z comes from the V-cycle afterwards); partials r.z, r.r
-template <bool JACOBI>
+// phi += alpha p; r -= alpha q; z = D^-1 r (the Jacobi-preconditioned iteration;
+// the multigrid one does its update inside the finest restriction); partials r.z, r.r
 __global__ void __launch_bounds__(kThreads)
 cg_update_kernel(long long NP, const double* __restrict__ dinv, const double* __restrict__ p,
                  const double* __restrict__ q, double* phi, double* r, double* zv,
@@ -294,11 +293,9 @@ cg_update_kernel(long long NP, const double* __restrict__ dinv, const double* __
     phi[i] += alpha * pi;
     const double ri = r[i] - alpha * q[i];
     r[i] = ri;
-    if (JACOBI) {
-      const double zi = dinv[i] * ri;
-      zv[i] = zi;
-      acc[0] += ri * zi;
-    }
+    const double zi = dinv[i] * ri;
+    zv[i] = zi;
+    acc[0] += ri * zi;
     acc[1] += ri * ri;
   }
   block_sums<2>(acc, partial + 2LL * ((long long)blockIdx.y * gridDim.x + blockIdx.x));
@@ -319,16 +316,16 @@ cg_beta_kernel(const double* partial, int nblk, int max_iter, CGState* st) {
   }
 }
 
-// with the multigrid preconditioner: r.z from the V-cycle's partials, r.r from the
-// update's
+// with the multigrid preconditioner: r.z from the V-cycle's partials (nblk_rz per
+// system), r.r from the update's (nblk per system)
 __global__ void __launch_bounds__(kRedThreads)
-cg_beta_mg_kernel(const double* partial, const double* partial_rz, int nblk, int max_iter,
-                  CGState* st) {
+cg_beta_mg_kernel(const double* partial, int nblk, const double* partial_rz, int nblk_rz,
+                  int max_iter, CGState* st) {
   st += blockIdx.y;
   if (st->done) return;
   __shared__ double s[2], t[1];
   reduce_partials<2>(partial + 2LL * blockIdx.y * nblk, nblk, s);
-  reduce_partials<1>(partial_rz + (long long)blockIdx.y * nblk, nblk, t);
+  reduce_partials<1>(partial_rz + (long long)blockIdx.y * nblk_rz, nblk_rz, t);
   if (threadIdx.x == 0) {
     st->beta = st->rz > 0.0 ? t[0] / st->rz : 0.0;
     st->rz = t[0];
@@ -464,15 +461,34 @@ __device__ __forceinline__ double mg_apply(unsigned j, int x, int y, int z, cons
 // 2, 1, 0 = x, y, z offsets) and sum them by shuffles, so the fine level runs one
 // node per thread.  Like the other level kernels it gives every XCD a contiguous
 // run of nodes (the x- and y-neighbours a node reads are then in that XCD's L2).
+//
+// UPD (the finest level inside a CG iteration): the CG update comes first, in the
+// same pass -- phi += alpha p, r_new = b - alpha q written to r_new (another buffer:
+// the neighbours here read b and q, and b = r_new - alpha q is formed where needed),
+// partial sums (0, r_new.r_new) per workgroup -- and the restriction takes r_new as
+// its right-hand side.
+template <bool UPD>
 __global__ void __launch_bounds__(kThreads)
 mg_restrict_kernel(MGLevelArgs L, MGGeo c, double w, const double* __restrict__ b,
-                   long long b_stride, double* bc, long long bc_stride, const CGState* st) {
+                   long long b_stride, double* bc, long long bc_stride, const CGState* st,
+                   const double* __restrict__ p, const double* __restrict__ q,
+                   double* __restrict__ phi, double* __restrict__ r_new,
+                   double* __restrict__ partial) {
   if (st[blockIdx.y].done) return;
+  const double alpha = UPD ? st[blockIdx.y].alpha : 0.0;
   b += blockIdx.y * b_stride;
   bc += blockIdx.y * bc_stride;
+  if (UPD) {
+    p += blockIdx.y * b_stride;
+    q += blockIdx.y * b_stride;
+    phi += blockIdx.y * b_stride;
+    r_new += blockIdx.y * b_stride;
+  }
   const unsigned NC = (unsigned)c.nx * c.ny * c.nz;
-  auto u = [&](unsigned j) { return w * L.dinv[j] * b[j]; };
+  auto rhs = [&](unsigned j) { return UPD ? b[j] - alpha * q[j] : b[j]; };
+  auto u = [&](unsigned j) { return w * L.dinv[j] * rhs(j); };
   const unsigned ch = threadIdx.x & 7;
+  double acc[2] = {0.0, 0.0};
   // trip counts are equal within each group of eight lanes (8 NC and the stride are
   // multiples of eight), so every shuffle below sees its whole group
   for (unsigned t = xcd_remap(blockIdx.x, gridDim.x) * kThreads + threadIdx.x; t < 8 * NC; t += gridDim.x * kThreads) {
@@ -484,56 +500,167 @@ mg_restrict_kernel(MGLevelArgs L, MGGeo c, double w, const double* __restrict__ 
     double s = 0.0;
     if (x < L.g.nx && y < L.g.ny && z < L.g.nz) {
       const unsigned j = ((unsigned)x * L.g.ny + y) * L.g.nz + z;
-      if (L.dinv[j] != 0.0) s = b[j] - mg_apply(j, x, y, z, L, u(j), u);   // active node
+      const double bj = rhs(j);
+      if (UPD) {
+        phi[j] += alpha * p[j];
+        r_new[j] = bj;
+        acc[1] += bj * bj;
+      }
+      const double dj = L.dinv[j];
+      if (dj != 0.0) s = bj - mg_apply(j, x, y, z, L, w * dj * bj, u);   // active node
     }
     s += __shfl_xor(s, 1, 8);
     s += __shfl_xor(s, 2, 8);
     s += __shfl_xor(s, 4, 8);
     if (ch == 0) bc[I] = s;
   }
+  if (UPD) block_sums<2>(acc, partial + 2LL * ((long long)blockIdx.y * gridDim.x + blockIdx.x));
 }
 
-// the coarsest level: sweeps (even) damped-Jacobi sweeps from zero, one workgroup
-__global__ void __launch_bounds__(kMGCoarsest)
-mg_coarsest_kernel(MGLevelArgs L, double w, int sweeps, const double* __restrict__ b,
-                   long long b_stride, double* u_out, long long u_stride, const CGState* st) {
-  if (st[blockIdx.y].done) return;
-  b += blockIdx.y * b_stride;
-  u_out += blockIdx.y * u_stride;
-  __shared__ double u[2][kMGCoarsest];
-  const unsigned n = (unsigned)L.g.nx * L.g.ny * L.g.nz;
-  const unsigned j = threadIdx.x;
-  // this node's row in registers: neighbour indices and weights (0 past the box)
-  unsigned nb[6] = {j, j, j, j, j, j};
-  double wt[6] = {0, 0, 0, 0, 0, 0}, dg = 0.0, wd = 0.0, bj = 0.0;
-  if (j < n) {
-    int x, y, z;
-    mg_coords(j, L.g, x, y, z);
-    const unsigned sx = (unsigned)L.g.ny * L.g.nz, sy = (unsigned)L.g.nz;
-    if (x + 1 < L.g.nx) { nb[0] = j + sx; wt[0] = L.ax[j]; }
-    if (x > 0) { nb[1] = j - sx; wt[1] = L.ax[j - sx]; }
-    if (y + 1 < L.g.ny) { nb[2] = j + sy; wt[2] = L.ay[j]; }
-    if (y > 0) { nb[3] = j - sy; wt[3] = L.ay[j - sy]; }
-    if (z + 1 < L.g.nz) { nb[4] = j + 1; wt[4] = L.az[j]; }
-    if (z > 0) { nb[5] = j - 1; wt[5] = L.az[j - 1]; }
-    dg = L.diag[j];
-    wd = w * L.dinv[j];
-    bj = b[j];
-  }
-  u[0][j] = 0.0;
-  __syncthreads();
-  for (int k = 0; k < sweeps; ++k) {
-    const double* uo = u[k & 1];
-    if (j < n) {
-      const double uj = uo[j];
-      double r = bj - dg * uj;
+// The coarse tail of the V-cycle: levels t .. t + nt - 1 (the last one the
+// coarsest), each of at most kMGTailNodes nodes, for one system per workgroup of
+// kMGTailNodes threads.  Thread j keeps node j's row of every tail level in
+// registers (loaded once) and the vectors live in LDS, so the steps below touch
+// memory only to read b_t and write u_t: restriction of the pre-smoothed residual
+// level by level, the coarsest level's (even number of) damped-Jacobi sweeps from
+// zero, and the corrections back up (prolonged coarse iterate plus w D^-1 b, then
+// one damped-Jacobi sweep) -- what the per-level kernels do on the finer levels.
+struct MGTailArgs {
+  int t, nt;
+  MGLevelArgs lv[kMGTailLevels];
+};
+
+// node j's row: diagonal, w D^-1, the six link weights (0 past the box or for an
+// inactive link) with the neighbours' indices (j itself where the weight is 0),
+// and the index of its aggregate on the next coarser level
+struct MGRow {
+  double dg, wd, a[6];
+  unsigned nb[6], parent;
+  bool on;
+};
+
+__device__ __forceinline__ MGRow mg_row(const MGLevelArgs& A, const MGGeo* c, unsigned j,
+                                        double w) {
+  MGRow r;
+  const unsigned n = (unsigned)A.g.nx * A.g.ny * A.g.nz;
+  r.on = j < n;
+  r.dg = 0.0;
+  r.wd = 0.0;
+  r.parent = 0;
 #pragma unroll
-      for (int q = 0; q < 6; ++q) r += wt[q] * uo[nb[q]];
-      u[(k + 1) & 1][j] = uj + wd * r;
+  for (int q = 0; q < 6; ++q) {
+    r.a[q] = 0.0;
+    r.nb[q] = j;
+  }
+  if (!r.on) return r;
+  int x, y, z;
+  mg_coords(j, A.g, x, y, z);
+  const unsigned sx = (unsigned)A.g.ny * A.g.nz, sy = (unsigned)A.g.nz;
+  if (x + 1 < A.g.nx) { r.a[0] = A.ax[j]; r.nb[0] = j + sx; }
+  if (x > 0) { r.a[1] = A.ax[j - sx]; r.nb[1] = j - sx; }
+  if (y + 1 < A.g.ny) { r.a[2] = A.ay[j]; r.nb[2] = j + sy; }
+  if (y > 0) { r.a[3] = A.ay[j - sy]; r.nb[3] = j - sy; }
+  if (z + 1 < A.g.nz) { r.a[4] = A.az[j]; r.nb[4] = j + 1; }
+  if (z > 0) { r.a[5] = A.az[j - 1]; r.nb[5] = j - 1; }
+  r.dg = A.diag[j];
+  r.wd = w * A.dinv[j];
+  if (c)
+    r.parent = (unsigned)(x >> 1) * ((unsigned)c->ny * c->nz) + (unsigned)(y >> 1) * c->nz +
+               (unsigned)(z >> 1);
+  return r;
+}
+
+// (A u)_j, the row's order of terms as in mg_apply
+__device__ __forceinline__ double mg_row_apply(const MGRow& r, const double* u, double uj) {
+  double s = r.dg * uj;
+#pragma unroll
+  for (int q = 0; q < 6; ++q) s -= r.a[q] * u[r.nb[q]];
+  return s;
+}
+
+__global__ void __launch_bounds__(kMGTailNodes)
+mg_tail_kernel(MGTailArgs T, double w, int sweeps, const double* __restrict__ bt,
+               double* __restrict__ ut, long long v_stride, const CGState* st) {
+  if (st[blockIdx.y].done) return;
+  bt += blockIdx.y * v_stride;
+  ut += blockIdx.y * v_stride;
+  // per level b and u, the coarsest level's second iterate, the residual scratch
+  __shared__ double sb[kMGTailLevels][kMGTailNodes], su[kMGTailLevels][kMGTailNodes];
+  __shared__ double su2[kMGTailNodes], sr[kMGTailNodes];
+  const unsigned j = threadIdx.x;
+  const int nt = T.nt;
+  MGRow row[kMGTailLevels];
+#pragma unroll
+  for (int s = 0; s < kMGTailLevels; ++s) {
+    row[s] = mg_row(T.lv[s], s + 1 < nt ? &T.lv[s + 1].g : nullptr, j, w);
+    row[s].on = row[s].on && s < nt;
+  }
+  if (row[0].on) sb[0][j] = bt[j];
+  __syncthreads();
+#pragma unroll
+  for (int s = 0; s + 1 < kMGTailLevels; ++s) {   // restriction s -> s + 1
+    if (s + 1 >= nt) break;
+    if (row[s].on) su[s][j] = row[s].wd * sb[s][j];
+    __syncthreads();
+    if (row[s].on)
+      sr[j] = row[s].wd != 0.0 ? sb[s][j] - mg_row_apply(row[s], su[s], su[s][j]) : 0.0;
+    __syncthreads();
+    if (row[s + 1].on) {   // sum over the children of this aggregate
+      const MGGeo& f = T.lv[s].g;
+      int X, Y, Z;
+      mg_coords(j, T.lv[s + 1].g, X, Y, Z);
+      double acc = 0.0;
+      for (int ch = 0; ch < 8; ++ch) {
+        const int x = 2 * X + (ch >> 2), y = 2 * Y + ((ch >> 1) & 1), z = 2 * Z + (ch & 1);
+        if (x < f.nx && y < f.ny && z < f.nz) acc += sr[((unsigned)x * f.ny + y) * f.nz + z];
+      }
+      sb[s + 1][j] = acc;
     }
     __syncthreads();
   }
-  if (j < n) u_out[j] = u[sweeps & 1][j];
+  // the coarsest level: sweeps from zero, ping-pong between su[c] and su2
+  const int c = nt - 1;
+  MGRow rc = row[0];
+  const double* bc = sb[0];
+  double* u0 = su[0];
+#pragma unroll
+  for (int s = 1; s < kMGTailLevels; ++s)
+    if (s == c) {
+      rc = row[s];
+      bc = sb[s];
+      u0 = su[s];
+    }
+  if (rc.on) u0[j] = 0.0;
+  __syncthreads();
+  for (int q = 0; q < sweeps; ++q) {
+    const double* uo = (q & 1) ? su2 : u0;
+    double* un = (q & 1) ? u0 : su2;
+    if (rc.on) {
+      const double uj = uo[j];
+      un[j] = uj + rc.wd * (bc[j] - mg_row_apply(rc, uo, uj));
+    }
+    __syncthreads();
+  }
+  if (nt == 1) {   // sweeps is even: the result is in u0
+    if (rc.on) ut[j] = u0[j];
+    return;
+  }
+#pragma unroll
+  for (int s = kMGTailLevels - 2; s >= 0; --s) {   // correction of s from s + 1
+    if (s + 1 >= nt) continue;
+    const double* E = (s + 1 == c) ? su[s + 1] : sb[s + 1];   // level s + 1's result
+    if (row[s].on)
+      su[s][j] = row[s].wd == 0.0 ? 0.0 : row[s].wd * sb[s][j] + E[row[s].parent];
+    __syncthreads();
+    if (row[s].on) {
+      const double uj = su[s][j];
+      const double o =
+          row[s].wd == 0.0 ? 0.0 : uj + row[s].wd * (sb[s][j] - mg_row_apply(row[s], su[s], uj));
+      if (s > 0) sb[s][j] = o;
+      else ut[j] = o;
+    }
+    __syncthreads();
+  }
 }
 
 // u' = w D^-1 b + alpha P e (the pre-smoothed u plus the prolonged correction),
@@ -1002,6 +1129,18 @@ hipError_t launch_cg_init(const PGeom& g, const double* cx, const double* cy, co
   return hipGetLastError();
 }
 
+namespace {
+MGGeo mg_geo(const MGLevel& L) { return MGGeo{L.nx, L.ny, L.nz, 1.0 / L.ny, 1.0 / L.nz}; }
+MGLevelArgs mg_args(const MGData& m, int k) {
+  const MGLevel& L = m.plan.lv[k];
+  return MGLevelArgs{mg_geo(L), m.ax + L.off, m.ay + L.off, m.az + L.off, m.diag + L.off,
+                     m.dinv + L.off};
+}
+}  // namespace
+
+hipError_t launch_mg_vcycle(const PGeom& g, const MGData& m, const double* r, double* z,
+                            const CGState* st, int nrhs, hipStream_t s, bool restrict0);
+
 hipError_t launch_cg_iter(const PGeom& g, const double* cx, const double* cy, const double* cz,
                           const double* dinv, const uint8_t* dir, double* z,
                           const double* p_old, double* p_new, double* q, double* phi,
@@ -1013,17 +1152,23 @@ hipError_t launch_cg_iter(const PGeom& g, const double* cx, const double* cy, co
                                            partial, st);
   cg_alpha_kernel<<<dim3(1, nrhs), kRedThreads, 0, s>>>(partial, nb, st);
   if (!mg) {
-    cg_update_kernel<true><<<dim3(nb, nrhs), kThreads, 0, s>>>(g.NP, dinv, p_new, q, phi, r, z,
+    cg_update_kernel<<<dim3(nb, nrhs), kThreads, 0, s>>>(g.NP, dinv, p_new, q, phi, r, z,
                                                                partial, st);
     cg_beta_kernel<<<dim3(1, nrhs), kRedThreads, 0, s>>>(partial, nb, max_iter, st);
     return hipGetLastError();
   }
-  cg_update_kernel<false><<<dim3(nb, nrhs), kThreads, 0, s>>>(g.NP, dinv, p_new, q, phi, r, z,
-                                                              partial, st);
-  const hipError_t e = launch_mg_vcycle(g, *mg, r, z, st, nrhs, s);
+  // the update inside the finest restriction: the new r goes to z's buffer (z is
+  // spent once p_new is formed) and the V-cycle's z to r's, so the caller swaps the
+  // two buffers from one iteration to the next
+  const MGPlan& P = mg->plan;
+  const unsigned nbu = (unsigned)sp_blocks(8 * P.lv[1].N);
+  mg_restrict_kernel<true><<<dim3(nbu, nrhs), kThreads, 0, s>>>(
+      mg_args(*mg, 0), mg_geo(P.lv[1]), kMGOmega, r, g.NP, mg->b + P.lv[1].voff, P.vtotal, st,
+      p_new, q, phi, z, partial);
+  const hipError_t e = launch_mg_vcycle(g, *mg, z, r, st, nrhs, s, false);
   if (e != hipSuccess) return e;
-  cg_beta_mg_kernel<<<dim3(1, nrhs), kRedThreads, 0, s>>>(partial, mg->partial_rz, nb, max_iter,
-                                                          st);
+  cg_beta_mg_kernel<<<dim3(1, nrhs), kRedThreads, 0, s>>>(partial, (int)nbu, mg->partial_rz, nb,
+                                                          max_iter, st);
   return hipGetLastError();
 }
 
@@ -1049,23 +1194,27 @@ MGPlan mg_plan(const PGeom& g) {
   }
   P.total = off;
   P.vtotal = voff;
+  // the tail: the levels of at most kMGTailNodes nodes, at most kMGTailLevels of
+  // them, never level 0 (level sizes do not grow towards the coarsest)
+  const int L = P.nlev - 1;
+  P.tail = L;
+  while (P.tail > 1 && P.tail > L - kMGTailLevels + 1 && P.lv[P.tail - 1].N <= kMGTailNodes)
+    --P.tail;
   return P;
 }
 
 namespace {
-MGGeo mgeo(const MGLevel& L) { return MGGeo{L.nx, L.ny, L.nz, 1.0 / L.ny, 1.0 / L.nz}; }
-MGLevelArgs margs(const MGData& m, int k) {
-  const MGLevel& L = m.plan.lv[k];
-  return MGLevelArgs{mgeo(L), m.ax + L.off, m.ay + L.off, m.az + L.off, m.diag + L.off,
-                     m.dinv + L.off};
-}
+MGGeo mgeo(const MGLevel& L) { return mg_geo(L); }
+MGLevelArgs margs(const MGData& m, int k) { return mg_args(m, k); }
 unsigned mg_blocks(long long n) { return (unsigned)sp_blocks(n); }
 }  // namespace
 
 hipError_t launch_mg_setup(const PGeom& g, const double* cx, const double* cy, const double* cz,
                            const uint8_t* dir, const MGData& m, hipStream_t s) {
   const MGPlan& P = m.plan;
-  if (P.lv[P.nlev - 1].N > kMGCoarsest || P.nlev < 2) return hipErrorInvalidValue;
+  if (P.lv[P.nlev - 1].N > kMGCoarsest || P.nlev < 2 || P.tail < 1 || P.tail >= P.nlev ||
+      P.nlev - P.tail > kMGTailLevels || P.lv[P.tail].N > kMGTailNodes)
+    return hipErrorInvalidValue;
   mg_level0_kernel<<<mg_blocks(g.NP), kThreads, 0, s>>>((unsigned)g.NP, mgeo(P.lv[0]), cx, cy,
                                                         cz, dir, m.ax, m.ay, m.az, m.diag,
                                                         m.dinv);
@@ -1078,21 +1227,29 @@ hipError_t launch_mg_setup(const PGeom& g, const double* cx, const double* cy, c
   return hipGetLastError();
 }
 
+// z = V-cycle(r) for nrhs systems (skipping finished ones), partial sums of r.z;
+// restrict0 false: the finest restriction has been done by the caller
 hipError_t launch_mg_vcycle(const PGeom& g, const MGData& m, const double* r, double* z,
-                            const CGState* st, int nrhs, hipStream_t s) {
+                            const CGState* st, int nrhs, hipStream_t s, bool restrict0) {
   const MGPlan& P = m.plan;
-  const int L = P.nlev - 1;
+  const int L = P.nlev - 1, t = P.tail;
   const long long vs = P.vtotal;
   auto bvec = [&](int k) { return k == 0 ? r : m.b + P.lv[k].voff; };
-  for (int k = 0; k < L; ++k) {
+  for (int k = restrict0 ? 0 : 1; k < t; ++k) {
     const MGLevel& C = P.lv[k + 1];
-    mg_restrict_kernel<<<dim3(mg_blocks(8 * C.N), nrhs), kThreads, 0, s>>>(
-        margs(m, k), mgeo(C), kMGOmega, bvec(k), k == 0 ? g.NP : vs, m.b + C.voff, vs, st);
+    mg_restrict_kernel<false><<<dim3(mg_blocks(8 * C.N), nrhs), kThreads, 0, s>>>(
+        margs(m, k), mgeo(C), kMGOmega, bvec(k), k == 0 ? g.NP : vs, m.b + C.voff, vs, st,
+        nullptr, nullptr, nullptr, nullptr, nullptr);
   }
-  mg_coarsest_kernel<<<dim3(1, nrhs), kMGCoarsest, 0, s>>>(margs(m, L), kMGOmega,
-                                                           kMGCoarseSweeps, m.b + P.lv[L].voff,
-                                                           vs, m.u + P.lv[L].voff, vs, st);
-  for (int k = L - 1; k >= 1; --k) {
+  MGTailArgs T{};
+  T.t = t;
+  T.nt = L - t + 1;
+  for (int k = t; k <= L; ++k) T.lv[k - t] = margs(m, k);
+  for (int k = L + 1; k < t + kMGTailLevels; ++k) T.lv[k - t] = margs(m, L);   // unused slots
+  mg_tail_kernel<<<dim3(1, nrhs), kMGTailNodes, 0, s>>>(T, kMGOmega, kMGCoarseSweeps,
+                                                         m.b + P.lv[t].voff, m.u + P.lv[t].voff,
+                                                         vs, st);
+  for (int k = t - 1; k >= 1; --k) {
     const MGLevel &F = P.lv[k], &C = P.lv[k + 1];
     mg_correct_kernel<false><<<dim3(mg_blocks(F.N), nrhs), kThreads, 0, s>>>(
         margs(m, k), mgeo(C), kMGOmega, 1.0, m.b + F.voff, vs, m.u + C.voff, vs, m.u + F.voff,
@@ -1107,7 +1264,7 @@ hipError_t launch_mg_vcycle(const PGeom& g, const MGData& m, const double* r, do
 
 hipError_t launch_mg_start(const PGeom& g, const MGData& m, const double* r, double* z,
                            CGState* st, int nrhs, hipStream_t s) {
-  const hipError_t e = launch_mg_vcycle(g, m, r, z, st, nrhs, s);
+  const hipError_t e = launch_mg_vcycle(g, m, r, z, st, nrhs, s, true);
   if (e != hipSuccess) return e;
   cg_rz_kernel<<<dim3(1, nrhs), kRedThreads, 0, s>>>(m.partial_rz, sp_blocks(g.NP), st);
   return hipGetLastError();

@@ -100,14 +100,20 @@ int poisson_prepare(const PGeom& g, double h, const double* eps, const uint8_t* 
 
 // A chunk of CG iterations recorded once as a hipGraph (kernels only) and
 // replayed: the launches of one iteration are short, so their gaps matter.
-// Reused while the solution buffer and the iteration cap stay the same.
+// Reused while everything the recorded launches take stays the same: the
+// solution, electrode-mask and workspace buffers, the box, the iteration cap, the
+// number of systems, the preconditioner and the device.
 struct CGGraph {
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
   const double* phi = nullptr;
+  const uint8_t* dir = nullptr;
+  const void* ws = nullptr;
+  int px = 0, py = 0, pz = 0;
   int max_iter = -1;
   int nrhs = 0;
   int precond = -1;
+  int device = -1;
   void reset() {
     if (exec) (void)hipGraphExecDestroy(exec);
     if (graph) (void)hipGraphDestroy(graph);
@@ -126,7 +132,10 @@ void launch_cg_chunk(const PGeom& g, const uint8_t* dir, double* phi, int max_it
   for (int c = 0; c < cg_chunk(mg); ++c) {
     double* po = (c % 2 == 0) ? w.p0 : w.p1;
     double* pn = (c % 2 == 0) ? w.p1 : w.p0;
-    HKP_CHECK(launch_cg_iter(g, w.cx, w.cy, w.cz, w.dinv, dir, w.z, po, pn, w.q, phi, w.r,
+    // with multigrid r and z trade buffers every iteration (chunks are even)
+    double* z = (mg && c % 2 == 1) ? w.r : w.z;
+    double* r = (mg && c % 2 == 1) ? w.z : w.r;
+    HKP_CHECK(launch_cg_iter(g, w.cx, w.cy, w.cz, w.dinv, dir, z, po, pn, w.q, phi, r,
                              w.partial, max_iter, w.st, s, nrhs, mg ? &w.mg : nullptr));
   }
 }
@@ -142,9 +151,12 @@ int poisson_cg(const PGeom& g, const uint8_t* dir, const double* phi_fixed, cons
   HKP_CHECK(launch_cg_init(g, w.cx, w.cy, w.cz, w.dinv, dir, phi_fixed, rho, kEoverEps0, phi,
                            w.r, w.z, w.p0, w.partial, tol, w.st, s, nrhs));
   if (mg) HKP_CHECK(launch_mg_start(g, w.mg, w.r, w.z, w.st, nrhs, s));
+  int device = -1;
+  HKP_CHECK(hipGetDevice(&device));
   if (gc && s != nullptr &&
-      (gc->phi != phi || gc->max_iter != max_iter || gc->nrhs != nrhs ||
-       gc->precond != precond || !gc->exec)) {
+      (gc->phi != phi || gc->dir != dir || gc->ws != w.st || gc->px != g.px || gc->py != g.py ||
+       gc->pz != g.pz || gc->max_iter != max_iter || gc->nrhs != nrhs ||
+       gc->precond != precond || gc->device != device || !gc->exec)) {
     gc->reset();
     HKP_CHECK(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
     try {
@@ -158,9 +170,15 @@ int poisson_cg(const PGeom& g, const uint8_t* dir, const double* phi_fixed, cons
     HKP_CHECK(hipStreamEndCapture(s, &gc->graph));
     HKP_CHECK(hipGraphInstantiate(&gc->exec, gc->graph, nullptr, nullptr, 0));
     gc->phi = phi;
+    gc->dir = dir;
+    gc->ws = w.st;
+    gc->px = g.px;
+    gc->py = g.py;
+    gc->pz = g.pz;
     gc->max_iter = max_iter;
     gc->nrhs = nrhs;
     gc->precond = precond;
+    gc->device = device;
   }
   const bool use_graph = gc && s != nullptr && gc->exec;
   std::vector<CGState> h((size_t)nrhs);
@@ -216,9 +234,12 @@ int run_poisson(const PoissonArgs& a, int* iters, double* relres) {
   const PoissonWS w = carve_poisson(c, g);
   const int rc = poisson_prepare(g, a.h, a.eps, a.dir, w, s);
   if (rc != HKP_OK) return rc;
-  CGGraph gc;
+  // one recorded chunk per host thread, kept across calls (repeated solves with the
+  // same buffers skip recording); never destroyed, so nothing runs at process exit
+  // after the HIP runtime has gone
+  thread_local CGGraph* gc = new CGGraph;
   return poisson_cg(g, a.dir, a.phi_fixed, a.rho, a.phi, a.tol, a.max_iter, w, s, iters,
-                    relres, &gc);
+                    relres, gc);
 }
 
 namespace {
