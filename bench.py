@@ -356,12 +356,13 @@ def adjoint_measure(torch, hkp, workload, reps=10):
 # electrode mask, write p and L p) and the vector update (read D^-1, p, L p, phi,
 # r; write phi, r, z)
 CG_BYTES_PER_NODE = (8 + 8 + 24 + 1 + 8 + 8) + (5 * 8 + 3 * 8)
-# one multigrid-preconditioned CG iteration, per node of the box: the CG kernels without
-# the Jacobi z (operator 57, update: read p, q, phi, r, write phi, r = 48), the V-cycle's
-# finest level (restriction: read b, D^-1, diag, three link weights = 48; correction: the
-# same 48, the coarse correction 1, write z 8) and its coarser levels (the same pattern
-# on 1/8 + 1/64 + ... of the nodes, about 15)
-MG_PCG_BYTES_PER_NODE = (57 + 48) + (48 + 57) + 15
+# one multigrid-preconditioned CG iteration, per node of the box: the operator (57, as
+# above), the CG update fused into the finest restriction (read p, q, phi, r, D^-1,
+# diag, three link weights = 72; write phi, the new r = 16; the coarse right-hand side
+# 1), the finest correction (read r, D^-1, diag, three link weights = 48, the coarse
+# correction 1; write z 8) and the coarser levels (the same pattern on 1/8 + 1/64 + ...
+# of the nodes, about 15)
+MG_PCG_BYTES_PER_NODE = 57 + (72 + 16 + 1) + (48 + 1 + 8) + 15
 
 
 def sp_measure(torch, hkp, anneal_K=15.0):

@@ -142,6 +142,43 @@ __device__ __forceinline__ double link_sum(unsigned i, int x, int y, int z, cons
   return s;
 }
 
+// The six neighbours of node i at (x, y, z) in an nx x ny x nz box with strides
+// sx, sy (order +x, -x, +y, -y, +z, -z), for branch-free stencils: indices clamped
+// to i itself where the neighbour would lie outside the box, with that link's
+// weight set to zero.  Every load of such a stencil is issued unconditionally, so
+// a thread's loads go out back to back instead of one conditional round trip to
+// memory per link.
+struct Hood {
+  unsigned j[6];
+  bool in[6];
+};
+__device__ __forceinline__ Hood hood(unsigned i, int x, int y, int z, int nx, int ny, int nz,
+                                     unsigned sx, unsigned sy) {
+  Hood h;
+  h.in[0] = x + 1 < nx;
+  h.in[1] = x > 0;
+  h.in[2] = y + 1 < ny;
+  h.in[3] = y > 0;
+  h.in[4] = z + 1 < nz;
+  h.in[5] = z > 0;
+  h.j[0] = h.in[0] ? i + sx : i;
+  h.j[1] = h.in[1] ? i - sx : i;
+  h.j[2] = h.in[2] ? i + sy : i;
+  h.j[3] = h.in[3] ? i - sy : i;
+  h.j[4] = h.in[4] ? i + 1 : i;
+  h.j[5] = h.in[5] ? i - 1 : i;
+  return h;
+}
+// weights of the six links from per-node +x, +y, +z link arrays (the link to the
+// lower neighbour is stored there), zero outside the box
+__device__ __forceinline__ void hood_weights(unsigned i, const Hood& h, const double* ax,
+                                             const double* ay, const double* az,
+                                             double (&c)[6]) {
+  const double v[6] = {ax[i], ax[h.j[1]], ay[i], ay[h.j[3]], az[i], az[h.j[5]]};
+#pragma unroll
+  for (int q = 0; q < 6; ++q) c[q] = h.in[q] ? v[q] : 0.0;
+}
+
 // Every CG kernel solves blockIdx.y = 0 .. nrhs-1 systems at once (the same
 // operator, right-hand sides and vectors vs = NP apart, a CGState each); the
 // single-system solves are nrhs = 1.
@@ -236,21 +273,25 @@ cg_matvec_kernel(unsigned NP, int px, int py, int pz, double ipy, double ipz,
   double acc[1] = {0.0};
   for (unsigned i = xcd_remap(blockIdx.x, gridDim.x) * kThreads + threadIdx.x; i < NP;
        i += gridDim.x * kThreads) {
-    if (dir[i]) {
-      p_new[i] = 0.0;
-      q[i] = 0.0;
-      continue;
-    }
     int x, y, z;
     coords(i, g, x, y, z);
+    const Hood h = hood(i, x, y, z, g.px, g.py, g.pz, g.sx, g.sy);
+    const bool d = dir[i] != 0;
+    double c[6], zn[6], pn[6];
+    hood_weights(i, h, cx, cy, cz, c);
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+      zn[k] = zv[h.j[k]];
+      pn[k] = p_old[h.j[k]];
+    }
     const double pi = zv[i] + beta * p_old[i];
     // electrode neighbours hold z = p_old = 0, so their p_new is 0 as well
-    const double qi = link_sum(i, x, y, z, g, cx, cy, cz, pi, [&](unsigned j) {
-      return zv[j] + beta * p_old[j];
-    });
-    p_new[i] = pi;
-    q[i] = qi;
-    acc[0] += pi * qi;
+    double qi = 0.0;
+#pragma unroll
+    for (int k = 0; k < 6; ++k) qi += c[k] * (pi - (zn[k] + beta * pn[k]));
+    p_new[i] = d ? 0.0 : pi;
+    q[i] = d ? 0.0 : qi;
+    acc[0] += d ? 0.0 : pi * qi;
   }
   block_sums<1>(acc, partial + (long long)blockIdx.y * gridDim.x + blockIdx.x);
 }
@@ -441,18 +482,22 @@ struct MGLevelArgs {
   const double *ax, *ay, *az, *diag, *dinv;
 };
 
-// (A u)_j with u given by a functor of the node index
+__device__ __forceinline__ Hood mg_hood(unsigned j, int x, int y, int z, const MGGeo& g) {
+  return hood(j, x, y, z, g.nx, g.ny, g.nz, (unsigned)g.ny * g.nz, (unsigned)g.nz);
+}
+
+// (A u)_j with u given by a functor of the neighbour's index and its direction
+// (0 .. 5 as in Hood); every load unconditional
 template <typename F>
-__device__ __forceinline__ double mg_apply(unsigned j, int x, int y, int z, const MGLevelArgs& L,
+__device__ __forceinline__ double mg_apply(unsigned j, const Hood& h, const MGLevelArgs& L,
                                            double uj, F u) {
-  const unsigned sx = (unsigned)L.g.ny * L.g.nz, sy = (unsigned)L.g.nz;
+  double c[6], v[6];
+  hood_weights(j, h, L.ax, L.ay, L.az, c);
+#pragma unroll
+  for (int k = 0; k < 6; ++k) v[k] = u(h.j[k], k);
   double s = L.diag[j] * uj;
-  if (x + 1 < L.g.nx) s -= L.ax[j] * u(j + sx);
-  if (x > 0) s -= L.ax[j - sx] * u(j - sx);
-  if (y + 1 < L.g.ny) s -= L.ay[j] * u(j + sy);
-  if (y > 0) s -= L.ay[j - sy] * u(j - sy);
-  if (z + 1 < L.g.nz) s -= L.az[j] * u(j + 1);
-  if (z > 0) s -= L.az[j - 1] * u(j - 1);
+#pragma unroll
+  for (int k = 0; k < 6; ++k) s -= c[k] * v[k];
   return s;
 }
 
@@ -486,7 +531,7 @@ mg_restrict_kernel(MGLevelArgs L, MGGeo c, double w, const double* __restrict__ 
   }
   const unsigned NC = (unsigned)c.nx * c.ny * c.nz;
   auto rhs = [&](unsigned j) { return UPD ? b[j] - alpha * q[j] : b[j]; };
-  auto u = [&](unsigned j) { return w * L.dinv[j] * rhs(j); };
+  auto u = [&](unsigned j, int) { return w * L.dinv[j] * rhs(j); };
   const unsigned ch = threadIdx.x & 7;
   double acc[2] = {0.0, 0.0};
   // trip counts are equal within each group of eight lanes (8 NC and the stride are
@@ -497,17 +542,19 @@ mg_restrict_kernel(MGLevelArgs L, MGGeo c, double w, const double* __restrict__ 
     mg_coords(I, c, X, Y, Z);
     const int x = 2 * X + (int)(ch >> 2), y = 2 * Y + (int)((ch >> 1) & 1),
               z = 2 * Z + (int)(ch & 1);
-    double s = 0.0;
-    if (x < L.g.nx && y < L.g.ny && z < L.g.nz) {
-      const unsigned j = ((unsigned)x * L.g.ny + y) * L.g.nz + z;
-      const double bj = rhs(j);
-      if (UPD) {
-        phi[j] += alpha * p[j];
-        r_new[j] = bj;
-        acc[1] += bj * bj;
-      }
-      const double dj = L.dinv[j];
-      if (dj != 0.0) s = bj - mg_apply(j, x, y, z, L, w * dj * bj, u);   // active node
+    // a child past a ragged edge of the box stands in for the aggregate's first
+    // child (which always exists) and contributes nothing
+    const bool inb = x < L.g.nx && y < L.g.ny && z < L.g.nz;
+    const int xx = inb ? x : 2 * X, yy = inb ? y : 2 * Y, zz = inb ? z : 2 * Z;
+    const unsigned j = ((unsigned)xx * L.g.ny + yy) * L.g.nz + zz;
+    const double bj = rhs(j);
+    const double dj = L.dinv[j];
+    const double sj = bj - mg_apply(j, mg_hood(j, xx, yy, zz, L.g), L, w * dj * bj, u);
+    double s = (inb && dj != 0.0) ? sj : 0.0;   // active nodes only
+    if (UPD && inb) {
+      phi[j] += alpha * p[j];
+      r_new[j] = bj;
+      acc[1] += bj * bj;
     }
     s += __shfl_xor(s, 1, 8);
     s += __shfl_xor(s, 2, 8);
@@ -676,32 +723,46 @@ mg_correct_kernel(MGLevelArgs L, MGGeo c, double w, double alpha, const double* 
   e += blockIdx.y * e_stride;
   out += blockIdx.y * out_stride;
   const unsigned N = (unsigned)L.g.nx * L.g.ny * L.g.nz;
-  const unsigned sxc = (unsigned)c.ny * c.nz, sx = (unsigned)L.g.ny * L.g.nz,
-                 sy = (unsigned)L.g.nz;
-  // u' at node j with coordinates (x, y, z)
-  auto up = [&](unsigned j, int x, int y, int z) {
-    const unsigned P = (unsigned)(x >> 1) * sxc + (unsigned)(y >> 1) * c.nz + (unsigned)(z >> 1);
-    const double dj = L.dinv[j];
-    return dj == 0.0 ? 0.0 : w * dj * b[j] + alpha * e[P];
+  const unsigned sxc = (unsigned)c.ny * c.nz;
+  auto parent = [&](int x, int y, int z) {
+    return (unsigned)(x >> 1) * sxc + (unsigned)(y >> 1) * c.nz + (unsigned)(z >> 1);
   };
   double acc[1] = {0.0};
   for (unsigned j = xcd_remap(blockIdx.x, gridDim.x) * kThreads + threadIdx.x; j < N; j += gridDim.x * kThreads) {
-    double o = 0.0;
-    if (L.dinv[j] != 0.0) {
-      int x, y, z;
-      mg_coords(j, L.g, x, y, z);
-      const double uj = up(j, x, y, z);
-      double au = L.diag[j] * uj;
-      if (x + 1 < L.g.nx) au -= L.ax[j] * up(j + sx, x + 1, y, z);
-      if (x > 0) au -= L.ax[j - sx] * up(j - sx, x - 1, y, z);
-      if (y + 1 < L.g.ny) au -= L.ay[j] * up(j + sy, x, y + 1, z);
-      if (y > 0) au -= L.ay[j - sy] * up(j - sy, x, y - 1, z);
-      if (z + 1 < L.g.nz) au -= L.az[j] * up(j + 1, x, y, z + 1);
-      if (z > 0) au -= L.az[j - 1] * up(j - 1, x, y, z - 1);
-      o = uj + w * L.dinv[j] * (b[j] - au);
+    int x, y, z;
+    mg_coords(j, L.g, x, y, z);
+    const Hood h = mg_hood(j, x, y, z, L.g);
+    // the node and its six neighbours (a clamped one is j itself, weight 0): D^-1, b
+    // and the coarse correction of the aggregate, all loaded before any is used
+    double dv[7], bv[7], ev[7], c[6];
+    {
+      unsigned m[7], P[7];
+      m[6] = j;
+      P[6] = parent(x, y, z);
+#pragma unroll
+      for (int k = 0; k < 6; ++k) {
+        const int dx = (k == 0) - (k == 1), dy = (k == 2) - (k == 3), dz = (k == 4) - (k == 5);
+        m[k] = h.j[k];
+        P[k] = h.in[k] ? parent(x + dx, y + dy, z + dz) : P[6];
+      }
+      hood_weights(j, h, L.ax, L.ay, L.az, c);
+#pragma unroll
+      for (int k = 0; k < 7; ++k) {
+        dv[k] = L.dinv[m[k]];
+        bv[k] = b[m[k]];
+        ev[k] = e[P[k]];
+      }
     }
+    // u' = w D^-1 b + alpha P e on active nodes, 0 elsewhere
+    double u[7];
+#pragma unroll
+    for (int k = 0; k < 7; ++k) u[k] = dv[k] == 0.0 ? 0.0 : w * dv[k] * bv[k] + alpha * ev[k];
+    double au = L.diag[j] * u[6];
+#pragma unroll
+    for (int k = 0; k < 6; ++k) au -= c[k] * u[k];
+    const double o = dv[6] == 0.0 ? 0.0 : u[6] + w * dv[6] * (bv[6] - au);
     out[j] = o;
-    if (FINEST) acc[0] += b[j] * o;
+    if (FINEST) acc[0] += bv[6] * o;
   }
   if (FINEST) block_sums<1>(acc, partial_rz + (long long)blockIdx.y * gridDim.x + blockIdx.x);
 }
