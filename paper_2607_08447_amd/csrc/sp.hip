@@ -84,14 +84,30 @@ __device__ __forceinline__ void block_sums(double (&v)[NV], double* out) {
 }
 
 // sums of nblk partial rows (stride NV) by one workgroup of kRedThreads, fixed order
+// (thread t adds rows t, t + kRedThreads, ... in turn).  Eight rows per thread are
+// loaded before any is added (a clamped index and a zero stand in past the end),
+// so a thread waits on memory once per eight rows rather than once per row.
 template <int NV>
 __device__ __forceinline__ void reduce_partials(const double* partial, int nblk, double* out) {
+  constexpr int kBatch = 8;
   double v[NV];
 #pragma unroll
   for (int k = 0; k < NV; ++k) v[k] = 0.0;
-  for (int b = threadIdx.x; b < nblk; b += kRedThreads)
+  for (int b0 = threadIdx.x; b0 < nblk; b0 += kBatch * kRedThreads) {
+    double t[kBatch][NV];
 #pragma unroll
-    for (int k = 0; k < NV; ++k) v[k] += partial[(long long)b * NV + k];
+    for (int u = 0; u < kBatch; ++u) {
+      const int b = b0 + u * kRedThreads;
+      const long long row = b < nblk ? b : nblk - 1;
+#pragma unroll
+      for (int k = 0; k < NV; ++k) t[u][k] = partial[row * NV + k];
+    }
+#pragma unroll
+    for (int u = 0; u < kBatch; ++u)
+#pragma unroll
+      for (int k = 0; k < NV; ++k)
+        if (b0 + u * kRedThreads < nblk) v[k] += t[u][k];
+  }
   block_sums<NV, kRedThreads>(v, out);
 }
 
