@@ -193,3 +193,57 @@ def test_restatement_converges_to_the_oracle_solution():
     phi, rel, _ = _pcg(shape, 0.4, eps, dirichlet, phi_fixed, rho, 40)
     assert rel < 1e-12
     assert np.abs(phi - ref).max() <= 1e-9 * np.abs(ref).max()
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("precond", ["multigrid", "jacobi"])
+def test_recorded_chunk_reused_with_new_coefficients_and_charge(precond):
+    """hkp_poisson keeps its recorded CG chunk across calls that pass the same
+    buffers.  The chunk must hold no coefficient or charge value: a second call on
+    the same workspace, solution and mask buffers with another permittivity,
+    charge and electrode potential, and a third with the first inputs again, each
+    reach the oracle's direct solution (the electrode mask's contents change too;
+    the mask buffer does not)."""
+    import ctypes as C
+    import torch
+    import paper_2607_08447_amd as hkp
+    from paper_2607_08447_amd import _lib as L
+    from paper_2607_08447_amd.api import _pgrid, _private_stream
+    from oracle import poisson_solve
+    shape, h = (21, 14, 9), 0.4
+    boxes = [_box(shape, 11), _box(shape, 12)]   # different electrodes too
+    pg = _pgrid(shape)
+    need = L.lib.hkp_poisson_workspace_bytes(C.byref(pg))
+    ws = torch.empty(need, dtype=torch.uint8, device="cuda")
+    dirm = torch.empty(shape, dtype=torch.uint8, device="cuda")
+    eps_d = torch.empty(shape, dtype=torch.float64, device="cuda")
+    rho_d = torch.empty(shape, dtype=torch.float64, device="cuda")
+    fix_d = torch.empty(shape, dtype=torch.float64, device="cuda")
+    phi = torch.empty(shape, dtype=torch.float64, device="cuda")
+    s = _private_stream()
+    prev = hkp.poisson_preconditioner(precond)
+    try:
+        for k in (0, 1, 0):
+            eps, dirichlet, phi_fixed, rho = boxes[k]
+            print(f"reused chunk {precond} call with box {k}", flush=True)
+            dirm.copy_(torch.from_numpy(dirichlet))
+            eps_d.copy_(torch.from_numpy(eps))
+            rho_d.copy_(torch.from_numpy(rho))
+            fix_d.copy_(torch.from_numpy(phi_fixed))
+            phi.zero_()
+            torch.cuda.synchronize()
+            it = C.c_int32(0)
+            rel = C.c_double(0.0)
+            with torch.cuda.stream(s):
+                code = L.lib.hkp_poisson(C.byref(pg), h, C.c_void_p(eps_d.data_ptr()),
+                                         C.c_void_p(dirm.data_ptr()), C.c_void_p(fix_d.data_ptr()),
+                                         C.c_void_p(rho_d.data_ptr()), C.c_void_p(phi.data_ptr()),
+                                         1e-13, 20000, C.c_void_p(ws.data_ptr()), C.c_size_t(need),
+                                         C.c_void_p(s.cuda_stream), C.byref(it), C.byref(rel))
+            s.synchronize()
+            assert code == 0 and rel.value <= 1e-13, (code, rel.value)
+            ref = poisson_solve(shape, h, eps, dirichlet, phi_fixed, rho)
+            err = np.abs(phi.cpu().numpy() - ref).max()
+            assert err <= 1e-9 * max(1.0, np.abs(ref).max()), (k, err)
+    finally:
+        hkp.poisson_preconditioner(prev)
