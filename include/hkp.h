@@ -554,6 +554,12 @@ size_t hkp_poisson_workspace_bytes(const hkp_pgrid* pgrid);
  *   phi        device double [px][py][pz]; in: finite guess, out: solution
  *              (electrode nodes set to phi_fixed)
  *   cg_iters, cg_relres  host, may be NULL: iterations and final |r|/|b|
+ * On a stream other than the legacy default stream the iterations run as a
+ * recorded hipGraph.  The library keeps the last recorded graph of each host
+ * thread (until the process ends) and replays it while the next call on that
+ * thread passes the same workspace, phi and dirichlet pointers, box, cg_max_iter,
+ * preconditioner and device; the graph holds pointers, never values, so the
+ * buffers' contents may change between calls.
  * Returns HKP_OK, HKP_W_NOT_CONVERGED (cg_max_iter reached) or an error. */
 int hkp_poisson(const hkp_pgrid* pgrid, double h_nm, const double* eps_r,
                 const uint8_t* dirichlet, const double* phi_fixed, const double* rho,
