@@ -73,6 +73,25 @@ def test_fin_dqd_small_fp64_vs_arpack(name, product):
     _check_pairs(w, res, E_ref, 1e-8, 1e-8)
 
 
+@pytest.mark.parametrize("precision,nb", [("fp64", 15), ("fp64", 21), ("fp64", 37),
+                                          ("mixed", 19)])
+def test_odd_block_sizes(precision, nb):
+    """Odd blocks: the Jacobi eigensolves pad the block with a decoupled player,
+    and the Gram and rotation kernels end in a partial tile of vectors."""
+    w = workload("fin_small")
+    nev = 12
+    H = hamiltonian_ls(Grid(*w.shape, w.h), SI_MATERIAL, w.V, w.strain.reshape(-1, 6), w.B)
+    E_ref, _ = lowest_arpack(H, nev, tol=1e-13)
+    if precision == "fp64":
+        res = _gpu_solve(w, nev=nev, nb=nb, tol=1e-9)
+        assert res.status == 0
+        _check_pairs(w, res, E_ref, 1e-8, 1e-8)
+    else:
+        res = _gpu_solve(w, nev=nev, nb=nb, tol=1e-6, precision="mixed")
+        assert res.status == 0
+        assert np.abs(res.E.cpu().numpy() - E_ref).max() <= 1e-6
+
+
 @pytest.mark.parametrize("product", [False, True], ids=["recurrence", "product"])
 def test_mixed_precision_within_1ueV(product):
     w = workload("fin_small")
