@@ -92,6 +92,27 @@ def test_odd_block_sizes(precision, nb):
         assert np.abs(res.E.cpu().numpy() - E_ref).max() <= 1e-6
 
 
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_tilted_field_with_z_component(precision):
+    """B with a z component: link phases vary over every plane (the general-phase
+    stencil, FP64 and FP32), on a 3-D fin against the oracle."""
+    import copy
+    w = copy.copy(workload("fin_small"))
+    w.B = (0.3, 0.2, 0.6)
+    nev = 12
+    H = hamiltonian_ls(Grid(*w.shape, w.h), SI_MATERIAL, w.V, w.strain.reshape(-1, 6), w.B)
+    E_ref, _ = lowest_arpack(H, nev, tol=1e-13)
+    if precision == "fp64":
+        res = _gpu_solve(w, nev=nev, nb=24, tol=1e-9)
+        assert res.status == 0
+        _check_pairs(w, res, E_ref, 1e-8, 1e-8)
+    else:
+        res = _gpu_solve(w, nev=nev, nb=24, tol=1e-6, precision="mixed")
+        assert res.status == 0
+        assert np.abs(res.E.cpu().numpy() - E_ref).max() <= 1e-6
+        assert res.stats["n_hx_fp32"] > 0
+
+
 @pytest.mark.parametrize("product", [False, True], ids=["recurrence", "product"])
 def test_mixed_precision_within_1ueV(product):
     w = workload("fin_small")
