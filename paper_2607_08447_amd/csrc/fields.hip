@@ -117,68 +117,135 @@ __global__ void phase_kernel(int nx, int nz, double h, double Bx, double By, dou
   }
 }
 
-// ABI block [v][x][y][z][6] (J, symmetric gauge) -> internal [v][c][z][y][x] (LS, GPU gauge)
+// The two layouts of a block run along different axes: the ABI's [v][x][y][z][6]
+// has z (then the six components) fastest, the internal [v][c][z][y][x] has x
+// fastest.  A workgroup converts a 16 x 16 tile of (x, z) points of one y row of
+// one vector through LDS: it reads the side whose fast axis it can cover with
+// consecutive lanes (16 points of one row), transforms, and writes the other side
+// the same way (for the ABI, 16 z points x 6 components = 1.5 KiB contiguous per x).
+constexpr int kTile = 16;
+constexpr int kTileRow = kTile * 6 + 1;   // complex entries per x row of the tile (padded)
+
+struct TileCoord {
+  int x0, y, z0;
+};
+__device__ __forceinline__ TileCoord tile_coord(int nx, int ny, int nz) {
+  const int ntx = (nx + kTile - 1) / kTile;
+  int t = blockIdx.x;
+  TileCoord c;
+  c.x0 = (t % ntx) * kTile;
+  t /= ntx;
+  c.y = t % ny;
+  c.z0 = (t / ny) * kTile;
+  return c;
+}
+
+// ABI block (J, symmetric gauge) -> internal (LS, GPU gauge)
 template <typename TO>
-__global__ void abi_to_internal_kernel(int nx, int ny, int nz, double h, double Bx, double By,
-                                       double Bz, const double2* abi, TO* internal) {
+__global__ void __launch_bounds__(256)
+abi_to_internal_kernel(int nx, int ny, int nz, double h, double Bx, double By, double Bz,
+                       const double2* abi, TO* internal) {
+  __shared__ double2 tile[kTile][kTileRow];   // [x][z * 6 + c]
   const long long N = (long long)nx * ny * nz;
-  const long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   const int v = blockIdx.y;
-  if (p >= N) return;
-  const int x = (int)(p % nx);
-  const int y = (int)((p / nx) % ny);
-  const int z = (int)(p / ((long long)nx * ny));
-  const long long a = ((long long)x * ny + y) * nz + z;
-  const double2* src = abi + ((long long)v * N + a) * 6;
-  double2 j[6];
-  for (int c = 0; c < 6; ++c) j[c] = src[c];
-  double s, co;
-  sincos(kEoverHbar * chi_at(x, y, z, nx, ny, nz, h, Bx, By, Bz), &s, &co);
-  const double2 g = make_double2(co, s);  // exp(+i k chi)
-  for (int c = 0; c < 6; ++c) {
-    // (U^H psi_J)_c = sum_j conj(U_jc) psi_J,j
-    double2 acc = make_double2(0, 0);
-    for (int r = 0; r < 6; ++r) {
-      const double2 u = make_double2(kUre[r][c] * kInvS6, -kUim[r][c] * kInvS6);
-      const double2 t = cmul(u, j[r]);
-      acc.x += t.x;
-      acc.y += t.y;
+  const TileCoord tc = tile_coord(nx, ny, nz);
+  {
+    // read: lanes along z (and the six components), one x per 16 lanes
+    const int xo = threadIdx.x >> 4, zo = threadIdx.x & 15;
+    const int x = tc.x0 + xo, z = tc.z0 + zo;
+    if (x < nx && z < nz) {
+      const long long a = ((long long)x * ny + tc.y) * nz + z;
+      const double2* src = abi + ((long long)v * N + a) * 6;
+      double2 j[6];
+#pragma unroll
+      for (int c = 0; c < 6; ++c) j[c] = src[c];
+      double s, co;
+      sincos(kEoverHbar * chi_at(x, tc.y, z, nx, ny, nz, h, Bx, By, Bz), &s, &co);
+      const double2 g = make_double2(co, s);  // exp(+i k chi)
+#pragma unroll
+      for (int c = 0; c < 6; ++c) {
+        // (U^H psi_J)_c = sum_j conj(U_jc) psi_J,j
+        double2 acc = make_double2(0, 0);
+#pragma unroll
+        for (int r = 0; r < 6; ++r) {
+          const double2 u = make_double2(kUre[r][c] * kInvS6, -kUim[r][c] * kInvS6);
+          const double2 t = cmul(u, j[r]);
+          acc.x += t.x;
+          acc.y += t.y;
+        }
+        tile[xo][zo * 6 + c] = cmul(g, acc);
+      }
     }
-    acc = cmul(g, acc);
-    TO* dst = internal + 2 * (((long long)v * 6 + c) * N + p);
-    dst[0] = (TO)acc.x;
-    dst[1] = (TO)acc.y;
+  }
+  __syncthreads();
+  {
+    // write: lanes along x
+    const int xi = threadIdx.x & 15, zi = threadIdx.x >> 4;
+    const int x = tc.x0 + xi, z = tc.z0 + zi;
+    if (x < nx && z < nz) {
+      const long long p = ((long long)z * ny + tc.y) * nx + x;
+#pragma unroll
+      for (int c = 0; c < 6; ++c) {
+        const double2 w = tile[xi][zi * 6 + c];
+        TO* dst = internal + 2 * (((long long)v * 6 + c) * N + p);
+        dst[0] = (TO)w.x;
+        dst[1] = (TO)w.y;
+      }
+    }
   }
 }
 
-__global__ void internal_to_abi_kernel(int nx, int ny, int nz, double h, double Bx, double By,
-                                       double Bz, const double2* internal, long long in_bstride,
-                                       double2* abi, long long abi_bstride, int nvec) {
+// internal (LS, GPU gauge) -> ABI block (J, symmetric gauge); vector v of batch
+// member b
+__global__ void __launch_bounds__(256)
+internal_to_abi_kernel(int nx, int ny, int nz, double h, double Bx, double By, double Bz,
+                       const double2* internal, long long in_bstride, double2* abi,
+                       long long abi_bstride, int nvec) {
+  __shared__ double2 tile[kTile][kTileRow];   // [x][z * 6 + r]
   const long long N = (long long)nx * ny * nz;
-  const long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   const int v = blockIdx.y;
   const int b = blockIdx.z;
-  if (p >= N) return;
-  const int x = (int)(p % nx);
-  const int y = (int)((p / nx) % ny);
-  const int z = (int)(p / ((long long)nx * ny));
-  const long long a = ((long long)x * ny + y) * nz + z;
-  double2 l[6];
-  const double2* src = internal + (long long)b * in_bstride + (long long)v * 6 * N;
-  double s, co;
-  sincos(kEoverHbar * chi_at(x, y, z, nx, ny, nz, h, Bx, By, Bz), &s, &co);
-  const double2 g = make_double2(co, -s);  // exp(-i k chi)
-  for (int c = 0; c < 6; ++c) l[c] = cmul(g, src[(long long)c * N + p]);
-  double2* dst = abi + (long long)b * abi_bstride + ((long long)v * N + a) * 6;
-  for (int r = 0; r < 6; ++r) {
-    double2 acc = make_double2(0, 0);
-    for (int c = 0; c < 6; ++c) {
-      const double2 u = make_double2(kUre[r][c] * kInvS6, kUim[r][c] * kInvS6);
-      const double2 t = cmul(u, l[c]);
-      acc.x += t.x;
-      acc.y += t.y;
+  const TileCoord tc = tile_coord(nx, ny, nz);
+  {
+    // read: lanes along x
+    const int xi = threadIdx.x & 15, zi = threadIdx.x >> 4;
+    const int x = tc.x0 + xi, z = tc.z0 + zi;
+    if (x < nx && z < nz) {
+      const long long p = ((long long)z * ny + tc.y) * nx + x;
+      const double2* src = internal + (long long)b * in_bstride + (long long)v * 6 * N;
+      double2 l[6];
+#pragma unroll
+      for (int c = 0; c < 6; ++c) l[c] = src[(long long)c * N + p];
+      double s, co;
+      sincos(kEoverHbar * chi_at(x, tc.y, z, nx, ny, nz, h, Bx, By, Bz), &s, &co);
+      const double2 g = make_double2(co, -s);  // exp(-i k chi)
+#pragma unroll
+      for (int c = 0; c < 6; ++c) l[c] = cmul(g, l[c]);
+#pragma unroll
+      for (int r = 0; r < 6; ++r) {
+        double2 acc = make_double2(0, 0);
+#pragma unroll
+        for (int c = 0; c < 6; ++c) {
+          const double2 u = make_double2(kUre[r][c] * kInvS6, kUim[r][c] * kInvS6);
+          const double2 t = cmul(u, l[c]);
+          acc.x += t.x;
+          acc.y += t.y;
+        }
+        tile[xi][zi * 6 + r] = acc;
+      }
     }
-    dst[r] = acc;
+  }
+  __syncthreads();
+  {
+    // write: lanes along z (16 points x 6 components contiguous per x)
+    const int xo = threadIdx.x >> 4, zo = threadIdx.x & 15;
+    const int x = tc.x0 + xo, z = tc.z0 + zo;
+    if (x < nx && z < nz) {
+      const long long a = ((long long)x * ny + tc.y) * nz + z;
+      double2* dst = abi + (long long)b * abi_bstride + ((long long)v * N + a) * 6;
+#pragma unroll
+      for (int r = 0; r < 6; ++r) dst[r] = tile[xo][zo * 6 + r];
+    }
   }
 }
 
@@ -301,6 +368,13 @@ hipError_t launch_phase_tables(int nx, int nz, double h, const double B[3], doub
   return hipGetLastError();
 }
 
+namespace {
+// workgroups of a layout conversion: 16 x 16 (x, z) tiles of every y row
+unsigned conv_tiles(int nx, int ny, int nz) {
+  return (unsigned)(((nx + kTile - 1) / kTile) * ny * ((nz + kTile - 1) / kTile));
+}
+}  // namespace
+
 hipError_t launch_abi_to_internal(int nx, int ny, int nz, double h, const double B[3],
                                   int nvec, const void* abi, void* internal, int to_fp32,
                                   hipStream_t s) {
@@ -310,7 +384,7 @@ hipError_t launch_abi_to_internal(int nx, int ny, int nz, double h, const double
   for (int v0 = 0; v0 < nvec; v0 += kChunk) {
     const int nv = nvec - v0 < kChunk ? nvec - v0 : kChunk;
     const long long off = (long long)v0 * N * 6;   // complex entries before the chunk
-    dim3 grid((unsigned)((N + 255) / 256), (unsigned)nv);
+    dim3 grid(conv_tiles(nx, ny, nz), (unsigned)nv);
     if (to_fp32)
       abi_to_internal_kernel<float><<<grid, 256, 0, s>>>(
           nx, ny, nz, h, B[0], B[1], B[2], (const double2*)abi + off,
@@ -329,8 +403,7 @@ hipError_t launch_internal_to_abi(int nx, int ny, int nz, double h, const double
                                   int nvec, int batch, const void* internal,
                                   long long in_bstride, void* abi, long long abi_bstride,
                                   hipStream_t s) {
-  const long long N = (long long)nx * ny * nz;
-  dim3 grid((unsigned)((N + 255) / 256), (unsigned)nvec, (unsigned)batch);
+  dim3 grid(conv_tiles(nx, ny, nz), (unsigned)nvec, (unsigned)batch);
   internal_to_abi_kernel<<<grid, 256, 0, s>>>(nx, ny, nz, h, B[0], B[1], B[2],
                                               (const double2*)internal, in_bstride,
                                               (double2*)abi, abi_bstride, nvec);
