@@ -278,6 +278,28 @@ int hkp_solve_batch(const hkp_grid* grid, const hkp_material* mat, const hkp_opt
                     double* resid_eV, void* workspace, size_t ws_bytes, void* hip_stream,
                     hkp_stats* stats);
 
+/* Progress of an eigensolve after an outer iteration (after each replayed chunk
+ * of iterations with HKP_FLAG_GRAPH).  Arrays are host memory owned by the
+ * library and valid during the call only; values are those of the last
+ * Rayleigh-Ritz step (Sec. II.B), per batch member. */
+typedef struct {
+  int32_t iter;              /* outer iterations done */
+  int32_t batch, nb, nev;
+  const int32_t* nconv;      /* [batch] wanted states meeting tol */
+  const int32_t* fp64;       /* [batch] 1 once the member's filter runs in FP64 */
+  const double* ritz_eV;     /* [batch][nb] Ritz values, ascending */
+  const double* resid_eV;    /* [batch][nb] residual norms ||H x - theta x|| */
+} hkp_iter_info;
+/* Returns nonzero to end the solve after this iteration (the results are then
+ * written as after max_iter: HKP_W_NOT_CONVERGED unless every state converged). */
+typedef int (*hkp_iter_fn)(const hkp_iter_info* info, void* user);
+
+/* Registers fn (NULL: none) for the eigensolves that the calling host thread runs
+ * from now on: hkp_solve, hkp_solve_batch and those inside hkp_sp_solve and
+ * hkp_autotune_block.  Each call of fn costs one host wait on the solver's
+ * stream and a copy of 2 nb doubles per member. */
+void hkp_set_iter_callback(hkp_iter_fn fn, void* user);
+
 /* Workspace of hkp_apply / hkp_filter_step for nvec vectors. */
 size_t hkp_apply_workspace_bytes(const hkp_grid* grid, int32_t nvec);
 

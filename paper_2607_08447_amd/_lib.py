@@ -126,6 +126,14 @@ class hkp_st_point(C.Structure):
                 ("J_perp_eV", C.c_double), ("J_par_eV", C.c_double)]
 
 
+class hkp_iter_info(C.Structure):
+    _fields_ = [("iter", C.c_int32), ("batch", C.c_int32), ("nb", C.c_int32), ("nev", C.c_int32),
+                ("nconv", C.POINTER(C.c_int32)), ("fp64", C.POINTER(C.c_int32)),
+                ("ritz_eV", C.POINTER(C.c_double)), ("resid_eV", C.POINTER(C.c_double))]
+
+
+HKP_ITER_FN = C.CFUNCTYPE(C.c_int, C.POINTER(hkp_iter_info), C.c_void_p)
+
 _P = C.c_void_p
 _D = C.POINTER(C.c_double)
 
@@ -192,6 +200,7 @@ SIGNATURES = {
                               C.c_size_t, _P]),
     "hkp_st_model": (C.c_int, [_P, _P, C.POINTER(hkp_st_opts), C.c_int32, _P, _P, _P, _P]),
     "hkp_poisson_preconditioner": (C.c_int, [C.c_int32]),
+    "hkp_set_iter_callback": (None, [HKP_ITER_FN, C.c_void_p]),
     "hkp_last_error": (C.c_char_p, []),
     "hkp_version": (C.c_int, []),
 }

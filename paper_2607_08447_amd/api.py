@@ -6,6 +6,7 @@ trailing Voigt axis of 6), spinor blocks complex128 [nvec, nx, ny, nz, 6] in
 the |J m_j> basis and the symmetric gauge.
 """
 
+import contextlib
 import ctypes as C
 import os
 from dataclasses import dataclass
@@ -60,6 +61,43 @@ def _private_stream():
     if s is None:
         s = _PRIVATE_STREAMS[dev] = torch.cuda.Stream(device=dev)
     return s
+
+
+@contextlib.contextmanager
+def _iter_callback(callback):
+    """While the block runs, the eigensolves of this thread report to callback
+    (None: nothing) after every outer iteration (every replayed chunk in graph
+    mode): a dict with iter, batch, nb, nev and numpy arrays nconv [batch],
+    fp64 [batch], ritz_eV and resid_eV [batch, nb].  A true return value ends the
+    solve (status 1 unless every state converged); an exception raised by the
+    callback ends it too and is raised again after the call."""
+    if callback is None:
+        yield
+        return
+    import numpy as np
+    raised = []
+
+    def _fn(pinfo, _user):
+        try:
+            i = pinfo.contents
+            arr = lambda ptr, shape: np.ctypeslib.as_array(ptr, shape).copy()
+            d = {"iter": i.iter, "batch": i.batch, "nb": i.nb, "nev": i.nev,
+                 "nconv": arr(i.nconv, (i.batch,)), "fp64": arr(i.fp64, (i.batch,)),
+                 "ritz_eV": arr(i.ritz_eV, (i.batch, i.nb)),
+                 "resid_eV": arr(i.resid_eV, (i.batch, i.nb))}
+            return 1 if callback(d) else 0
+        except BaseException as e:   # noqa: BLE001 -- kept and raised after the solve
+            raised.append(e)
+            return 1
+
+    fn = L.HKP_ITER_FN(_fn)
+    L.lib.hkp_set_iter_callback(fn, None)
+    try:
+        yield
+    finally:
+        L.lib.hkp_set_iter_callback(L.HKP_ITER_FN(), None)
+    if raised:
+        raise raised[0]
 
 
 def _stream(stream=None):
@@ -132,7 +170,7 @@ def _npsi(g, o, nev, block):
 def solve(V, h, nev, strain=None, B=(0.0, 0.0, 0.0), nb=0, degree=0, tol=1e-8,
           precision="fp64", max_iter=200, seed=1, X0=None, graph=False, material=None,
           return_psi=True, workspace=None, polish=True, lock=True, psi_block=False,
-          spin_free=False, cheb_product=False):
+          spin_free=False, cheb_product=False, callback=None):
     """Lowest `nev` eigenpairs of H for the potential V (float64 [nx, ny, nz], eV).
 
     spin_free=True solves the orbital problem H_0 without spin-orbit coupling
@@ -146,7 +184,8 @@ def solve(V, h, nev, strain=None, B=(0.0, 0.0, 0.0), nb=0, degree=0, tol=1e-8,
     block in every iteration (no soft locking of converged Kramers pairs).
     cheb_product=True evaluates the Chebyshev filter in product form over its
     roots instead of the three-term recurrence (the same polynomial; two blocks
-    moved per step instead of three)."""
+    moved per step instead of three).  callback(progress) is called after every
+    outer iteration (see _iter_callback); returning True ends the solve."""
     V = _dev(V, torch.float64)
     shape = tuple(V.shape)
     if len(shape) != 3:
@@ -179,15 +218,16 @@ def solve(V, h, nev, strain=None, B=(0.0, 0.0, 0.0), nb=0, degree=0, tol=1e-8,
     mat = _material(material)
     if stream_ctx is not None:
         stream_ctx.wait_stream(torch.cuda.current_stream())
-        with torch.cuda.stream(stream_ctx):
+        with torch.cuda.stream(stream_ctx), _iter_callback(callback):
             code = L.lib.hkp_solve(C.byref(g), C.byref(mat), C.byref(o), _ptr(V), _ptr(strain),
                                    _B(B), _ptr(X0d), _ptr(E), _ptr(psi), _ptr(R), _ptr(ws),
                                    C.c_size_t(ws.numel()), _stream(stream_ctx), C.byref(st))
         torch.cuda.current_stream().wait_stream(stream_ctx)
     else:
-        code = L.lib.hkp_solve(C.byref(g), C.byref(mat), C.byref(o), _ptr(V), _ptr(strain),
-                               _B(B), _ptr(X0d), _ptr(E), _ptr(psi), _ptr(R), _ptr(ws),
-                               C.c_size_t(ws.numel()), _stream(), C.byref(st))
+        with _iter_callback(callback):
+            code = L.lib.hkp_solve(C.byref(g), C.byref(mat), C.byref(o), _ptr(V), _ptr(strain),
+                                   _B(B), _ptr(X0d), _ptr(E), _ptr(psi), _ptr(R), _ptr(ws),
+                                   C.c_size_t(ws.numel()), _stream(), C.byref(st))
     L.check(code)
     return SolveResult(E, psi, R, st.as_dict(), code)
 
@@ -195,10 +235,10 @@ def solve(V, h, nev, strain=None, B=(0.0, 0.0, 0.0), nb=0, degree=0, tol=1e-8,
 def solve_batch(V, h, nev, strain=None, B=(0.0, 0.0, 0.0), nb=0, degree=0, tol=1e-8,
                 precision="fp64", max_iter=200, seed=1, graph=True, material=None,
                 return_psi=False, workspace=None, polish=True, lock=True, X0=None,
-                psi_block=False, spin_free=False, cheb_product=False):
+                psi_block=False, spin_free=False, cheb_product=False, callback=None):
     """Lowest eigenpairs of `batch` Hamiltonians differing in V ([batch, nx, ny, nz]).
     X0 (optional, complex128): [batch, nb or nev, nx, ny, nz, 6]; X0 and
-    psi_block, cheb_product as in solve()."""
+    psi_block, cheb_product, callback as in solve()."""
     V = _dev(V, torch.float64)
     if V.dim() != 4:
         raise ValueError("V must be [batch, nx, ny, nz]")
@@ -231,7 +271,7 @@ def solve_batch(V, h, nev, strain=None, B=(0.0, 0.0, 0.0), nb=0, degree=0, tol=1
     mat = _material(material)
     s = _private_stream()
     s.wait_stream(torch.cuda.current_stream())
-    with torch.cuda.stream(s):
+    with torch.cuda.stream(s), _iter_callback(callback):
         code = L.lib.hkp_solve_batch(C.byref(g), C.byref(mat), C.byref(o), batch, _ptr(V),
                                      _ptr(strain), _B(B), _ptr(X0d), _ptr(E), _ptr(psi), _ptr(R),
                                      _ptr(ws), C.c_size_t(ws.numel()), _stream(s),

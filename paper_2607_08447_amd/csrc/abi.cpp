@@ -909,6 +909,8 @@ int hkp_st_model(const void* gm, const double* J_eV, const hkp_st_opts* opts, in
   });
 }
 
+void hkp_set_iter_callback(hkp_iter_fn fn, void* user) { set_iter_callback(fn, user); }
+
 int hkp_poisson_preconditioner(int32_t kind) {
   if (kind != HKP_PRECOND_MULTIGRID && kind != HKP_PRECOND_JACOBI) {
     set_error("hkp_poisson_preconditioner: HKP_PRECOND_MULTIGRID or HKP_PRECOND_JACOBI");

@@ -676,6 +676,16 @@ int default_nb(int nev, long long n6) {
 
 size_t plan_bytes(const Plan& p) { return make_layout(p).total; }
 
+namespace {
+thread_local hkp_iter_fn g_iter_fn = nullptr;
+thread_local void* g_iter_user = nullptr;
+}  // namespace
+
+void set_iter_callback(hkp_iter_fn fn, void* user) {
+  g_iter_fn = fn;
+  g_iter_user = user;
+}
+
 int run_solve(const SolveArgs& A, hkp_stats* stats) {
   int n_sync = 0, n_graph = 0;   // host waits on the stream, graph replays
   const auto t_start = std::chrono::steady_clock::now();
@@ -828,6 +838,28 @@ int run_solve(const SolveArgs& A, hkp_stats* stats) {
       if (!hflags[8 * b]) return false;
     return true;
   };
+  // the caller's progress callback (after read_flags); true: it asks to stop
+  bool user_stop = false;
+  auto report = [&](int done_iters) {
+    if (!g_iter_fn || user_stop) return;
+    const size_t nbb = (size_t)p.batch * p.nb;
+    std::vector<double> th(nbb), res(nbb);
+    HKP_CHECK(hipMemcpyAsync(th.data(), c.at<double>(c.L.theta), nbb * 8, hipMemcpyDeviceToHost,
+                             c.s));
+    HKP_CHECK(hipMemcpyAsync(res.data(), c.at<double>(c.L.r2), nbb * 8, hipMemcpyDeviceToHost,
+                             c.s));
+    HKP_CHECK(hipStreamSynchronize(c.s));
+    ++n_sync;
+    for (double& r : res) r = std::sqrt(r > 0.0 ? r : 0.0);
+    std::vector<int32_t> nconv(p.batch), fp64(p.batch);
+    for (int b = 0; b < p.batch; ++b) {
+      nconv[b] = hflags[8 * b + 4];
+      fp64[b] = hflags[8 * b + 1];
+    }
+    hkp_iter_info info{done_iters, p.batch, p.nb, p.nev, nconv.data(), fp64.data(), th.data(),
+                       res.data()};
+    user_stop = g_iter_fn(&info, g_iter_user) != 0;
+  };
   auto degree_at = [&](int it) {   // it = 1, 2, ...
     if (p.degree_fixed) return p.degree;
     const int ramp = it == 1 ? 16 : (it == 2 ? 32 : p.degree);
@@ -881,7 +913,7 @@ int run_solve(const SolveArgs& A, hkp_stats* stats) {
   // eager iterations: all of them, or in graph mode the ramp-up ones
   const int eager_iters = eager ? A.max_iter : (p.degree_fixed ? 0 : 2);
   {
-    while (iters < std::min(A.max_iter, eager_iters) && !all_done()) {
+    while (iters < std::min(A.max_iter, eager_iters) && !all_done() && !user_stop) {
       ++iters;
       m_cur = degree_at(iters);
       count_work();
@@ -892,6 +924,7 @@ int run_solve(const SolveArgs& A, hkp_stats* stats) {
         iteration(iters, false, false, degree_at(iters + 1));
       }
       read_flags();
+      report(iters);
       if (trace) {
         double bd[4];
         HKP_CHECK(hipMemcpy(bd, c.at<double>(c.L.bounds), 32, hipMemcpyDeviceToHost));
@@ -912,7 +945,7 @@ int run_solve(const SolveArgs& A, hkp_stats* stats) {
       sst.collect();
     }
   }
-  if (!eager && iters < A.max_iter && !all_done()) {
+  if (!eager && iters < A.max_iter && !all_done() && !user_stop) {
     // record a chunk of iterations once, replay until converged
     m_cur = p.degree;
     const int chunk = std::max(1, std::min(A.graph_chunk > 0 ? A.graph_chunk : 4, A.max_iter));
@@ -943,13 +976,14 @@ int run_solve(const SolveArgs& A, hkp_stats* stats) {
     const double chunk_bytes = sst.hx_bytes - bytes_before;
     sst.hx_bytes = bytes_before;
     HKP_CHECK(hipGraphInstantiate(&rec.exec, rec.graph, nullptr, nullptr, 0));
-    while (iters < A.max_iter && !all_done()) {
+    while (iters < A.max_iter && !all_done() && !user_stop) {
       for (int k = 0; k < chunk; ++k) count_work();   // upper estimate per replay
       sst.hx_bytes += chunk_bytes;
       HKP_CHECK(hipGraphLaunch(rec.exec, c.s));
       ++n_graph;
       iters += chunk;
       read_flags();
+      report(iters);
     }
   }
 

@@ -93,6 +93,8 @@ int run_autotune_block(const hkp_grid& g, const hkp_material& mat, const hkp_opt
 Plan make_plan(const hkp_grid& g, const hkp_opts& o, int batch);
 size_t plan_bytes(const Plan& p);
 int run_solve(const SolveArgs& a, hkp_stats* stats);
+// the calling thread's progress callback of its eigensolves (NULL: none)
+void set_iter_callback(hkp_iter_fn fn, void* user);
 size_t apply_bytes(const hkp_grid& g, int nvec);
 int run_filter_step(const FilterArgs& a);
 // two recurrence steps in FP32 (one pass when the two-step kernel supports the

@@ -236,3 +236,42 @@ def test_batch_of_one_equals_single_solve():
     r1 = hkp.solve(torch.from_numpy(w.V), w.h, 8, **kw)
     assert rb.status == 0 and r1.status == 0
     assert np.abs(rb.E.cpu().numpy()[0] - r1.E.cpu().numpy()).max() <= 1e-9
+
+
+def test_iteration_callback_reports_and_stops():
+    """hkp_set_iter_callback (solve(callback=...)): one report per outer iteration
+    whose last Ritz values are the returned eigenvalues; a true return ends the
+    solve after that iteration (status 1); an exception in the callback ends it
+    and is raised again; graph mode reports per replayed chunk; nothing stays
+    registered after the call."""
+    w = workload("fin_small")
+    nev = 12
+    seen = []
+    res = _gpu_solve(w, nev=nev, nb=24, tol=1e-9, callback=lambda d: seen.append(d) or False)
+    assert res.status == 0
+    assert [d["iter"] for d in seen] == list(range(1, res.stats["iters"] + 1))
+    last = seen[-1]
+    assert last["batch"] == 1 and last["nb"] == 24 and last["nev"] == nev
+    assert last["nconv"][0] == nev and last["ritz_eV"].shape == (1, 24)
+    assert np.all(np.diff(last["ritz_eV"][0]) >= -1e-12)
+    assert np.abs(last["ritz_eV"][0, :nev] - res.E.cpu().numpy()).max() <= 1e-12
+    assert last["resid_eV"][0, :nev].max() <= 1e-9
+    assert seen[0]["resid_eV"][0, :nev].max() > last["resid_eV"][0, :nev].max()
+
+    stopped = _gpu_solve(w, nev=nev, nb=24, tol=1e-9, callback=lambda d: d["iter"] >= 2)
+    assert stopped.status == 1 and stopped.stats["iters"] == 2
+
+    def bad(d):
+        raise KeyError("from the callback")
+    with pytest.raises(KeyError):
+        _gpu_solve(w, nev=nev, nb=24, tol=1e-9, callback=bad)
+
+    chunks = []
+    g = _gpu_solve(w, nev=nev, nb=24, tol=1e-9, graph=True,
+                   callback=lambda d: chunks.append(d["iter"]) or False)
+    assert g.status == 0 and chunks == sorted(set(chunks)) and chunks[-1] == g.stats["iters"]
+    assert np.abs(g.E.cpu().numpy() - res.E.cpu().numpy()).max() <= 1e-10
+
+    plain = _gpu_solve(w, nev=nev, nb=24, tol=1e-9)   # no report reaches the lists now
+    n_seen, n_chunks = len(seen), len(chunks)
+    assert plain.status == 0 and len(seen) == n_seen and len(chunks) == n_chunks
