@@ -370,7 +370,9 @@ def sp_measure(torch, hkp, anneal_K=15.0):
     inside a 272 x 64 x 88 Poisson box (1.53M nodes), two holes at 1.5 K, mixed
     precision eigensolves to 1e-7 eV, stopped at max |phi_out - phi_in| <= 1e-6 V:
     annealed from anneal_K (the main figures), then the direct loop at 1.5 K for
-    comparison; and the Poisson CG iteration rate against the HBM roofline (HIP
+    comparison, both with the eigensolves' filter in product form (the loop's
+    default), and the annealed loop with the three-term recurrence beside them;
+    and the Poisson CG iteration rate against the HBM roofline (HIP
     events around a fixed number of iterations on the library's stream)."""
     from synth import sp_device
     d = sp_device("sp_dqd_256x48x48")
@@ -389,11 +391,15 @@ def sp_measure(torch, hkp, anneal_K=15.0):
 
     r, wall = loop(anneal_K)
     direct, wall_direct = loop(0.0)
+    kw["cheb_product"] = False   # the same loop with the eigensolves' filter as a recurrence
+    rec, wall_rec = loop(anneal_K)
+    kw.pop("cheb_product")
     st = r.stats
     NP = int(np.prod(d.pshape))
     return {"workload": "sp_dqd_256x48x48", "grid": list(d.shape), "poisson_box": list(d.pshape),
             "poisson_nodes": NP, "n_holes": d.n_holes, "T_K": d.T, "nev": d.nev, "nb": d.nb,
             "precision": "mixed", "stop": "max |phi_out - phi_in| <= 1e-6 V, eigen tol 1e-7 eV",
+            "filter": "product form (the loop's default)",
             "anneal_K": anneal_K, "anneal_iterations": st["anneal_iters"],
             "status": r.status, "sp_iterations": st["iters"], "converged": st["converged"],
             "delta_V": st["delta_V"], "seconds": round(wall, 3),
@@ -406,6 +412,11 @@ def sp_measure(torch, hkp, anneal_K=15.0):
                        "converged": direct.stats["converged"], "seconds": round(wall_direct, 3),
                        "max_abs_dE_vs_annealed_eV": float((direct.E - r.E).abs().max()),
                        "max_abs_dphi_vs_annealed_V": float((direct.phi - r.phi).abs().max())},
+            "recurrence": {"sp_iterations": rec.stats["iters"], "converged": rec.stats["converged"],
+                           "seconds": round(wall_rec, 3),
+                           "t_schroedinger_s": round(rec.stats["t_schroedinger"], 3),
+                           "max_abs_dE_vs_product_eV": float((rec.E - r.E).abs().max()),
+                           "max_abs_dphi_vs_product_V": float((rec.phi - r.phi).abs().max())},
             "poisson_cg": poisson_measure(torch, hkp, d, r.density)}
 
 

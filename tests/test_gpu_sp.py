@@ -168,12 +168,16 @@ def _gpu_loop(hkp, d, **kw):
                         B=d.B, nb=d.nb, **kw)
 
 
+@pytest.mark.parametrize("product", [True, False], ids=["product", "recurrence"])
 @pytest.mark.parametrize("name", ["sp_tiny", "sp_dqd_small"])
-def test_sp_loop_vs_oracle(name):
+def test_sp_loop_vs_oracle(name, product):
+    """Both evaluations of the eigensolves' filter: product form (the binding's
+    default for the loop) and the three-term recurrence."""
     import paper_2607_08447_amd as hkp
     d = sp_device(name)
-    print(f"sp loop {name}", flush=True)
-    r = _gpu_loop(hkp, d, tol=1e-10, tol_V=1e-9, mixing=0.3, history=5, cg_tol=1e-13)
+    print(f"sp loop {name} product {product}", flush=True)
+    r = _gpu_loop(hkp, d, tol=1e-10, tol_V=1e-9, mixing=0.3, history=5, cg_tol=1e-13,
+                  cheb_product=product)
     assert r.status == 0 and r.stats["converged"] == 1
     ref = sp_loop(Grid(*d.shape, d.h), d.nev, d.V_off, d.pshape, d.offset, d.eps_r,
                   d.dirichlet, d.phi_fixed, d.n_holes, d.T, strain=d.strain, B=d.B, mixing=0.3,
