@@ -524,10 +524,10 @@ __device__ __forceinline__ double mg_apply(unsigned j, const Hood& h, const MGLe
 // run of nodes (the x- and y-neighbours a node reads are then in that XCD's L2).
 //
 // UPD (the finest level inside a CG iteration): the CG update comes first, in the
-// same pass -- phi += alpha p, r_new = b - alpha q written to r_new (another buffer:
-// the neighbours here read b and q, and b = r_new - alpha q is formed where needed),
-// partial sums (0, r_new.r_new) per workgroup -- and the restriction takes r_new as
-// its right-hand side.
+// same pass -- phi += alpha p and the new residual b - alpha q (b: the old residual),
+// formed wherever it is needed (at the node, and at its neighbours from their old b
+// and q) and stored to r_new, another buffer, with partial sums (0, r_new.r_new) per
+// workgroup -- and the restriction takes the new residual as its right-hand side.
 template <bool UPD>
 __global__ void __launch_bounds__(kThreads)
 mg_restrict_kernel(MGLevelArgs L, MGGeo c, double w, const double* __restrict__ b,
