@@ -758,16 +758,26 @@ dot_partial_kernel(const double* A, const double* B, long long bstride, long lon
   }
 }
 
-__global__ void dot_reduce_kernel(int nparts, const double* partial, double* out) {
+// one wave per batch member: lane l adds partials l, l + 64, ... in turn, then the
+// lanes are summed by a fixed shuffle tree (the same order on every run)
+__global__ void __launch_bounds__(64)
+dot_reduce_kernel(int nparts, const double* partial, double* out) {
   const int b = blockIdx.x;
-  if (threadIdx.x != 0) return;
+  const double2* pb = reinterpret_cast<const double2*>(partial) + (long long)b * nparts;
   double sr = 0.0, si = 0.0;
-  for (int k = 0; k < nparts; ++k) {
-    sr += partial[2 * ((long long)b * nparts + k)];
-    si += partial[2 * ((long long)b * nparts + k) + 1];
+  for (int k = threadIdx.x; k < nparts; k += 64) {
+    const double2 v = pb[k];
+    sr += v.x;
+    si += v.y;
   }
-  out[2 * b] = sr;
-  out[2 * b + 1] = si;
+  for (int off = 32; off > 0; off >>= 1) {
+    sr += __shfl_down(sr, off, 64);
+    si += __shfl_down(si, off, 64);
+  }
+  if (threadIdx.x == 0) {
+    out[2 * b] = sr;
+    out[2 * b + 1] = si;
+  }
 }
 
 // w <- w - alpha v - beta vprev, alpha = Re(dot) and beta = sqrt(norm2prev) read
