@@ -376,3 +376,24 @@ def test_tune_cache_file_round_trip_and_errors(tmp_path):
     assert L.lib.hkp_tune_cache_save(None) == L.HKP_E_ARG
     assert L.lib.hkp_tuned_shape(C.byref(g), 0, 1, 1, 1, C.byref(t)) == L.HKP_E_ARG
     assert L.lib.hkp_tuned_shape(C.byref(g), 16, 1, 1, 3, C.byref(t)) == L.HKP_E_ARG
+
+
+def test_iteration_callback_registration_on_the_host():
+    """hkp_set_iter_callback takes a function or NULL without touching the device;
+    with one registered, a call that fails its argument checks reports the same code
+    and never calls it (it runs only after outer iterations)."""
+    L, g, m, o = _structs()
+    calls = []
+    fn = L.HKP_ITER_FN(lambda info, user: calls.append(1) or 0)
+    L.lib.hkp_set_iter_callback(fn, None)
+    try:
+        o.nev = 8
+        o.nb = 4                       # nb <= nev: rejected before any device work
+        fake = C.c_void_p(16)
+        stats = L.hkp_stats()
+        code = L.lib.hkp_solve(C.byref(g), C.byref(m), C.byref(o), fake, None, (C.c_double * 3)(),
+                               None, fake, fake, fake, fake, C.c_size_t(1 << 30), None,
+                               C.byref(stats))
+        assert code == L.HKP_E_ARG and calls == []
+    finally:
+        L.lib.hkp_set_iter_callback(L.HKP_ITER_FN(), None)
