@@ -20,12 +20,34 @@ def _runtime():
     return hits[-1] if hits else None
 
 
+def _build_module():
+    import importlib.util
+    spec = importlib.util.spec_from_file_location(
+        "_hkp_build", os.path.join(ROOT, "paper_2607_08447_amd", "build.py"))
+    mod = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(mod)
+    return mod
+
+
+def _stale(mod):
+    """The sanitized library is older than a host source, a header or the normal
+    library whose kernel objects it links."""
+    t = os.path.getmtime(ASAN_LIB)
+    deps = [os.path.join(mod.SRC, f) for f in mod.ASAN_SOURCES]
+    deps += glob.glob(os.path.join(mod.SRC, "*.h")) + glob.glob(os.path.join(ROOT, "include", "*.h"))
+    deps.append(mod.LIB)
+    return any(os.path.exists(d) and os.path.getmtime(d) > t for d in deps)
+
+
 def test_host_abi_checks_under_sanitizers():
     rt = _runtime()
     if rt is None:
         pytest.skip("no clang AddressSanitizer runtime in this image")
     if not os.path.exists(ASAN_LIB):
         pytest.skip("libhkp_asan.so not built (build() of __graft_entry__ builds it)")
+    mod = _build_module()
+    if _stale(mod):   # rebuilt from the current sources rather than testing an old one
+        mod.build_asan()
     env = dict(os.environ, LD_PRELOAD=rt, HKP_LIB=ASAN_LIB,
                ASAN_OPTIONS="detect_leaks=0:halt_on_error=1",
                UBSAN_OPTIONS="halt_on_error=1:print_stacktrace=1")
